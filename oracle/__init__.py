@@ -1,0 +1,208 @@
+"""CPU oracle for the pipelined BiCGStab solvers -- TEST INFRASTRUCTURE ONLY.
+
+Thin ctypes wrapper around ``oracle.c`` (plain FP64 C, no fused multiply-add).
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package; the HIP library never does, and the two share no
+code.  ``exact.py`` next to it is an exact-rational twin used to pin the FP64
+oracle on tiny systems.
+
+Algorithms (numbered as in arXiv 1612.01395, in order of appearance):
+``ALG_BICGSTAB`` -> Algorithm 7 (Algorithm 10 when ``dinv`` is given);
+``ALG_PBICGSTAB`` -> Algorithm 9 (Algorithm 11 with ``dinv``);
+``ALG_PBICGSTAB_RR`` -> the same with residual replacement (Section 4.2).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+ALG_BICGSTAB = 0
+ALG_PBICGSTAB = 1
+ALG_PBICGSTAB_RR = 2
+
+SUCCESS, MAXIT, BREAKDOWN, NONFINITE = 0, 1, 2, 3
+STATUS_NAMES = {0: "success", 1: "maxit", 2: "breakdown", 3: "nonfinite"}
+
+_lib = None
+
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def build() -> None:
+    """Compile ``oracle.c`` into ``liboracle.so`` (gcc, -ffp-contract=off)."""
+    subprocess.run(["sh", os.path.join(_HERE, "build.sh")], check=True)
+
+
+def _nullable(ptr_type):
+    """ndpointer that also accepts None (passed as NULL)."""
+
+    class _P(ptr_type):
+        @classmethod
+        def from_param(cls, obj):
+            if obj is None:
+                return None
+            return ptr_type.from_param(obj)
+
+    return _P
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.or_assemble_nnz.restype = ctypes.c_int64
+        L.or_assemble_nnz.argtypes = [ctypes.c_int32] * 3
+        L.or_assemble.restype = ctypes.c_int64
+        L.or_assemble.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _f64p,
+                                  _nullable(_f64p), ctypes.c_double, _i32p, _i32p, _f64p]
+        L.or_spmv.restype = None
+        L.or_spmv.argtypes = [ctypes.c_int32, _i32p, _i32p, _f64p, _f64p, _f64p]
+        L.or_dot.restype = ctypes.c_double
+        L.or_dot.argtypes = [ctypes.c_int64, _f64p, _f64p]
+        L.or_pairwise_sum.restype = ctypes.c_double
+        L.or_pairwise_sum.argtypes = [ctypes.c_int64, _f64p]
+        L.or_jacobi_dinv.restype = ctypes.c_int
+        L.or_jacobi_dinv.argtypes = [ctypes.c_int32, _i32p, _i32p, _f64p, _f64p]
+        L.or_solve.restype = ctypes.c_int
+        L.or_solve.argtypes = [ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _f64p,
+                               _nullable(_f64p), _f64p, _f64p, ctypes.c_double, ctypes.c_int32,
+                               ctypes.c_int32, ctypes.c_int32, _nullable(_f64p), _nullable(_f64p),
+                               _i32p, _f64p]
+        L.or_counters_get.restype = None
+        L.or_counters_get.argtypes = [np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")]
+        L.or_counters_reset.restype = None
+        L.or_counters_reset.argtypes = []
+        L.or_set_threads.restype = None
+        L.or_set_threads.argtypes = [ctypes.c_int32]
+        L.or_get_threads.restype = ctypes.c_int32
+        L.or_get_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def set_threads(t: int) -> None:
+    lib().or_set_threads(int(t))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
+
+
+class CSR:
+    """Host CSR matrix: int32 row_ptr[n+1], int32 col[nnz], float64 val[nnz]."""
+
+    def __init__(self, row_ptr, col, val):
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.val = np.ascontiguousarray(val, dtype=np.float64)
+        self.n = len(self.row_ptr) - 1
+
+    @property
+    def nnz(self) -> int:
+        return len(self.val)
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.col, self.row_ptr), shape=(self.n, self.n))
+
+
+def assemble_nnz(dim: int, n: int, npts: int) -> int:
+    return int(lib().or_assemble_nnz(dim, n, npts))
+
+
+def assemble(dim: int, n: int, npts: int, beta, kappa=None, shift: float = 0.0) -> CSR:
+    """The convection-diffusion operator of the workloads, assembled plainly in C."""
+    nnz = assemble_nnz(dim, n, npts)
+    if nnz < 0:
+        raise ValueError(f"unsupported operator dim={dim} npts={npts} n={n}")
+    N = n ** dim
+    rp = np.zeros(N + 1, np.int32)
+    col = np.zeros(nnz, np.int32)
+    val = np.zeros(nnz, np.float64)
+    b = np.zeros(3, np.float64)
+    b[:dim] = beta
+    k = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+    got = lib().or_assemble(dim, n, npts, b, k, float(shift), rp, col, val)
+    if got != nnz:
+        raise RuntimeError("oracle assembly failed")
+    return CSR(rp, col, val)
+
+
+def assemble_workload(w, kappa=None) -> CSR:
+    """Assemble a :class:`paper_1612_01395_amd.inputs.Workload`."""
+    return assemble(w.dim, w.n, w.npts, w.beta, kappa, w.shift)
+
+
+def spmv(A: CSR, x) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(A.n, np.float64)
+    lib().or_spmv(A.n, A.row_ptr, A.col, A.val, x, y)
+    return y
+
+
+def dot(x, y) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    return float(lib().or_dot(len(x), x, y))
+
+
+def pairwise_sum(a) -> float:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return float(lib().or_pairwise_sum(len(a), a))
+
+
+def jacobi_dinv(A: CSR) -> np.ndarray:
+    d = np.empty(A.n, np.float64)
+    st = lib().or_jacobi_dinv(A.n, A.row_ptr, A.col, A.val, d)
+    if st != 0:
+        raise ValueError("zero or missing diagonal entry")
+    return d
+
+
+def solve(A: CSR, b, *, algo: int = ALG_PBICGSTAB_RR, dinv=None, x0=None, tol: float = 1e-8,
+          maxit: int = 2000, rr_period: int = 50, rr_max: int = -1, history: bool = False,
+          scalars: bool = False):
+    """Run one solver of the paper; returns ``(x, info)``.
+
+    ``info`` holds iters, n_rr, status, relres_rec (last ||r_i||/||r_0||),
+    relres_true (||b - A x|| / ||r_0||) and, on request, the residual
+    history (length maxit+1) and the per-iteration scalars alpha, omega, beta.
+    """
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    dv = None if dinv is None else np.ascontiguousarray(dinv, dtype=np.float64)
+    hist = np.full(maxit + 1, np.nan) if history else None
+    sc = np.full(3 * max(maxit, 1), np.nan) if scalars else None
+    ints = np.zeros(3, np.int32)
+    dbl = np.zeros(2, np.float64)
+    st = lib().or_solve(algo, A.n, A.row_ptr, A.col, A.val, dv, b, x, float(tol), int(maxit),
+                        int(rr_period), int(rr_max), hist, sc, ints, dbl)
+    if st < 0:
+        raise ValueError(f"oracle solve failed with code {st}")
+    info = {"iters": int(ints[0]), "n_rr": int(ints[1]), "status": int(ints[2]),
+            "relres_rec": float(dbl[0]), "relres_true": float(dbl[1])}
+    if history:
+        info["history"] = hist[: info["iters"] + 1]
+    if scalars:
+        info["scalars"] = sc[: 3 * info["iters"]].reshape(-1, 3)
+    return x, info
+
+
+def counters() -> dict:
+    out = np.zeros(6, np.int64)
+    lib().or_counters_get(out)
+    return dict(zip(["spmv", "pc", "glred", "dots", "flops", "rec"], (int(v) for v in out)))
+
+
+def reset_counters() -> None:
+    lib().or_counters_reset()

@@ -1,0 +1,606 @@
+/*
+ * CPU oracle for the pipelined BiCGStab solvers -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously correct FP64 reference used by the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark.  It shares no code
+ * with the HIP library and the product path never loads it.
+ *
+ * Source: S. Cools, W. Vanroose, "The communication-hiding pipelined BiCGStab
+ * method for the parallel solution of large unsymmetric linear systems"
+ * (arXiv 1612.01395).  The paper numbers its listings in order of
+ * appearance; the solvers below follow them step by step, in the paper's
+ * order and notation:
+ *
+ *   Algorithm 7   standard BiCGStab                     (Section 3.1)
+ *   Algorithm 9   pipelined BiCGStab, unpreconditioned   (Section 3.3)
+ *   Algorithm 10  right-preconditioned BiCGStab          (Section 3.6)
+ *   Algorithm 11  preconditioned pipelined BiCGStab      (Section 3.6)
+ *
+ * Residual replacement follows Section 4.2: every k iterations r, r^, w and
+ * s, s^, z are recomputed from their definitions (4 SpMVs + 2 preconditioner
+ * applications).  Stopping test: ||r_i||_2 / ||r_0||_2 <= tol on the
+ * recursive residual (Section 4.1).
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *  - shadow residual r~ = r_0; quantities with index -1 are zero, omega_{-1}=0;
+ *  - alpha_{i+1} uses the four-dot expression (eq. 3), not eq. (5);
+ *  - residual replacement in iteration i with (i+1) mod k == 0: r, r^, w are
+ *    replaced after the x-update of iteration i (so the second reduction,
+ *    beta_i, alpha_{i+1}, w^ and t all see the true values) and s, s^, z
+ *    are replaced at the start of iteration i+1, right after the p^ update;
+ *  - breakdown: (y,y) = 0 means q = 0, i.e. exact convergence: x += alpha p^;
+ *    a zero denominator elsewhere, or omega = 0, stops with BREAKDOWN;
+ *  - floating point: every + and * is one binary64 operation in the written
+ *    order (built with -ffp-contract=off, so no fused multiply-add);
+ *    the SpMV sums each row in stored (ascending column) order starting from
+ *    0.0; a dot product (x,y) is the sum of the rounded products x_i*y_i in
+ *    pairwise order -- the balanced binary tree over the index range padded
+ *    with zeros to a power of two -- followed by "+ 0.0" so that a zero sum
+ *    is always +0.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_SUCCESS 0
+#define OR_MAXIT 1
+#define OR_BREAKDOWN 2
+#define OR_NONFINITE 3
+#define OR_ERR_INVALID_ARG (-1)
+#define OR_ERR_ALLOC (-2)
+
+#define PAR _Pragma("omp parallel for schedule(static)")
+
+/* ------------------------------------------------------------------------ */
+/* counters used to check the per-iteration cost model of Table 1            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t spmv;   /* sparse matrix-vector products                        */
+    int64_t pc;     /* preconditioner applications M^{-1} v                 */
+    int64_t glred;  /* global reduction phases (groups of dot products)     */
+    int64_t dots;   /* dot products counted by the paper (no norm of r)     */
+    int64_t flops;  /* AXPY + dot flops per vector element (the "x N")      */
+    int64_t rec;    /* recurrence (AXPY) lines executed                      */
+} or_counters;
+
+static or_counters g_ctr;
+
+void or_counters_get(int64_t* out6)
+{
+    out6[0] = g_ctr.spmv; out6[1] = g_ctr.pc; out6[2] = g_ctr.glred;
+    out6[3] = g_ctr.dots; out6[4] = g_ctr.flops; out6[5] = g_ctr.rec;
+}
+
+void or_counters_reset(void) { memset(&g_ctr, 0, sizeof g_ctr); }
+
+/* ------------------------------------------------------------------------ */
+/* matrix assembly (the workload definition, not part of the method)         */
+/* ------------------------------------------------------------------------ */
+
+/* Number of stored entries of the convection-diffusion operator. */
+int64_t or_assemble_nnz(int32_t dim, int32_t n, int32_t npts)
+{
+    int64_t m = n;
+    if (n <= 0) return -1;
+    if (dim == 2 && npts == 5) return 5 * m * m - 4 * m;
+    if (dim == 3 && npts == 7) return 7 * m * m * m - 6 * m * m;
+    if (dim == 3 && npts == 27) return (3 * m - 2) * (3 * m - 2) * (3 * m - 2);
+    return -1;
+}
+
+/*
+ * h^2-scaled upwind convection-diffusion operator on the n^dim interior
+ * nodes of the unit square/cube, homogeneous Dirichlet boundaries (couplings
+ * to boundary nodes are not stored), rows ordered x fastest, columns
+ * ascending within a row.
+ *
+ *   hb_a = beta_a / (n + 1)
+ *   5/7-point:  off-diagonal -1, plus -|hb_a| on the upwind neighbour of axis
+ *               a (p - e_a if beta_a >= 0, else p + e_a);
+ *               diagonal (4 + |hbx|) + |hby|   or   ((6 + |hbx|) + |hby|) + |hbz|
+ *   27-point:   kbar_d = mean of the cell coefficients kappa shared by node p
+ *               and its neighbour p + d (4, 2 or 1 cells), summed c, b, a
+ *               lexicographically then scaled by 1/count; coupling -kbar_d,
+ *               plus -|hb_a| on the upwind face of axis a; diagonal
+ *               (sum_d kbar_d over all 26 d + ((|hbx| + |hby|) + |hbz|)) + shift.
+ *
+ * Returns nnz, or -1 for unsupported arguments.
+ */
+int64_t or_assemble(int32_t dim, int32_t n, int32_t npts, const double* beta,
+                    const double* kappa, double shift,
+                    int32_t* row_ptr, int32_t* col, double* val)
+{
+    int64_t nnz_expected = or_assemble_nnz(dim, n, npts);
+    if (nnz_expected < 0 || beta == NULL) return -1;
+    if (npts == 27 && kappa == NULL) return -1;
+    const int nz = (dim == 3) ? n : 1;
+    const int64_t nn = (int64_t)n * n;
+    double hb[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < dim; ++a) hb[a] = beta[a] / (double)(n + 1);
+    const int64_t cn = n + 1; /* cells per axis */
+
+    int64_t pos = 0;
+    row_ptr[0] = 0;
+    for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+        const int64_t row = i + (int64_t)n * j + nn * k;
+        if (npts == 5 || npts == 7) {
+            /* entries in ascending column order: (-z), -y, -x, diagonal, +x, +y, (+z);
+             * entry e is axis ax[e] on side sd[e] (sd 0 marks the diagonal) */
+            static const int ax3[7] = {2, 1, 0, 0, 0, 1, 2}, sd3[7] = {-1, -1, -1, 0, 1, 1, 1};
+            static const int ax2[5] = {1, 0, 0, 0, 1}, sd2[5] = {-1, -1, 0, 1, 1};
+            const int* ax = (dim == 3) ? ax3 : ax2;
+            const int* sd = (dim == 3) ? sd3 : sd2;
+            for (int e = 0; e < npts; ++e) {
+                if (sd[e] == 0) {
+                    double d;
+                    if (dim == 2) d = (4.0 + fabs(hb[0])) + fabs(hb[1]);
+                    else d = ((6.0 + fabs(hb[0])) + fabs(hb[1])) + fabs(hb[2]);
+                    col[pos] = (int32_t)row;
+                    val[pos] = d;
+                    ++pos;
+                    continue;
+                }
+                const int a = ax[e], side = sd[e];
+                int ci = i, cj = j, ck = k;
+                if (a == 0) ci += side;
+                if (a == 1) cj += side;
+                if (a == 2) ck += side;
+                if (ci < 0 || ci >= n || cj < 0 || cj >= n || ck < 0 || ck >= nz) continue;
+                /* upwind neighbour: p - e_a for beta_a >= 0, p + e_a otherwise */
+                int upwind = (beta[a] >= 0.0) ? (side < 0) : (side > 0);
+                col[pos] = (int32_t)(ci + (int64_t)n * cj + nn * ck);
+                val[pos] = upwind ? (-1.0 - fabs(hb[a])) : -1.0;
+                ++pos;
+            }
+        } else {
+            /* 27-point: offsets in (dz, dy, dx) lexicographic order */
+            double diag_sum = 0.0;
+            int64_t diag_pos = -1;
+            for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0 && dz == 0) {
+                    diag_pos = pos;
+                    col[pos] = (int32_t)row;
+                    val[pos] = 0.0; /* filled in below */
+                    ++pos;
+                    continue;
+                }
+                /* cells shared by node p and p + d */
+                int alo = (dx > 0) ? 1 : 0, ahi = (dx < 0) ? 0 : 1;
+                int blo = (dy > 0) ? 1 : 0, bhi = (dy < 0) ? 0 : 1;
+                int clo = (dz > 0) ? 1 : 0, chi = (dz < 0) ? 0 : 1;
+                double ksum = 0.0;
+                int count = 0;
+                for (int c = clo; c <= chi; ++c)
+                for (int b = blo; b <= bhi; ++b)
+                for (int a = alo; a <= ahi; ++a) {
+                    ksum = ksum + kappa[(i + a) + cn * ((j + b) + cn * (k + c))];
+                    ++count;
+                }
+                double kbar = ksum * (1.0 / (double)count);
+                diag_sum = diag_sum + kbar;
+                int ci = i + dx, cj = j + dy, ck = k + dz;
+                if (ci < 0 || ci >= n || cj < 0 || cj >= n || ck < 0 || ck >= n) continue;
+                double v = -kbar;
+                int nzc = (dx != 0) + (dy != 0) + (dz != 0);
+                if (nzc == 1) {
+                    int a = (dx != 0) ? 0 : ((dy != 0) ? 1 : 2);
+                    int side = (dx != 0) ? dx : ((dy != 0) ? dy : dz);
+                    int upwind = (beta[a] >= 0.0) ? (side < 0) : (side > 0);
+                    if (upwind) v = -kbar - fabs(hb[a]);
+                }
+                col[pos] = (int32_t)(ci + (int64_t)n * cj + nn * ck);
+                val[pos] = v;
+                ++pos;
+            }
+            val[diag_pos] = (diag_sum + ((fabs(hb[0]) + fabs(hb[1])) + fabs(hb[2]))) + shift;
+        }
+        row_ptr[row + 1] = (int32_t)pos;
+    }
+    return (pos == nnz_expected) ? pos : -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* kernels of the method: SpMV, dot product, Jacobi                          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n;
+    const int32_t* rp;
+    const int32_t* ci;
+    const double* va;
+} csr_t;
+
+/* y := A x, each row summed in stored order from 0.0 (Section 2: SPMV). */
+static void spmv(const csr_t* A, const double* x, double* y)
+{
+    PAR for (int32_t i = 0; i < A->n; ++i) {
+        double acc = 0.0;
+        for (int32_t k = A->rp[i]; k < A->rp[i + 1]; ++k) acc = acc + A->va[k] * x[A->ci[k]];
+        y[i] = acc;
+    }
+    g_ctr.spmv++;
+}
+
+void or_spmv(int32_t n, const int32_t* rp, const int32_t* ci, const double* va,
+             const double* x, double* y)
+{
+    csr_t A = {n, rp, ci, va};
+    spmv(&A, x, y);
+}
+
+/* Sum of a[0 .. len), len a power of two: left half + right half. */
+static double pairwise(const double* a, int64_t len)
+{
+    if (len == 1) return a[0];
+    return pairwise(a, len / 2) + pairwise(a + len / 2, len / 2);
+}
+
+/* The same tree with the 64 top subtrees evaluated by separate threads. */
+static double pairwise_par(const double* a, int64_t len)
+{
+    if (len < (1 << 16)) return pairwise(a, len);
+    double part[64];
+    const int64_t bl = len / 64;
+    PAR for (int b = 0; b < 64; ++b) part[b] = pairwise(a + b * bl, bl);
+    return pairwise(part, 64);
+}
+
+static int64_t pow2_at_least(int64_t n)
+{
+    int64_t p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+/* (x, y) = sum_i x_i y_i in pairwise order; prod is scratch of pow2(n). */
+static double dot_ws(int64_t n, const double* x, const double* y, double* prod)
+{
+    const int64_t len = pow2_at_least(n);
+    PAR for (int64_t i = 0; i < len; ++i) prod[i] = (i < n) ? x[i] * y[i] : 0.0;
+    return pairwise_par(prod, len) + 0.0;
+}
+
+double or_dot(int64_t n, const double* x, const double* y)
+{
+    if (n <= 0) return 0.0;
+    double* prod = (double*)malloc(sizeof(double) * (size_t)pow2_at_least(n));
+    if (!prod) return NAN;
+    double s = dot_ws(n, x, y, prod);
+    free(prod);
+    return s;
+}
+
+/* The pairwise sum of a plain array (used to check the tree order). */
+double or_pairwise_sum(int64_t n, const double* a)
+{
+    if (n <= 0) return 0.0;
+    const int64_t len = pow2_at_least(n);
+    double* buf = (double*)calloc((size_t)len, sizeof(double));
+    if (!buf) return NAN;
+    memcpy(buf, a, sizeof(double) * (size_t)n);
+    double s = pairwise_par(buf, len) + 0.0;
+    free(buf);
+    return s;
+}
+
+/* Jacobi: M = diag(A), dinv_i = 1 / a_ii.  Error if a diagonal is absent or 0. */
+int or_jacobi_dinv(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, double* dinv)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i) d = va[k];
+        if (d == 0.0 || !isfinite(d)) return OR_ERR_INVALID_ARG;
+        dinv[i] = 1.0 / d;
+    }
+    return OR_SUCCESS;
+}
+
+/* ------------------------------------------------------------------------ */
+/* solver bookkeeping                                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double tol;
+    int32_t maxit;
+    int32_t rr_period;  /* k; 0 disables residual replacement */
+    int32_t rr_max;     /* -1: unlimited */
+    double* history;    /* NULL or maxit+1 entries: ||r_i|| / ||r_0|| */
+    double* scalars;    /* NULL or 3*maxit entries: alpha_i, omega_i, beta_i */
+} or_opts;
+
+typedef struct {
+    int32_t iters, n_rr, status;
+    double relres_rec;
+    double relres_true;
+} or_info;
+
+#define DOT(a, b) dot_ws(n, (a), (b), prod)
+#define NEWVEC(p) do { (p) = (double*)calloc((size_t)n, sizeof(double)); if (!(p)) goto oom; } while (0)
+#define FLOPS(k) (g_ctr.flops += (k))
+#define REC(k) (g_ctr.rec += (k))
+
+static int rr_due(const or_opts* o, int32_t i, int32_t n_rr)
+{
+    if (o->rr_period <= 0) return 0;
+    if ((i + 1) % o->rr_period != 0) return 0;
+    return (o->rr_max < 0) || (n_rr < o->rr_max);
+}
+
+static void finish(const csr_t* A, const double* b, const double* x, double rho0,
+                   double* tmp, double* prod, or_info* info)
+{
+    const int32_t n = A->n;
+    spmv(A, x, tmp);
+    g_ctr.spmv--; /* the final true residual is bookkeeping, not an iteration cost */
+    PAR for (int32_t j = 0; j < n; ++j) tmp[j] = b[j] - tmp[j];
+    double nr = dot_ws(n, tmp, tmp, prod);
+    info->relres_true = (rho0 > 0.0) ? sqrt(nr) / rho0 : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 7 (standard BiCGStab) and Alg. 10 (its right-preconditioned form,    */
+/* A M^{-1} y = b, M x = y).  dinv == NULL selects Alg. 7.                   */
+/* ------------------------------------------------------------------------ */
+static int bicgstab(const csr_t* A, const double* dinv, const double* b, double* x,
+                    const or_opts* o, or_info* info)
+{
+    const int32_t n = A->n;
+    const int pc = (dinv != NULL);
+    double *r0 = 0, *r = 0, *p = 0, *ph = 0, *s = 0, *q = 0, *qh = 0, *y = 0, *tmp = 0, *prod = 0;
+    NEWVEC(r0); NEWVEC(r); NEWVEC(p); NEWVEC(s); NEWVEC(q); NEWVEC(y); NEWVEC(tmp);
+    if (pc) { NEWVEC(ph); NEWVEC(qh); } else { ph = p; qh = q; }
+    prod = (double*)malloc(sizeof(double) * (size_t)pow2_at_least(n));
+    if (!prod) goto oom;
+
+    info->iters = 0; info->n_rr = 0; info->relres_rec = 0.0; info->relres_true = 0.0;
+    /* l.2: r_0 := b - A x_0 ; p_0 := r_0 */
+    spmv(A, x, tmp);
+    PAR for (int32_t j = 0; j < n; ++j) r0[j] = b[j] - tmp[j];
+    double gamma = DOT(r0, r0); /* (r_0, r_0) = (r_0, r_i) at i = 0 */
+    const double rho0 = sqrt(gamma);
+    if (o->history) o->history[0] = 1.0;
+    info->relres_rec = 1.0;
+    if (!isfinite(rho0)) { info->status = OR_NONFINITE; goto done; }
+    if (rho0 == 0.0) { info->status = OR_SUCCESS; info->relres_rec = 0.0; goto done; }
+    memcpy(r, r0, sizeof(double) * (size_t)n);
+    memcpy(p, r0, sizeof(double) * (size_t)n);
+
+    for (int32_t i = 0; i < o->maxit; ++i) {
+        /* l.4-5 (Alg. 10): p^_i := M^{-1} p_i ; s_i := A p^_i */
+        if (pc) { PAR for (int32_t j = 0; j < n; ++j) ph[j] = dinv[j] * p[j]; g_ctr.pc++; }
+        spmv(A, ph, s);
+        /* reduction (r_0, s_i) ; alpha_i := (r_0, r_i) / (r_0, s_i) */
+        double delta = DOT(r0, s);
+        g_ctr.glred++; g_ctr.dots++; FLOPS(2);
+        if (!isfinite(delta)) { info->status = OR_NONFINITE; goto done; }
+        if (delta == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+        double alpha = gamma / delta;
+        if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
+        /* q_i := r_i - alpha_i s_i ; q^_i := M^{-1} q_i ; y_i := A q^_i */
+        PAR for (int32_t j = 0; j < n; ++j) q[j] = r[j] - alpha * s[j];
+        FLOPS(2); REC(1);
+        if (pc) { PAR for (int32_t j = 0; j < n; ++j) qh[j] = dinv[j] * q[j]; g_ctr.pc++; }
+        spmv(A, qh, y);
+        /* reduction (q_i, y_i), (y_i, y_i) ; omega_i := (q_i, y_i) / (y_i, y_i) */
+        double th1 = DOT(q, y), th2 = DOT(y, y);
+        g_ctr.glred++; g_ctr.dots += 2; FLOPS(4);
+        if (!isfinite(th1) || !isfinite(th2)) { info->status = OR_NONFINITE; goto done; }
+        if (th2 == 0.0) {
+            /* y_i = A q^_i = 0 means q_i = 0: x_i + alpha_i p^_i solves the system */
+            PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * ph[j];
+            info->iters = i + 1; info->relres_rec = 0.0; info->status = OR_SUCCESS;
+            if (o->history) o->history[i + 1] = 0.0;
+            goto done;
+        }
+        double omega = th1 / th2;
+        if (!isfinite(omega)) { info->status = OR_NONFINITE; goto done; }
+        /* x_{i+1} := x_i + alpha_i p^_i + omega_i q^_i ; r_{i+1} := q_i - omega_i y_i */
+        PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * ph[j] + omega * qh[j];
+        PAR for (int32_t j = 0; j < n; ++j) r[j] = q[j] - omega * y[j];
+        FLOPS(4 + 2); REC(2);
+        info->iters = i + 1;
+        /* reduction (r_0, r_{i+1}) together with the norm for the stopping test */
+        double gamma1 = DOT(r0, r), nu = DOT(r, r);
+        g_ctr.glred++; g_ctr.dots++; FLOPS(2);
+        if (o->scalars) { o->scalars[3 * i] = alpha; o->scalars[3 * i + 1] = omega; }
+        if (!isfinite(gamma1) || !isfinite(nu)) { info->status = OR_NONFINITE; goto done; }
+        info->relres_rec = sqrt(nu) / rho0;
+        if (o->history) o->history[i + 1] = info->relres_rec;
+        if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
+        if (omega == 0.0 || gamma == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+        /* beta_i := (alpha_i / omega_i) (r_0, r_{i+1}) / (r_0, r_i) */
+        double beta = (alpha / omega) * (gamma1 / gamma);
+        if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }
+        if (o->scalars) o->scalars[3 * i + 2] = beta;
+        /* p_{i+1} := r_{i+1} + beta_i (p_i - omega_i s_i) */
+        PAR for (int32_t j = 0; j < n; ++j) p[j] = r[j] + beta * (p[j] - omega * s[j]);
+        FLOPS(4); REC(1);
+        gamma = gamma1;
+    }
+    info->status = OR_MAXIT;
+done:
+    finish(A, b, x, rho0, tmp, prod, info);
+    free(r0); free(r); free(p); free(s); free(q); free(y); free(tmp); free(prod);
+    if (pc) { free(ph); free(qh); }
+    return info->status;
+oom:
+    free(r0); free(r); free(p); free(s); free(q); free(y); free(tmp); free(prod);
+    if (pc) { free(ph); free(qh); }
+    return OR_ERR_ALLOC;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 9 (p-BiCGStab) and Alg. 11 (preconditioned p-BiCGStab), with the    */
+/* residual replacement of Section 4.2.  dinv == NULL selects Alg. 9, where  */
+/* every hatted vector is the unhatted one.                                  */
+/* ------------------------------------------------------------------------ */
+static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double* x,
+                     const or_opts* o, or_info* info)
+{
+    const int32_t n = A->n;
+    const int pc = (dinv != NULL);
+    double *r0 = 0, *r = 0, *rh = 0, *w = 0, *wh = 0, *t = 0, *ph = 0, *s = 0, *sh = 0;
+    double *z = 0, *zh = 0, *v = 0, *q = 0, *qh = 0, *y = 0, *tmp = 0, *prod = 0;
+    NEWVEC(r0); NEWVEC(r); NEWVEC(w); NEWVEC(t); NEWVEC(ph); NEWVEC(s); NEWVEC(z);
+    NEWVEC(v); NEWVEC(q); NEWVEC(y); NEWVEC(tmp);
+    if (pc) { NEWVEC(rh); NEWVEC(wh); NEWVEC(sh); NEWVEC(zh); NEWVEC(qh); }
+    else { rh = r; wh = w; sh = s; zh = z; qh = q; }
+    prod = (double*)malloc(sizeof(double) * (size_t)pow2_at_least(n));
+    if (!prod) goto oom;
+
+    info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
+    /* l.2: r_0 := b - A x_0 ; r^_0 := M^{-1} r_0 ; w_0 := A r^_0 ; w^_0 := M^{-1} w_0 */
+    spmv(A, x, tmp);
+    PAR for (int32_t j = 0; j < n; ++j) r0[j] = b[j] - tmp[j];
+    double gamma = DOT(r0, r0); /* (r_0, r_0) */
+    const double rho0 = sqrt(gamma);
+    if (o->history) o->history[0] = 1.0;
+    if (!isfinite(rho0)) { info->status = OR_NONFINITE; goto done; }
+    if (rho0 == 0.0) { info->status = OR_SUCCESS; info->relres_rec = 0.0; goto done; }
+    memcpy(r, r0, sizeof(double) * (size_t)n);
+    if (pc) { PAR for (int32_t j = 0; j < n; ++j) rh[j] = dinv[j] * r[j]; g_ctr.pc++; }
+    spmv(A, rh, w);
+    if (pc) { PAR for (int32_t j = 0; j < n; ++j) wh[j] = dinv[j] * w[j]; g_ctr.pc++; }
+    /* l.3: t_0 := A w^_0 ; alpha_0 := (r_0, r_0) / (r_0, w_0) ; beta_{-1} := 0 */
+    spmv(A, wh, t);
+    double delta = DOT(r0, w);
+    if (!isfinite(delta)) { info->status = OR_NONFINITE; goto done; }
+    if (delta == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+    double alpha = gamma / delta, beta = 0.0, omega = 0.0;
+    if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
+    /* p^_{-1} = s_{-1} = s^_{-1} = z_{-1} = z^_{-1} = v_{-1} = 0 (calloc) */
+    int rr_pending = 0;
+    int32_t n_rr = 0;
+
+    for (int32_t i = 0; i < o->maxit; ++i) {
+        /* l.5: p^_i := r^_i + beta_{i-1} (p^_{i-1} - omega_{i-1} s^_{i-1}) */
+        PAR for (int32_t j = 0; j < n; ++j) ph[j] = rh[j] + beta * (ph[j] - omega * sh[j]);
+        FLOPS(4); REC(1);
+        if (rr_pending) {
+            /* residual replacement, second half: s_i := A p^_i ; s^_i := M^{-1} s_i ; z_i := A s^_i */
+            spmv(A, ph, s);
+            if (pc) { PAR for (int32_t j = 0; j < n; ++j) sh[j] = dinv[j] * s[j]; g_ctr.pc++; }
+            spmv(A, sh, z);
+            rr_pending = 0;
+        } else {
+            /* l.6: s_i := w_i + beta_{i-1} (s_{i-1} - omega_{i-1} z_{i-1}) */
+            PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + beta * (s[j] - omega * z[j]);
+            /* l.7: s^_i := w^_i + beta_{i-1} (s^_{i-1} - omega_{i-1} z^_{i-1}) */
+            if (pc) PAR for (int32_t j = 0; j < n; ++j) sh[j] = wh[j] + beta * (sh[j] - omega * zh[j]);
+            /* l.8: z_i := t_i + beta_{i-1} (z_{i-1} - omega_{i-1} v_{i-1}) */
+            PAR for (int32_t j = 0; j < n; ++j) z[j] = t[j] + beta * (z[j] - omega * v[j]);
+            FLOPS(pc ? 12 : 8); REC(pc ? 3 : 2);
+        }
+        /* l.9-11: q_i := r_i - alpha_i s_i ; q^_i := r^_i - alpha_i s^_i ; y_i := w_i - alpha_i z_i */
+        PAR for (int32_t j = 0; j < n; ++j) q[j] = r[j] - alpha * s[j];
+        if (pc) PAR for (int32_t j = 0; j < n; ++j) qh[j] = rh[j] - alpha * sh[j];
+        PAR for (int32_t j = 0; j < n; ++j) y[j] = w[j] - alpha * z[j];
+        FLOPS(pc ? 6 : 4); REC(pc ? 3 : 2);
+        /* l.12: begin reduction (q_i, y_i), (y_i, y_i) */
+        double th1 = DOT(q, y), th2 = DOT(y, y);
+        g_ctr.glred++; g_ctr.dots += 2; FLOPS(4);
+        /* l.13-14: z^_i := M^{-1} z_i ; v_i := A z^_i  (overlapping the reduction) */
+        if (pc) { PAR for (int32_t j = 0; j < n; ++j) zh[j] = dinv[j] * z[j]; g_ctr.pc++; }
+        spmv(A, zh, v);
+        /* l.15-16: end reduction ; omega_i := (q_i, y_i) / (y_i, y_i) */
+        if (!isfinite(th1) || !isfinite(th2)) { info->status = OR_NONFINITE; goto done; }
+        if (th2 == 0.0) {
+            PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * ph[j];
+            info->iters = i + 1; info->relres_rec = 0.0; info->status = OR_SUCCESS;
+            if (o->history) o->history[i + 1] = 0.0;
+            goto done;
+        }
+        omega = th1 / th2;
+        if (!isfinite(omega)) { info->status = OR_NONFINITE; goto done; }
+        /* l.17: x_{i+1} := x_i + alpha_i p^_i + omega_i q^_i */
+        PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * ph[j] + omega * qh[j];
+        /* l.18: r_{i+1} := q_i - omega_i y_i */
+        PAR for (int32_t j = 0; j < n; ++j) r[j] = q[j] - omega * y[j];
+        /* l.19: r^_{i+1} := q^_i - omega_i (w^_i - alpha_i z^_i) */
+        if (pc) PAR for (int32_t j = 0; j < n; ++j) rh[j] = qh[j] - omega * (wh[j] - alpha * zh[j]);
+        /* l.20: w_{i+1} := y_i - omega_i (t_i - alpha_i v_i) */
+        PAR for (int32_t j = 0; j < n; ++j) w[j] = y[j] - omega * (t[j] - alpha * v[j]);
+        FLOPS(pc ? 14 : 10); REC(pc ? 4 : 3);
+        info->iters = i + 1;
+        if (rr_due(o, i, n_rr)) {
+            /* residual replacement, first half: r := b - A x ; r^ := M^{-1} r ; w := A r^ */
+            spmv(A, x, tmp);
+            PAR for (int32_t j = 0; j < n; ++j) r[j] = b[j] - tmp[j];
+            if (pc) { PAR for (int32_t j = 0; j < n; ++j) rh[j] = dinv[j] * r[j]; g_ctr.pc++; }
+            spmv(A, rh, w);
+            rr_pending = 1;
+            ++n_rr;
+            info->n_rr = n_rr;
+        }
+        /* l.21: begin reduction (r_0,r_{i+1}), (r_0,w_{i+1}), (r_0,s_i), (r_0,z_i), plus ||r_{i+1}||^2 */
+        double gamma1 = DOT(r0, r), eta = DOT(r0, w), sig_s = DOT(r0, s), sig_z = DOT(r0, z);
+        double nu = DOT(r, r);
+        g_ctr.glred++; g_ctr.dots += 4; FLOPS(8);
+        if (o->scalars) { o->scalars[3 * i] = alpha; o->scalars[3 * i + 1] = omega; }
+        if (!isfinite(gamma1) || !isfinite(eta) || !isfinite(sig_s) || !isfinite(sig_z) || !isfinite(nu)) {
+            info->status = OR_NONFINITE; goto done;
+        }
+        info->relres_rec = sqrt(nu) / rho0;
+        if (o->history) o->history[i + 1] = info->relres_rec;
+        if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
+        /* l.22-23: w^_{i+1} := M^{-1} w_{i+1} ; t_{i+1} := A w^_{i+1} */
+        if (pc) { PAR for (int32_t j = 0; j < n; ++j) wh[j] = dinv[j] * w[j]; g_ctr.pc++; }
+        spmv(A, wh, t);
+        /* l.24-26: end reduction ; beta_i ; alpha_{i+1} by eq. (3) */
+        if (omega == 0.0 || gamma == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+        beta = (alpha / omega) * (gamma1 / gamma);
+        if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }
+        if (o->scalars) o->scalars[3 * i + 2] = beta;
+        double den = eta + beta * sig_s - beta * omega * sig_z;
+        if (den == 0.0 || gamma1 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+        alpha = gamma1 / den;
+        if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
+        gamma = gamma1;
+    }
+    info->status = OR_MAXIT;
+done:
+    finish(A, b, x, rho0, tmp, prod, info);
+    free(r0); free(r); free(w); free(t); free(ph); free(s); free(z); free(v); free(q); free(y);
+    free(tmp); free(prod);
+    if (pc) { free(rh); free(wh); free(sh); free(zh); free(qh); }
+    return info->status;
+oom:
+    free(r0); free(r); free(w); free(t); free(ph); free(s); free(z); free(v); free(q); free(y);
+    free(tmp); free(prod);
+    if (pc) { free(rh); free(wh); free(sh); free(zh); free(qh); }
+    return OR_ERR_ALLOC;
+}
+
+/*
+ * Entry point.  algo: 0 BiCGStab (Alg. 7 / 10), 1 p-BiCGStab (Alg. 9 / 11),
+ * 2 p-BiCGStab with residual replacement.  dinv NULL = no preconditioner.
+ * x holds x_0 on entry and the final iterate on return.
+ * ints_out[3] = {iters, n_rr, status}; dbl_out[2] = {relres_rec, relres_true}.
+ */
+int or_solve(int32_t algo, int32_t n, const int32_t* rp, const int32_t* ci, const double* va,
+             const double* dinv, const double* b, double* x,
+             double tol, int32_t maxit, int32_t rr_period, int32_t rr_max,
+             double* history, double* scalars, int32_t* ints_out, double* dbl_out)
+{
+    if (n <= 0 || !rp || !ci || !va || !b || !x || maxit < 0 || !(tol >= 0.0)) return OR_ERR_INVALID_ARG;
+    csr_t A = {n, rp, ci, va};
+    or_opts o = {tol, maxit, (algo == 2) ? rr_period : 0, rr_max, history, scalars};
+    or_info info = {0, 0, 0, 0.0, 0.0};
+    int st;
+    if (algo == 0) st = bicgstab(&A, dinv, b, x, &o, &info);
+    else if (algo == 1 || algo == 2) st = pbicgstab(&A, dinv, b, x, &o, &info);
+    else return OR_ERR_INVALID_ARG;
+    if (st < 0) return st;
+    ints_out[0] = info.iters; ints_out[1] = info.n_rr; ints_out[2] = info.status;
+    dbl_out[0] = info.relres_rec; dbl_out[1] = info.relres_true;
+    return st;
+}
+
+/* Thread control for the OpenMP loops (results do not depend on it). */
+#include <omp.h>
+void or_set_threads(int32_t t) { if (t > 0) omp_set_num_threads(t); }
+int32_t or_get_threads(void) { return (int32_t)omp_get_max_threads(); }
