@@ -1,0 +1,210 @@
+"""Benchmark: p-BiCGStab(+RR) iterations/s and HBM bandwidth on one MI355X,
+against plain BiCGStab on the same GPU.
+
+Workload (the metric's configuration): 3-D 7-point first-order upwind
+convection-diffusion on a 128^3 grid (2,097,152 unknowns, 14,581,760
+non-zeros), h^2-scaled, beta = (50, 30, 10), CSR FP64, Jacobi, x_true ~ U[0,1)
+(seed 1), b = A x_true, x0 = 0, tol 1e-8 on ||r_i||/||r_0||, residual
+replacement every 50 iterations.  Inputs are synthetic and resident in HBM
+before the timed region.
+
+One step = one complete solve (setup, every iteration, the replacements and
+the final true-residual check).  value = iterations / second over the timed
+steps.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--n", type=int, default=128, help="grid side of the 3-D workload")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    p.add_argument("--only", default="", help="comma list of legs to run: pipe,bicg,stencil")
+    return p.parse_args()
+
+
+def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool):
+    """Algorithmic HBM bytes of the two fused kernels of one iteration.
+
+    Every array the kernel touches is counted once: the operator (int32
+    row_ptr, int32 col, f64 val; nothing for the stencil) and one read or
+    write of each N-vector (the gathered SpMV input counted once).  Jacobi
+    with a constant diagonal is a scalar (no dinv vector).
+    p-BiCGStab (Algorithm 11): phase A reads w^, r, w, v, s, z, r^, s^, z^, p^
+    and writes p^, s^, s, t, z, z^ (16 vectors); phase B reads z^, r, s, w, z, t,
+    r^, s^, w^, x, p^, r0 and writes x, v, r, r^, w, w^ (18 vectors).
+    BiCGStab (Algorithm 10), SpMV phases: s = A p^ with (r0, s): reads p^, r0,
+    writes s (3); y = A q^ with (q,y), (y,y): reads q^, q, writes y (3).
+    """
+    vec = 8 * N
+    mat = 0 if stencil else 4 * (N + 1) + 12 * nnz
+    if variant == "bicgstab":
+        return mat + 3 * vec, mat + 3 * vec, 23 * vec + 2 * mat
+    return mat + 16 * vec, mat + 18 * vec, 34 * vec + 2 * mat
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1612_01395_amd import inputs, solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    w = inputs.workload("c2", n=args.n)
+    N = w.N
+    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "stencil"}
+
+    # ---- inputs resident in HBM -------------------------------------------------
+    rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
+    nnz = val.numel()
+    A = solver.csr(rp, col, val)
+    xt = torch.from_numpy(inputs.x_true(N)).to(dev)
+    b = solver.spmv(A, xt)
+    mid = w.n // 2
+    crow = mid + w.n * mid + w.n * w.n * mid  # an interior row: all 7 coefficients
+    coef = val[rp[crow].item(): rp[crow + 1].item()].cpu().tolist()
+    S = solver.stencil(w.n, w.n, w.n, coef) if len(coef) == 7 else None
+    xbuf = torch.empty_like(b)
+    torch.cuda.synchronize()
+
+    common = dict(precond="jacobi", tol=w.tol, maxit=w.maxit, rr_period=w.rr_period)
+
+    def timed_leg(op, variant):
+        for _ in range(args.warmup):
+            solver.solve(op, b, variant=variant, out=xbuf, **common)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = 0
+        last = None
+        for _ in range(args.steps):
+            _, info = solver.solve(op, b, variant=variant, out=xbuf, **common)
+            iters += info.iters
+            last = info
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return iters, dt, last
+
+    res = {}
+    if "pipe" in legs:
+        res["pipe"] = timed_leg(A, "pbicgstab_rr")
+    if "bicg" in legs:
+        res["bicg"] = timed_leg(A, "bicgstab")
+    if "stencil" in legs and S is not None:
+        res["st_pipe"] = timed_leg(S, "pbicgstab_rr")
+        res["st_bicg"] = timed_leg(S, "bicgstab")
+
+    # ---- roofline of the dominant kernel: one solve with per-kernel events -------
+    _, pinfo = solver.solve(A, b, variant="pbicgstab_rr", out=xbuf, time_kernels=True, **common)
+    ba, bb, _ = algorithmic_bytes(N, nnz, "pbicgstab", False)
+    avg = [pinfo.kernel_ms[k] / max(pinfo.kernel_calls[k], 1) for k in range(2)]
+    dom = 0 if pinfo.kernel_ms[0] >= pinfo.kernel_ms[1] else 1
+    dom_bytes = (ba, bb)[dom]
+    achieved = dom_bytes / (avg[dom] * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": ("k_pa (t = A w^, recurrences, (q,y),(y,y))", "k_pb (v = A z^, updates, 5 dots)")[dom],
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "bytes_per_launch": dom_bytes,
+        "avg_launch_us": round(avg[dom] * 1e3, 2),
+        "other_kernel_avg_us": round(avg[1 - dom] * 1e3, 2),
+        "launches_timed": pinfo.kernel_calls[dom],
+    }
+
+    # ---- CPU baseline: the oracle on a bounded sample ---------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        Ah = oracle.assemble_workload(w)
+        bh = b.cpu().numpy()
+        dinv = oracle.jacobi_dinv(Ah)
+        t0 = time.perf_counter()
+        oracle.solve(Ah, bh, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=0.0, maxit=5, rr_period=w.rr_period)
+        per_it = (time.perf_counter() - t0) / 5
+        k = int(max(5, min(w.maxit, args.cpu_seconds / max(per_it, 1e-6))))
+        t0 = time.perf_counter()
+        _, oinfo = oracle.solve(Ah, bh, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=0.0, maxit=k,
+                                rr_period=w.rr_period)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(oinfo["iters"] / dt, 3), "unit": "iters/s", "cores": oracle.get_threads(),
+               "kind": "oracle",
+               "sample": f"{oinfo['iters']} p-BiCGStab+RR iterations (tol 0, fixed count) of the same "
+                         f"{w.n}^3 system from x0 = 0, {dt:.1f} s"}
+
+    it, dt, info = res.get("pipe", (0, 1.0, None))
+    value = it / dt if it else None
+    _, _, per_iter_bytes = algorithmic_bytes(N, nnz, "pbicgstab", False)
+    out = {
+        "metric": "p-BiCGStab iters/sec + HBM GB/s (3D 7-pt 128^3 FP64) vs plain BiCGStab, same GPU",
+        "value": round(value, 2) if value else None,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3-D 7-point upwind convection-diffusion {w.n}^3 (N={N}, nnz={nnz}), "
+                               f"beta=(50,30,10), CSR FP64, Jacobi, tol 1e-8, p-BiCGStab with residual "
+                               f"replacement every {w.rr_period}; one step = one full solve",
+                   "global_batch": 1, "parallelism": "single GPU"},
+        "iters_per_solve": info.iters if info else None,
+        "relres_true": info.relres_true if info else None,
+        "gbps_effective": round(per_iter_bytes * value / 1e9, 1) if value else None,
+        "syncs_per_iter": info.syncs_per_iter if info else None,
+    }
+    if "bicg" in res:
+        bit, bdt, binfo = res["bicg"]
+        bval = bit / bdt
+        _, _, bbytes = algorithmic_bytes(N, nnz, "bicgstab", False)
+        out["bicgstab"] = {"iters_per_s": round(bval, 2), "iters_per_solve": binfo.iters,
+                           "ms_per_solve": round(bdt / args.steps * 1e3, 3),
+                           "gbps_effective": round(bbytes * bval / 1e9, 1), "syncs_per_iter": binfo.syncs_per_iter}
+        if value:
+            out["pbicgstab_over_bicgstab_iters_per_s"] = round(value / bval, 4)
+            out["pbicgstab_over_bicgstab_time_to_solution"] = round((bdt / args.steps) / (dt / args.steps), 4)
+    for key, variant in (("st_pipe", "pbicgstab"), ("st_bicg", "bicgstab")):
+        if key in res:
+            sit, sdt, sinfo = res[key]
+            sval = sit / sdt
+            _, _, sbytes = algorithmic_bytes(N, nnz, variant, True)
+            out.setdefault("stencil", {})[variant] = {
+                "iters_per_s": round(sval, 2), "iters_per_solve": sinfo.iters,
+                "ms_per_solve": round(sdt / args.steps * 1e3, 3), "gbps_effective": round(sbytes * sval / 1e9, 1)}
+    out["roofline"] = roofline
+    out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

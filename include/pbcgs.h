@@ -1,0 +1,175 @@
+/*
+ * pbcgs -- pipelined BiCGStab with residual replacement on one MI355X (gfx950).
+ *
+ * C ABI of the HIP library libpbcgs.so.  It solves A x = b for an unsymmetric
+ * sparse A (CSR, or a matrix-free constant-coefficient 5/7-point stencil)
+ * with one of three Krylov methods of S. Cools and W. Vanroose, "The
+ * communication-hiding pipelined BiCGStab method for the parallel solution of
+ * large unsymmetric linear systems" (arXiv 1612.01395):
+ *
+ *   PBCGS_BICGSTAB       standard BiCGStab, the paper's Algorithm 7, or its
+ *                        right-preconditioned form Algorithm 10 (Section 3.6);
+ *   PBCGS_PBICGSTAB      pipelined BiCGStab, Algorithm 9 (Section 3.3), or the
+ *                        preconditioned pipelined form Algorithm 11 (Section 3.6);
+ *   PBCGS_PBICGSTAB_RR   Algorithm 9/11 with residual replacement every k
+ *                        iterations (Section 4.2).
+ *
+ * Right preconditioning solves A M^{-1} y = b, M x = y (Section 3.6).  The only
+ * preconditioner is Jacobi, M = diag(A).  The stopping test is
+ * ||r_i||_2 / ||r_0||_2 <= tol on the recursive residual (Section 4.1).
+ *
+ * Arithmetic contract (FP64): every + and * is one IEEE binary64 operation in
+ * the order the paper writes it (no fused multiply-add); each SpMV row is
+ * summed in stored column order from 0.0; a dot product is the sum of the
+ * rounded products in pairwise order (balanced binary tree over the index
+ * range padded with zeros to a power of two) plus 0.0.  Results therefore do
+ * not depend on the launch configuration and are reproducible bit for bit.
+ *
+ * Conventions of every call:
+ *  - array arguments are DEVICE pointers unless stated otherwise; the library
+ *    borrows them and never frees them;
+ *  - a negative return value is an API or runtime error (see pbcgs_status);
+ *    then outputs are untouched and pbcgs_last_error() describes the cause;
+ *  - a context serialises all work on one HIP stream; a context is not
+ *    thread-safe, two contexts on the same device are independent.
+ */
+#ifndef PBCGS_H
+#define PBCGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pbcgs_ctx_s* pbcgs_ctx_t;
+typedef struct pbcgs_op_s* pbcgs_op_t;
+
+/* Return codes.  Non-negative: numerical outcome of a solve (x holds the last
+ * iterate).  Negative: the call failed and changed nothing. */
+typedef enum {
+    PBCGS_SUCCESS = 0,            /* ||r_i|| / ||r_0|| <= tol (or r_0 = 0)               */
+    PBCGS_MAXIT = 1,              /* maxit iterations done without meeting tol             */
+    PBCGS_BREAKDOWN = 2,          /* a denominator of the method vanished, or omega = 0    */
+    PBCGS_NONFINITE = 3,          /* a reduced scalar became Inf or NaN                    */
+    PBCGS_ERR_INVALID_ARG = -1,   /* bad pointer, size, option or matrix structure         */
+    PBCGS_ERR_ALLOC = -2,         /* device memory allocation failed                       */
+    PBCGS_ERR_HIP = -3,           /* a HIP runtime call failed                             */
+    PBCGS_ERR_UNSUPPORTED = -4    /* valid request this build does not implement           */
+} pbcgs_status;
+
+enum { PBCGS_BICGSTAB = 0, PBCGS_PBICGSTAB = 1, PBCGS_PBICGSTAB_RR = 2 };
+enum { PBCGS_PRECOND_NONE = 0, PBCGS_PRECOND_JACOBI = 1 };
+enum { PBCGS_FP64 = 0 };
+
+/* Solver options (host struct). */
+typedef struct {
+    int32_t variant;     /* PBCGS_BICGSTAB, PBCGS_PBICGSTAB or PBCGS_PBICGSTAB_RR          */
+    int32_t precond;     /* PBCGS_PRECOND_NONE or PBCGS_PRECOND_JACOBI                     */
+    int32_t precision;   /* PBCGS_FP64                                                      */
+    int32_t maxit;       /* iteration budget, >= 0                                          */
+    double tol;          /* relative tolerance on the recursive residual, >= 0              */
+    int32_t rr_period;   /* k: replace in iteration i when (i+1) mod k == 0; 0 = never      */
+    int32_t rr_max;      /* at most this many replacements; -1 = unlimited                  */
+    int32_t check_every; /* iterations between host polls of the device status; 0 = auto   */
+    int32_t flags;       /* bit 0: launch each kernel directly instead of through a
+                            captured HIP graph; bit 1: time the fused kernels with events  */
+    double* history;     /* nullable DEVICE array of maxit+1 doubles: history[i] =
+                            ||r_i|| / ||r_0|| after i iterations (history[0] = 1)           */
+} pbcgs_opts;
+
+/* Solver report (host struct), filled by pbcgs_solve. */
+typedef struct {
+    int32_t iters;           /* completed x-updates                                       */
+    int32_t n_rr;            /* residual replacements performed                           */
+    int32_t status;          /* pbcgs_status of the numerical outcome                     */
+    int32_t syncs_per_iter;  /* kernel boundaries of one regular iteration (5 or 2)       */
+    double relres_rec;       /* last ||r_i|| / ||r_0|| of the recurrence                  */
+    double relres_true;      /* ||b - A x|| / ||r_0|| of the returned x                   */
+    double ms;               /* wall time of the iteration loop (HIP events), ms           */
+    double kernel_ms[2];     /* with flags bit 1: summed duration of the two fused kernels
+                                of the iteration (p-BiCGStab: t-phase, v-phase; BiCGStab:
+                                the two SpMV phases)                                      */
+    int32_t kernel_calls[2]; /* launches timed for kernel_ms                              */
+} pbcgs_info;
+
+/* Create a context on HIP device `device` working on stream `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+int pbcgs_ctx_create(int device, void* hip_stream, pbcgs_ctx_t* out);
+
+/* Free the context's workspace.  Operators made on it must be destroyed first. */
+int pbcgs_ctx_destroy(pbcgs_ctx_t ctx);
+
+/* Message describing the last error on ctx (NULL ctx: the last global error). */
+const char* pbcgs_last_error(pbcgs_ctx_t ctx);
+
+/* Static name of a status code. */
+const char* pbcgs_status_str(int status);
+
+/*
+ * CSR operator (Section 2: the SPMV building block): n x n, int32 row_ptr[n+1]
+ * with row_ptr[0] = 0 and row_ptr[n] = nnz, int32 col_idx[nnz] in [0, n),
+ * float64 val[nnz].  Each row is applied in stored order; ascending columns
+ * are the convention.  The arrays are borrowed and must outlive the operator.
+ * The structure is validated on the device (ERR_INVALID_ARG if malformed).
+ */
+int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                 const int32_t* col_idx, const double* val, pbcgs_op_t* out);
+
+/*
+ * Matrix-free constant-coefficient stencil on the interior nodes of an
+ * nx x ny (x nz) grid, rows ordered x fastest, Dirichlet boundaries (entries
+ * that would leave the grid are dropped).  npts = 5 (nz must be 1) or 7.
+ * coef is a HOST array of npts coefficients in ascending-column order:
+ * 5-point {-y, -x, centre, +x, +y}; 7-point {-z, -y, -x, centre, +x, +y, +z}.
+ * Applying it gives bit for bit the product with the equivalent CSR matrix.
+ */
+int pbcgs_op_stencil(pbcgs_ctx_t ctx, int32_t nx, int32_t ny, int32_t nz, int32_t npts,
+                     const double* coef, pbcgs_op_t* out);
+
+int pbcgs_op_destroy(pbcgs_op_t op);
+
+/* Number of rows of op (host), or a negative status. */
+int64_t pbcgs_op_rows(pbcgs_op_t op);
+
+/* y := A x (device pointers, n doubles each; x and y must not overlap). */
+int pbcgs_spmv(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* x, double* y);
+
+/* (x, y) in pairwise order, written to *result (HOST double). */
+int pbcgs_dot(pbcgs_ctx_t ctx, int64_t n, const double* x, const double* y, double* result);
+
+/* Jacobi: dinv_i := 1 / a_ii (Section 3.6 with M = diag(A)); ERR_INVALID_ARG if a
+ * diagonal entry is zero or missing. */
+int pbcgs_jacobi_dinv(pbcgs_ctx_t ctx, pbcgs_op_t A, double* dinv);
+
+/*
+ * Solve A x = b.  b: n doubles (device, read only).  x: n doubles (device),
+ * holds x_0 on entry and the final iterate on return.  dinv: n doubles
+ * (device) of M^{-1} = diag(dinv) when opts->precond is JACOBI, or NULL to
+ * derive dinv = 1/diag(A) inside the call; ignored without a preconditioner.
+ * opts and info are host structs.  The call enqueues on the context's stream
+ * and returns after the solve has finished; the host reads the 64-byte device
+ * status once every check_every iterations.
+ */
+int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const double* dinv,
+                const pbcgs_opts* opts, pbcgs_info* info);
+
+/*
+ * Workload builder (not part of the method): assembles on the device the
+ * h^2-scaled first-order upwind convection-diffusion operator used by the
+ * tests and the benchmark, h = 1/(n+1), Dirichlet boundaries, rows x fastest,
+ * ascending columns.  dim 2 / npts 5, or dim 3 / npts 7 or 27.  beta: HOST
+ * array of dim doubles.  kappa: DEVICE array of (n+1)^3 cell coefficients for
+ * npts 27 (NULL otherwise).  shift is added to the 27-point diagonal.  The
+ * caller allocates row_ptr[n^dim + 1], col_idx[nnz], val[nnz] with nnz from
+ * pbcgs_convdiff_nnz().
+ */
+int64_t pbcgs_convdiff_nnz(int32_t dim, int32_t n, int32_t npts);
+int pbcgs_assemble_convdiff(pbcgs_ctx_t ctx, int32_t dim, int32_t n, int32_t npts,
+                            const double* beta, const double* kappa, double shift,
+                            int32_t* row_ptr, int32_t* col_idx, double* val);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBCGS_H */

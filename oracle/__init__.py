@@ -65,6 +65,10 @@ def lib():
         L.or_assemble.restype = ctypes.c_int64
         L.or_assemble.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _f64p,
                                   _nullable(_f64p), ctypes.c_double, _i32p, _i32p, _f64p]
+        L.or_assemble_rows.restype = ctypes.c_int64
+        L.or_assemble_rows.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _f64p,
+                                       _nullable(_f64p), ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                       _i32p, _i32p, _f64p]
         L.or_spmv.restype = None
         L.or_spmv.argtypes = [ctypes.c_int32, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.or_dot.restype = ctypes.c_double
@@ -136,6 +140,22 @@ def assemble(dim: int, n: int, npts: int, beta, kappa=None, shift: float = 0.0) 
     if got != nnz:
         raise RuntimeError("oracle assembly failed")
     return CSR(rp, col, val)
+
+
+def assemble_rows(dim: int, n: int, npts: int, beta, row_begin: int, row_end: int, kappa=None,
+                  shift: float = 0.0):
+    """Rows [row_begin, row_end) of the operator: (row_ptr relative to row_begin, col, val)."""
+    cnt = row_end - row_begin
+    rp = np.zeros(cnt + 1, np.int32)
+    col = np.zeros(cnt * npts, np.int32)
+    val = np.zeros(cnt * npts, np.float64)
+    b = np.zeros(3, np.float64)
+    b[:dim] = beta
+    k = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+    got = lib().or_assemble_rows(dim, n, npts, b, k, float(shift), row_begin, row_end, rp, col, val)
+    if got < 0:
+        raise ValueError("unsupported operator")
+    return rp, col[:got], val[:got]
 
 
 def assemble_workload(w, kappa=None) -> CSR:

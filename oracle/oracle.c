@@ -105,11 +105,12 @@ int64_t or_assemble_nnz(int32_t dim, int32_t n, int32_t npts)
  *               plus -|hb_a| on the upwind face of axis a; diagonal
  *               (sum_d kbar_d over all 26 d + ((|hbx| + |hby|) + |hbz|)) + shift.
  *
- * Returns nnz, or -1 for unsupported arguments.
+ * or_assemble_rows emits only rows [row_begin, row_end) (row pointers relative
+ * to row_begin) and returns their entry count; -1 for unsupported arguments.
  */
-int64_t or_assemble(int32_t dim, int32_t n, int32_t npts, const double* beta,
-                    const double* kappa, double shift,
-                    int32_t* row_ptr, int32_t* col, double* val)
+int64_t or_assemble_rows(int32_t dim, int32_t n, int32_t npts, const double* beta,
+                         const double* kappa, double shift, int64_t row_begin, int64_t row_end,
+                         int32_t* row_ptr, int32_t* col, double* val)
 {
     int64_t nnz_expected = or_assemble_nnz(dim, n, npts);
     if (nnz_expected < 0 || beta == NULL) return -1;
@@ -126,6 +127,7 @@ int64_t or_assemble(int32_t dim, int32_t n, int32_t npts, const double* beta,
     for (int j = 0; j < n; ++j)
     for (int i = 0; i < n; ++i) {
         const int64_t row = i + (int64_t)n * j + nn * k;
+        if (row < row_begin || row >= row_end) continue;
         if (npts == 5 || npts == 7) {
             /* entries in ascending column order: (-z), -y, -x, diagonal, +x, +y, (+z);
              * entry e is axis ax[e] on side sd[e] (sd 0 marks the diagonal) */
@@ -199,9 +201,19 @@ int64_t or_assemble(int32_t dim, int32_t n, int32_t npts, const double* beta,
             }
             val[diag_pos] = (diag_sum + ((fabs(hb[0]) + fabs(hb[1])) + fabs(hb[2]))) + shift;
         }
-        row_ptr[row + 1] = (int32_t)pos;
+        row_ptr[row - row_begin + 1] = (int32_t)pos;
     }
-    return (pos == nnz_expected) ? pos : -1;
+    return pos;
+}
+
+/* The whole operator: rows [0, n^dim). */
+int64_t or_assemble(int32_t dim, int32_t n, int32_t npts, const double* beta,
+                    const double* kappa, double shift,
+                    int32_t* row_ptr, int32_t* col, double* val)
+{
+    const int64_t N = (dim == 3) ? (int64_t)n * n * n : (int64_t)n * n;
+    int64_t nnz = or_assemble_rows(dim, n, npts, beta, kappa, shift, 0, N, row_ptr, col, val);
+    return (nnz == or_assemble_nnz(dim, n, npts)) ? nnz : -1;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,686 @@
+// Host side of the pipelined BiCGStab library: contexts, operators, the
+// iteration driver (launch schedule, HIP-graph capture, status polling) and
+// the C ABI declared in include/pbcgs.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/pbcgs.h"
+#include "internal.hpp"
+#include "kernels.hpp"
+
+using namespace pbcgs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+enum OpKind { OP_CSR = 0, OP_ST5 = 1, OP_ST7 = 2 };
+
+}  // namespace
+
+struct pbcgs_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  DevState* st = nullptr;   // device scalars and status
+  DevState* hst = nullptr;  // pinned host copies, two poll slots
+  double* part = nullptr;   // [kMaxD][kMaxG]
+  double* ws = nullptr;     // solver vectors
+  size_t ws_cap = 0;        // doubles
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+  hipEvent_t ev_poll[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> kev;  // pool for per-kernel timing
+  std::map<std::string, hipGraphExec_t> graphs;
+  std::string err;
+  int ops = 0;
+  bool own_stream = false;
+};
+
+struct pbcgs_op_s {
+  pbcgs_ctx_t ctx = nullptr;
+  int kind = OP_CSR;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  const int32_t* rp = nullptr;
+  const int32_t* ci = nullptr;
+  const double* va = nullptr;
+  int32_t nx = 0, ny = 0, nz = 0;
+  double coef[7] = {0, 0, 0, 0, 0, 0, 0};
+};
+
+namespace {
+
+int fail(pbcgs_ctx_t ctx, int code, const std::string& msg) {
+  g_last_error = msg;
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+// Keeps the caller's current device; switches to the context's device.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+#define HIP_TRY(ctx, call)                                                                 \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((ctx), PBCGS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Launch shape: tiles of 256 rows, tpw (power of two) tiles per workgroup so
+// that the grid has at most `gtarget` workgroups.
+struct Shape {
+  int32_t n, ntiles, tpw, G;
+};
+
+int gtarget_default() {
+  const char* e = std::getenv("PBCGS_GTARGET");
+  if (e) {
+    int v = std::atoi(e);
+    if (v >= 1 && v <= kMaxG) return v;
+  }
+  return 1024;
+}
+
+bool make_shape(int32_t n, Shape* sh) {
+  if (n <= 0) return false;
+  const int32_t ntiles = (n + kTile - 1) / kTile;
+  const int gt = gtarget_default();
+  int tpw = 1;
+  while ((ntiles + tpw - 1) / tpw > gt && tpw < kMaxTpw) tpw *= 2;
+  const int32_t G = (ntiles + tpw - 1) / tpw;
+  if (G > kMaxG) return false;
+  *sh = {n, ntiles, tpw, G};
+  return true;
+}
+
+Args base_args(pbcgs_ctx_t ctx, const Shape& sh) {
+  Args a;
+  std::memset(&a, 0, sizeof a);
+  a.n = sh.n;
+  a.ntiles = sh.ntiles;
+  a.tpw = sh.tpw;
+  a.G = sh.G;
+  a.st = ctx->st;
+  a.part = ctx->part;
+  return a;
+}
+
+int ensure_ws(pbcgs_ctx_t ctx, size_t doubles) {
+  if (ctx->ws_cap >= doubles) return PBCGS_SUCCESS;
+  if (ctx->ws) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_cap = 0;
+    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+  }
+  if (hipMalloc(&ctx->ws, doubles * sizeof(double)) != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(ctx, PBCGS_ERR_ALLOC, "workspace allocation of " + std::to_string(doubles * 8) + " bytes failed");
+  }
+  ctx->ws_cap = doubles;
+  return PBCGS_SUCCESS;
+}
+
+size_t padded(int32_t n) { return ((size_t)n + 63) / 64 * 64; }
+
+int read_state(pbcgs_ctx_t ctx, DevState* out) {
+  HIP_TRY(ctx, hipMemcpyAsync(out, ctx->st, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return PBCGS_SUCCESS;
+}
+
+int map_status(int32_t ds, bool running_is_maxit) {
+  switch (ds) {
+    case DS_SUCCESS: return PBCGS_SUCCESS;
+    case DS_BREAKDOWN: return PBCGS_BREAKDOWN;
+    case DS_NONFINITE: return PBCGS_NONFINITE;
+    default: return running_is_maxit ? PBCGS_MAXIT : PBCGS_SUCCESS;
+  }
+}
+
+// Residual replacement schedule (Section 4.2): iteration i replaces r, r^, w
+// when (i+1) mod k == 0 and fewer than rr_max replacements came before.
+bool rr_due(const pbcgs_opts& o, int64_t i) {
+  if (o.variant != PBCGS_PBICGSTAB_RR || o.rr_period <= 0) return false;
+  if ((i + 1) % o.rr_period != 0) return false;
+  const int64_t before = (i + 1) / o.rr_period - 1;
+  return o.rr_max < 0 || before < o.rr_max;
+}
+
+// ---------------------------------------------------------------------------
+// Per-(operator, preconditioner) driver.
+// ---------------------------------------------------------------------------
+template <class Op, int PC>
+struct Driver {
+  pbcgs_ctx_t ctx;
+  Op op;
+  Args a;
+  const pbcgs_opts& o;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[2];
+  size_t ev_used = 0;
+
+  Driver(pbcgs_ctx_t c, Op op_, const Args& a_, const pbcgs_opts& o_) : ctx(c), op(op_), a(a_), o(o_) {}
+
+  hipEvent_t next_event() {
+    if (ev_used == ctx->kev.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ctx->kev.push_back(e);
+    }
+    return ctx->kev[ev_used++];
+  }
+
+  template <class F>
+  void timed(int slot, F launch) {
+    if (!timing) { launch(); return; }
+    hipEvent_t e0 = next_event(), e1 = next_event();
+    if (e0 && e1) (void)hipEventRecord(e0, ctx->stream);
+    launch();
+    if (e0 && e1) {
+      (void)hipEventRecord(e1, ctx->stream);
+      tev[slot].push_back({e0, e1});
+    }
+  }
+
+  dim3 grid() const { return dim3((unsigned)a.G); }
+
+  void setup() {
+    hipStream_t s = ctx->stream;
+    if (o.variant == PBCGS_BICGSTAB) {
+      k_setup_r0<Op, PC, false><<<grid(), kWG, 0, s>>>(op, a);
+    } else {
+      k_setup_r0<Op, PC, true><<<grid(), kWG, 0, s>>>(op, a);
+      k_setup_w0<Op, PC><<<grid(), kWG, 0, s>>>(op, a);
+    }
+  }
+
+  // Kernels of iteration i.
+  void iteration(int64_t i) {
+    hipStream_t s = ctx->stream;
+    if (o.variant == PBCGS_BICGSTAB) {
+      timed(0, [&] { k_b1<Op, PC><<<grid(), kWG, 0, s>>>(op, a); });
+      k_b2<PC><<<grid(), kWG, 0, s>>>(a);
+      timed(1, [&] { k_b3<Op, PC><<<grid(), kWG, 0, s>>>(op, a); });
+      k_b4<PC><<<grid(), kWG, 0, s>>>(a);
+      k_b5<PC><<<grid(), kWG, 0, s>>>(a);
+      return;
+    }
+    const bool pending = (i > 0) && rr_due(o, i - 1);
+    const bool rr = rr_due(o, i);
+    if (pending) {
+      k_rr_p<PC><<<grid(), kWG, 0, s>>>(a);
+      k_rr_s<Op, PC><<<grid(), kWG, 0, s>>>(op, a);
+      k_pa<Op, PC, true><<<grid(), kWG, 0, s>>>(op, a);
+    } else {
+      timed(0, [&] { k_pa<Op, PC, false><<<grid(), kWG, 0, s>>>(op, a); });
+    }
+    if (rr) {
+      k_rr_x<PC><<<grid(), kWG, 0, s>>>(a);
+      k_rr_r<Op, PC><<<grid(), kWG, 0, s>>>(op, a);
+      k_rr_w<Op, PC><<<grid(), kWG, 0, s>>>(op, a);
+    } else {
+      timed(1, [&] { k_pb<Op, PC><<<grid(), kWG, 0, s>>>(op, a); });
+    }
+  }
+
+  std::string graph_key(int64_t i0, int m) const {
+    std::string k;
+    char buf[64];
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(&a);
+    k.reserve(sizeof(Args) + sizeof(Op) + 96);
+    k.append(reinterpret_cast<const char*>(p), sizeof(Args));
+    k.append(reinterpret_cast<const char*>(&op), sizeof(Op));
+    std::snprintf(buf, sizeof buf, "|%d|%d|%d|", PC, o.variant, m);
+    k += buf;
+    for (int j = 0; j < m; ++j) {
+      const int64_t i = i0 + j;
+      const int code = ((i > 0 && rr_due(o, i - 1)) ? 1 : 0) | (rr_due(o, i) ? 2 : 0);
+      k += char('0' + code);
+    }
+    return k;
+  }
+
+  int chunk(int64_t i0, int m, bool use_graph) {
+    if (!use_graph) {
+      for (int j = 0; j < m; ++j) iteration(i0 + j);
+      HIP_TRY(ctx, hipGetLastError());
+      return PBCGS_SUCCESS;
+    }
+    const std::string key = graph_key(i0, m);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+      if (ctx->graphs.size() >= 32) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+        ctx->graphs.clear();
+      }
+      hipGraph_t g = nullptr;
+      HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      for (int j = 0; j < m; ++j) iteration(i0 + j);
+      hipError_t ce = hipStreamEndCapture(ctx->stream, &g);
+      if (ce != hipSuccess) return fail(ctx, PBCGS_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+      hipGraphExec_t ex = nullptr;
+      hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) return fail(ctx, PBCGS_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+      it = ctx->graphs.emplace(key, ex).first;
+    }
+    HIP_TRY(ctx, hipGraphLaunch(it->second, ctx->stream));
+    return PBCGS_SUCCESS;
+  }
+
+  int run(pbcgs_info* info) {
+    const bool use_graph = !(o.flags & 1) && !(o.flags & 2);
+    timing = (o.flags & 2) != 0;
+    int check = o.check_every > 0 ? o.check_every : (a.n >= (1 << 20) ? 8 : 32);
+    hipStream_t s = ctx->stream;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_start, s));
+    k_init_state<<<1, 64, 0, s>>>(a.st, o.tol);
+    setup();
+    HIP_TRY(ctx, hipGetLastError());
+    // Chunks of `check` iterations; the status after chunk c is polled while
+    // chunk c+1 is already queued, so the device does not wait for the host.
+    // Kernels queued after convergence see the final status and exit at once.
+    int64_t launched = 0;
+    int pend[2];
+    int npend = 0, next_slot = 0;
+    bool stop = false;
+    for (;;) {
+      while (!stop && launched < o.maxit && npend < 2) {
+        const int m = (int)std::min<int64_t>(check, o.maxit - launched);
+        int rc = chunk(launched, m, use_graph);
+        if (rc != PBCGS_SUCCESS) return rc;
+        launched += m;
+        HIP_TRY(ctx, hipMemcpyAsync(&ctx->hst[next_slot], ctx->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipEventRecord(ctx->ev_poll[next_slot], s));
+        pend[npend++] = next_slot;
+        next_slot ^= 1;
+      }
+      if (npend == 0) break;
+      const int slot = pend[0];
+      pend[0] = pend[1];
+      --npend;
+      HIP_TRY(ctx, hipEventSynchronize(ctx->ev_poll[slot]));
+      if (ctx->hst[slot].status != DS_RUNNING) stop = true;
+    }
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_stop, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    DevState fin;
+    int rc = read_state(ctx, &fin);
+    if (rc != PBCGS_SUCCESS) return rc;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop);
+    // true residual of the returned x, same pairwise arithmetic
+    k_true_res<Op><<<grid(), kWG, 0, s>>>(op, a);
+    HIP_TRY(ctx, hipGetLastError());
+    DevState tr;
+    rc = read_state(ctx, &tr);
+    if (rc != PBCGS_SUCCESS) return rc;
+    info->iters = fin.iters;
+    info->n_rr = fin.n_rr;
+    info->status = map_status(fin.status, true);
+    info->syncs_per_iter = (o.variant == PBCGS_BICGSTAB) ? 5 : 2;
+    info->relres_rec = fin.relres;
+    info->relres_true = (fin.rho0 > 0.0) ? std::sqrt(tr.result) / fin.rho0 : 0.0;
+    info->ms = ms;
+    for (int k = 0; k < 2; ++k) {
+      double tot = 0.0;
+      for (auto& pr : tev[k]) {
+        float e = 0.f;
+        if (hipEventElapsedTime(&e, pr.first, pr.second) == hipSuccess) tot += e;
+      }
+      info->kernel_ms[k] = tot;
+      info->kernel_calls[k] = (int32_t)tev[k].size();
+    }
+    return info->status;
+  }
+};
+
+int check_flag(pbcgs_ctx_t ctx, int32_t* flag) {
+  DevState h;
+  int rc = read_state(ctx, &h);
+  if (rc != PBCGS_SUCCESS) return rc;
+  *flag = h.errflag;
+  return PBCGS_SUCCESS;
+}
+
+template <int PC, class F>
+int with_op(pbcgs_op_t A, F f) {
+  if (A->kind == OP_CSR) return f(CsrOp{A->rp, A->ci, A->va});
+  if (A->kind == OP_ST7) {
+    StencilOp<7> s;
+    std::memset(&s, 0, sizeof s);
+    s.nx = A->nx; s.ny = A->ny; s.nz = A->nz;
+    for (int k = 0; k < 7; ++k) s.c[k] = A->coef[k];
+    return f(s);
+  }
+  StencilOp<5> s;
+  std::memset(&s, 0, sizeof s);
+  s.nx = A->nx; s.ny = A->ny; s.nz = 1;
+  for (int k = 0; k < 5; ++k) s.c[k] = A->coef[k];
+  return f(s);
+}
+
+}  // namespace
+
+void* pbcgs_internal_stream(pbcgs_ctx_t ctx) { return ctx ? ctx->stream : nullptr; }
+
+int pbcgs_internal_fail(pbcgs_ctx_t ctx, int code, const char* msg) { return fail(ctx, code, msg); }
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* pbcgs_status_str(int status) {
+  switch (status) {
+    case PBCGS_SUCCESS: return "success";
+    case PBCGS_MAXIT: return "maxit";
+    case PBCGS_BREAKDOWN: return "breakdown";
+    case PBCGS_NONFINITE: return "nonfinite";
+    case PBCGS_ERR_INVALID_ARG: return "invalid argument";
+    case PBCGS_ERR_ALLOC: return "allocation failed";
+    case PBCGS_ERR_HIP: return "HIP runtime error";
+    case PBCGS_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* pbcgs_last_error(pbcgs_ctx_t ctx) {
+  if (ctx) return ctx->err.c_str();
+  return g_last_error.c_str();
+}
+
+int pbcgs_ctx_create(int device, void* hip_stream, pbcgs_ctx_t* out) {
+  if (!out) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "out is NULL");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+    return fail(nullptr, PBCGS_ERR_HIP, "no HIP device available");
+  if (device < 0 || device >= count) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "device index out of range");
+  DeviceGuard guard(device);
+  pbcgs_ctx_t c = new pbcgs_ctx_s();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (!c->stream) {
+    // a blocking stream of our own: ordered with the null stream, and
+    // unlike the null stream it can be captured into HIP graphs
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      return fail(nullptr, PBCGS_ERR_HIP, "stream creation failed");
+    }
+    c->own_stream = true;
+  }
+  bool ok = hipMalloc(&c->st, sizeof(DevState)) == hipSuccess &&
+            hipMalloc(&c->part, sizeof(double) * kMaxD * kMaxG) == hipSuccess &&
+            hipHostMalloc(&c->hst, 2 * sizeof(DevState), hipHostMallocDefault) == hipSuccess &&
+            hipEventCreate(&c->ev_start) == hipSuccess && hipEventCreate(&c->ev_stop) == hipSuccess &&
+            hipEventCreateWithFlags(&c->ev_poll[0], hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    pbcgs_ctx_destroy(c);
+    return fail(nullptr, PBCGS_ERR_ALLOC, "context allocation failed");
+  }
+  k_init_state<<<1, 64, 0, c->stream>>>(c->st, 0.0);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    pbcgs_ctx_destroy(c);
+    return fail(nullptr, PBCGS_ERR_HIP, "context initialisation failed");
+  }
+  *out = c;
+  return PBCGS_SUCCESS;
+}
+
+int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
+  if (!ctx) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "ctx is NULL");
+  DeviceGuard guard(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+  for (auto e : ctx->kev) (void)hipEventDestroy(e);
+  if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
+  if (ctx->ev_stop) (void)hipEventDestroy(ctx->ev_stop);
+  for (auto e : ctx->ev_poll) if (e) (void)hipEventDestroy(e);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->part) (void)hipFree(ctx->part);
+  if (ctx->st) (void)hipFree(ctx->st);
+  if (ctx->hst) (void)hipHostFree(ctx->hst);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return PBCGS_SUCCESS;
+}
+
+int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                 const double* val, pbcgs_op_t* out) {
+  if (!ctx || !out) return fail(ctx, PBCGS_ERR_INVALID_ARG, "ctx or out is NULL");
+  if (n <= 0 || nnz < 0 || nnz > INT32_MAX) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad n or nnz");
+  if (!row_ptr || (nnz > 0 && (!col_idx || !val))) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL CSR array");
+  Shape sh;
+  if (!make_shape(n, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows for one launch");
+  DeviceGuard guard(ctx->device);
+  CsrOp op{row_ptr, col_idx, val};
+  k_init_state<<<1, 64, 0, ctx->stream>>>(ctx->st, 0.0);
+  k_csr_check<<<(n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(op, n, nnz, ctx->st);
+  HIP_TRY(ctx, hipGetLastError());
+  int32_t flag = 0;
+  int rc = check_flag(ctx, &flag);
+  if (rc != PBCGS_SUCCESS) return rc;
+  if (flag) return fail(ctx, PBCGS_ERR_INVALID_ARG, "malformed CSR structure (row_ptr or col_idx)");
+  pbcgs_op_t A = new pbcgs_op_s();
+  A->ctx = ctx;
+  A->kind = OP_CSR;
+  A->n = n;
+  A->nnz = nnz;
+  A->rp = row_ptr;
+  A->ci = col_idx;
+  A->va = val;
+  ctx->ops++;
+  *out = A;
+  return PBCGS_SUCCESS;
+}
+
+int pbcgs_op_stencil(pbcgs_ctx_t ctx, int32_t nx, int32_t ny, int32_t nz, int32_t npts, const double* coef,
+                     pbcgs_op_t* out) {
+  if (!ctx || !out || !coef) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad grid size");
+  if (npts != 5 && npts != 7) return fail(ctx, PBCGS_ERR_INVALID_ARG, "npts must be 5 or 7");
+  if (npts == 5 && nz != 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "5-point stencil needs nz == 1");
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (n > INT32_MAX) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "grid too large");
+  Shape sh;
+  if (!make_shape((int32_t)n, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows for one launch");
+  pbcgs_op_t A = new pbcgs_op_s();
+  A->ctx = ctx;
+  A->kind = (npts == 7) ? OP_ST7 : OP_ST5;
+  A->n = (int32_t)n;
+  A->nx = nx;
+  A->ny = ny;
+  A->nz = nz;
+  for (int k = 0; k < npts; ++k) A->coef[k] = coef[k];
+  int64_t nnz = 0;  // stored entries of the equivalent CSR matrix
+  {
+    const int64_t X = nx, Y = ny, Z = nz;
+    nnz = X * Y * Z + 2 * ((X - 1) * Y * Z + X * (Y - 1) * Z) + (npts == 7 ? 2 * X * Y * (Z - 1) : 0);
+  }
+  A->nnz = nnz;
+  ctx->ops++;
+  *out = A;
+  return PBCGS_SUCCESS;
+}
+
+int pbcgs_op_destroy(pbcgs_op_t op) {
+  if (!op) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "op is NULL");
+  pbcgs_ctx_t ctx = op->ctx;
+  if (ctx) {
+    // cached graphs may embed this operator's arrays
+    DeviceGuard guard(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+    ctx->ops--;
+  }
+  delete op;
+  return PBCGS_SUCCESS;
+}
+
+int64_t pbcgs_op_rows(pbcgs_op_t op) {
+  if (!op) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "op is NULL");
+  return op->n;
+}
+
+int pbcgs_spmv(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* x, double* y) {
+  if (!ctx || !A || !x || !y) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  if (A->ctx != ctx) return fail(ctx, PBCGS_ERR_INVALID_ARG, "operator belongs to another context");
+  if ((const void*)x == (const void*)y) return fail(ctx, PBCGS_ERR_INVALID_ARG, "x and y must not overlap");
+  DeviceGuard guard(ctx->device);
+  Shape sh;
+  make_shape(A->n, &sh);
+  Args a = base_args(ctx, sh);
+  return with_op<0>(A, [&](auto op) -> int {
+    k_spmv<decltype(op)><<<sh.G, kWG, 0, ctx->stream>>>(op, a, x, y);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return PBCGS_SUCCESS;
+  });
+}
+
+int pbcgs_dot(pbcgs_ctx_t ctx, int64_t n, const double* x, const double* y, double* result) {
+  if (!ctx || !x || !y || !result) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  if (n <= 0 || n > INT32_MAX) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad length");
+  DeviceGuard guard(ctx->device);
+  Shape sh;
+  if (!make_shape((int32_t)n, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "vector too long");
+  Args a = base_args(ctx, sh);
+  k_init_state<<<1, 64, 0, ctx->stream>>>(ctx->st, 0.0);
+  k_dot<<<sh.G, kWG, 0, ctx->stream>>>(a, x, y);
+  HIP_TRY(ctx, hipGetLastError());
+  DevState h;
+  int rc = read_state(ctx, &h);
+  if (rc != PBCGS_SUCCESS) return rc;
+  *result = h.result;
+  return PBCGS_SUCCESS;
+}
+
+int pbcgs_jacobi_dinv(pbcgs_ctx_t ctx, pbcgs_op_t A, double* dinv) {
+  if (!ctx || !A || !dinv) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  DeviceGuard guard(ctx->device);
+  if (A->kind != OP_CSR) {
+    const double c = (A->kind == OP_ST7) ? A->coef[3] : A->coef[2];
+    if (c == 0.0 || !std::isfinite(c)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero diagonal");
+    const double d = 1.0 / c;
+    std::vector<double> h((size_t)A->n, d);
+    HIP_TRY(ctx, hipMemcpyAsync(dinv, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return PBCGS_SUCCESS;
+  }
+  k_init_state<<<1, 64, 0, ctx->stream>>>(ctx->st, 0.0);
+  k_dinv_csr<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(CsrOp{A->rp, A->ci, A->va}, A->n, dinv, ctx->st);
+  HIP_TRY(ctx, hipGetLastError());
+  int32_t flag = 0;
+  int rc = check_flag(ctx, &flag);
+  if (rc != PBCGS_SUCCESS) return rc;
+  if (flag & 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero, non-finite or missing diagonal entry");
+  return PBCGS_SUCCESS;
+}
+
+int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const double* dinv,
+                const pbcgs_opts* opts, pbcgs_info* info) {
+  if (!ctx || !A || !b || !x || !opts || !info) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  if (A->ctx != ctx) return fail(ctx, PBCGS_ERR_INVALID_ARG, "operator belongs to another context");
+  const pbcgs_opts& o = *opts;
+  if (o.variant < PBCGS_BICGSTAB || o.variant > PBCGS_PBICGSTAB_RR)
+    return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown variant");
+  if (o.precond != PBCGS_PRECOND_NONE && o.precond != PBCGS_PRECOND_JACOBI)
+    return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown preconditioner");
+  if (o.precision != PBCGS_FP64) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "only FP64 is implemented");
+  if (o.maxit < 0 || !(o.tol >= 0.0)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad maxit or tol");
+  if (o.variant == PBCGS_PBICGSTAB_RR && o.rr_period < 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad rr_period");
+  if ((const void*)b == (const void*)x) return fail(ctx, PBCGS_ERR_INVALID_ARG, "b and x must not overlap");
+  DeviceGuard guard(ctx->device);
+  Shape sh;
+  if (!make_shape(A->n, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows");
+  std::memset(info, 0, sizeof *info);
+
+  const size_t np = padded(A->n);
+  const int nvec = 14;
+  int rc = ensure_ws(ctx, np * nvec);
+  if (rc != PBCGS_SUCCESS) return rc;
+  Args a = base_args(ctx, sh);
+  a.hist = o.history;
+  a.b = b;
+  a.x = x;
+  double* v[nvec];
+  for (int k = 0; k < nvec; ++k) v[k] = ctx->ws + (size_t)k * np;
+
+  // preconditioner mode
+  int pc = PC_NONE;
+  if (o.precond == PBCGS_PRECOND_JACOBI) {
+    const double* dv = dinv;
+    if (!dv && A->kind != OP_CSR) {
+      // constant-coefficient stencil: M^{-1} is one scalar, 1 / centre
+      const double c = (A->kind == OP_ST7) ? A->coef[3] : A->coef[2];
+      if (c == 0.0 || !std::isfinite(c)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero diagonal");
+      pc = PC_SCALAR;
+      a.dinv_s = 1.0 / c;
+    } else if (!dv) {
+      rc = pbcgs_jacobi_dinv(ctx, A, v[13]);
+      if (rc != PBCGS_SUCCESS) return rc;
+      dv = v[13];
+    }
+  }
+  if (o.precond == PBCGS_PRECOND_JACOBI && pc == PC_NONE) {
+    const double* dv = dinv ? dinv : v[13];
+    k_init_state<<<1, 64, 0, ctx->stream>>>(ctx->st, 0.0);
+    k_dinv_const<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(A->n, dv, ctx->st);
+    HIP_TRY(ctx, hipGetLastError());
+    int32_t flag = 0;
+    rc = check_flag(ctx, &flag);
+    if (rc != PBCGS_SUCCESS) return rc;
+    if (flag & 2) {
+      pc = PC_VEC;
+      a.dinv = dv;
+    } else {
+      pc = PC_SCALAR;
+      HIP_TRY(ctx, hipMemcpyAsync(&a.dinv_s, dv, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+  }
+  const bool hat = (pc != PC_NONE);
+  if (o.variant == PBCGS_BICGSTAB) {
+    a.r0 = v[0]; a.r = v[1]; a.p = v[2]; a.s = v[3]; a.q = v[4]; a.y = v[5];
+    a.ph = hat ? v[6] : a.p;
+    a.qh = hat ? v[7] : a.q;
+  } else {
+    a.r0 = v[0]; a.r = v[1]; a.w = v[2]; a.t = v[3]; a.ph = v[4]; a.s = v[5]; a.z = v[6]; a.v = v[7];
+    a.rh = hat ? v[8] : a.r;
+    a.wh = hat ? v[9] : a.w;
+    a.sh = hat ? v[10] : a.s;
+    a.zh = hat ? v[11] : a.z;
+  }
+
+  return with_op<0>(A, [&](auto op) -> int {
+    using Op = decltype(op);
+    if (pc == PC_NONE) return Driver<Op, PC_NONE>(ctx, op, a, o).run(info);
+    if (pc == PC_VEC) return Driver<Op, PC_VEC>(ctx, op, a, o).run(info);
+    return Driver<Op, PC_SCALAR>(ctx, op, a, o).run(info);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+"""PyTorch-facing wrapper of the pipelined BiCGStab library.
+
+Tensors provide device memory and the current HIP stream; every computation
+is a call into libpbcgs.so.  The solvers are those of Cools & Vanroose,
+arXiv 1612.01395: standard BiCGStab (Algorithm 7, preconditioned: 10),
+pipelined BiCGStab (Algorithm 9, preconditioned: 11) and pipelined BiCGStab
+with residual replacement (Section 4.2).
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+VARIANTS = {"bicgstab": L.BICGSTAB, "pbicgstab": L.PBICGSTAB, "pbicgstab_rr": L.PBICGSTAB_RR}
+STATUS = {0: "success", 1: "maxit", 2: "breakdown", 3: "nonfinite"}
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_vec(t: torch.Tensor, n: int, name: str, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor with {n} elements")
+
+
+class Context:
+    """A library context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int | None = None, stream: torch.cuda.Stream | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        raw = stream.cuda_stream
+        h = ctypes.c_void_p()
+        L.check(L.lib().pbcgs_ctx_create(self.device, ctypes.c_void_p(raw) if raw else None, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.lib().pbcgs_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self) -> str:
+        return L.last_error(self.handle)
+
+
+_contexts: dict = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    stream = torch.cuda.current_stream(device)
+    key = (int(device), stream.cuda_stream)
+    ctx = _contexts.get(key)
+    if ctx is None:
+        ctx = Context(device, stream)
+        _contexts[key] = ctx
+    return ctx
+
+
+class Operator:
+    """A sparse operator known to the library (CSR or matrix-free stencil)."""
+
+    def __init__(self, ctx: Context, handle, n: int, keep: tuple, kind: str):
+        self.ctx = ctx
+        self.handle = handle
+        self.n = n
+        self._keep = keep  # the borrowed device arrays stay alive with the operator
+        self.kind = kind
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.lib().pbcgs_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def csr(row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor, ctx: Context | None = None) -> Operator:
+    """CSR operator from int32 row_ptr[n+1], int32 col_idx[nnz], float64 val[nnz] on the GPU."""
+    ctx = ctx or default_context(row_ptr.device.index)
+    n = row_ptr.numel() - 1
+    nnz = val.numel()
+    _check_vec(row_ptr, n + 1, "row_ptr", torch.int32)
+    _check_vec(col_idx, nnz, "col_idx", torch.int32)
+    _check_vec(val, nnz, "val")
+    h = ctypes.c_void_p()
+    L.check(L.lib().pbcgs_op_csr(ctx.handle, n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(val), ctypes.byref(h)),
+            ctx.handle)
+    return Operator(ctx, h, n, (row_ptr, col_idx, val), "csr")
+
+
+def stencil(nx: int, ny: int, nz: int, coef, ctx: Context | None = None) -> Operator:
+    """Matrix-free constant-coefficient 5- (nz == 1) or 7-point stencil; coef in
+    ascending-column order ({-y,-x,c,+x,+y} or {-z,-y,-x,c,+x,+y,+z})."""
+    ctx = ctx or default_context()
+    coef = [float(c) for c in coef]
+    arr = (ctypes.c_double * len(coef))(*coef)
+    h = ctypes.c_void_p()
+    L.check(L.lib().pbcgs_op_stencil(ctx.handle, nx, ny, nz, len(coef), arr, ctypes.byref(h)), ctx.handle)
+    return Operator(ctx, h, nx * ny * nz, (), f"stencil{len(coef)}")
+
+
+def convdiff_nnz(dim: int, n: int, npts: int) -> int:
+    return int(L.check(L.lib().pbcgs_convdiff_nnz(dim, n, npts)))
+
+
+def assemble_convdiff(dim: int, n: int, npts: int, beta, kappa: torch.Tensor | None = None, shift: float = 0.0,
+                      device: int | None = None, ctx: Context | None = None):
+    """Device assembly of the workloads' convection-diffusion operator -> (row_ptr, col_idx, val)."""
+    ctx = ctx or default_context(device)
+    dev = torch.device("cuda", ctx.device)
+    N = n ** dim
+    nnz = convdiff_nnz(dim, n, npts)
+    rp = torch.empty(N + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(nnz, dtype=torch.int32, device=dev)
+    val = torch.empty(nnz, dtype=torch.float64, device=dev)
+    b = (ctypes.c_double * 3)(*([float(v) for v in beta] + [0.0] * (3 - len(beta))))
+    if npts == 27:
+        _check_vec(kappa, (n + 1) ** 3, "kappa")
+    L.check(L.lib().pbcgs_assemble_convdiff(ctx.handle, dim, n, npts, b, _ptr(kappa), float(shift),
+                                            _ptr(rp), _ptr(col), _ptr(val)), ctx.handle)
+    return rp, col, val
+
+
+def spmv(A: Operator, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    _check_vec(x, A.n, "x")
+    y = torch.empty_like(x) if out is None else out
+    _check_vec(y, A.n, "out")
+    L.check(L.lib().pbcgs_spmv(A.ctx.handle, A.handle, _ptr(x), _ptr(y)), A.ctx.handle)
+    return y
+
+
+def dot(x: torch.Tensor, y: torch.Tensor, ctx: Context | None = None) -> float:
+    """(x, y) in pairwise order (bit-reproducible)."""
+    ctx = ctx or default_context(x.device.index)
+    _check_vec(x, x.numel(), "x")
+    _check_vec(y, x.numel(), "y")
+    res = ctypes.c_double()
+    L.check(L.lib().pbcgs_dot(ctx.handle, x.numel(), _ptr(x), _ptr(y), ctypes.byref(res)), ctx.handle)
+    return res.value
+
+
+def jacobi_dinv(A: Operator) -> torch.Tensor:
+    d = torch.empty(A.n, dtype=torch.float64, device=torch.device("cuda", A.ctx.device))
+    L.check(L.lib().pbcgs_jacobi_dinv(A.ctx.handle, A.handle, _ptr(d)), A.ctx.handle)
+    return d
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    n_rr: int
+    status: int
+    syncs_per_iter: int
+    relres_rec: float
+    relres_true: float
+    ms: float
+    kernel_ms: tuple
+    kernel_calls: tuple
+    history: torch.Tensor | None = None
+
+    @property
+    def status_name(self) -> str:
+        return STATUS.get(self.status, str(self.status))
+
+
+def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, variant: str = "pbicgstab_rr",
+          precond: str | None = None, dinv: torch.Tensor | None = None, tol: float = 1e-8, maxit: int = 2000,
+          rr_period: int = 50, rr_max: int = -1, history: bool = False, check_every: int = 0,
+          graph: bool = True, time_kernels: bool = False, out: torch.Tensor | None = None):
+    """Solve A x = b; returns (x, SolveInfo).  x0 defaults to zero; ``out``
+    (optional) receives the iterate in place of a new tensor."""
+    _check_vec(b, A.n, "b")
+    if variant not in VARIANTS:
+        raise ValueError(f"variant must be one of {sorted(VARIANTS)}")
+    if precond not in (None, "none", "jacobi"):
+        raise ValueError("precond must be None or 'jacobi'")
+    if out is not None:
+        _check_vec(out, A.n, "out")
+        x = out
+        if x0 is None:
+            x.zero_()
+        else:
+            x.copy_(x0)
+    else:
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+    _check_vec(x, A.n, "x")
+    if dinv is not None:
+        _check_vec(dinv, A.n, "dinv")
+    hist = torch.full((maxit + 1,), float("nan"), dtype=torch.float64, device=b.device) if history else None
+    o = L.Opts()
+    o.variant = VARIANTS[variant]
+    o.precond = L.PRECOND_JACOBI if precond == "jacobi" else L.PRECOND_NONE
+    o.precision = L.FP64
+    o.maxit = int(maxit)
+    o.tol = float(tol)
+    o.rr_period = int(rr_period)
+    o.rr_max = int(rr_max)
+    o.check_every = int(check_every)
+    o.flags = (0 if graph else L.FLAG_DIRECT) | (L.FLAG_TIME_KERNELS if time_kernels else 0)
+    o.history = hist.data_ptr() if hist is not None else None
+    info = L.Info()
+    L.check(L.lib().pbcgs_solve(A.ctx.handle, A.handle, _ptr(b), _ptr(x), _ptr(dinv), ctypes.byref(o),
+                                ctypes.byref(info)), A.ctx.handle)
+    si = SolveInfo(info.iters, info.n_rr, info.status, info.syncs_per_iter, info.relres_rec, info.relres_true,
+                   info.ms, tuple(info.kernel_ms), tuple(info.kernel_calls))
+    if hist is not None:
+        si.history = hist[: info.iters + 1]
+    return x, si

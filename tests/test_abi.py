@@ -1,0 +1,70 @@
+"""CPU checks of the C ABI boundary: the library loads, exports every function
+include/pbcgs.h declares, reports errors without a GPU, and the product path
+never touches the oracle."""
+
+import ctypes
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_1612_01395_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_function():
+    L = _lib.lib()
+    names = _lib.declared_functions()
+    assert len(names) >= 14
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding knows every declared function's signature
+    assert set(names) <= set(_lib._SIGNATURES), set(names) - set(_lib._SIGNATURES)
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(names) <= exported
+
+
+def test_status_strings_and_nnz_without_gpu():
+    L = _lib.lib()
+    for code, name in [(0, b"success"), (1, b"maxit"), (2, b"breakdown"), (3, b"nonfinite"),
+                       (-1, b"invalid argument"), (-4, b"unsupported")]:
+        assert L.pbcgs_status_str(code) == name
+    import oracle
+    for dim, npts in ((2, 5), (3, 7), (3, 27)):
+        for n in (1, 2, 7, 64):
+            assert L.pbcgs_convdiff_nnz(dim, n, npts) == oracle.assemble_nnz(dim, n, npts)
+    assert L.pbcgs_convdiff_nnz(2, 8, 7) == _lib.ERR_INVALID_ARG
+
+
+def test_null_arguments_are_rejected_not_crashing():
+    L = _lib.lib()
+    assert L.pbcgs_ctx_create(0, None, None) == _lib.ERR_INVALID_ARG
+    assert L.pbcgs_ctx_destroy(None) == _lib.ERR_INVALID_ARG
+    assert L.pbcgs_op_destroy(None) == _lib.ERR_INVALID_ARG
+    assert _lib.last_error(None)
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd") and os.access("/dev/kfd", os.R_OK), reason="a GPU is present")
+def test_context_creation_fails_cleanly_without_gpu():
+    h = ctypes.c_void_p()
+    rc = _lib.lib().pbcgs_ctx_create(0, None, ctypes.byref(h))
+    assert rc < 0
+    assert _lib.last_error(None)
+
+
+def test_product_path_does_not_load_the_oracle():
+    code = ("import sys; import paper_1612_01395_amd.solver, paper_1612_01395_amd._lib as L; L.lib(); "
+            "print('oracle' in sys.modules)")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "False"
+    pkg = os.path.join(ROOT, "paper_1612_01395_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text, f

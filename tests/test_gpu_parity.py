@@ -1,0 +1,219 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+The library's arithmetic contract (no fused multiply-add, rows summed in
+column order, pairwise dot products) is the oracle's, so every comparison
+below is bitwise: assembly, SpMV, dot products, Jacobi, and whole solves --
+iterates, iteration counts, replacement counts, residuals and histories.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1612_01395_amd import inputs, solver
+from gpu_util import csr_op, dev_t, host, require_gpu, same, say, stencil_coefs
+
+pytestmark = pytest.mark.gpu
+
+ALG = {"bicgstab": oracle.ALG_BICGSTAB, "pbicgstab": oracle.ALG_PBICGSTAB, "pbicgstab_rr": oracle.ALG_PBICGSTAB_RR}
+
+
+def small_cases():
+    c3n = 10
+    return {
+        "c1": (oracle.assemble_workload(inputs.workload("c1")), None, 2, 64),
+        "c2_24": (oracle.assemble_workload(inputs.workload("c2", n=24)), None, 3, 24),
+        "c3_10": (oracle.assemble_workload(inputs.workload("c3", n=c3n), inputs.kappa_cells(c3n)), None, 3, c3n),
+    }
+
+
+CASES = small_cases()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_spmv_bitwise(name):
+    require_gpu()
+    A, _, dim, n = CASES[name]
+    say(f"spmv {name} n={A.n}")
+    x = inputs.random_vector(A.n, 1)
+    y_or = oracle.spmv(A, x)
+    op = csr_op(A)
+    y = host(solver.spmv(op, dev_t(x)))
+    assert same(y, y_or)
+    if name != "c3_10":
+        st = solver.stencil(n, n, n if dim == 3 else 1, stencil_coefs(A, dim, n))
+        assert same(host(solver.spmv(st, dev_t(x))), y_or)
+
+
+@pytest.mark.parametrize("n", [1, 7, 255, 256, 257, 4096, 65549, 1 << 21, 3000001])
+def test_dot_bitwise_and_shape_independent(n):
+    require_gpu()
+    say(f"dot n={n}")
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) * np.exp(rng.uniform(-30, 30, n))
+    y = rng.standard_normal(n)
+    ref = oracle.dot(x, y)
+    xd, yd = dev_t(x), dev_t(y)
+    old = os.environ.get("PBCGS_GTARGET")
+    try:
+        for g in ("1024", "7", "64", "4096"):
+            os.environ["PBCGS_GTARGET"] = g
+            assert same(solver.dot(xd, yd), ref), g
+    finally:
+        if old is None:
+            os.environ.pop("PBCGS_GTARGET", None)
+        else:
+            os.environ["PBCGS_GTARGET"] = old
+
+
+@pytest.mark.parametrize("name,n", [("c1", 64), ("c1", 5), ("c2", 1), ("c2", 33), ("c3", 2), ("c3", 12)])
+def test_device_assembly_bitwise(name, n):
+    require_gpu()
+    w = inputs.workload(name, n=n)
+    kappa = inputs.kappa_cells(n, w.kappa_sigma) if w.npts == 27 else None
+    say(f"assembly {name} n={n}")
+    A = oracle.assemble_workload(w, kappa)
+    rp, col, val = solver.assemble_convdiff(w.dim, n, w.npts, w.beta, None if kappa is None else dev_t(kappa),
+                                            w.shift)
+    assert np.array_equal(host(rp), A.row_ptr)
+    assert np.array_equal(host(col), A.col)
+    assert same(host(val), A.val)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_jacobi_dinv_bitwise(name):
+    require_gpu()
+    A = CASES[name][0]
+    assert same(host(solver.jacobi_dinv(csr_op(A))), oracle.jacobi_dinv(A))
+
+
+def _compare(name, variant, precond, opkind, A, dim, n, dinv_vec=None, tol=1e-10, rr=20, maxit=2000):
+    say(f"solve {name} {variant} precond={precond} op={opkind} dinv_vec={dinv_vec is not None}")
+    xt = inputs.x_true(A.n)
+    b = oracle.spmv(A, xt)
+    dv = None
+    if precond == "jacobi":
+        dv = dinv_vec if dinv_vec is not None else oracle.jacobi_dinv(A)
+    x_or, info_or = oracle.solve(A, b, algo=ALG[variant], dinv=dv, tol=tol, maxit=maxit, rr_period=rr,
+                                 history=True)
+    if opkind == "csr":
+        op = csr_op(A)
+    else:
+        op = solver.stencil(n, n, n if dim == 3 else 1, stencil_coefs(A, dim, n))
+    x, info = solver.solve(op, dev_t(b), variant=variant, precond=precond,
+                           dinv=None if dinv_vec is None else dev_t(dinv_vec), tol=tol, maxit=maxit,
+                           rr_period=rr, history=True)
+    assert info.status == info_or["status"], (info, info_or)
+    assert info.iters == info_or["iters"], (info, info_or)
+    assert info.n_rr == info_or["n_rr"]
+    assert same(host(x), x_or), float(np.abs(host(x) - x_or).max())
+    assert same([info.relres_rec, info.relres_true], [info_or["relres_rec"], info_or["relres_true"]])
+    assert same(host(info.history), info_or["history"])
+    return info
+
+
+@pytest.mark.parametrize("variant", list(ALG))
+@pytest.mark.parametrize("precond", [None, "jacobi"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_bitwise_csr(name, variant, precond):
+    require_gpu()
+    A, _, dim, n = CASES[name]
+    _compare(name, variant, precond, "csr", A, dim, n)
+
+
+@pytest.mark.parametrize("variant", list(ALG))
+@pytest.mark.parametrize("precond", [None, "jacobi"])
+@pytest.mark.parametrize("name", ["c1", "c2_24"])
+def test_solve_bitwise_stencil(name, variant, precond):
+    require_gpu()
+    A, _, dim, n = CASES[name]
+    _compare(name, variant, precond, "stencil", A, dim, n)
+
+
+@pytest.mark.parametrize("variant", list(ALG))
+def test_solve_bitwise_vector_jacobi(variant):
+    """A non-constant M^{-1} exercises the vector preconditioner path."""
+    require_gpu()
+    A, _, dim, n = CASES["c2_24"]
+    d = oracle.jacobi_dinv(A) * (1.0 + 0.25 * np.random.default_rng(3).random(A.n))
+    _compare("c2_24", variant, "jacobi", "csr", A, dim, n, dinv_vec=d)
+
+
+def test_launch_modes_and_shapes_identical():
+    require_gpu()
+    A, _, dim, n = CASES["c2_24"]
+    op = csr_op(A)
+    b = dev_t(oracle.spmv(A, inputs.x_true(A.n)))
+    ref, info_ref = solver.solve(op, b, variant="pbicgstab_rr", precond="jacobi", tol=1e-10, rr_period=7)
+    ref = host(ref)
+    variants = [dict(graph=False), dict(time_kernels=True), dict(check_every=1), dict(check_every=5),
+                dict(check_every=1000)]
+    for kw in variants:
+        say(f"mode {kw}")
+        x, info = solver.solve(op, b, variant="pbicgstab_rr", precond="jacobi", tol=1e-10, rr_period=7, **kw)
+        assert same(host(x), ref) and info.iters == info_ref.iters, kw
+    old = os.environ.get("PBCGS_GTARGET")
+    try:
+        for g in ("3", "16", "4096"):
+            os.environ["PBCGS_GTARGET"] = g
+            say(f"gtarget {g}")
+            x, info = solver.solve(op, b, variant="pbicgstab_rr", precond="jacobi", tol=1e-10, rr_period=7)
+            assert same(host(x), ref) and info.iters == info_ref.iters, g
+    finally:
+        if old is None:
+            os.environ.pop("PBCGS_GTARGET", None)
+        else:
+            os.environ["PBCGS_GTARGET"] = old
+
+
+def test_rr_max_and_maxit_and_x0():
+    require_gpu()
+    A, _, dim, n = CASES["c1"]
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    x0 = inputs.random_vector(A.n, 5)
+    for kw in (dict(rr_period=10, rr_max=2, tol=1e-12, maxit=200), dict(rr_period=1, rr_max=-1, tol=1e-9, maxit=500),
+               dict(rr_period=10, rr_max=-1, tol=0.0, maxit=37)):
+        say(f"rr case {kw}")
+        x_or, i_or = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, x0=x0, **kw)
+        x, info = solver.solve(csr_op(A), dev_t(b), dev_t(x0), variant="pbicgstab_rr", **kw)
+        assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"])
+        assert same(host(x), x_or)
+
+
+def test_status_cases_match_oracle():
+    require_gpu()
+    skew = oracle.CSR([0, 1, 2], [1, 0], [1.0, -1.0])
+    twoI = oracle.CSR(np.arange(6), np.arange(5), np.full(5, 2.0))
+    C = oracle.assemble_workload(inputs.workload("c1", n=8))
+    bn = np.ones(C.n)
+    bn[5] = np.nan
+    cases = [("skew", skew, np.array([1.0, 2.0]), {}), ("2I", twoI, np.array([1.0, -3.0, 0.5, 7.0, 2.0]), {}),
+             ("zero-b", C, np.zeros(C.n), {}), ("nan-b", C, bn, {}),
+             ("maxit", C, oracle.spmv(C, inputs.x_true(C.n)), dict(tol=1e-14, maxit=3))]
+    for name, A, b, kw in cases:
+        for variant in ALG:
+            say(f"status {name} {variant}")
+            x_or, i_or = oracle.solve(A, b, algo=ALG[variant], **kw)
+            x, info = solver.solve(csr_op(A), dev_t(b), variant=variant, **kw)
+            assert (info.status, info.iters) == (i_or["status"], i_or["iters"]), (name, variant, info, i_or)
+            assert same(host(x), x_or), (name, variant)
+
+
+def test_api_errors():
+    require_gpu()
+    from paper_1612_01395_amd import _lib
+    bad = oracle.CSR([0, 2, 1], [0, 1], [1.0, 1.0])  # decreasing row pointer
+    with pytest.raises(_lib.PbcgsError):
+        csr_op(bad)
+    badcol = oracle.CSR([0, 1, 2], [0, 5], [1.0, 1.0])
+    with pytest.raises(_lib.PbcgsError):
+        csr_op(badcol)
+    nodiag = oracle.CSR([0, 1, 2], [1, 0], [1.0, 1.0])
+    op = csr_op(nodiag)
+    with pytest.raises(_lib.PbcgsError):
+        solver.solve(op, dev_t(np.ones(2)), precond="jacobi")
+    with pytest.raises(_lib.PbcgsError):
+        solver.solve(op, dev_t(np.ones(2)), tol=-1.0)

@@ -190,3 +190,15 @@ def test_ptp_stencils_via_beta_free_operator():
     S = L.to_scipy().toarray()
     assert (np.diag(S) == 4.0).all()
     assert sorted(set(S[np.nonzero(S - np.diag(np.diag(S)))])) == [-1.0]
+
+
+def test_row_range_assembly_is_a_slice_of_the_whole():
+    n = 9
+    kappa = inputs.kappa_cells(n, 1.0)
+    A = oracle.assemble(3, n, 27, (100.0, 0.0, 50.0), kappa, 0.1)
+    for r0, r1 in ((0, 1), (100, 300), (700, n ** 3)):
+        rp, col, val = oracle.assemble_rows(3, n, 27, (100.0, 0.0, 50.0), r0, r1, kappa, 0.1)
+        lo, hi = A.row_ptr[r0], A.row_ptr[r1]
+        np.testing.assert_array_equal(rp, A.row_ptr[r0:r1 + 1] - lo)
+        np.testing.assert_array_equal(col, A.col[lo:hi])
+        np.testing.assert_array_equal(val, A.val[lo:hi])
