@@ -3,28 +3,34 @@
 // Every solver iteration is a short chain of fused kernels.  A fused kernel
 // streams over the rows once: one SpMV row, the AXPY recurrences of that row
 // and the row's products for the dot products of the next reduction phase.
-// The kernel boundary is the only grid-wide synchronisation, and the last
-// workgroup to finish a kernel completes that kernel's reduction and computes
-// the scalars of the method on the device, so the host is never in the loop.
+// The kernel boundary is the only grid-wide synchronisation and the scalars of
+// the method are computed on the device, so the host is never in the loop.
 //
 //   p-BiCGStab (paper Algorithms 9 and 11, Sections 3.3 and 3.6):
-//     k_pa  t := A w^ ; lines 5-11 and 13 of Algorithm 11 ; partial (q,y), (y,y)
-//           last workgroup: omega_i                                (reduction 1)
-//     k_pb  v := A z^ ; lines 17-20 and 22 ; partial (r0,r), (r0,w), (r0,s),
-//           (r0,z), (r,r); last workgroup: beta_i, alpha_{i+1}, stop (reduction 2)
+//     k_pa  finishes reduction 2 of the previous iteration (stop test, beta,
+//           alpha), then t := A w^ ; lines 5-11 and 13 ; partials (q,y), (y,y)
+//     k_pb  finishes reduction 1 (omega), then v := A z^ ; lines 17-20 and 22 ;
+//           partials (r0,r), (r0,w), (r0,s), (r0,z), (r,r)
 //   two kernel boundaries per iteration, against five for BiCGStab (Algorithm 7:
 //   SpMV | reduction | AXPY | SpMV + reduction | AXPY + reduction | AXPY).
 //
-// Determinism: rows map to threads one to one inside tiles of 256 rows; a
-// workgroup owns a contiguous, aligned run of tpw tiles (tpw a power of two),
-// and the workgroups' partial sums are combined in workgroup order.  Wave
-// butterflies (xor 1, 2, ..., 32), the (w0 + w1) + (w2 + w3) combination of
-// the four waves, the tree over the tiles of a workgroup and the tree over the
-// workgroups all follow the balanced binary tree over the row index.  The sum
-// is therefore the pairwise sum of the products, whatever the grid shape, and
-// equals a sequential pairwise evaluation bit for bit.  (Padding subtrees of
-// zeros only add +0, which changes no value; the final + 0.0 fixes the sign
-// of a zero result.)  Compiled with -ffp-contract=off: no fused multiply-add.
+// Reductions complete on read: a kernel writes one partial sum per workgroup,
+// and every workgroup of the next kernel adds those partials itself (a few KB
+// from L2, the same pairwise tree, so every workgroup obtains the same bits)
+// before computing the method's scalars.  No workgroup waits for another and
+// no device-scope fence or atomic is needed; the kernel boundary is the only
+// synchronisation.  The scalars travel in a two-slot state: launch q reads
+// slot q mod 2 and workgroup 0 writes slot (q+1) mod 2.
+//
+// Row layout and determinism: wave w of workgroup b handles R consecutive
+// blocks of 64 rows starting at row 64 R (4 b + w); lane l handles row l of
+// each block, so vector loads are fully coalesced.  A DPP tree sums each
+// block into lane 63, the workgroup adds its 4 R block sums as a balanced
+// tree, and the consumer adds the workgroups' partials as a balanced tree:
+// altogether the balanced binary tree over the row index, whatever R and the
+// grid size are.  (Padding subtrees of zeros only add +0, which changes no
+// value; the final + 0.0 fixes the sign of a zero result.)  Compiled with
+// -ffp-contract=off: no fused multiply-add anywhere.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,17 +38,16 @@
 
 namespace pbcgs {
 
-constexpr int kWG = 256;                      // threads per workgroup: 4 x wave64
-constexpr int kTile = 256;                    // rows per tile: one row per thread
-constexpr int kMaxTpw = 256;                  // tiles per workgroup (power of two)
-constexpr int kFinalChunk = 4;                // partials per thread in the final tree
-constexpr int kMaxG = kWG * kFinalChunk;      // workgroups per reduction kernel
-constexpr int kMaxD = 5;                      // dot products per reduction phase
+constexpr int kWG = 256;                  // threads per workgroup: 4 x wave64
+constexpr int kMaxD = 5;                  // dot products per reduction phase
+constexpr int kMaxR = 64;                 // 64-row blocks per wave
+constexpr int kMaxG = 1024;               // workgroups of a producing kernel
+constexpr int kChunk = kMaxG / kWG;       // partials per thread when consuming
 
 enum : int32_t { DS_RUNNING = 0, DS_SUCCESS = 1, DS_BREAKDOWN = 2, DS_NONFINITE = 3 };
 
 // Device-resident solver state: scalars of the method and the status word.
-struct alignas(64) DevState {
+struct alignas(128) DevState {
   double alpha;   // alpha_i
   double beta;    // beta_{i-1}
   double omega;   // omega_{i-1} (omega_i once reduction 1 of iteration i is done)
@@ -53,11 +58,8 @@ struct alignas(64) DevState {
   double result;  // output of utility reductions
   int32_t status;
   int32_t iters;  // completed x updates
-  int32_t yzero;  // (y, y) == 0 seen in reduction 1: the next x update finishes
-  int32_t n_rr;
-  uint32_t counter;  // arrivals for the last-workgroup election
-  int32_t errflag;   // utility kernels: structural error seen
-  int32_t pad[2];
+  int32_t n_rr;   // residual replacements done
+  int32_t pad[5];
 };
 
 // ---------------------------------------------------------------------------
@@ -67,10 +69,27 @@ struct CsrOp {
   const int32_t* __restrict__ rp;
   const int32_t* __restrict__ ci;
   const double* __restrict__ va;
+  // Entries are fetched 8 at a time with the index clamped into the row, so
+  // all loads of a short row are in flight together; only the entries that
+  // exist are added, in stored order.
   __device__ __forceinline__ double apply(int32_t row, const double* __restrict__ x) const {
-    const int32_t e = rp[row + 1];
+    const int32_t b = rp[row], e = rp[row + 1];
     double acc = 0.0;
-    for (int32_t k = rp[row]; k < e; ++k) acc = acc + va[k] * x[ci[k]];
+    for (int32_t k0 = b; k0 < e; k0 += 8) {
+      int32_t c[8];
+      double v[8], xv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int32_t k = min(k0 + j, e - 1);
+        c[j] = ci[k];
+        v[j] = va[k];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xv[j] = x[c[j]];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (k0 + j < e) acc = acc + v[j] * xv[j];
+    }
     return acc;
   }
 };
@@ -112,13 +131,21 @@ struct StencilOp {
 // 1/a_ii, Jacobi with one constant 1/a_ii (constant diagonal).
 enum { PC_NONE = 0, PC_VEC = 1, PC_SCALAR = 2 };
 
-// Kernel arguments: sizes, launch shape and every vector of the solvers.
-// Without a preconditioner the hatted pointers alias the unhatted ones.
+// Kernel arguments: sizes, launch shape, state slots, partial-sum buffers and
+// every vector of the solvers.  Without a preconditioner the hatted pointers
+// alias the unhatted ones.
 struct Args {
-  int32_t n, ntiles, tpw, G;
-  DevState* st;
-  double* part;       // [kMaxD][kMaxG] workgroup partial sums
-  double* hist;       // nullable history of ||r_i|| / ||r_0||
+  int32_t n;              // rows
+  int32_t G;              // workgroups of this launch (producing kernels)
+  int32_t R;              // 64-row blocks per wave (power of two <= kMaxR)
+  int32_t Gin;            // partials to consume (workgroups of the producer)
+  int32_t first;          // first iteration: consume the setup reduction
+  int32_t pad_;
+  const DevState* sin;    // state read by this launch
+  DevState* sout;         // state written by workgroup 0
+  const double* pin;      // partials consumed: pin[k * kMaxG + wg]
+  double* pout;           // partials produced: pout[k * kMaxG + wg]
+  double* hist;           // nullable history of ||r_i|| / ||r_0||
   const double* b;
   double* x;
   double *r0, *r, *rh, *w, *wh, *t, *ph, *s, *sh, *z, *zh, *v;  // p-BiCGStab
@@ -137,252 +164,261 @@ __device__ __forceinline__ double apply_pc(const Args& a, int32_t row, double va
 // ---------------------------------------------------------------------------
 // Pairwise reduction machinery.
 // ---------------------------------------------------------------------------
-template <int ND>
-__device__ __forceinline__ void wave_tree(double (&v)[ND]) {
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) {
-#pragma unroll
-    for (int k = 0; k < ND; ++k) v[k] = v[k] + __shfl_xor(v[k], m, 64);
-  }
+
+// 64-bit DPP move: lane l receives the value of the lane selected by CTRL in
+// the rows enabled by ROW_MASK; other lanes receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
 
+// Balanced-tree sum over the 64 lanes of a wave; the result is valid in lane
+// 63.  Level m adds to the last lane of every aligned block of 2m lanes the
+// sum held by the last lane of the block's left half (row_shr 1, 2, 4, 8,
+// then row_bcast 15 and 31 across the 16-lane rows), so lane 63 ends with
+// ((l0 + l1) + (l2 + l3)) + ... exactly as the pairwise order prescribes.
 template <int ND>
-struct TileRed {
-  double lw[2][4][ND];        // per-wave sums, double-buffered by tile parity
-  double tp[ND][kMaxTpw];     // the workgroup's tile sums, in tile order
-};
-
-// Sum of the 256 rows of one tile into sm.tp[.][tl] (thread 0 writes).
-template <int ND>
-__device__ __forceinline__ void tile_reduce(TileRed<ND>& sm, double (&v)[ND], int tl) {
-  wave_tree<ND>(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
+__device__ __forceinline__ void wave_sum63(double (&v)[ND]) {
 #pragma unroll
-    for (int k = 0; k < ND; ++k) sm.lw[tl & 1][wave][k] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x111, 0xF>(v[k]);
 #pragma unroll
-    for (int k = 0; k < ND; ++k)
-      sm.tp[k][tl] = (sm.lw[tl & 1][0][k] + sm.lw[tl & 1][1][k]) +
-                     (sm.lw[tl & 1][2][k] + sm.lw[tl & 1][3][k]);
-  }
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x112, 0xF>(v[k]);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x114, 0xF>(v[k]);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x118, 0xF>(v[k]);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x142, 0xA>(v[k]);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x143, 0xC>(v[k]);
 }
 
-// Tree over the workgroup's ntl tile sums (wave w holds tiles 64w..64w+63);
-// thread 0 writes part[k][bid].
+// Balanced-tree sum of one value per thread over the workgroup (256 threads,
+// 4 waves); every thread receives the totals.
 template <int ND>
-__device__ __forceinline__ void wg_partial(TileRed<ND>& sm, int ntl, double* part, int bid) {
+__device__ __forceinline__ void wg_sum_all(double (&v)[ND], double (&out)[ND]) {
+  __shared__ double lw[4][ND];
+  wave_sum63<ND>(v);
+  if ((threadIdx.x & 63) == 63) {
+#pragma unroll
+    for (int k = 0; k < ND; ++k) lw[threadIdx.x >> 6][k] = v[k];
+  }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) out[k] = (lw[0][k] + lw[1][k]) + (lw[2][k] + lw[3][k]);
+  __syncthreads();
+}
+
+// Totals of the Gin partials of each of the ND sums in pin, in pairwise
+// order, "+ 0.0"; identical in every thread of every workgroup.
+template <int ND>
+__device__ __forceinline__ void gather_sums(const Args& a, double (&tot)[ND]) {
+  const int base = (int)threadIdx.x * kChunk;
   double v[ND];
-#pragma unroll
-  for (int k = 0; k < ND; ++k) v[k] = ((int)threadIdx.x < ntl) ? sm.tp[k][threadIdx.x] : 0.0;
-  wave_tree<ND>(v);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < ND; ++k) sm.lw[0][wave][k] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < ND; ++k)
-      part[k * kMaxG + bid] = (sm.lw[0][0][k] + sm.lw[0][1][k]) + (sm.lw[0][2][k] + sm.lw[0][3][k]);
-  }
-}
-
-// Arrival at the end of a kernel; true in the workgroup that arrives last,
-// which then sees every other workgroup's writes.
-__device__ __forceinline__ bool elect_last(DevState* st, int G) {
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(&st->counter, 1u);
-    s_last = (prev == (unsigned)(G - 1));
-  }
-  __syncthreads();
-  const bool last = s_last != 0;
-  if (last) __threadfence();
-  return last;
-}
-
-// Tree over the G workgroup partials of each of the ND sums (G <= kMaxG);
-// result valid in thread 0, already "+ 0.0".
-template <int ND>
-__device__ __forceinline__ void final_reduce(const double* part, int G, double (&out)[ND]) {
-  __shared__ double lw[4][kMaxD];
-  double v[ND];
-  const int base = threadIdx.x * kFinalChunk;
 #pragma unroll
   for (int k = 0; k < ND; ++k) {
-    double c[kFinalChunk];
+    double c[kChunk];
 #pragma unroll
-    for (int j = 0; j < kFinalChunk; ++j)
-      c[j] = (base + j < G) ? part[k * kMaxG + base + j] : 0.0;
+    for (int j = 0; j < kChunk; ++j) c[j] = (base + j < a.Gin) ? a.pin[k * kMaxG + base + j] : 0.0;
 #pragma unroll
-    for (int w = 1; w < kFinalChunk; w <<= 1) {
+    for (int w = 1; w < kChunk; w <<= 1) {
 #pragma unroll
-      for (int j = 0; j < kFinalChunk; j += 2 * w) c[j] = c[j] + c[j + w];
+      for (int j = 0; j < kChunk; j += 2 * w) c[j] = c[j] + c[j + w];
     }
     v[k] = c[0];
   }
-  wave_tree<ND>(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
+  wg_sum_all<ND>(v, tot);
 #pragma unroll
-    for (int k = 0; k < ND; ++k) lw[wave][k] = v[k];
+  for (int k = 0; k < ND; ++k) tot[k] = tot[k] + 0.0;
+}
+
+// The workgroup's rows with ND products each; writes its partial sums to
+// pout[k][blockIdx.x].  Body(row, d) handles one row (rows past n give 0).
+template <int ND, class Body>
+__device__ __forceinline__ void produce(const Args& a, Body body) {
+  __shared__ double blk[ND][kWG];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t wbase = ((int64_t)blockIdx.x * 4 + wave) * a.R * 64;
+  for (int j = 0; j < a.R; ++j) {
+    const int64_t b0 = wbase + (int64_t)j * 64;
+    double d[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) d[k] = 0.0;
+    if (b0 < a.n) {
+      const int64_t row = b0 + lane;
+      if (row < a.n) body((int32_t)row, d);
+      wave_sum63<ND>(d);
+    }
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < ND; ++k) blk[k][wave * a.R + j] = d[k];
+    }
   }
   __syncthreads();
+  double v[ND], tot[ND];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) v[k] = ((int)threadIdx.x < 4 * a.R) ? blk[k][threadIdx.x] : 0.0;
+  wg_sum_all<ND>(v, tot);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < ND; ++k) out[k] = ((lw[0][k] + lw[1][k]) + (lw[2][k] + lw[3][k])) + 0.0;
+    for (int k = 0; k < ND; ++k) a.pout[k * kMaxG + blockIdx.x] = tot[k];
+  }
+}
+
+// The workgroup's rows without a reduction.
+template <class Body>
+__device__ __forceinline__ void each_row(const Args& a, Body body) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t wbase = ((int64_t)blockIdx.x * 4 + wave) * a.R * 64;
+  for (int j = 0; j < a.R; ++j) {
+    const int64_t row = wbase + (int64_t)j * 64 + lane;
+    if (row < a.n) body((int32_t)row);
   }
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+__device__ __forceinline__ bool leader() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// Register copy of the state (field by field: no aligned aggregate on the stack).
+struct State {
+  double alpha, beta, omega, gamma, rho0, relres, tol, result;
+  int32_t status, iters, n_rr;
+};
+
+__device__ __forceinline__ State load_state(const DevState* p) {
+  State s;
+  s.alpha = p->alpha; s.beta = p->beta; s.omega = p->omega; s.gamma = p->gamma;
+  s.rho0 = p->rho0; s.relres = p->relres; s.tol = p->tol; s.result = p->result;
+  s.status = p->status; s.iters = p->iters; s.n_rr = p->n_rr;
+  return s;
+}
+
+__device__ __forceinline__ void publish(const Args& a, const State& s) {
+  if (leader()) {
+    DevState* p = a.sout;
+    p->alpha = s.alpha; p->beta = s.beta; p->omega = s.omega; p->gamma = s.gamma;
+    p->rho0 = s.rho0; p->relres = s.relres; p->tol = s.tol; p->result = s.result;
+    p->status = s.status; p->iters = s.iters; p->n_rr = s.n_rr;
+  }
+}
 
 // ---------------------------------------------------------------------------
-// Scalar steps of the method, run by thread 0 of the last workgroup.
+// Scalar steps of the method.  Every thread evaluates them on identical
+// inputs; only the leader writes the history.
 // ---------------------------------------------------------------------------
 
 // gamma = (r0, r0), rho0 = ||r0|| (Algorithms 7-11, line 2).
-__device__ __forceinline__ void fin_setup_gamma(DevState* st, double* hist, double g) {
-  st->gamma = g;
+__device__ __forceinline__ void fin_setup_gamma(State& s, double* hist, double g) {
+  s.gamma = g;
   const double rho0 = sqrt(g);
-  st->rho0 = rho0;
-  st->relres = 1.0;
-  if (hist) hist[0] = 1.0;
-  if (!finite(rho0)) st->status = DS_NONFINITE;
-  else if (rho0 == 0.0) { st->status = DS_SUCCESS; st->relres = 0.0; }
+  s.rho0 = rho0;
+  s.relres = 1.0;
+  if (hist && leader()) hist[0] = 1.0;
+  if (!finite(rho0)) s.status = DS_NONFINITE;
+  else if (rho0 == 0.0) { s.status = DS_SUCCESS; s.relres = 0.0; }
 }
 
 // alpha_0 = (r0, r0) / (r0, w0), beta_{-1} = omega_{-1} = 0 (Algorithm 9/11, lines 2-3).
-__device__ __forceinline__ void fin_setup_alpha(DevState* st, double delta) {
-  if (!finite(delta)) { st->status = DS_NONFINITE; return; }
-  if (delta == 0.0) { st->status = DS_BREAKDOWN; return; }
-  const double alpha = st->gamma / delta;
-  if (!finite(alpha)) { st->status = DS_NONFINITE; return; }
-  st->alpha = alpha;
-  st->beta = 0.0;
-  st->omega = 0.0;
+__device__ __forceinline__ void fin_setup_alpha(State& s, double delta) {
+  if (!finite(delta)) { s.status = DS_NONFINITE; return; }
+  if (delta == 0.0) { s.status = DS_BREAKDOWN; return; }
+  const double alpha = s.gamma / delta;
+  if (!finite(alpha)) { s.status = DS_NONFINITE; return; }
+  s.alpha = alpha;
+  s.beta = 0.0;
+  s.omega = 0.0;
 }
 
-// omega_i = (q, y) / (y, y)  (reduction 1; Algorithm 9 line 12, Algorithm 11 line 16).
-__device__ __forceinline__ void fin_omega(DevState* st, double qy, double yy) {
-  if (!finite(qy) || !finite(yy)) { st->status = DS_NONFINITE; return; }
-  if (yy == 0.0) { st->yzero = 1; return; }  // y = A q^ = 0: q = 0, exact convergence
+// omega_i = (q, y) / (y, y)  (reduction 1; Algorithm 7 lines 9-10, Algorithm
+// 9 line 12, Algorithm 11 line 16).  Returns true when (y, y) = 0: then q = 0
+// and x_i + alpha_i p^_i is the solution; the caller applies that update.
+__device__ __forceinline__ bool fin_omega(State& s, double* hist, double qy, double yy) {
+  if (!finite(qy) || !finite(yy)) { s.status = DS_NONFINITE; return false; }
+  if (yy == 0.0) {
+    s.iters += 1;
+    s.relres = 0.0;
+    if (hist && leader()) hist[s.iters] = 0.0;
+    s.status = DS_SUCCESS;
+    return true;
+  }
   const double omega = qy / yy;
-  if (!finite(omega)) { st->status = DS_NONFINITE; return; }
-  st->omega = omega;
-}
-
-// The x update of (y, y) == 0 finished the solve.
-__device__ __forceinline__ void fin_yzero(DevState* st, double* hist) {
-  st->iters += 1;
-  st->relres = 0.0;
-  if (hist) hist[st->iters] = 0.0;
-  st->status = DS_SUCCESS;
+  if (!finite(omega)) { s.status = DS_NONFINITE; return false; }
+  s.omega = omega;
+  return false;
 }
 
 // Reduction 2 of p-BiCGStab: stopping test, beta_i and alpha_{i+1} by eq. (3)
 // (Algorithm 9 lines 17-20, Algorithm 11 lines 24-26).
-__device__ __forceinline__ void fin_pipe_b(DevState* st, double* hist, const double (&d)[5]) {
+__device__ __forceinline__ void fin_pipe_b(State& s, double* hist, const double (&d)[5]) {
   const double g1 = d[0], eta = d[1], sig_s = d[2], sig_z = d[3], nu = d[4];
-  st->iters += 1;
+  s.iters += 1;
   if (!finite(g1) || !finite(eta) || !finite(sig_s) || !finite(sig_z) || !finite(nu)) {
-    st->status = DS_NONFINITE;
+    s.status = DS_NONFINITE;
     return;
   }
-  const double relres = sqrt(nu) / st->rho0;
-  st->relres = relres;
-  if (hist) hist[st->iters] = relres;
-  if (relres <= st->tol) { st->status = DS_SUCCESS; return; }
-  const double alpha = st->alpha, omega = st->omega, gamma = st->gamma;
-  if (omega == 0.0 || gamma == 0.0) { st->status = DS_BREAKDOWN; return; }
+  const double relres = sqrt(nu) / s.rho0;
+  s.relres = relres;
+  if (hist && leader()) hist[s.iters] = relres;
+  if (relres <= s.tol) { s.status = DS_SUCCESS; return; }
+  const double alpha = s.alpha, omega = s.omega, gamma = s.gamma;
+  if (omega == 0.0 || gamma == 0.0) { s.status = DS_BREAKDOWN; return; }
   const double beta = (alpha / omega) * (g1 / gamma);
-  if (!finite(beta)) { st->status = DS_NONFINITE; return; }
-  st->beta = beta;
+  if (!finite(beta)) { s.status = DS_NONFINITE; return; }
+  s.beta = beta;
   const double den = eta + beta * sig_s - beta * omega * sig_z;
-  if (den == 0.0 || g1 == 0.0) { st->status = DS_BREAKDOWN; return; }
+  if (den == 0.0 || g1 == 0.0) { s.status = DS_BREAKDOWN; return; }
   const double an = g1 / den;
-  if (!finite(an)) { st->status = DS_NONFINITE; return; }
-  st->alpha = an;
-  st->gamma = g1;
+  if (!finite(an)) { s.status = DS_NONFINITE; return; }
+  s.alpha = an;
+  s.gamma = g1;
 }
 
 // alpha_i = (r0, r_i) / (r0, s_i)  (Algorithm 7 lines 5-6).
-__device__ __forceinline__ void fin_bicg_alpha(DevState* st, double delta) {
-  if (!finite(delta)) { st->status = DS_NONFINITE; return; }
-  if (delta == 0.0) { st->status = DS_BREAKDOWN; return; }
-  const double alpha = st->gamma / delta;
-  if (!finite(alpha)) { st->status = DS_NONFINITE; return; }
-  st->alpha = alpha;
+__device__ __forceinline__ void fin_bicg_alpha(State& s, double delta) {
+  if (!finite(delta)) { s.status = DS_NONFINITE; return; }
+  if (delta == 0.0) { s.status = DS_BREAKDOWN; return; }
+  const double alpha = s.gamma / delta;
+  if (!finite(alpha)) { s.status = DS_NONFINITE; return; }
+  s.alpha = alpha;
 }
 
 // Stopping test and beta_i = (alpha/omega) (r0, r_{i+1}) / (r0, r_i)  (Algorithm 7 lines 13-14).
-__device__ __forceinline__ void fin_bicg_beta(DevState* st, double* hist, double g1, double nu) {
-  st->iters += 1;
-  if (!finite(g1) || !finite(nu)) { st->status = DS_NONFINITE; return; }
-  const double relres = sqrt(nu) / st->rho0;
-  st->relres = relres;
-  if (hist) hist[st->iters] = relres;
-  if (relres <= st->tol) { st->status = DS_SUCCESS; return; }
-  const double alpha = st->alpha, omega = st->omega, gamma = st->gamma;
-  if (omega == 0.0 || gamma == 0.0) { st->status = DS_BREAKDOWN; return; }
+__device__ __forceinline__ void fin_bicg_beta(State& s, double* hist, double g1, double nu) {
+  s.iters += 1;
+  if (!finite(g1) || !finite(nu)) { s.status = DS_NONFINITE; return; }
+  const double relres = sqrt(nu) / s.rho0;
+  s.relres = relres;
+  if (hist && leader()) hist[s.iters] = relres;
+  if (relres <= s.tol) { s.status = DS_SUCCESS; return; }
+  const double alpha = s.alpha, omega = s.omega, gamma = s.gamma;
+  if (omega == 0.0 || gamma == 0.0) { s.status = DS_BREAKDOWN; return; }
   const double beta = (alpha / omega) * (g1 / gamma);
-  if (!finite(beta)) { st->status = DS_NONFINITE; return; }
-  st->beta = beta;
-  st->gamma = g1;
+  if (!finite(beta)) { s.status = DS_NONFINITE; return; }
+  s.beta = beta;
+  s.gamma = g1;
 }
 
-// ---------------------------------------------------------------------------
-// Kernel skeleton: loop over the workgroup's tiles, one row per thread.
-// Body(row, d) computes the row and its ND products; rows past n give zeros.
-// ---------------------------------------------------------------------------
-template <int ND, class Body>
-__device__ __forceinline__ void tile_loop(TileRed<ND>& sm, const Args& a, Body body) {
-  const int bid = blockIdx.x;
-  int ntl = 0;
-  for (int tl = 0; tl < a.tpw; ++tl) {
-    const int tile = bid * a.tpw + tl;
-    if (tile >= a.ntiles) break;
-    ++ntl;
-    const int32_t row = tile * kTile + (int32_t)threadIdx.x;
-    double d[ND];
-#pragma unroll
-    for (int k = 0; k < ND; ++k) d[k] = 0.0;
-    if (row < a.n) body(row, d);
-    tile_reduce<ND>(sm, d, tl);
+// Reads the incoming state; a stopped solve is passed through unchanged.
+#define PBCGS_PROLOGUE(st)                      \
+  State st = load_state(a.sin);                 \
+  if (st.status != DS_RUNNING) {                \
+    publish(a, st);                             \
+    return;                                     \
   }
-  wg_partial<ND>(sm, ntl, a.part, bid);
-}
-
-template <class Body>
-__device__ __forceinline__ void row_loop(const Args& a, Body body) {
-  const int bid = blockIdx.x;
-  for (int tl = 0; tl < a.tpw; ++tl) {
-    const int tile = bid * a.tpw + tl;
-    if (tile >= a.ntiles) break;
-    const int32_t row = tile * kTile + (int32_t)threadIdx.x;
-    if (row < a.n) body(row);
-  }
-}
-
-__device__ __forceinline__ bool running(const DevState* st) { return st->status == DS_RUNNING; }
 
 // ===========================================================================
 // p-BiCGStab kernels (Algorithm 9, PC == PC_NONE; Algorithm 11 otherwise).
 // ===========================================================================
 
 // Setup 1: r0 = b - A x0 ; r = r0 ; r^ = M^{-1} r0 ; p^ = s = s^ = z = z^ = v = 0 ;
-// reduction (r0, r0).  PIPE = false: BiCGStab setup, p = r0 ; p^ = M^{-1} p.
+// partials of (r0, r0).  PIPE = false: BiCGStab setup, p = r0 ; p^ = M^{-1} p.
 template <class Op, int PC, bool PIPE>
 __global__ __launch_bounds__(kWG) void k_setup_r0(Op op, Args a) {
-  __shared__ TileRed<1> sm;
-  DevState* st = a.st;
-  if (!running(st)) return;
-  tile_loop<1>(sm, a, [&](int32_t row, double (&d)[1]) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  produce<1>(a, [&](int32_t row, double (&d)[1]) {
     const double r0 = a.b[row] - op.apply(row, a.x);
     a.r0[row] = r0;
     a.r[row] = r0;
@@ -402,47 +438,51 @@ __global__ __launch_bounds__(kWG) void k_setup_r0(Op op, Args a) {
     }
     d[0] = r0 * r0;
   });
-  if (!elect_last(st, a.G)) return;
-  double g[1];
-  final_reduce<1>(a.part, a.G, g);
-  if (threadIdx.x == 0) {
-    fin_setup_gamma(st, a.hist, g[0]);
-    st->counter = 0;
-  }
 }
 
-// Setup 2: w0 = A r^0 ; w^0 = M^{-1} w0 ; reduction (r0, w0) -> alpha_0.
+// Setup 2: gamma, rho0 from setup 1 ; w0 = A r^0 ; w^0 = M^{-1} w0 ;
+// partials of (r0, w0).
 template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_setup_w0(Op op, Args a) {
-  __shared__ TileRed<1> sm;
-  DevState* st = a.st;
-  if (!running(st)) return;
-  tile_loop<1>(sm, a, [&](int32_t row, double (&d)[1]) {
+  PBCGS_PROLOGUE(st)
+  double g[1];
+  gather_sums<1>(a, g);
+  fin_setup_gamma(st, a.hist, g[0]);
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  produce<1>(a, [&](int32_t row, double (&d)[1]) {
     const double w = op.apply(row, a.rh);
     a.w[row] = w;
     if (PC != PC_NONE) a.wh[row] = apply_pc<PC>(a, row, w);
     d[0] = a.r0[row] * w;
   });
-  if (!elect_last(st, a.G)) return;
-  double g[1];
-  final_reduce<1>(a.part, a.G, g);
-  if (threadIdx.x == 0) {
-    fin_setup_alpha(st, g[0]);
-    st->counter = 0;
-  }
 }
 
-// Phase A of iteration i.  RR2 = false: t = A w^ and the recurrences of lines
-// 5-11 (13).  RR2 = true (the iteration after a residual replacement): p^, s,
-// s^ were already recomputed, so t = A w^ and z = A s^ (both gathers), then
-// lines 9-11 and 13.  Reduction 1: (q, y), (y, y) -> omega_i.
+// Phase A of iteration i.  First it finishes the previous reduction: in the
+// first iteration alpha_0 (setup 2), later reduction 2 of iteration i-1 (stop
+// test, beta_{i-1}, alpha_i).  RR2 = false: t = A w^ and the recurrences of
+// lines 5-11 and 13.  RR2 = true (the iteration after a residual replacement):
+// p^, s, s^ were already recomputed and reduction 2 already finished, so
+// t = A w^ and z = A s^ (both gathers), then lines 9-11 and 13.
+// Partials: (q, y), (y, y).
 template <class Op, int PC, bool RR2>
 __global__ __launch_bounds__(kWG) void k_pa(Op op, Args a) {
-  __shared__ TileRed<2> sm;
-  DevState* st = a.st;
-  if (!running(st)) return;
-  const double alpha = st->alpha, beta = st->beta, omega = st->omega;
-  tile_loop<2>(sm, a, [&](int32_t row, double (&d)[2]) {
+  PBCGS_PROLOGUE(st)
+  if (!RR2) {
+    if (a.first) {
+      double g[1];
+      gather_sums<1>(a, g);
+      fin_setup_alpha(st, g[0]);
+    } else {
+      double g[5];
+      gather_sums<5>(a, g);
+      fin_pipe_b(st, a.hist, g);
+    }
+  }
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double alpha = st.alpha, beta = st.beta, omega = st.omega;
+  produce<2>(a, [&](int32_t row, double (&d)[2]) {
     const double t = op.apply(row, a.wh);  // line 23 of the previous iteration
     const double r = a.r[row], w = a.w[row];
     double s, z;
@@ -472,33 +512,26 @@ __global__ __launch_bounds__(kWG) void k_pa(Op op, Args a) {
     d[0] = q * y;
     d[1] = y * y;
   });
-  if (!elect_last(st, a.G)) return;
-  double g[2];
-  final_reduce<2>(a.part, a.G, g);
-  if (threadIdx.x == 0) {
-    fin_omega(st, g[0], g[1]);
-    st->counter = 0;
-  }
 }
 
-// Phase B of iteration i: v = A z^ ; lines 9-11 recomputed ; lines 17-20 ;
-// line 22 ; reduction 2 (r0,r), (r0,w), (r0,s), (r0,z), (r,r) -> beta, alpha.
+// Phase B of iteration i: omega_i from phase A's partials ; v = A z^ ;
+// lines 9-11 recomputed ; lines 17-20 ; line 22 ; partials of (r0,r),
+// (r0,w), (r0,s), (r0,z), (r,r) (reduction 2).
 template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_pb(Op op, Args a) {
-  __shared__ TileRed<5> sm;
-  DevState* st = a.st;
-  if (!running(st)) return;
-  const double alpha = st->alpha, omega = st->omega;
-  const bool yz = st->yzero != 0;
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2>(a, g2);
+  const double alpha = st.alpha;
+  const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
   if (yz) {
-    row_loop(a, [&](int32_t row) { a.x[row] = a.x[row] + alpha * a.ph[row]; });
-    if (elect_last(st, a.G) && threadIdx.x == 0) {
-      fin_yzero(st, a.hist);
-      st->counter = 0;
-    }
+    each_row(a, [&](int32_t row) { a.x[row] = a.x[row] + alpha * a.ph[row]; });
     return;
   }
-  tile_loop<5>(sm, a, [&](int32_t row, double (&d)[5]) {
+  if (st.status != DS_RUNNING) return;
+  const double omega = st.omega;
+  produce<5>(a, [&](int32_t row, double (&d)[5]) {
     const double v = op.apply(row, a.zh);                              // line 14
     const double r = a.r[row], s = a.s[row], w = a.w[row], z = a.z[row];
     const double q = r - alpha * s;
@@ -527,24 +560,21 @@ __global__ __launch_bounds__(kWG) void k_pb(Op op, Args a) {
     d[3] = r0 * z;
     d[4] = rn * rn;
   });
-  if (!elect_last(st, a.G)) return;
-  double g[5];
-  final_reduce<5>(a.part, a.G, g);
-  if (threadIdx.x == 0) {
-    fin_pipe_b(st, a.hist, g);
-    st->counter = 0;
-  }
 }
 
-// Residual-replacement iteration, phase B': only the x update of line 17
-// (r, r^, w are replaced next, so lines 18-20 and v are not needed).
+// Residual-replacement iteration, phase B': omega_i, then only the x update
+// of line 17 (r, r^, w are replaced next, so lines 18-20 and v are not needed).
 template <int PC>
 __global__ __launch_bounds__(kWG) void k_rr_x(Args a) {
-  DevState* st = a.st;
-  if (!running(st)) return;
-  const double alpha = st->alpha, omega = st->omega;
-  const bool yz = st->yzero != 0;
-  row_loop(a, [&](int32_t row) {
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2>(a, g2);
+  const double alpha = st.alpha;
+  const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
+  if (!yz && st.status != DS_RUNNING) return;
+  const double omega = st.omega;
+  each_row(a, [&](int32_t row) {
     if (yz) {
       a.x[row] = a.x[row] + alpha * a.ph[row];
     } else {
@@ -552,18 +582,14 @@ __global__ __launch_bounds__(kWG) void k_rr_x(Args a) {
       a.x[row] = a.x[row] + alpha * a.ph[row] + omega * qh;
     }
   });
-  if (yz && elect_last(st, a.G) && threadIdx.x == 0) {
-    fin_yzero(st, a.hist);
-    st->counter = 0;
-  }
 }
 
 // Residual replacement, first half (Section 4.2): r = b - A x ; r^ = M^{-1} r.
 template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_rr_r(Op op, Args a) {
-  DevState* st = a.st;
-  if (!running(st)) return;
-  row_loop(a, [&](int32_t row) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  each_row(a, [&](int32_t row) {
     const double r = a.b[row] - op.apply(row, a.x);
     a.r[row] = r;
     if (PC != PC_NONE) a.rh[row] = apply_pc<PC>(a, row, r);
@@ -571,13 +597,13 @@ __global__ __launch_bounds__(kWG) void k_rr_r(Op op, Args a) {
 }
 
 // Residual replacement, first half continued: w = A r^ ; w^ = M^{-1} w ;
-// reduction 2 on the true r, w.
+// partials of reduction 2 on the true r, w.
 template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_rr_w(Op op, Args a) {
-  __shared__ TileRed<5> sm;
-  DevState* st = a.st;
-  if (!running(st)) return;
-  tile_loop<5>(sm, a, [&](int32_t row, double (&d)[5]) {
+  PBCGS_PROLOGUE(st)
+  st.n_rr += 1;
+  publish(a, st);
+  produce<5>(a, [&](int32_t row, double (&d)[5]) {
     const double w = op.apply(row, a.rh);
     a.w[row] = w;
     if (PC != PC_NONE) a.wh[row] = apply_pc<PC>(a, row, w);
@@ -588,23 +614,20 @@ __global__ __launch_bounds__(kWG) void k_rr_w(Op op, Args a) {
     d[3] = r0 * a.z[row];
     d[4] = r * r;
   });
-  if (!elect_last(st, a.G)) return;
-  double g[5];
-  final_reduce<5>(a.part, a.G, g);
-  if (threadIdx.x == 0) {
-    st->n_rr += 1;
-    fin_pipe_b(st, a.hist, g);
-    st->counter = 0;
-  }
 }
 
-// Second half, iteration after a replacement: line 5 (p^ update) alone.
+// Second half, in the iteration after a replacement: reduction 2 (stop test,
+// beta, alpha), then line 5 (p^ update) alone.
 template <int PC>
 __global__ __launch_bounds__(kWG) void k_rr_p(Args a) {
-  DevState* st = a.st;
-  if (!running(st)) return;
-  const double beta = st->beta, omega = st->omega;
-  row_loop(a, [&](int32_t row) {
+  PBCGS_PROLOGUE(st)
+  double g[5];
+  gather_sums<5>(a, g);
+  fin_pipe_b(st, a.hist, g);
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double beta = st.beta, omega = st.omega;
+  each_row(a, [&](int32_t row) {
     if (PC != PC_NONE) a.ph[row] = a.rh[row] + beta * (a.ph[row] - omega * a.sh[row]);
     else a.ph[row] = a.r[row] + beta * (a.ph[row] - omega * a.s[row]);
   });
@@ -613,9 +636,9 @@ __global__ __launch_bounds__(kWG) void k_rr_p(Args a) {
 // Second half continued: s = A p^ ; s^ = M^{-1} s.
 template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_rr_s(Op op, Args a) {
-  DevState* st = a.st;
-  if (!running(st)) return;
-  row_loop(a, [&](int32_t row) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  each_row(a, [&](int32_t row) {
     const double s = op.apply(row, a.ph);
     a.s[row] = s;
     if (PC != PC_NONE) a.sh[row] = apply_pc<PC>(a, row, s);
@@ -626,76 +649,70 @@ __global__ __launch_bounds__(kWG) void k_rr_s(Op op, Args a) {
 // BiCGStab kernels (Algorithm 7, PC == PC_NONE; Algorithm 10 otherwise).
 // ===========================================================================
 
-// s = A p^ ; reduction (r0, s) -> alpha_i.
+// (first iteration: gamma, rho0 from the setup) ; s = A p^ ; partials of (r0, s).
 template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_b1(Op op, Args a) {
-  __shared__ TileRed<1> sm;
-  DevState* st = a.st;
-  if (!running(st)) return;
-  tile_loop<1>(sm, a, [&](int32_t row, double (&d)[1]) {
+  PBCGS_PROLOGUE(st)
+  if (a.first) {
+    double g[1];
+    gather_sums<1>(a, g);
+    fin_setup_gamma(st, a.hist, g[0]);
+  }
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  produce<1>(a, [&](int32_t row, double (&d)[1]) {
     const double s = op.apply(row, a.ph);
     a.s[row] = s;
     d[0] = a.r0[row] * s;
   });
-  if (!elect_last(st, a.G)) return;
-  double g[1];
-  final_reduce<1>(a.part, a.G, g);
-  if (threadIdx.x == 0) {
-    fin_bicg_alpha(st, g[0]);
-    st->counter = 0;
-  }
 }
 
-// q = r - alpha s ; q^ = M^{-1} q.
+// alpha_i ; q = r - alpha s ; q^ = M^{-1} q.
 template <int PC>
 __global__ __launch_bounds__(kWG) void k_b2(Args a) {
-  DevState* st = a.st;
-  if (!running(st)) return;
-  const double alpha = st->alpha;
-  row_loop(a, [&](int32_t row) {
+  PBCGS_PROLOGUE(st)
+  double g[1];
+  gather_sums<1>(a, g);
+  fin_bicg_alpha(st, g[0]);
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double alpha = st.alpha;
+  each_row(a, [&](int32_t row) {
     const double q = a.r[row] - alpha * a.s[row];
     a.q[row] = q;
     if (PC != PC_NONE) a.qh[row] = apply_pc<PC>(a, row, q);
   });
 }
 
-// y = A q^ ; reduction (q, y), (y, y) -> omega_i.
+// y = A q^ ; partials of (q, y), (y, y).
 template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_b3(Op op, Args a) {
-  __shared__ TileRed<2> sm;
-  DevState* st = a.st;
-  if (!running(st)) return;
-  tile_loop<2>(sm, a, [&](int32_t row, double (&d)[2]) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  produce<2>(a, [&](int32_t row, double (&d)[2]) {
     const double y = op.apply(row, a.qh);
     a.y[row] = y;
     d[0] = a.q[row] * y;
     d[1] = y * y;
   });
-  if (!elect_last(st, a.G)) return;
-  double g[2];
-  final_reduce<2>(a.part, a.G, g);
-  if (threadIdx.x == 0) {
-    fin_omega(st, g[0], g[1]);
-    st->counter = 0;
-  }
 }
 
-// x = x + alpha p^ + omega q^ ; r = q - omega y ; reduction (r0, r), (r, r).
+// omega_i ; x = x + alpha p^ + omega q^ ; r = q - omega y ; partials of (r0, r), (r, r).
 template <int PC>
 __global__ __launch_bounds__(kWG) void k_b4(Args a) {
-  __shared__ TileRed<2> sm;
-  DevState* st = a.st;
-  if (!running(st)) return;
-  const double alpha = st->alpha, omega = st->omega;
-  if (st->yzero != 0) {
-    row_loop(a, [&](int32_t row) { a.x[row] = a.x[row] + alpha * a.ph[row]; });
-    if (elect_last(st, a.G) && threadIdx.x == 0) {
-      fin_yzero(st, a.hist);
-      st->counter = 0;
-    }
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2>(a, g2);
+  const double alpha = st.alpha;
+  const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
+  if (yz) {
+    each_row(a, [&](int32_t row) { a.x[row] = a.x[row] + alpha * a.ph[row]; });
     return;
   }
-  tile_loop<2>(sm, a, [&](int32_t row, double (&d)[2]) {
+  if (st.status != DS_RUNNING) return;
+  const double omega = st.omega;
+  produce<2>(a, [&](int32_t row, double (&d)[2]) {
     const double q = a.q[row];
     a.x[row] = a.x[row] + alpha * a.ph[row] + omega * a.qh[row];
     const double r = q - omega * a.y[row];
@@ -703,26 +720,52 @@ __global__ __launch_bounds__(kWG) void k_b4(Args a) {
     d[0] = a.r0[row] * r;
     d[1] = r * r;
   });
-  if (!elect_last(st, a.G)) return;
-  double g[2];
-  final_reduce<2>(a.part, a.G, g);
-  if (threadIdx.x == 0) {
-    fin_bicg_beta(st, a.hist, g[0], g[1]);
-    st->counter = 0;
-  }
 }
 
-// p = r + beta (p - omega s) ; p^ = M^{-1} p.
+// stop test and beta_i ; p = r + beta (p - omega s) ; p^ = M^{-1} p.
 template <int PC>
 __global__ __launch_bounds__(kWG) void k_b5(Args a) {
-  DevState* st = a.st;
-  if (!running(st)) return;
-  const double beta = st->beta, omega = st->omega;
-  row_loop(a, [&](int32_t row) {
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2>(a, g2);
+  fin_bicg_beta(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double beta = st.beta, omega = st.omega;
+  each_row(a, [&](int32_t row) {
     const double p = a.r[row] + beta * (a.p[row] - omega * a.s[row]);
     a.p[row] = p;
     if (PC != PC_NONE) a.ph[row] = apply_pc<PC>(a, row, p);
   });
+}
+
+// Finishes a pending reduction in one workgroup: MODE 0 reduction 2 of
+// p-BiCGStab, 1 the setup alpha, 2 the setup gamma, 3 a plain sum into result.
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_finish(Args a) {
+  State st = load_state(a.sin);
+  if (MODE == 3) {
+    double g[1];
+    gather_sums<1>(a, g);
+    st.result = g[0];
+    publish(a, st);
+    return;
+  }
+  if (st.status != DS_RUNNING) {
+    publish(a, st);
+    return;
+  }
+  if (MODE == 0) {
+    double g[5];
+    gather_sums<5>(a, g);
+    fin_pipe_b(st, a.hist, g);
+  } else {
+    double g[1];
+    gather_sums<1>(a, g);
+    if (MODE == 1) fin_setup_alpha(st, g[0]);
+    else fin_setup_gamma(st, a.hist, g[0]);
+  }
+  publish(a, st);
 }
 
 // ===========================================================================
@@ -733,70 +776,52 @@ __global__ void k_init_state(DevState* st, double tol) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->alpha = 0.0; st->beta = 0.0; st->omega = 0.0; st->gamma = 0.0;
     st->rho0 = 0.0; st->relres = 1.0; st->tol = tol; st->result = 0.0;
-    st->status = DS_RUNNING; st->iters = 0; st->yzero = 0; st->n_rr = 0;
-    st->counter = 0; st->errflag = 0;
+    st->status = DS_RUNNING; st->iters = 0; st->n_rr = 0;
+    for (int k = 0; k < 5; ++k) st->pad[k] = 0;
   }
 }
 
 template <class Op>
 __global__ __launch_bounds__(kWG) void k_spmv(Op op, Args a, const double* __restrict__ xin,
                                               double* __restrict__ yout) {
-  row_loop(a, [&](int32_t row) { yout[row] = op.apply(row, xin); });
+  each_row(a, [&](int32_t row) { yout[row] = op.apply(row, xin); });
 }
 
-// result = (x, y) in pairwise order.
+// partials of (x, y).
 __global__ __launch_bounds__(kWG) void k_dot(Args a, const double* __restrict__ xv,
                                              const double* __restrict__ yv) {
-  __shared__ TileRed<1> sm;
-  DevState* st = a.st;
-  tile_loop<1>(sm, a, [&](int32_t row, double (&d)[1]) { d[0] = xv[row] * yv[row]; });
-  if (!elect_last(st, a.G)) return;
-  double g[1];
-  final_reduce<1>(a.part, a.G, g);
-  if (threadIdx.x == 0) {
-    st->result = g[0];
-    st->counter = 0;
-  }
+  produce<1>(a, [&](int32_t row, double (&d)[1]) { d[0] = xv[row] * yv[row]; });
 }
 
-// result = ||b - A x||^2 in pairwise order (true residual of the returned x).
+// partials of ||b - A x||^2 (true residual of the returned x).
 template <class Op>
 __global__ __launch_bounds__(kWG) void k_true_res(Op op, Args a) {
-  __shared__ TileRed<1> sm;
-  DevState* st = a.st;
-  tile_loop<1>(sm, a, [&](int32_t row, double (&d)[1]) {
+  produce<1>(a, [&](int32_t row, double (&d)[1]) {
     const double r = a.b[row] - op.apply(row, a.x);
     d[0] = r * r;
   });
-  if (!elect_last(st, a.G)) return;
-  double g[1];
-  final_reduce<1>(a.part, a.G, g);
-  if (threadIdx.x == 0) {
-    st->result = g[0];
-    st->counter = 0;
-  }
 }
 
-// dinv_i = 1 / a_ii ; errflag if a diagonal entry is zero, non-finite or absent.
-__global__ __launch_bounds__(kWG) void k_dinv_csr(CsrOp op, int32_t n, double* dinv, DevState* st) {
+// dinv_i = 1 / a_ii ; flag bit 0 if a diagonal entry is zero, non-finite or absent.
+__global__ __launch_bounds__(kWG) void k_dinv_csr(CsrOp op, int32_t n, double* dinv, int32_t* flag) {
   const int32_t row = blockIdx.x * kWG + threadIdx.x;
   if (row >= n) return;
   double d = 0.0;
   for (int32_t k = op.rp[row]; k < op.rp[row + 1]; ++k)
     if (op.ci[k] == row) d = op.va[k];
-  if (d == 0.0 || !finite(d)) atomicOr(&st->errflag, 1);
+  if (d == 0.0 || !finite(d)) atomicOr(flag, 1);
   dinv[row] = 1.0 / d;
 }
 
-// errflag bit 1 unless every dinv_i equals dinv_0 (then Jacobi is one scalar).
-__global__ __launch_bounds__(kWG) void k_dinv_const(int32_t n, const double* dinv, DevState* st) {
+// flag bit 1 unless every dinv_i equals dinv_0 (then Jacobi is one scalar).
+__global__ __launch_bounds__(kWG) void k_dinv_const(int32_t n, const double* dinv, int32_t* flag) {
   const int32_t row = blockIdx.x * kWG + threadIdx.x;
   if (row >= n) return;
-  if (!(dinv[row] == dinv[0]) || !finite(dinv[row]) || dinv[row] == 0.0) atomicOr(&st->errflag, 2);
+  if (!(dinv[row] == dinv[0]) || !finite(dinv[row]) || dinv[row] == 0.0) atomicOr(flag, 2);
 }
 
-// CSR structure check: errflag bit 0 on a malformed row pointer or column.
-__global__ __launch_bounds__(kWG) void k_csr_check(CsrOp op, int32_t n, int64_t nnz, DevState* st) {
+// CSR structure check: flag bit 0 on a malformed row pointer or column.
+__global__ __launch_bounds__(kWG) void k_csr_check(CsrOp op, int32_t n, int64_t nnz, int32_t* flag) {
   const int32_t row = blockIdx.x * kWG + threadIdx.x;
   if (row >= n) return;
   const int32_t b = op.rp[row], e = op.rp[row + 1];
@@ -809,7 +834,7 @@ __global__ __launch_bounds__(kWG) void k_csr_check(CsrOp op, int32_t n, int64_t 
       if (c < 0 || c >= n) { bad = true; break; }
     }
   }
-  if (bad) atomicOr(&st->errflag, 1);
+  if (bad) atomicOr(flag, 1);
 }
 
 }  // namespace pbcgs

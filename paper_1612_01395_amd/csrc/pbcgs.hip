@@ -3,6 +3,7 @@
 // the C ABI declared in include/pbcgs.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -23,14 +24,20 @@ thread_local std::string g_last_error;
 
 enum OpKind { OP_CSR = 0, OP_ST5 = 1, OP_ST7 = 2 };
 
+// Partial-sum buffers, one per producing kernel role.
+enum PartBuf { PB_SETUP1 = 0, PB_SETUP2, PB_A, PB_B, PB_B1, PB_B3, PB_B4, PB_UTIL, PB_COUNT };
+
 }  // namespace
 
 struct pbcgs_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
-  DevState* st = nullptr;   // device scalars and status
-  DevState* hst = nullptr;  // pinned host copies, two poll slots
-  double* part = nullptr;   // [kMaxD][kMaxG]
+  bool own_stream = false;
+  DevState* st = nullptr;   // two state slots (device)
+  DevState* hst = nullptr;  // pinned host copies for polling (two slots)
+  int32_t* flag = nullptr;  // structural error flags of utility kernels
+  int32_t* hflag = nullptr; // pinned host copy
+  double* part = nullptr;   // PB_COUNT buffers of kMaxD * kMaxG partial sums
   double* ws = nullptr;     // solver vectors
   size_t ws_cap = 0;        // doubles
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
@@ -38,8 +45,6 @@ struct pbcgs_ctx_s {
   std::vector<hipEvent_t> kev;  // pool for per-kernel timing
   std::map<std::string, hipGraphExec_t> graphs;
   std::string err;
-  int ops = 0;
-  bool own_stream = false;
 };
 
 struct pbcgs_op_s {
@@ -82,44 +87,48 @@ struct DeviceGuard {
       return fail((ctx), PBCGS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Launch shape: tiles of 256 rows, tpw (power of two) tiles per workgroup so
-// that the grid has at most `gtarget` workgroups.
-struct Shape {
-  int32_t n, ntiles, tpw, G;
-};
-
-int gtarget_default() {
-  const char* e = std::getenv("PBCGS_GTARGET");
-  if (e) {
-    int v = std::atoi(e);
-    if (v >= 1 && v <= kMaxG) return v;
-  }
-  return 1024;
+int env_int(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : dflt;
 }
+
+// Launch shape: a wave handles R blocks of 64 rows (R a power of two), a
+// workgroup 4 R blocks; R is the smallest power of two with at most `gtarget`
+// workgroups (default 512: two workgroups per CU, each streaming 16 rows per
+// thread for the 128^3 workload).
+struct Shape {
+  int32_t n, R, G;
+};
 
 bool make_shape(int32_t n, Shape* sh) {
   if (n <= 0) return false;
-  const int32_t ntiles = (n + kTile - 1) / kTile;
-  const int gt = gtarget_default();
-  int tpw = 1;
-  while ((ntiles + tpw - 1) / tpw > gt && tpw < kMaxTpw) tpw *= 2;
-  const int32_t G = (ntiles + tpw - 1) / tpw;
-  if (G > kMaxG) return false;
-  *sh = {n, ntiles, tpw, G};
-  return true;
+  int gt = env_int("PBCGS_GTARGET", 512);
+  if (gt < 1 || gt > kMaxG) gt = 512;
+  const int forced = env_int("PBCGS_R", 0);
+  for (int R = 1; R <= kMaxR; R *= 2) {
+    const int64_t G = ((int64_t)n + 256 * (int64_t)R - 1) / (256 * (int64_t)R);
+    if (forced > 0 && R != forced) continue;
+    if (G <= gt || (R == kMaxR && G <= kMaxG) || (forced > 0 && G <= kMaxG)) {
+      *sh = {n, R, (int32_t)G};
+      return true;
+    }
+  }
+  return false;
 }
 
 Args base_args(pbcgs_ctx_t ctx, const Shape& sh) {
   Args a;
   std::memset(&a, 0, sizeof a);
   a.n = sh.n;
-  a.ntiles = sh.ntiles;
-  a.tpw = sh.tpw;
   a.G = sh.G;
-  a.st = ctx->st;
-  a.part = ctx->part;
+  a.R = sh.R;
+  a.Gin = sh.G;
+  a.sin = ctx->st;
+  a.sout = ctx->st + 1;
   return a;
 }
+
+double* part_buf(pbcgs_ctx_t ctx, int which) { return ctx->part + (size_t)which * kMaxD * kMaxG; }
 
 int ensure_ws(pbcgs_ctx_t ctx, size_t doubles) {
   if (ctx->ws_cap >= doubles) return PBCGS_SUCCESS;
@@ -141,28 +150,58 @@ int ensure_ws(pbcgs_ctx_t ctx, size_t doubles) {
 
 size_t padded(int32_t n) { return ((size_t)n + 63) / 64 * 64; }
 
-int read_state(pbcgs_ctx_t ctx, DevState* out) {
-  HIP_TRY(ctx, hipMemcpyAsync(out, ctx->st, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
+int read_state(pbcgs_ctx_t ctx, int slot, DevState* out) {
+  HIP_TRY(ctx, hipMemcpyAsync(out, ctx->st + slot, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return PBCGS_SUCCESS;
 }
 
-int map_status(int32_t ds, bool running_is_maxit) {
+int reset_flag(pbcgs_ctx_t ctx) {
+  HIP_TRY(ctx, hipMemsetAsync(ctx->flag, 0, sizeof(int32_t), ctx->stream));
+  return PBCGS_SUCCESS;
+}
+
+int read_flag(pbcgs_ctx_t ctx, int32_t* out) {
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->hflag, ctx->flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  *out = *ctx->hflag;
+  return PBCGS_SUCCESS;
+}
+
+int map_status(int32_t ds) {
   switch (ds) {
     case DS_SUCCESS: return PBCGS_SUCCESS;
     case DS_BREAKDOWN: return PBCGS_BREAKDOWN;
     case DS_NONFINITE: return PBCGS_NONFINITE;
-    default: return running_is_maxit ? PBCGS_MAXIT : PBCGS_SUCCESS;
+    default: return PBCGS_MAXIT;
   }
 }
 
 // Residual replacement schedule (Section 4.2): iteration i replaces r, r^, w
 // when (i+1) mod k == 0 and fewer than rr_max replacements came before.
 bool rr_due(const pbcgs_opts& o, int64_t i) {
-  if (o.variant != PBCGS_PBICGSTAB_RR || o.rr_period <= 0) return false;
+  if (o.variant != PBCGS_PBICGSTAB_RR || o.rr_period <= 0 || i < 0) return false;
   if ((i + 1) % o.rr_period != 0) return false;
   const int64_t before = (i + 1) / o.rr_period - 1;
   return o.rr_max < 0 || before < o.rr_max;
+}
+
+// Total of a utility reduction (k_dot / k_true_res partials), via state slot 1.
+int finish_sum(pbcgs_ctx_t ctx, const Shape& sh, double* result) {
+  Args f = base_args(ctx, sh);
+  f.pin = part_buf(ctx, PB_UTIL);
+  f.Gin = sh.G;
+  f.sin = ctx->st;
+  f.sout = ctx->st + 1;
+  k_init_state<<<1, 64, 0, ctx->stream>>>(ctx->st, 0.0);
+  k_finish<3><<<1, kWG, 0, ctx->stream>>>(f);
+  HIP_TRY(ctx, hipGetLastError());
+  DevState h;
+  int rc = read_state(ctx, 1, &h);
+  if (rc != PBCGS_SUCCESS) return rc;
+  *result = h.result;
+  return PBCGS_SUCCESS;
 }
 
 // ---------------------------------------------------------------------------
@@ -175,6 +214,7 @@ struct Driver {
   Args a;
   const pbcgs_opts& o;
   bool timing = false;
+  int64_t q = 0;  // kernel launches of this solve that passed the state on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[2];
   size_t ev_used = 0;
 
@@ -201,15 +241,28 @@ struct Driver {
     }
   }
 
+  // Arguments of the next launch: state slots by launch parity, partials.
+  Args L(int pin, int pout, bool first = false) {
+    Args b = a;
+    b.sin = ctx->st + (q & 1);
+    b.sout = ctx->st + ((q + 1) & 1);
+    b.pin = pin >= 0 ? part_buf(ctx, pin) : nullptr;
+    b.pout = pout >= 0 ? part_buf(ctx, pout) : nullptr;
+    b.Gin = a.G;
+    b.first = first ? 1 : 0;
+    ++q;
+    return b;
+  }
+
   dim3 grid() const { return dim3((unsigned)a.G); }
 
   void setup() {
     hipStream_t s = ctx->stream;
     if (o.variant == PBCGS_BICGSTAB) {
-      k_setup_r0<Op, PC, false><<<grid(), kWG, 0, s>>>(op, a);
+      k_setup_r0<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
     } else {
-      k_setup_r0<Op, PC, true><<<grid(), kWG, 0, s>>>(op, a);
-      k_setup_w0<Op, PC><<<grid(), kWG, 0, s>>>(op, a);
+      k_setup_r0<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
+      k_setup_w0<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_SETUP1, PB_SETUP2));
     }
   }
 
@@ -217,43 +270,61 @@ struct Driver {
   void iteration(int64_t i) {
     hipStream_t s = ctx->stream;
     if (o.variant == PBCGS_BICGSTAB) {
-      timed(0, [&] { k_b1<Op, PC><<<grid(), kWG, 0, s>>>(op, a); });
-      k_b2<PC><<<grid(), kWG, 0, s>>>(a);
-      timed(1, [&] { k_b3<Op, PC><<<grid(), kWG, 0, s>>>(op, a); });
-      k_b4<PC><<<grid(), kWG, 0, s>>>(a);
-      k_b5<PC><<<grid(), kWG, 0, s>>>(a);
+      timed(0, [&] { k_b1<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_SETUP1, PB_B1, i == 0)); });
+      k_b2<PC><<<grid(), kWG, 0, s>>>(L(PB_B1, -1));
+      timed(1, [&] { k_b3<Op, PC><<<grid(), kWG, 0, s>>>(op, L(-1, PB_B3)); });
+      k_b4<PC><<<grid(), kWG, 0, s>>>(L(PB_B3, PB_B4));
+      k_b5<PC><<<grid(), kWG, 0, s>>>(L(PB_B4, -1));
       return;
     }
-    const bool pending = (i > 0) && rr_due(o, i - 1);
+    const bool pending = rr_due(o, i - 1);
     const bool rr = rr_due(o, i);
     if (pending) {
-      k_rr_p<PC><<<grid(), kWG, 0, s>>>(a);
-      k_rr_s<Op, PC><<<grid(), kWG, 0, s>>>(op, a);
-      k_pa<Op, PC, true><<<grid(), kWG, 0, s>>>(op, a);
+      k_rr_p<PC><<<grid(), kWG, 0, s>>>(L(PB_B, -1));
+      k_rr_s<Op, PC><<<grid(), kWG, 0, s>>>(op, L(-1, -1));
+      k_pa<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_A));
     } else {
-      timed(0, [&] { k_pa<Op, PC, false><<<grid(), kWG, 0, s>>>(op, a); });
+      timed(0, [&] { k_pa<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0)); });
     }
     if (rr) {
-      k_rr_x<PC><<<grid(), kWG, 0, s>>>(a);
-      k_rr_r<Op, PC><<<grid(), kWG, 0, s>>>(op, a);
-      k_rr_w<Op, PC><<<grid(), kWG, 0, s>>>(op, a);
+      k_rr_x<PC><<<grid(), kWG, 0, s>>>(L(PB_A, -1));
+      k_rr_r<Op, PC><<<grid(), kWG, 0, s>>>(op, L(-1, -1));
+      k_rr_w<Op, PC><<<grid(), kWG, 0, s>>>(op, L(-1, PB_B));
     } else {
-      timed(1, [&] { k_pb<Op, PC><<<grid(), kWG, 0, s>>>(op, a); });
+      timed(1, [&] { k_pb<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B)); });
     }
+  }
+
+  // Launch count of iteration i (the schedule of iteration()).
+  void count_iteration(int64_t i) {
+    if (o.variant == PBCGS_BICGSTAB) {
+      q += 5;
+      return;
+    }
+    q += (rr_due(o, i - 1) ? 3 : 1) + (rr_due(o, i) ? 3 : 1);
+  }
+
+  // The reduction left pending by the last kernel, finished by one workgroup.
+  void finish(int64_t iters_launched) {
+    hipStream_t s = ctx->stream;
+    if (o.variant == PBCGS_BICGSTAB) {
+      if (iters_launched == 0) k_finish<2><<<1, kWG, 0, s>>>(L(PB_SETUP1, -1));
+      return;
+    }
+    if (iters_launched == 0) k_finish<1><<<1, kWG, 0, s>>>(L(PB_SETUP2, -1));
+    else k_finish<0><<<1, kWG, 0, s>>>(L(PB_B, -1));
   }
 
   std::string graph_key(int64_t i0, int m) const {
     std::string k;
-    char buf[64];
-    const unsigned char* p = reinterpret_cast<const unsigned char*>(&a);
-    k.reserve(sizeof(Args) + sizeof(Op) + 96);
-    k.append(reinterpret_cast<const char*>(p), sizeof(Args));
+    char buf[96];
+    k.append(reinterpret_cast<const char*>(&a), sizeof(Args));
     k.append(reinterpret_cast<const char*>(&op), sizeof(Op));
-    std::snprintf(buf, sizeof buf, "|%d|%d|%d|", PC, o.variant, m);
+    std::snprintf(buf, sizeof buf, "|%d|%d|%d|%lld|%d|", PC, o.variant, m, (long long)(q & 1), i0 == 0 ? 1 : 0);
     k += buf;
     for (int j = 0; j < m; ++j) {
       const int64_t i = i0 + j;
-      const int code = ((i > 0 && rr_due(o, i - 1)) ? 1 : 0) | (rr_due(o, i) ? 2 : 0);
+      const int code = (rr_due(o, i - 1) ? 1 : 0) | (rr_due(o, i) ? 2 : 0);
       k += char('0' + code);
     }
     return k;
@@ -266,6 +337,7 @@ struct Driver {
       return PBCGS_SUCCESS;
     }
     const std::string key = graph_key(i0, m);
+    const int64_t q0 = q;
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
       if (ctx->graphs.size() >= 32) {
@@ -283,6 +355,10 @@ struct Driver {
       (void)hipGraphDestroy(g);
       if (ie != hipSuccess) return fail(ctx, PBCGS_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
       it = ctx->graphs.emplace(key, ex).first;
+    } else {
+      // replaying: advance the launch counter as the captured launches did
+      q = q0;
+      for (int j = 0; j < m; ++j) count_iteration(i0 + j);
     }
     HIP_TRY(ctx, hipGraphLaunch(it->second, ctx->stream));
     return PBCGS_SUCCESS;
@@ -291,15 +367,16 @@ struct Driver {
   int run(pbcgs_info* info) {
     const bool use_graph = !(o.flags & 1) && !(o.flags & 2);
     timing = (o.flags & 2) != 0;
-    int check = o.check_every > 0 ? o.check_every : (a.n >= (1 << 20) ? 8 : 32);
+    const int check = o.check_every > 0 ? o.check_every : (a.n >= (1 << 20) ? 8 : 32);
     hipStream_t s = ctx->stream;
     HIP_TRY(ctx, hipEventRecord(ctx->ev_start, s));
-    k_init_state<<<1, 64, 0, s>>>(a.st, o.tol);
+    k_init_state<<<1, 64, 0, s>>>(ctx->st, o.tol);
+    q = 0;
     setup();
     HIP_TRY(ctx, hipGetLastError());
     // Chunks of `check` iterations; the status after chunk c is polled while
     // chunk c+1 is already queued, so the device does not wait for the host.
-    // Kernels queued after convergence see the final status and exit at once.
+    // Kernels queued after the stop see the final status and exit at once.
     int64_t launched = 0;
     int pend[2];
     int npend = 0, next_slot = 0;
@@ -310,7 +387,8 @@ struct Driver {
         int rc = chunk(launched, m, use_graph);
         if (rc != PBCGS_SUCCESS) return rc;
         launched += m;
-        HIP_TRY(ctx, hipMemcpyAsync(&ctx->hst[next_slot], ctx->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipMemcpyAsync(&ctx->hst[next_slot], ctx->st + (q & 1), sizeof(DevState),
+                                    hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipEventRecord(ctx->ev_poll[next_slot], s));
         pend[npend++] = next_slot;
         next_slot ^= 1;
@@ -322,25 +400,29 @@ struct Driver {
       HIP_TRY(ctx, hipEventSynchronize(ctx->ev_poll[slot]));
       if (ctx->hst[slot].status != DS_RUNNING) stop = true;
     }
+    finish(launched);
+    HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipEventRecord(ctx->ev_stop, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
     DevState fin;
-    int rc = read_state(ctx, &fin);
+    int rc = read_state(ctx, (int)(q & 1), &fin);
     if (rc != PBCGS_SUCCESS) return rc;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop);
     // true residual of the returned x, same pairwise arithmetic
-    k_true_res<Op><<<grid(), kWG, 0, s>>>(op, a);
+    Args t = a;
+    t.pout = part_buf(ctx, PB_UTIL);
+    k_true_res<Op><<<grid(), kWG, 0, s>>>(op, t);
     HIP_TRY(ctx, hipGetLastError());
-    DevState tr;
-    rc = read_state(ctx, &tr);
+    const Shape sh = {a.n, a.R, a.G};
+    double nr = 0.0;
+    rc = finish_sum(ctx, sh, &nr);
     if (rc != PBCGS_SUCCESS) return rc;
     info->iters = fin.iters;
     info->n_rr = fin.n_rr;
-    info->status = map_status(fin.status, true);
+    info->status = map_status(fin.status);
     info->syncs_per_iter = (o.variant == PBCGS_BICGSTAB) ? 5 : 2;
     info->relres_rec = fin.relres;
-    info->relres_true = (fin.rho0 > 0.0) ? std::sqrt(tr.result) / fin.rho0 : 0.0;
+    info->relres_true = (fin.rho0 > 0.0) ? std::sqrt(nr) / fin.rho0 : 0.0;
     info->ms = ms;
     for (int k = 0; k < 2; ++k) {
       double tot = 0.0;
@@ -355,15 +437,7 @@ struct Driver {
   }
 };
 
-int check_flag(pbcgs_ctx_t ctx, int32_t* flag) {
-  DevState h;
-  int rc = read_state(ctx, &h);
-  if (rc != PBCGS_SUCCESS) return rc;
-  *flag = h.errflag;
-  return PBCGS_SUCCESS;
-}
-
-template <int PC, class F>
+template <class F>
 int with_op(pbcgs_op_t A, F f) {
   if (A->kind == OP_CSR) return f(CsrOp{A->rp, A->ci, A->va});
   if (A->kind == OP_ST7) {
@@ -429,9 +503,11 @@ int pbcgs_ctx_create(int device, void* hip_stream, pbcgs_ctx_t* out) {
     }
     c->own_stream = true;
   }
-  bool ok = hipMalloc(&c->st, sizeof(DevState)) == hipSuccess &&
-            hipMalloc(&c->part, sizeof(double) * kMaxD * kMaxG) == hipSuccess &&
+  bool ok = hipMalloc(&c->st, 2 * sizeof(DevState)) == hipSuccess &&
+            hipMalloc(&c->part, sizeof(double) * kMaxD * kMaxG * PB_COUNT) == hipSuccess &&
+            hipMalloc(&c->flag, 64) == hipSuccess &&
             hipHostMalloc(&c->hst, 2 * sizeof(DevState), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(&c->hflag, 64, hipHostMallocDefault) == hipSuccess &&
             hipEventCreate(&c->ev_start) == hipSuccess && hipEventCreate(&c->ev_stop) == hipSuccess &&
             hipEventCreateWithFlags(&c->ev_poll[0], hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) == hipSuccess;
@@ -440,6 +516,7 @@ int pbcgs_ctx_create(int device, void* hip_stream, pbcgs_ctx_t* out) {
     return fail(nullptr, PBCGS_ERR_ALLOC, "context allocation failed");
   }
   k_init_state<<<1, 64, 0, c->stream>>>(c->st, 0.0);
+  k_init_state<<<1, 64, 0, c->stream>>>(c->st + 1, 0.0);
   if (hipStreamSynchronize(c->stream) != hipSuccess) {
     pbcgs_ctx_destroy(c);
     return fail(nullptr, PBCGS_ERR_HIP, "context initialisation failed");
@@ -452,16 +529,18 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
   if (!ctx) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "ctx is NULL");
   DeviceGuard guard(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  else (void)hipDeviceSynchronize();
   for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
   for (auto e : ctx->kev) (void)hipEventDestroy(e);
   if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
   if (ctx->ev_stop) (void)hipEventDestroy(ctx->ev_stop);
-  for (auto e : ctx->ev_poll) if (e) (void)hipEventDestroy(e);
+  for (auto e : ctx->ev_poll)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->part) (void)hipFree(ctx->part);
+  if (ctx->flag) (void)hipFree(ctx->flag);
   if (ctx->st) (void)hipFree(ctx->st);
   if (ctx->hst) (void)hipHostFree(ctx->hst);
+  if (ctx->hflag) (void)hipHostFree(ctx->hflag);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return PBCGS_SUCCESS;
@@ -476,11 +555,11 @@ int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr
   if (!make_shape(n, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows for one launch");
   DeviceGuard guard(ctx->device);
   CsrOp op{row_ptr, col_idx, val};
-  k_init_state<<<1, 64, 0, ctx->stream>>>(ctx->st, 0.0);
-  k_csr_check<<<(n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(op, n, nnz, ctx->st);
-  HIP_TRY(ctx, hipGetLastError());
+  int rc = reset_flag(ctx);
+  if (rc != PBCGS_SUCCESS) return rc;
+  k_csr_check<<<(n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(op, n, nnz, ctx->flag);
   int32_t flag = 0;
-  int rc = check_flag(ctx, &flag);
+  rc = read_flag(ctx, &flag);
   if (rc != PBCGS_SUCCESS) return rc;
   if (flag) return fail(ctx, PBCGS_ERR_INVALID_ARG, "malformed CSR structure (row_ptr or col_idx)");
   pbcgs_op_t A = new pbcgs_op_s();
@@ -491,7 +570,6 @@ int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr
   A->rp = row_ptr;
   A->ci = col_idx;
   A->va = val;
-  ctx->ops++;
   *out = A;
   return PBCGS_SUCCESS;
 }
@@ -514,13 +592,8 @@ int pbcgs_op_stencil(pbcgs_ctx_t ctx, int32_t nx, int32_t ny, int32_t nz, int32_
   A->ny = ny;
   A->nz = nz;
   for (int k = 0; k < npts; ++k) A->coef[k] = coef[k];
-  int64_t nnz = 0;  // stored entries of the equivalent CSR matrix
-  {
-    const int64_t X = nx, Y = ny, Z = nz;
-    nnz = X * Y * Z + 2 * ((X - 1) * Y * Z + X * (Y - 1) * Z) + (npts == 7 ? 2 * X * Y * (Z - 1) : 0);
-  }
-  A->nnz = nnz;
-  ctx->ops++;
+  const int64_t X = nx, Y = ny, Z = nz;  // stored entries of the equivalent CSR matrix
+  A->nnz = X * Y * Z + 2 * ((X - 1) * Y * Z + X * (Y - 1) * Z) + (npts == 7 ? 2 * X * Y * (Z - 1) : 0);
   *out = A;
   return PBCGS_SUCCESS;
 }
@@ -534,7 +607,6 @@ int pbcgs_op_destroy(pbcgs_op_t op) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
     ctx->graphs.clear();
-    ctx->ops--;
   }
   delete op;
   return PBCGS_SUCCESS;
@@ -551,9 +623,9 @@ int pbcgs_spmv(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* x, double* y) {
   if ((const void*)x == (const void*)y) return fail(ctx, PBCGS_ERR_INVALID_ARG, "x and y must not overlap");
   DeviceGuard guard(ctx->device);
   Shape sh;
-  make_shape(A->n, &sh);
+  if (!make_shape(A->n, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows");
   Args a = base_args(ctx, sh);
-  return with_op<0>(A, [&](auto op) -> int {
+  return with_op(A, [&](auto op) -> int {
     k_spmv<decltype(op)><<<sh.G, kWG, 0, ctx->stream>>>(op, a, x, y);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -568,14 +640,10 @@ int pbcgs_dot(pbcgs_ctx_t ctx, int64_t n, const double* x, const double* y, doub
   Shape sh;
   if (!make_shape((int32_t)n, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "vector too long");
   Args a = base_args(ctx, sh);
-  k_init_state<<<1, 64, 0, ctx->stream>>>(ctx->st, 0.0);
+  a.pout = part_buf(ctx, PB_UTIL);
   k_dot<<<sh.G, kWG, 0, ctx->stream>>>(a, x, y);
   HIP_TRY(ctx, hipGetLastError());
-  DevState h;
-  int rc = read_state(ctx, &h);
-  if (rc != PBCGS_SUCCESS) return rc;
-  *result = h.result;
-  return PBCGS_SUCCESS;
+  return finish_sum(ctx, sh, result);
 }
 
 int pbcgs_jacobi_dinv(pbcgs_ctx_t ctx, pbcgs_op_t A, double* dinv) {
@@ -590,11 +658,11 @@ int pbcgs_jacobi_dinv(pbcgs_ctx_t ctx, pbcgs_op_t A, double* dinv) {
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return PBCGS_SUCCESS;
   }
-  k_init_state<<<1, 64, 0, ctx->stream>>>(ctx->st, 0.0);
-  k_dinv_csr<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(CsrOp{A->rp, A->ci, A->va}, A->n, dinv, ctx->st);
-  HIP_TRY(ctx, hipGetLastError());
+  int rc = reset_flag(ctx);
+  if (rc != PBCGS_SUCCESS) return rc;
+  k_dinv_csr<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(CsrOp{A->rp, A->ci, A->va}, A->n, dinv, ctx->flag);
   int32_t flag = 0;
-  int rc = check_flag(ctx, &flag);
+  rc = read_flag(ctx, &flag);
   if (rc != PBCGS_SUCCESS) return rc;
   if (flag & 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero, non-finite or missing diagonal entry");
   return PBCGS_SUCCESS;
@@ -629,37 +697,35 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
   double* v[nvec];
   for (int k = 0; k < nvec; ++k) v[k] = ctx->ws + (size_t)k * np;
 
-  // preconditioner mode
+  // preconditioner mode: none, a vector of 1/a_ii, or one constant
   int pc = PC_NONE;
   if (o.precond == PBCGS_PRECOND_JACOBI) {
     const double* dv = dinv;
     if (!dv && A->kind != OP_CSR) {
-      // constant-coefficient stencil: M^{-1} is one scalar, 1 / centre
       const double c = (A->kind == OP_ST7) ? A->coef[3] : A->coef[2];
       if (c == 0.0 || !std::isfinite(c)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero diagonal");
       pc = PC_SCALAR;
       a.dinv_s = 1.0 / c;
-    } else if (!dv) {
-      rc = pbcgs_jacobi_dinv(ctx, A, v[13]);
-      if (rc != PBCGS_SUCCESS) return rc;
-      dv = v[13];
-    }
-  }
-  if (o.precond == PBCGS_PRECOND_JACOBI && pc == PC_NONE) {
-    const double* dv = dinv ? dinv : v[13];
-    k_init_state<<<1, 64, 0, ctx->stream>>>(ctx->st, 0.0);
-    k_dinv_const<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(A->n, dv, ctx->st);
-    HIP_TRY(ctx, hipGetLastError());
-    int32_t flag = 0;
-    rc = check_flag(ctx, &flag);
-    if (rc != PBCGS_SUCCESS) return rc;
-    if (flag & 2) {
-      pc = PC_VEC;
-      a.dinv = dv;
     } else {
-      pc = PC_SCALAR;
-      HIP_TRY(ctx, hipMemcpyAsync(&a.dinv_s, dv, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      if (!dv) {
+        rc = pbcgs_jacobi_dinv(ctx, A, v[13]);
+        if (rc != PBCGS_SUCCESS) return rc;
+        dv = v[13];
+      }
+      rc = reset_flag(ctx);
+      if (rc != PBCGS_SUCCESS) return rc;
+      k_dinv_const<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(A->n, dv, ctx->flag);
+      int32_t flag = 0;
+      rc = read_flag(ctx, &flag);
+      if (rc != PBCGS_SUCCESS) return rc;
+      if (flag & 2) {
+        pc = PC_VEC;
+        a.dinv = dv;
+      } else {
+        pc = PC_SCALAR;
+        HIP_TRY(ctx, hipMemcpyAsync(&a.dinv_s, dv, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      }
     }
   }
   const bool hat = (pc != PC_NONE);
@@ -675,7 +741,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     a.zh = hat ? v[11] : a.z;
   }
 
-  return with_op<0>(A, [&](auto op) -> int {
+  return with_op(A, [&](auto op) -> int {
     using Op = decltype(op);
     if (pc == PC_NONE) return Driver<Op, PC_NONE>(ctx, op, a, o).run(info);
     if (pc == PC_VEC) return Driver<Op, PC_VEC>(ctx, op, a, o).run(info);

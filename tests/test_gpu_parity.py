@@ -59,7 +59,7 @@ def test_dot_bitwise_and_shape_independent(n):
     xd, yd = dev_t(x), dev_t(y)
     old = os.environ.get("PBCGS_GTARGET")
     try:
-        for g in ("1024", "7", "64", "4096"):
+        for g in ("512", "7", "64", "1024", "1"):
             os.environ["PBCGS_GTARGET"] = g
             assert same(solver.dot(xd, yd), ref), g
     finally:
@@ -155,18 +155,26 @@ def test_launch_modes_and_shapes_identical():
         say(f"mode {kw}")
         x, info = solver.solve(op, b, variant="pbicgstab_rr", precond="jacobi", tol=1e-10, rr_period=7, **kw)
         assert same(host(x), ref) and info.iters == info_ref.iters, kw
-    old = os.environ.get("PBCGS_GTARGET")
+    saved = {k: os.environ.get(k) for k in ("PBCGS_GTARGET", "PBCGS_R")}
     try:
-        for g in ("3", "16", "4096"):
-            os.environ["PBCGS_GTARGET"] = g
-            say(f"gtarget {g}")
+        for var, val in (("PBCGS_GTARGET", "3"), ("PBCGS_GTARGET", "16"), ("PBCGS_GTARGET", "1024"),
+                         ("PBCGS_R", "1"), ("PBCGS_R", "2"), ("PBCGS_R", "8"), ("PBCGS_R", "64")):
+            for k in saved:
+                os.environ.pop(k, None)
+            os.environ[var] = val
+            say(f"{var}={val}")
             x, info = solver.solve(op, b, variant="pbicgstab_rr", precond="jacobi", tol=1e-10, rr_period=7)
-            assert same(host(x), ref) and info.iters == info_ref.iters, g
+            assert same(host(x), ref) and info.iters == info_ref.iters, (var, val)
+            for variant in ("bicgstab", "pbicgstab"):
+                x2, i2 = solver.solve(op, b, variant=variant, precond="jacobi", tol=1e-10)
+                x3, i3 = solver.solve(op, b, variant=variant, precond="jacobi", tol=1e-10, graph=False)
+                assert same(host(x2), host(x3)) and i2.iters == i3.iters
     finally:
-        if old is None:
-            os.environ.pop("PBCGS_GTARGET", None)
-        else:
-            os.environ["PBCGS_GTARGET"] = old
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
 
 
 def test_rr_max_and_maxit_and_x0():
