@@ -69,27 +69,54 @@ struct CsrOp {
   const int32_t* __restrict__ rp;
   const int32_t* __restrict__ ci;
   const double* __restrict__ va;
-  // Entries are fetched 8 at a time with the index clamped into the row, so
-  // all loads of a short row are in flight together; only the entries that
-  // exist are added, in stored order.
-  __device__ __forceinline__ double apply(int32_t row, const double* __restrict__ x) const {
-    const int32_t b = rp[row], e = rp[row + 1];
+  int32_t n;
+
+  static constexpr int kStage = 512;  // staged non-zeros per wave and round
+
+  // Row `row` of A x, computed by the whole wave for its 64-row block (all 64
+  // lanes call it; lanes with valid == false return 0).  The block's
+  // non-zeros are contiguous in CSR, so the wave loads them with coalesced
+  // loads, multiplies by the gathered x and stages the products in LDS
+  // (CSR-stream); each lane then adds its own row's products in stored order,
+  // starting from 0.0 -- the same operations as a row-by-row loop.
+  __device__ __forceinline__ double spmv(int32_t row, bool valid, const double* __restrict__ x) const {
+    __shared__ double stage[4][kStage];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t b0 = __builtin_amdgcn_readfirstlane(row);  // lane 0: first row of the block
+    const int32_t rc = min(row, n - 1);  // clamped: the four loads issue together
+    const int32_t rlo = rp[b0];
+    const int32_t rhi = rp[min(b0 + 64, n)];
+    const int32_t rb0 = rp[rc], re0 = rp[rc + 1];
+    const int32_t rb = valid ? rb0 : rhi;
+    const int32_t re = valid ? re0 : rhi;
     double acc = 0.0;
-    for (int32_t k0 = b; k0 < e; k0 += 8) {
-      int32_t c[8];
-      double v[8], xv[8];
+    for (int32_t c0 = rlo; c0 < rhi; c0 += kStage) {
+      const int32_t c1 = min(c0 + kStage, rhi);
+      // branch-free: indices past the chunk are clamped into it (their
+      // products land in slots that are never read), so all loads issue at once
+      int32_t cc[kStage / 64];
+      double vv[kStage / 64];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int32_t k = min(k0 + j, e - 1);
-        c[j] = ci[k];
-        v[j] = va[k];
+      for (int u = 0; u < kStage / 64; ++u) {
+        const int32_t k = min(c0 + u * 64 + lane, c1 - 1);
+        cc[u] = ci[k];
+        vv[u] = va[k];
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) xv[j] = x[c[j]];
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (k0 + j < e) acc = acc + v[j] * xv[j];
+      for (int u = 0; u < kStage / 64; ++u) stage[wave][u * 64 + lane] = vv[u] * x[cc[u]];
+      __builtin_amdgcn_wave_barrier();
+      const int32_t kb = max(rb, c0), ke = min(re, c1);
+      for (int32_t k = kb; k < ke; ++k) acc = acc + stage[wave][k - c0];
+      __builtin_amdgcn_wave_barrier();
     }
+    return acc;
+  }
+
+  // One row by itself (utility kernels).
+  __device__ __forceinline__ double apply(int32_t row, const double* __restrict__ x) const {
+    const int32_t e = rp[row + 1];
+    double acc = 0.0;
+    for (int32_t k = rp[row]; k < e; ++k) acc = acc + va[k] * x[ci[k]];
     return acc;
   }
 };
@@ -101,6 +128,9 @@ template <int NPTS>
 struct StencilOp {
   int32_t nx, ny, nz, pad;
   double c[NPTS];
+  __device__ __forceinline__ double spmv(int32_t row, bool valid, const double* __restrict__ x) const {
+    return valid ? apply(row, x) : 0.0;
+  }
   __device__ __forceinline__ double apply(int32_t row, const double* __restrict__ x) const {
     const int32_t i = row % nx;
     const int32_t jk = row / nx;
@@ -221,7 +251,10 @@ __device__ __forceinline__ void gather_sums(const Args& a, double (&tot)[ND]) {
   for (int k = 0; k < ND; ++k) {
     double c[kChunk];
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) c[j] = (base + j < a.Gin) ? a.pin[k * kMaxG + base + j] : 0.0;
+    for (int j = 0; j < kChunk; ++j) {
+      const double p = a.pin[k * kMaxG + min(base + j, a.Gin - 1)];  // clamped: branch-free
+      c[j] = (base + j < a.Gin) ? p : 0.0;
+    }
 #pragma unroll
     for (int w = 1; w < kChunk; w <<= 1) {
 #pragma unroll
@@ -235,7 +268,9 @@ __device__ __forceinline__ void gather_sums(const Args& a, double (&tot)[ND]) {
 }
 
 // The workgroup's rows with ND products each; writes its partial sums to
-// pout[k][blockIdx.x].  Body(row, d) handles one row (rows past n give 0).
+// pout[k][blockIdx.x].  Body(row, valid, d) is called by all 64 lanes of a
+// block (so an operator may work on the block cooperatively); lanes with
+// valid == false (rows past n) must leave d at 0 and touch no vector.
 template <int ND, class Body>
 __device__ __forceinline__ void produce(const Args& a, Body body) {
   __shared__ double blk[ND][kWG];
@@ -247,8 +282,8 @@ __device__ __forceinline__ void produce(const Args& a, Body body) {
 #pragma unroll
     for (int k = 0; k < ND; ++k) d[k] = 0.0;
     if (b0 < a.n) {
-      const int64_t row = b0 + lane;
-      if (row < a.n) body((int32_t)row, d);
+      const int32_t row = (int32_t)(b0 + lane);
+      body(row, row < a.n, d);
       wave_sum63<ND>(d);
     }
     if (lane == 63) {
@@ -267,14 +302,17 @@ __device__ __forceinline__ void produce(const Args& a, Body body) {
   }
 }
 
-// The workgroup's rows without a reduction.
+// The workgroup's rows without a reduction; Body(row, valid) as above.
 template <class Body>
 __device__ __forceinline__ void each_row(const Args& a, Body body) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t wbase = ((int64_t)blockIdx.x * 4 + wave) * a.R * 64;
   for (int j = 0; j < a.R; ++j) {
-    const int64_t row = wbase + (int64_t)j * 64 + lane;
-    if (row < a.n) body((int32_t)row);
+    const int64_t b0 = wbase + (int64_t)j * 64;
+    if (b0 < a.n) {
+      const int32_t row = (int32_t)(b0 + lane);
+      body(row, row < a.n);
+    }
   }
 }
 
@@ -418,8 +456,10 @@ template <class Op, int PC, bool PIPE>
 __global__ __launch_bounds__(kWG) void k_setup_r0(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   publish(a, st);
-  produce<1>(a, [&](int32_t row, double (&d)[1]) {
-    const double r0 = a.b[row] - op.apply(row, a.x);
+  produce<1>(a, [&](int32_t row, bool valid, double (&d)[1]) {
+    const double ax = op.spmv(row, valid, a.x);
+    if (!valid) return;
+    const double r0 = a.b[row] - ax;
     a.r0[row] = r0;
     a.r[row] = r0;
     if (PIPE) {
@@ -450,8 +490,9 @@ __global__ __launch_bounds__(kWG) void k_setup_w0(Op op, Args a) {
   fin_setup_gamma(st, a.hist, g[0]);
   publish(a, st);
   if (st.status != DS_RUNNING) return;
-  produce<1>(a, [&](int32_t row, double (&d)[1]) {
-    const double w = op.apply(row, a.rh);
+  produce<1>(a, [&](int32_t row, bool valid, double (&d)[1]) {
+    const double w = op.spmv(row, valid, a.rh);
+    if (!valid) return;
     a.w[row] = w;
     if (PC != PC_NONE) a.wh[row] = apply_pc<PC>(a, row, w);
     d[0] = a.r0[row] * w;
@@ -482,13 +523,15 @@ __global__ __launch_bounds__(kWG) void k_pa(Op op, Args a) {
   publish(a, st);
   if (st.status != DS_RUNNING) return;
   const double alpha = st.alpha, beta = st.beta, omega = st.omega;
-  produce<2>(a, [&](int32_t row, double (&d)[2]) {
-    const double t = op.apply(row, a.wh);  // line 23 of the previous iteration
+  produce<2>(a, [&](int32_t row, bool valid, double (&d)[2]) {
+    const double t = op.spmv(row, valid, a.wh);  // line 23 of the previous iteration
+    const double z_rr = RR2 ? op.spmv(row, valid, a.sh) : 0.0;
+    if (!valid) return;
     const double r = a.r[row], w = a.w[row];
     double s, z;
     if (RR2) {
       s = a.s[row];
-      z = op.apply(row, a.sh);
+      z = z_rr;
     } else {
       const double v = a.v[row];
       const double s_old = a.s[row], z_old = a.z[row];
@@ -526,13 +569,16 @@ __global__ __launch_bounds__(kWG) void k_pb(Op op, Args a) {
   const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
   publish(a, st);
   if (yz) {
-    each_row(a, [&](int32_t row) { a.x[row] = a.x[row] + alpha * a.ph[row]; });
+    each_row(a, [&](int32_t row, bool valid) {
+      if (valid) a.x[row] = a.x[row] + alpha * a.ph[row];
+    });
     return;
   }
   if (st.status != DS_RUNNING) return;
   const double omega = st.omega;
-  produce<5>(a, [&](int32_t row, double (&d)[5]) {
-    const double v = op.apply(row, a.zh);                              // line 14
+  produce<5>(a, [&](int32_t row, bool valid, double (&d)[5]) {
+    const double v = op.spmv(row, valid, a.zh);                        // line 14
+    if (!valid) return;
     const double r = a.r[row], s = a.s[row], w = a.w[row], z = a.z[row];
     const double q = r - alpha * s;
     const double y = w - alpha * z;
@@ -574,7 +620,8 @@ __global__ __launch_bounds__(kWG) void k_rr_x(Args a) {
   publish(a, st);
   if (!yz && st.status != DS_RUNNING) return;
   const double omega = st.omega;
-  each_row(a, [&](int32_t row) {
+  each_row(a, [&](int32_t row, bool valid) {
+    if (!valid) return;
     if (yz) {
       a.x[row] = a.x[row] + alpha * a.ph[row];
     } else {
@@ -589,8 +636,10 @@ template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_rr_r(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   publish(a, st);
-  each_row(a, [&](int32_t row) {
-    const double r = a.b[row] - op.apply(row, a.x);
+  each_row(a, [&](int32_t row, bool valid) {
+    const double ax = op.spmv(row, valid, a.x);
+    if (!valid) return;
+    const double r = a.b[row] - ax;
     a.r[row] = r;
     if (PC != PC_NONE) a.rh[row] = apply_pc<PC>(a, row, r);
   });
@@ -603,8 +652,9 @@ __global__ __launch_bounds__(kWG) void k_rr_w(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   st.n_rr += 1;
   publish(a, st);
-  produce<5>(a, [&](int32_t row, double (&d)[5]) {
-    const double w = op.apply(row, a.rh);
+  produce<5>(a, [&](int32_t row, bool valid, double (&d)[5]) {
+    const double w = op.spmv(row, valid, a.rh);
+    if (!valid) return;
     a.w[row] = w;
     if (PC != PC_NONE) a.wh[row] = apply_pc<PC>(a, row, w);
     const double r0 = a.r0[row], r = a.r[row];
@@ -627,7 +677,8 @@ __global__ __launch_bounds__(kWG) void k_rr_p(Args a) {
   publish(a, st);
   if (st.status != DS_RUNNING) return;
   const double beta = st.beta, omega = st.omega;
-  each_row(a, [&](int32_t row) {
+  each_row(a, [&](int32_t row, bool valid) {
+    if (!valid) return;
     if (PC != PC_NONE) a.ph[row] = a.rh[row] + beta * (a.ph[row] - omega * a.sh[row]);
     else a.ph[row] = a.r[row] + beta * (a.ph[row] - omega * a.s[row]);
   });
@@ -638,8 +689,9 @@ template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_rr_s(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   publish(a, st);
-  each_row(a, [&](int32_t row) {
-    const double s = op.apply(row, a.ph);
+  each_row(a, [&](int32_t row, bool valid) {
+    const double s = op.spmv(row, valid, a.ph);
+    if (!valid) return;
     a.s[row] = s;
     if (PC != PC_NONE) a.sh[row] = apply_pc<PC>(a, row, s);
   });
@@ -660,8 +712,9 @@ __global__ __launch_bounds__(kWG) void k_b1(Op op, Args a) {
   }
   publish(a, st);
   if (st.status != DS_RUNNING) return;
-  produce<1>(a, [&](int32_t row, double (&d)[1]) {
-    const double s = op.apply(row, a.ph);
+  produce<1>(a, [&](int32_t row, bool valid, double (&d)[1]) {
+    const double s = op.spmv(row, valid, a.ph);
+    if (!valid) return;
     a.s[row] = s;
     d[0] = a.r0[row] * s;
   });
@@ -677,7 +730,8 @@ __global__ __launch_bounds__(kWG) void k_b2(Args a) {
   publish(a, st);
   if (st.status != DS_RUNNING) return;
   const double alpha = st.alpha;
-  each_row(a, [&](int32_t row) {
+  each_row(a, [&](int32_t row, bool valid) {
+    if (!valid) return;
     const double q = a.r[row] - alpha * a.s[row];
     a.q[row] = q;
     if (PC != PC_NONE) a.qh[row] = apply_pc<PC>(a, row, q);
@@ -689,8 +743,9 @@ template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_b3(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   publish(a, st);
-  produce<2>(a, [&](int32_t row, double (&d)[2]) {
-    const double y = op.apply(row, a.qh);
+  produce<2>(a, [&](int32_t row, bool valid, double (&d)[2]) {
+    const double y = op.spmv(row, valid, a.qh);
+    if (!valid) return;
     a.y[row] = y;
     d[0] = a.q[row] * y;
     d[1] = y * y;
@@ -707,12 +762,15 @@ __global__ __launch_bounds__(kWG) void k_b4(Args a) {
   const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
   publish(a, st);
   if (yz) {
-    each_row(a, [&](int32_t row) { a.x[row] = a.x[row] + alpha * a.ph[row]; });
+    each_row(a, [&](int32_t row, bool valid) {
+      if (valid) a.x[row] = a.x[row] + alpha * a.ph[row];
+    });
     return;
   }
   if (st.status != DS_RUNNING) return;
   const double omega = st.omega;
-  produce<2>(a, [&](int32_t row, double (&d)[2]) {
+  produce<2>(a, [&](int32_t row, bool valid, double (&d)[2]) {
+    if (!valid) return;
     const double q = a.q[row];
     a.x[row] = a.x[row] + alpha * a.ph[row] + omega * a.qh[row];
     const double r = q - omega * a.y[row];
@@ -732,7 +790,8 @@ __global__ __launch_bounds__(kWG) void k_b5(Args a) {
   publish(a, st);
   if (st.status != DS_RUNNING) return;
   const double beta = st.beta, omega = st.omega;
-  each_row(a, [&](int32_t row) {
+  each_row(a, [&](int32_t row, bool valid) {
+    if (!valid) return;
     const double p = a.r[row] + beta * (a.p[row] - omega * a.s[row]);
     a.p[row] = p;
     if (PC != PC_NONE) a.ph[row] = apply_pc<PC>(a, row, p);
@@ -784,20 +843,27 @@ __global__ void k_init_state(DevState* st, double tol) {
 template <class Op>
 __global__ __launch_bounds__(kWG) void k_spmv(Op op, Args a, const double* __restrict__ xin,
                                               double* __restrict__ yout) {
-  each_row(a, [&](int32_t row) { yout[row] = op.apply(row, xin); });
+  each_row(a, [&](int32_t row, bool valid) {
+    const double y = op.spmv(row, valid, xin);
+    if (valid) yout[row] = y;
+  });
 }
 
 // partials of (x, y).
 __global__ __launch_bounds__(kWG) void k_dot(Args a, const double* __restrict__ xv,
                                              const double* __restrict__ yv) {
-  produce<1>(a, [&](int32_t row, double (&d)[1]) { d[0] = xv[row] * yv[row]; });
+  produce<1>(a, [&](int32_t row, bool valid, double (&d)[1]) {
+    if (valid) d[0] = xv[row] * yv[row];
+  });
 }
 
 // partials of ||b - A x||^2 (true residual of the returned x).
 template <class Op>
 __global__ __launch_bounds__(kWG) void k_true_res(Op op, Args a) {
-  produce<1>(a, [&](int32_t row, double (&d)[1]) {
-    const double r = a.b[row] - op.apply(row, a.x);
+  produce<1>(a, [&](int32_t row, bool valid, double (&d)[1]) {
+    const double ax = op.spmv(row, valid, a.x);
+    if (!valid) return;
+    const double r = a.b[row] - ax;
     d[0] = r * r;
   });
 }

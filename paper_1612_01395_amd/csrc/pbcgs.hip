@@ -94,16 +94,16 @@ int env_int(const char* name, int dflt) {
 
 // Launch shape: a wave handles R blocks of 64 rows (R a power of two), a
 // workgroup 4 R blocks; R is the smallest power of two with at most `gtarget`
-// workgroups (default 512: two workgroups per CU, each streaming 16 rows per
-// thread for the 128^3 workload).
+// workgroups (default 1024: four workgroups per CU, 8 rows per thread for the
+// 128^3 workload).
 struct Shape {
   int32_t n, R, G;
 };
 
 bool make_shape(int32_t n, Shape* sh) {
   if (n <= 0) return false;
-  int gt = env_int("PBCGS_GTARGET", 512);
-  if (gt < 1 || gt > kMaxG) gt = 512;
+  int gt = env_int("PBCGS_GTARGET", 1024);
+  if (gt < 1 || gt > kMaxG) gt = 1024;
   const int forced = env_int("PBCGS_R", 0);
   for (int R = 1; R <= kMaxR; R *= 2) {
     const int64_t G = ((int64_t)n + 256 * (int64_t)R - 1) / (256 * (int64_t)R);
@@ -439,7 +439,7 @@ struct Driver {
 
 template <class F>
 int with_op(pbcgs_op_t A, F f) {
-  if (A->kind == OP_CSR) return f(CsrOp{A->rp, A->ci, A->va});
+  if (A->kind == OP_CSR) return f(CsrOp{A->rp, A->ci, A->va, A->n});
   if (A->kind == OP_ST7) {
     StencilOp<7> s;
     std::memset(&s, 0, sizeof s);
@@ -554,7 +554,7 @@ int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr
   Shape sh;
   if (!make_shape(n, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows for one launch");
   DeviceGuard guard(ctx->device);
-  CsrOp op{row_ptr, col_idx, val};
+  CsrOp op{row_ptr, col_idx, val, n};
   int rc = reset_flag(ctx);
   if (rc != PBCGS_SUCCESS) return rc;
   k_csr_check<<<(n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(op, n, nnz, ctx->flag);
@@ -660,7 +660,7 @@ int pbcgs_jacobi_dinv(pbcgs_ctx_t ctx, pbcgs_op_t A, double* dinv) {
   }
   int rc = reset_flag(ctx);
   if (rc != PBCGS_SUCCESS) return rc;
-  k_dinv_csr<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(CsrOp{A->rp, A->ci, A->va}, A->n, dinv, ctx->flag);
+  k_dinv_csr<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(CsrOp{A->rp, A->ci, A->va, A->n}, A->n, dinv, ctx->flag);
   int32_t flag = 0;
   rc = read_flag(ctx, &flag);
   if (rc != PBCGS_SUCCESS) return rc;
