@@ -374,16 +374,27 @@ struct Driver {
     q = 0;
     setup();
     HIP_TRY(ctx, hipGetLastError());
-    // Chunks of `check` iterations; the status after chunk c is polled while
-    // chunk c+1 is already queued, so the device does not wait for the host.
-    // Kernels queued after the stop see the final status and exit at once.
+    // Chunks of at most `check` iterations; the status after chunk c is polled
+    // while chunk c+1 is already queued, so the device does not wait for the
+    // host.  Near the end the chunks shrink: the observed convergence rate of
+    // ||r_i|| / ||r_0|| predicts how many iterations remain, so few kernels
+    // are queued past the stop (those see the final status and exit at once).
     int64_t launched = 0;
     int pend[2];
     int npend = 0, next_slot = 0;
     bool stop = false;
+    double last_rel = 1.0;
+    int64_t last_it = 0;
+    double rate = 0.0;  // d log(relres) / d iteration, < 0 when converging
     for (;;) {
       while (!stop && launched < o.maxit && npend < 2) {
-        const int m = (int)std::min<int64_t>(check, o.maxit - launched);
+        int m = (int)std::min<int64_t>(check, o.maxit - launched);
+        if (rate < 0.0 && o.tol > 0.0 && last_rel > 0.0) {
+          const double need = (std::log(o.tol) - std::log(last_rel)) / rate;  // from the last poll
+          const int64_t ahead = launched - last_it;                           // queued since then
+          const int64_t left = (int64_t)std::ceil(need) - ahead;
+          if (left < m) m = (int)std::max<int64_t>(1, left);
+        }
         int rc = chunk(launched, m, use_graph);
         if (rc != PBCGS_SUCCESS) return rc;
         launched += m;
@@ -398,7 +409,15 @@ struct Driver {
       pend[0] = pend[1];
       --npend;
       HIP_TRY(ctx, hipEventSynchronize(ctx->ev_poll[slot]));
-      if (ctx->hst[slot].status != DS_RUNNING) stop = true;
+      const DevState& h = ctx->hst[slot];
+      if (h.status != DS_RUNNING) {
+        stop = true;
+      } else if (h.iters > last_it && h.relres > 0.0 && last_rel > 0.0) {
+        const double r = (std::log(h.relres) - std::log(last_rel)) / (double)(h.iters - last_it);
+        rate = (rate < 0.0) ? 0.5 * (rate + r) : r;
+        last_rel = h.relres;
+        last_it = h.iters;
+      }
     }
     finish(launched);
     HIP_TRY(ctx, hipGetLastError());
