@@ -8,9 +8,15 @@ non-zeros), h^2-scaled, beta = (50, 30, 10), CSR FP64, Jacobi, x_true ~ U[0,1)
 replacement every 50 iterations.  Inputs are synthetic and resident in HBM
 before the timed region.
 
-One step = one complete solve (setup, every iteration, the replacements and
-the final true-residual check).  value = iterations / second over the timed
-steps.  Prints one JSON line.
+Jacobi is right preconditioning (A M^{-1} y = b, x = M^{-1} y).  The headline
+runs it with A M^{-1} formed once per solve, so the unpreconditioned
+p-BiCGStab (Algorithm 9) iterates on it; the literal Algorithm 11 (M^{-1}
+applied to hatted vectors) and the two forms of plain BiCGStab (Algorithm 7 on
+A M^{-1}, Algorithm 10) are timed beside it on the same kernels.
+
+One step = one complete solve (forming A M^{-1}, setup, every iteration, the
+replacements, x = M^{-1} y and the final true-residual check).  value =
+iterations / second over the timed steps.  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -62,29 +68,38 @@ def parse():
     p.add_argument("--n", type=int, default=128, help="grid side of the 3-D workload")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
-    p.add_argument("--only", default="", help="comma list of legs to run: pipe,bicg,stencil")
+    p.add_argument("--only", default="", help="comma list of legs to run: pipe,bicg,explicit,stencil")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
     return p.parse_args()
 
 
-def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool):
-    """Algorithmic HBM bytes of the two fused kernels of one iteration.
+def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: bool = True):
+    """Algorithmic HBM bytes of the two dominant kernels of one iteration and
+    of the whole iteration: (K_a, K_b, iteration).
 
-    Every array the kernel touches is counted once: the operator (int32
+    Every array a kernel touches is counted once: the operator (int32
     row_ptr, int32 col, f64 val; nothing for the stencil) and one read or
     write of each N-vector (the gathered SpMV input counted once).  Jacobi
     with a constant diagonal is a scalar (no dinv vector).
-    p-BiCGStab (Algorithm 11): phase A reads w^, r, w, v, s, z, r^, s^, z^, p^
-    and writes p^, s^, s, t, z, z^ (16 vectors); phase B reads z^, r, s, w, z, t,
-    r^, s^, w^, x, p^, r0 and writes x, v, r, r^, w, w^ (18 vectors).
-    BiCGStab (Algorithm 10), SpMV phases: s = A p^ with (r0, s): reads p^, r0,
-    writes s (3); y = A q^ with (q,y), (y,y): reads q^, q, writes y (3).
+
+    Folded Jacobi (A M^{-1} formed, Algorithm 9 on it): K_a reads w, r, v, s,
+    z, p and writes p, s, t, z (10 vectors); K_b reads z, r, s, w, t, x, p, r0
+    and writes x, v, r, w (12): 22 per iteration.  Literal Algorithm 11: K_a
+    reads w^, r, w, v, s, z, r^, s^, z^, p^ and writes p^, s^, s, t, z, z^ (16);
+    K_b reads z^, r, s, w, z, t, r^, s^, w^, x, p^, r0 and writes x, v, r, r^,
+    w, w^ (18): 34.  BiCGStab, SpMV kernels s = A p^ + (r0,s) and y = A q^ +
+    (q,y), (y,y): 3 + 2 (folded, Algorithm 7: 19 per iteration) or 3 + 3
+    (Algorithm 10: 23 per iteration).
     """
     vec = 8 * N
     mat = 0 if stencil else 4 * (N + 1) + 12 * nnz
     if variant == "bicgstab":
+        if folded:
+            return mat + 3 * vec, mat + 2 * vec, 19 * vec + 2 * mat
         return mat + 3 * vec, mat + 3 * vec, 23 * vec + 2 * mat
+    if folded:
+        return mat + 10 * vec, mat + 12 * vec, 22 * vec + 2 * mat
     return mat + 16 * vec, mat + 18 * vec, 34 * vec + 2 * mat
 
 
@@ -104,7 +119,7 @@ def main():
     dev = torch.device("cuda", 0)
     w = inputs.workload("c2", n=args.n)
     N = w.N
-    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "stencil"}
+    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil"}
 
     # ---- inputs resident in HBM -------------------------------------------------
     rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
@@ -119,34 +134,48 @@ def main():
     xbuf = torch.empty_like(b)
     torch.cuda.synchronize()
 
-    common = dict(precond="jacobi", tol=w.tol, maxit=w.maxit, rr_period=w.rr_period)
+    common = dict(tol=w.tol, maxit=w.maxit, rr_period=w.rr_period)
 
-    def timed_leg(op, variant):
+    def timed_leg(op, variant, precond):
         for _ in range(args.warmup):
-            solver.solve(op, b, variant=variant, out=xbuf, **common)
+            solver.solve(op, b, variant=variant, precond=precond, out=xbuf, **common)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         iters = 0
         last = None
         for _ in range(args.steps):
-            _, info = solver.solve(op, b, variant=variant, out=xbuf, **common)
+            _, info = solver.solve(op, b, variant=variant, precond=precond, out=xbuf, **common)
             iters += info.iters
             last = info
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         return iters, dt, last
 
+    # legs: (operator, variant, preconditioner form)
+    LEGS = {
+        "pipe": ("csr", "pbicgstab_rr", "jacobi_folded"),        # the metric
+        "bicg": ("csr", "bicgstab", "jacobi_folded"),
+        "pipe_alg11": ("csr", "pbicgstab_rr", "jacobi"),
+        "bicg_alg10": ("csr", "bicgstab", "jacobi"),
+        "st_pipe": ("stencil", "pbicgstab_rr", "jacobi_folded"),
+        "st_bicg": ("stencil", "bicgstab", "jacobi_folded"),
+    }
+    groups = {"pipe": ["pipe"], "bicg": ["bicg"], "explicit": ["pipe_alg11", "bicg_alg10"],
+              "stencil": ["st_pipe", "st_bicg"]}
     res = {}
-    if "pipe" in legs:
-        res["pipe"] = timed_leg(A, "pbicgstab_rr")
-    if "bicg" in legs:
-        res["bicg"] = timed_leg(A, "bicgstab")
-    if "stencil" in legs and S is not None:
-        res["st_pipe"] = timed_leg(S, "pbicgstab_rr")
-        res["st_bicg"] = timed_leg(S, "bicgstab")
+    for g in ("pipe", "bicg", "explicit", "stencil"):
+        if g not in legs:
+            continue
+        for leg in groups[g]:
+            kind, variant, precond = LEGS[leg]
+            op = A if kind == "csr" else S
+            if op is None:
+                continue
+            res[leg] = timed_leg(op, variant, precond)
 
     # ---- roofline of the dominant kernel: one solve with per-kernel events -------
-    _, pinfo = solver.solve(A, b, variant="pbicgstab_rr", out=xbuf, time_kernels=True, **common)
+    _, pinfo = solver.solve(A, b, variant="pbicgstab_rr", precond="jacobi_folded", out=xbuf, time_kernels=True,
+                            **common)
     ba, bb, _ = algorithmic_bytes(N, nnz, "pbicgstab", False)
     avg = [pinfo.kernel_ms[k] / max(pinfo.kernel_calls[k], 1) for k in range(2)]
     dom = 0 if pinfo.kernel_ms[0] >= pinfo.kernel_ms[1] else 1
@@ -154,7 +183,7 @@ def main():
     achieved = dom_bytes / (avg[dom] * 1e-3) / 1e9
     roofline = {
         "bound": "hbm",
-        "kernel": ("k_pa (t = A w^, recurrences, (q,y),(y,y))", "k_pb (v = A z^, updates, 5 dots)")[dom],
+        "kernel": ("k_pa (t = A w, recurrences, (q,y),(y,y))", "k_pb (v = A z, x/r/w updates, 5 dots)")[dom],
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -185,14 +214,14 @@ def main():
         solves, iters, dt = 0, 0, 0.0
         while solves == 0 or (dt < args.cpu_seconds and solves < 100):
             t0 = time.perf_counter()
-            _, oinfo = oracle.solve(Ah, bh, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=w.tol, maxit=w.maxit,
-                                    rr_period=w.rr_period)
+            _, oinfo = oracle.solve_folded(Ah, bh, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=w.tol,
+                                           maxit=w.maxit, rr_period=w.rr_period)
             dt += time.perf_counter() - t0
             iters += oinfo["iters"]
             solves += 1
         cpu = {"value": round(iters / dt, 3), "unit": "iters/s", "cores": oracle.get_threads(),
                "kind": "oracle",
-               "sample": f"{solves} complete p-BiCGStab+RR solves ({oinfo['iters']} iterations each, tol "
+               "sample": f"{solves} complete p-BiCGStab+RR folded-Jacobi solves ({oinfo['iters']} iterations each, tol "
                          f"{w.tol:g}) of the same {w.n}^3 system from x0 = 0, {dt:.1f} s"}
 
     it, dt, info = res.get("pipe", (0, 1.0, None))
@@ -212,32 +241,37 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"3-D 7-point upwind convection-diffusion {w.n}^3 (N={N}, nnz={nnz}), "
-                               f"beta=(50,30,10), CSR FP64, Jacobi, tol 1e-8, p-BiCGStab with residual "
-                               f"replacement every {w.rr_period}; one step = one full solve",
+                               f"beta=(50,30,10), CSR FP64, Jacobi (right preconditioning, A M^-1 formed), "
+                               f"tol 1e-8, p-BiCGStab with residual replacement every {w.rr_period}; "
+                               f"one step = one full solve",
                    "global_batch": 1, "parallelism": "single GPU"},
         "iters_per_solve": info.iters if info else None,
         "relres_true": info.relres_true if info else None,
         "gbps_effective": round(per_iter_bytes * value / 1e9, 1) if value else None,
         "syncs_per_iter": info.syncs_per_iter if info else None,
     }
+
+    def leg_summary(key, variant, stencil, folded):
+        lit, ldt, linfo = res[key]
+        lval = lit / ldt
+        _, _, lbytes = algorithmic_bytes(N, nnz, variant, stencil, folded)
+        return {"iters_per_s": round(lval, 2), "iters_per_solve": linfo.iters,
+                "ms_per_solve": round(ldt / args.steps * 1e3, 3), "gbps_effective": round(lbytes * lval / 1e9, 1),
+                "syncs_per_iter": linfo.syncs_per_iter, "relres_true": linfo.relres_true}
+
     if "bicg" in res:
-        bit, bdt, binfo = res["bicg"]
-        bval = bit / bdt
-        _, _, bbytes = algorithmic_bytes(N, nnz, "bicgstab", False)
-        out["bicgstab"] = {"iters_per_s": round(bval, 2), "iters_per_solve": binfo.iters,
-                           "ms_per_solve": round(bdt / args.steps * 1e3, 3),
-                           "gbps_effective": round(bbytes * bval / 1e9, 1), "syncs_per_iter": binfo.syncs_per_iter}
+        out["bicgstab"] = leg_summary("bicg", "bicgstab", False, True)
         if value:
+            bval = out["bicgstab"]["iters_per_s"]
             out["pbicgstab_over_bicgstab_iters_per_s"] = round(value / bval, 4)
-            out["pbicgstab_over_bicgstab_time_to_solution"] = round((bdt / args.steps) / (dt / args.steps), 4)
+            out["pbicgstab_over_bicgstab_time_to_solution"] = round(
+                out["bicgstab"]["ms_per_solve"] / (dt / args.steps * 1e3), 4)
+    if "pipe_alg11" in res:
+        out["explicit_jacobi"] = {"pbicgstab_rr_alg11": leg_summary("pipe_alg11", "pbicgstab", False, False),
+                                  "bicgstab_alg10": leg_summary("bicg_alg10", "bicgstab", False, False)}
     for key, variant in (("st_pipe", "pbicgstab"), ("st_bicg", "bicgstab")):
         if key in res:
-            sit, sdt, sinfo = res[key]
-            sval = sit / sdt
-            _, _, sbytes = algorithmic_bytes(N, nnz, variant, True)
-            out.setdefault("stencil", {})[variant] = {
-                "iters_per_s": round(sval, 2), "iters_per_solve": sinfo.iters,
-                "ms_per_solve": round(sdt / args.steps * 1e3, 3), "gbps_effective": round(sbytes * sval / 1e9, 1)}
+            out.setdefault("stencil", {})[variant] = leg_summary(key, variant, True, True)
     out["roofline"] = roofline
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -59,13 +59,20 @@ typedef enum {
 } pbcgs_status;
 
 enum { PBCGS_BICGSTAB = 0, PBCGS_PBICGSTAB = 1, PBCGS_PBICGSTAB_RR = 2 };
-enum { PBCGS_PRECOND_NONE = 0, PBCGS_PRECOND_JACOBI = 1 };
+/* Preconditioners.  JACOBI applies M^{-1} = diag(dinv) inside Algorithm 10 / 11
+ * (the hatted vectors of Section 3.6).  JACOBI_FOLDED is the same right
+ * preconditioning with the operator formed: the unpreconditioned Algorithm 7 / 9
+ * runs on A M^{-1} (entries a_ij * dinv_j) from y_0 = x_0 / dinv and returns
+ * x = dinv * y.  In exact arithmetic both give the same iterates x_i; the folded
+ * form moves fewer vectors per iteration (no hatted copies).  With a stencil
+ * it needs a constant diagonal (ERR_UNSUPPORTED otherwise). */
+enum { PBCGS_PRECOND_NONE = 0, PBCGS_PRECOND_JACOBI = 1, PBCGS_PRECOND_JACOBI_FOLDED = 2 };
 enum { PBCGS_FP64 = 0 };
 
 /* Solver options (host struct). */
 typedef struct {
     int32_t variant;     /* PBCGS_BICGSTAB, PBCGS_PBICGSTAB or PBCGS_PBICGSTAB_RR          */
-    int32_t precond;     /* PBCGS_PRECOND_NONE or PBCGS_PRECOND_JACOBI                     */
+    int32_t precond;     /* PBCGS_PRECOND_NONE, _JACOBI or _JACOBI_FOLDED                  */
     int32_t precision;   /* PBCGS_FP64                                                      */
     int32_t maxit;       /* iteration budget, >= 0                                          */
     double tol;          /* relative tolerance on the recursive residual, >= 0              */
@@ -145,11 +152,14 @@ int pbcgs_jacobi_dinv(pbcgs_ctx_t ctx, pbcgs_op_t A, double* dinv);
 /*
  * Solve A x = b.  b: n doubles (device, read only).  x: n doubles (device),
  * holds x_0 on entry and the final iterate on return.  dinv: n doubles
- * (device) of M^{-1} = diag(dinv) when opts->precond is JACOBI, or NULL to
- * derive dinv = 1/diag(A) inside the call; ignored without a preconditioner.
- * opts and info are host structs.  The call enqueues on the context's stream
- * and returns after the solve has finished; the host reads the 64-byte device
- * status once every check_every iterations.
+ * (device) of M^{-1} = diag(dinv) when opts->precond is JACOBI or
+ * JACOBI_FOLDED, or NULL to derive dinv = 1/diag(A) inside the call; ignored
+ * without a preconditioner.  With JACOBI_FOLDED the context forms A M^{-1}
+ * (CSR: nnz doubles of context-owned workspace, grown on demand) and x holds
+ * y = M x during the call.  relres_true is always ||b - A x|| / ||r_0|| with the
+ * caller's A and the returned x.  opts and info are host structs.  The call
+ * enqueues on the context's stream and returns after the solve has finished;
+ * the host reads the 64-byte device status once every check_every iterations.
  */
 int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const double* dinv,
                 const pbcgs_opts* opts, pbcgs_info* info);

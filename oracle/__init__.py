@@ -10,11 +10,14 @@ Algorithms (numbered as in arXiv 1612.01395, in order of appearance):
 ``ALG_BICGSTAB`` -> Algorithm 7 (Algorithm 10 when ``dinv`` is given);
 ``ALG_PBICGSTAB`` -> Algorithm 9 (Algorithm 11 with ``dinv``);
 ``ALG_PBICGSTAB_RR`` -> the same with residual replacement (Section 4.2).
+:func:`solve_folded` runs Algorithm 7 / 9 on A M^{-1} formed explicitly (the
+right preconditioning of Section 3.6 with the product built).
 """
 
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -215,6 +218,38 @@ def solve(A: CSR, b, *, algo: int = ALG_PBICGSTAB_RR, dinv=None, x0=None, tol: f
         info["history"] = hist[: info["iters"] + 1]
     if scalars:
         info["scalars"] = sc[: 3 * info["iters"]].reshape(-1, 3)
+    return x, info
+
+
+def fold_columns(A: CSR, dinv) -> CSR:
+    """A M^{-1} for M^{-1} = diag(dinv): entry (i, j) times dinv_j, one
+    rounding per entry.  Section 3.6 right-preconditions as A M^{-1} y = b,
+    M x = y; with this product formed, the unpreconditioned algorithms apply."""
+    d = np.ascontiguousarray(dinv, dtype=np.float64)
+    return CSR(A.row_ptr, A.col, A.val * d[A.col])
+
+
+def solve_folded(A: CSR, b, *, algo: int, dinv, x0=None, **kw):
+    """Right-preconditioned solve with A M^{-1} formed (Section 3.6): Algorithm 7
+    (``ALG_BICGSTAB``) or 9 (``ALG_PBICGSTAB``, ``ALG_PBICGSTAB_RR``) on
+    A M^{-1} y = b from y_0 = M x_0 = x_0 / dinv; returns x = M^{-1} y = dinv * y.
+
+    In exact arithmetic the iterates x_i are those of Algorithm 10 / 11.  The
+    stopping test and the history use the residual of the folded system,
+    b - A M^{-1} y_i (the unpreconditioned residual of x_i);
+    ``relres_true`` is ||b - A x|| / ||r_0|| with the original A and the
+    returned x, r_0 = b - A M^{-1} y_0.  Other keywords as :func:`solve`."""
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    d = np.ascontiguousarray(dinv, dtype=np.float64)
+    Ah = fold_columns(A, d)
+    x0a = np.zeros(A.n) if x0 is None else np.asarray(x0, dtype=np.float64)
+    y0 = x0a / d
+    y, info = solve(Ah, b, algo=algo, dinv=None, x0=y0, **kw)
+    x = d * y
+    r0 = b - spmv(Ah, y0)
+    rho0 = math.sqrt(dot(r0, r0))
+    r = b - spmv(A, x)
+    info["relres_true"] = math.sqrt(dot(r, r)) / rho0 if rho0 > 0.0 else 0.0
     return x, info
 
 

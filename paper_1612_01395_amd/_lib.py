@@ -17,7 +17,7 @@ SUCCESS, MAXIT, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 ERR_INVALID_ARG, ERR_ALLOC, ERR_HIP, ERR_UNSUPPORTED = -1, -2, -3, -4
 
 BICGSTAB, PBICGSTAB, PBICGSTAB_RR = 0, 1, 2
-PRECOND_NONE, PRECOND_JACOBI = 0, 1
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_JACOBI_FOLDED = 0, 1, 2
 FP64 = 0
 
 FLAG_DIRECT = 1       # launch kernels directly instead of replaying a HIP graph

@@ -94,13 +94,16 @@ struct CsrOp {
       const int32_t c1 = min(c0 + kStage, rhi);
       // branch-free: indices past the chunk are clamped into it (their
       // products land in slots that are never read), so all loads issue at once
+      // The matrix is streamed once per product: its loads are non-temporal
+      // so that they do not evict the Krylov vectors, which the next kernel
+      // reads again, from L2 and the Infinity Cache.
       int32_t cc[kStage / 64];
       double vv[kStage / 64];
 #pragma unroll
       for (int u = 0; u < kStage / 64; ++u) {
         const int32_t k = min(c0 + u * 64 + lane, c1 - 1);
-        cc[u] = ci[k];
-        vv[u] = va[k];
+        cc[u] = __builtin_nontemporal_load(&ci[k]);
+        vv[u] = __builtin_nontemporal_load(&va[k]);
       }
 #pragma unroll
       for (int u = 0; u < kStage / 64; ++u) stage[wave][u * 64 + lane] = vv[u] * x[cc[u]];
@@ -116,7 +119,8 @@ struct CsrOp {
   __device__ __forceinline__ double apply(int32_t row, const double* __restrict__ x) const {
     const int32_t e = rp[row + 1];
     double acc = 0.0;
-    for (int32_t k = rp[row]; k < e; ++k) acc = acc + va[k] * x[ci[k]];
+    for (int32_t k = rp[row]; k < e; ++k)
+      acc = acc + __builtin_nontemporal_load(&va[k]) * x[__builtin_nontemporal_load(&ci[k])];
     return acc;
   }
 };
@@ -866,6 +870,30 @@ __global__ __launch_bounds__(kWG) void k_true_res(Op op, Args a) {
     const double r = a.b[row] - ax;
     d[0] = r * r;
   });
+}
+
+// Right preconditioning with the operator formed explicitly (Section 3.6
+// solves A M^{-1} y = b and returns x = M^{-1} y): the entries of A M^{-1} are
+// a_ij * dinv_j, one rounding each.  The unpreconditioned Algorithms 7 and 9
+// then run on it.  Grid-stride over the non-zeros.
+template <int PC>
+__global__ __launch_bounds__(kWG) void k_fold_csr(CsrOp op, int64_t nnz, double* __restrict__ ahat,
+                                                  const double* __restrict__ dinv, double dinv_s) {
+  for (int64_t k = (int64_t)blockIdx.x * kWG + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kWG) {
+    const double d = (PC == PC_VEC) ? dinv[op.ci[k]] : dinv_s;
+    ahat[k] = op.va[k] * d;
+  }
+}
+
+// TO_Y: y_0 = M x_0 = x_0 / dinv before the iteration; otherwise x = M^{-1} y
+// = dinv * y after it.  In place.
+template <int PC, bool TO_Y>
+__global__ __launch_bounds__(kWG) void k_fold_x(int32_t n, double* __restrict__ x,
+                                                const double* __restrict__ dinv, double dinv_s) {
+  const int32_t row = blockIdx.x * kWG + threadIdx.x;
+  if (row >= n) return;
+  const double d = (PC == PC_VEC) ? dinv[row] : dinv_s;
+  x[row] = TO_Y ? x[row] / d : d * x[row];
 }
 
 // dinv_i = 1 / a_ii ; flag bit 0 if a diagonal entry is zero, non-finite or absent.

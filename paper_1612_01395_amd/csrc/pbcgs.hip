@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/pbcgs.h"
@@ -40,6 +41,8 @@ struct pbcgs_ctx_s {
   double* part = nullptr;   // PB_COUNT buffers of kMaxD * kMaxG partial sums
   double* ws = nullptr;     // solver vectors
   size_t ws_cap = 0;        // doubles
+  double* ahat = nullptr;   // values of A M^{-1} (folded Jacobi, CSR)
+  size_t ahat_cap = 0;      // doubles
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
   hipEvent_t ev_poll[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> kev;  // pool for per-kernel timing
@@ -148,6 +151,22 @@ int ensure_ws(pbcgs_ctx_t ctx, size_t doubles) {
   return PBCGS_SUCCESS;
 }
 
+int ensure_ahat(pbcgs_ctx_t ctx, size_t doubles) {
+  if (ctx->ahat_cap >= doubles) return PBCGS_SUCCESS;
+  if (ctx->ahat) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->ahat);
+    ctx->ahat = nullptr;
+    ctx->ahat_cap = 0;
+  }
+  if (hipMalloc(&ctx->ahat, std::max<size_t>(doubles, 1) * sizeof(double)) != hipSuccess) {
+    ctx->ahat = nullptr;
+    return fail(ctx, PBCGS_ERR_ALLOC, "allocation of " + std::to_string(doubles * 8) + " bytes for A M^-1 failed");
+  }
+  ctx->ahat_cap = doubles;
+  return PBCGS_SUCCESS;
+}
+
 size_t padded(int32_t n) { return ((size_t)n + 63) / 64 * 64; }
 
 int read_state(pbcgs_ctx_t ctx, int slot, DevState* out) {
@@ -204,6 +223,21 @@ int finish_sum(pbcgs_ctx_t ctx, const Shape& sh, double* result) {
   return PBCGS_SUCCESS;
 }
 
+// ||b - A x|| / rho0 in the pairwise arithmetic of the method (0 when rho0 = 0).
+template <class Op>
+int true_relres(pbcgs_ctx_t ctx, const Op& op, const Args& a0, double rho0, double* out) {
+  Args t = a0;
+  t.pout = part_buf(ctx, PB_UTIL);
+  k_true_res<Op><<<t.G, kWG, 0, ctx->stream>>>(op, t);
+  HIP_TRY(ctx, hipGetLastError());
+  const Shape sh = {a0.n, a0.R, a0.G};
+  double nr = 0.0;
+  const int rc = finish_sum(ctx, sh, &nr);
+  if (rc != PBCGS_SUCCESS) return rc;
+  *out = (rho0 > 0.0) ? std::sqrt(nr) / rho0 : 0.0;
+  return PBCGS_SUCCESS;
+}
+
 // ---------------------------------------------------------------------------
 // Per-(operator, preconditioner) driver.
 // ---------------------------------------------------------------------------
@@ -214,6 +248,8 @@ struct Driver {
   Args a;
   const pbcgs_opts& o;
   bool timing = false;
+  bool true_res = true;  // false: the caller computes relres_true itself
+  double rho0 = 0.0;     // ||r_0|| of the finished solve
   int64_t q = 0;  // kernel launches of this solve that passed the state on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[2];
   size_t ev_used = 0;
@@ -427,21 +463,16 @@ struct Driver {
     if (rc != PBCGS_SUCCESS) return rc;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop);
-    // true residual of the returned x, same pairwise arithmetic
-    Args t = a;
-    t.pout = part_buf(ctx, PB_UTIL);
-    k_true_res<Op><<<grid(), kWG, 0, s>>>(op, t);
-    HIP_TRY(ctx, hipGetLastError());
-    const Shape sh = {a.n, a.R, a.G};
-    double nr = 0.0;
-    rc = finish_sum(ctx, sh, &nr);
-    if (rc != PBCGS_SUCCESS) return rc;
+    rho0 = fin.rho0;
+    if (true_res) {  // true residual of the returned x, same pairwise arithmetic
+      rc = true_relres(ctx, op, a, fin.rho0, &info->relres_true);
+      if (rc != PBCGS_SUCCESS) return rc;
+    }
     info->iters = fin.iters;
     info->n_rr = fin.n_rr;
     info->status = map_status(fin.status);
     info->syncs_per_iter = (o.variant == PBCGS_BICGSTAB) ? 5 : 2;
     info->relres_rec = fin.relres;
-    info->relres_true = (fin.rho0 > 0.0) ? std::sqrt(nr) / fin.rho0 : 0.0;
     info->ms = ms;
     for (int k = 0; k < 2; ++k) {
       double tot = 0.0;
@@ -555,6 +586,7 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
   for (auto e : ctx->ev_poll)
     if (e) (void)hipEventDestroy(e);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->ahat) (void)hipFree(ctx->ahat);
   if (ctx->part) (void)hipFree(ctx->part);
   if (ctx->flag) (void)hipFree(ctx->flag);
   if (ctx->st) (void)hipFree(ctx->st);
@@ -694,8 +726,10 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
   const pbcgs_opts& o = *opts;
   if (o.variant < PBCGS_BICGSTAB || o.variant > PBCGS_PBICGSTAB_RR)
     return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown variant");
-  if (o.precond != PBCGS_PRECOND_NONE && o.precond != PBCGS_PRECOND_JACOBI)
+  if (o.precond != PBCGS_PRECOND_NONE && o.precond != PBCGS_PRECOND_JACOBI &&
+      o.precond != PBCGS_PRECOND_JACOBI_FOLDED)
     return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown preconditioner");
+  const bool folded = (o.precond == PBCGS_PRECOND_JACOBI_FOLDED);
   if (o.precision != PBCGS_FP64) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "only FP64 is implemented");
   if (o.maxit < 0 || !(o.tol >= 0.0)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad maxit or tol");
   if (o.variant == PBCGS_PBICGSTAB_RR && o.rr_period < 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad rr_period");
@@ -718,7 +752,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
 
   // preconditioner mode: none, a vector of 1/a_ii, or one constant
   int pc = PC_NONE;
-  if (o.precond == PBCGS_PRECOND_JACOBI) {
+  if (o.precond != PBCGS_PRECOND_NONE) {
     const double* dv = dinv;
     if (!dv && A->kind != OP_CSR) {
       const double c = (A->kind == OP_ST7) ? A->coef[3] : A->coef[2];
@@ -747,7 +781,9 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
       }
     }
   }
-  const bool hat = (pc != PC_NONE);
+  if (folded && pc == PC_VEC && A->kind != OP_CSR)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "folded Jacobi on a stencil needs a constant diagonal");
+  const bool hat = (pc != PC_NONE) && !folded;
   if (o.variant == PBCGS_BICGSTAB) {
     a.r0 = v[0]; a.r = v[1]; a.p = v[2]; a.s = v[3]; a.q = v[4]; a.y = v[5];
     a.ph = hat ? v[6] : a.p;
@@ -758,6 +794,46 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     a.wh = hat ? v[9] : a.w;
     a.sh = hat ? v[10] : a.s;
     a.zh = hat ? v[11] : a.z;
+  }
+
+  if (folded) {
+    // A M^{-1} y = b from y_0 = x_0 / dinv, then x = dinv * y (Section 3.6)
+    const int xg = (A->n + kWG - 1) / kWG;
+    const double* dv = a.dinv;
+    const double ds = a.dinv_s;
+    a.dinv = nullptr;
+    a.dinv_s = 0.0;
+    if (A->kind == OP_CSR) {
+      rc = ensure_ahat(ctx, (size_t)A->nnz);
+      if (rc != PBCGS_SUCCESS) return rc;
+    }
+    return with_op(A, [&](auto op) -> int {
+      using Op = decltype(op);
+      Op fop = op;
+      if constexpr (std::is_same<Op, CsrOp>::value) {
+        const int fg = (int)std::min<int64_t>((A->nnz + kWG - 1) / kWG, 8192);
+        if (A->nnz > 0) {
+          if (pc == PC_VEC) k_fold_csr<PC_VEC><<<fg, kWG, 0, ctx->stream>>>(op, A->nnz, ctx->ahat, dv, ds);
+          else k_fold_csr<PC_SCALAR><<<fg, kWG, 0, ctx->stream>>>(op, A->nnz, ctx->ahat, dv, ds);
+        }
+        fop.va = ctx->ahat;
+      } else {
+        for (double& c : fop.c) c = c * ds;  // one rounding per coefficient, as a_ij * dinv_j
+      }
+      if (pc == PC_VEC) k_fold_x<PC_VEC, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+      else k_fold_x<PC_SCALAR, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+      HIP_TRY(ctx, hipGetLastError());
+      Driver<Op, PC_NONE> drv(ctx, fop, a, o);
+      drv.true_res = false;
+      const int st = drv.run(info);
+      if (st < 0) return st;
+      if (pc == PC_VEC) k_fold_x<PC_VEC, false><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+      else k_fold_x<PC_SCALAR, false><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+      HIP_TRY(ctx, hipGetLastError());
+      const int rc2 = true_relres(ctx, op, a, drv.rho0, &info->relres_true);
+      if (rc2 != PBCGS_SUCCESS) return rc2;
+      return st;
+    });
   }
 
   return with_op(A, [&](auto op) -> int {

@@ -18,6 +18,10 @@ from . import _lib as L
 
 VARIANTS = {"bicgstab": L.BICGSTAB, "pbicgstab": L.PBICGSTAB, "pbicgstab_rr": L.PBICGSTAB_RR}
 STATUS = {0: "success", 1: "maxit", 2: "breakdown", 3: "nonfinite"}
+# "jacobi": M^{-1} = diag(1/a_ii) applied inside Algorithm 10 / 11; "jacobi_folded":
+# the same right preconditioning with A M^{-1} formed, Algorithm 7 / 9 run on it.
+PRECONDS = {None: L.PRECOND_NONE, "none": L.PRECOND_NONE, "jacobi": L.PRECOND_JACOBI,
+            "jacobi_folded": L.PRECOND_JACOBI_FOLDED}
 
 
 def _ptr(t: torch.Tensor | None):
@@ -196,8 +200,8 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
     _check_vec(b, A.n, "b")
     if variant not in VARIANTS:
         raise ValueError(f"variant must be one of {sorted(VARIANTS)}")
-    if precond not in (None, "none", "jacobi"):
-        raise ValueError("precond must be None or 'jacobi'")
+    if precond not in PRECONDS:
+        raise ValueError(f"precond must be one of {sorted(k for k in PRECONDS if k)} or None")
     if out is not None:
         _check_vec(out, A.n, "out")
         x = out
@@ -213,7 +217,7 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
     hist = torch.full((maxit + 1,), float("nan"), dtype=torch.float64, device=b.device) if history else None
     o = L.Opts()
     o.variant = VARIANTS[variant]
-    o.precond = L.PRECOND_JACOBI if precond == "jacobi" else L.PRECOND_NONE
+    o.precond = PRECONDS[precond]
     o.precision = L.FP64
     o.maxit = int(maxit)
     o.tol = float(tol)

@@ -49,15 +49,17 @@ def test_c2_assembly_and_rhs_bitwise(c2):
     assert same(host(b), b_or)
 
 
+@pytest.mark.parametrize("precond", ["jacobi", "jacobi_folded"])
 @pytest.mark.parametrize("variant", ["pbicgstab_rr", "bicgstab", "pbicgstab"])
-def test_c2_full_solve_bitwise(c2, variant):
+def test_c2_full_solve_bitwise(c2, variant, precond):
     w, A, _, op, b, b_or = c2
     dinv = oracle.jacobi_dinv(A)
     t0 = time.time()
-    x_or, i_or = oracle.solve(A, b_or, algo=ALG[variant], dinv=dinv, tol=w.tol, maxit=w.maxit,
-                              rr_period=w.rr_period, history=True)
-    say(f"c2 {variant}: oracle {i_or['iters']} it in {time.time() - t0:.1f}s")
-    x, info = solver.solve(op, b, variant=variant, precond="jacobi", tol=w.tol, maxit=w.maxit,
+    solve = oracle.solve_folded if precond == "jacobi_folded" else oracle.solve
+    x_or, i_or = solve(A, b_or, algo=ALG[variant], dinv=dinv, tol=w.tol, maxit=w.maxit,
+                       rr_period=w.rr_period, history=True)
+    say(f"c2 {variant} {precond}: oracle {i_or['iters']} it in {time.time() - t0:.1f}s")
+    x, info = solver.solve(op, b, variant=variant, precond=precond, tol=w.tol, maxit=w.maxit,
                            rr_period=w.rr_period, history=True)
     assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"])
     assert same(host(x), x_or)
@@ -73,9 +75,10 @@ def test_c2_stencil_equals_csr(c2):
     row = mid + w.n * mid + w.n * w.n * mid
     coef = list(A.val[A.row_ptr[row]:A.row_ptr[row + 1]])
     st = solver.stencil(w.n, w.n, w.n, coef)
-    x1, i1 = solver.solve(op, b, variant="pbicgstab_rr", precond="jacobi", tol=w.tol, rr_period=w.rr_period)
-    x2, i2 = solver.solve(st, b, variant="pbicgstab_rr", precond="jacobi", tol=w.tol, rr_period=w.rr_period)
-    assert i1.iters == i2.iters and same(host(x1), host(x2))
+    for precond in ("jacobi", "jacobi_folded"):
+        x1, i1 = solver.solve(op, b, variant="pbicgstab_rr", precond=precond, tol=w.tol, rr_period=w.rr_period)
+        x2, i2 = solver.solve(st, b, variant="pbicgstab_rr", precond=precond, tol=w.tol, rr_period=w.rr_period)
+        assert i1.iters == i2.iters and same(host(x1), host(x2))
 
 
 @pytest.fixture(scope="module")

@@ -95,10 +95,10 @@ def _compare(name, variant, precond, opkind, A, dim, n, dinv_vec=None, tol=1e-10
     xt = inputs.x_true(A.n)
     b = oracle.spmv(A, xt)
     dv = None
-    if precond == "jacobi":
+    if precond in ("jacobi", "jacobi_folded"):
         dv = dinv_vec if dinv_vec is not None else oracle.jacobi_dinv(A)
-    x_or, info_or = oracle.solve(A, b, algo=ALG[variant], dinv=dv, tol=tol, maxit=maxit, rr_period=rr,
-                                 history=True)
+    solve = oracle.solve_folded if precond == "jacobi_folded" else oracle.solve
+    x_or, info_or = solve(A, b, algo=ALG[variant], dinv=dv, tol=tol, maxit=maxit, rr_period=rr, history=True)
     if opkind == "csr":
         op = csr_op(A)
     else:
@@ -116,7 +116,7 @@ def _compare(name, variant, precond, opkind, A, dim, n, dinv_vec=None, tol=1e-10
 
 
 @pytest.mark.parametrize("variant", list(ALG))
-@pytest.mark.parametrize("precond", [None, "jacobi"])
+@pytest.mark.parametrize("precond", [None, "jacobi", "jacobi_folded"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_solve_bitwise_csr(name, variant, precond):
     require_gpu()
@@ -125,7 +125,7 @@ def test_solve_bitwise_csr(name, variant, precond):
 
 
 @pytest.mark.parametrize("variant", list(ALG))
-@pytest.mark.parametrize("precond", [None, "jacobi"])
+@pytest.mark.parametrize("precond", [None, "jacobi", "jacobi_folded"])
 @pytest.mark.parametrize("name", ["c1", "c2_24"])
 def test_solve_bitwise_stencil(name, variant, precond):
     require_gpu()
@@ -134,12 +134,33 @@ def test_solve_bitwise_stencil(name, variant, precond):
 
 
 @pytest.mark.parametrize("variant", list(ALG))
-def test_solve_bitwise_vector_jacobi(variant):
+@pytest.mark.parametrize("precond", ["jacobi", "jacobi_folded"])
+def test_solve_bitwise_vector_jacobi(variant, precond):
     """A non-constant M^{-1} exercises the vector preconditioner path."""
     require_gpu()
     A, _, dim, n = CASES["c2_24"]
     d = oracle.jacobi_dinv(A) * (1.0 + 0.25 * np.random.default_rng(3).random(A.n))
-    _compare("c2_24", variant, "jacobi", "csr", A, dim, n, dinv_vec=d)
+    _compare("c2_24", variant, precond, "csr", A, dim, n, dinv_vec=d)
+
+
+def test_folded_with_x0_and_repeated_calls():
+    """Folded Jacobi from a non-zero x_0 (y_0 = x_0 / dinv), on a matrix with a
+    variable diagonal, twice in a row on one context (the folded values are
+    recomputed per call), and a smaller system after a larger one."""
+    require_gpu()
+    for name in ("c3_10", "c3_10", "c1"):
+        A = CASES[name][0]
+        b = oracle.spmv(A, inputs.x_true(A.n))
+        x0 = inputs.random_vector(A.n, 9)
+        dv = oracle.jacobi_dinv(A)
+        for variant in ("pbicgstab_rr", "bicgstab"):
+            say(f"folded x0 {name} {variant}")
+            x_or, i_or = oracle.solve_folded(A, b, algo=ALG[variant], dinv=dv, x0=x0, tol=1e-11, rr_period=6)
+            x, info = solver.solve(csr_op(A), dev_t(b), dev_t(x0), variant=variant, precond="jacobi_folded",
+                                   tol=1e-11, rr_period=6)
+            assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"])
+            assert same(host(x), x_or)
+            assert same([info.relres_rec, info.relres_true], [i_or["relres_rec"], i_or["relres_true"]])
 
 
 def test_launch_modes_and_shapes_identical():
@@ -225,3 +246,8 @@ def test_api_errors():
         solver.solve(op, dev_t(np.ones(2)), precond="jacobi")
     with pytest.raises(_lib.PbcgsError):
         solver.solve(op, dev_t(np.ones(2)), tol=-1.0)
+    with pytest.raises(_lib.PbcgsError):
+        solver.solve(op, dev_t(np.ones(2)), precond="jacobi_folded")
+    st = solver.stencil(4, 4, 1, [-1.0, -1.0, 4.5, -1.0, -1.0])
+    with pytest.raises(_lib.PbcgsError):
+        solver.solve(st, dev_t(np.ones(16)), precond="jacobi_folded", dinv=dev_t(np.linspace(0.2, 0.3, 16)))

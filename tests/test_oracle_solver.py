@@ -356,3 +356,101 @@ def test_thread_count_does_not_change_results():
         oracle.set_threads(t0)
     np.testing.assert_array_equal(x1, x2)
     assert i1 == i2
+
+
+# ---------------------------------------------------------------------------
+# Right preconditioning with A M^{-1} formed (Section 3.6): Algorithms 7 and 9
+# on A M^{-1} y = b, x = M^{-1} y.
+# ---------------------------------------------------------------------------
+
+def _exact_fold(A_rows, dinv):
+    """Exact A M^{-1}: entry (i, j) times dinv_j."""
+    return [[(c, v * dinv[c]) for c, v in row] for row in A_rows]
+
+
+@pytest.mark.parametrize("name,S,b", tiny_systems()[:4], ids=_IDS)
+def test_exact_folded_form_equals_preconditioned_algorithms(name, S, b):
+    """In exact arithmetic, Algorithm 9 (7) on A M^{-1} from y_0 = M x_0, with
+    x_i = M^{-1} y_i, reproduces Algorithm 11 (10) iterate by iterate: same x_i,
+    same residuals r_i = b - A x_i, same alpha, omega, beta.  A row scaling
+    (left preconditioning) instead of the column scaling would change the
+    residuals and fail this."""
+    A = frac_rows(S)
+    bf = [Fraction(float(v)) for v in b]
+    N = len(bf)
+    steps = N + 2 if N <= 4 else EXACT_STEPS
+    dinv = [1 / Fraction(float(d)) for d in S.diagonal()]
+    x0 = [Fraction(k + 1, 4) for k in range(N)]
+    y0 = [x / d for x, d in zip(x0, dinv)]
+    Ah = _exact_fold(A, dinv)
+    for plain, pre in ((exact.bicgstab, exact.bicgstab), (exact.pbicgstab, exact.pbicgstab)):
+        ref = pre(A, bf, x0, steps, dinv=dinv)
+        got = plain(Ah, bf, y0, steps)
+        assert ref[1] == got[1] and len(ref[0]) == len(got[0])
+        for rr, gg in zip(ref[0], got[0]):
+            assert exact.scale(dinv, gg["x"]) == rr["x"]
+            assert gg["r"] == rr["r"]
+            assert (gg["alpha"], gg["omega"], gg["beta"]) == (rr["alpha"], rr["omega"], rr["beta"])
+    if len(set(dinv)) > 1:
+        # with a variable diagonal the left-scaled operator M^{-1} A gives other iterates
+        Al = [[(c, v * dinv[i]) for c, v in row] for i, row in enumerate(A)]
+        left, _, _ = exact.pbicgstab(Al, exact.scale(dinv, bf), x0, 2)
+        right, _, _ = exact.pbicgstab(Ah, bf, y0, 2)
+        assert [exact.scale(dinv, r["x"]) for r in right] != [r["x"] for r in left]
+
+
+@pytest.mark.parametrize("algo", ALGS)
+def test_fp64_folded_oracle_tracks_exact_iterates(algo):
+    """``solve_folded`` follows the exact Algorithm 10 / 11 iterates to 1e-13 (k <= 6)."""
+    name, S, b = tiny_systems()[2]
+    A = oracle.CSR(S.indptr, S.indices, S.data)
+    dinv = oracle.jacobi_dinv(A)
+    Af = frac_rows(S)
+    bf = [Fraction(float(v)) for v in b]
+    x0 = [Fraction(0)] * len(bf)
+    df = [1 / Fraction(float(d)) for d in S.diagonal()]
+    if algo == oracle.ALG_BICGSTAB:
+        ref, _ = exact.bicgstab(Af, bf, x0, 6, dinv=df)
+    else:
+        ref, _, _ = exact.pbicgstab(Af, bf, x0, 6, dinv=df, rr_period=3 if algo == oracle.ALG_PBICGSTAB_RR else 0)
+    for k in range(1, 7):
+        x, info = oracle.solve_folded(A, b, algo=algo, dinv=dinv, tol=0.0, maxit=k, rr_period=3, scalars=True)
+        if info["status"] != oracle.MAXIT:
+            break
+        xr = _frac_to_float(ref[k - 1]["x"])
+        assert np.linalg.norm(x - xr) <= 1e-13 * np.linalg.norm(xr)
+        a, w, _ = info["scalars"][k - 1]
+        tol = 1e-13 if k <= 3 else 1e-10
+        assert abs(a - float(ref[k - 1]["alpha"])) <= tol * abs(float(ref[k - 1]["alpha"]))
+        assert abs(w - float(ref[k - 1]["omega"])) <= tol * abs(float(ref[k - 1]["omega"]))
+
+
+@pytest.mark.parametrize("name,A,pc", dense_cases(), ids=lambda v: v if isinstance(v, str) else "")
+@pytest.mark.parametrize("algo", ALGS)
+def test_folded_solution_against_dense_lu(name, A, pc, algo):
+    xt = inputs.x_true(A.n)
+    b = oracle.spmv(A, xt)
+    dinv = oracle.jacobi_dinv(A)
+    x, info = oracle.solve_folded(A, b, algo=algo, dinv=dinv, tol=1e-10, rr_period=10)
+    assert info["status"] == oracle.SUCCESS
+    D = A.to_scipy().toarray()
+    x_lu = np.linalg.solve(D, b)
+    assert info["relres_true"] <= 1e-9
+    assert np.linalg.norm(x - x_lu) <= 10 * np.linalg.cond(D) * 1e-10 * np.linalg.norm(x_lu)
+    # the recursive residual of the folded system is the unpreconditioned one
+    assert info["relres_rec"] <= 1e-10
+    assert abs(info["relres_true"] - info["relres_rec"]) <= 1e-9
+
+
+def test_folded_constant_diagonal_is_a_scaling():
+    """M^{-1} = I/4 on the operator 4A: A M^{-1} = A exactly (a power of two),
+    so the folded iterates y_i are those of the unpreconditioned solve on A,
+    bit for bit, and x = y / 4."""
+    A = oracle.assemble_workload(inputs.workload("c1"))
+    A4 = oracle.CSR(A.row_ptr, A.col, A.val * 4.0)
+    dinv = np.full(A.n, 0.25)
+    b = oracle.spmv(A4, inputs.x_true(A.n))
+    x, info = oracle.solve_folded(A4, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=1e-9, rr_period=20)
+    y, info2 = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, tol=1e-9, rr_period=20)
+    assert info["iters"] == info2["iters"]
+    assert np.array_equal(x, y * 0.25)
