@@ -37,6 +37,7 @@ _lib = None
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
 
 
 def build() -> None:
@@ -85,6 +86,14 @@ def lib():
                                _nullable(_f64p), _f64p, _f64p, ctypes.c_double, ctypes.c_int32,
                                ctypes.c_int32, ctypes.c_int32, _nullable(_f64p), _nullable(_f64p),
                                _i32p, _f64p]
+        L.or_solve_mp.restype = ctypes.c_int
+        L.or_solve_mp.argtypes = [ctypes.c_int32, _i32p, _i32p, _f64p, _f64p, _f64p, ctypes.c_double,
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _nullable(_f64p),
+                                  _nullable(_f64p), _i32p, _f64p]
+        L.or_dot32.restype = ctypes.c_double
+        L.or_dot32.argtypes = [ctypes.c_int64, _f32p, _f32p]
+        L.or_spmv32.restype = None
+        L.or_spmv32.argtypes = [ctypes.c_int32, _i32p, _i32p, _f32p, _f32p, _f32p]
         L.or_counters_get.restype = None
         L.or_counters_get.argtypes = [np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")]
         L.or_counters_reset.restype = None
@@ -250,6 +259,60 @@ def solve_folded(A: CSR, b, *, algo: int, dinv, x0=None, **kw):
     rho0 = math.sqrt(dot(r0, r0))
     r = b - spmv(A, x)
     info["relres_true"] = math.sqrt(dot(r, r)) / rho0 if rho0 > 0.0 else 0.0
+    return x, info
+
+
+def dot32(x, y) -> float:
+    """(x, y) in binary32: pairwise sum of the binary32 products, widened."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    return float(lib().or_dot32(len(x), x, y))
+
+
+def spmv32(A: CSR, x) -> np.ndarray:
+    """y = f(A) x in binary32 (values rounded to binary32, rows in stored order)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.empty(A.n, np.float32)
+    lib().or_spmv32(A.n, A.row_ptr, A.col, np.ascontiguousarray(A.val.astype(np.float32)), x, y)
+    return y
+
+
+def solve_mp(A: CSR, b, *, dinv=None, x0=None, tol: float = 1e-10, maxit: int = 4000, rr_period: int = 50,
+             rr_max: int = -1, history: bool = False, scalars: bool = False):
+    """Precision form of p-BiCGStab with residual replacement: binary32
+    vectors, SpMV, recurrences and dot products; binary64 replacement steps
+    (Section 4.2), x update and alpha, beta, omega; convergence of the
+    binary32 recursive residual confirmed by the binary64 true residual.
+    With ``dinv`` the solve runs on A M^{-1} formed (see :func:`solve_folded`).
+    Returns ``(x, info)`` like :func:`solve`."""
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    Ah, d = A, None
+    x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    if dinv is not None:
+        d = np.ascontiguousarray(dinv, dtype=np.float64)
+        Ah = fold_columns(A, d)
+        x = x / d
+    y0 = x.copy()
+    hist = np.full(maxit + 1, np.nan) if history else None
+    sc = np.full(3 * max(maxit, 1), np.nan) if scalars else None
+    ints = np.zeros(3, np.int32)
+    dbl = np.zeros(2, np.float64)
+    st = lib().or_solve_mp(Ah.n, Ah.row_ptr, Ah.col, Ah.val, b, x, float(tol), int(maxit), int(rr_period),
+                           int(rr_max), hist, sc, ints, dbl)
+    if st < 0:
+        raise ValueError(f"oracle solve failed with code {st}")
+    info = {"iters": int(ints[0]), "n_rr": int(ints[1]), "status": int(ints[2]),
+            "relres_rec": float(dbl[0]), "relres_true": float(dbl[1])}
+    if d is not None:
+        x = d * x
+        r0 = (b - spmv(Ah, y0)).astype(np.float32)
+        rho0 = math.sqrt(dot32(r0, r0))
+        r = b - spmv(A, x)
+        info["relres_true"] = math.sqrt(dot(r, r)) / rho0 if rho0 > 0.0 else 0.0
+    if history:
+        info["history"] = hist[: info["iters"] + 1]
+    if scalars:
+        info["scalars"] = sc[: 3 * info["iters"]].reshape(-1, 3)
     return x, info
 
 

@@ -16,6 +16,14 @@
  *   Algorithm 10  right-preconditioned BiCGStab          (Section 3.6)
  *   Algorithm 11  preconditioned pipelined BiCGStab      (Section 3.6)
  *
+ * or_solve_mp is the precision form of Algorithm 9 with residual replacement:
+ * binary32 vectors, SpMV, recurrences and dot products, binary64 replacement
+ * steps, x update and scalars, and a binary64 true-residual check before any
+ * SUCCESS.  Its pins are special cases and accuracy facts (exact binary32
+ * cases, tracking of the binary64 iterates, the stall without replacement,
+ * the confirmed convergence); its exact rounding sequence beyond them is
+ * parity unpinned.
+ *
  * Residual replacement follows Section 4.2: every k iterations r, r^, w and
  * s, s^, z are recomputed from their definitions (4 SpMVs + 2 preconditioner
  * applications).  Stopping test: ||r_i||_2 / ||r_0||_2 <= tol on the
@@ -585,6 +593,255 @@ oom:
     free(tmp); free(prod);
     if (pc) { free(rh); free(wh); free(sh); free(zh); free(qh); }
     return OR_ERR_ALLOC;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Precision form: p-BiCGStab (Alg. 9) with FP32 vectors, SpMV, recurrences */
+/* and dot products, and FP64 residual replacement (Section 4.2), x update  */
+/* and scalars alpha, beta, omega.                                           */
+/*                                                                           */
+/* f() is rounding to binary32.  The FP32 operator holds f(a_ij).  A dot    */
+/* product is the pairwise sum of the binary32 products in binary32, + 0.0f, */
+/* then widened.  Vector updates take the scalars rounded to binary32.  The  */
+/* replacement steps run in binary64 on the binary64 operator and the       */
+/* binary64 x, and round once when stored: r = f(b - A x), w = f(A (b - A x)),*/
+/* s = f(A p), z = f(A (A p)).  The setup is such a replacement.             */
+/* Convergence of the FP32 recursive residual is confirmed with the FP64    */
+/* true residual ||b - A x|| / rho0; if that is still above tol, the        */
+/* iteration is a replacement iteration and goes on.                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n;
+    const int32_t* rp;
+    const int32_t* ci;
+    const float* va;
+} csr32_t;
+
+/* y := A x in binary32, rows in stored order from 0.0f. */
+static void spmv32(const csr32_t* A, const float* x, float* y)
+{
+    PAR for (int32_t i = 0; i < A->n; ++i) {
+        float acc = 0.0f;
+        for (int32_t k = A->rp[i]; k < A->rp[i + 1]; ++k) acc = acc + A->va[k] * x[A->ci[k]];
+        y[i] = acc;
+    }
+    g_ctr.spmv++;
+}
+
+/* y := A x in binary64 for a binary32 x (widened exactly). */
+static void spmv_wide(const csr_t* A, const float* x, double* y)
+{
+    PAR for (int32_t i = 0; i < A->n; ++i) {
+        double acc = 0.0;
+        for (int32_t k = A->rp[i]; k < A->rp[i + 1]; ++k) acc = acc + A->va[k] * (double)x[A->ci[k]];
+        y[i] = acc;
+    }
+    g_ctr.spmv++;
+}
+
+static float pairwise32(const float* a, int64_t len)
+{
+    if (len == 1) return a[0];
+    return pairwise32(a, len / 2) + pairwise32(a + len / 2, len / 2);
+}
+
+static float pairwise32_par(const float* a, int64_t len)
+{
+    if (len < (1 << 16)) return pairwise32(a, len);
+    float part[64];
+    const int64_t bl = len / 64;
+    PAR for (int b = 0; b < 64; ++b) part[b] = pairwise32(a + b * bl, bl);
+    return pairwise32(part, 64);
+}
+
+/* (x, y) in binary32, pairwise, widened to binary64. */
+static double dot32_ws(int64_t n, const float* x, const float* y, float* prod)
+{
+    const int64_t len = pow2_at_least(n);
+    PAR for (int64_t i = 0; i < len; ++i) prod[i] = (i < n) ? x[i] * y[i] : 0.0f;
+    return (double)(pairwise32_par(prod, len) + 0.0f);
+}
+
+double or_dot32(int64_t n, const float* x, const float* y)
+{
+    if (n <= 0) return 0.0;
+    float* prod = (float*)malloc(sizeof(float) * (size_t)pow2_at_least(n));
+    if (!prod) return NAN;
+    double s = dot32_ws(n, x, y, prod);
+    free(prod);
+    return s;
+}
+
+void or_spmv32(int32_t n, const int32_t* rp, const int32_t* ci, const float* va, const float* x, float* y)
+{
+    csr32_t A = {n, rp, ci, va};
+    spmv32(&A, x, y);
+}
+
+/* periodic replacement in iteration i: (i+1) mod k == 0, at most rr_max of them */
+static int rr_due_periodic(const or_opts* o, int32_t i)
+{
+    if (o->rr_period <= 0 || (i + 1) % o->rr_period != 0) return 0;
+    return (o->rr_max < 0) || ((i + 1) / o->rr_period <= o->rr_max);
+}
+
+#define NEWV32(p) do { (p) = (float*)calloc((size_t)n, sizeof(float)); if (!(p)) goto oom; } while (0)
+#define DOT32(a, b) dot32_ws(n, (a), (b), prod32)
+
+static int pbicgstab_mp(const csr_t* A, const double* b, double* x, const or_opts* o, or_info* info)
+{
+    const int32_t n = A->n;
+    float *va32 = 0, *r0 = 0, *r = 0, *w = 0, *t = 0, *p = 0, *s = 0, *z = 0, *v = 0, *q = 0, *y = 0;
+    float* prod32 = 0;
+    double *r64 = 0, *w64 = 0, *tmp = 0, *prod = 0;
+    const int64_t nnz = A->rp[n];
+    va32 = (float*)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!va32) goto oom;
+    for (int64_t k = 0; k < nnz; ++k) va32[k] = (float)A->va[k];
+    csr32_t A32 = {n, A->rp, A->ci, va32};
+    NEWV32(r0); NEWV32(r); NEWV32(w); NEWV32(t); NEWV32(p); NEWV32(s); NEWV32(z); NEWV32(v);
+    NEWV32(q); NEWV32(y);
+    NEWVEC(r64); NEWVEC(w64); NEWVEC(tmp);
+    prod32 = (float*)malloc(sizeof(float) * (size_t)pow2_at_least(n));
+    prod = (double*)malloc(sizeof(double) * (size_t)pow2_at_least(n));
+    if (!prod32 || !prod) goto oom;
+
+    info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
+    /* setup as a replacement: r_0 = f(b - A x_0), w_0 = f(A (b - A x_0)) */
+    spmv(A, x, tmp);
+    PAR for (int32_t j = 0; j < n; ++j) r64[j] = b[j] - tmp[j];
+    PAR for (int32_t j = 0; j < n; ++j) { r0[j] = (float)r64[j]; r[j] = r0[j]; }
+    double gamma = DOT32(r0, r0);
+    const double rho0 = sqrt(gamma);
+    if (o->history) o->history[0] = 1.0;
+    if (!isfinite(rho0)) { info->status = OR_NONFINITE; goto done; }
+    if (rho0 == 0.0) { info->status = OR_SUCCESS; info->relres_rec = 0.0; goto done; }
+    spmv(A, r64, w64);
+    PAR for (int32_t j = 0; j < n; ++j) w[j] = (float)w64[j];
+    spmv32(&A32, w, t);
+    double delta = DOT32(r0, w);
+    if (!isfinite(delta)) { info->status = OR_NONFINITE; goto done; }
+    if (delta == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+    double alpha = gamma / delta, beta = 0.0, omega = 0.0;
+    if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
+    int rr_pending = 0;
+    int32_t n_rr = 0;
+
+    for (int32_t i = 0; i < o->maxit; ++i) {
+        const float af = (float)alpha, bf = (float)beta, wf = (float)omega;
+        /* l.4: p_i := r_i + beta (p_{i-1} - omega s_{i-1}) */
+        PAR for (int32_t j = 0; j < n; ++j) p[j] = r[j] + bf * (p[j] - wf * s[j]);
+        if (rr_pending) {
+            /* replacement, second half, in binary64: s = f(A p), z = f(A (A p)) */
+            spmv_wide(A, p, r64);
+            PAR for (int32_t j = 0; j < n; ++j) s[j] = (float)r64[j];
+            spmv(A, r64, w64);
+            PAR for (int32_t j = 0; j < n; ++j) z[j] = (float)w64[j];
+            rr_pending = 0;
+        } else {
+            /* l.5-6: s_i, z_i from the old s, z, v */
+            PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + bf * (s[j] - wf * z[j]);
+            PAR for (int32_t j = 0; j < n; ++j) z[j] = t[j] + bf * (z[j] - wf * v[j]);
+        }
+        /* l.7-8: q_i := r_i - alpha s_i ; y_i := w_i - alpha z_i */
+        PAR for (int32_t j = 0; j < n; ++j) { q[j] = r[j] - af * s[j]; y[j] = w[j] - af * z[j]; }
+        double th1 = DOT32(q, y), th2 = DOT32(y, y);
+        /* l.10: v_i := A z_i */
+        spmv32(&A32, z, v);
+        if (!isfinite(th1) || !isfinite(th2)) { info->status = OR_NONFINITE; goto done; }
+        if (th2 == 0.0) {
+            PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * (double)p[j];
+            info->iters = i + 1; info->relres_rec = 0.0; info->status = OR_SUCCESS;
+            if (o->history) o->history[i + 1] = 0.0;
+            goto done;
+        }
+        omega = th1 / th2;
+        if (!isfinite(omega)) { info->status = OR_NONFINITE; goto done; }
+        const float wn = (float)omega;
+        /* l.13 in binary64: x_{i+1} := x_i + alpha p_i + omega q_i */
+        PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * (double)p[j] + omega * (double)q[j];
+        /* l.14-15: r_{i+1} := q_i - omega y_i ; w_{i+1} := y_i - omega (t_i - alpha v_i) */
+        PAR for (int32_t j = 0; j < n; ++j) {
+            r[j] = q[j] - wn * y[j];
+            w[j] = y[j] - wn * (t[j] - af * v[j]);
+        }
+        info->iters = i + 1;
+        int replaced = 0;
+        for (;;) {
+            if (!replaced && rr_due_periodic(o, i)) replaced = 1;
+            if (replaced == 1 || replaced == 3) {
+                /* replacement, first half, in binary64 */
+                spmv(A, x, tmp);
+                PAR for (int32_t j = 0; j < n; ++j) r64[j] = b[j] - tmp[j];
+                PAR for (int32_t j = 0; j < n; ++j) r[j] = (float)r64[j];
+                spmv(A, r64, w64);
+                PAR for (int32_t j = 0; j < n; ++j) w[j] = (float)w64[j];
+                rr_pending = 1;
+                ++n_rr;
+                info->n_rr = n_rr;
+                replaced = (replaced == 3) ? 4 : 2;  /* 4: forced; no second stop test */
+            }
+            /* l.16: (r0,r), (r0,w), (r0,s), (r0,z) and ||r||^2 */
+            double gamma1 = DOT32(r0, r), eta = DOT32(r0, w), sig_s = DOT32(r0, s), sig_z = DOT32(r0, z);
+            double nu = DOT32(r, r);
+            if (!isfinite(gamma1) || !isfinite(eta) || !isfinite(sig_s) || !isfinite(sig_z) || !isfinite(nu)) {
+                info->status = OR_NONFINITE; goto done;
+            }
+            info->relres_rec = sqrt(nu) / rho0;
+            if (o->history) o->history[i + 1] = info->relres_rec;
+            if (o->scalars) { o->scalars[3 * i] = alpha; o->scalars[3 * i + 1] = omega; }
+            if (info->relres_rec <= o->tol && replaced != 4) {
+                /* confirm with the binary64 true residual */
+                spmv(A, x, tmp);
+                PAR for (int32_t j = 0; j < n; ++j) r64[j] = b[j] - tmp[j];
+                const double tr = sqrt(DOT(r64, r64)) / rho0;
+                if (tr <= o->tol) { info->status = OR_SUCCESS; goto done; }
+                replaced = 3;  /* not converged: replace now and reduce again */
+                continue;
+            }
+            /* l.17: t_{i+1} := A w_{i+1} */
+            spmv32(&A32, w, t);
+            /* l.18-20: beta_i ; alpha_{i+1} by eq. (3) */
+            if (omega == 0.0 || gamma == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+            beta = (alpha / omega) * (gamma1 / gamma);
+            if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }
+            if (o->scalars) o->scalars[3 * i + 2] = beta;
+            double den = eta + beta * sig_s - beta * omega * sig_z;
+            if (den == 0.0 || gamma1 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+            alpha = gamma1 / den;
+            if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
+            gamma = gamma1;
+            break;
+        }
+    }
+    info->status = OR_MAXIT;
+done:
+    finish(A, b, x, rho0, tmp, prod, info);
+    free(va32); free(r0); free(r); free(w); free(t); free(p); free(s); free(z); free(v); free(q); free(y);
+    free(prod32); free(r64); free(w64); free(tmp); free(prod);
+    return info->status;
+oom:
+    free(va32); free(r0); free(r); free(w); free(t); free(p); free(s); free(z); free(v); free(q); free(y);
+    free(prod32); free(r64); free(w64); free(tmp); free(prod);
+    return OR_ERR_ALLOC;
+}
+
+/* Entry point of the precision form (no preconditioner argument: a
+ * preconditioned solve passes A M^{-1} formed).  Arguments as or_solve. */
+int or_solve_mp(int32_t n, const int32_t* rp, const int32_t* ci, const double* va,
+                const double* b, double* x, double tol, int32_t maxit, int32_t rr_period, int32_t rr_max,
+                double* history, double* scalars, int32_t* ints_out, double* dbl_out)
+{
+    if (n <= 0 || !rp || !ci || !va || !b || !x || maxit < 0 || !(tol >= 0.0) || rr_period < 0)
+        return OR_ERR_INVALID_ARG;
+    csr_t A = {n, rp, ci, va};
+    or_opts o = {tol, maxit, rr_period, rr_max, history, scalars};
+    or_info info = {0, 0, 0, 0.0, 0.0};
+    int st = pbicgstab_mp(&A, b, x, &o, &info);
+    if (st < 0) return st;
+    ints_out[0] = info.iters; ints_out[1] = info.n_rr; ints_out[2] = info.status;
+    dbl_out[0] = info.relres_rec; dbl_out[1] = info.relres_true;
+    return st;
 }
 
 /*
