@@ -67,13 +67,24 @@ enum { PBCGS_BICGSTAB = 0, PBCGS_PBICGSTAB = 1, PBCGS_PBICGSTAB_RR = 2 };
  * form moves fewer vectors per iteration (no hatted copies).  With a stencil
  * it needs a constant diagonal (ERR_UNSUPPORTED otherwise). */
 enum { PBCGS_PRECOND_NONE = 0, PBCGS_PRECOND_JACOBI = 1, PBCGS_PRECOND_JACOBI_FOLDED = 2 };
-enum { PBCGS_FP64 = 0 };
+/* Precision.  FP64: every operation in binary64.  FP32_RR64 (precision form,
+ * p-BiCGStab with residual replacement only, preconditioner NONE or
+ * JACOBI_FOLDED): binary32 vectors, SpMV on the operator rounded to binary32,
+ * recurrences and dot products (binary32 pairwise sums); binary64 residual
+ * replacement (Section 4.2: r = b - A x, w = A r, s = A p, z = A s, each
+ * rounded once when stored), x update and alpha, beta, omega.  The setup is a
+ * replacement.  When the binary32 recursive residual passes tol, the binary64
+ * true residual ||b - A x|| / ||r_0|| decides: SUCCESS if it is below tol too,
+ * otherwise a replacement in that iteration and the iteration goes on.
+ * rr_period = 0 leaves only those confirmation replacements.  CSR operators
+ * need nnz floats of context-owned workspace (plus nnz doubles when folded). */
+enum { PBCGS_FP64 = 0, PBCGS_FP32_RR64 = 1 };
 
 /* Solver options (host struct). */
 typedef struct {
     int32_t variant;     /* PBCGS_BICGSTAB, PBCGS_PBICGSTAB or PBCGS_PBICGSTAB_RR          */
     int32_t precond;     /* PBCGS_PRECOND_NONE, _JACOBI or _JACOBI_FOLDED                  */
-    int32_t precision;   /* PBCGS_FP64                                                      */
+    int32_t precision;   /* PBCGS_FP64 or PBCGS_FP32_RR64                                   */
     int32_t maxit;       /* iteration budget, >= 0                                          */
     double tol;          /* relative tolerance on the recursive residual, >= 0              */
     int32_t rr_period;   /* k: replace in iteration i when (i+1) mod k == 0; 0 = never      */

@@ -18,7 +18,7 @@ ERR_INVALID_ARG, ERR_ALLOC, ERR_HIP, ERR_UNSUPPORTED = -1, -2, -3, -4
 
 BICGSTAB, PBICGSTAB, PBICGSTAB_RR = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_JACOBI_FOLDED = 0, 1, 2
-FP64 = 0
+FP64, FP32_RR64 = 0, 1
 
 FLAG_DIRECT = 1       # launch kernels directly instead of replaying a HIP graph
 FLAG_TIME_KERNELS = 2  # time the two fused kernels of each iteration with events

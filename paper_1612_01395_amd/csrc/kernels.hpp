@@ -44,7 +44,9 @@ constexpr int kMaxR = 64;                 // 64-row blocks per wave
 constexpr int kMaxG = 1024;               // workgroups of a producing kernel
 constexpr int kChunk = kMaxG / kWG;       // partials per thread when consuming
 
-enum : int32_t { DS_RUNNING = 0, DS_SUCCESS = 1, DS_BREAKDOWN = 2, DS_NONFINITE = 3 };
+// DS_CHECK (precision form only): the binary32 recursive residual passed tol;
+// the host confirms with the binary64 true residual before declaring SUCCESS.
+enum : int32_t { DS_RUNNING = 0, DS_SUCCESS = 1, DS_BREAKDOWN = 2, DS_NONFINITE = 3, DS_CHECK = 4 };
 
 // Device-resident solver state: scalars of the method and the status word.
 struct alignas(128) DevState {
@@ -65,10 +67,12 @@ struct alignas(128) DevState {
 // ---------------------------------------------------------------------------
 // Operators: apply one row of y = A x, summing in ascending column order.
 // ---------------------------------------------------------------------------
-struct CsrOp {
+template <class V>
+struct CsrOpT {
+  using Val = V;
   const int32_t* __restrict__ rp;
   const int32_t* __restrict__ ci;
-  const double* __restrict__ va;
+  const V* __restrict__ va;
   int32_t n;
 
   static constexpr int kStage = 512;  // staged non-zeros per wave and round
@@ -78,9 +82,11 @@ struct CsrOp {
   // non-zeros are contiguous in CSR, so the wave loads them with coalesced
   // loads, multiplies by the gathered x and stages the products in LDS
   // (CSR-stream); each lane then adds its own row's products in stored order,
-  // starting from 0.0 -- the same operations as a row-by-row loop.
-  __device__ __forceinline__ double spmv(int32_t row, bool valid, const double* __restrict__ x) const {
-    __shared__ double stage[4][kStage];
+  // starting from 0.0 -- the same operations as a row-by-row loop.  V is the
+  // arithmetic type of the product; x (type X) is widened to it first.
+  template <class X>
+  __device__ __forceinline__ V spmv(int32_t row, bool valid, const X* __restrict__ x) const {
+    __shared__ V stage[4][kStage];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t b0 = __builtin_amdgcn_readfirstlane(row);  // lane 0: first row of the block
     const int32_t rc = min(row, n - 1);  // clamped: the four loads issue together
@@ -89,7 +95,7 @@ struct CsrOp {
     const int32_t rb0 = rp[rc], re0 = rp[rc + 1];
     const int32_t rb = valid ? rb0 : rhi;
     const int32_t re = valid ? re0 : rhi;
-    double acc = 0.0;
+    V acc = V(0);
     for (int32_t c0 = rlo; c0 < rhi; c0 += kStage) {
       const int32_t c1 = min(c0 + kStage, rhi);
       // branch-free: indices past the chunk are clamped into it (their
@@ -98,7 +104,7 @@ struct CsrOp {
       // so that they do not evict the Krylov vectors, which the next kernel
       // reads again, from L2 and the Infinity Cache.
       int32_t cc[kStage / 64];
-      double vv[kStage / 64];
+      V vv[kStage / 64];
 #pragma unroll
       for (int u = 0; u < kStage / 64; ++u) {
         const int32_t k = min(c0 + u * 64 + lane, c1 - 1);
@@ -106,7 +112,7 @@ struct CsrOp {
         vv[u] = __builtin_nontemporal_load(&va[k]);
       }
 #pragma unroll
-      for (int u = 0; u < kStage / 64; ++u) stage[wave][u * 64 + lane] = vv[u] * x[cc[u]];
+      for (int u = 0; u < kStage / 64; ++u) stage[wave][u * 64 + lane] = vv[u] * V(x[cc[u]]);
       __builtin_amdgcn_wave_barrier();
       const int32_t kb = max(rb, c0), ke = min(re, c1);
       for (int32_t k = kb; k < ke; ++k) acc = acc + stage[wave][k - c0];
@@ -116,46 +122,52 @@ struct CsrOp {
   }
 
   // One row by itself (utility kernels).
-  __device__ __forceinline__ double apply(int32_t row, const double* __restrict__ x) const {
+  template <class X>
+  __device__ __forceinline__ V apply(int32_t row, const X* __restrict__ x) const {
     const int32_t e = rp[row + 1];
-    double acc = 0.0;
+    V acc = V(0);
     for (int32_t k = rp[row]; k < e; ++k)
-      acc = acc + __builtin_nontemporal_load(&va[k]) * x[__builtin_nontemporal_load(&ci[k])];
+      acc = acc + __builtin_nontemporal_load(&va[k]) * V(x[__builtin_nontemporal_load(&ci[k])]);
     return acc;
   }
 };
+using CsrOp = CsrOpT<double>;
+using CsrOp32 = CsrOpT<float>;
 
 // Constant-coefficient 5-point (nz == 1) or 7-point stencil, Dirichlet
 // boundaries; c[] in ascending column order, so the result equals the CSR
 // product of the assembled matrix bit for bit.
-template <int NPTS>
+template <int NPTS, class V = double>
 struct StencilOp {
+  using Val = V;
   int32_t nx, ny, nz, pad;
-  double c[NPTS];
-  __device__ __forceinline__ double spmv(int32_t row, bool valid, const double* __restrict__ x) const {
-    return valid ? apply(row, x) : 0.0;
+  V c[NPTS];
+  template <class X>
+  __device__ __forceinline__ V spmv(int32_t row, bool valid, const X* __restrict__ x) const {
+    return valid ? apply(row, x) : V(0);
   }
-  __device__ __forceinline__ double apply(int32_t row, const double* __restrict__ x) const {
+  template <class X>
+  __device__ __forceinline__ V apply(int32_t row, const X* __restrict__ x) const {
     const int32_t i = row % nx;
     const int32_t jk = row / nx;
-    double acc = 0.0;
+    V acc = V(0);
     if (NPTS == 7) {
       const int32_t j = jk % ny, k = jk / ny;
       const int32_t nxy = nx * ny;
-      if (k > 0) acc = acc + c[0] * x[row - nxy];
-      if (j > 0) acc = acc + c[1] * x[row - nx];
-      if (i > 0) acc = acc + c[2] * x[row - 1];
-      acc = acc + c[3] * x[row];
-      if (i < nx - 1) acc = acc + c[4] * x[row + 1];
-      if (j < ny - 1) acc = acc + c[5] * x[row + nx];
-      if (k < nz - 1) acc = acc + c[6] * x[row + nxy];
+      if (k > 0) acc = acc + c[0] * V(x[row - nxy]);
+      if (j > 0) acc = acc + c[1] * V(x[row - nx]);
+      if (i > 0) acc = acc + c[2] * V(x[row - 1]);
+      acc = acc + c[3] * V(x[row]);
+      if (i < nx - 1) acc = acc + c[4] * V(x[row + 1]);
+      if (j < ny - 1) acc = acc + c[5] * V(x[row + nx]);
+      if (k < nz - 1) acc = acc + c[6] * V(x[row + nxy]);
     } else {
       const int32_t j = jk;
-      if (j > 0) acc = acc + c[0] * x[row - nx];
-      if (i > 0) acc = acc + c[1] * x[row - 1];
-      acc = acc + c[2] * x[row];
-      if (i < nx - 1) acc = acc + c[3] * x[row + 1];
-      if (j < ny - 1) acc = acc + c[4] * x[row + nx];
+      if (j > 0) acc = acc + c[0] * V(x[row - nx]);
+      if (i > 0) acc = acc + c[1] * V(x[row - 1]);
+      acc = acc + c[2] * V(x[row]);
+      if (i < nx - 1) acc = acc + c[3] * V(x[row + 1]);
+      if (j < ny - 1) acc = acc + c[4] * V(x[row + nx]);
     }
     return acc;
   }
@@ -174,7 +186,7 @@ struct Args {
   int32_t R;              // 64-row blocks per wave (power of two <= kMaxR)
   int32_t Gin;            // partials to consume (workgroups of the producer)
   int32_t first;          // first iteration: consume the setup reduction
-  int32_t pad_;
+  int32_t mode;           // precision form: 1 = reduction after a forced replacement
   const DevState* sin;    // state read by this launch
   DevState* sout;         // state written by workgroup 0
   const double* pin;      // partials consumed: pin[k * kMaxG + wg]
@@ -186,6 +198,9 @@ struct Args {
   double *p, *q, *qh, *y;                                       // BiCGStab
   const double* dinv;
   double dinv_s;
+  // precision form: binary32 vectors and binary64 replacement scratch
+  float *r0f, *rf, *wf, *tf, *pf, *sf, *zf, *vf;
+  double *r64, *s64;
 };
 
 template <int PC>
@@ -208,33 +223,44 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+template <int CTRL, int ROW_MASK, class T>
+__device__ __forceinline__ T dpp_t(T v) {
+  if constexpr (sizeof(T) == 8) return dpp_f64<CTRL, ROW_MASK>(v);
+  else return dpp_f32<CTRL, ROW_MASK>(v);
+}
+
 // Balanced-tree sum over the 64 lanes of a wave; the result is valid in lane
 // 63.  Level m adds to the last lane of every aligned block of 2m lanes the
 // sum held by the last lane of the block's left half (row_shr 1, 2, 4, 8,
 // then row_bcast 15 and 31 across the 16-lane rows), so lane 63 ends with
 // ((l0 + l1) + (l2 + l3)) + ... exactly as the pairwise order prescribes.
-template <int ND>
-__device__ __forceinline__ void wave_sum63(double (&v)[ND]) {
+template <int ND, class T>
+__device__ __forceinline__ void wave_sum63(T (&v)[ND]) {
 #pragma unroll
-  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x111, 0xF>(v[k]);
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_t<0x111, 0xF>(v[k]);
 #pragma unroll
-  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x112, 0xF>(v[k]);
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_t<0x112, 0xF>(v[k]);
 #pragma unroll
-  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x114, 0xF>(v[k]);
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_t<0x114, 0xF>(v[k]);
 #pragma unroll
-  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x118, 0xF>(v[k]);
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_t<0x118, 0xF>(v[k]);
 #pragma unroll
-  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x142, 0xA>(v[k]);
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_t<0x142, 0xA>(v[k]);
 #pragma unroll
-  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_f64<0x143, 0xC>(v[k]);
+  for (int k = 0; k < ND; ++k) v[k] = v[k] + dpp_t<0x143, 0xC>(v[k]);
 }
 
 // Balanced-tree sum of one value per thread over the workgroup (256 threads,
 // 4 waves); every thread receives the totals.
-template <int ND>
-__device__ __forceinline__ void wg_sum_all(double (&v)[ND], double (&out)[ND]) {
-  __shared__ double lw[4][ND];
-  wave_sum63<ND>(v);
+template <int ND, class T>
+__device__ __forceinline__ void wg_sum_all(T (&v)[ND], T (&out)[ND]) {
+  __shared__ T lw[4][ND];
+  wave_sum63<ND, T>(v);
   if ((threadIdx.x & 63) == 63) {
 #pragma unroll
     for (int k = 0; k < ND; ++k) lw[threadIdx.x >> 6][k] = v[k];
@@ -246,18 +272,20 @@ __device__ __forceinline__ void wg_sum_all(double (&v)[ND], double (&out)[ND]) {
 }
 
 // Totals of the Gin partials of each of the ND sums in pin, in pairwise
-// order, "+ 0.0"; identical in every thread of every workgroup.
-template <int ND>
-__device__ __forceinline__ void gather_sums(const Args& a, double (&tot)[ND]) {
+// order, "+ 0.0"; identical in every thread of every workgroup.  T is the
+// arithmetic type of the sums (binary32 partials are stored widened, exactly);
+// the totals are returned widened to binary64.
+template <int ND, class T = double>
+__device__ __forceinline__ void gather_sums(const Args& a, double (&res)[ND]) {
   const int base = (int)threadIdx.x * kChunk;
-  double v[ND];
+  T v[ND], tot[ND];
 #pragma unroll
   for (int k = 0; k < ND; ++k) {
-    double c[kChunk];
+    T c[kChunk];
 #pragma unroll
     for (int j = 0; j < kChunk; ++j) {
-      const double p = a.pin[k * kMaxG + min(base + j, a.Gin - 1)];  // clamped: branch-free
-      c[j] = (base + j < a.Gin) ? p : 0.0;
+      const T p = T(a.pin[k * kMaxG + min(base + j, a.Gin - 1)]);  // clamped: branch-free
+      c[j] = (base + j < a.Gin) ? p : T(0);
     }
 #pragma unroll
     for (int w = 1; w < kChunk; w <<= 1) {
@@ -266,29 +294,29 @@ __device__ __forceinline__ void gather_sums(const Args& a, double (&tot)[ND]) {
     }
     v[k] = c[0];
   }
-  wg_sum_all<ND>(v, tot);
+  wg_sum_all<ND, T>(v, tot);
 #pragma unroll
-  for (int k = 0; k < ND; ++k) tot[k] = tot[k] + 0.0;
+  for (int k = 0; k < ND; ++k) res[k] = double(tot[k] + T(0));
 }
 
 // The workgroup's rows with ND products each; writes its partial sums to
 // pout[k][blockIdx.x].  Body(row, valid, d) is called by all 64 lanes of a
 // block (so an operator may work on the block cooperatively); lanes with
 // valid == false (rows past n) must leave d at 0 and touch no vector.
-template <int ND, class Body>
+template <int ND, class T = double, class Body>
 __device__ __forceinline__ void produce(const Args& a, Body body) {
-  __shared__ double blk[ND][kWG];
+  __shared__ T blk[ND][kWG];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t wbase = ((int64_t)blockIdx.x * 4 + wave) * a.R * 64;
   for (int j = 0; j < a.R; ++j) {
     const int64_t b0 = wbase + (int64_t)j * 64;
-    double d[ND];
+    T d[ND];
 #pragma unroll
-    for (int k = 0; k < ND; ++k) d[k] = 0.0;
+    for (int k = 0; k < ND; ++k) d[k] = T(0);
     if (b0 < a.n) {
       const int32_t row = (int32_t)(b0 + lane);
       body(row, row < a.n, d);
-      wave_sum63<ND>(d);
+      wave_sum63<ND, T>(d);
     }
     if (lane == 63) {
 #pragma unroll
@@ -296,13 +324,13 @@ __device__ __forceinline__ void produce(const Args& a, Body body) {
     }
   }
   __syncthreads();
-  double v[ND], tot[ND];
+  T v[ND], tot[ND];
 #pragma unroll
-  for (int k = 0; k < ND; ++k) v[k] = ((int)threadIdx.x < 4 * a.R) ? blk[k][threadIdx.x] : 0.0;
-  wg_sum_all<ND>(v, tot);
+  for (int k = 0; k < ND; ++k) v[k] = ((int)threadIdx.x < 4 * a.R) ? blk[k][threadIdx.x] : T(0);
+  wg_sum_all<ND, T>(v, tot);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < ND; ++k) a.pout[k * kMaxG + blockIdx.x] = tot[k];
+    for (int k = 0; k < ND; ++k) a.pout[k * kMaxG + blockIdx.x] = double(tot[k]);
   }
 }
 
@@ -829,6 +857,286 @@ __global__ __launch_bounds__(kWG) void k_finish(Args a) {
     else fin_setup_gamma(st, a.hist, g[0]);
   }
   publish(a, st);
+}
+
+// ===========================================================================
+// Precision form of Algorithm 9 with residual replacement: binary32 vectors,
+// SpMV (on the operator rounded to binary32), recurrences and dot products
+// (binary32 pairwise sums); binary64 replacement steps on the binary64
+// operator, x update and scalars alpha, beta, omega.  Vector updates use the
+// scalars rounded to binary32.  The setup is a replacement: r_0 = f(b - A x_0),
+// w_0 = f(A (b - A x_0)) with f the rounding to binary32.  When the recursive
+// residual passes tol the status becomes DS_CHECK and the host confirms with
+// the binary64 true residual (Section 4.2 supplies the replacement that
+// continues the iteration when it is not yet below tol).
+// ===========================================================================
+
+// Reduction 2 of the precision form.  recheck: the reduction that follows a
+// forced replacement -- it neither counts an iteration nor tests convergence.
+__device__ __forceinline__ void fin_pipe_b_mp(State& s, double* hist, const double (&d)[5], bool recheck) {
+  const double g1 = d[0], eta = d[1], sig_s = d[2], sig_z = d[3], nu = d[4];
+  if (!recheck) s.iters += 1;
+  if (!finite(g1) || !finite(eta) || !finite(sig_s) || !finite(sig_z) || !finite(nu)) {
+    s.status = DS_NONFINITE;
+    return;
+  }
+  const double relres = sqrt(nu) / s.rho0;
+  s.relres = relres;
+  if (hist && leader()) hist[s.iters] = relres;
+  if (!recheck && relres <= s.tol) { s.status = DS_CHECK; return; }
+  const double alpha = s.alpha, omega = s.omega, gamma = s.gamma;
+  if (omega == 0.0 || gamma == 0.0) { s.status = DS_BREAKDOWN; return; }
+  const double beta = (alpha / omega) * (g1 / gamma);
+  if (!finite(beta)) { s.status = DS_NONFINITE; return; }
+  s.beta = beta;
+  const double den = eta + beta * sig_s - beta * omega * sig_z;
+  if (den == 0.0 || g1 == 0.0) { s.status = DS_BREAKDOWN; return; }
+  const double an = g1 / den;
+  if (!finite(an)) { s.status = DS_NONFINITE; return; }
+  s.alpha = an;
+  s.gamma = g1;
+}
+
+// Setup 1: r64 = b - A x0 (binary64) ; r0 = r = f(r64) ; p = s = z = v = 0 ;
+// partials of (r0, r0) in binary32.
+template <class Op64>
+__global__ __launch_bounds__(kWG) void k_mp_setup_r0(Op64 op, Args a) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  produce<1, float>(a, [&](int32_t row, bool valid, float (&d)[1]) {
+    const double ax = op.spmv(row, valid, a.x);
+    if (!valid) return;
+    const double r = a.b[row] - ax;
+    a.r64[row] = r;
+    const float rf = float(r);
+    a.r0f[row] = rf;
+    a.rf[row] = rf;
+    a.pf[row] = 0.0f;
+    a.sf[row] = 0.0f;
+    a.zf[row] = 0.0f;
+    a.vf[row] = 0.0f;
+    d[0] = rf * rf;
+  });
+}
+
+// Setup 2: gamma, rho0 ; w = f(A r64) ; partials of (r0, w).
+template <class Op64>
+__global__ __launch_bounds__(kWG) void k_mp_setup_w0(Op64 op, Args a) {
+  PBCGS_PROLOGUE(st)
+  double g[1];
+  gather_sums<1, float>(a, g);
+  fin_setup_gamma(st, a.hist, g[0]);
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  produce<1, float>(a, [&](int32_t row, bool valid, float (&d)[1]) {
+    const double w = op.spmv(row, valid, a.r64);
+    if (!valid) return;
+    const float wf = float(w);
+    a.wf[row] = wf;
+    d[0] = a.r0f[row] * wf;
+  });
+}
+
+// Phase A: finishes the previous reduction (setup alpha or reduction 2), then
+// t = A w (binary32) and lines 4-8 of Algorithm 9.  RR2: s was replaced by
+// f(A p) already; z = f(A s64) in binary64 instead of the recurrence.
+template <class Op32, class Op64, bool RR2>
+__global__ __launch_bounds__(kWG) void k_mp_pa(Op32 op, Op64 op64, Args a) {
+  PBCGS_PROLOGUE(st)
+  if (!RR2) {
+    if (a.first) {
+      double g[1];
+      gather_sums<1, float>(a, g);
+      fin_setup_alpha(st, g[0]);
+    } else {
+      double g[5];
+      gather_sums<5, float>(a, g);
+      fin_pipe_b_mp(st, a.hist, g, false);
+    }
+  }
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const float af = float(st.alpha), bf = float(st.beta), wf_ = float(st.omega);
+  produce<2, float>(a, [&](int32_t row, bool valid, float (&d)[2]) {
+    const float t = op.spmv(row, valid, a.wf);
+    const double z64 = RR2 ? op64.spmv(row, valid, a.s64) : 0.0;
+    if (!valid) return;
+    const float r = a.rf[row], w = a.wf[row];
+    float s, z;
+    if (RR2) {
+      s = a.sf[row];
+      z = float(z64);
+    } else {
+      const float v = a.vf[row];
+      const float s_old = a.sf[row], z_old = a.zf[row];
+      a.pf[row] = r + bf * (a.pf[row] - wf_ * s_old);
+      s = w + bf * (s_old - wf_ * z_old);
+      z = t + bf * (z_old - wf_ * v);
+      a.sf[row] = s;
+    }
+    const float q = r - af * s;
+    const float y = w - af * z;
+    a.tf[row] = t;
+    a.zf[row] = z;
+    d[0] = q * y;
+    d[1] = y * y;
+  });
+}
+
+// Phase B: omega (binary64) ; v = A z (binary32) ; x += alpha p + omega q in
+// binary64 ; r, w in binary32 ; partials (r0,r), (r0,w), (r0,s), (r0,z), (r,r).
+template <class Op32>
+__global__ __launch_bounds__(kWG) void k_mp_pb(Op32 op, Args a) {
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2, float>(a, g2);
+  const double alpha = st.alpha;
+  const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
+  if (yz) {
+    each_row(a, [&](int32_t row, bool valid) {
+      if (valid) a.x[row] = a.x[row] + alpha * double(a.pf[row]);
+    });
+    return;
+  }
+  if (st.status != DS_RUNNING) return;
+  const double omega = st.omega;
+  const float af = float(alpha), wn = float(omega);
+  produce<5, float>(a, [&](int32_t row, bool valid, float (&d)[5]) {
+    const float v = op.spmv(row, valid, a.zf);
+    if (!valid) return;
+    const float r = a.rf[row], s = a.sf[row], w = a.wf[row], z = a.zf[row];
+    const float q = r - af * s;
+    const float y = w - af * z;
+    const float t = a.tf[row];
+    a.x[row] = a.x[row] + alpha * double(a.pf[row]) + omega * double(q);
+    const float rn = q - wn * y;
+    const float wnew = y - wn * (t - af * v);
+    a.vf[row] = v;
+    a.rf[row] = rn;
+    a.wf[row] = wnew;
+    const float r0 = a.r0f[row];
+    d[0] = r0 * rn;
+    d[1] = r0 * wnew;
+    d[2] = r0 * s;
+    d[3] = r0 * z;
+    d[4] = rn * rn;
+  });
+}
+
+// Replacement iteration, phase B': omega, then only the binary64 x update.
+__global__ __launch_bounds__(kWG) void k_mp_rr_x(Args a) {
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2, float>(a, g2);
+  const double alpha = st.alpha;
+  const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
+  if (yz) {
+    each_row(a, [&](int32_t row, bool valid) {
+      if (valid) a.x[row] = a.x[row] + alpha * double(a.pf[row]);
+    });
+    return;
+  }
+  if (st.status != DS_RUNNING) return;
+  const double omega = st.omega;
+  const float af = float(alpha);
+  each_row(a, [&](int32_t row, bool valid) {
+    if (!valid) return;
+    const float q = a.rf[row] - af * a.sf[row];
+    a.x[row] = a.x[row] + alpha * double(a.pf[row]) + omega * double(q);
+  });
+}
+
+// Replacement, first half: r64 = b - A x (binary64) ; r = f(r64).
+template <class Op64>
+__global__ __launch_bounds__(kWG) void k_mp_rr_r(Op64 op, Args a) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  each_row(a, [&](int32_t row, bool valid) {
+    const double ax = op.spmv(row, valid, a.x);
+    if (!valid) return;
+    const double r = a.b[row] - ax;
+    a.r64[row] = r;
+    a.rf[row] = float(r);
+  });
+}
+
+// w = f(A r64) ; one more replacement ; partials of reduction 2.
+template <class Op64>
+__global__ __launch_bounds__(kWG) void k_mp_rr_w(Op64 op, Args a) {
+  PBCGS_PROLOGUE(st)
+  st.n_rr += 1;
+  publish(a, st);
+  produce<5, float>(a, [&](int32_t row, bool valid, float (&d)[5]) {
+    const double w = op.spmv(row, valid, a.r64);
+    if (!valid) return;
+    const float wf = float(w);
+    a.wf[row] = wf;
+    const float r0 = a.r0f[row], r = a.rf[row];
+    d[0] = r0 * r;
+    d[1] = r0 * wf;
+    d[2] = r0 * a.sf[row];
+    d[3] = r0 * a.zf[row];
+    d[4] = r * r;
+  });
+}
+
+// Iteration after a replacement, first kernel: reduction 2 (a.mode = 1 after
+// a forced replacement), then p = r + beta (p - omega s) in binary32.
+__global__ __launch_bounds__(kWG) void k_mp_rr_p(Args a) {
+  PBCGS_PROLOGUE(st)
+  double g[5];
+  gather_sums<5, float>(a, g);
+  fin_pipe_b_mp(st, a.hist, g, a.mode == 1);
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const float bf = float(st.beta), wf_ = float(st.omega);
+  each_row(a, [&](int32_t row, bool valid) {
+    if (valid) a.pf[row] = a.rf[row] + bf * (a.pf[row] - wf_ * a.sf[row]);
+  });
+}
+
+// Replacement, second half: s64 = A p (binary64, p widened) ; s = f(s64).
+template <class Op64>
+__global__ __launch_bounds__(kWG) void k_mp_rr_s(Op64 op, Args a) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  each_row(a, [&](int32_t row, bool valid) {
+    const double s = op.spmv(row, valid, a.pf);
+    if (!valid) return;
+    a.s64[row] = s;
+    a.sf[row] = float(s);
+  });
+}
+
+// Pending reduction finished by one workgroup: MODE 0 reduction 2 (a.mode as
+// in k_mp_rr_p), 1 the setup alpha.
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_mp_finish(Args a) {
+  PBCGS_PROLOGUE(st)
+  if (MODE == 0) {
+    double g[5];
+    gather_sums<5, float>(a, g);
+    fin_pipe_b_mp(st, a.hist, g, a.mode == 1);
+  } else {
+    double g[1];
+    gather_sums<1, float>(a, g);
+    fin_setup_alpha(st, g[0]);
+  }
+  publish(a, st);
+}
+
+// A solve waiting in DS_CHECK goes on (the host found the true residual above tol).
+__global__ void k_resume(DevState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && st->status == DS_CHECK) st->status = DS_RUNNING;
+}
+
+// Binary32 copy of an operator's values.
+__global__ __launch_bounds__(kWG) void k_round_vals(int64_t nnz, const double* __restrict__ v64,
+                                                    float* __restrict__ v32) {
+  for (int64_t k = (int64_t)blockIdx.x * kWG + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kWG)
+    v32[k] = float(v64[k]);
 }
 
 // ===========================================================================

@@ -34,7 +34,7 @@ struct pbcgs_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  DevState* st = nullptr;   // two state slots (device)
+  DevState* st = nullptr;   // state slots (device): 0, 1 solver ring; 2, 3 utility reductions
   DevState* hst = nullptr;  // pinned host copies for polling (two slots)
   int32_t* flag = nullptr;  // structural error flags of utility kernels
   int32_t* hflag = nullptr; // pinned host copy
@@ -43,6 +43,8 @@ struct pbcgs_ctx_s {
   size_t ws_cap = 0;        // doubles
   double* ahat = nullptr;   // values of A M^{-1} (folded Jacobi, CSR)
   size_t ahat_cap = 0;      // doubles
+  float* a32 = nullptr;     // binary32 operator values (precision form, CSR)
+  size_t a32_cap = 0;       // floats
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
   hipEvent_t ev_poll[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> kev;  // pool for per-kernel timing
@@ -167,6 +169,39 @@ int ensure_ahat(pbcgs_ctx_t ctx, size_t doubles) {
   return PBCGS_SUCCESS;
 }
 
+int ensure_a32(pbcgs_ctx_t ctx, size_t floats) {
+  if (ctx->a32_cap >= floats) return PBCGS_SUCCESS;
+  if (ctx->a32) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->a32);
+    ctx->a32 = nullptr;
+    ctx->a32_cap = 0;
+  }
+  if (hipMalloc(&ctx->a32, std::max<size_t>(floats, 1) * sizeof(float)) != hipSuccess) {
+    ctx->a32 = nullptr;
+    return fail(ctx, PBCGS_ERR_ALLOC, "allocation of " + std::to_string(floats * 4) + " bytes of binary32 values failed");
+  }
+  ctx->a32_cap = floats;
+  return PBCGS_SUCCESS;
+}
+
+// The binary32 twin of an operator: values rounded once.
+CsrOp32 to_binary32(pbcgs_ctx_t ctx, const CsrOp& op, int64_t nnz) {
+  if (nnz > 0) {
+    const int g = (int)std::min<int64_t>((nnz + kWG - 1) / kWG, 8192);
+    k_round_vals<<<g, kWG, 0, ctx->stream>>>(nnz, op.va, ctx->a32);
+  }
+  return CsrOp32{op.rp, op.ci, ctx->a32, op.n};
+}
+template <int NPTS>
+StencilOp<NPTS, float> to_binary32(pbcgs_ctx_t, const StencilOp<NPTS, double>& op, int64_t) {
+  StencilOp<NPTS, float> f;
+  std::memset(&f, 0, sizeof f);
+  f.nx = op.nx; f.ny = op.ny; f.nz = op.nz;
+  for (int k = 0; k < NPTS; ++k) f.c[k] = float(op.c[k]);
+  return f;
+}
+
 size_t padded(int32_t n) { return ((size_t)n + 63) / 64 * 64; }
 
 int read_state(pbcgs_ctx_t ctx, int slot, DevState* out) {
@@ -211,13 +246,13 @@ int finish_sum(pbcgs_ctx_t ctx, const Shape& sh, double* result) {
   Args f = base_args(ctx, sh);
   f.pin = part_buf(ctx, PB_UTIL);
   f.Gin = sh.G;
-  f.sin = ctx->st;
-  f.sout = ctx->st + 1;
-  k_init_state<<<1, 64, 0, ctx->stream>>>(ctx->st, 0.0);
+  f.sin = ctx->st + 2;  // slots 2, 3: utility reductions leave a solve's state alone
+  f.sout = ctx->st + 3;
+  k_init_state<<<1, 64, 0, ctx->stream>>>(ctx->st + 2, 0.0);
   k_finish<3><<<1, kWG, 0, ctx->stream>>>(f);
   HIP_TRY(ctx, hipGetLastError());
   DevState h;
-  int rc = read_state(ctx, 1, &h);
+  int rc = read_state(ctx, 3, &h);
   if (rc != PBCGS_SUCCESS) return rc;
   *result = h.result;
   return PBCGS_SUCCESS;
@@ -241,10 +276,12 @@ int true_relres(pbcgs_ctx_t ctx, const Op& op, const Args& a0, double rho0, doub
 // ---------------------------------------------------------------------------
 // Per-(operator, preconditioner) driver.
 // ---------------------------------------------------------------------------
-template <class Op, int PC>
+// MP: precision form (Op is the binary32 operator, Op64 the binary64 one).
+template <class Op, int PC, class Op64 = Op, bool MP = false>
 struct Driver {
   pbcgs_ctx_t ctx;
   Op op;
+  Op64 op64;
   Args a;
   const pbcgs_opts& o;
   bool timing = false;
@@ -253,8 +290,15 @@ struct Driver {
   int64_t q = 0;  // kernel launches of this solve that passed the state on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[2];
   size_t ev_used = 0;
+  std::vector<int64_t> forced;  // precision form: iterations ended by a forced replacement
 
-  Driver(pbcgs_ctx_t c, Op op_, const Args& a_, const pbcgs_opts& o_) : ctx(c), op(op_), a(a_), o(o_) {}
+  Driver(pbcgs_ctx_t c, Op op_, const Args& a_, const pbcgs_opts& o_) : ctx(c), op(op_), op64(), a(a_), o(o_) {}
+  Driver(pbcgs_ctx_t c, Op op_, Op64 op64_, const Args& a_, const pbcgs_opts& o_)
+      : ctx(c), op(op_), op64(op64_), a(a_), o(o_) {}
+
+  bool was_forced(int64_t i) const { return std::find(forced.begin(), forced.end(), i) != forced.end(); }
+  // iteration i starts with the second half of a replacement
+  bool pending_rr(int64_t i) const { return rr_due(o, i - 1) || (MP && was_forced(i - 1)); }
 
   hipEvent_t next_event() {
     if (ev_used == ctx->kev.size()) {
@@ -278,8 +322,9 @@ struct Driver {
   }
 
   // Arguments of the next launch: state slots by launch parity, partials.
-  Args L(int pin, int pout, bool first = false) {
+  Args L(int pin, int pout, bool first = false, int mode = 0) {
     Args b = a;
+    b.mode = mode;
     b.sin = ctx->st + (q & 1);
     b.sout = ctx->st + ((q + 1) & 1);
     b.pin = pin >= 0 ? part_buf(ctx, pin) : nullptr;
@@ -294,6 +339,11 @@ struct Driver {
 
   void setup() {
     hipStream_t s = ctx->stream;
+    if constexpr (MP) {
+      k_mp_setup_r0<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, PB_SETUP1));
+      k_mp_setup_w0<Op64><<<grid(), kWG, 0, s>>>(op64, L(PB_SETUP1, PB_SETUP2));
+      return;
+    }
     if (o.variant == PBCGS_BICGSTAB) {
       k_setup_r0<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
     } else {
@@ -305,6 +355,26 @@ struct Driver {
   // Kernels of iteration i.
   void iteration(int64_t i) {
     hipStream_t s = ctx->stream;
+    if constexpr (MP) {
+      const bool pending = pending_rr(i), recheck = was_forced(i - 1), rr = rr_due(o, i);
+      if (pending) {
+        k_mp_rr_p<<<grid(), kWG, 0, s>>>(L(PB_B, -1, false, recheck ? 1 : 0));
+        k_mp_rr_s<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, -1));
+        k_mp_pa<Op, Op64, true><<<grid(), kWG, 0, s>>>(op, op64, L(-1, PB_A));
+      } else {
+        timed(0, [&] {
+          k_mp_pa<Op, Op64, false><<<grid(), kWG, 0, s>>>(op, op64, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
+        });
+      }
+      if (rr) {
+        k_mp_rr_x<<<grid(), kWG, 0, s>>>(L(PB_A, -1));
+        k_mp_rr_r<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, -1));
+        k_mp_rr_w<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, PB_B));
+      } else {
+        timed(1, [&] { k_mp_pb<Op><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B)); });
+      }
+      return;
+    }
     if (o.variant == PBCGS_BICGSTAB) {
       timed(0, [&] { k_b1<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_SETUP1, PB_B1, i == 0)); });
       k_b2<PC><<<grid(), kWG, 0, s>>>(L(PB_B1, -1));
@@ -337,12 +407,17 @@ struct Driver {
       q += 5;
       return;
     }
-    q += (rr_due(o, i - 1) ? 3 : 1) + (rr_due(o, i) ? 3 : 1);
+    q += (pending_rr(i) ? 3 : 1) + (rr_due(o, i) ? 3 : 1);
   }
 
   // The reduction left pending by the last kernel, finished by one workgroup.
   void finish(int64_t iters_launched) {
     hipStream_t s = ctx->stream;
+    if constexpr (MP) {
+      if (iters_launched == 0) k_mp_finish<1><<<1, kWG, 0, s>>>(L(PB_SETUP2, -1));
+      else k_mp_finish<0><<<1, kWG, 0, s>>>(L(PB_B, -1, false, was_forced(iters_launched - 1) ? 1 : 0));
+      return;
+    }
     if (o.variant == PBCGS_BICGSTAB) {
       if (iters_launched == 0) k_finish<2><<<1, kWG, 0, s>>>(L(PB_SETUP1, -1));
       return;
@@ -356,11 +431,13 @@ struct Driver {
     char buf[96];
     k.append(reinterpret_cast<const char*>(&a), sizeof(Args));
     k.append(reinterpret_cast<const char*>(&op), sizeof(Op));
-    std::snprintf(buf, sizeof buf, "|%d|%d|%d|%lld|%d|", PC, o.variant, m, (long long)(q & 1), i0 == 0 ? 1 : 0);
+    k.append(reinterpret_cast<const char*>(&op64), sizeof(Op64));
+    std::snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%lld|%d|", PC, MP ? 1 : 0, o.variant, m, (long long)(q & 1),
+                  i0 == 0 ? 1 : 0);
     k += buf;
     for (int j = 0; j < m; ++j) {
       const int64_t i = i0 + j;
-      const int code = (rr_due(o, i - 1) ? 1 : 0) | (rr_due(o, i) ? 2 : 0);
+      const int code = (pending_rr(i) ? 1 : 0) | (rr_due(o, i) ? 2 : 0) | (MP && was_forced(i - 1) ? 4 : 0);
       k += char('0' + code);
     }
     return k;
@@ -417,55 +494,84 @@ struct Driver {
     // are queued past the stop (those see the final status and exit at once).
     int64_t launched = 0;
     int pend[2];
-    int npend = 0, next_slot = 0;
-    bool stop = false;
+    int next_slot = 0;
     double last_rel = 1.0;
     int64_t last_it = 0;
     double rate = 0.0;  // d log(relres) / d iteration, < 0 when converging
-    for (;;) {
-      while (!stop && launched < o.maxit && npend < 2) {
-        int m = (int)std::min<int64_t>(check, o.maxit - launched);
-        if (rate < 0.0 && o.tol > 0.0 && last_rel > 0.0) {
-          const double need = (std::log(o.tol) - std::log(last_rel)) / rate;  // from the last poll
-          const int64_t ahead = launched - last_it;                           // queued since then
-          const int64_t left = (int64_t)std::ceil(need) - ahead;
-          if (left < m) m = (int)std::max<int64_t>(1, left);
-        }
-        int rc = chunk(launched, m, use_graph);
-        if (rc != PBCGS_SUCCESS) return rc;
-        launched += m;
-        HIP_TRY(ctx, hipMemcpyAsync(&ctx->hst[next_slot], ctx->st + (q & 1), sizeof(DevState),
-                                    hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipEventRecord(ctx->ev_poll[next_slot], s));
-        pend[npend++] = next_slot;
-        next_slot ^= 1;
-      }
-      if (npend == 0) break;
-      const int slot = pend[0];
-      pend[0] = pend[1];
-      --npend;
-      HIP_TRY(ctx, hipEventSynchronize(ctx->ev_poll[slot]));
-      const DevState& h = ctx->hst[slot];
-      if (h.status != DS_RUNNING) {
-        stop = true;
-      } else if (h.iters > last_it && h.relres > 0.0 && last_rel > 0.0) {
-        const double r = (std::log(h.relres) - std::log(last_rel)) / (double)(h.iters - last_it);
-        rate = (rate < 0.0) ? 0.5 * (rate + r) : r;
-        last_rel = h.relres;
-        last_it = h.iters;
-      }
-    }
-    finish(launched);
-    HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_stop, s));
     DevState fin;
-    int rc = read_state(ctx, (int)(q & 1), &fin);
-    if (rc != PBCGS_SUCCESS) return rc;
+    for (;;) {  // the precision form comes back here after a forced replacement
+      int npend = 0;
+      bool stop = false;
+      for (;;) {
+        while (!stop && launched < o.maxit && npend < 2) {
+          int m = (int)std::min<int64_t>(check, o.maxit - launched);
+          if (rate < 0.0 && o.tol > 0.0 && last_rel > 0.0) {
+            const double need = (std::log(o.tol) - std::log(last_rel)) / rate;  // from the last poll
+            const int64_t ahead = launched - last_it;                           // queued since then
+            const int64_t left = (int64_t)std::ceil(need) - ahead;
+            if (left < m) m = (int)std::max<int64_t>(1, left);
+          }
+          int rc = chunk(launched, m, use_graph);
+          if (rc != PBCGS_SUCCESS) return rc;
+          launched += m;
+          HIP_TRY(ctx, hipMemcpyAsync(&ctx->hst[next_slot], ctx->st + (q & 1), sizeof(DevState),
+                                      hipMemcpyDeviceToHost, s));
+          HIP_TRY(ctx, hipEventRecord(ctx->ev_poll[next_slot], s));
+          pend[npend++] = next_slot;
+          next_slot ^= 1;
+        }
+        if (npend == 0) break;
+        const int slot = pend[0];
+        pend[0] = pend[1];
+        --npend;
+        HIP_TRY(ctx, hipEventSynchronize(ctx->ev_poll[slot]));
+        const DevState& h = ctx->hst[slot];
+        if (h.status != DS_RUNNING) {
+          stop = true;
+        } else if (h.iters > last_it && h.relres > 0.0 && last_rel > 0.0) {
+          const double r = (std::log(h.relres) - std::log(last_rel)) / (double)(h.iters - last_it);
+          rate = (rate < 0.0) ? 0.5 * (rate + r) : r;
+          last_rel = h.relres;
+          last_it = h.iters;
+        }
+      }
+      finish(launched);
+      HIP_TRY(ctx, hipGetLastError());
+      int rc = read_state(ctx, (int)(q & 1), &fin);
+      if (rc != PBCGS_SUCCESS) return rc;
+      if constexpr (MP) {
+        if (fin.status == DS_CHECK) {
+          // the binary32 recursive residual passed tol: confirm in binary64
+          double tr = 0.0;
+          rc = true_relres(ctx, op64, a, fin.rho0, &tr);
+          if (rc != PBCGS_SUCCESS) return rc;
+          if (tr <= o.tol) {
+            fin.status = DS_SUCCESS;
+            break;
+          }
+          // not yet: replace r, w now and go on (s, z follow in the next iteration)
+          k_resume<<<1, 64, 0, s>>>(ctx->st + (q & 1));
+          k_mp_rr_r<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, -1));
+          k_mp_rr_w<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, PB_B));
+          HIP_TRY(ctx, hipGetLastError());
+          forced.push_back((int64_t)fin.iters - 1);
+          launched = fin.iters;
+          last_it = fin.iters;  // predict the remaining iterations from the true residual
+          last_rel = tr;
+          continue;
+        }
+      }
+      break;
+    }
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_stop, s));
+    HIP_TRY(ctx, hipEventSynchronize(ctx->ev_stop));
+    int rc = PBCGS_SUCCESS;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop);
     rho0 = fin.rho0;
-    if (true_res) {  // true residual of the returned x, same pairwise arithmetic
-      rc = true_relres(ctx, op, a, fin.rho0, &info->relres_true);
+    if (true_res) {  // true residual of the returned x, same pairwise arithmetic (binary64)
+      if constexpr (MP) rc = true_relres(ctx, op64, a, fin.rho0, &info->relres_true);
+      else rc = true_relres(ctx, op, a, fin.rho0, &info->relres_true);
       if (rc != PBCGS_SUCCESS) return rc;
     }
     info->iters = fin.iters;
@@ -553,7 +659,7 @@ int pbcgs_ctx_create(int device, void* hip_stream, pbcgs_ctx_t* out) {
     }
     c->own_stream = true;
   }
-  bool ok = hipMalloc(&c->st, 2 * sizeof(DevState)) == hipSuccess &&
+  bool ok = hipMalloc(&c->st, 4 * sizeof(DevState)) == hipSuccess &&
             hipMalloc(&c->part, sizeof(double) * kMaxD * kMaxG * PB_COUNT) == hipSuccess &&
             hipMalloc(&c->flag, 64) == hipSuccess &&
             hipHostMalloc(&c->hst, 2 * sizeof(DevState), hipHostMallocDefault) == hipSuccess &&
@@ -587,6 +693,7 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
     if (e) (void)hipEventDestroy(e);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->ahat) (void)hipFree(ctx->ahat);
+  if (ctx->a32) (void)hipFree(ctx->a32);
   if (ctx->part) (void)hipFree(ctx->part);
   if (ctx->flag) (void)hipFree(ctx->flag);
   if (ctx->st) (void)hipFree(ctx->st);
@@ -730,7 +837,13 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
       o.precond != PBCGS_PRECOND_JACOBI_FOLDED)
     return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown preconditioner");
   const bool folded = (o.precond == PBCGS_PRECOND_JACOBI_FOLDED);
-  if (o.precision != PBCGS_FP64) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "only FP64 is implemented");
+  if (o.precision != PBCGS_FP64 && o.precision != PBCGS_FP32_RR64)
+    return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown precision");
+  const bool mp = (o.precision == PBCGS_FP32_RR64);
+  if (mp && o.variant != PBCGS_PBICGSTAB_RR)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the binary32 form is p-BiCGStab with residual replacement");
+  if (mp && o.precond == PBCGS_PRECOND_JACOBI)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the binary32 form takes Jacobi as PBCGS_PRECOND_JACOBI_FOLDED");
   if (o.maxit < 0 || !(o.tol >= 0.0)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad maxit or tol");
   if (o.variant == PBCGS_PBICGSTAB_RR && o.rr_period < 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad rr_period");
   if ((const void*)b == (const void*)x) return fail(ctx, PBCGS_ERR_INVALID_ARG, "b and x must not overlap");
@@ -794,6 +907,58 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     a.wh = hat ? v[9] : a.w;
     a.sh = hat ? v[10] : a.s;
     a.zh = hat ? v[11] : a.z;
+  }
+
+  if (mp) {
+    // binary32 vectors, then the binary64 scratch r64, s64
+    float* f32 = reinterpret_cast<float*>(ctx->ws);
+    float** fv[8] = {&a.r0f, &a.rf, &a.wf, &a.tf, &a.pf, &a.sf, &a.zf, &a.vf};
+    for (int k = 0; k < 8; ++k) *fv[k] = f32 + (size_t)k * np;
+    a.r64 = ctx->ws + 4 * np;
+    a.s64 = ctx->ws + 5 * np;
+    const int xg = (A->n + kWG - 1) / kWG;
+    const double* dv = a.dinv;
+    const double ds = a.dinv_s;
+    a.dinv = nullptr;
+    a.dinv_s = 0.0;
+    if (folded && A->kind == OP_CSR) {
+      rc = ensure_ahat(ctx, (size_t)A->nnz);
+      if (rc != PBCGS_SUCCESS) return rc;
+    }
+    if (A->kind == OP_CSR) {
+      rc = ensure_a32(ctx, (size_t)A->nnz);
+      if (rc != PBCGS_SUCCESS) return rc;
+    }
+    return with_op(A, [&](auto op) -> int {
+      using Op = decltype(op);
+      Op op64 = op;
+      if (folded) {
+        if constexpr (std::is_same<Op, CsrOp>::value) {
+          const int fg = (int)std::min<int64_t>((A->nnz + kWG - 1) / kWG, 8192);
+          if (A->nnz > 0) {
+            if (pc == PC_VEC) k_fold_csr<PC_VEC><<<fg, kWG, 0, ctx->stream>>>(op, A->nnz, ctx->ahat, dv, ds);
+            else k_fold_csr<PC_SCALAR><<<fg, kWG, 0, ctx->stream>>>(op, A->nnz, ctx->ahat, dv, ds);
+          }
+          op64.va = ctx->ahat;
+        } else {
+          for (double& c : op64.c) c = c * ds;
+        }
+        if (pc == PC_VEC) k_fold_x<PC_VEC, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+        else k_fold_x<PC_SCALAR, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+      }
+      auto op32 = to_binary32(ctx, op64, A->nnz);
+      HIP_TRY(ctx, hipGetLastError());
+      Driver<decltype(op32), PC_NONE, Op, true> drv(ctx, op32, op64, a, o);
+      drv.true_res = !folded;
+      const int st = drv.run(info);
+      if (st < 0 || !folded) return st;
+      if (pc == PC_VEC) k_fold_x<PC_VEC, false><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+      else k_fold_x<PC_SCALAR, false><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+      HIP_TRY(ctx, hipGetLastError());
+      const int rc2 = true_relres(ctx, op, a, drv.rho0, &info->relres_true);
+      if (rc2 != PBCGS_SUCCESS) return rc2;
+      return st;
+    });
   }
 
   if (folded) {

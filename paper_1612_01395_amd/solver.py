@@ -22,6 +22,9 @@ STATUS = {0: "success", 1: "maxit", 2: "breakdown", 3: "nonfinite"}
 # the same right preconditioning with A M^{-1} formed, Algorithm 7 / 9 run on it.
 PRECONDS = {None: L.PRECOND_NONE, "none": L.PRECOND_NONE, "jacobi": L.PRECOND_JACOBI,
             "jacobi_folded": L.PRECOND_JACOBI_FOLDED}
+# "fp64": every operation in binary64; "fp32_rr64": binary32 vectors, SpMV, recurrences and
+# dot products with binary64 residual replacement, x update and scalars (p-BiCGStab+RR only).
+PRECISIONS = {"fp64": L.FP64, "fp32_rr64": L.FP32_RR64}
 
 
 def _ptr(t: torch.Tensor | None):
@@ -194,12 +197,15 @@ class SolveInfo:
 def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, variant: str = "pbicgstab_rr",
           precond: str | None = None, dinv: torch.Tensor | None = None, tol: float = 1e-8, maxit: int = 2000,
           rr_period: int = 50, rr_max: int = -1, history: bool = False, check_every: int = 0,
-          graph: bool = True, time_kernels: bool = False, out: torch.Tensor | None = None):
+          graph: bool = True, time_kernels: bool = False, out: torch.Tensor | None = None,
+          precision: str = "fp64"):
     """Solve A x = b; returns (x, SolveInfo).  x0 defaults to zero; ``out``
     (optional) receives the iterate in place of a new tensor."""
     _check_vec(b, A.n, "b")
     if variant not in VARIANTS:
         raise ValueError(f"variant must be one of {sorted(VARIANTS)}")
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
     if precond not in PRECONDS:
         raise ValueError(f"precond must be one of {sorted(k for k in PRECONDS if k)} or None")
     if out is not None:
@@ -218,7 +224,7 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
     o = L.Opts()
     o.variant = VARIANTS[variant]
     o.precond = PRECONDS[precond]
-    o.precision = L.FP64
+    o.precision = PRECISIONS[precision]
     o.maxit = int(maxit)
     o.tol = float(tol)
     o.rr_period = int(rr_period)
