@@ -68,7 +68,7 @@ def parse():
     p.add_argument("--n", type=int, default=128, help="grid side of the 3-D workload")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
-    p.add_argument("--only", default="", help="comma list of legs to run: pipe,bicg,explicit,stencil")
+    p.add_argument("--only", default="", help="comma list of legs to run: pipe,bicg,explicit,stencil,precision")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
     return p.parse_args()
@@ -119,7 +119,7 @@ def main():
     dev = torch.device("cuda", 0)
     w = inputs.workload("c2", n=args.n)
     N = w.N
-    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil"}
+    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "precision"}
 
     # ---- inputs resident in HBM -------------------------------------------------
     rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
@@ -194,6 +194,42 @@ def main():
         "other_kernel_avg_us": round(avg[1 - dom] * 1e3, 2),
         "launches_timed": pinfo.kernel_calls[dom],
     }
+
+    # ---- precision form at 256^3 (tol 1e-10): binary32 + binary64 replacement vs binary64
+    precision = None
+    if "precision" in legs:
+        w4 = inputs.workload("c4")
+        rp4, col4, val4 = solver.assemble_convdiff(w4.dim, w4.n, w4.npts, w4.beta)
+        A4 = solver.csr(rp4, col4, val4)
+        b4 = solver.spmv(A4, torch.from_numpy(inputs.x_true(w4.N)).to(dev))
+        x4 = torch.empty_like(b4)
+
+        def leg4(prec, k):
+            kw = dict(variant="pbicgstab_rr", precond="jacobi_folded", tol=w4.tol, maxit=w4.maxit, rr_period=k,
+                      precision=prec, out=x4)
+            solver.solve(A4, b4, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its = 0
+            for _ in range(3):
+                _, inf = solver.solve(A4, b4, **kw)
+                its += inf.iters
+            torch.cuda.synchronize()
+            dt4 = (time.perf_counter() - t0) / 3
+            return {"iters_per_s": round(its / 3 / dt4, 1), "iters_per_solve": inf.iters, "n_rr": inf.n_rr,
+                    "rr_period": k, "ms_per_solve": round(dt4 * 1e3, 2), "relres_true": inf.relres_true,
+                    "status": inf.status}
+
+        f64 = leg4("fp64", 50)
+        x64 = x4.clone()
+        f32 = leg4("fp32_rr64", w4.rr_period)
+        f32["err_vs_fp64_solution"] = (torch.linalg.norm(x4 - x64) / torch.linalg.norm(x64)).item()
+        precision = {"workload": f"3-D 7-point {w4.n}^3 (N={w4.N}, nnz={val4.numel()}), folded Jacobi, "
+                                 f"tol {w4.tol:g}; the binary64 solve equals the oracle's bit for bit",
+                     "fp64": f64, "fp32_rr64": f32,
+                     "time_to_solution_speedup": round(f64["ms_per_solve"] / f32["ms_per_solve"], 4)}
+        del A4, rp4, col4, val4, b4, x4, x64
+        torch.cuda.empty_cache()
 
     if args.copy_calib:
         # a plain copy of known size: 256 MiB read + 256 MiB written per dispatch
@@ -272,6 +308,8 @@ def main():
     for key, variant in (("st_pipe", "pbicgstab"), ("st_bicg", "bicgstab")):
         if key in res:
             out.setdefault("stencil", {})[variant] = leg_summary(key, variant, True, True)
+    if precision is not None:
+        out["precision_form"] = precision
     out["roofline"] = roofline
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

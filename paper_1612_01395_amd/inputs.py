@@ -13,7 +13,8 @@ boundaries, rows ordered x fastest):
 * ``c2``   3-D 7-point, 128^3, beta = (50, 30, 10), Jacobi.
 * ``c3``   3-D 27-point variable coefficient, 256^3, beta = (100, 0, 50),
            log-normal (sigma = 1) cell diffusion, shift +0.1, Jacobi, RR k = 50.
-* ``c4``   3-D 7-point, 256^3, beta = (50, 30, 10), Jacobi (precision form).
+* ``c4``   3-D 7-point, 256^3, beta = (50, 30, 10), Jacobi, tol 1e-10, RR k = 20
+           (precision form).
 * ``c5``   512 independent 2-D 5-point systems, side n_k log-uniform in
            [32, 512], beta_k ~ U[0, 200]^2 (batched form).
 * ``ptp1`` / ``ptp2``  the paper's two parallel test problems (Section 5),
@@ -61,7 +62,7 @@ WORKLOADS = {
     "c3": Workload("c3", 3, 256, 27, (100.0, 0.0, 50.0), shift=0.1,
                    kappa_sigma=1.0, precond="jacobi"),
     "c4": Workload("c4", 3, 256, 7, (50.0, 30.0, 10.0), precond="jacobi",
-                   tol=1e-10),
+                   tol=1e-10, maxit=5000, rr_period=20),
 }
 
 

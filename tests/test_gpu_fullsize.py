@@ -9,6 +9,9 @@ benchmark uses.
   row-by-row assembly, then the whole matrix, the first iterations and the
   complete RR solve (k = 50, tol 1e-8) against the oracle bit for bit, plus
   properties that hold at any size (true residual, error against x_true).
+* 3-D 7-point 256^3 precision form (binary32 + binary64 replacement, folded
+  Jacobi, tol 1e-10, k = 20) and its all-binary64 counterpart, each against
+  the oracle bit for bit; the binary64 true residual below 1e-10.
 """
 
 import time
@@ -150,3 +153,38 @@ def test_c3_first_iterations_bitwise_and_full_solve(c3):
     assert info.n_rr == info.iters // w.rr_period
     err = torch.linalg.norm(x - xt).item() / torch.linalg.norm(xt).item()
     assert err < 1e-5
+
+
+def test_c4_precision_form_bitwise():
+    require_gpu()
+    w = inputs.workload("c4")
+    t0 = time.time()
+    A = oracle.assemble_workload(w)
+    rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
+    assert np.array_equal(host(rp), A.row_ptr) and np.array_equal(host(col), A.col) and same(host(val), A.val)
+    op = solver.csr(rp, col, val)
+    xt = inputs.x_true(A.n)
+    b_or = oracle.spmv(A, xt)
+    b = solver.spmv(op, dev_t(xt))
+    assert same(host(b), b_or)
+    dinv = oracle.jacobi_dinv(A)
+    say(f"c4 assembled {time.time() - t0:.1f}s")
+    t0 = time.time()
+    x_or, i_or = oracle.solve_mp(A, b_or, dinv=dinv, tol=w.tol, maxit=w.maxit, rr_period=w.rr_period)
+    say(f"c4 oracle binary32 form: {i_or['iters']} it, {i_or['n_rr']} RR, {time.time() - t0:.1f}s")
+    x, info = solver.solve(op, b, variant="pbicgstab_rr", precond="jacobi_folded", precision="fp32_rr64",
+                           tol=w.tol, maxit=w.maxit, rr_period=w.rr_period)
+    assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"])
+    assert same(host(x), x_or)
+    assert same([info.relres_rec, info.relres_true], [i_or["relres_rec"], i_or["relres_true"]])
+    assert info.status == 0 and info.relres_true <= w.tol
+    t0 = time.time()
+    x64_or, i64 = oracle.solve_folded(A, b_or, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=w.tol, maxit=w.maxit,
+                                      rr_period=50)
+    say(f"c4 oracle binary64: {i64['iters']} it, {time.time() - t0:.1f}s")
+    x64, info64 = solver.solve(op, b, variant="pbicgstab_rr", precond="jacobi_folded", tol=w.tol, maxit=w.maxit,
+                               rr_period=50)
+    assert (info64.status, info64.iters) == (i64["status"], i64["iters"]) and same(host(x64), x64_or)
+    err = np.linalg.norm(x_or - x64_or) / np.linalg.norm(x64_or)
+    say(f"c4 binary32 form vs binary64 solution: {err:.2e}")
+    assert err < 1e-6
