@@ -176,6 +176,23 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
                 const pbcgs_opts* opts, pbcgs_info* info);
 
 /*
+ * Batched solve of nsys independent systems A[k] x[k] = b[k] with the same
+ * options (the batched workload of many small and large systems).  A: HOST
+ * array of nsys CSR operators of ctx; b, x: HOST arrays of nsys DEVICE
+ * pointers (x[k] holds x_0 on entry, the final iterate on return); infos:
+ * HOST array of nsys reports.  Every kernel launch covers all systems: each
+ * workgroup belongs to one system, each system has its own scalars, status,
+ * reductions and stopping test, and a system that stops leaves the later
+ * launches at once.  Reductions are the same pairwise trees as in
+ * pbcgs_solve, so each system's result equals that of its own pbcgs_solve
+ * bit for bit.  No preconditioner, binary64, no history (ERR_UNSUPPORTED
+ * otherwise).  The context keeps the batch workspace (8 vectors per system).
+ * Returns the largest numerical status of the systems, or a negative error.
+ */
+int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const double* const* b,
+                        double* const* x, const pbcgs_opts* opts, pbcgs_info* infos);
+
+/*
  * Workload builder (not part of the method): assembles on the device the
  * h^2-scaled first-order upwind convection-diffusion operator used by the
  * tests and the benchmark, h = 1/(n+1), Dirichlet boundaries, rows x fastest,

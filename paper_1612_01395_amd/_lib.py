@@ -79,6 +79,8 @@ _SIGNATURES = {
     "pbcgs_dot": (ctypes.c_int, [_vp, _i64, _vp, _vp, ctypes.POINTER(_f64)]),
     "pbcgs_jacobi_dinv": (ctypes.c_int, [_vp, _vp, _vp]),
     "pbcgs_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
+    "pbcgs_solve_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                           ctypes.POINTER(_vp), ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
     "pbcgs_convdiff_nnz": (_i64, [_i32, _i32, _i32]),
     "pbcgs_assemble_convdiff": (ctypes.c_int, [_vp, _i32, _i32, _i32, ctypes.POINTER(_f64), _vp, _f64,
                                                _vp, _vp, _vp]),

@@ -151,7 +151,7 @@ struct StencilOp {
     const int32_t i = row % nx;
     const int32_t jk = row / nx;
     V acc = V(0);
-    if (NPTS == 7) {
+    if constexpr (NPTS == 7) {
       const int32_t j = jk % ny, k = jk / ny;
       const int32_t nxy = nx * ny;
       if (k > 0) acc = acc + c[0] * V(x[row - nxy]);
@@ -187,6 +187,10 @@ struct Args {
   int32_t Gin;            // partials to consume (workgroups of the producer)
   int32_t first;          // first iteration: consume the setup reduction
   int32_t mode;           // precision form: 1 = reduction after a forced replacement
+  int32_t wg;             // workgroup index within the system (-1: blockIdx.x)
+  int32_t pstride;        // stride between the ND partial-sum rows (kMaxG, or the batch's workgroups)
+  int32_t par;            // batched launches: state slot read (written: par ^ 1)
+  int32_t pad2_;
   const DevState* sin;    // state read by this launch
   DevState* sout;         // state written by workgroup 0
   const double* pin;      // partials consumed: pin[k * kMaxG + wg]
@@ -284,7 +288,7 @@ __device__ __forceinline__ void gather_sums(const Args& a, double (&res)[ND]) {
     T c[kChunk];
 #pragma unroll
     for (int j = 0; j < kChunk; ++j) {
-      const T p = T(a.pin[k * kMaxG + min(base + j, a.Gin - 1)]);  // clamped: branch-free
+      const T p = T(a.pin[k * a.pstride + min(base + j, a.Gin - 1)]);  // clamped: branch-free
       c[j] = (base + j < a.Gin) ? p : T(0);
     }
 #pragma unroll
@@ -299,6 +303,11 @@ __device__ __forceinline__ void gather_sums(const Args& a, double (&res)[ND]) {
   for (int k = 0; k < ND; ++k) res[k] = double(tot[k] + T(0));
 }
 
+// Index of this workgroup among the workgroups of its system.
+__device__ __forceinline__ int wg_index(const Args& a) { return a.wg >= 0 ? a.wg : (int)blockIdx.x; }
+// first thread of the system's first workgroup (batched launches hold many systems)
+__device__ __forceinline__ bool sys_leader(const Args& a) { return wg_index(a) == 0 && threadIdx.x == 0; }
+
 // The workgroup's rows with ND products each; writes its partial sums to
 // pout[k][blockIdx.x].  Body(row, valid, d) is called by all 64 lanes of a
 // block (so an operator may work on the block cooperatively); lanes with
@@ -307,7 +316,7 @@ template <int ND, class T = double, class Body>
 __device__ __forceinline__ void produce(const Args& a, Body body) {
   __shared__ T blk[ND][kWG];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t wbase = ((int64_t)blockIdx.x * 4 + wave) * a.R * 64;
+  const int64_t wbase = ((int64_t)wg_index(a) * 4 + wave) * a.R * 64;
   for (int j = 0; j < a.R; ++j) {
     const int64_t b0 = wbase + (int64_t)j * 64;
     T d[ND];
@@ -330,7 +339,7 @@ __device__ __forceinline__ void produce(const Args& a, Body body) {
   wg_sum_all<ND, T>(v, tot);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < ND; ++k) a.pout[k * kMaxG + blockIdx.x] = double(tot[k]);
+    for (int k = 0; k < ND; ++k) a.pout[k * a.pstride + wg_index(a)] = double(tot[k]);
   }
 }
 
@@ -338,7 +347,7 @@ __device__ __forceinline__ void produce(const Args& a, Body body) {
 template <class Body>
 __device__ __forceinline__ void each_row(const Args& a, Body body) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t wbase = ((int64_t)blockIdx.x * 4 + wave) * a.R * 64;
+  const int64_t wbase = ((int64_t)wg_index(a) * 4 + wave) * a.R * 64;
   for (int j = 0; j < a.R; ++j) {
     const int64_t b0 = wbase + (int64_t)j * 64;
     if (b0 < a.n) {
@@ -366,7 +375,7 @@ __device__ __forceinline__ State load_state(const DevState* p) {
 }
 
 __device__ __forceinline__ void publish(const Args& a, const State& s) {
-  if (leader()) {
+  if (sys_leader(a)) {
     DevState* p = a.sout;
     p->alpha = s.alpha; p->beta = s.beta; p->omega = s.omega; p->gamma = s.gamma;
     p->rho0 = s.rho0; p->relres = s.relres; p->tol = s.tol; p->result = s.result;
@@ -485,7 +494,7 @@ __device__ __forceinline__ void fin_bicg_beta(State& s, double* hist, double g1,
 // Setup 1: r0 = b - A x0 ; r = r0 ; r^ = M^{-1} r0 ; p^ = s = s^ = z = z^ = v = 0 ;
 // partials of (r0, r0).  PIPE = false: BiCGStab setup, p = r0 ; p^ = M^{-1} p.
 template <class Op, int PC, bool PIPE>
-__global__ __launch_bounds__(kWG) void k_setup_r0(Op op, Args a) {
+__device__ __forceinline__ void d_setup_r0(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   publish(a, st);
   produce<1>(a, [&](int32_t row, bool valid, double (&d)[1]) {
@@ -511,11 +520,13 @@ __global__ __launch_bounds__(kWG) void k_setup_r0(Op op, Args a) {
     d[0] = r0 * r0;
   });
 }
+template <class Op, int PC, bool PIPE>
+__global__ __launch_bounds__(kWG) void k_setup_r0(Op op, Args a) { d_setup_r0<Op, PC, PIPE>(op, a); }
 
 // Setup 2: gamma, rho0 from setup 1 ; w0 = A r^0 ; w^0 = M^{-1} w0 ;
 // partials of (r0, w0).
 template <class Op, int PC>
-__global__ __launch_bounds__(kWG) void k_setup_w0(Op op, Args a) {
+__device__ __forceinline__ void d_setup_w0(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   double g[1];
   gather_sums<1>(a, g);
@@ -530,6 +541,8 @@ __global__ __launch_bounds__(kWG) void k_setup_w0(Op op, Args a) {
     d[0] = a.r0[row] * w;
   });
 }
+template <class Op, int PC>
+__global__ __launch_bounds__(kWG) void k_setup_w0(Op op, Args a) { d_setup_w0<Op, PC>(op, a); }
 
 // Phase A of iteration i.  First it finishes the previous reduction: in the
 // first iteration alpha_0 (setup 2), later reduction 2 of iteration i-1 (stop
@@ -539,7 +552,7 @@ __global__ __launch_bounds__(kWG) void k_setup_w0(Op op, Args a) {
 // t = A w^ and z = A s^ (both gathers), then lines 9-11 and 13.
 // Partials: (q, y), (y, y).
 template <class Op, int PC, bool RR2>
-__global__ __launch_bounds__(kWG) void k_pa(Op op, Args a) {
+__device__ __forceinline__ void d_pa(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   if (!RR2) {
     if (a.first) {
@@ -588,12 +601,14 @@ __global__ __launch_bounds__(kWG) void k_pa(Op op, Args a) {
     d[1] = y * y;
   });
 }
+template <class Op, int PC, bool RR2>
+__global__ __launch_bounds__(kWG) void k_pa(Op op, Args a) { d_pa<Op, PC, RR2>(op, a); }
 
 // Phase B of iteration i: omega_i from phase A's partials ; v = A z^ ;
 // lines 9-11 recomputed ; lines 17-20 ; line 22 ; partials of (r0,r),
 // (r0,w), (r0,s), (r0,z), (r,r) (reduction 2).
 template <class Op, int PC>
-__global__ __launch_bounds__(kWG) void k_pb(Op op, Args a) {
+__device__ __forceinline__ void d_pb(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   double g2[2];
   gather_sums<2>(a, g2);
@@ -639,11 +654,13 @@ __global__ __launch_bounds__(kWG) void k_pb(Op op, Args a) {
     d[4] = rn * rn;
   });
 }
+template <class Op, int PC>
+__global__ __launch_bounds__(kWG) void k_pb(Op op, Args a) { d_pb<Op, PC>(op, a); }
 
 // Residual-replacement iteration, phase B': omega_i, then only the x update
 // of line 17 (r, r^, w are replaced next, so lines 18-20 and v are not needed).
 template <int PC>
-__global__ __launch_bounds__(kWG) void k_rr_x(Args a) {
+__device__ __forceinline__ void d_rr_x(Args a) {
   PBCGS_PROLOGUE(st)
   double g2[2];
   gather_sums<2>(a, g2);
@@ -662,10 +679,12 @@ __global__ __launch_bounds__(kWG) void k_rr_x(Args a) {
     }
   });
 }
+template <int PC>
+__global__ __launch_bounds__(kWG) void k_rr_x(Args a) { d_rr_x<PC>(a); }
 
 // Residual replacement, first half (Section 4.2): r = b - A x ; r^ = M^{-1} r.
 template <class Op, int PC>
-__global__ __launch_bounds__(kWG) void k_rr_r(Op op, Args a) {
+__device__ __forceinline__ void d_rr_r(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   publish(a, st);
   each_row(a, [&](int32_t row, bool valid) {
@@ -676,11 +695,13 @@ __global__ __launch_bounds__(kWG) void k_rr_r(Op op, Args a) {
     if (PC != PC_NONE) a.rh[row] = apply_pc<PC>(a, row, r);
   });
 }
+template <class Op, int PC>
+__global__ __launch_bounds__(kWG) void k_rr_r(Op op, Args a) { d_rr_r<Op, PC>(op, a); }
 
 // Residual replacement, first half continued: w = A r^ ; w^ = M^{-1} w ;
 // partials of reduction 2 on the true r, w.
 template <class Op, int PC>
-__global__ __launch_bounds__(kWG) void k_rr_w(Op op, Args a) {
+__device__ __forceinline__ void d_rr_w(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   st.n_rr += 1;
   publish(a, st);
@@ -697,11 +718,13 @@ __global__ __launch_bounds__(kWG) void k_rr_w(Op op, Args a) {
     d[4] = r * r;
   });
 }
+template <class Op, int PC>
+__global__ __launch_bounds__(kWG) void k_rr_w(Op op, Args a) { d_rr_w<Op, PC>(op, a); }
 
 // Second half, in the iteration after a replacement: reduction 2 (stop test,
 // beta, alpha), then line 5 (p^ update) alone.
 template <int PC>
-__global__ __launch_bounds__(kWG) void k_rr_p(Args a) {
+__device__ __forceinline__ void d_rr_p(Args a) {
   PBCGS_PROLOGUE(st)
   double g[5];
   gather_sums<5>(a, g);
@@ -715,10 +738,12 @@ __global__ __launch_bounds__(kWG) void k_rr_p(Args a) {
     else a.ph[row] = a.r[row] + beta * (a.ph[row] - omega * a.s[row]);
   });
 }
+template <int PC>
+__global__ __launch_bounds__(kWG) void k_rr_p(Args a) { d_rr_p<PC>(a); }
 
 // Second half continued: s = A p^ ; s^ = M^{-1} s.
 template <class Op, int PC>
-__global__ __launch_bounds__(kWG) void k_rr_s(Op op, Args a) {
+__device__ __forceinline__ void d_rr_s(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   publish(a, st);
   each_row(a, [&](int32_t row, bool valid) {
@@ -728,6 +753,8 @@ __global__ __launch_bounds__(kWG) void k_rr_s(Op op, Args a) {
     if (PC != PC_NONE) a.sh[row] = apply_pc<PC>(a, row, s);
   });
 }
+template <class Op, int PC>
+__global__ __launch_bounds__(kWG) void k_rr_s(Op op, Args a) { d_rr_s<Op, PC>(op, a); }
 
 // ===========================================================================
 // BiCGStab kernels (Algorithm 7, PC == PC_NONE; Algorithm 10 otherwise).
@@ -735,7 +762,7 @@ __global__ __launch_bounds__(kWG) void k_rr_s(Op op, Args a) {
 
 // (first iteration: gamma, rho0 from the setup) ; s = A p^ ; partials of (r0, s).
 template <class Op, int PC>
-__global__ __launch_bounds__(kWG) void k_b1(Op op, Args a) {
+__device__ __forceinline__ void d_b1(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   if (a.first) {
     double g[1];
@@ -751,10 +778,12 @@ __global__ __launch_bounds__(kWG) void k_b1(Op op, Args a) {
     d[0] = a.r0[row] * s;
   });
 }
+template <class Op, int PC>
+__global__ __launch_bounds__(kWG) void k_b1(Op op, Args a) { d_b1<Op, PC>(op, a); }
 
 // alpha_i ; q = r - alpha s ; q^ = M^{-1} q.
 template <int PC>
-__global__ __launch_bounds__(kWG) void k_b2(Args a) {
+__device__ __forceinline__ void d_b2(Args a) {
   PBCGS_PROLOGUE(st)
   double g[1];
   gather_sums<1>(a, g);
@@ -769,10 +798,12 @@ __global__ __launch_bounds__(kWG) void k_b2(Args a) {
     if (PC != PC_NONE) a.qh[row] = apply_pc<PC>(a, row, q);
   });
 }
+template <int PC>
+__global__ __launch_bounds__(kWG) void k_b2(Args a) { d_b2<PC>(a); }
 
 // y = A q^ ; partials of (q, y), (y, y).
 template <class Op, int PC>
-__global__ __launch_bounds__(kWG) void k_b3(Op op, Args a) {
+__device__ __forceinline__ void d_b3(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   publish(a, st);
   produce<2>(a, [&](int32_t row, bool valid, double (&d)[2]) {
@@ -783,10 +814,12 @@ __global__ __launch_bounds__(kWG) void k_b3(Op op, Args a) {
     d[1] = y * y;
   });
 }
+template <class Op, int PC>
+__global__ __launch_bounds__(kWG) void k_b3(Op op, Args a) { d_b3<Op, PC>(op, a); }
 
 // omega_i ; x = x + alpha p^ + omega q^ ; r = q - omega y ; partials of (r0, r), (r, r).
 template <int PC>
-__global__ __launch_bounds__(kWG) void k_b4(Args a) {
+__device__ __forceinline__ void d_b4(Args a) {
   PBCGS_PROLOGUE(st)
   double g2[2];
   gather_sums<2>(a, g2);
@@ -811,10 +844,12 @@ __global__ __launch_bounds__(kWG) void k_b4(Args a) {
     d[1] = r * r;
   });
 }
+template <int PC>
+__global__ __launch_bounds__(kWG) void k_b4(Args a) { d_b4<PC>(a); }
 
 // stop test and beta_i ; p = r + beta (p - omega s) ; p^ = M^{-1} p.
 template <int PC>
-__global__ __launch_bounds__(kWG) void k_b5(Args a) {
+__device__ __forceinline__ void d_b5(Args a) {
   PBCGS_PROLOGUE(st)
   double g2[2];
   gather_sums<2>(a, g2);
@@ -829,11 +864,13 @@ __global__ __launch_bounds__(kWG) void k_b5(Args a) {
     if (PC != PC_NONE) a.ph[row] = apply_pc<PC>(a, row, p);
   });
 }
+template <int PC>
+__global__ __launch_bounds__(kWG) void k_b5(Args a) { d_b5<PC>(a); }
 
 // Finishes a pending reduction in one workgroup: MODE 0 reduction 2 of
 // p-BiCGStab, 1 the setup alpha, 2 the setup gamma, 3 a plain sum into result.
 template <int MODE>
-__global__ __launch_bounds__(kWG) void k_finish(Args a) {
+__device__ __forceinline__ void d_finish(Args a) {
   State st = load_state(a.sin);
   if (MODE == 3) {
     double g[1];
@@ -858,6 +895,8 @@ __global__ __launch_bounds__(kWG) void k_finish(Args a) {
   }
   publish(a, st);
 }
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_finish(Args a) { d_finish<MODE>(a); }
 
 // ===========================================================================
 // Precision form of Algorithm 9 with residual replacement: binary32 vectors,
@@ -1171,7 +1210,7 @@ __global__ __launch_bounds__(kWG) void k_dot(Args a, const double* __restrict__ 
 
 // partials of ||b - A x||^2 (true residual of the returned x).
 template <class Op>
-__global__ __launch_bounds__(kWG) void k_true_res(Op op, Args a) {
+__device__ __forceinline__ void d_true_res(Op op, Args a) {
   produce<1>(a, [&](int32_t row, bool valid, double (&d)[1]) {
     const double ax = op.spmv(row, valid, a.x);
     if (!valid) return;
@@ -1179,6 +1218,8 @@ __global__ __launch_bounds__(kWG) void k_true_res(Op op, Args a) {
     d[0] = r * r;
   });
 }
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_true_res(Op op, Args a) { d_true_res<Op>(op, a); }
 
 // Right preconditioning with the operator formed explicitly (Section 3.6
 // solves A M^{-1} y = b and returns x = M^{-1} y): the entries of A M^{-1} are
@@ -1238,5 +1279,129 @@ __global__ __launch_bounds__(kWG) void k_csr_check(CsrOp op, int32_t n, int64_t 
   }
   if (bad) atomicOr(flag, 1);
 }
+
+// ===========================================================================
+// Batched launches: many independent CSR systems (no preconditioner) in one
+// grid.  Workgroup g belongs to system map[g]; a system's workgroups are
+// consecutive, so its rows, its partial sums and its scalar state are its
+// own, and each reduction is the same pairwise tree as in a solve of that
+// system alone (so the results are the same bits).  A system that has
+// stopped passes its state on and its workgroups return at once.
+// ===========================================================================
+struct SysDesc {
+  const int32_t* rp;
+  const int32_t* ci;
+  const double* va;
+  double* ws;        // 8 vectors of np doubles
+  double* x;
+  const double* b;
+  DevState* st;      // 4 state slots: 0, 1 the iteration ring, 2, 3 utility sums
+  int64_t np;
+  int32_t n, G, R, wg0;  // rows, workgroups, blocks per wave, first workgroup of the grid
+};
+
+// Per-system arguments from the launch template: rows, shape, state slots
+// (template field par), partial-sum rows (offset to the system's workgroups)
+// and the vector layout of p-BiCGStab (PIPE) or BiCGStab.
+template <bool PIPE>
+__device__ __forceinline__ void bind_sys(const SysDesc& d, Args& a, CsrOp& op) {
+  op = CsrOp{d.rp, d.ci, d.va, d.n};
+  a.n = d.n;
+  a.G = d.G;
+  a.R = d.R;
+  a.Gin = d.G;
+  a.sin = d.st + a.par;
+  a.sout = d.st + (a.par ^ 1);
+  if (a.pin) a.pin += d.wg0;
+  if (a.pout) a.pout += d.wg0;
+  a.x = d.x;
+  a.b = d.b;
+  a.hist = nullptr;
+  a.dinv = nullptr;
+  double* v = d.ws;
+  const int64_t np = d.np;
+  if (PIPE) {
+    a.r0 = v; a.r = v + np; a.w = v + 2 * np; a.t = v + 3 * np;
+    a.ph = v + 4 * np; a.s = v + 5 * np; a.z = v + 6 * np; a.v = v + 7 * np;
+    a.rh = a.r; a.wh = a.w; a.sh = a.s; a.zh = a.z;
+  } else {
+    a.r0 = v; a.r = v + np; a.p = v + 2 * np; a.s = v + 3 * np; a.q = v + 4 * np; a.y = v + 5 * np;
+    a.ph = a.p; a.qh = a.q;
+  }
+}
+
+#define PBCGS_BIND_WG(PIPE)                        \
+  const SysDesc d_ = sys[map[blockIdx.x]];         \
+  a.wg = (int32_t)blockIdx.x - d_.wg0;             \
+  CsrOp op;                                        \
+  bind_sys<PIPE>(d_, a, op);
+
+template <bool PIPE>
+__global__ __launch_bounds__(kWG) void kb_setup_r0(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(PIPE) d_setup_r0<CsrOp, PC_NONE, PIPE>(op, a);
+}
+__global__ __launch_bounds__(kWG) void kb_setup_w0(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(true) d_setup_w0<CsrOp, PC_NONE>(op, a);
+}
+template <bool RR2>
+__global__ __launch_bounds__(kWG) void kb_pa(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(true) d_pa<CsrOp, PC_NONE, RR2>(op, a);
+}
+__global__ __launch_bounds__(kWG) void kb_pb(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(true) d_pb<CsrOp, PC_NONE>(op, a);
+}
+__global__ __launch_bounds__(kWG) void kb_rr_x(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(true) (void)op; d_rr_x<PC_NONE>(a);
+}
+__global__ __launch_bounds__(kWG) void kb_rr_r(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(true) d_rr_r<CsrOp, PC_NONE>(op, a);
+}
+__global__ __launch_bounds__(kWG) void kb_rr_w(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(true) d_rr_w<CsrOp, PC_NONE>(op, a);
+}
+__global__ __launch_bounds__(kWG) void kb_rr_p(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(true) (void)op; d_rr_p<PC_NONE>(a);
+}
+__global__ __launch_bounds__(kWG) void kb_rr_s(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(true) d_rr_s<CsrOp, PC_NONE>(op, a);
+}
+__global__ __launch_bounds__(kWG) void kb_b1(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(false) d_b1<CsrOp, PC_NONE>(op, a);
+}
+__global__ __launch_bounds__(kWG) void kb_b2(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(false) (void)op; d_b2<PC_NONE>(a);
+}
+__global__ __launch_bounds__(kWG) void kb_b3(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(false) d_b3<CsrOp, PC_NONE>(op, a);
+}
+__global__ __launch_bounds__(kWG) void kb_b4(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(false) (void)op; d_b4<PC_NONE>(a);
+}
+__global__ __launch_bounds__(kWG) void kb_b5(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(false) (void)op; d_b5<PC_NONE>(a);
+}
+__global__ __launch_bounds__(kWG) void kb_true_res(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(true) d_true_res<CsrOp>(op, a);
+}
+// One workgroup per system: a pending reduction (modes of k_finish).
+template <int MODE, bool PIPE>
+__global__ __launch_bounds__(kWG) void kb_finish(const SysDesc* sys, Args a) {
+  const SysDesc d = sys[blockIdx.x];
+  a.wg = 0;
+  CsrOp op;
+  bind_sys<PIPE>(d, a, op);
+  d_finish<MODE>(a);
+}
+// Slot `slot` of every system's state: running, no scalars yet.
+__global__ void kb_init_state(const SysDesc* sys, int32_t nsys, int32_t slot, double tol) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nsys) return;
+  DevState* st = sys[k].st + slot;
+  st->alpha = 0.0; st->beta = 0.0; st->omega = 0.0; st->gamma = 0.0;
+  st->rho0 = 0.0; st->relres = 1.0; st->tol = tol; st->result = 0.0;
+  st->status = DS_RUNNING; st->iters = 0; st->n_rr = 0;
+  for (int j = 0; j < 5; ++j) st->pad[j] = 0;
+}
+#undef PBCGS_BIND_WG
 
 }  // namespace pbcgs

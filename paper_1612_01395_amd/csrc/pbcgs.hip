@@ -45,6 +45,19 @@ struct pbcgs_ctx_s {
   size_t ahat_cap = 0;      // doubles
   float* a32 = nullptr;     // binary32 operator values (precision form, CSR)
   size_t a32_cap = 0;       // floats
+  // batched solves: system table, workgroup map, vectors, states, partials, host poll copies
+  SysDesc* bsys = nullptr;
+  size_t bsys_cap = 0;
+  int32_t* bmap = nullptr;
+  size_t bmap_cap = 0;
+  double* bws = nullptr;
+  size_t bws_cap = 0;
+  DevState* bst = nullptr;
+  size_t bst_cap = 0;
+  double* bpart = nullptr;
+  size_t bpart_cap = 0;
+  DevState* bhst = nullptr;  // pinned, two poll slots of bst_cap states
+  size_t bhst_cap = 0;
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
   hipEvent_t ev_poll[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> kev;  // pool for per-kernel timing
@@ -130,6 +143,8 @@ Args base_args(pbcgs_ctx_t ctx, const Shape& sh) {
   a.Gin = sh.G;
   a.sin = ctx->st;
   a.sout = ctx->st + 1;
+  a.wg = -1;           // one system: the workgroup index is blockIdx.x
+  a.pstride = kMaxG;
   return a;
 }
 
@@ -619,6 +634,234 @@ int pbcgs_internal_fail(pbcgs_ctx_t ctx, int code, const char* msg) { return fai
 // ===========================================================================
 // C ABI
 // ===========================================================================
+namespace {
+
+// Device buffer of at least `count` elements (contents not kept).
+template <class T>
+int grow(pbcgs_ctx_t ctx, T*& p, size_t& cap, size_t count, const char* what) {
+  if (cap >= count) return PBCGS_SUCCESS;
+  if (p) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+    p = nullptr;
+    return fail(ctx, PBCGS_ERR_ALLOC, std::string("allocation failed: ") + what);
+  }
+  cap = count;
+  return PBCGS_SUCCESS;
+}
+
+// Batched solve of independent CSR systems without a preconditioner: the
+// schedule of Driver, every launch covering all systems (see SysDesc).
+struct BatchDriver {
+  pbcgs_ctx_t ctx;
+  const pbcgs_opts& o;
+  int32_t nsys, totalG;
+  Args tmpl;
+  int64_t q = 0;
+  const bool pipe;
+
+  BatchDriver(pbcgs_ctx_t c, const pbcgs_opts& o_, int32_t ns, int32_t tg)
+      : ctx(c), o(o_), nsys(ns), totalG(tg), pipe(o_.variant != PBCGS_BICGSTAB) {
+    std::memset(&tmpl, 0, sizeof tmpl);
+    tmpl.pstride = tg;
+  }
+
+  double* part(int which) const { return ctx->bpart + (size_t)which * kMaxD * totalG; }
+
+  Args L(int pin, int pout, bool first = false) {
+    Args b = tmpl;
+    b.par = (int32_t)(q & 1);
+    b.pin = pin >= 0 ? part(pin) : nullptr;
+    b.pout = pout >= 0 ? part(pout) : nullptr;
+    b.first = first ? 1 : 0;
+    ++q;
+    return b;
+  }
+
+  void setup() {
+    hipStream_t s = ctx->stream;
+    if (!pipe) {
+      kb_setup_r0<false><<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, L(-1, PB_SETUP1));
+      return;
+    }
+    kb_setup_r0<true><<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, L(-1, PB_SETUP1));
+    kb_setup_w0<<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, L(PB_SETUP1, PB_SETUP2));
+  }
+
+  void iteration(int64_t i) {
+    hipStream_t s = ctx->stream;
+    const SysDesc* S = ctx->bsys;
+    const int32_t* M = ctx->bmap;
+    if (!pipe) {
+      kb_b1<<<totalG, kWG, 0, s>>>(S, M, L(PB_SETUP1, PB_B1, i == 0));
+      kb_b2<<<totalG, kWG, 0, s>>>(S, M, L(PB_B1, -1));
+      kb_b3<<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_B3));
+      kb_b4<<<totalG, kWG, 0, s>>>(S, M, L(PB_B3, PB_B4));
+      kb_b5<<<totalG, kWG, 0, s>>>(S, M, L(PB_B4, -1));
+      return;
+    }
+    if (rr_due(o, i - 1)) {
+      kb_rr_p<<<totalG, kWG, 0, s>>>(S, M, L(PB_B, -1));
+      kb_rr_s<<<totalG, kWG, 0, s>>>(S, M, L(-1, -1));
+      kb_pa<true><<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_A));
+    } else {
+      kb_pa<false><<<totalG, kWG, 0, s>>>(S, M, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
+    }
+    if (rr_due(o, i)) {
+      kb_rr_x<<<totalG, kWG, 0, s>>>(S, M, L(PB_A, -1));
+      kb_rr_r<<<totalG, kWG, 0, s>>>(S, M, L(-1, -1));
+      kb_rr_w<<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_B));
+    } else {
+      kb_pb<<<totalG, kWG, 0, s>>>(S, M, L(PB_A, PB_B));
+    }
+  }
+
+  void count_iteration(int64_t i) {
+    if (!pipe) { q += 5; return; }
+    q += (rr_due(o, i - 1) ? 3 : 1) + (rr_due(o, i) ? 3 : 1);
+  }
+
+  void finish(int64_t launched) {
+    hipStream_t s = ctx->stream;
+    if (!pipe) {
+      if (launched == 0) kb_finish<2, false><<<nsys, kWG, 0, s>>>(ctx->bsys, L(PB_SETUP1, -1));
+      return;
+    }
+    if (launched == 0) kb_finish<1, true><<<nsys, kWG, 0, s>>>(ctx->bsys, L(PB_SETUP2, -1));
+    else kb_finish<0, true><<<nsys, kWG, 0, s>>>(ctx->bsys, L(PB_B, -1));
+  }
+
+  std::string key(int64_t i0, int m) const {
+    std::string k = "batch|";
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%p|%p|%p|%d|%d|%d|%d|%lld|%d|", (void*)ctx->bsys, (void*)ctx->bmap,
+                  (void*)ctx->bpart, nsys, totalG, o.variant, m, (long long)(q & 1), i0 == 0 ? 1 : 0);
+    k += buf;
+    for (int j = 0; j < m; ++j) {
+      const int64_t i = i0 + j;
+      k += char('0' + ((rr_due(o, i - 1) ? 1 : 0) | (rr_due(o, i) ? 2 : 0)));
+    }
+    return k;
+  }
+
+  int chunk(int64_t i0, int m, bool use_graph) {
+    if (!use_graph) {
+      for (int j = 0; j < m; ++j) iteration(i0 + j);
+      HIP_TRY(ctx, hipGetLastError());
+      return PBCGS_SUCCESS;
+    }
+    const std::string k = key(i0, m);
+    const int64_t q0 = q;
+    auto it = ctx->graphs.find(k);
+    if (it == ctx->graphs.end()) {
+      if (ctx->graphs.size() >= 32) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+        ctx->graphs.clear();
+      }
+      hipGraph_t g = nullptr;
+      HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      for (int j = 0; j < m; ++j) iteration(i0 + j);
+      hipError_t ce = hipStreamEndCapture(ctx->stream, &g);
+      if (ce != hipSuccess) return fail(ctx, PBCGS_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+      hipGraphExec_t ex = nullptr;
+      hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) return fail(ctx, PBCGS_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+      it = ctx->graphs.emplace(k, ex).first;
+    } else {
+      q = q0;
+      for (int j = 0; j < m; ++j) count_iteration(i0 + j);
+    }
+    HIP_TRY(ctx, hipGraphLaunch(it->second, ctx->stream));
+    return PBCGS_SUCCESS;
+  }
+
+  int run(pbcgs_info* infos) {
+    hipStream_t s = ctx->stream;
+    const bool use_graph = !(o.flags & 1);
+    const int check = o.check_every > 0 ? o.check_every : 8;
+    const size_t nst = (size_t)nsys * 4;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_start, s));
+    kb_init_state<<<(nsys + 63) / 64, 64, 0, s>>>(ctx->bsys, nsys, 0, o.tol);
+    q = 0;
+    setup();
+    HIP_TRY(ctx, hipGetLastError());
+    int64_t launched = 0;
+    int pend[2], npend = 0, next = 0;
+    int64_t qpoll[2] = {0, 0};
+    bool stop = false;
+    for (;;) {
+      while (!stop && launched < o.maxit && npend < 2) {
+        const int m = (int)std::min<int64_t>(check, o.maxit - launched);
+        int rc = chunk(launched, m, use_graph);
+        if (rc != PBCGS_SUCCESS) return rc;
+        launched += m;
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->bhst + (size_t)next * nst, ctx->bst, nst * sizeof(DevState),
+                                    hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipEventRecord(ctx->ev_poll[next], s));
+        qpoll[next] = q;
+        pend[npend++] = next;
+        next ^= 1;
+      }
+      if (npend == 0) break;
+      const int slot = pend[0];
+      pend[0] = pend[1];
+      --npend;
+      HIP_TRY(ctx, hipEventSynchronize(ctx->ev_poll[slot]));
+      const DevState* h = ctx->bhst + (size_t)slot * nst;
+      const int cur = (int)(qpoll[slot] & 1);
+      bool any = false;
+      for (int32_t k = 0; k < nsys && !any; ++k) any = (h[(size_t)k * 4 + cur].status == DS_RUNNING);
+      if (!any) stop = true;
+    }
+    finish(launched);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_stop, s));
+    std::vector<DevState> fin(nst);
+    HIP_TRY(ctx, hipMemcpyAsync(fin.data(), ctx->bst, nst * sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop);
+    // true residuals ||b - A x|| of every system, pairwise, via utility slots 2 -> 3
+    Args t = tmpl;
+    t.pout = part(PB_UTIL);
+    kb_true_res<<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, t);
+    kb_init_state<<<(nsys + 63) / 64, 64, 0, s>>>(ctx->bsys, nsys, 2, 0.0);
+    Args f = tmpl;
+    f.par = 2;
+    f.pin = part(PB_UTIL);
+    kb_finish<3, true><<<nsys, kWG, 0, s>>>(ctx->bsys, f);
+    HIP_TRY(ctx, hipGetLastError());
+    std::vector<DevState> util(nst);
+    HIP_TRY(ctx, hipMemcpyAsync(util.data(), ctx->bst, nst * sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const int cur = (int)(q & 1);
+    int worst = PBCGS_SUCCESS;
+    for (int32_t k = 0; k < nsys; ++k) {
+      const DevState& d = fin[(size_t)k * 4 + cur];
+      pbcgs_info& in = infos[k];
+      std::memset(&in, 0, sizeof in);
+      in.iters = d.iters;
+      in.n_rr = d.n_rr;
+      in.status = map_status(d.status);
+      in.syncs_per_iter = pipe ? 2 : 5;
+      in.relres_rec = d.relres;
+      const double nr = util[(size_t)k * 4 + 3].result;
+      in.relres_true = (d.rho0 > 0.0) ? std::sqrt(nr) / d.rho0 : 0.0;
+      in.ms = ms;
+      worst = std::max(worst, in.status);
+    }
+    return worst;
+  }
+};
+
+}  // namespace
+
 extern "C" {
 
 const char* pbcgs_status_str(int status) {
@@ -694,6 +937,12 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->ahat) (void)hipFree(ctx->ahat);
   if (ctx->a32) (void)hipFree(ctx->a32);
+  if (ctx->bsys) (void)hipFree(ctx->bsys);
+  if (ctx->bmap) (void)hipFree(ctx->bmap);
+  if (ctx->bws) (void)hipFree(ctx->bws);
+  if (ctx->bst) (void)hipFree(ctx->bst);
+  if (ctx->bpart) (void)hipFree(ctx->bpart);
+  if (ctx->bhst) (void)hipHostFree(ctx->bhst);
   if (ctx->part) (void)hipFree(ctx->part);
   if (ctx->flag) (void)hipFree(ctx->flag);
   if (ctx->st) (void)hipFree(ctx->st);
@@ -1007,6 +1256,80 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     if (pc == PC_VEC) return Driver<Op, PC_VEC>(ctx, op, a, o).run(info);
     return Driver<Op, PC_SCALAR>(ctx, op, a, o).run(info);
   });
+}
+
+// Batched solve (see include/pbcgs.h).
+int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const double* const* b,
+                        double* const* x, const pbcgs_opts* opts, pbcgs_info* infos) {
+  if (!ctx || !A || !b || !x || !opts || !infos) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  if (nsys <= 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "nsys must be positive");
+  const pbcgs_opts& o = *opts;
+  if (o.variant < PBCGS_BICGSTAB || o.variant > PBCGS_PBICGSTAB_RR)
+    return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown variant");
+  if (o.precond != PBCGS_PRECOND_NONE)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves take no preconditioner");
+  if (o.precision != PBCGS_FP64) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves are binary64");
+  if (o.maxit < 0 || !(o.tol >= 0.0)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad maxit or tol");
+  if (o.variant == PBCGS_PBICGSTAB_RR && o.rr_period < 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad rr_period");
+  if (o.history) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves keep no history");
+  int gcap = env_int("PBCGS_BATCH_GCAP", 64);
+  if (gcap < 1 || gcap > kMaxG) gcap = 64;
+  std::vector<SysDesc> desc((size_t)nsys);
+  int64_t totalG = 0;
+  size_t wsneed = 0;
+  for (int32_t k = 0; k < nsys; ++k) {
+    const pbcgs_op_t op = A[k];
+    if (!op || op->ctx != ctx) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad operator " + std::to_string(k));
+    if (op->kind != OP_CSR) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves take CSR operators");
+    if (!b[k] || !x[k] || (const void*)b[k] == (const void*)x[k])
+      return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad b or x of system " + std::to_string(k));
+    int32_t R = 1;
+    int64_t G = ((int64_t)op->n + 255) / 256;
+    while (G > gcap && R < kMaxR) {
+      R *= 2;
+      G = ((int64_t)op->n + 256 * (int64_t)R - 1) / (256 * (int64_t)R);
+    }
+    if (G > kMaxG) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "system " + std::to_string(k) + " too large");
+    SysDesc& d = desc[(size_t)k];
+    d.rp = op->rp; d.ci = op->ci; d.va = op->va;
+    d.x = x[k]; d.b = b[k];
+    d.np = (int64_t)padded(op->n);
+    d.n = op->n; d.G = (int32_t)G; d.R = R; d.wg0 = (int32_t)totalG;
+    totalG += G;
+    wsneed += (size_t)8 * (size_t)d.np;
+  }
+  if (totalG > (int64_t)INT32_MAX / 2) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many workgroups");
+  DeviceGuard guard(ctx->device);
+  const size_t nst = (size_t)nsys * 4;
+  int rc = grow(ctx, ctx->bsys, ctx->bsys_cap, (size_t)nsys, "batch table");
+  if (rc == PBCGS_SUCCESS) rc = grow(ctx, ctx->bmap, ctx->bmap_cap, (size_t)totalG, "workgroup map");
+  if (rc == PBCGS_SUCCESS) rc = grow(ctx, ctx->bws, ctx->bws_cap, wsneed, "batch vectors");
+  if (rc == PBCGS_SUCCESS) rc = grow(ctx, ctx->bst, ctx->bst_cap, nst, "batch states");
+  if (rc == PBCGS_SUCCESS) rc = grow(ctx, ctx->bpart, ctx->bpart_cap, (size_t)PB_COUNT * kMaxD * totalG, "partials");
+  if (rc != PBCGS_SUCCESS) return rc;
+  if (ctx->bhst_cap < nst) {
+    if (ctx->bhst) { (void)hipStreamSynchronize(ctx->stream); (void)hipHostFree(ctx->bhst); ctx->bhst = nullptr; }
+    ctx->bhst_cap = 0;
+    if (hipHostMalloc(&ctx->bhst, 2 * nst * sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+      ctx->bhst = nullptr;
+      return fail(ctx, PBCGS_ERR_ALLOC, "pinned poll buffer");
+    }
+    ctx->bhst_cap = nst;
+  }
+  std::vector<int32_t> map((size_t)totalG);
+  size_t off = 0;
+  for (int32_t k = 0; k < nsys; ++k) {
+    SysDesc& d = desc[(size_t)k];
+    d.ws = ctx->bws + off;
+    off += (size_t)8 * (size_t)d.np;
+    d.st = ctx->bst + (size_t)k * 4;
+    for (int32_t g = 0; g < d.G; ++g) map[(size_t)d.wg0 + g] = k;
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->bsys, desc.data(), desc.size() * sizeof(SysDesc), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->bmap, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the host tables may go away after this
+  BatchDriver drv(ctx, o, nsys, (int32_t)totalG);
+  return drv.run(infos);
 }
 
 }  // extern "C"

@@ -240,3 +240,53 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
     if hist is not None:
         si.history = hist[: info.iters + 1]
     return x, si
+
+
+def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str = "pbicgstab_rr", tol: float = 1e-8,
+                  maxit: int = 2000, rr_period: int = 50, rr_max: int = -1, check_every: int = 0, graph: bool = True,
+                  outs: list | None = None):
+    """Solve the independent systems ops[k] x_k = bs[k] in one batched call
+    (CSR operators of one context, no preconditioner, binary64).  Returns
+    (xs, infos); each system's result equals its own :func:`solve` bit for bit."""
+    nsys = len(ops)
+    if nsys == 0 or len(bs) != nsys:
+        raise ValueError("ops and bs must be non-empty lists of the same length")
+    if variant not in VARIANTS:
+        raise ValueError(f"variant must be one of {sorted(VARIANTS)}")
+    ctx = ops[0].ctx
+    xs = []
+    for k, (A, b) in enumerate(zip(ops, bs)):
+        if A.ctx is not ctx:
+            raise ValueError("all operators must belong to one context")
+        _check_vec(b, A.n, f"bs[{k}]")
+        if outs is not None:
+            x = outs[k]
+            _check_vec(x, A.n, f"outs[{k}]")
+            if x0s is None:
+                x.zero_()
+            else:
+                x.copy_(x0s[k])
+        else:
+            x = torch.zeros_like(b) if x0s is None else x0s[k].clone()
+        _check_vec(x, A.n, f"x[{k}]")
+        xs.append(x)
+    o = L.Opts()
+    o.variant = VARIANTS[variant]
+    o.precond = L.PRECOND_NONE
+    o.precision = L.FP64
+    o.maxit = int(maxit)
+    o.tol = float(tol)
+    o.rr_period = int(rr_period)
+    o.rr_max = int(rr_max)
+    o.check_every = int(check_every)
+    o.flags = 0 if graph else L.FLAG_DIRECT
+    o.history = None
+    VP = ctypes.c_void_p * nsys
+    hs = VP(*[A.handle.value for A in ops])
+    bp = VP(*[b.data_ptr() for b in bs])
+    xp = VP(*[x.data_ptr() for x in xs])
+    infos = (L.Info * nsys)()
+    L.check(L.lib().pbcgs_solve_batched(ctx.handle, nsys, hs, bp, xp, ctypes.byref(o), infos), ctx.handle)
+    out = [SolveInfo(i.iters, i.n_rr, i.status, i.syncs_per_iter, i.relres_rec, i.relres_true, i.ms,
+                     tuple(i.kernel_ms), tuple(i.kernel_calls)) for i in infos]
+    return xs, out

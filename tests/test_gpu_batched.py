@@ -1,0 +1,87 @@
+"""GPU parity of batched solves: independent systems of uneven size in one
+batched call, each against its own oracle solve, bit for bit (iterates,
+iteration and replacement counts, statuses, residuals).  Systems converge at
+different iterations; a stopped system must leave the later launches alone."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_01395_amd import inputs, solver
+from gpu_util import csr_op, dev_t, host, require_gpu, same, say
+
+pytestmark = pytest.mark.gpu
+
+ALG = {"bicgstab": oracle.ALG_BICGSTAB, "pbicgstab": oracle.ALG_PBICGSTAB, "pbicgstab_rr": oracle.ALG_PBICGSTAB_RR}
+
+
+def small_batch():
+    """2-D and 3-D systems from 1 to ~40K unknowns, uneven convection."""
+    sys = []
+    rng = np.random.default_rng(5)
+    for k, n in enumerate([1, 2, 5, 16, 33, 64, 100, 150, 200]):
+        beta = tuple(rng.uniform(0.0, 200.0, 2))
+        sys.append(oracle.assemble(2, n, 5, beta))
+    for n in (3, 12, 24, 34):
+        sys.append(oracle.assemble(3, n, 7, tuple(rng.uniform(0.0, 100.0, 3))))
+    return sys
+
+
+BATCH = small_batch()
+
+
+@pytest.mark.parametrize("variant", list(ALG))
+def test_batched_equals_individual_oracle_solves(variant):
+    require_gpu()
+    say(f"batched {variant}: {len(BATCH)} systems, N = {[A.n for A in BATCH]}")
+    bs = [oracle.spmv(A, inputs.batch_x_true(k, A.n)) for k, A in enumerate(BATCH)]
+    ops = [csr_op(A) for A in BATCH]
+    kw = dict(tol=1e-10, maxit=3000, rr_period=17)
+    xs, infos = solver.solve_batched(ops, [dev_t(b) for b in bs], variant=variant, **kw)
+    for k, (A, b) in enumerate(zip(BATCH, bs)):
+        x_or, i_or = oracle.solve(A, b, algo=ALG[variant], **kw)
+        info = infos[k]
+        assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"]), (k, info, i_or)
+        assert same(host(xs[k]), x_or), k
+        assert same([info.relres_rec, info.relres_true], [i_or["relres_rec"], i_or["relres_true"]]), k
+    # statuses differ in general: the loop above covers successes and the tiny systems' early exits
+
+
+def test_batched_x0_maxit_and_shapes():
+    require_gpu()
+    import os
+    sub = BATCH[3:8]
+    bs = [oracle.spmv(A, inputs.batch_x_true(k, A.n)) for k, A in enumerate(sub)]
+    x0s = [inputs.random_vector(A.n, 30 + k) for k, A in enumerate(sub)]
+    ops = [csr_op(A) for A in sub]
+    for kw in (dict(tol=0.0, maxit=23, rr_period=5), dict(tol=1e-9, maxit=40, rr_period=0)):
+        ref = [oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, x0=x0, **kw) for A, b, x0 in zip(sub, bs, x0s)]
+        old = os.environ.get("PBCGS_BATCH_GCAP")
+        try:
+            for gcap in ("1", "4", "64"):
+                os.environ["PBCGS_BATCH_GCAP"] = gcap
+                for graph in (True, False):
+                    say(f"batched x0 {kw} gcap={gcap} graph={graph}")
+                    xs, infos = solver.solve_batched(ops, [dev_t(b) for b in bs], [dev_t(x0) for x0 in x0s],
+                                                     variant="pbicgstab_rr", graph=graph, **kw)
+                    for k, (x_or, i_or) in enumerate(ref):
+                        assert (infos[k].status, infos[k].iters) == (i_or["status"], i_or["iters"])
+                        assert same(host(xs[k]), x_or)
+        finally:
+            if old is None:
+                os.environ.pop("PBCGS_BATCH_GCAP", None)
+            else:
+                os.environ["PBCGS_BATCH_GCAP"] = old
+
+
+def test_batched_errors():
+    require_gpu()
+    from paper_1612_01395_amd import _lib
+    A = BATCH[5]
+    op = csr_op(A)
+    b = dev_t(oracle.spmv(A, inputs.x_true(A.n)))
+    st = solver.stencil(8, 8, 1, [-1.0, -1.0, 4.5, -1.0, -1.0])
+    with pytest.raises(_lib.PbcgsError):
+        solver.solve_batched([op, st], [b, dev_t(np.ones(64))])
+    with pytest.raises(ValueError):
+        solver.solve_batched([], [])
