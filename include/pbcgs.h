@@ -147,6 +147,24 @@ int pbcgs_op_stencil(pbcgs_ctx_t ctx, int32_t nx, int32_t ny, int32_t nz, int32_
 
 int pbcgs_op_destroy(pbcgs_op_t op);
 
+/*
+ * Transpose of a CSR operator, for the adjoint solve A^T lambda = g that
+ * differentiates a loss through A x = b (lambda = A^{-T} dL/dx gives
+ * dL/db = lambda and dL/da_ij = -lambda_i x_j).  *out receives a new CSR
+ * operator whose arrays the library allocates and frees with it.  Row j of
+ * A^T lists column j of A in ascending row order, so its products sum in
+ * ascending column order like every other operator; the result does not
+ * depend on the order of the device's atomic operations.  ERR_UNSUPPORTED
+ * for a stencil.
+ */
+int pbcgs_op_transpose(pbcgs_ctx_t ctx, pbcgs_op_t A, pbcgs_op_t* out);
+
+/*
+ * grad[k] := -lambda[i] * x[j] for every stored entry k = (i, j) of the CSR
+ * operator A (device arrays: lambda, x of n doubles, grad of nnz doubles).
+ */
+int pbcgs_csr_outer_grad(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* lambda, const double* x, double* grad);
+
 /* Number of rows of op (host), or a negative status. */
 int64_t pbcgs_op_rows(pbcgs_op_t op);
 

@@ -316,6 +316,25 @@ def solve_mp(A: CSR, b, *, dinv=None, x0=None, tol: float = 1e-10, maxit: int = 
     return x, info
 
 
+def transpose(A: CSR) -> CSR:
+    """A^T by its definition: row j lists column j of A in ascending row order
+    (a stable sort of the entries by column; the row-major entry order breaks
+    ties)."""
+    rows = np.repeat(np.arange(A.n, dtype=np.int32), np.diff(A.row_ptr))
+    order = np.argsort(A.col, kind="stable")
+    counts = np.bincount(A.col, minlength=A.n)
+    rp = np.zeros(A.n + 1, np.int64)
+    rp[1:] = np.cumsum(counts)
+    return CSR(rp.astype(np.int32), rows[order], A.val[order])
+
+
+def outer_grad(A: CSR, lam, x) -> np.ndarray:
+    """dL/da_ij = -lambda_i x_j at every stored entry (i, j): the gradient of a
+    loss through A x = b, with lambda = A^{-T} dL/dx."""
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    return -(np.asarray(lam, dtype=np.float64)[rows] * np.asarray(x, dtype=np.float64)[A.col])
+
+
 def counters() -> dict:
     out = np.zeros(6, np.int64)
     lib().or_counters_get(out)

@@ -1263,6 +1263,100 @@ __global__ __launch_bounds__(kWG) void k_dinv_const(int32_t n, const double* din
   if (!(dinv[row] == dinv[0]) || !finite(dinv[row]) || dinv[row] == 0.0) atomicOr(flag, 2);
 }
 
+// ---------------------------------------------------------------------------
+// Transpose of a CSR matrix (for the adjoint solve A^T lambda = g).  Row j of
+// A^T lists the entries of column j of A in ascending row order (ties, which
+// only duplicate entries can produce, in stored order), so that the SpMV with
+// A^T sums in ascending column order as every other product does.
+// ---------------------------------------------------------------------------
+constexpr int kScanChunk = 4096;  // entries per workgroup in the scans below
+
+__global__ __launch_bounds__(kWG) void k_count_cols(CsrOp op, int64_t nnz, int32_t* __restrict__ cnt) {
+  for (int64_t k = (int64_t)blockIdx.x * kWG + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * kWG)
+    atomicAdd(&cnt[op.ci[k]], 1);
+}
+
+// Exclusive prefix sum of the kScanChunk values of each workgroup (in place
+// into out) and the chunk's total into bsum.
+__global__ __launch_bounds__(kWG) void k_scan_chunks(const int32_t* __restrict__ in, int32_t n,
+                                                     int32_t* __restrict__ out, int32_t* __restrict__ bsum) {
+  __shared__ int32_t tsum[kWG];
+  constexpr int per = kScanChunk / kWG;
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * per;
+  int32_t v[per];
+  int32_t acc = 0;
+  for (int j = 0; j < per; ++j) {
+    v[j] = (base + j < n) ? in[base + j] : 0;
+    acc += v[j];
+  }
+  tsum[threadIdx.x] = acc;
+  __syncthreads();
+  // inclusive scan of the thread totals (Hillis-Steele)
+  for (int d = 1; d < kWG; d <<= 1) {
+    const int32_t t = (threadIdx.x >= (unsigned)d) ? tsum[threadIdx.x - d] : 0;
+    __syncthreads();
+    tsum[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int32_t run = tsum[threadIdx.x] - acc;
+  for (int j = 0; j < per; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == kWG - 1) bsum[blockIdx.x] = tsum[kWG - 1];
+}
+
+// Adds the exclusive prefix of the chunk totals (boff) to every chunk.
+__global__ __launch_bounds__(kWG) void k_scan_add(int32_t* __restrict__ out, int32_t n, const int32_t* __restrict__ boff) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < n) out[i] += boff[i / kScanChunk];
+}
+
+// Scatter entry k = (i, j, a_ij) to row j of A^T; orig keeps k for the sort.
+__global__ __launch_bounds__(kWG) void k_fill_t(CsrOp op, int32_t* __restrict__ cursor, int32_t* __restrict__ ci_t,
+                                                double* __restrict__ va_t, int32_t* __restrict__ orig) {
+  const int32_t i = blockIdx.x * kWG + threadIdx.x;
+  if (i >= op.n) return;
+  for (int32_t k = op.rp[i]; k < op.rp[i + 1]; ++k) {
+    const int32_t pos = atomicAdd(&cursor[op.ci[k]], 1);
+    ci_t[pos] = i;
+    va_t[pos] = op.va[k];
+    orig[pos] = k;
+  }
+}
+
+// Orders each row of A^T by (row of A, stored position): insertion sort.
+__global__ __launch_bounds__(kWG) void k_sort_t(int32_t n, const int32_t* __restrict__ rp_t, int32_t* __restrict__ ci_t,
+                                                double* __restrict__ va_t, int32_t* __restrict__ orig) {
+  const int32_t j = blockIdx.x * kWG + threadIdx.x;
+  if (j >= n) return;
+  const int32_t b = rp_t[j], e = rp_t[j + 1];
+  for (int32_t k = b + 1; k < e; ++k) {
+    const int32_t c = ci_t[k], o = orig[k];
+    const double v = va_t[k];
+    int32_t m = k - 1;
+    while (m >= b && (ci_t[m] > c || (ci_t[m] == c && orig[m] > o))) {
+      ci_t[m + 1] = ci_t[m];
+      va_t[m + 1] = va_t[m];
+      orig[m + 1] = orig[m];
+      --m;
+    }
+    ci_t[m + 1] = c;
+    va_t[m + 1] = v;
+    orig[m + 1] = o;
+  }
+}
+
+// Gradient of a loss L(x) through A x = b with respect to the stored entries:
+// dL/da_ij = -lambda_i x_j, lambda = A^{-T} dL/dx.
+__global__ __launch_bounds__(kWG) void k_outer_grad(CsrOp op, const double* __restrict__ lam,
+                                                    const double* __restrict__ x, double* __restrict__ g) {
+  const int32_t i = blockIdx.x * kWG + threadIdx.x;
+  if (i >= op.n) return;
+  const double li = lam[i];
+  for (int32_t k = op.rp[i]; k < op.rp[i + 1]; ++k) g[k] = -(li * x[op.ci[k]]);
+}
+
 // CSR structure check: flag bit 0 on a malformed row pointer or column.
 __global__ __launch_bounds__(kWG) void k_csr_check(CsrOp op, int32_t n, int64_t nnz, int32_t* flag) {
   const int32_t row = blockIdx.x * kWG + threadIdx.x;

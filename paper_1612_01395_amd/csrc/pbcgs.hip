@@ -75,6 +75,10 @@ struct pbcgs_op_s {
   const double* va = nullptr;
   int32_t nx = 0, ny = 0, nz = 0;
   double coef[7] = {0, 0, 0, 0, 0, 0, 0};
+  // arrays the library allocated for this operator (a transpose), freed with it
+  int32_t* own_rp = nullptr;
+  int32_t* own_ci = nullptr;
+  double* own_va = nullptr;
 };
 
 namespace {
@@ -1014,6 +1018,9 @@ int pbcgs_op_destroy(pbcgs_op_t op) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
     ctx->graphs.clear();
+    if (op->own_rp) (void)hipFree(op->own_rp);
+    if (op->own_ci) (void)hipFree(op->own_ci);
+    if (op->own_va) (void)hipFree(op->own_va);
   }
   delete op;
   return PBCGS_SUCCESS;
@@ -1256,6 +1263,99 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     if (pc == PC_VEC) return Driver<Op, PC_VEC>(ctx, op, a, o).run(info);
     return Driver<Op, PC_SCALAR>(ctx, op, a, o).run(info);
   });
+}
+
+// Transpose of a CSR operator (see include/pbcgs.h).
+int pbcgs_op_transpose(pbcgs_ctx_t ctx, pbcgs_op_t A, pbcgs_op_t* out) {
+  if (!ctx || !A || !out) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  if (A->ctx != ctx) return fail(ctx, PBCGS_ERR_INVALID_ARG, "operator belongs to another context");
+  if (A->kind != OP_CSR) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "only CSR operators are transposed");
+  DeviceGuard guard(ctx->device);
+  const int32_t n = A->n;
+  const int64_t nnz = A->nnz;
+  const int32_t nchunks = (int32_t)(((int64_t)n + kScanChunk - 1) / kScanChunk);
+  int32_t *rp_t = nullptr, *ci_t = nullptr, *cnt = nullptr, *orig = nullptr, *bsum = nullptr, *boff = nullptr;
+  double* va_t = nullptr;
+  auto cleanup = [&]() {
+    if (cnt) (void)hipFree(cnt);
+    if (orig) (void)hipFree(orig);
+    if (bsum) (void)hipFree(bsum);
+    if (boff) (void)hipFree(boff);
+  };
+  bool ok = hipMalloc(&rp_t, sizeof(int32_t) * ((size_t)n + 1)) == hipSuccess &&
+            hipMalloc(&ci_t, sizeof(int32_t) * std::max<size_t>((size_t)nnz, 1)) == hipSuccess &&
+            hipMalloc(&va_t, sizeof(double) * std::max<size_t>((size_t)nnz, 1)) == hipSuccess &&
+            hipMalloc(&cnt, sizeof(int32_t) * ((size_t)n + 1)) == hipSuccess &&
+            hipMalloc(&orig, sizeof(int32_t) * std::max<size_t>((size_t)nnz, 1)) == hipSuccess &&
+            hipMalloc(&bsum, sizeof(int32_t) * (size_t)nchunks) == hipSuccess &&
+            hipMalloc(&boff, sizeof(int32_t) * (size_t)nchunks) == hipSuccess;
+  if (!ok) {
+    cleanup();
+    if (rp_t) (void)hipFree(rp_t);
+    if (ci_t) (void)hipFree(ci_t);
+    if (va_t) (void)hipFree(va_t);
+    return fail(ctx, PBCGS_ERR_ALLOC, "transpose allocation failed");
+  }
+  hipStream_t s = ctx->stream;
+  const CsrOp op{A->rp, A->ci, A->va, n};
+  auto run = [&]() -> int {
+    HIP_TRY(ctx, hipMemsetAsync(cnt, 0, sizeof(int32_t) * ((size_t)n + 1), s));
+    const int g = (int)std::min<int64_t>((nnz + kWG - 1) / kWG, 8192);
+    if (nnz > 0) k_count_cols<<<g, kWG, 0, s>>>(op, nnz, cnt);
+    // row pointers of A^T: exclusive prefix sum of the column counts
+    k_scan_chunks<<<nchunks, kWG, 0, s>>>(cnt, n, rp_t, bsum);
+    HIP_TRY(ctx, hipGetLastError());
+    std::vector<int32_t> hb((size_t)nchunks), ho((size_t)nchunks);
+    HIP_TRY(ctx, hipMemcpyAsync(hb.data(), bsum, sizeof(int32_t) * hb.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    int64_t run_total = 0;
+    for (int32_t c = 0; c < nchunks; ++c) {
+      ho[(size_t)c] = (int32_t)run_total;
+      run_total += hb[(size_t)c];
+    }
+    if (run_total != nnz) return fail(ctx, PBCGS_ERR_INVALID_ARG, "column counts do not add up to nnz");
+    HIP_TRY(ctx, hipMemcpyAsync(boff, ho.data(), sizeof(int32_t) * ho.size(), hipMemcpyHostToDevice, s));
+    k_scan_add<<<(n + kWG - 1) / kWG, kWG, 0, s>>>(rp_t, n, boff);
+    const int32_t last = (int32_t)nnz;
+    HIP_TRY(ctx, hipMemcpyAsync(rp_t + n, &last, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // cursors start at the row pointers; scatter, then order each row
+    HIP_TRY(ctx, hipMemcpyAsync(cnt, rp_t, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    k_fill_t<<<(n + kWG - 1) / kWG, kWG, 0, s>>>(op, cnt, ci_t, va_t, orig);
+    k_sort_t<<<(n + kWG - 1) / kWG, kWG, 0, s>>>(n, rp_t, ci_t, va_t, orig);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return PBCGS_SUCCESS;
+  };
+  const int rc = run();
+  cleanup();
+  if (rc != PBCGS_SUCCESS) {
+    (void)hipFree(rp_t);
+    (void)hipFree(ci_t);
+    (void)hipFree(va_t);
+    return rc;
+  }
+  pbcgs_op_t T = new pbcgs_op_s();
+  T->ctx = ctx;
+  T->kind = OP_CSR;
+  T->n = n;
+  T->nnz = nnz;
+  T->rp = T->own_rp = rp_t;
+  T->ci = T->own_ci = ci_t;
+  T->va = T->own_va = va_t;
+  *out = T;
+  return PBCGS_SUCCESS;
+}
+
+// Entry gradient dL/da_ij = -lambda_i x_j (see include/pbcgs.h).
+int pbcgs_csr_outer_grad(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* lambda, const double* x, double* grad) {
+  if (!ctx || !A || !lambda || !x || !grad) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  if (A->ctx != ctx) return fail(ctx, PBCGS_ERR_INVALID_ARG, "operator belongs to another context");
+  if (A->kind != OP_CSR) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "CSR operators only");
+  DeviceGuard guard(ctx->device);
+  k_outer_grad<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(CsrOp{A->rp, A->ci, A->va, A->n}, lambda, x, grad);
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return PBCGS_SUCCESS;
 }
 
 // Batched solve (see include/pbcgs.h).

@@ -130,6 +130,25 @@ def stencil(nx: int, ny: int, nz: int, coef, ctx: Context | None = None) -> Oper
     return Operator(ctx, h, nx * ny * nz, (), f"stencil{len(coef)}")
 
 
+def transpose(A: Operator) -> Operator:
+    """The transposed CSR operator (the library owns its arrays)."""
+    h = ctypes.c_void_p()
+    L.check(L.lib().pbcgs_op_transpose(A.ctx.handle, A.handle, ctypes.byref(h)), A.ctx.handle)
+    return Operator(A.ctx, h, A.n, (A,), "csr")
+
+
+def csr_outer_grad(A: Operator, lam: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """grad[k] = -lam[i] x[j] for every stored entry k = (i, j) of the CSR operator A."""
+    _check_vec(lam, A.n, "lam")
+    _check_vec(x, A.n, "x")
+    nnz = A._keep[2].numel() if A.kind == "csr" and len(A._keep) == 3 else None
+    if nnz is None:
+        raise ValueError("csr_outer_grad needs a CSR operator built from row_ptr, col_idx, val")
+    g = torch.empty(nnz, dtype=torch.float64, device=lam.device)
+    L.check(L.lib().pbcgs_csr_outer_grad(A.ctx.handle, A.handle, _ptr(lam), _ptr(x), _ptr(g)), A.ctx.handle)
+    return g
+
+
 def convdiff_nnz(dim: int, n: int, npts: int) -> int:
     return int(L.check(L.lib().pbcgs_convdiff_nnz(dim, n, npts)))
 
@@ -290,3 +309,47 @@ def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str 
     out = [SolveInfo(i.iters, i.n_rr, i.status, i.syncs_per_iter, i.relres_rec, i.relres_true, i.ms,
                      tuple(i.kernel_ms), tuple(i.kernel_calls)) for i in infos]
     return xs, out
+
+
+class SolveFn(torch.autograd.Function):
+    """x = A^{-1} b for the CSR matrix (row_ptr, col_idx, vals), differentiable
+    in vals and b.  The backward pass is the adjoint solve with A^T on the
+    same solver: lambda = A^{-T} dL/dx, dL/db = lambda, dL/dvals_k =
+    -lambda_i x_j for the stored entry k = (i, j).  ``opts`` are keyword
+    arguments of :func:`solve` (the adjoint solve uses them too, with
+    ``adjoint_tol`` in place of ``tol`` when given)."""
+
+    @staticmethod
+    def forward(ctx, vals, b, row_ptr, col_idx, opts):
+        opts = dict(opts or {})
+        adj_tol = opts.pop("adjoint_tol", None)
+        A = csr(row_ptr, col_idx, vals)
+        x, info = solve(A, b, **opts)
+        ctx.save_for_backward(vals, row_ptr, col_idx, x)
+        ctx.opts = opts
+        ctx.adj_tol = adj_tol
+        ctx.info = info
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        vals, row_ptr, col_idx, x = ctx.saved_tensors
+        A = csr(row_ptr, col_idx, vals)
+        AT = transpose(A)
+        opts = dict(ctx.opts)
+        opts.pop("x0", None)
+        opts.pop("out", None)
+        if ctx.adj_tol is not None:
+            opts["tol"] = ctx.adj_tol
+        lam, _ = solve(AT, gx.contiguous(), **opts)
+        gvals = csr_outer_grad(A, lam, x) if ctx.needs_input_grad[0] else None
+        gb = lam if ctx.needs_input_grad[1] else None
+        return gvals, gb, None, None, None
+
+
+def solve_adjoint_batched(ops: list, gs: list, **kw):
+    """lambda_k = A_k^{-T} g_k for a batch of CSR operators (one batched call on
+    their transposes); returns (lambdas, infos, transposes)."""
+    ts = [transpose(A) for A in ops]
+    lams, infos = solve_batched(ts, gs, **kw)
+    return lams, infos, ts
