@@ -68,7 +68,8 @@ def parse():
     p.add_argument("--n", type=int, default=128, help="grid side of the 3-D workload")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
-    p.add_argument("--only", default="", help="comma list of legs to run: pipe,bicg,explicit,stencil,precision")
+    p.add_argument("--only", default="",
+                   help="comma list of legs to run: pipe,bicg,explicit,stencil,precision,batched")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
     return p.parse_args()
@@ -119,7 +120,7 @@ def main():
     dev = torch.device("cuda", 0)
     w = inputs.workload("c2", n=args.n)
     N = w.N
-    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "precision"}
+    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "precision", "batched"}
 
     # ---- inputs resident in HBM -------------------------------------------------
     rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
@@ -231,6 +232,52 @@ def main():
         del A4, rp4, col4, val4, b4, x4, x64
         torch.cuda.empty_cache()
 
+    # ---- batched form: 512 independent 2-D systems of uneven size, forward and adjoint
+    batched = None
+    if "batched" in legs:
+        systems = inputs.batch_systems()
+        bops, bbs, bws, bN, bnnz = [], [], [], [], []
+        for sy in systems:
+            rpk, colk, valk = solver.assemble_convdiff(2, sy.n, 5, sy.beta)
+            Ak = solver.csr(rpk, colk, valk)
+            Nk = sy.n * sy.n
+            bops.append(Ak)
+            bbs.append(solver.spmv(Ak, torch.from_numpy(inputs.batch_x_true(sy.k, Nk)).to(dev)))
+            bws.append(torch.from_numpy(inputs.batch_loss_weights(sy.k, Nk)).to(dev))
+            bN.append(Nk)
+            bnnz.append(valk.numel())
+        bts = [solver.transpose(Ak) for Ak in bops]
+        outs = [torch.empty_like(bk) for bk in bbs]
+        kwb = dict(tol=1e-8, maxit=20000, rr_period=50)
+
+        def batch_leg(ops_, rhs, variant, passes):
+            solver.solve_batched(ops_, rhs, variant=variant, outs=outs, **kwb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 2
+            for _ in range(reps):
+                _, infs = solver.solve_batched(ops_, rhs, variant=variant, outs=outs, **kwb)
+            torch.cuda.synchronize()
+            dtb = (time.perf_counter() - t0) / reps
+            its = [i.iters for i in infs]
+            byts = sum(it_ * (passes * 8 * Nk + 2 * (4 * (Nk + 1) + 12 * zk)) for it_, Nk, zk in zip(its, bN, bnnz))
+            return {"ms_per_batch_solve": round(dtb * 1e3, 2), "iters_total": int(sum(its)),
+                    "iters_max": int(max(its)), "iters_per_s_aggregate": round(sum(its) / dtb, 1),
+                    "gbps_effective": round(byts / dtb / 1e9, 1),
+                    "all_converged": all(i.status == 0 for i in infs),
+                    "max_relres_true": max(i.relres_true for i in infs)}
+
+        batched = {"workload": f"{len(systems)} 2-D 5-point systems, side log-uniform in [32, 512], "
+                               f"beta ~ U[0,200]^2, sum N = {sum(bN)}, sum nnz = {sum(bnnz)}, CSR FP64, "
+                               f"no preconditioner, tol 1e-8, RR every 50; one step = all systems solved",
+                   "pbicgstab_rr": batch_leg(bops, bbs, "pbicgstab_rr", 22),
+                   "bicgstab": batch_leg(bops, bbs, "bicgstab", 19),
+                   "adjoint_pbicgstab_rr": batch_leg(bts, bws, "pbicgstab_rr", 22)}
+        batched["pbicgstab_over_bicgstab_time"] = round(
+            batched["bicgstab"]["ms_per_batch_solve"] / batched["pbicgstab_rr"]["ms_per_batch_solve"], 4)
+        del bops, bbs, bws, bts, outs
+        torch.cuda.empty_cache()
+
     if args.copy_calib:
         # a plain copy of known size: 256 MiB read + 256 MiB written per dispatch
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -310,6 +357,8 @@ def main():
             out.setdefault("stencil", {})[variant] = leg_summary(key, variant, True, True)
     if precision is not None:
         out["precision_form"] = precision
+    if batched is not None:
+        out["batched"] = batched
     out["roofline"] = roofline
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

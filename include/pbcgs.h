@@ -210,6 +210,38 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
 int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const double* const* b,
                         double* const* x, const pbcgs_opts* opts, pbcgs_info* infos);
 
+/* Report of an autotuning run: candidates tried, their cost per iteration
+ * and the one kept. */
+typedef struct {
+    int32_t best;              /* the chosen value (R, or the workgroup cap)          */
+    int32_t ncand;             /* candidates tried (at most 12)                       */
+    int32_t cand[12];
+    double ms_per_iter[12];    /* measured wall time per iteration of each candidate  */
+    double best_ms_per_iter;
+} pbcgs_tune_report;
+
+/*
+ * Autotuner of the launch shape, measured on the device: runs `iters`
+ * iterations (tol 0) of the solve described by opts (b: DEVICE right-hand
+ * side; x is a scratch vector of its own) for every rows-per-wave block
+ * count R whose grid fits, and keeps the fastest R on the operator; later
+ * pbcgs_solve calls on A use it (the environment variables PBCGS_R and
+ * PBCGS_GTARGET still take precedence).  The shape never changes a result:
+ * every reduction is the same pairwise tree whatever R is.
+ */
+int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts* opts, int32_t iters,
+               pbcgs_tune_report* rep);
+
+/*
+ * The same for batched solves: tries per-system workgroup caps 8 .. 512 (a
+ * system of n rows gets the smallest R with at most that many workgroups)
+ * and keeps the fastest on the context for later pbcgs_solve_batched calls
+ * (PBCGS_BATCH_GCAP takes precedence).  Arguments as pbcgs_solve_batched,
+ * without x (scratch of its own).
+ */
+int pbcgs_tune_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const double* const* b,
+                       const pbcgs_opts* opts, int32_t iters, pbcgs_tune_report* rep);
+
 /*
  * Workload builder (not part of the method): assembles on the device the
  * h^2-scaled first-order upwind convection-diffusion operator used by the

@@ -53,6 +53,16 @@ class Info(ctypes.Structure):
     ]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [
+        ("best", ctypes.c_int32),
+        ("ncand", ctypes.c_int32),
+        ("cand", ctypes.c_int32 * 12),
+        ("ms_per_iter", ctypes.c_double * 12),
+        ("best_ms_per_iter", ctypes.c_double),
+    ]
+
+
 class PbcgsError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"pbcgs error {code}: {msg}")
@@ -83,6 +93,9 @@ _SIGNATURES = {
     "pbcgs_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
     "pbcgs_solve_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                            ctypes.POINTER(_vp), ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
+    "pbcgs_tune": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(Opts), _i32, ctypes.POINTER(TuneReport)]),
+    "pbcgs_tune_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(Opts),
+                                          _i32, ctypes.POINTER(TuneReport)]),
     "pbcgs_convdiff_nnz": (_i64, [_i32, _i32, _i32]),
     "pbcgs_assemble_convdiff": (ctypes.c_int, [_vp, _i32, _i32, _i32, ctypes.POINTER(_f64), _vp, _f64,
                                                _vp, _vp, _vp]),

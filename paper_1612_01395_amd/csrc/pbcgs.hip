@@ -58,6 +58,7 @@ struct pbcgs_ctx_s {
   size_t bpart_cap = 0;
   DevState* bhst = nullptr;  // pinned, two poll slots of bst_cap states
   size_t bhst_cap = 0;
+  int32_t batch_gcap = 0;    // per-system workgroup cap chosen by pbcgs_tune_batched (0: 64)
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
   hipEvent_t ev_poll[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> kev;  // pool for per-kernel timing
@@ -75,6 +76,7 @@ struct pbcgs_op_s {
   const double* va = nullptr;
   int32_t nx = 0, ny = 0, nz = 0;
   double coef[7] = {0, 0, 0, 0, 0, 0, 0};
+  int32_t tuned_R = 0;  // rows-per-wave blocks chosen by pbcgs_tune (0: default shape)
   // arrays the library allocated for this operator (a transpose), freed with it
   int32_t* own_rp = nullptr;
   int32_t* own_ci = nullptr;
@@ -122,11 +124,12 @@ struct Shape {
   int32_t n, R, G;
 };
 
-bool make_shape(int32_t n, Shape* sh) {
+bool make_shape(int32_t n, Shape* sh, int prefer_R = 0) {
   if (n <= 0) return false;
   int gt = env_int("PBCGS_GTARGET", 1024);
   if (gt < 1 || gt > kMaxG) gt = 1024;
-  const int forced = env_int("PBCGS_R", 0);
+  int forced = env_int("PBCGS_R", 0);
+  if (forced <= 0 && !std::getenv("PBCGS_GTARGET")) forced = prefer_R;  // an autotuned shape
   for (int R = 1; R <= kMaxR; R *= 2) {
     const int64_t G = ((int64_t)n + 256 * (int64_t)R - 1) / (256 * (int64_t)R);
     if (forced > 0 && R != forced) continue;
@@ -1105,7 +1108,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
   if ((const void*)b == (const void*)x) return fail(ctx, PBCGS_ERR_INVALID_ARG, "b and x must not overlap");
   DeviceGuard guard(ctx->device);
   Shape sh;
-  if (!make_shape(A->n, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows");
+  if (!make_shape(A->n, &sh, A->tuned_R)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows");
   std::memset(info, 0, sizeof *info);
 
   const size_t np = padded(A->n);
@@ -1372,7 +1375,7 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
   if (o.maxit < 0 || !(o.tol >= 0.0)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad maxit or tol");
   if (o.variant == PBCGS_PBICGSTAB_RR && o.rr_period < 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad rr_period");
   if (o.history) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves keep no history");
-  int gcap = env_int("PBCGS_BATCH_GCAP", 64);
+  int gcap = env_int("PBCGS_BATCH_GCAP", ctx->batch_gcap > 0 ? ctx->batch_gcap : 64);
   if (gcap < 1 || gcap > kMaxG) gcap = 64;
   std::vector<SysDesc> desc((size_t)nsys);
   int64_t totalG = 0;
@@ -1430,6 +1433,107 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the host tables may go away after this
   BatchDriver drv(ctx, o, nsys, (int32_t)totalG);
   return drv.run(infos);
+}
+
+// Autotuner of the launch shape (see include/pbcgs.h).
+int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts* opts, int32_t iters,
+               pbcgs_tune_report* rep) {
+  if (!ctx || !A || !b || !opts || !rep) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  if (iters < 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "iters must be positive");
+  DeviceGuard guard(ctx->device);
+  std::memset(rep, 0, sizeof *rep);
+  double* xs = nullptr;
+  if (hipMalloc(&xs, sizeof(double) * (size_t)A->n) != hipSuccess) return fail(ctx, PBCGS_ERR_ALLOC, "tune scratch");
+  pbcgs_opts o = *opts;
+  o.tol = 0.0;
+  o.maxit = iters;
+  o.history = nullptr;
+  o.flags = 0;
+  o.check_every = 0;
+  const int32_t saved = A->tuned_R;
+  double best = -1.0;
+  int rc = PBCGS_SUCCESS;
+  for (int R = 1; R <= kMaxR && rep->ncand < 12; R *= 2) {
+    const int64_t G = ((int64_t)A->n + 256 * (int64_t)R - 1) / (256 * (int64_t)R);
+    if (G > kMaxG) continue;
+    A->tuned_R = R;
+    double ms = 0.0;
+    for (int t = 0; t < 2 && rc >= 0; ++t) {  // the first run captures the graphs
+      pbcgs_info info;
+      HIP_TRY(ctx, hipMemsetAsync(xs, 0, sizeof(double) * (size_t)A->n, ctx->stream));
+      rc = pbcgs_solve(ctx, A, b, xs, nullptr, &o, &info);
+      ms = info.ms;
+    }
+    if (rc < 0) break;
+    const double per = ms / iters;
+    rep->cand[rep->ncand] = R;
+    rep->ms_per_iter[rep->ncand] = per;
+    ++rep->ncand;
+    if (best < 0.0 || per < best) { best = per; rep->best = R; }
+    if (G <= 1) break;  // larger R only adds idle waves
+  }
+  (void)hipFree(xs);
+  if (rc < 0) {
+    A->tuned_R = saved;
+    return rc;
+  }
+  A->tuned_R = rep->best;
+  rep->best_ms_per_iter = best;
+  return PBCGS_SUCCESS;
+}
+
+int pbcgs_tune_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const double* const* b,
+                       const pbcgs_opts* opts, int32_t iters, pbcgs_tune_report* rep) {
+  if (!ctx || !A || !b || !opts || !rep || nsys <= 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad argument");
+  if (iters < 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "iters must be positive");
+  DeviceGuard guard(ctx->device);
+  std::memset(rep, 0, sizeof *rep);
+  size_t tot = 0;
+  for (int32_t k = 0; k < nsys; ++k) {
+    if (!A[k]) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL operator");
+    tot += padded(A[k]->n);
+  }
+  double* xs = nullptr;
+  if (hipMalloc(&xs, sizeof(double) * std::max<size_t>(tot, 1)) != hipSuccess)
+    return fail(ctx, PBCGS_ERR_ALLOC, "tune scratch");
+  std::vector<double*> xp((size_t)nsys);
+  size_t off = 0;
+  for (int32_t k = 0; k < nsys; ++k) {
+    xp[(size_t)k] = xs + off;
+    off += padded(A[k]->n);
+  }
+  pbcgs_opts o = *opts;
+  o.tol = 0.0;
+  o.maxit = iters;
+  o.history = nullptr;
+  o.flags = 0;
+  const int32_t saved = ctx->batch_gcap;
+  std::vector<pbcgs_info> infos((size_t)nsys);
+  double best = -1.0;
+  int rc = PBCGS_SUCCESS;
+  for (int gcap = 8; gcap <= 512 && rep->ncand < 12; gcap *= 2) {
+    ctx->batch_gcap = gcap;
+    double ms = 0.0;
+    for (int t = 0; t < 2 && rc >= 0; ++t) {
+      HIP_TRY(ctx, hipMemsetAsync(xs, 0, sizeof(double) * std::max<size_t>(tot, 1), ctx->stream));
+      rc = pbcgs_solve_batched(ctx, nsys, A, b, xp.data(), &o, infos.data());
+      ms = infos[0].ms;
+    }
+    if (rc < 0) break;
+    const double per = ms / iters;
+    rep->cand[rep->ncand] = gcap;
+    rep->ms_per_iter[rep->ncand] = per;
+    ++rep->ncand;
+    if (best < 0.0 || per < best) { best = per; rep->best = gcap; }
+  }
+  (void)hipFree(xs);
+  if (rc < 0) {
+    ctx->batch_gcap = saved;
+    return rc;
+  }
+  ctx->batch_gcap = rep->best;
+  rep->best_ms_per_iter = best;
+  return PBCGS_SUCCESS;
 }
 
 }  // extern "C"

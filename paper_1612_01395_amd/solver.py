@@ -353,3 +353,47 @@ def solve_adjoint_batched(ops: list, gs: list, **kw):
     ts = [transpose(A) for A in ops]
     lams, infos = solve_batched(ts, gs, **kw)
     return lams, infos, ts
+
+
+def _opts(variant="pbicgstab_rr", precond=None, precision="fp64", tol=1e-8, maxit=2000, rr_period=50, rr_max=-1):
+    o = L.Opts()
+    o.variant = VARIANTS[variant]
+    o.precond = PRECONDS[precond]
+    o.precision = PRECISIONS[precision]
+    o.maxit = int(maxit)
+    o.tol = float(tol)
+    o.rr_period = int(rr_period)
+    o.rr_max = int(rr_max)
+    o.check_every = 0
+    o.flags = 0
+    o.history = None
+    return o
+
+
+def _report(r) -> dict:
+    return {"best": r.best, "best_ms_per_iter": r.best_ms_per_iter,
+            "tried": {int(r.cand[i]): float(r.ms_per_iter[i]) for i in range(r.ncand)}}
+
+
+def tune(A: Operator, b: torch.Tensor, iters: int = 20, **opts) -> dict:
+    """Time `iters` iterations for each launch shape (rows-per-wave blocks R)
+    and keep the fastest on A for later solves; returns the report."""
+    _check_vec(b, A.n, "b")
+    o = _opts(**opts)
+    r = L.TuneReport()
+    L.check(L.lib().pbcgs_tune(A.ctx.handle, A.handle, _ptr(b), ctypes.byref(o), int(iters), ctypes.byref(r)),
+            A.ctx.handle)
+    return _report(r)
+
+
+def tune_batched(ops: list, bs: list, iters: int = 20, **opts) -> dict:
+    """The same for batched solves: the per-system workgroup cap, kept on the context."""
+    nsys = len(ops)
+    ctx = ops[0].ctx
+    VP = ctypes.c_void_p * nsys
+    o = _opts(**opts)
+    r = L.TuneReport()
+    L.check(L.lib().pbcgs_tune_batched(ctx.handle, nsys, VP(*[A.handle.value for A in ops]),
+                                       VP(*[b.data_ptr() for b in bs]), ctypes.byref(o), int(iters),
+                                       ctypes.byref(r)), ctx.handle)
+    return _report(r)

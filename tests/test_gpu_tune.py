@@ -1,0 +1,42 @@
+"""The autotuner: it measures every launch shape, keeps the fastest, and
+cannot change a result (the reductions are the same pairwise trees for every
+shape), so solves after tuning equal the oracle bit for bit."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_01395_amd import inputs, solver
+from gpu_util import csr_op, dev_t, host, require_gpu, same, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_single_system_keeps_results():
+    require_gpu()
+    A = oracle.assemble_workload(inputs.workload("c2", n=40))
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    op = csr_op(A)
+    d = oracle.jacobi_dinv(A)
+    x_or, i_or = oracle.solve_folded(A, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=d, tol=1e-10, rr_period=20)
+    rep = solver.tune(op, dev_t(b), iters=10, variant="pbicgstab_rr", precond="jacobi_folded", rr_period=20)
+    say(f"tune: {rep}")
+    assert rep["best"] in rep["tried"] and len(rep["tried"]) >= 2
+    assert rep["best_ms_per_iter"] == min(rep["tried"].values())
+    x, info = solver.solve(op, dev_t(b), variant="pbicgstab_rr", precond="jacobi_folded", tol=1e-10, rr_period=20)
+    assert info.iters == i_or["iters"] and same(host(x), x_or)
+
+
+def test_tune_batched_keeps_results():
+    require_gpu()
+    systems = inputs.batch_systems(count=24, lo=8, hi=160)
+    As = [oracle.assemble(2, sy.n, 5, sy.beta) for sy in systems]
+    bs = [oracle.spmv(A, inputs.batch_x_true(sy.k, A.n)) for sy, A in zip(systems, As)]
+    ops = [csr_op(A) for A in As]
+    rep = solver.tune_batched(ops, [dev_t(b) for b in bs], iters=8, variant="pbicgstab_rr")
+    say(f"tune batched: {rep}")
+    assert rep["best"] in rep["tried"]
+    xs, infos = solver.solve_batched(ops, [dev_t(b) for b in bs], variant="pbicgstab_rr", tol=1e-9)
+    for k, (A, b) in enumerate(zip(As, bs)):
+        x_or, i_or = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, tol=1e-9)
+        assert infos[k].iters == i_or["iters"] and same(host(xs[k]), x_or)
