@@ -69,7 +69,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     p.add_argument("--only", default="",
-                   help="comma list of legs to run: pipe,bicg,explicit,stencil,precision,batched")
+                   help="comma list of legs to run: pipe,bicg,explicit,stencil,precision,batched,sweep")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
     return p.parse_args()
@@ -120,7 +120,8 @@ def main():
     dev = torch.device("cuda", 0)
     w = inputs.workload("c2", n=args.n)
     N = w.N
-    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "precision", "batched"}
+    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "precision", "batched",
+                                                         "sweep"}
 
     # ---- inputs resident in HBM -------------------------------------------------
     rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
@@ -231,6 +232,35 @@ def main():
                      "time_to_solution_speedup": round(f64["ms_per_solve"] / f32["ms_per_solve"], 4)}
         del A4, rp4, col4, val4, b4, x4, x64
         torch.cuda.empty_cache()
+
+    # ---- size sweep: where the two kernel boundaries per iteration pay off
+    sweep = None
+    if "sweep" in legs:
+        sweep = {}
+        for ns in (16, 24, 32, 48, 64, 96):
+            ws_ = inputs.workload("c2", n=ns)
+            rps, cols, vals = solver.assemble_convdiff(ws_.dim, ns, ws_.npts, ws_.beta)
+            As = solver.csr(rps, cols, vals)
+            bs_ = solver.spmv(As, torch.from_numpy(inputs.x_true(ws_.N)).to(dev))
+            xs_ = torch.empty_like(bs_)
+            row = {}
+            for variant in ("pbicgstab_rr", "bicgstab"):
+                kws = dict(variant=variant, precond="jacobi_folded", tol=ws_.tol, maxit=ws_.maxit,
+                           rr_period=ws_.rr_period, out=xs_)
+                solver.solve(As, bs_, **kws)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                its = 0
+                for _ in range(5):
+                    _, inf = solver.solve(As, bs_, **kws)
+                    its += inf.iters
+                torch.cuda.synchronize()
+                dts = time.perf_counter() - t0
+                row[variant] = {"iters_per_s": round(its / dts, 1), "us_per_iter": round(dts / its * 1e6, 2),
+                                "iters_per_solve": inf.iters}
+            row["pbicgstab_over_bicgstab_iters_per_s"] = round(
+                row["pbicgstab_rr"]["iters_per_s"] / row["bicgstab"]["iters_per_s"], 4)
+            sweep[f"{ns}^3"] = row
 
     # ---- batched form: 512 independent 2-D systems of uneven size, forward and adjoint
     batched = None
@@ -359,6 +389,8 @@ def main():
         out["precision_form"] = precision
     if batched is not None:
         out["batched"] = batched
+    if sweep is not None:
+        out["size_sweep_3d_7pt_csr_folded_jacobi"] = sweep
     out["roofline"] = roofline
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
