@@ -364,9 +364,7 @@ struct Driver {
     if constexpr (MP) {
       k_mp_setup_r0<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, PB_SETUP1));
       k_mp_setup_w0<Op64><<<grid(), kWG, 0, s>>>(op64, L(PB_SETUP1, PB_SETUP2));
-      return;
-    }
-    if (o.variant == PBCGS_BICGSTAB) {
+    } else if (o.variant == PBCGS_BICGSTAB) {
       k_setup_r0<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
     } else {
       k_setup_r0<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
@@ -395,8 +393,14 @@ struct Driver {
       } else {
         timed(1, [&] { k_mp_pb<Op><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B)); });
       }
-      return;
+    } else {
+      iteration64(i);
     }
+  }
+
+  // Kernels of iteration i of the binary64 solvers.
+  void iteration64(int64_t i) {
+    hipStream_t s = ctx->stream;
     if (o.variant == PBCGS_BICGSTAB) {
       timed(0, [&] { k_b1<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_SETUP1, PB_B1, i == 0)); });
       k_b2<PC><<<grid(), kWG, 0, s>>>(L(PB_B1, -1));
@@ -439,7 +443,13 @@ struct Driver {
       if (iters_launched == 0) k_mp_finish<1><<<1, kWG, 0, s>>>(L(PB_SETUP2, -1));
       else k_mp_finish<0><<<1, kWG, 0, s>>>(L(PB_B, -1, false, was_forced(iters_launched - 1) ? 1 : 0));
       return;
+    } else {
+      finish64(iters_launched);
     }
+  }
+
+  void finish64(int64_t iters_launched) {
+    hipStream_t s = ctx->stream;
     if (o.variant == PBCGS_BICGSTAB) {
       if (iters_launched == 0) k_finish<2><<<1, kWG, 0, s>>>(L(PB_SETUP1, -1));
       return;
