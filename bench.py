@@ -69,7 +69,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     p.add_argument("--only", default="",
-                   help="comma list of legs to run: pipe,bicg,explicit,stencil,precision,batched,sweep")
+                   help="comma list of legs to run: pipe,bicg,explicit,stencil,precision,batched,sweep,paper")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
     return p.parse_args()
@@ -121,7 +121,7 @@ def main():
     w = inputs.workload("c2", n=args.n)
     N = w.N
     legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "precision", "batched",
-                                                         "sweep"}
+                                                         "sweep", "paper"}
 
     # ---- inputs resident in HBM -------------------------------------------------
     rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
@@ -232,6 +232,30 @@ def main():
                      "time_to_solution_speedup": round(f64["ms_per_solve"] / f32["ms_per_solve"], 4)}
         del A4, rp4, col4, val4, b4, x4, x64
         torch.cuda.empty_cache()
+
+    # ---- the paper's test problems (Section 5): 1000^2 five-point stencils, x_hat = 1, tol 1e-6
+    paper = None
+    if "paper" in legs:
+        eps = 1.0 - 0.001
+        paper = {}
+        for name, coef, variants in (("PTP1", [-eps, -1.0, 4.0, -eps, -1.0], ("bicgstab", "pbicgstab", "pbicgstab_rr")),
+                                     ("PTP2", [-1.0, -1.0, 1.0, -1.0, -1.0], ("bicgstab", "pbicgstab"))):
+            Sp = solver.stencil(1000, 1000, 1, coef)
+            bp = solver.spmv(Sp, torch.ones(1000 * 1000, dtype=torch.float64, device=dev))
+            xp = torch.empty_like(bp)
+            row = {}
+            for variant in variants:
+                kwp = dict(variant=variant, tol=1e-6, maxit=4000, rr_period=100, rr_max=10, out=xp)
+                solver.solve(Sp, bp, **kwp)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, inf = solver.solve(Sp, bp, **kwp)
+                torch.cuda.synchronize()
+                row[variant] = {"iterations": inf.iters, "ms": round((time.perf_counter() - t0) * 1e3, 2),
+                                "true_residual": inf.relres_true * torch.linalg.norm(bp).item()}
+            paper[name] = row
+        paper["note"] = ("paper (20 nodes, 240 ranks): PTP1 205-282 iterations, PTP2 1283-2112; "
+                         "matrix-free stencil here, bitwise equal to the CSR solve and the oracle")
 
     # ---- size sweep: where the two kernel boundaries per iteration pay off
     sweep = None
@@ -391,6 +415,8 @@ def main():
         out["batched"] = batched
     if sweep is not None:
         out["size_sweep_3d_7pt_csr_folded_jacobi"] = sweep
+    if paper is not None:
+        out["paper_test_problems"] = paper
     out["roofline"] = roofline
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
