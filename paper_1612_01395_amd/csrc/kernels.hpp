@@ -1498,4 +1498,152 @@ __global__ void kb_init_state(const SysDesc* sys, int32_t nsys, int32_t slot, do
 }
 #undef PBCGS_BIND_WG
 
+// ===========================================================================
+// Persistent form for small systems: the whole solve in one cooperative
+// launch.  The phases are those of the graph schedule (the same device
+// bodies, state ring and partial-sum buffers); a grid barrier replaces each
+// kernel boundary.  Every wait is bounded: a barrier that does not complete
+// in about a quarter of a second sets an error flag and the kernel ends.
+// ===========================================================================
+struct GridBar {
+  unsigned cnt;   // arrivals at the current barrier
+  unsigned gen;   // completed barriers
+  int err;        // set when a wait timed out
+  int pad;
+};
+
+// Partial-sum buffers by role (the same roles as the launches of the driver).
+enum : int { PBR_SETUP1 = 0, PBR_SETUP2, PBR_A, PBR_B, PBR_B1, PBR_B3, PBR_B4 };
+
+struct PersistCfg {
+  DevState* st;      // the two-slot state ring
+  double* parts;     // partial-sum buffers, kMaxD * kMaxG doubles per role
+  GridBar* bar;
+  int64_t* qout;     // phases run (the state is in slot qout & 1 at the end)
+  int32_t variant;   // 0 BiCGStab, 1 p-BiCGStab, 2 p-BiCGStab with replacement
+  int32_t rr_period, rr_max, maxit;
+};
+
+// Grid-wide barrier with release/acquire at agent scope; false after a timeout.
+__device__ __forceinline__ bool grid_sync(GridBar* b, unsigned nwg) {
+  __shared__ int ok_;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned g = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned prev = atomicAdd(&b->cnt, 1u);
+    if (prev == nwg - 1) {
+      atomicExch(&b->cnt, 0u);
+      __threadfence();
+      atomicAdd(&b->gen, 1u);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1u << 22)) {
+          atomicOr(&b->err, 1);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    if (__hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+    __threadfence();
+    ok_ = ok;
+  }
+  __syncthreads();
+  return ok_ != 0;
+}
+
+__device__ __forceinline__ bool rr_due_dev(const PersistCfg& c, int64_t i) {
+  if (c.variant != 2 || c.rr_period <= 0 || i < 0) return false;
+  if ((i + 1) % c.rr_period != 0) return false;
+  const int64_t before = (i + 1) / c.rr_period - 1;
+  return c.rr_max < 0 || before < c.rr_max;
+}
+
+template <class Op, int PC>
+__global__ __launch_bounds__(kWG) void k_persist(Op op, Args base, PersistCfg c) {
+  int64_t q = 0;
+  const unsigned nwg = gridDim.x;
+  bool ok = true;
+  auto L = [&](int pin, int pout, bool first) {
+    Args a = base;
+    a.wg = -1;
+    a.sin = c.st + (q & 1);
+    a.sout = c.st + ((q + 1) & 1);
+    a.pin = pin >= 0 ? c.parts + (size_t)pin * kMaxD * kMaxG : nullptr;
+    a.pout = pout >= 0 ? c.parts + (size_t)pout * kMaxD * kMaxG : nullptr;
+    a.Gin = base.G;
+    a.first = first ? 1 : 0;
+    ++q;
+    return a;
+  };
+  auto sync = [&]() {
+    if (ok) ok = grid_sync(c.bar, nwg);
+    return ok;
+  };
+  const bool pipe = c.variant != 0;
+  if (pipe) {
+    d_setup_r0<Op, PC, true>(op, L(-1, PBR_SETUP1, false));
+    if (sync()) d_setup_w0<Op, PC>(op, L(PBR_SETUP1, PBR_SETUP2, false));
+  } else {
+    d_setup_r0<Op, PC, false>(op, L(-1, PBR_SETUP1, false));
+  }
+  sync();
+  int64_t i = 0;
+  for (; ok && i < c.maxit; ++i) {
+    if (!pipe) {
+      d_b1<Op, PC>(op, L(PBR_SETUP1, PBR_B1, i == 0));
+      if (sync()) d_b2<PC>(L(PBR_B1, -1, false));
+      if (sync()) d_b3<Op, PC>(op, L(-1, PBR_B3, false));
+      if (sync()) d_b4<PC>(L(PBR_B3, PBR_B4, false));
+      if (sync()) d_b5<PC>(L(PBR_B4, -1, false));
+      sync();
+    } else {
+      if (rr_due_dev(c, i - 1)) {
+        d_rr_p<PC>(L(PBR_B, -1, false));
+        if (sync()) d_rr_s<Op, PC>(op, L(-1, -1, false));
+        if (sync()) d_pa<Op, PC, true>(op, L(-1, PBR_A, false));
+      } else {
+        d_pa<Op, PC, false>(op, L(i == 0 ? PBR_SETUP2 : PBR_B, PBR_A, i == 0));
+      }
+      sync();
+      if (ok && rr_due_dev(c, i)) {
+        d_rr_x<PC>(L(PBR_A, -1, false));
+        if (sync()) d_rr_r<Op, PC>(op, L(-1, -1, false));
+        if (sync()) d_rr_w<Op, PC>(op, L(-1, PBR_B, false));
+      } else if (ok) {
+        d_pb<Op, PC>(op, L(PBR_A, PBR_B, false));
+      }
+      sync();
+    }
+    if (!ok) break;
+    // the state after this iteration, published before the barrier
+    const int32_t status = __hip_atomic_load(&c.st[q & 1].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (status != DS_RUNNING) break;
+  }
+  // maxit reached: the reduction left pending by the last phase, in workgroup 0
+  if (ok && i == c.maxit) {
+    if (pipe) {
+      const Args a = (c.maxit == 0) ? L(PBR_SETUP2, -1, false) : L(PBR_B, -1, false);
+      if (blockIdx.x == 0) {
+        Args a0 = a;
+        a0.wg = 0;
+        if (c.maxit == 0) d_finish<1>(a0);
+        else d_finish<0>(a0);
+      }
+    } else if (c.maxit == 0) {
+      const Args a = L(PBR_SETUP1, -1, false);
+      if (blockIdx.x == 0) {
+        Args a0 = a;
+        a0.wg = 0;
+        d_finish<2>(a0);
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *c.qout = q;
+}
+
 }  // namespace pbcgs

@@ -37,6 +37,9 @@ struct pbcgs_ctx_s {
   DevState* st = nullptr;   // state slots (device): 0, 1 solver ring; 2, 3 utility reductions
   DevState* hst = nullptr;  // pinned host copies for polling (two slots)
   int32_t* flag = nullptr;  // structural error flags of utility kernels
+  GridBar* bar = nullptr;   // grid barrier of the persistent form
+  int64_t* qout = nullptr;  // phases run by the persistent form
+  int coop = -1;            // device supports cooperative launches (-1: not asked yet)
   int32_t* hflag = nullptr; // pinned host copy
   double* part = nullptr;   // PB_COUNT buffers of kMaxD * kMaxG partial sums
   double* ws = nullptr;     // solver vectors
@@ -509,7 +512,66 @@ struct Driver {
     return PBCGS_SUCCESS;
   }
 
+  // The persistent form (binary64, no per-kernel timing), on request only
+  // (PBCGS_PERSIST=1): measured on MI355X, a grid barrier -- an agent-scope
+  // release per workgroup, which writes back the per-XCD L2 caches -- costs
+  // more than a kernel boundary between graph-launched kernels, and more the
+  // larger the grid, so the graph schedule is the default at every size.
+  bool use_persistent() {
+    if constexpr (MP) return false;
+    if (o.flags & 2) return false;
+    if (o.maxit > 200000) return false;
+    if (env_int("PBCGS_PERSIST", 0) != 1) return false;
+    if (ctx->coop < 0) {
+      int v = 0;
+      ctx->coop = (hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, ctx->device) == hipSuccess && v) ? 1 : 0;
+    }
+    if (ctx->coop != 1) return false;
+    // every workgroup must be resident at once
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_persist<Op, PC>), kWG,
+                                                     0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
+      return false;
+    return (int64_t)a.G <= (int64_t)per_cu * cus;
+  }
+
+  int run_persistent(pbcgs_info* info) {
+    hipStream_t s = ctx->stream;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_start, s));
+    k_init_state<<<1, 64, 0, s>>>(ctx->st, o.tol);
+    HIP_TRY(ctx, hipMemsetAsync(ctx->bar, 0, sizeof(GridBar), s));
+    PersistCfg c;
+    c.st = ctx->st;
+    c.parts = ctx->part;
+    c.bar = ctx->bar;
+    c.qout = ctx->qout;
+    c.variant = o.variant;
+    c.rr_period = o.rr_period;
+    c.rr_max = o.rr_max;
+    c.maxit = o.maxit;
+    Args base = a;
+    void* args[] = {&op, &base, &c};
+    HIP_TRY(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_persist<Op, PC>), dim3((unsigned)a.G),
+                                            dim3(kWG), args, 0, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_stop, s));
+    GridBar hb;
+    int64_t hq = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&hb, ctx->bar, sizeof hb, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(&hq, ctx->qout, sizeof hq, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (hb.err) return fail(ctx, PBCGS_ERR_HIP, "persistent solve: a grid barrier timed out");
+    q = hq;
+    DevState fin;
+    int rc = read_state(ctx, (int)(q & 1), &fin);
+    if (rc != PBCGS_SUCCESS) return rc;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop);
+    return report(info, fin, ms);
+  }
+
   int run(pbcgs_info* info) {
+    if (use_persistent()) return run_persistent(info);
     const bool use_graph = !(o.flags & 1) && !(o.flags & 2);
     timing = (o.flags & 2) != 0;
     const int check = o.check_every > 0 ? o.check_every : (a.n >= (1 << 20) ? 8 : 32);
@@ -597,9 +659,14 @@ struct Driver {
     }
     HIP_TRY(ctx, hipEventRecord(ctx->ev_stop, s));
     HIP_TRY(ctx, hipEventSynchronize(ctx->ev_stop));
-    int rc = PBCGS_SUCCESS;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop);
+    return report(info, fin, ms);
+  }
+
+  // Fills info from the final state (and the true residual of the returned x).
+  int report(pbcgs_info* info, const DevState& fin, float ms) {
+    int rc = PBCGS_SUCCESS;
     rho0 = fin.rho0;
     if (true_res) {  // true residual of the returned x, same pairwise arithmetic (binary64)
       if constexpr (MP) rc = true_relres(ctx, op64, a, fin.rho0, &info->relres_true);
@@ -922,6 +989,8 @@ int pbcgs_ctx_create(int device, void* hip_stream, pbcgs_ctx_t* out) {
   bool ok = hipMalloc(&c->st, 4 * sizeof(DevState)) == hipSuccess &&
             hipMalloc(&c->part, sizeof(double) * kMaxD * kMaxG * PB_COUNT) == hipSuccess &&
             hipMalloc(&c->flag, 64) == hipSuccess &&
+            hipMalloc(&c->bar, sizeof(GridBar)) == hipSuccess &&
+            hipMalloc(&c->qout, sizeof(int64_t)) == hipSuccess &&
             hipHostMalloc(&c->hst, 2 * sizeof(DevState), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc(&c->hflag, 64, hipHostMallocDefault) == hipSuccess &&
             hipEventCreate(&c->ev_start) == hipSuccess && hipEventCreate(&c->ev_stop) == hipSuccess &&
@@ -962,6 +1031,8 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
   if (ctx->bhst) (void)hipHostFree(ctx->bhst);
   if (ctx->part) (void)hipFree(ctx->part);
   if (ctx->flag) (void)hipFree(ctx->flag);
+  if (ctx->bar) (void)hipFree(ctx->bar);
+  if (ctx->qout) (void)hipFree(ctx->qout);
   if (ctx->st) (void)hipFree(ctx->st);
   if (ctx->hst) (void)hipHostFree(ctx->hst);
   if (ctx->hflag) (void)hipHostFree(ctx->hflag);
