@@ -69,7 +69,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     p.add_argument("--only", default="",
-                   help="comma list of legs to run: pipe,bicg,explicit,stencil,precision,batched,sweep,paper")
+                   help="comma list of legs to run: pipe,bicg,explicit,stencil,precision,batched,sweep,paper,configs")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
     return p.parse_args()
@@ -121,7 +121,7 @@ def main():
     w = inputs.workload("c2", n=args.n)
     N = w.N
     legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "precision", "batched",
-                                                         "sweep", "paper"}
+                                                         "sweep", "paper", "configs"}
 
     # ---- inputs resident in HBM -------------------------------------------------
     rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
@@ -235,6 +235,42 @@ def main():
                      "time_to_solution_speedup": round(f64["ms_per_solve"] / f32["ms_per_solve"], 4)}
         del A4, rp4, col4, val4, b4, x4, x64
         torch.cuda.empty_cache()
+
+    # ---- the other configurations: 2-D 64^2 (latency-bound) and 3-D 27-point 256^3 (matrix-bound)
+    configs = None
+    if "configs" in legs:
+        configs = {}
+        for name, precond, steps in (("c1", None, 20), ("c3", "jacobi_folded", 2)):
+            wc = inputs.workload(name)
+            kappa = None
+            if wc.npts == 27:
+                kappa = torch.from_numpy(inputs.kappa_cells(wc.n, wc.kappa_sigma)).to(dev)
+            rpc, colc, valc = solver.assemble_convdiff(wc.dim, wc.n, wc.npts, wc.beta, kappa, wc.shift)
+            Ac = solver.csr(rpc, colc, valc)
+            bc = solver.spmv(Ac, torch.from_numpy(inputs.x_true(wc.N)).to(dev))
+            xc = torch.empty_like(bc)
+            row = {"workload": f"{wc.dim}-D {wc.npts}-point {wc.n}^{wc.dim} (N={wc.N}, nnz={valc.numel()}), "
+                               f"precond {precond or 'none'}, tol {wc.tol:g}, RR every {wc.rr_period}"}
+            for variant in ("pbicgstab_rr", "bicgstab"):
+                kwc = dict(variant=variant, precond=precond, tol=wc.tol, maxit=wc.maxit, rr_period=wc.rr_period,
+                           out=xc)
+                solver.solve(Ac, bc, **kwc)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                its = 0
+                for _ in range(steps):
+                    _, inf = solver.solve(Ac, bc, **kwc)
+                    its += inf.iters
+                torch.cuda.synchronize()
+                dtc = time.perf_counter() - t0
+                row[variant] = {"iters_per_s": round(its / dtc, 1), "us_per_iter": round(dtc / its * 1e6, 2),
+                                "iters_per_solve": inf.iters, "ms_per_solve": round(dtc / steps * 1e3, 3),
+                                "syncs_per_iter": inf.syncs_per_iter, "relres_true": inf.relres_true}
+            row["pbicgstab_over_bicgstab_iters_per_s"] = round(
+                row["pbicgstab_rr"]["iters_per_s"] / row["bicgstab"]["iters_per_s"], 4)
+            configs[name] = row
+            del Ac, rpc, colc, valc, bc, xc, kappa
+            torch.cuda.empty_cache()
 
     # ---- the paper's test problems (Section 5): 1000^2 five-point stencils, x_hat = 1, tol 1e-6
     paper = None
@@ -427,6 +463,8 @@ def main():
         out["size_sweep_3d_7pt_csr_folded_jacobi"] = sweep
     if paper is not None:
         out["paper_test_problems"] = paper
+    if configs is not None:
+        out["other_configs"] = configs
     out["roofline"] = roofline
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
