@@ -91,7 +91,9 @@ typedef struct {
     int32_t rr_max;      /* at most this many replacements; -1 = unlimited                  */
     int32_t check_every; /* iterations between host polls of the device status; 0 = auto   */
     int32_t flags;       /* bit 0: launch each kernel directly instead of through a
-                            captured HIP graph; bit 1: time the fused kernels with events  */
+                            captured HIP graph; bit 1: time the fused kernels with events;
+                            bit 2: alpha_{i+1} of PBICGSTAB(_RR) by eq. (5), the form
+                            without (r0, s_i), instead of eq. (3) (Section 3.1)          */
     double* history;     /* nullable DEVICE array of maxit+1 doubles: history[i] =
                             ||r_i|| / ||r_0|| after i iterations (history[0] = 1)           */
 } pbcgs_opts;

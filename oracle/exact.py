@@ -138,9 +138,10 @@ def ca_bicgstab(A, b, x0, maxit):
     return out, "maxit"
 
 
-def pbicgstab(A, b, x0, maxit, dinv=None, rr_period=0):
+def pbicgstab(A, b, x0, maxit, dinv=None, rr_period=0, alpha_form=3):
     """Algorithm 9; with ``dinv`` Algorithm 11.  ``rr_period`` > 0 adds the
-    residual replacement of Section 4.2 (same placement as the FP64 oracle)."""
+    residual replacement of Section 4.2 (same placement as the FP64 oracle).
+    ``alpha_form`` 5 takes alpha_{i+1} from eq. (5) instead of eq. (3)."""
     n = len(b)
     pc = dinv is not None
     M = (lambda v: scale(dinv, v)) if pc else (lambda v: list(v))
@@ -224,10 +225,18 @@ def pbicgstab(A, b, x0, maxit, dinv=None, rr_period=0):
             out.append(_rec(x, r, alpha, omega, None))
             return out, "breakdown", replaced
         beta = (alpha / omega) * (g1 / gamma)
-        den = eta + beta * ss - beta * omega * sz
         out.append(_rec(x, r, alpha, omega, beta))
-        if den == 0:
-            return out, "breakdown", replaced
-        alpha = g1 / den
+        if alpha_form == 5:
+            if g1 == 0:
+                return out, "breakdown", replaced
+            den = (1 / omega + eta / g1) - (beta * omega) * (sz / g1)
+            if den == 0:
+                return out, "breakdown", replaced
+            alpha = 1 / den
+        else:
+            den = eta + beta * ss - beta * omega * sz
+            if den == 0:
+                return out, "breakdown", replaced
+            alpha = g1 / den
         gamma = g1
     return out, "maxit", replaced

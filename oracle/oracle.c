@@ -31,7 +31,8 @@
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *  - shadow residual r~ = r_0; quantities with index -1 are zero, omega_{-1}=0;
- *  - alpha_{i+1} uses the four-dot expression (eq. 3), not eq. (5);
+ *  - alpha_{i+1} uses the four-dot expression (eq. 3) by default; eq. (5),
+ *    the three-dot form, on request (or_set_alpha_form);
  *  - residual replacement in iteration i with (i+1) mod k == 0: r, r^, w are
  *    replaced after the x-update of iteration i (so the second reduction,
  *    beta_i, alpha_{i+1}, w^ and t all see the true values) and s, s^, z
@@ -73,6 +74,12 @@ typedef struct {
 } or_counters;
 
 static or_counters g_ctr;
+
+/* alpha_{i+1} of the pipelined solvers: 3 = eq. (3), four dot products (the
+ * default, as in Algorithms 9 and 11); 5 = eq. (5), the three-dot form that
+ * is equal in exact arithmetic. */
+static int g_alpha_form = 3;
+void or_set_alpha_form(int32_t form) { g_alpha_form = (form == 5) ? 5 : 3; }
 
 void or_counters_get(int64_t* out6)
 {
@@ -575,9 +582,18 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
         beta = (alpha / omega) * (gamma1 / gamma);
         if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }
         if (o->scalars) o->scalars[3 * i + 2] = beta;
-        double den = eta + beta * sig_s - beta * omega * sig_z;
-        if (den == 0.0 || gamma1 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
-        alpha = gamma1 / den;
+        if (g_alpha_form == 5) {
+            /* eq. (5): (1/omega + (r0,w)/(r0,r) - (beta omega) ((r0,z)/(r0,r)))^{-1}, three quotients
+               summed in the order the equation writes them */
+            if (gamma1 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+            double den5 = (1.0 / omega + eta / gamma1) - (beta * omega) * (sig_z / gamma1);
+            if (den5 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+            alpha = 1.0 / den5;
+        } else {
+            double den = eta + beta * sig_s - beta * omega * sig_z;
+            if (den == 0.0 || gamma1 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+            alpha = gamma1 / den;
+        }
         if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
         gamma = gamma1;
     }
@@ -806,9 +822,16 @@ static int pbicgstab_mp(const csr_t* A, const double* b, double* x, const or_opt
             beta = (alpha / omega) * (gamma1 / gamma);
             if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }
             if (o->scalars) o->scalars[3 * i + 2] = beta;
-            double den = eta + beta * sig_s - beta * omega * sig_z;
-            if (den == 0.0 || gamma1 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
-            alpha = gamma1 / den;
+            if (g_alpha_form == 5) {
+                if (gamma1 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+                double den5 = (1.0 / omega + eta / gamma1) - (beta * omega) * (sig_z / gamma1);
+                if (den5 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+                alpha = 1.0 / den5;
+            } else {
+                double den = eta + beta * sig_s - beta * omega * sig_z;
+                if (den == 0.0 || gamma1 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+                alpha = gamma1 / den;
+            }
             if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
             gamma = gamma1;
             break;

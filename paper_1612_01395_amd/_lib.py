@@ -22,6 +22,7 @@ FP64, FP32_RR64 = 0, 1
 
 FLAG_DIRECT = 1       # launch kernels directly instead of replaying a HIP graph
 FLAG_TIME_KERNELS = 2  # time the two fused kernels of each iteration with events
+FLAG_ALPHA_EQ5 = 4     # alpha_{i+1} of the pipelined variants by eq. (5) instead of eq. (3)
 
 
 class Opts(ctypes.Structure):

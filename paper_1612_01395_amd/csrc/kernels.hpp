@@ -190,7 +190,7 @@ struct Args {
   int32_t wg;             // workgroup index within the system (-1: blockIdx.x)
   int32_t pstride;        // stride between the ND partial-sum rows (kMaxG, or the batch's workgroups)
   int32_t par;            // batched launches: state slot read (written: par ^ 1)
-  int32_t pad2_;
+  int32_t aform;          // alpha_{i+1} of the pipelined solvers: 5 = eq. (5), otherwise eq. (3)
   const DevState* sin;    // state read by this launch
   DevState* sout;         // state written by workgroup 0
   const double* pin;      // partials consumed: pin[k * kMaxG + wg]
@@ -428,9 +428,32 @@ __device__ __forceinline__ bool fin_omega(State& s, double* hist, double qy, dou
   return false;
 }
 
+// alpha_{i+1} of the pipelined solvers from gamma' = (r0, r_{i+1}), eta = (r0, w_{i+1}),
+// sigma_s = (r0, s_i), sigma_z = (r0, z_i): eq. (3) is gamma' / (eta + beta sigma_s
+// - beta omega sigma_z); eq. (5) is the same quantity rearranged so that sigma_s
+// drops out, (1/omega + eta/gamma' - (beta omega) (sigma_z/gamma'))^{-1}.  Both
+// evaluate in the order and grouping the equations write, without contraction.
+__device__ __forceinline__ void next_alpha(State& s, int32_t aform, double g1, double eta, double sig_s,
+                                           double sig_z, double beta, double omega) {
+  double an;
+  if (aform == 5) {
+    if (g1 == 0.0) { s.status = DS_BREAKDOWN; return; }
+    const double den = (1.0 / omega + eta / g1) - (beta * omega) * (sig_z / g1);
+    if (den == 0.0) { s.status = DS_BREAKDOWN; return; }
+    an = 1.0 / den;
+  } else {
+    const double den = eta + beta * sig_s - beta * omega * sig_z;
+    if (den == 0.0 || g1 == 0.0) { s.status = DS_BREAKDOWN; return; }
+    an = g1 / den;
+  }
+  if (!finite(an)) { s.status = DS_NONFINITE; return; }
+  s.alpha = an;
+  s.gamma = g1;
+}
+
 // Reduction 2 of p-BiCGStab: stopping test, beta_i and alpha_{i+1} by eq. (3)
-// (Algorithm 9 lines 17-20, Algorithm 11 lines 24-26).
-__device__ __forceinline__ void fin_pipe_b(State& s, double* hist, const double (&d)[5]) {
+// or eq. (5) (Algorithm 9, Algorithm 11).
+__device__ __forceinline__ void fin_pipe_b(State& s, double* hist, const double (&d)[5], int32_t aform) {
   const double g1 = d[0], eta = d[1], sig_s = d[2], sig_z = d[3], nu = d[4];
   s.iters += 1;
   if (!finite(g1) || !finite(eta) || !finite(sig_s) || !finite(sig_z) || !finite(nu)) {
@@ -446,12 +469,7 @@ __device__ __forceinline__ void fin_pipe_b(State& s, double* hist, const double 
   const double beta = (alpha / omega) * (g1 / gamma);
   if (!finite(beta)) { s.status = DS_NONFINITE; return; }
   s.beta = beta;
-  const double den = eta + beta * sig_s - beta * omega * sig_z;
-  if (den == 0.0 || g1 == 0.0) { s.status = DS_BREAKDOWN; return; }
-  const double an = g1 / den;
-  if (!finite(an)) { s.status = DS_NONFINITE; return; }
-  s.alpha = an;
-  s.gamma = g1;
+  next_alpha(s, aform, g1, eta, sig_s, sig_z, beta, omega);
 }
 
 // alpha_i = (r0, r_i) / (r0, s_i)  (Algorithm 7 lines 5-6).
@@ -562,7 +580,7 @@ __device__ __forceinline__ void d_pa(Op op, Args a) {
     } else {
       double g[5];
       gather_sums<5>(a, g);
-      fin_pipe_b(st, a.hist, g);
+      fin_pipe_b(st, a.hist, g, a.aform);
     }
   }
   publish(a, st);
@@ -728,7 +746,7 @@ __device__ __forceinline__ void d_rr_p(Args a) {
   PBCGS_PROLOGUE(st)
   double g[5];
   gather_sums<5>(a, g);
-  fin_pipe_b(st, a.hist, g);
+  fin_pipe_b(st, a.hist, g, a.aform);
   publish(a, st);
   if (st.status != DS_RUNNING) return;
   const double beta = st.beta, omega = st.omega;
@@ -886,7 +904,7 @@ __device__ __forceinline__ void d_finish(Args a) {
   if (MODE == 0) {
     double g[5];
     gather_sums<5>(a, g);
-    fin_pipe_b(st, a.hist, g);
+    fin_pipe_b(st, a.hist, g, a.aform);
   } else {
     double g[1];
     gather_sums<1>(a, g);
@@ -912,7 +930,8 @@ __global__ __launch_bounds__(kWG) void k_finish(Args a) { d_finish<MODE>(a); }
 
 // Reduction 2 of the precision form.  recheck: the reduction that follows a
 // forced replacement -- it neither counts an iteration nor tests convergence.
-__device__ __forceinline__ void fin_pipe_b_mp(State& s, double* hist, const double (&d)[5], bool recheck) {
+__device__ __forceinline__ void fin_pipe_b_mp(State& s, double* hist, const double (&d)[5], bool recheck,
+                                              int32_t aform) {
   const double g1 = d[0], eta = d[1], sig_s = d[2], sig_z = d[3], nu = d[4];
   if (!recheck) s.iters += 1;
   if (!finite(g1) || !finite(eta) || !finite(sig_s) || !finite(sig_z) || !finite(nu)) {
@@ -928,12 +947,7 @@ __device__ __forceinline__ void fin_pipe_b_mp(State& s, double* hist, const doub
   const double beta = (alpha / omega) * (g1 / gamma);
   if (!finite(beta)) { s.status = DS_NONFINITE; return; }
   s.beta = beta;
-  const double den = eta + beta * sig_s - beta * omega * sig_z;
-  if (den == 0.0 || g1 == 0.0) { s.status = DS_BREAKDOWN; return; }
-  const double an = g1 / den;
-  if (!finite(an)) { s.status = DS_NONFINITE; return; }
-  s.alpha = an;
-  s.gamma = g1;
+  next_alpha(s, aform, g1, eta, sig_s, sig_z, beta, omega);
 }
 
 // Setup 1: r64 = b - A x0 (binary64) ; r0 = r = f(r64) ; p = s = z = v = 0 ;
@@ -990,7 +1004,7 @@ __global__ __launch_bounds__(kWG) void k_mp_pa(Op32 op, Op64 op64, Args a) {
     } else {
       double g[5];
       gather_sums<5, float>(a, g);
-      fin_pipe_b_mp(st, a.hist, g, false);
+      fin_pipe_b_mp(st, a.hist, g, false, a.aform);
     }
   }
   publish(a, st);
@@ -1127,7 +1141,7 @@ __global__ __launch_bounds__(kWG) void k_mp_rr_p(Args a) {
   PBCGS_PROLOGUE(st)
   double g[5];
   gather_sums<5, float>(a, g);
-  fin_pipe_b_mp(st, a.hist, g, a.mode == 1);
+  fin_pipe_b_mp(st, a.hist, g, a.mode == 1, a.aform);
   publish(a, st);
   if (st.status != DS_RUNNING) return;
   const float bf = float(st.beta), wf_ = float(st.omega);
@@ -1157,7 +1171,7 @@ __global__ __launch_bounds__(kWG) void k_mp_finish(Args a) {
   if (MODE == 0) {
     double g[5];
     gather_sums<5, float>(a, g);
-    fin_pipe_b_mp(st, a.hist, g, a.mode == 1);
+    fin_pipe_b_mp(st, a.hist, g, a.mode == 1, a.aform);
   } else {
     double g[1];
     gather_sums<1, float>(a, g);

@@ -144,6 +144,9 @@ bool make_shape(int32_t n, Shape* sh, int prefer_R = 0) {
   return false;
 }
 
+// opts.flags bit 2 selects eq. (5) for alpha_{i+1}; eq. (3) otherwise.
+int32_t alpha_form(const pbcgs_opts& o) { return (o.flags & 4) ? 5 : 3; }
+
 Args base_args(pbcgs_ctx_t ctx, const Shape& sh) {
   Args a;
   std::memset(&a, 0, sizeof a);
@@ -317,9 +320,13 @@ struct Driver {
   size_t ev_used = 0;
   std::vector<int64_t> forced;  // precision form: iterations ended by a forced replacement
 
-  Driver(pbcgs_ctx_t c, Op op_, const Args& a_, const pbcgs_opts& o_) : ctx(c), op(op_), op64(), a(a_), o(o_) {}
+  Driver(pbcgs_ctx_t c, Op op_, const Args& a_, const pbcgs_opts& o_) : ctx(c), op(op_), op64(), a(a_), o(o_) {
+    a.aform = alpha_form(o);
+  }
   Driver(pbcgs_ctx_t c, Op op_, Op64 op64_, const Args& a_, const pbcgs_opts& o_)
-      : ctx(c), op(op_), op64(op64_), a(a_), o(o_) {}
+      : ctx(c), op(op_), op64(op64_), a(a_), o(o_) {
+    a.aform = alpha_form(o);
+  }
 
   bool was_forced(int64_t i) const { return std::find(forced.begin(), forced.end(), i) != forced.end(); }
   // iteration i starts with the second half of a replacement
@@ -752,6 +759,7 @@ struct BatchDriver {
       : ctx(c), o(o_), nsys(ns), totalG(tg), pipe(o_.variant != PBCGS_BICGSTAB) {
     std::memset(&tmpl, 0, sizeof tmpl);
     tmpl.pstride = tg;
+    tmpl.aform = alpha_form(o_);
   }
 
   double* part(int which) const { return ctx->bpart + (size_t)which * kMaxD * totalG; }

@@ -31,6 +31,11 @@ def _ptr(t: torch.Tensor | None):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _check_alpha_form(alpha_form: int):
+    if alpha_form not in (3, 5):
+        raise ValueError("alpha_form must be 3 (eq. (3)) or 5 (eq. (5))")
+
+
 def _check_vec(t: torch.Tensor, n: int, name: str, dtype=torch.float64):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a GPU tensor")
@@ -217,10 +222,13 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
           precond: str | None = None, dinv: torch.Tensor | None = None, tol: float = 1e-8, maxit: int = 2000,
           rr_period: int = 50, rr_max: int = -1, history: bool = False, check_every: int = 0,
           graph: bool = True, time_kernels: bool = False, out: torch.Tensor | None = None,
-          precision: str = "fp64"):
+          precision: str = "fp64", alpha_form: int = 3):
     """Solve A x = b; returns (x, SolveInfo).  x0 defaults to zero; ``out``
-    (optional) receives the iterate in place of a new tensor."""
+    (optional) receives the iterate in place of a new tensor.  ``alpha_form``
+    5 takes alpha_{i+1} of the pipelined variants from eq. (5) instead of
+    eq. (3) (Section 3.1)."""
     _check_vec(b, A.n, "b")
+    _check_alpha_form(alpha_form)
     if variant not in VARIANTS:
         raise ValueError(f"variant must be one of {sorted(VARIANTS)}")
     if precision not in PRECISIONS:
@@ -249,7 +257,8 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
     o.rr_period = int(rr_period)
     o.rr_max = int(rr_max)
     o.check_every = int(check_every)
-    o.flags = (0 if graph else L.FLAG_DIRECT) | (L.FLAG_TIME_KERNELS if time_kernels else 0)
+    o.flags = ((0 if graph else L.FLAG_DIRECT) | (L.FLAG_TIME_KERNELS if time_kernels else 0)
+               | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0))
     o.history = hist.data_ptr() if hist is not None else None
     info = L.Info()
     L.check(L.lib().pbcgs_solve(A.ctx.handle, A.handle, _ptr(b), _ptr(x), _ptr(dinv), ctypes.byref(o),
@@ -263,10 +272,11 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
 
 def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str = "pbicgstab_rr", tol: float = 1e-8,
                   maxit: int = 2000, rr_period: int = 50, rr_max: int = -1, check_every: int = 0, graph: bool = True,
-                  outs: list | None = None):
+                  outs: list | None = None, alpha_form: int = 3):
     """Solve the independent systems ops[k] x_k = bs[k] in one batched call
     (CSR operators of one context, no preconditioner, binary64).  Returns
     (xs, infos); each system's result equals its own :func:`solve` bit for bit."""
+    _check_alpha_form(alpha_form)
     nsys = len(ops)
     if nsys == 0 or len(bs) != nsys:
         raise ValueError("ops and bs must be non-empty lists of the same length")
@@ -298,7 +308,7 @@ def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str 
     o.rr_period = int(rr_period)
     o.rr_max = int(rr_max)
     o.check_every = int(check_every)
-    o.flags = 0 if graph else L.FLAG_DIRECT
+    o.flags = (0 if graph else L.FLAG_DIRECT) | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0)
     o.history = None
     VP = ctypes.c_void_p * nsys
     hs = VP(*[A.handle.value for A in ops])

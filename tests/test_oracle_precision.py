@@ -107,3 +107,20 @@ def test_recursive_convergence_is_confirmed():
     # binary32 p-BiCGStab without any replacement is not stable to tighter tolerances
     _, bad = oracle.solve_mp(A, b, dinv=d, tol=1e-7, maxit=2000, rr_period=0)
     assert bad["status"] != oracle.SUCCESS
+
+
+def test_precision_form_alpha_eq5_is_less_robust():
+    """Section 3.1 reports eq. (3) as the more robust alpha_{i+1}, notably with
+    residual replacement.  In the precision form the 2-D problem shows it:
+    eq. (3) converges, eq. (5) diverges to a non-finite scalar, and with
+    Jacobi eq. (5) needs more than twice the iterations."""
+    A = oracle.assemble_workload(inputs.workload("c1"))
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    kw = dict(tol=1e-10, maxit=3000, rr_period=20)
+    _, i3 = oracle.solve_mp(A, b, **kw)
+    _, i5 = oracle.solve_mp(A, b, alpha_form=5, **kw)
+    assert i3["status"] == oracle.SUCCESS and i5["status"] == oracle.NONFINITE
+    dv = oracle.jacobi_dinv(A)
+    _, j3 = oracle.solve_mp(A, b, dinv=dv, **kw)
+    _, j5 = oracle.solve_mp(A, b, dinv=dv, alpha_form=5, **kw)
+    assert j3["status"] == j5["status"] == oracle.SUCCESS and j5["iters"] > 2 * j3["iters"]

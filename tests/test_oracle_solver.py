@@ -454,3 +454,61 @@ def test_folded_constant_diagonal_is_a_scaling():
     y, info2 = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, tol=1e-9, rr_period=20)
     assert info["iters"] == info2["iters"]
     assert np.array_equal(x, y * 0.25)
+
+
+@pytest.mark.parametrize("name,S,b", tiny_systems(), ids=_IDS)
+@pytest.mark.parametrize("pc", [False, True])
+def test_exact_alpha_eq5_equals_eq3(name, S, b, pc):
+    """Eq. (5) is an algebraic rearrangement of eq. (3): in exact arithmetic
+    both give the same alpha_{i+1}, so the whole iterate sequence agrees."""
+    A = frac_rows(S)
+    bf = [Fraction(float(v)) for v in b]
+    x0 = [Fraction(0)] * len(bf)
+    N = len(bf)
+    steps = N + 2 if N <= 4 else EXACT_STEPS
+    dinv = [1 / Fraction(float(d)) for d in S.diagonal()] if pc else None
+    r3, s3, _ = exact.pbicgstab(A, bf, x0, steps, dinv=dinv, alpha_form=3)
+    r5, s5, _ = exact.pbicgstab(A, bf, x0, steps, dinv=dinv, alpha_form=5)
+    rb, sb = exact.bicgstab(A, bf, x0, steps, dinv=dinv)
+    assert s3 == s5 == sb and len(r3) == len(r5) == len(rb)
+    _same_records([rb, r3, r5])
+
+
+@pytest.mark.parametrize("algo", [oracle.ALG_PBICGSTAB, oracle.ALG_PBICGSTAB_RR])
+@pytest.mark.parametrize("pc", [False, True])
+def test_fp64_oracle_alpha_eq5_tracks_exact_iterates(algo, pc):
+    """The FP64 oracle with eq. (5) agrees with the exact recurrence for k <= 3."""
+    name, S, b = tiny_systems()[2]
+    A = oracle.CSR(S.indptr, S.indices, S.data)
+    dinv = oracle.jacobi_dinv(A) if pc else None
+    Af = frac_rows(S)
+    bf = [Fraction(float(v)) for v in b]
+    x0 = [Fraction(0)] * len(bf)
+    df = [1 / Fraction(float(d)) for d in S.diagonal()] if pc else None
+    ref, _, _ = exact.pbicgstab(Af, bf, x0, 3, dinv=df, rr_period=3 if algo == oracle.ALG_PBICGSTAB_RR else 0,
+                                alpha_form=5)
+    for k in range(1, 4):
+        x, info = oracle.solve(A, b, algo=algo, dinv=dinv, tol=0.0, maxit=k, rr_period=3, scalars=True,
+                               alpha_form=5)
+        assert info["status"] == oracle.MAXIT
+        xr = _frac_to_float(ref[k - 1]["x"])
+        assert np.linalg.norm(x - xr) <= 1e-13 * np.linalg.norm(xr)
+        a = info["scalars"][k - 1][0]
+        assert abs(a - float(ref[k - 1]["alpha"])) <= 1e-13 * abs(float(ref[k - 1]["alpha"]))
+
+
+@pytest.mark.parametrize("pc", [False, True])
+def test_fp64_oracle_alpha_eq5_converges(pc):
+    """Eq. (5) in FP64 reaches the dense-LU solution and the requested
+    tolerance, in an iteration count close to the eq. (3) run."""
+    from paper_1612_01395_amd import inputs
+    A = oracle.assemble_workload(inputs.workload("c1"))
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    dinv = oracle.jacobi_dinv(A) if pc else None
+    x3, i3 = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=1e-10, rr_period=20)
+    x5, i5 = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=1e-10, rr_period=20, alpha_form=5)
+    assert i5["status"] == oracle.SUCCESS and i5["relres_true"] <= 1e-9
+    assert abs(i5["iters"] - i3["iters"]) <= max(3, i3["iters"] // 20)
+    # the option is per call: the next default call is eq. (3) again
+    x3b, i3b = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=1e-10, rr_period=20)
+    assert np.array_equal(x3, x3b) and not np.array_equal(x3, x5)
