@@ -29,6 +29,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 ALG_BICGSTAB = 0
 ALG_PBICGSTAB = 1
 ALG_PBICGSTAB_RR = 2
+ALG_CA_BICGSTAB = 3  # Algorithm 8, unpreconditioned (a preconditioned solve folds A M^{-1})
 
 SUCCESS, MAXIT, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 STATUS_NAMES = {0: "success", 1: "maxit", 2: "breakdown", 3: "nonfinite"}

@@ -90,8 +90,9 @@ def bicgstab(A, b, x0, maxit, dinv=None):
     return out, "maxit"
 
 
-def ca_bicgstab(A, b, x0, maxit):
-    """Algorithm 8 (communication-avoiding BiCGStab), unpreconditioned."""
+def ca_bicgstab(A, b, x0, maxit, alpha_form=3):
+    """Algorithm 8 (communication-avoiding BiCGStab), unpreconditioned;
+    ``alpha_form`` 5 takes alpha_{i+1} from eq. (5)."""
     n = len(b)
     x = list(x0)
     r0 = sub(b, matvec(A, x))
@@ -129,12 +130,20 @@ def ca_bicgstab(A, b, x0, maxit):
             out.append(_rec(x, r_new, alpha, omega, None))
             return out, "converged"
         beta = (alpha / omega) * (g1 / g0)
-        den = dot(r0, w) + beta * dot(r0, s) - beta * omega * dot(r0, z)
+        if alpha_form == 5:
+            if g1 == 0:
+                out.append(_rec(x, r_new, alpha, omega, beta))
+                return out, "breakdown"
+            den = (1 / omega + dot(r0, w) / g1) - (beta * omega) * (dot(r0, z) / g1)
+            num = 1
+        else:
+            den = dot(r0, w) + beta * dot(r0, s) - beta * omega * dot(r0, z)
+            num = g1
         out.append(_rec(x, r_new, alpha, omega, beta))
         r = r_new
         if den == 0:
             return out, "breakdown"
-        alpha = g1 / den
+        alpha = num / den
     return out, "maxit"
 
 

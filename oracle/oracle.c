@@ -12,6 +12,7 @@
  * order and notation:
  *
  *   Algorithm 7   standard BiCGStab                     (Section 3.1)
+ *   Algorithm 8   communication-avoiding BiCGStab        (Section 3.1)
  *   Algorithm 9   pipelined BiCGStab, unpreconditioned   (Section 3.3)
  *   Algorithm 10  right-preconditioned BiCGStab          (Section 3.6)
  *   Algorithm 11  preconditioned pipelined BiCGStab      (Section 3.6)
@@ -612,6 +613,110 @@ oom:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Alg. 8 (communication-avoiding BiCGStab, Section 3.1), unpreconditioned: */
+/* s_i and y_i come from recurrences (eqs. (1) and (4)), so the iteration   */
+/* has two reduction phases, (q,y), (y,y) and then (r_0,r_{i+1}),           */
+/* (r_0,w_{i+1}), (r_0,s_i), (r_0,z_i), the second one finishing beta_i and */
+/* alpha_{i+1} together.  The squared norm of r_{i+1} joins that second     */
+/* phase for the stopping test.  No residual replacement.                   */
+/* ------------------------------------------------------------------------ */
+static int ca_bicgstab(const csr_t* A, const double* b, double* x, const or_opts* o, or_info* info)
+{
+    const int32_t n = A->n;
+    double *r0 = 0, *r = 0, *w = 0, *p = 0, *s = 0, *z = 0, *q = 0, *y = 0, *tmp = 0, *prod = 0;
+    NEWVEC(r0); NEWVEC(r); NEWVEC(w); NEWVEC(p); NEWVEC(s); NEWVEC(z); NEWVEC(q); NEWVEC(y); NEWVEC(tmp);
+    prod = (double*)malloc(sizeof(double) * (size_t)pow2_at_least(n));
+    if (!prod) goto oom;
+
+    info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
+    /* r_0 := b - A x_0 ; w_0 := A r_0 ; alpha_0 := (r_0, r_0) / (r_0, w_0) ; beta_{-1} := 0 */
+    spmv(A, x, tmp);
+    PAR for (int32_t j = 0; j < n; ++j) r0[j] = b[j] - tmp[j];
+    double gamma = DOT(r0, r0);
+    const double rho0 = sqrt(gamma);
+    if (o->history) o->history[0] = 1.0;
+    if (!isfinite(rho0)) { info->status = OR_NONFINITE; goto done; }
+    if (rho0 == 0.0) { info->status = OR_SUCCESS; info->relres_rec = 0.0; goto done; }
+    memcpy(r, r0, sizeof(double) * (size_t)n);
+    spmv(A, r, w);
+    double delta = DOT(r0, w);
+    if (!isfinite(delta)) { info->status = OR_NONFINITE; goto done; }
+    if (delta == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+    double alpha = gamma / delta, beta = 0.0, omega = 0.0;
+    if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
+    /* p_{-1} = s_{-1} = z_{-1} = 0 (calloc), omega_{-1} = 0 */
+
+    for (int32_t i = 0; i < o->maxit; ++i) {
+        /* p_i := r_i + beta_{i-1} (p_{i-1} - omega_{i-1} s_{i-1}) */
+        PAR for (int32_t j = 0; j < n; ++j) p[j] = r[j] + beta * (p[j] - omega * s[j]);
+        /* s_i := w_i + beta_{i-1} (s_{i-1} - omega_{i-1} z_{i-1})   (eq. (1)) */
+        PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + beta * (s[j] - omega * z[j]);
+        FLOPS(8); REC(2);
+        /* z_i := A s_i */
+        spmv(A, s, z);
+        /* q_i := r_i - alpha_i s_i ; y_i := w_i - alpha_i z_i   (eq. (4)) */
+        PAR for (int32_t j = 0; j < n; ++j) q[j] = r[j] - alpha * s[j];
+        PAR for (int32_t j = 0; j < n; ++j) y[j] = w[j] - alpha * z[j];
+        FLOPS(4); REC(2);
+        /* reduction (q_i, y_i), (y_i, y_i) ; omega_i */
+        double th1 = DOT(q, y), th2 = DOT(y, y);
+        g_ctr.glred++; g_ctr.dots += 2; FLOPS(4);
+        if (!isfinite(th1) || !isfinite(th2)) { info->status = OR_NONFINITE; goto done; }
+        if (th2 == 0.0) {
+            PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
+            info->iters = i + 1; info->relres_rec = 0.0; info->status = OR_SUCCESS;
+            if (o->history) o->history[i + 1] = 0.0;
+            goto done;
+        }
+        omega = th1 / th2;
+        if (!isfinite(omega)) { info->status = OR_NONFINITE; goto done; }
+        /* x_{i+1} := x_i + alpha_i p_i + omega_i q_i ; r_{i+1} := q_i - omega_i y_i */
+        PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j] + omega * q[j];
+        PAR for (int32_t j = 0; j < n; ++j) r[j] = q[j] - omega * y[j];
+        FLOPS(6); REC(2);
+        info->iters = i + 1;
+        /* w_{i+1} := A r_{i+1} */
+        spmv(A, r, w);
+        /* reduction (r_0,r_{i+1}), (r_0,w_{i+1}), (r_0,s_i), (r_0,z_i), plus ||r_{i+1}||^2 */
+        double gamma1 = DOT(r0, r), eta = DOT(r0, w), sig_s = DOT(r0, s), sig_z = DOT(r0, z);
+        double nu = DOT(r, r);
+        g_ctr.glred++; g_ctr.dots += 4; FLOPS(8);
+        if (o->scalars) { o->scalars[3 * i] = alpha; o->scalars[3 * i + 1] = omega; }
+        if (!isfinite(gamma1) || !isfinite(eta) || !isfinite(sig_s) || !isfinite(sig_z) || !isfinite(nu)) {
+            info->status = OR_NONFINITE; goto done;
+        }
+        info->relres_rec = sqrt(nu) / rho0;
+        if (o->history) o->history[i + 1] = info->relres_rec;
+        if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
+        /* beta_i := (alpha_i / omega_i) (r_0, r_{i+1}) / (r_0, r_i) ; alpha_{i+1} by eq. (3) or (5) */
+        if (omega == 0.0 || gamma == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+        beta = (alpha / omega) * (gamma1 / gamma);
+        if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }
+        if (o->scalars) o->scalars[3 * i + 2] = beta;
+        if (g_alpha_form == 5) {
+            if (gamma1 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+            double den5 = (1.0 / omega + eta / gamma1) - (beta * omega) * (sig_z / gamma1);
+            if (den5 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+            alpha = 1.0 / den5;
+        } else {
+            double den = eta + beta * sig_s - beta * omega * sig_z;
+            if (den == 0.0 || gamma1 == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+            alpha = gamma1 / den;
+        }
+        if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
+        gamma = gamma1;
+    }
+    info->status = OR_MAXIT;
+done:
+    finish(A, b, x, rho0, tmp, prod, info);
+    free(r0); free(r); free(w); free(p); free(s); free(z); free(q); free(y); free(tmp); free(prod);
+    return info->status;
+oom:
+    free(r0); free(r); free(w); free(p); free(s); free(z); free(q); free(y); free(tmp); free(prod);
+    return OR_ERR_ALLOC;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Precision form: p-BiCGStab (Alg. 9) with FP32 vectors, SpMV, recurrences */
 /* and dot products, and FP64 residual replacement (Section 4.2), x update  */
 /* and scalars alpha, beta, omega.                                           */
@@ -869,7 +974,8 @@ int or_solve_mp(int32_t n, const int32_t* rp, const int32_t* ci, const double* v
 
 /*
  * Entry point.  algo: 0 BiCGStab (Alg. 7 / 10), 1 p-BiCGStab (Alg. 9 / 11),
- * 2 p-BiCGStab with residual replacement.  dinv NULL = no preconditioner.
+ * 2 p-BiCGStab with residual replacement, 3 CA-BiCGStab (Alg. 8; dinv must
+ * be NULL).  dinv NULL = no preconditioner.
  * x holds x_0 on entry and the final iterate on return.
  * ints_out[3] = {iters, n_rr, status}; dbl_out[2] = {relres_rec, relres_true}.
  */
@@ -885,6 +991,7 @@ int or_solve(int32_t algo, int32_t n, const int32_t* rp, const int32_t* ci, cons
     int st;
     if (algo == 0) st = bicgstab(&A, dinv, b, x, &o, &info);
     else if (algo == 1 || algo == 2) st = pbicgstab(&A, dinv, b, x, &o, &info);
+    else if (algo == 3 && !dinv) st = ca_bicgstab(&A, b, x, &o, &info);
     else return OR_ERR_INVALID_ARG;
     if (st < 0) return st;
     ints_out[0] = info.iters; ints_out[1] = info.n_rr; ints_out[2] = info.status;

@@ -512,3 +512,81 @@ def test_fp64_oracle_alpha_eq5_converges(pc):
     # the option is per call: the next default call is eq. (3) again
     x3b, i3b = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=1e-10, rr_period=20)
     assert np.array_equal(x3, x3b) and not np.array_equal(x3, x5)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 8, CA-BiCGStab (Section 3.1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,S,b", tiny_systems(), ids=_IDS)
+def test_exact_ca_alpha_eq5_equals_eq3(name, S, b):
+    """Eq. (5) is derived in the CA setting; with it Algorithm 8 still equals Algorithm 7 exactly."""
+    A = frac_rows(S)
+    bf = [Fraction(float(v)) for v in b]
+    x0 = [Fraction(0)] * len(bf)
+    N = len(bf)
+    steps = N + 2 if N <= 4 else EXACT_STEPS
+    r7, s7 = exact.bicgstab(A, bf, x0, steps)
+    r8, s8 = exact.ca_bicgstab(A, bf, x0, steps, alpha_form=5)
+    assert s7 == s8 and len(r7) == len(r8)
+    _same_records([r7, r8])
+
+
+@pytest.mark.parametrize("alpha_form", [3, 5])
+def test_fp64_ca_tracks_exact_iterates(alpha_form):
+    """The FP64 Algorithm 8 agrees with the exact recurrence: x_k to 1e-13 for k <= 6,
+    the scalars to 1e-13 for k <= 3 and 1e-10 up to k = 6."""
+    name, S, b = tiny_systems()[2]
+    A = oracle.CSR(S.indptr, S.indices, S.data)
+    Af = frac_rows(S)
+    bf = [Fraction(float(v)) for v in b]
+    ref, _ = exact.ca_bicgstab(Af, bf, [Fraction(0)] * len(bf), 6, alpha_form=alpha_form)
+    for k in range(1, 7):
+        x, info = oracle.solve(A, b, algo=oracle.ALG_CA_BICGSTAB, tol=0.0, maxit=k, scalars=True,
+                               alpha_form=alpha_form)
+        if info["status"] != oracle.MAXIT:
+            break
+        xr = _frac_to_float(ref[k - 1]["x"])
+        assert np.linalg.norm(x - xr) <= 1e-13 * np.linalg.norm(xr)
+        a, w, _ = info["scalars"][k - 1]
+        tol = 1e-13 if k <= 3 else 1e-10
+        assert abs(a - float(ref[k - 1]["alpha"])) <= tol * abs(float(ref[k - 1]["alpha"]))
+        assert abs(w - float(ref[k - 1]["omega"])) <= tol * abs(float(ref[k - 1]["omega"]))
+
+
+def test_ca_cost_counters():
+    """Section 3.1: Algorithm 8 keeps two SpMVs, has two reduction phases instead of
+    three, and two dot products more than Algorithm 7 (six against four)."""
+    A = oracle.assemble_workload(inputs.workload("c1"))
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    c7 = _per_iteration_counters(A, b, oracle.ALG_BICGSTAB, None)
+    c8 = _per_iteration_counters(A, b, oracle.ALG_CA_BICGSTAB, None)
+    assert (c7["spmv"], c7["glred"], c7["dots"]) == (2, 3, 4)
+    assert (c8["spmv"], c8["glred"], c8["dots"], c8["pc"]) == (2, 2, 6, 0)
+    # recurrences p, s (eq. (1)), q, y (eq. (4)), x, r
+    assert c8["rec"] == 6
+
+
+@pytest.mark.parametrize("name,A,pc", dense_cases(), ids=lambda v: v if isinstance(v, str) else "")
+def test_ca_solution_against_dense_lu(name, A, pc):
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    if pc:
+        x, info = oracle.solve_folded(A, b, algo=oracle.ALG_CA_BICGSTAB, dinv=oracle.jacobi_dinv(A), tol=1e-10)
+    else:
+        x, info = oracle.solve(A, b, algo=oracle.ALG_CA_BICGSTAB, tol=1e-10)
+    assert info["status"] == oracle.SUCCESS and info["n_rr"] == 0
+    D = A.to_scipy().toarray()
+    x_lu = np.linalg.solve(D, b)
+    assert info["relres_true"] <= 1e-9
+    assert np.linalg.norm(x - x_lu) <= 10 * np.linalg.cond(D) * 1e-10 * np.linalg.norm(x_lu)
+
+
+def test_ca_early_iterates_match_standard_and_rejects_dinv():
+    A = oracle.assemble_workload(inputs.workload("c1"))
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    for k in range(1, 11):
+        xs, _ = oracle.solve(A, b, algo=oracle.ALG_BICGSTAB, tol=0.0, maxit=k)
+        xc, _ = oracle.solve(A, b, algo=oracle.ALG_CA_BICGSTAB, tol=0.0, maxit=k)
+        assert np.linalg.norm(xc - xs) <= 1e-10 * np.linalg.norm(xs)
+    with pytest.raises(ValueError):
+        oracle.solve(A, b, algo=oracle.ALG_CA_BICGSTAB, dinv=oracle.jacobi_dinv(A))
