@@ -91,10 +91,16 @@ def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: boo
     K_b reads z^, r, s, w, z, t, r^, s^, w^, x, p^, r0 and writes x, v, r, r^,
     w, w^ (18): 34.  BiCGStab, SpMV kernels s = A p^ + (r0,s) and y = A q^ +
     (q,y), (y,y): 3 + 2 (folded, Algorithm 7: 19 per iteration) or 3 + 3
-    (Algorithm 10: 23 per iteration).
+    (Algorithm 10: 23 per iteration).  CA-BiCGStab (Algorithm 8, folded), its
+    two SpMV kernels z = A s + (q,y), (y,y) (reads s, r, w, writes z: 4) and
+    w = A r + five dots (reads r, r0, s, z, writes w: 5), and the two update
+    kernels p, s (reads r, p, s, w, z, writes p, s: 7) and x, r (reads r, s,
+    w, z, x, p, writes x, r: 8): 24 per iteration.
     """
     vec = 8 * N
     mat = 0 if stencil else 4 * (N + 1) + 12 * nnz
+    if variant == "ca_bicgstab":
+        return mat + 4 * vec, mat + 5 * vec, 24 * vec + 2 * mat
     if variant == "bicgstab":
         if folded:
             return mat + 3 * vec, mat + 2 * vec, 19 * vec + 2 * mat
@@ -159,13 +165,14 @@ def main():
     LEGS = {
         "pipe": ("csr", "pbicgstab_rr", "jacobi_folded"),        # the metric
         "bicg": ("csr", "bicgstab", "jacobi_folded"),
+        "ca": ("csr", "ca_bicgstab", "jacobi_folded"),
         "pipe_norr": ("csr", "pbicgstab", "jacobi_folded"),
         "pipe_alg11": ("csr", "pbicgstab_rr", "jacobi"),
         "bicg_alg10": ("csr", "bicgstab", "jacobi"),
         "st_pipe": ("stencil", "pbicgstab_rr", "jacobi_folded"),
         "st_bicg": ("stencil", "bicgstab", "jacobi_folded"),
     }
-    groups = {"pipe": ["pipe", "pipe_norr"], "bicg": ["bicg"], "explicit": ["pipe_alg11", "bicg_alg10"],
+    groups = {"pipe": ["pipe", "pipe_norr"], "bicg": ["bicg", "ca"], "explicit": ["pipe_alg11", "bicg_alg10"],
               "stencil": ["st_pipe", "st_bicg"]}
     res = {}
     for g in ("pipe", "bicg", "explicit", "stencil"):
@@ -447,6 +454,10 @@ def main():
             out["pbicgstab_over_bicgstab_iters_per_s"] = round(value / bval, 4)
             out["pbicgstab_over_bicgstab_time_to_solution"] = round(
                 out["bicgstab"]["ms_per_solve"] / (dt / args.steps * 1e3), 4)
+    if "ca" in res:
+        out["ca_bicgstab"] = leg_summary("ca", "ca_bicgstab", False, True)
+        if value:
+            out["pbicgstab_over_ca_bicgstab_iters_per_s"] = round(value / out["ca_bicgstab"]["iters_per_s"], 4)
     if "pipe_norr" in res:
         out["pbicgstab_without_replacement"] = leg_summary("pipe_norr", "pbicgstab", False, True)
     if "pipe_alg11" in res:

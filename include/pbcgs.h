@@ -12,7 +12,12 @@
  *   PBCGS_PBICGSTAB      pipelined BiCGStab, Algorithm 9 (Section 3.3), or the
  *                        preconditioned pipelined form Algorithm 11 (Section 3.6);
  *   PBCGS_PBICGSTAB_RR   Algorithm 9/11 with residual replacement every k
- *                        iterations (Section 4.2).
+ *                        iterations (Section 4.2);
+ *   PBCGS_CA_BICGSTAB    communication-avoiding BiCGStab, Algorithm 8
+ *                        (Section 3.1): two reduction phases like p-BiCGStab
+ *                        but no overlap, so four kernel boundaries per
+ *                        iteration.  No preconditioner, or Jacobi as
+ *                        PBCGS_PRECOND_JACOBI_FOLDED; binary64; not batched.
  *
  * Right preconditioning solves A M^{-1} y = b, M x = y (Section 3.6).  The only
  * preconditioner is Jacobi, M = diag(A).  The stopping test is
@@ -58,7 +63,7 @@ typedef enum {
     PBCGS_ERR_UNSUPPORTED = -4    /* valid request this build does not implement           */
 } pbcgs_status;
 
-enum { PBCGS_BICGSTAB = 0, PBCGS_PBICGSTAB = 1, PBCGS_PBICGSTAB_RR = 2 };
+enum { PBCGS_BICGSTAB = 0, PBCGS_PBICGSTAB = 1, PBCGS_PBICGSTAB_RR = 2, PBCGS_CA_BICGSTAB = 3 };
 /* Preconditioners.  JACOBI applies M^{-1} = diag(dinv) inside Algorithm 10 / 11
  * (the hatted vectors of Section 3.6).  JACOBI_FOLDED is the same right
  * preconditioning with the operator formed: the unpreconditioned Algorithm 7 / 9
@@ -82,7 +87,8 @@ enum { PBCGS_FP64 = 0, PBCGS_FP32_RR64 = 1 };
 
 /* Solver options (host struct). */
 typedef struct {
-    int32_t variant;     /* PBCGS_BICGSTAB, PBCGS_PBICGSTAB or PBCGS_PBICGSTAB_RR          */
+    int32_t variant;     /* PBCGS_BICGSTAB, PBCGS_PBICGSTAB, PBCGS_PBICGSTAB_RR or
+                            PBCGS_CA_BICGSTAB                                              */
     int32_t precond;     /* PBCGS_PRECOND_NONE, _JACOBI or _JACOBI_FOLDED                  */
     int32_t precision;   /* PBCGS_FP64 or PBCGS_FP32_RR64                                   */
     int32_t maxit;       /* iteration budget, >= 0                                          */
@@ -92,7 +98,7 @@ typedef struct {
     int32_t check_every; /* iterations between host polls of the device status; 0 = auto   */
     int32_t flags;       /* bit 0: launch each kernel directly instead of through a
                             captured HIP graph; bit 1: time the fused kernels with events;
-                            bit 2: alpha_{i+1} of PBICGSTAB(_RR) by eq. (5), the form
+                            bit 2: alpha_{i+1} of PBICGSTAB(_RR) and CA_BICGSTAB by eq. (5), the form
                             without (r0, s_i), instead of eq. (3) (Section 3.1)          */
     double* history;     /* nullable DEVICE array of maxit+1 doubles: history[i] =
                             ||r_i|| / ||r_0|| after i iterations (history[0] = 1)           */
@@ -103,7 +109,7 @@ typedef struct {
     int32_t iters;           /* completed x-updates                                       */
     int32_t n_rr;            /* residual replacements performed                           */
     int32_t status;          /* pbcgs_status of the numerical outcome                     */
-    int32_t syncs_per_iter;  /* kernel boundaries of one regular iteration (5 or 2)       */
+    int32_t syncs_per_iter;  /* kernel boundaries of one regular iteration (5, 4 or 2)    */
     double relres_rec;       /* last ||r_i|| / ||r_0|| of the recurrence                  */
     double relres_true;      /* ||b - A x|| / ||r_0|| of the returned x                   */
     double ms;               /* wall time of the iteration loop (HIP events), ms           */

@@ -775,6 +775,106 @@ template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_rr_s(Op op, Args a) { d_rr_s<Op, PC>(op, a); }
 
 // ===========================================================================
+// CA-BiCGStab kernels (Algorithm 8, no preconditioner; Jacobi reaches it
+// folded into the operator).  s and y follow their recurrences (eqs. (1) and
+// (4)); the two reductions are those of p-BiCGStab, so the scalar steps are
+// shared.  Each SpMV reads a vector that the preceding kernel finished, which
+// gives four kernel boundaries per iteration.  p is stored in the p^ slot.
+// The setup is that of p-BiCGStab (r0, r, w = A r0, alpha_0); its t is not
+// used.
+// ===========================================================================
+
+// First finishes the previous reduction (alpha_0 in the first iteration, else
+// the stop test, beta_{i-1} and alpha_i), then
+// p_i = r_i + beta (p_{i-1} - omega s_{i-1}) ; s_i = w_i + beta (s_{i-1} - omega z_{i-1}).
+__device__ __forceinline__ void d_ca_ps(Args a) {
+  PBCGS_PROLOGUE(st)
+  if (a.first) {
+    double g[1];
+    gather_sums<1>(a, g);
+    fin_setup_alpha(st, g[0]);
+  } else {
+    double g[5];
+    gather_sums<5>(a, g);
+    fin_pipe_b(st, a.hist, g, a.aform);
+  }
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double beta = st.beta, omega = st.omega;
+  each_row(a, [&](int32_t row, bool valid) {
+    if (!valid) return;
+    const double s_old = a.s[row];
+    a.ph[row] = a.r[row] + beta * (a.ph[row] - omega * s_old);
+    a.s[row] = a.w[row] + beta * (s_old - omega * a.z[row]);
+  });
+}
+__global__ __launch_bounds__(kWG) void k_ca_ps(Args a) { d_ca_ps(a); }
+
+// z_i = A s_i ; q_i = r_i - alpha_i s_i ; y_i = w_i - alpha_i z_i ;
+// partials of (q, y), (y, y).  q and y are recomputed by the next kernel.
+template <class Op>
+__device__ __forceinline__ void d_ca_z(Op op, Args a) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  const double alpha = st.alpha;
+  produce<2>(a, [&](int32_t row, bool valid, double (&d)[2]) {
+    const double z = op.spmv(row, valid, a.s);
+    if (!valid) return;
+    const double q = a.r[row] - alpha * a.s[row];
+    const double y = a.w[row] - alpha * z;
+    a.z[row] = z;
+    d[0] = q * y;
+    d[1] = y * y;
+  });
+}
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_ca_z(Op op, Args a) { d_ca_z<Op>(op, a); }
+
+// omega_i ; x_{i+1} = x_i + alpha_i p_i + omega_i q_i ; r_{i+1} = q_i - omega_i y_i.
+__device__ __forceinline__ void d_ca_x(Args a) {
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2>(a, g2);
+  const double alpha = st.alpha;
+  const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
+  if (!yz && st.status != DS_RUNNING) return;
+  const double omega = st.omega;
+  each_row(a, [&](int32_t row, bool valid) {
+    if (!valid) return;
+    if (yz) {
+      a.x[row] = a.x[row] + alpha * a.ph[row];
+      return;
+    }
+    const double q = a.r[row] - alpha * a.s[row];
+    const double y = a.w[row] - alpha * a.z[row];
+    a.x[row] = a.x[row] + alpha * a.ph[row] + omega * q;
+    a.r[row] = q - omega * y;
+  });
+}
+__global__ __launch_bounds__(kWG) void k_ca_x(Args a) { d_ca_x(a); }
+
+// w_{i+1} = A r_{i+1} ; partials of (r0, r), (r0, w), (r0, s), (r0, z), (r, r).
+template <class Op>
+__device__ __forceinline__ void d_ca_w(Op op, Args a) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  produce<5>(a, [&](int32_t row, bool valid, double (&d)[5]) {
+    const double w = op.spmv(row, valid, a.r);
+    if (!valid) return;
+    a.w[row] = w;
+    const double r0 = a.r0[row], r = a.r[row];
+    d[0] = r0 * r;
+    d[1] = r0 * w;
+    d[2] = r0 * a.s[row];
+    d[3] = r0 * a.z[row];
+    d[4] = r * r;
+  });
+}
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_ca_w(Op op, Args a) { d_ca_w<Op>(op, a); }
+
+// ===========================================================================
 // BiCGStab kernels (Algorithm 7, PC == PC_NONE; Algorithm 10 otherwise).
 // ===========================================================================
 

@@ -411,6 +411,15 @@ struct Driver {
   // Kernels of iteration i of the binary64 solvers.
   void iteration64(int64_t i) {
     hipStream_t s = ctx->stream;
+    if constexpr (PC == PC_NONE) {
+      if (o.variant == PBCGS_CA_BICGSTAB) {
+        k_ca_ps<<<grid(), kWG, 0, s>>>(L(i == 0 ? PB_SETUP2 : PB_B, -1, i == 0));
+        timed(0, [&] { k_ca_z<Op><<<grid(), kWG, 0, s>>>(op, L(-1, PB_A)); });
+        k_ca_x<<<grid(), kWG, 0, s>>>(L(PB_A, -1));
+        timed(1, [&] { k_ca_w<Op><<<grid(), kWG, 0, s>>>(op, L(-1, PB_B)); });
+        return;
+      }
+    }
     if (o.variant == PBCGS_BICGSTAB) {
       timed(0, [&] { k_b1<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_SETUP1, PB_B1, i == 0)); });
       k_b2<PC><<<grid(), kWG, 0, s>>>(L(PB_B1, -1));
@@ -441,6 +450,10 @@ struct Driver {
   void count_iteration(int64_t i) {
     if (o.variant == PBCGS_BICGSTAB) {
       q += 5;
+      return;
+    }
+    if (o.variant == PBCGS_CA_BICGSTAB) {
+      q += 4;
       return;
     }
     q += (pending_rr(i) ? 3 : 1) + (rr_due(o, i) ? 3 : 1);
@@ -527,6 +540,7 @@ struct Driver {
   bool use_persistent() {
     if constexpr (MP) return false;
     if (o.flags & 2) return false;
+    if (o.variant == PBCGS_CA_BICGSTAB) return false;
     if (o.maxit > 200000) return false;
     if (env_int("PBCGS_PERSIST", 0) != 1) return false;
     if (ctx->coop < 0) {
@@ -683,7 +697,7 @@ struct Driver {
     info->iters = fin.iters;
     info->n_rr = fin.n_rr;
     info->status = map_status(fin.status);
-    info->syncs_per_iter = (o.variant == PBCGS_BICGSTAB) ? 5 : 2;
+    info->syncs_per_iter = (o.variant == PBCGS_BICGSTAB) ? 5 : (o.variant == PBCGS_CA_BICGSTAB) ? 4 : 2;
     info->relres_rec = fin.relres;
     info->ms = ms;
     for (int k = 0; k < 2; ++k) {
@@ -1179,11 +1193,13 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
   if (!ctx || !A || !b || !x || !opts || !info) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
   if (A->ctx != ctx) return fail(ctx, PBCGS_ERR_INVALID_ARG, "operator belongs to another context");
   const pbcgs_opts& o = *opts;
-  if (o.variant < PBCGS_BICGSTAB || o.variant > PBCGS_PBICGSTAB_RR)
+  if (o.variant < PBCGS_BICGSTAB || o.variant > PBCGS_CA_BICGSTAB)
     return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown variant");
   if (o.precond != PBCGS_PRECOND_NONE && o.precond != PBCGS_PRECOND_JACOBI &&
       o.precond != PBCGS_PRECOND_JACOBI_FOLDED)
     return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown preconditioner");
+  if (o.variant == PBCGS_CA_BICGSTAB && o.precond == PBCGS_PRECOND_JACOBI)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "CA-BiCGStab takes Jacobi as PBCGS_PRECOND_JACOBI_FOLDED");
   const bool folded = (o.precond == PBCGS_PRECOND_JACOBI_FOLDED);
   if (o.precision != PBCGS_FP64 && o.precision != PBCGS_FP32_RR64)
     return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown precision");
@@ -1456,8 +1472,10 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
   if (!ctx || !A || !b || !x || !opts || !infos) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
   if (nsys <= 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "nsys must be positive");
   const pbcgs_opts& o = *opts;
-  if (o.variant < PBCGS_BICGSTAB || o.variant > PBCGS_PBICGSTAB_RR)
+  if (o.variant < PBCGS_BICGSTAB || o.variant > PBCGS_CA_BICGSTAB)
     return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown variant");
+  if (o.variant == PBCGS_CA_BICGSTAB)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves run BiCGStab or p-BiCGStab");
   if (o.precond != PBCGS_PRECOND_NONE)
     return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves take no preconditioner");
   if (o.precision != PBCGS_FP64) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves are binary64");
