@@ -30,6 +30,9 @@ ALG_BICGSTAB = 0
 ALG_PBICGSTAB = 1
 ALG_PBICGSTAB_RR = 2
 ALG_CA_BICGSTAB = 3  # Algorithm 8, unpreconditioned (a preconditioned solve folds A M^{-1})
+ALG_CG = 4         # Algorithm 2 (symmetric positive definite A)
+ALG_CGCG = 5       # Algorithm 4
+ALG_PIPE_CG = 6    # Algorithm 6 (p-CG)
 
 SUCCESS, MAXIT, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 STATUS_NAMES = {0: "success", 1: "maxit", 2: "breakdown", 3: "nonfinite"}

@@ -249,3 +249,126 @@ def pbicgstab(A, b, x0, maxit, dinv=None, rr_period=0, alpha_form=3):
             alpha = g1 / den
         gamma = g1
     return out, "maxit", replaced
+
+
+# ---------------------------------------------------------------------------
+# The CG family of Section 2 (symmetric positive definite A).  Each record
+# holds x_{i+1}, r_{i+1}, alpha_i and the beta_i that built p_i (0 for i = 0),
+# so the three algorithms can be compared record by record.
+# ---------------------------------------------------------------------------
+
+def cg(A, b, x0, maxit, dinv=None):
+    """Algorithm 2 (standard preconditioned CG)."""
+    M = (lambda v: scale(dinv, v)) if dinv is not None else (lambda v: list(v))
+    x = list(x0)
+    r = sub(b, matvec(A, x))
+    if all(v == 0 for v in r):
+        return [], "converged"
+    u = M(r)
+    p = list(u)
+    gamma = dot(r, u)
+    beta = ZERO
+    out = []
+    for _ in range(maxit):
+        s = matvec(A, p)
+        delta = dot(s, p)
+        if delta == 0:
+            return out, "breakdown"
+        alpha = gamma / delta
+        x = axpy(alpha, p, x)
+        r = axpy(-alpha, s, r)
+        u = M(r)
+        out.append(_rec(x, r, alpha, None, beta))
+        if all(v == 0 for v in r):
+            return out, "converged"
+        gamma1 = dot(r, u)
+        beta = gamma1 / gamma
+        p = axpy(beta, p, u)
+        gamma = gamma1
+    return out, "maxit"
+
+
+def cgcg(A, b, x0, maxit, dinv=None):
+    """Algorithm 4 (Chronopoulos & Gear CG)."""
+    n = len(b)
+    M = (lambda v: scale(dinv, v)) if dinv is not None else (lambda v: list(v))
+    x = list(x0)
+    r = sub(b, matvec(A, x))
+    if all(v == 0 for v in r):
+        return [], "converged"
+    u = M(r)
+    w = matvec(A, u)
+    gamma, delta = dot(r, u), dot(w, u)
+    if delta == 0:
+        return [], "breakdown"
+    alpha, beta = gamma / delta, ZERO
+    p = [ZERO] * n
+    s = [ZERO] * n
+    out = []
+    for _ in range(maxit):
+        p = axpy(beta, p, u)
+        s = axpy(beta, s, w)
+        x = axpy(alpha, p, x)
+        r = axpy(-alpha, s, r)
+        u = M(r)
+        w = matvec(A, u)
+        out.append(_rec(x, r, alpha, None, beta))
+        if all(v == 0 for v in r):
+            return out, "converged"
+        gamma1, delta = dot(r, u), dot(w, u)
+        if gamma1 == 0:
+            return out, "breakdown"
+        beta = gamma1 / gamma
+        den = delta / gamma1 - beta / alpha
+        if den == 0:
+            return out, "breakdown"
+        alpha = 1 / den
+        gamma = gamma1
+    return out, "maxit"
+
+
+def pipe_cg(A, b, x0, maxit, dinv=None):
+    """Algorithm 6 (pipelined CG)."""
+    n = len(b)
+    M = (lambda v: scale(dinv, v)) if dinv is not None else (lambda v: list(v))
+    x = list(x0)
+    r = sub(b, matvec(A, x))
+    if all(v == 0 for v in r):
+        return [], "converged"
+    u = M(r)
+    w = matvec(A, u)
+    z = [ZERO] * n
+    q = [ZERO] * n
+    s = [ZERO] * n
+    p = [ZERO] * n
+    alpha = gamma = None
+    out = []
+    for i in range(maxit):
+        gamma1, delta = dot(r, u), dot(w, u)
+        m = M(w)
+        nv = matvec(A, m)
+        if i == 0:
+            if delta == 0:
+                return out, "breakdown"
+            beta, alpha = ZERO, gamma1 / delta
+        else:
+            if gamma1 == 0:
+                return out, "breakdown"
+            beta = gamma1 / gamma
+            den = delta / gamma1 - beta / alpha
+            if den == 0:
+                return out, "breakdown"
+            alpha = 1 / den
+        gamma = gamma1
+        z = axpy(beta, z, nv)
+        q = axpy(beta, q, m)
+        s = axpy(beta, s, w)
+        p = axpy(beta, p, u)
+        x = axpy(alpha, p, x)
+        r = axpy(-alpha, s, r)
+        u = axpy(-alpha, q, u)
+        w = axpy(-alpha, z, w)
+        out.append(_rec(x, r, alpha, None, beta))
+        if all(v == 0 for v in r):
+            return out, "converged"
+    return out, "maxit"

@@ -11,6 +11,9 @@
  * appearance; the solvers below follow them step by step, in the paper's
  * order and notation:
  *
+ *   Algorithm 2   standard preconditioned CG             (Section 2)
+ *   Algorithm 4   Chronopoulos & Gear CG                 (Section 2)
+ *   Algorithm 6   pipelined CG                           (Section 2)
  *   Algorithm 7   standard BiCGStab                     (Section 3.1)
  *   Algorithm 8   communication-avoiding BiCGStab        (Section 3.1)
  *   Algorithm 9   pipelined BiCGStab, unpreconditioned   (Section 3.3)
@@ -717,6 +720,238 @@ oom:
 }
 
 /* ------------------------------------------------------------------------ */
+/* The CG family of Section 2, for symmetric positive definite A (and M):   */
+/*   Alg. 2  standard preconditioned CG: two reduction phases per iteration; */
+/*   Alg. 4  Chronopoulos & Gear CG: one reduction phase, w = A u by         */
+/*           recurrence-free SpMV, alpha from (delta/gamma - beta/alpha)^-1; */
+/*   Alg. 6  pipelined CG (p-CG): one reduction phase overlapped with the   */
+/*           SpMV n = A M^{-1} w; z, q, s, p, x, r, u, w by recurrences.    */
+/* M^{-1} = diag(dinv) or the identity (dinv == NULL; then u = r, and in    */
+/* Alg. 6 also m = w and q = s).  The squared norm of r joins a reduction   */
+/* phase for the stopping test ||r_i|| / ||r_0|| <= tol.  scalars[3i] and    */
+/* scalars[3i+2] hold alpha_i and beta_{i+1} (Alg. 2) or beta_i (Alg. 4, 6). */
+/* ------------------------------------------------------------------------ */
+static int cg(const csr_t* A, const double* dinv, const double* b, double* x, const or_opts* o, or_info* info)
+{
+    const int32_t n = A->n;
+    const int pc = (dinv != NULL);
+    double *r = 0, *u = 0, *p = 0, *s = 0, *tmp = 0, *prod = 0;
+    NEWVEC(r); NEWVEC(p); NEWVEC(s); NEWVEC(tmp);
+    if (pc) NEWVEC(u); else u = r;
+    prod = (double*)malloc(sizeof(double) * (size_t)pow2_at_least(n));
+    if (!prod) goto oom;
+
+    info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
+    /* r_0 := b - A x_0 ; u_0 := M^{-1} r_0 ; p_0 := u_0 */
+    spmv(A, x, tmp);
+    PAR for (int32_t j = 0; j < n; ++j) r[j] = b[j] - tmp[j];
+    if (pc) { PAR for (int32_t j = 0; j < n; ++j) u[j] = dinv[j] * r[j]; }
+    memcpy(p, u, sizeof(double) * (size_t)n);
+    const double rho0 = sqrt(DOT(r, r));
+    double gamma = DOT(r, u);
+    if (o->history) o->history[0] = 1.0;
+    if (!isfinite(rho0) || !isfinite(gamma)) { info->status = OR_NONFINITE; goto done; }
+    if (rho0 == 0.0) { info->status = OR_SUCCESS; info->relres_rec = 0.0; goto done; }
+
+    for (int32_t i = 0; i < o->maxit; ++i) {
+        /* s_i := A p_i ; reduction (s_i, p_i) ; alpha_i := (r_i, u_i) / (s_i, p_i) */
+        spmv(A, p, s);
+        double delta = DOT(s, p);
+        g_ctr.glred++; g_ctr.dots++; FLOPS(2);
+        if (!isfinite(delta)) { info->status = OR_NONFINITE; goto done; }
+        if (delta == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+        double alpha = gamma / delta;
+        if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
+        /* x_{i+1} := x_i + alpha_i p_i ; r_{i+1} := r_i - alpha_i s_i ; u_{i+1} := M^{-1} r_{i+1} */
+        PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
+        PAR for (int32_t j = 0; j < n; ++j) r[j] = r[j] - alpha * s[j];
+        if (pc) { PAR for (int32_t j = 0; j < n; ++j) u[j] = dinv[j] * r[j]; g_ctr.pc++; }
+        FLOPS(4); REC(2);
+        info->iters = i + 1;
+        if (o->scalars) o->scalars[3 * i] = alpha;
+        /* reduction (r_{i+1}, u_{i+1}) with ||r_{i+1}||^2 */
+        double gamma1 = DOT(r, u), nu = DOT(r, r);
+        g_ctr.glred++; g_ctr.dots++; FLOPS(2);
+        if (!isfinite(gamma1) || !isfinite(nu)) { info->status = OR_NONFINITE; goto done; }
+        info->relres_rec = sqrt(nu) / rho0;
+        if (o->history) o->history[i + 1] = info->relres_rec;
+        if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
+        /* beta_{i+1} := (r_{i+1}, u_{i+1}) / (r_i, u_i) ; p_{i+1} := u_{i+1} + beta_{i+1} p_i */
+        if (gamma == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+        double beta = gamma1 / gamma;
+        if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }
+        if (o->scalars) o->scalars[3 * i + 2] = beta;
+        PAR for (int32_t j = 0; j < n; ++j) p[j] = u[j] + beta * p[j];
+        FLOPS(2); REC(1);
+        gamma = gamma1;
+    }
+    info->status = OR_MAXIT;
+done:
+    finish(A, b, x, rho0, tmp, prod, info);
+    free(r); free(p); free(s); free(tmp); free(prod);
+    if (pc) free(u);
+    return info->status;
+oom:
+    free(r); free(p); free(s); free(tmp); free(prod);
+    if (pc) free(u);
+    return OR_ERR_ALLOC;
+}
+
+/* alpha of Alg. 4 and Alg. 6 after the first iteration: (delta/gamma - beta/alpha_prev)^{-1}. */
+static int cg_next_alpha(double gamma1, double gamma, double delta, double alpha_prev, double* beta,
+                         double* alpha)
+{
+    if (gamma == 0.0 || gamma1 == 0.0 || alpha_prev == 0.0) return OR_BREAKDOWN;
+    *beta = gamma1 / gamma;
+    if (!isfinite(*beta)) return OR_NONFINITE;
+    double den = delta / gamma1 - *beta / alpha_prev;
+    if (den == 0.0) return OR_BREAKDOWN;
+    *alpha = 1.0 / den;
+    if (!isfinite(*alpha)) return OR_NONFINITE;
+    return OR_SUCCESS;
+}
+
+static int cgcg(const csr_t* A, const double* dinv, const double* b, double* x, const or_opts* o, or_info* info)
+{
+    const int32_t n = A->n;
+    const int pc = (dinv != NULL);
+    double *r = 0, *u = 0, *w = 0, *p = 0, *s = 0, *tmp = 0, *prod = 0;
+    NEWVEC(r); NEWVEC(w); NEWVEC(p); NEWVEC(s); NEWVEC(tmp);
+    if (pc) NEWVEC(u); else u = r;
+    prod = (double*)malloc(sizeof(double) * (size_t)pow2_at_least(n));
+    if (!prod) goto oom;
+
+    info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
+    /* r_0 := b - A x_0 ; u_0 := M^{-1} r_0 ; w_0 := A u_0 */
+    spmv(A, x, tmp);
+    PAR for (int32_t j = 0; j < n; ++j) r[j] = b[j] - tmp[j];
+    if (pc) { PAR for (int32_t j = 0; j < n; ++j) u[j] = dinv[j] * r[j]; }
+    spmv(A, u, w);
+    const double rho0 = sqrt(DOT(r, r));
+    double gamma = DOT(r, u), delta = DOT(w, u);
+    if (o->history) o->history[0] = 1.0;
+    if (!isfinite(rho0) || !isfinite(gamma) || !isfinite(delta)) { info->status = OR_NONFINITE; goto done; }
+    if (rho0 == 0.0) { info->status = OR_SUCCESS; info->relres_rec = 0.0; goto done; }
+    /* alpha_0 := (r_0, u_0) / (w_0, u_0) ; beta_0 := 0 ; p_{-1} = s_{-1} = 0 */
+    if (delta == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+    double alpha = gamma / delta, beta = 0.0;
+    if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
+
+    for (int32_t i = 0; i < o->maxit; ++i) {
+        /* p_i := u_i + beta_i p_{i-1} ; s_i := w_i + beta_i s_{i-1} */
+        PAR for (int32_t j = 0; j < n; ++j) p[j] = u[j] + beta * p[j];
+        PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + beta * s[j];
+        /* x_{i+1} := x_i + alpha_i p_i ; r_{i+1} := r_i - alpha_i s_i */
+        PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
+        PAR for (int32_t j = 0; j < n; ++j) r[j] = r[j] - alpha * s[j];
+        FLOPS(8); REC(4);
+        /* u_{i+1} := M^{-1} r_{i+1} ; w_{i+1} := A u_{i+1} */
+        if (pc) { PAR for (int32_t j = 0; j < n; ++j) u[j] = dinv[j] * r[j]; g_ctr.pc++; }
+        spmv(A, u, w);
+        info->iters = i + 1;
+        if (o->scalars) o->scalars[3 * i] = alpha;
+        /* reduction gamma_{i+1} := (r_{i+1}, u_{i+1}) ; delta := (w_{i+1}, u_{i+1}) ; ||r_{i+1}||^2 */
+        double gamma1 = DOT(r, u), nu = DOT(r, r);
+        delta = DOT(w, u);
+        g_ctr.glred++; g_ctr.dots += 2; FLOPS(4);
+        if (!isfinite(gamma1) || !isfinite(delta) || !isfinite(nu)) { info->status = OR_NONFINITE; goto done; }
+        info->relres_rec = sqrt(nu) / rho0;
+        if (o->history) o->history[i + 1] = info->relres_rec;
+        if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
+        /* beta_{i+1} := gamma_{i+1} / gamma_i ; alpha_{i+1} := (delta / gamma_{i+1} - beta_{i+1} / alpha_i)^{-1} */
+        int st = cg_next_alpha(gamma1, gamma, delta, alpha, &beta, &alpha);
+        if (st != OR_SUCCESS) { info->status = st; goto done; }
+        if (o->scalars && i + 1 < o->maxit) o->scalars[3 * (i + 1) + 2] = beta;
+        gamma = gamma1;
+    }
+    info->status = OR_MAXIT;
+done:
+    finish(A, b, x, rho0, tmp, prod, info);
+    free(r); free(w); free(p); free(s); free(tmp); free(prod);
+    if (pc) free(u);
+    return info->status;
+oom:
+    free(r); free(w); free(p); free(s); free(tmp); free(prod);
+    if (pc) free(u);
+    return OR_ERR_ALLOC;
+}
+
+static int pipe_cg(const csr_t* A, const double* dinv, const double* b, double* x, const or_opts* o,
+                   or_info* info)
+{
+    const int32_t n = A->n;
+    const int pc = (dinv != NULL);
+    double *r = 0, *u = 0, *w = 0, *m = 0, *nv = 0, *z = 0, *q = 0, *s = 0, *p = 0, *tmp = 0, *prod = 0;
+    NEWVEC(r); NEWVEC(w); NEWVEC(nv); NEWVEC(z); NEWVEC(s); NEWVEC(p); NEWVEC(tmp);
+    if (pc) { NEWVEC(u); NEWVEC(m); NEWVEC(q); } else { u = r; m = w; q = s; }
+    prod = (double*)malloc(sizeof(double) * (size_t)pow2_at_least(n));
+    if (!prod) goto oom;
+
+    info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
+    /* r_0 := b - A x_0 ; u_0 := M^{-1} r_0 ; w_0 := A u_0 ; z_{-1} = q_{-1} = s_{-1} = p_{-1} = 0 */
+    spmv(A, x, tmp);
+    PAR for (int32_t j = 0; j < n; ++j) r[j] = b[j] - tmp[j];
+    if (pc) { PAR for (int32_t j = 0; j < n; ++j) u[j] = dinv[j] * r[j]; }
+    spmv(A, u, w);
+    double rho0 = 0.0, alpha = 0.0, beta = 0.0, gamma = 0.0;
+    if (o->history) o->history[0] = 1.0;
+
+    for (int32_t i = 0;; ++i) {
+        /* reduction gamma_i := (r_i, u_i) ; delta := (w_i, u_i) ; ||r_i||^2 */
+        double gamma1 = DOT(r, u), delta = DOT(w, u), nu = DOT(r, r);
+        if (i > 0) { g_ctr.glred++; g_ctr.dots += 2; FLOPS(4); }
+        if (!isfinite(gamma1) || !isfinite(delta) || !isfinite(nu)) { info->status = OR_NONFINITE; goto done; }
+        if (i == 0) {
+            rho0 = sqrt(nu);
+            if (rho0 == 0.0) { info->status = OR_SUCCESS; info->relres_rec = 0.0; goto done; }
+        } else {
+            info->relres_rec = sqrt(nu) / rho0;
+            if (o->history) o->history[i] = info->relres_rec;
+            if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
+        }
+        if (i == o->maxit) { info->status = OR_MAXIT; goto done; }
+        /* m_i := M^{-1} w_i ; n_i := A m_i   (overlapping the reduction) */
+        if (pc) { PAR for (int32_t j = 0; j < n; ++j) m[j] = dinv[j] * w[j]; g_ctr.pc++; }
+        spmv(A, m, nv);
+        /* end reduction: beta_i, alpha_i */
+        if (i == 0) {
+            if (delta == 0.0) { info->status = OR_BREAKDOWN; goto done; }
+            beta = 0.0;
+            alpha = gamma1 / delta;
+            if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
+        } else {
+            int st = cg_next_alpha(gamma1, gamma, delta, alpha, &beta, &alpha);
+            if (st != OR_SUCCESS) { info->status = st; goto done; }
+        }
+        gamma = gamma1;
+        if (o->scalars) { o->scalars[3 * i] = alpha; o->scalars[3 * i + 2] = beta; }
+        /* z_i := n_i + beta_i z_{i-1} ; q_i := m_i + beta_i q_{i-1} ; s_i := w_i + beta_i s_{i-1} ;
+           p_i := u_i + beta_i p_{i-1} */
+        PAR for (int32_t j = 0; j < n; ++j) z[j] = nv[j] + beta * z[j];
+        if (pc) PAR for (int32_t j = 0; j < n; ++j) q[j] = m[j] + beta * q[j];
+        PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + beta * s[j];
+        PAR for (int32_t j = 0; j < n; ++j) p[j] = u[j] + beta * p[j];
+        /* x_{i+1} := x_i + alpha_i p_i ; r_{i+1} := r_i - alpha_i s_i ; u_{i+1} := u_i - alpha_i q_i ;
+           w_{i+1} := w_i - alpha_i z_i */
+        PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
+        PAR for (int32_t j = 0; j < n; ++j) r[j] = r[j] - alpha * s[j];
+        if (pc) PAR for (int32_t j = 0; j < n; ++j) u[j] = u[j] - alpha * q[j];
+        PAR for (int32_t j = 0; j < n; ++j) w[j] = w[j] - alpha * z[j];
+        FLOPS(pc ? 16 : 12); REC(pc ? 8 : 6);
+        info->iters = i + 1;
+    }
+done:
+    finish(A, b, x, rho0, tmp, prod, info);
+    free(r); free(w); free(nv); free(z); free(s); free(p); free(tmp); free(prod);
+    if (pc) { free(u); free(m); free(q); }
+    return info->status;
+oom:
+    free(r); free(w); free(nv); free(z); free(s); free(p); free(tmp); free(prod);
+    if (pc) { free(u); free(m); free(q); }
+    return OR_ERR_ALLOC;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Precision form: p-BiCGStab (Alg. 9) with FP32 vectors, SpMV, recurrences */
 /* and dot products, and FP64 residual replacement (Section 4.2), x update  */
 /* and scalars alpha, beta, omega.                                           */
@@ -975,7 +1210,9 @@ int or_solve_mp(int32_t n, const int32_t* rp, const int32_t* ci, const double* v
 /*
  * Entry point.  algo: 0 BiCGStab (Alg. 7 / 10), 1 p-BiCGStab (Alg. 9 / 11),
  * 2 p-BiCGStab with residual replacement, 3 CA-BiCGStab (Alg. 8; dinv must
- * be NULL).  dinv NULL = no preconditioner.
+ * be NULL), 4 CG (Alg. 2), 5 Chronopoulos & Gear CG (Alg. 4), 6 p-CG
+ * (Alg. 6); the last three need a symmetric positive definite A.
+ * dinv NULL = no preconditioner.
  * x holds x_0 on entry and the final iterate on return.
  * ints_out[3] = {iters, n_rr, status}; dbl_out[2] = {relres_rec, relres_true}.
  */
@@ -992,6 +1229,9 @@ int or_solve(int32_t algo, int32_t n, const int32_t* rp, const int32_t* ci, cons
     if (algo == 0) st = bicgstab(&A, dinv, b, x, &o, &info);
     else if (algo == 1 || algo == 2) st = pbicgstab(&A, dinv, b, x, &o, &info);
     else if (algo == 3 && !dinv) st = ca_bicgstab(&A, b, x, &o, &info);
+    else if (algo == 4) st = cg(&A, dinv, b, x, &o, &info);
+    else if (algo == 5) st = cgcg(&A, dinv, b, x, &o, &info);
+    else if (algo == 6) st = pipe_cg(&A, dinv, b, x, &o, &info);
     else return OR_ERR_INVALID_ARG;
     if (st < 0) return st;
     ints_out[0] = info.iters; ints_out[1] = info.n_rr; ints_out[2] = info.status;

@@ -19,6 +19,9 @@ boundaries, rows ordered x fastest):
            [32, 512], beta_k ~ U[0, 200]^2 (batched form).
 * ``ptp1`` / ``ptp2``  the paper's two parallel test problems (Section 5),
            1000 x 1000 five-point stencils with exact solution all ones.
+* ``c1s`` / ``c2s`` / ``c3s``  the same grids without convection (beta = 0):
+           symmetric positive definite operators for the CG family
+           (Algorithms 2, 4 and 6), which needs symmetry.
 
 The right-hand side of every system is b = A x_true with x_true drawn here.
 """
@@ -63,6 +66,11 @@ WORKLOADS = {
                    kappa_sigma=1.0, precond="jacobi"),
     "c4": Workload("c4", 3, 256, 7, (50.0, 30.0, 10.0), precond="jacobi",
                    tol=1e-10, maxit=5000, rr_period=20),
+    # symmetric positive definite counterparts (beta = 0) for the CG family
+    "c1s": Workload("c1s", 2, 64, 5, (0.0, 0.0), precond="none"),
+    "c2s": Workload("c2s", 3, 128, 7, (0.0, 0.0, 0.0), precond="jacobi"),
+    "c3s": Workload("c3s", 3, 256, 27, (0.0, 0.0, 0.0), shift=0.1,
+                    kappa_sigma=1.0, precond="jacobi"),
 }
 
 
