@@ -69,7 +69,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     p.add_argument("--only", default="",
-                   help="comma list of legs to run: pipe,bicg,explicit,stencil,precision,batched,sweep,paper,configs")
+                   help="comma list of legs to run: pipe,bicg,explicit,stencil,cg,precision,batched,sweep,paper,configs")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
     return p.parse_args()
@@ -110,6 +110,25 @@ def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: boo
     return mat + 16 * vec, mat + 18 * vec, 34 * vec + 2 * mat
 
 
+def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool):
+    """Algorithmic HBM bytes of one iteration of the CG family (Section 2) on
+    a CSR operator with Jacobi by a constant (a scalar, no vector) or none.
+
+    CG (Algorithm 2): s = A p (gathers p, writes s), x/r/u (reads p, x, r, s,
+    writes x, r and u), p (reads u, p, writes p): 12 vector passes with
+    Jacobi, 11 without (u = r).  Chronopoulos & Gear (Algorithm 4): p, s, x,
+    r, u (reads u, p, w, s, x, r, writes p, s, x, r, u) and w = A u (gathers
+    u, reads r, writes w): 14, or 11 without.  p-CG (Algorithm 6): one
+    kernel reading m (gathered), w, z, q, s, u, p, x, r and writing z, q, s,
+    p, x, r, u, w and the next m: 18; without a preconditioner q = s, u = r,
+    m = w: 12.  One SpMV per iteration in each.
+    """
+    vec = 8 * N
+    mat = 4 * (N + 1) + 12 * nnz
+    passes = {"cg": (12, 11), "cgcg": (14, 11), "pipe_cg": (18, 12)}[variant][0 if jacobi else 1]
+    return passes * vec + mat
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -126,8 +145,8 @@ def main():
     dev = torch.device("cuda", 0)
     w = inputs.workload("c2", n=args.n)
     N = w.N
-    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "precision", "batched",
-                                                         "sweep", "paper", "configs"}
+    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "cg", "precision",
+                                                         "batched", "sweep", "paper", "configs"}
 
     # ---- inputs resident in HBM -------------------------------------------------
     rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
@@ -184,6 +203,40 @@ def main():
             if op is None:
                 continue
             res[leg] = timed_leg(op, variant, precond)
+
+    # ---- the CG family (Section 2) on the symmetric counterpart of the operator --
+    cgfam = None
+    if "cg" in legs:
+        cgfam = {"workload": "3-D 7-point Poisson (beta = 0), CSR FP64, Jacobi, tol 1e-8; one step = one full "
+                             "solve; at the benchmark grid and at 32^3 (latency-bound)"}
+        for side in (args.n, 32):
+            ws = inputs.workload("c2s", n=side)
+            rps, cols, vals = solver.assemble_convdiff(ws.dim, ws.n, ws.npts, ws.beta)
+            As = solver.csr(rps, cols, vals)
+            bs = solver.spmv(As, torch.from_numpy(inputs.x_true(ws.N)).to(dev))
+            xs = torch.empty_like(bs)
+            torch.cuda.synchronize()
+            entry = {}
+            for variant in ("cg", "cgcg", "pipe_cg"):
+                kw = dict(variant=variant, precond="jacobi", tol=ws.tol, maxit=ws.maxit, out=xs)
+                for _ in range(args.warmup):
+                    solver.solve(As, bs, **kw)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                its = 0
+                for _ in range(args.steps):
+                    _, cinfo = solver.solve(As, bs, **kw)
+                    its += cinfo.iters
+                torch.cuda.synchronize()
+                cdt = time.perf_counter() - t0
+                rate = its / cdt
+                entry[variant] = {"iters_per_s": round(rate, 2), "iters_per_solve": cinfo.iters,
+                                  "ms_per_solve": round(cdt / args.steps * 1e3, 3),
+                                  "gbps_effective": round(algorithmic_bytes_cg(ws.N, vals.numel(), variant, True)
+                                                          * rate / 1e9, 1),
+                                  "syncs_per_iter": cinfo.syncs_per_iter, "relres_true": cinfo.relres_true}
+            cgfam[f"{side}^3"] = entry
+            del As, bs, xs, rps, cols, vals
 
     # ---- roofline of the dominant kernel: one solve with per-kernel events -------
     _, pinfo = solver.solve(A, b, variant="pbicgstab_rr", precond="jacobi_folded", out=xbuf, time_kernels=True,
@@ -466,6 +519,8 @@ def main():
     for key, variant in (("st_pipe", "pbicgstab"), ("st_bicg", "bicgstab")):
         if key in res:
             out.setdefault("stencil", {})[variant] = leg_summary(key, variant, True, True)
+    if cgfam is not None:
+        out["cg_family"] = cgfam
     if precision is not None:
         out["precision_form"] = precision
     if batched is not None:

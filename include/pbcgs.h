@@ -17,7 +17,18 @@
  *                        (Section 3.1): two reduction phases like p-BiCGStab
  *                        but no overlap, so four kernel boundaries per
  *                        iteration.  No preconditioner, or Jacobi as
- *                        PBCGS_PRECOND_JACOBI_FOLDED; binary64; not batched.
+ *                        PBCGS_PRECOND_JACOBI_FOLDED; binary64; not batched;
+ *   PBCGS_CG             preconditioned CG, Algorithm 2 (Section 2), three
+ *                        kernel boundaries per iteration;
+ *   PBCGS_CGCG           Chronopoulos & Gear CG, Algorithm 4 (Section 2): one
+ *                        reduction phase, two kernel boundaries;
+ *   PBCGS_PIPE_CG        pipelined CG, Algorithm 6 (Section 2): its reduction
+ *                        and its SpMV both use only the previous iteration's
+ *                        vectors, so one kernel boundary per iteration.
+ *                        The CG family needs a symmetric positive definite A
+ *                        (not checked) and takes Jacobi as PBCGS_PRECOND_JACOBI
+ *                        (M^{-1} applied as the algorithms write it; the folded
+ *                        form A M^{-1} is not symmetric); binary64; not batched.
  *
  * Right preconditioning solves A M^{-1} y = b, M x = y (Section 3.6).  The only
  * preconditioner is Jacobi, M = diag(A).  The stopping test is
@@ -63,7 +74,15 @@ typedef enum {
     PBCGS_ERR_UNSUPPORTED = -4    /* valid request this build does not implement           */
 } pbcgs_status;
 
-enum { PBCGS_BICGSTAB = 0, PBCGS_PBICGSTAB = 1, PBCGS_PBICGSTAB_RR = 2, PBCGS_CA_BICGSTAB = 3 };
+enum {
+    PBCGS_BICGSTAB = 0,
+    PBCGS_PBICGSTAB = 1,
+    PBCGS_PBICGSTAB_RR = 2,
+    PBCGS_CA_BICGSTAB = 3,
+    PBCGS_CG = 4,
+    PBCGS_CGCG = 5,
+    PBCGS_PIPE_CG = 6
+};
 /* Preconditioners.  JACOBI applies M^{-1} = diag(dinv) inside Algorithm 10 / 11
  * (the hatted vectors of Section 3.6).  JACOBI_FOLDED is the same right
  * preconditioning with the operator formed: the unpreconditioned Algorithm 7 / 9
@@ -87,8 +106,8 @@ enum { PBCGS_FP64 = 0, PBCGS_FP32_RR64 = 1 };
 
 /* Solver options (host struct). */
 typedef struct {
-    int32_t variant;     /* PBCGS_BICGSTAB, PBCGS_PBICGSTAB, PBCGS_PBICGSTAB_RR or
-                            PBCGS_CA_BICGSTAB                                              */
+    int32_t variant;     /* PBCGS_BICGSTAB, PBCGS_PBICGSTAB, PBCGS_PBICGSTAB_RR,
+                            PBCGS_CA_BICGSTAB, PBCGS_CG, PBCGS_CGCG or PBCGS_PIPE_CG       */
     int32_t precond;     /* PBCGS_PRECOND_NONE, _JACOBI or _JACOBI_FOLDED                  */
     int32_t precision;   /* PBCGS_FP64 or PBCGS_FP32_RR64                                   */
     int32_t maxit;       /* iteration budget, >= 0                                          */
@@ -109,7 +128,7 @@ typedef struct {
     int32_t iters;           /* completed x-updates                                       */
     int32_t n_rr;            /* residual replacements performed                           */
     int32_t status;          /* pbcgs_status of the numerical outcome                     */
-    int32_t syncs_per_iter;  /* kernel boundaries of one regular iteration (5, 4 or 2)    */
+    int32_t syncs_per_iter;  /* kernel boundaries of one regular iteration (1 to 5)       */
     double relres_rec;       /* last ||r_i|| / ||r_0|| of the recurrence                  */
     double relres_true;      /* ||b - A x|| / ||r_0|| of the returned x                   */
     double ms;               /* wall time of the iteration loop (HIP events), ms           */

@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pbcgs.h")
 SUCCESS, MAXIT, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 ERR_INVALID_ARG, ERR_ALLOC, ERR_HIP, ERR_UNSUPPORTED = -1, -2, -3, -4
 
-BICGSTAB, PBICGSTAB, PBICGSTAB_RR, CA_BICGSTAB = 0, 1, 2, 3
+BICGSTAB, PBICGSTAB, PBICGSTAB_RR, CA_BICGSTAB, CG, CGCG, PIPE_CG = 0, 1, 2, 3, 4, 5, 6
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_JACOBI_FOLDED = 0, 1, 2
 FP64, FP32_RR64 = 0, 1
 

@@ -875,6 +875,311 @@ template <class Op>
 __global__ __launch_bounds__(kWG) void k_ca_w(Op op, Args a) { d_ca_w<Op>(op, a); }
 
 // ===========================================================================
+// CG family (Section 2), for symmetric positive definite A with Jacobi
+// M = diag(A) or none.  u = M^{-1} r lives in the r^ slot (aliasing r without a
+// preconditioner).  Reductions of the two one-phase forms carry, in order,
+// gamma = (r, u), delta = (w, u), nu = (r, r).
+//   Algorithm 2 (CG): s = A p | alpha ; x, r, u | stop, beta ; p  -- three kernels.
+//   Algorithm 4 (Chronopoulos & Gear): alpha, beta ; p, s, x, r, u | w = A u  -- two.
+//   Algorithm 6 (p-CG): alpha, beta ; n = A M^{-1} w and every recurrence -- one.
+// ===========================================================================
+
+// First reduction of Algorithms 4 and 6: rho0 = sqrt(nu_0), alpha_0 = gamma_0 / delta_0, beta_0 = 0.
+__device__ __forceinline__ void fin_cgs_first(State& s, double* hist, const double (&d)[3]) {
+  const double gamma = d[0], delta = d[1], nu = d[2];
+  s.relres = 1.0;
+  if (hist && leader()) hist[0] = 1.0;
+  if (!finite(gamma) || !finite(delta) || !finite(nu)) { s.status = DS_NONFINITE; return; }
+  const double rho0 = sqrt(nu);
+  s.rho0 = rho0;
+  if (rho0 == 0.0) { s.status = DS_SUCCESS; s.relres = 0.0; return; }
+  if (delta == 0.0) { s.status = DS_BREAKDOWN; return; }
+  const double alpha = gamma / delta;
+  if (!finite(alpha)) { s.status = DS_NONFINITE; return; }
+  s.alpha = alpha;
+  s.beta = 0.0;
+  s.gamma = gamma;
+}
+
+// Later reductions of Algorithms 4 and 6: stopping test on ||r_i|| (i = s.iters),
+// beta_i = gamma_i / gamma_{i-1}, alpha_i = (delta / gamma_i - beta_i / alpha_{i-1})^{-1}.
+__device__ __forceinline__ void fin_cgs_next(State& s, double* hist, const double (&d)[3]) {
+  const double g1 = d[0], delta = d[1], nu = d[2];
+  if (!finite(g1) || !finite(delta) || !finite(nu)) { s.status = DS_NONFINITE; return; }
+  const double relres = sqrt(nu) / s.rho0;
+  s.relres = relres;
+  if (hist && leader()) hist[s.iters] = relres;
+  if (relres <= s.tol) { s.status = DS_SUCCESS; return; }
+  if (s.gamma == 0.0 || g1 == 0.0 || s.alpha == 0.0) { s.status = DS_BREAKDOWN; return; }
+  const double beta = g1 / s.gamma;
+  if (!finite(beta)) { s.status = DS_NONFINITE; return; }
+  const double den = delta / g1 - beta / s.alpha;
+  if (den == 0.0) { s.status = DS_BREAKDOWN; return; }
+  const double alpha = 1.0 / den;
+  if (!finite(alpha)) { s.status = DS_NONFINITE; return; }
+  s.beta = beta;
+  s.alpha = alpha;
+  s.gamma = g1;
+}
+
+// Setup of Algorithm 2: r = b - A x ; u = M^{-1} r ; p = u ; partials (r, r), (r, u).
+// ONEPHASE (Algorithms 4 and 6): no p; p = s = z = q = 0 instead.
+template <class Op, int PC, bool ONEPHASE>
+__device__ __forceinline__ void d_cg_setup(Op op, Args a) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  produce<2>(a, [&](int32_t row, bool valid, double (&d)[2]) {
+    const double ax = op.spmv(row, valid, a.x);
+    if (!valid) return;
+    const double r = a.b[row] - ax;
+    a.r[row] = r;
+    const double u = (PC != PC_NONE) ? apply_pc<PC>(a, row, r) : r;
+    if (PC != PC_NONE) a.rh[row] = u;
+    if (ONEPHASE) {
+      a.p[row] = 0.0;
+      a.s[row] = 0.0;
+      a.z[row] = 0.0;
+      if (PC != PC_NONE) a.sh[row] = 0.0;
+    } else {
+      a.p[row] = u;
+    }
+    d[0] = r * r;
+    d[1] = r * u;
+  });
+}
+template <class Op, int PC, bool ONEPHASE>
+__global__ __launch_bounds__(kWG) void k_cg_setup(Op op, Args a) { d_cg_setup<Op, PC, ONEPHASE>(op, a); }
+
+// Setup of Algorithms 4 and 6, continued: w = A u ; with PIPE (Algorithm 6)
+// and a preconditioner also m = M^{-1} w into w^ ; partials (r, u), (w, u),
+// (r, r).
+template <class Op, int PC, bool PIPE>
+__device__ __forceinline__ void d_cg_setup_w(Op op, Args a) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  produce<3>(a, [&](int32_t row, bool valid, double (&d)[3]) {
+    const double w = op.spmv(row, valid, a.rh);
+    if (!valid) return;
+    a.w[row] = w;
+    if (PIPE && PC != PC_NONE) a.wh[row] = apply_pc<PC>(a, row, w);
+    const double r = a.r[row], u = a.rh[row];
+    d[0] = r * u;
+    d[1] = w * u;
+    d[2] = r * r;
+  });
+}
+template <class Op, int PC, bool PIPE>
+__global__ __launch_bounds__(kWG) void k_cg_setup_w(Op op, Args a) { d_cg_setup_w<Op, PC, PIPE>(op, a); }
+
+// Algorithm 2, kernel 1: (first iteration: rho0, gamma_0 from the setup) ;
+// s = A p ; partials of (s, p).
+template <class Op>
+__device__ __forceinline__ void d_cg_a(Op op, Args a) {
+  PBCGS_PROLOGUE(st)
+  if (a.first) {
+    double g[2];
+    gather_sums<2>(a, g);
+    st.relres = 1.0;
+    if (a.hist && leader()) a.hist[0] = 1.0;
+    const double rho0 = sqrt(g[0]);
+    st.rho0 = rho0;
+    st.gamma = g[1];
+    if (!finite(rho0) || !finite(g[1])) st.status = DS_NONFINITE;
+    else if (rho0 == 0.0) { st.status = DS_SUCCESS; st.relres = 0.0; }
+  }
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  produce<1>(a, [&](int32_t row, bool valid, double (&d)[1]) {
+    const double s = op.spmv(row, valid, a.p);
+    if (!valid) return;
+    a.s[row] = s;
+    d[0] = s * a.p[row];
+  });
+}
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_cg_a(Op op, Args a) { d_cg_a<Op>(op, a); }
+
+// Algorithm 2, kernel 2: alpha = gamma / (s, p) ; x += alpha p ; r -= alpha s ;
+// u = M^{-1} r ; partials (r, u), (r, r).
+template <int PC>
+__device__ __forceinline__ void d_cg_b(Args a) {
+  PBCGS_PROLOGUE(st)
+  double g[1];
+  gather_sums<1>(a, g);
+  const double delta = g[0];
+  if (!finite(delta)) st.status = DS_NONFINITE;
+  else if (delta == 0.0) st.status = DS_BREAKDOWN;
+  else {
+    const double alpha = st.gamma / delta;
+    if (!finite(alpha)) st.status = DS_NONFINITE;
+    else st.alpha = alpha;
+  }
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double alpha = st.alpha;
+  produce<2>(a, [&](int32_t row, bool valid, double (&d)[2]) {
+    if (!valid) return;
+    const double p = a.p[row];
+    a.x[row] = a.x[row] + alpha * p;
+    const double r = a.r[row] - alpha * a.s[row];
+    a.r[row] = r;
+    const double u = (PC != PC_NONE) ? apply_pc<PC>(a, row, r) : r;
+    if (PC != PC_NONE) a.rh[row] = u;
+    d[0] = r * u;
+    d[1] = r * r;
+  });
+}
+template <int PC>
+__global__ __launch_bounds__(kWG) void k_cg_b(Args a) { d_cg_b<PC>(a); }
+
+// Algorithm 2, kernel 3: stopping test, beta = (r', u') / (r, u) ; p = u + beta p.
+__device__ __forceinline__ void fin_cg_beta(State& s, double* hist, const double (&d)[2]) {
+  const double g1 = d[0], nu = d[1];
+  s.iters += 1;
+  if (!finite(g1) || !finite(nu)) { s.status = DS_NONFINITE; return; }
+  const double relres = sqrt(nu) / s.rho0;
+  s.relres = relres;
+  if (hist && leader()) hist[s.iters] = relres;
+  if (relres <= s.tol) { s.status = DS_SUCCESS; return; }
+  if (s.gamma == 0.0) { s.status = DS_BREAKDOWN; return; }
+  const double beta = g1 / s.gamma;
+  if (!finite(beta)) { s.status = DS_NONFINITE; return; }
+  s.beta = beta;
+  s.gamma = g1;
+}
+
+template <int PC>
+__device__ __forceinline__ void d_cg_c(Args a) {
+  PBCGS_PROLOGUE(st)
+  double g[2];
+  gather_sums<2>(a, g);
+  fin_cg_beta(st, a.hist, g);
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double beta = st.beta;
+  each_row(a, [&](int32_t row, bool valid) {
+    if (!valid) return;
+    a.p[row] = a.rh[row] + beta * a.p[row];
+  });
+}
+template <int PC>
+__global__ __launch_bounds__(kWG) void k_cg_c(Args a) { d_cg_c<PC>(a); }
+
+// Algorithm 4, kernel 1: finish the reduction (alpha_0 in the first
+// iteration, else stop test, beta, alpha) ; p = u + beta p ; s = w + beta s ;
+// x += alpha p ; r -= alpha s ; u = M^{-1} r.
+template <int PC>
+__device__ __forceinline__ void d_cc_a(Args a) {
+  PBCGS_PROLOGUE(st)
+  double g[3];
+  gather_sums<3>(a, g);
+  if (a.first) fin_cgs_first(st, a.hist, g);
+  else fin_cgs_next(st, a.hist, g);
+  if (st.status == DS_RUNNING) st.iters += 1;  // the x update below
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double alpha = st.alpha, beta = st.beta;
+  each_row(a, [&](int32_t row, bool valid) {
+    if (!valid) return;
+    const double p = a.rh[row] + beta * a.p[row];
+    const double s = a.w[row] + beta * a.s[row];
+    a.p[row] = p;
+    a.s[row] = s;
+    a.x[row] = a.x[row] + alpha * p;
+    const double r = a.r[row] - alpha * s;
+    a.r[row] = r;
+    if (PC != PC_NONE) a.rh[row] = apply_pc<PC>(a, row, r);
+  });
+}
+template <int PC>
+__global__ __launch_bounds__(kWG) void k_cc_a(Args a) { d_cc_a<PC>(a); }
+
+// Algorithm 6, the whole iteration: finish the reduction (alpha_0, or stop
+// test, beta_i, alpha_i) ; n = A m with m = M^{-1} w (gathered from w^, which
+// the previous launch finished) ; z, q, s, p, x, r, u, w by their recurrences ;
+// m' = M^{-1} w' into the other buffer t (without a preconditioner m = w, so
+// w itself alternates between w^ and t) ; partials (r, u), (w, u), (r, r).
+template <class Op, int PC>
+__device__ __forceinline__ void d_pcg(Op op, Args a) {
+  PBCGS_PROLOGUE(st)
+  double g[3];
+  gather_sums<3>(a, g);
+  if (a.first) fin_cgs_first(st, a.hist, g);
+  else fin_cgs_next(st, a.hist, g);
+  if (st.status == DS_RUNNING) st.iters += 1;  // the x update below
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double alpha = st.alpha, beta = st.beta;
+  produce<3>(a, [&](int32_t row, bool valid, double (&d)[3]) {
+    const double nv = op.spmv(row, valid, a.wh);
+    if (!valid) return;
+    const double m = a.wh[row];
+    const double w = (PC != PC_NONE) ? a.w[row] : m;
+    const double z = nv + beta * a.z[row];
+    const double sv = w + beta * a.s[row];
+    a.z[row] = z;
+    a.s[row] = sv;
+    double p, r, u, wn;
+    if (PC != PC_NONE) {
+      const double q = m + beta * a.sh[row];
+      a.sh[row] = q;
+      p = a.rh[row] + beta * a.p[row];
+      a.x[row] = a.x[row] + alpha * p;
+      r = a.r[row] - alpha * sv;
+      u = a.rh[row] - alpha * q;
+      wn = w - alpha * z;
+      a.rh[row] = u;
+      a.w[row] = wn;
+      a.t[row] = apply_pc<PC>(a, row, wn);
+    } else {
+      p = a.r[row] + beta * a.p[row];
+      a.x[row] = a.x[row] + alpha * p;
+      r = a.r[row] - alpha * sv;
+      u = r;
+      wn = w - alpha * z;
+      a.t[row] = wn;
+    }
+    a.p[row] = p;
+    a.r[row] = r;
+    d[0] = r * u;
+    d[1] = wn * u;
+    d[2] = r * r;
+  });
+}
+template <class Op, int PC>
+__global__ __launch_bounds__(kWG) void k_pcg(Op op, Args a) { d_pcg<Op, PC>(op, a); }
+
+// Final reduction of the CG family.  MODE 0: Algorithm 2's setup (rho0,
+// gamma_0); 1: first reduction of Algorithms 4 and 6; 2: a later one.
+template <int MODE>
+__device__ __forceinline__ void d_cg_finish(Args a) {
+  State st = load_state(a.sin);
+  if (st.status != DS_RUNNING) {
+    publish(a, st);
+    return;
+  }
+  if (MODE == 0) {
+    double g[2];
+    gather_sums<2>(a, g);
+    st.relres = 1.0;
+    if (a.hist && leader()) a.hist[0] = 1.0;
+    const double rho0 = sqrt(g[0]);
+    st.rho0 = rho0;
+    st.gamma = g[1];
+    if (!finite(rho0) || !finite(g[1])) st.status = DS_NONFINITE;
+    else if (rho0 == 0.0) { st.status = DS_SUCCESS; st.relres = 0.0; }
+  } else {
+    double g[3];
+    gather_sums<3>(a, g);
+    if (MODE == 1) fin_cgs_first(st, a.hist, g);
+    else fin_cgs_next(st, a.hist, g);
+  }
+  publish(a, st);
+}
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_cg_finish(Args a) { d_cg_finish<MODE>(a); }
+
+// ===========================================================================
 // BiCGStab kernels (Algorithm 7, PC == PC_NONE; Algorithm 10 otherwise).
 // ===========================================================================
 

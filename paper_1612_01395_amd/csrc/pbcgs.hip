@@ -144,6 +144,21 @@ bool make_shape(int32_t n, Shape* sh, int prefer_R = 0) {
   return false;
 }
 
+// Kernel boundaries of one regular iteration of each variant.
+int32_t syncs_per_iteration(int32_t variant) {
+  switch (variant) {
+    case PBCGS_BICGSTAB: return 5;
+    case PBCGS_CA_BICGSTAB: return 4;
+    case PBCGS_CG: return 3;
+    case PBCGS_PIPE_CG: return 1;
+    default: return 2;  // p-BiCGStab, Chronopoulos & Gear CG
+  }
+}
+
+bool cg_family(int32_t variant) {
+  return variant == PBCGS_CG || variant == PBCGS_CGCG || variant == PBCGS_PIPE_CG;
+}
+
 // opts.flags bit 2 selects eq. (5) for alpha_{i+1}; eq. (3) otherwise.
 int32_t alpha_form(const pbcgs_opts& o) { return (o.flags & 4) ? 5 : 3; }
 
@@ -376,6 +391,14 @@ struct Driver {
       k_mp_setup_w0<Op64><<<grid(), kWG, 0, s>>>(op64, L(PB_SETUP1, PB_SETUP2));
     } else if (o.variant == PBCGS_BICGSTAB) {
       k_setup_r0<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
+    } else if (o.variant == PBCGS_CG) {
+      k_cg_setup<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
+    } else if (o.variant == PBCGS_CGCG) {
+      k_cg_setup<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
+      k_cg_setup_w<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP2));
+    } else if (o.variant == PBCGS_PIPE_CG) {
+      k_cg_setup<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
+      k_cg_setup_w<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP2));
     } else {
       k_setup_r0<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
       k_setup_w0<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_SETUP1, PB_SETUP2));
@@ -420,6 +443,25 @@ struct Driver {
         return;
       }
     }
+    if (o.variant == PBCGS_CG) {
+      timed(0, [&] { k_cg_a<Op><<<grid(), kWG, 0, s>>>(op, L(i == 0 ? PB_SETUP1 : -1, PB_A, i == 0)); });
+      timed(1, [&] { k_cg_b<PC><<<grid(), kWG, 0, s>>>(L(PB_A, PB_B)); });
+      k_cg_c<PC><<<grid(), kWG, 0, s>>>(L(PB_B, -1));
+      return;
+    }
+    if (o.variant == PBCGS_CGCG) {
+      timed(0, [&] { k_cc_a<PC><<<grid(), kWG, 0, s>>>(L(i == 0 ? PB_SETUP2 : PB_B, -1, i == 0)); });
+      timed(1, [&] { k_cg_setup_w<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(-1, PB_B)); });
+      return;
+    }
+    if (o.variant == PBCGS_PIPE_CG) {
+      // iteration i gathers m_i (w_i without a preconditioner) from one buffer
+      // and writes m_{i+1} to the other; the partial sums alternate likewise
+      Args b = L(pcg_part(i), pcg_part(i + 1), i == 0);
+      if (i & 1) std::swap(b.wh, b.t);
+      timed(0, [&] { k_pcg<Op, PC><<<grid(), kWG, 0, s>>>(op, b); });
+      return;
+    }
     if (o.variant == PBCGS_BICGSTAB) {
       timed(0, [&] { k_b1<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_SETUP1, PB_B1, i == 0)); });
       k_b2<PC><<<grid(), kWG, 0, s>>>(L(PB_B1, -1));
@@ -456,6 +498,10 @@ struct Driver {
       q += 4;
       return;
     }
+    if (o.variant == PBCGS_CG || o.variant == PBCGS_CGCG || o.variant == PBCGS_PIPE_CG) {
+      q += (o.variant == PBCGS_CG) ? 3 : (o.variant == PBCGS_CGCG) ? 2 : 1;
+      return;
+    }
     q += (pending_rr(i) ? 3 : 1) + (rr_due(o, i) ? 3 : 1);
   }
 
@@ -471,8 +517,21 @@ struct Driver {
     }
   }
 
+  // partial-sum buffer holding the reduction that p-CG's iteration i consumes
+  static int pcg_part(int64_t i) { return i == 0 ? PB_SETUP2 : ((i & 1) ? PB_A : PB_B); }
+
   void finish64(int64_t iters_launched) {
     hipStream_t s = ctx->stream;
+    if (o.variant == PBCGS_CG) {
+      if (iters_launched == 0) k_cg_finish<0><<<1, kWG, 0, s>>>(L(PB_SETUP1, -1));
+      return;
+    }
+    if (o.variant == PBCGS_CGCG || o.variant == PBCGS_PIPE_CG) {
+      const int pin = (o.variant == PBCGS_CGCG) ? (iters_launched == 0 ? PB_SETUP2 : PB_B) : pcg_part(iters_launched);
+      if (iters_launched == 0) k_cg_finish<1><<<1, kWG, 0, s>>>(L(pin, -1));
+      else k_cg_finish<2><<<1, kWG, 0, s>>>(L(pin, -1));
+      return;
+    }
     if (o.variant == PBCGS_BICGSTAB) {
       if (iters_launched == 0) k_finish<2><<<1, kWG, 0, s>>>(L(PB_SETUP1, -1));
       return;
@@ -487,8 +546,8 @@ struct Driver {
     k.append(reinterpret_cast<const char*>(&a), sizeof(Args));
     k.append(reinterpret_cast<const char*>(&op), sizeof(Op));
     k.append(reinterpret_cast<const char*>(&op64), sizeof(Op64));
-    std::snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%lld|%d|", PC, MP ? 1 : 0, o.variant, m, (long long)(q & 1),
-                  i0 == 0 ? 1 : 0);
+    std::snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%lld|%d|%d|", PC, MP ? 1 : 0, o.variant, m, (long long)(q & 1),
+                  i0 == 0 ? 1 : 0, (int)(i0 & 1));
     k += buf;
     for (int j = 0; j < m; ++j) {
       const int64_t i = i0 + j;
@@ -540,7 +599,7 @@ struct Driver {
   bool use_persistent() {
     if constexpr (MP) return false;
     if (o.flags & 2) return false;
-    if (o.variant == PBCGS_CA_BICGSTAB) return false;
+    if (o.variant >= PBCGS_CA_BICGSTAB) return false;
     if (o.maxit > 200000) return false;
     if (env_int("PBCGS_PERSIST", 0) != 1) return false;
     if (ctx->coop < 0) {
@@ -697,7 +756,7 @@ struct Driver {
     info->iters = fin.iters;
     info->n_rr = fin.n_rr;
     info->status = map_status(fin.status);
-    info->syncs_per_iter = (o.variant == PBCGS_BICGSTAB) ? 5 : (o.variant == PBCGS_CA_BICGSTAB) ? 4 : 2;
+    info->syncs_per_iter = syncs_per_iteration(o.variant);
     info->relres_rec = fin.relres;
     info->ms = ms;
     for (int k = 0; k < 2; ++k) {
@@ -1193,11 +1252,13 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
   if (!ctx || !A || !b || !x || !opts || !info) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
   if (A->ctx != ctx) return fail(ctx, PBCGS_ERR_INVALID_ARG, "operator belongs to another context");
   const pbcgs_opts& o = *opts;
-  if (o.variant < PBCGS_BICGSTAB || o.variant > PBCGS_CA_BICGSTAB)
+  if (o.variant < PBCGS_BICGSTAB || o.variant > PBCGS_PIPE_CG)
     return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown variant");
   if (o.precond != PBCGS_PRECOND_NONE && o.precond != PBCGS_PRECOND_JACOBI &&
       o.precond != PBCGS_PRECOND_JACOBI_FOLDED)
     return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown preconditioner");
+  if (cg_family(o.variant) && o.precond == PBCGS_PRECOND_JACOBI_FOLDED)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the CG family needs a symmetric operator: use PBCGS_PRECOND_JACOBI");
   if (o.variant == PBCGS_CA_BICGSTAB && o.precond == PBCGS_PRECOND_JACOBI)
     return fail(ctx, PBCGS_ERR_UNSUPPORTED, "CA-BiCGStab takes Jacobi as PBCGS_PRECOND_JACOBI_FOLDED");
   const bool folded = (o.precond == PBCGS_PRECOND_JACOBI_FOLDED);
@@ -1261,7 +1322,15 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
   if (folded && pc == PC_VEC && A->kind != OP_CSR)
     return fail(ctx, PBCGS_ERR_UNSUPPORTED, "folded Jacobi on a stencil needs a constant diagonal");
   const bool hat = (pc != PC_NONE) && !folded;
-  if (o.variant == PBCGS_BICGSTAB) {
+  if (cg_family(o.variant)) {
+    // r, p, s, w, z; u = M^{-1} r in r^ and q in s^ (aliases without a preconditioner)
+    a.r = v[1]; a.p = v[2]; a.s = v[3]; a.w = v[4]; a.z = v[5];
+    a.rh = hat ? v[8] : a.r;
+    a.sh = hat ? v[10] : a.s;
+    // p-CG's alternating gather buffers: m (with Jacobi) or w itself (without)
+    a.wh = hat ? v[6] : a.w;
+    a.t = v[7];
+  } else if (o.variant == PBCGS_BICGSTAB) {
     a.r0 = v[0]; a.r = v[1]; a.p = v[2]; a.s = v[3]; a.q = v[4]; a.y = v[5];
     a.ph = hat ? v[6] : a.p;
     a.qh = hat ? v[7] : a.q;
@@ -1472,9 +1541,9 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
   if (!ctx || !A || !b || !x || !opts || !infos) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
   if (nsys <= 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "nsys must be positive");
   const pbcgs_opts& o = *opts;
-  if (o.variant < PBCGS_BICGSTAB || o.variant > PBCGS_CA_BICGSTAB)
+  if (o.variant < PBCGS_BICGSTAB || o.variant > PBCGS_PIPE_CG)
     return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown variant");
-  if (o.variant == PBCGS_CA_BICGSTAB)
+  if (o.variant >= PBCGS_CA_BICGSTAB)
     return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves run BiCGStab or p-BiCGStab");
   if (o.precond != PBCGS_PRECOND_NONE)
     return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves take no preconditioner");

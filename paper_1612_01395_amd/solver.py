@@ -17,7 +17,7 @@ import torch
 from . import _lib as L
 
 VARIANTS = {"bicgstab": L.BICGSTAB, "pbicgstab": L.PBICGSTAB, "pbicgstab_rr": L.PBICGSTAB_RR,
-            "ca_bicgstab": L.CA_BICGSTAB}
+            "ca_bicgstab": L.CA_BICGSTAB, "cg": L.CG, "cgcg": L.CGCG, "pipe_cg": L.PIPE_CG}
 STATUS = {0: "success", 1: "maxit", 2: "breakdown", 3: "nonfinite"}
 # "jacobi": M^{-1} = diag(1/a_ii) applied inside Algorithm 10 / 11; "jacobi_folded":
 # the same right preconditioning with A M^{-1} formed, Algorithm 7 / 9 run on it.
