@@ -4,6 +4,9 @@ benchmark uses.
 * 3-D 7-point 128^3 (2,097,152 unknowns): device assembly, b = A x_true and
   complete p-BiCGStab+RR / BiCGStab / p-BiCGStab solves (Jacobi, tol 1e-8)
   against the oracle, bit for bit; the matrix-free stencil gives the same x.
+* the same grid for CA-BiCGStab and the eq. (5) alpha (folded Jacobi), and its
+  symmetric counterpart (Poisson) for CG, Chronopoulos & Gear CG and p-CG
+  (Jacobi), each complete solve against the oracle bit for bit.
 * 3-D 27-point variable-coefficient 256^3 (16,777,216 unknowns, 449,455,096
   non-zeros): assembled rows sampled across the grid against the oracle's
   row-by-row assembly, then the whole matrix, the first iterations and the
@@ -74,6 +77,52 @@ def test_c2_full_solve_bitwise(c2, variant, precond):
     assert same(host(info.history), i_or["history"])
     # the benchmark spec's bound, met trivially by bitwise equality
     assert np.linalg.norm(host(x) - x_or) <= 1e-8 * np.linalg.norm(x_or)
+
+
+@pytest.mark.parametrize("variant,alpha_form", [("ca_bicgstab", 3), ("pbicgstab_rr", 5)])
+def test_c2_other_algorithms_bitwise(c2, variant, alpha_form):
+    """CA-BiCGStab (Algorithm 8) and the eq. (5) alpha at the benchmark's size
+    and launch configuration (folded Jacobi)."""
+    w, A, _, op, b, b_or = c2
+    algo = oracle.ALG_CA_BICGSTAB if variant == "ca_bicgstab" else ALG[variant]
+    t0 = time.time()
+    x_or, i_or = oracle.solve_folded(A, b_or, algo=algo, dinv=oracle.jacobi_dinv(A), tol=w.tol, maxit=w.maxit,
+                                     rr_period=w.rr_period, history=True, alpha_form=alpha_form)
+    say(f"c2 {variant} eq.({alpha_form}): oracle {i_or['iters']} it in {time.time() - t0:.1f}s")
+    x, info = solver.solve(op, b, variant=variant, precond="jacobi_folded", tol=w.tol, maxit=w.maxit,
+                           rr_period=w.rr_period, history=True, alpha_form=alpha_form)
+    assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"])
+    assert info.status == 0
+    assert same(host(x), x_or)
+    assert same(host(info.history), i_or["history"])
+
+
+@pytest.fixture(scope="module")
+def c2s():
+    require_gpu()
+    w = inputs.workload("c2s")
+    A = oracle.assemble_workload(w)
+    rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
+    assert np.array_equal(host(rp), A.row_ptr) and same(host(val), A.val)
+    xt = inputs.x_true(A.n)
+    return w, A, solver.csr(rp, col, val), solver.spmv(solver.csr(rp, col, val), dev_t(xt)), oracle.spmv(A, xt)
+
+
+@pytest.mark.parametrize("variant,algo", [("cg", oracle.ALG_CG), ("cgcg", oracle.ALG_CGCG),
+                                          ("pipe_cg", oracle.ALG_PIPE_CG)])
+def test_c2s_cg_family_full_solve_bitwise(c2s, variant, algo):
+    """The CG family on the 128^3 Poisson operator with Jacobi, as the benchmark runs it."""
+    w, A, op, b, b_or = c2s
+    assert same(host(b), b_or)
+    t0 = time.time()
+    x_or, i_or = oracle.solve(A, b_or, algo=algo, dinv=oracle.jacobi_dinv(A), tol=w.tol, maxit=w.maxit,
+                              history=True)
+    say(f"c2s {variant}: oracle {i_or['iters']} it in {time.time() - t0:.1f}s")
+    x, info = solver.solve(op, b, variant=variant, precond="jacobi", tol=w.tol, maxit=w.maxit, history=True)
+    assert (info.status, info.iters) == (i_or["status"], i_or["iters"]) and info.status == 0
+    assert same(host(x), x_or)
+    assert same([info.relres_rec, info.relres_true], [i_or["relres_rec"], i_or["relres_true"]])
+    assert same(host(info.history), i_or["history"])
 
 
 def test_c2_stencil_equals_csr(c2):
