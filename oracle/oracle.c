@@ -909,11 +909,7 @@ static int pipe_cg(const csr_t* A, const double* dinv, const double* b, double* 
             if (o->history) o->history[i] = info->relres_rec;
             if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
         }
-        if (i == o->maxit) { info->status = OR_MAXIT; goto done; }
-        /* m_i := M^{-1} w_i ; n_i := A m_i   (overlapping the reduction) */
-        if (pc) { PAR for (int32_t j = 0; j < n; ++j) m[j] = dinv[j] * w[j]; g_ctr.pc++; }
-        spmv(A, m, nv);
-        /* end reduction: beta_i, alpha_i */
+        /* end reduction: beta_i, alpha_i (taken, like Alg. 4's, before the iteration budget is checked) */
         if (i == 0) {
             if (delta == 0.0) { info->status = OR_BREAKDOWN; goto done; }
             beta = 0.0;
@@ -924,7 +920,12 @@ static int pipe_cg(const csr_t* A, const double* dinv, const double* b, double* 
             if (st != OR_SUCCESS) { info->status = st; goto done; }
         }
         gamma = gamma1;
+        if (i == o->maxit) { info->status = OR_MAXIT; goto done; }
         if (o->scalars) { o->scalars[3 * i] = alpha; o->scalars[3 * i + 2] = beta; }
+        /* m_i := M^{-1} w_i ; n_i := A m_i   (in the paper overlapping the reduction; here after it,
+           which changes no value) */
+        if (pc) { PAR for (int32_t j = 0; j < n; ++j) m[j] = dinv[j] * w[j]; g_ctr.pc++; }
+        spmv(A, m, nv);
         /* z_i := n_i + beta_i z_{i-1} ; q_i := m_i + beta_i q_{i-1} ; s_i := w_i + beta_i s_{i-1} ;
            p_i := u_i + beta_i p_{i-1} */
         PAR for (int32_t j = 0; j < n; ++j) z[j] = nv[j] + beta * z[j];
