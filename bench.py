@@ -69,7 +69,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     p.add_argument("--only", default="",
-                   help="comma list of legs to run: pipe,bicg,explicit,stencil,cg,precision,batched,sweep,paper,configs")
+                   help="comma list of legs to run: pipe,bicg,explicit,stencil,fixed,cg,precision,batched,sweep,paper,"
+                        "configs")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
     return p.parse_args()
@@ -145,8 +146,8 @@ def main():
     dev = torch.device("cuda", 0)
     w = inputs.workload("c2", n=args.n)
     N = w.N
-    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "cg", "precision",
-                                                         "batched", "sweep", "paper", "configs"}
+    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "fixed", "cg",
+                                                         "precision", "batched", "sweep", "paper", "configs"}
 
     # ---- inputs resident in HBM -------------------------------------------------
     rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
@@ -203,6 +204,25 @@ def main():
             if op is None:
                 continue
             res[leg] = timed_leg(op, variant, precond)
+
+    # ---- fixed-iteration mode: tol = 0, 200 iterations, device-timed -----------
+    fixed = None
+    if "fixed" in legs:
+        fixed = {"mode": "tol = 0, maxit = 200, HIP events from the setup to the last kernel (no true-residual "
+                         "check), median of 5 after one warm-up; the 128^3 system, folded Jacobi"}
+        for key, op_, variant in (("pbicgstab_rr_csr", A, "pbicgstab_rr"), ("bicgstab_csr", A, "bicgstab"),
+                                  ("ca_bicgstab_csr", A, "ca_bicgstab"), ("pbicgstab_rr_stencil", S, "pbicgstab_rr"),
+                                  ("bicgstab_stencil", S, "bicgstab")):
+            if op_ is None:
+                continue
+            kw = dict(variant=variant, precond="jacobi_folded", tol=0.0, maxit=200, rr_period=w.rr_period, out=xbuf)
+            solver.solve(op_, b, **kw)
+            times = []
+            for _ in range(5):
+                _, finfo = solver.solve(op_, b, **kw)
+                times.append(finfo.ms)
+            med = sorted(times)[2]
+            fixed[key] = {"us_per_iter": round(med / finfo.iters * 1e3, 2), "iters": finfo.iters}
 
     # ---- the CG family (Section 2) on the symmetric counterpart of the operator --
     cgfam = None
@@ -519,6 +539,8 @@ def main():
     for key, variant in (("st_pipe", "pbicgstab"), ("st_bicg", "bicgstab")):
         if key in res:
             out.setdefault("stencil", {})[variant] = leg_summary(key, variant, True, True)
+    if fixed is not None:
+        out["fixed_iterations"] = fixed
     if cgfam is not None:
         out["cg_family"] = cgfam
     if precision is not None:
