@@ -223,6 +223,29 @@ def main():
                 times.append(finfo.ms)
             med = sorted(times)[2]
             fixed[key] = {"us_per_iter": round(med / finfo.iters * 1e3, 2), "iters": finfo.iters}
+        # latency-bound sizes: the marginal cost of an iteration (slope between
+        # 50 and 200 iterations) and the fixed cost of a solve (intercept)
+        for wname, side, pc in (("c1", 64, None), ("c2", 32, "jacobi_folded")):
+            ws = inputs.workload(wname, n=side)
+            rps, cols, vals = solver.assemble_convdiff(ws.dim, ws.n, ws.npts, ws.beta)
+            As = solver.csr(rps, cols, vals)
+            bs = solver.spmv(As, torch.from_numpy(inputs.x_true(ws.N)).to(dev))
+            xs = torch.empty_like(bs)
+            entry = {}
+            for variant in ("pbicgstab_rr", "bicgstab"):
+                med = {}
+                for m in (50, 200):
+                    kw = dict(variant=variant, precond=pc, tol=0.0, maxit=m, rr_period=ws.rr_period, out=xs)
+                    solver.solve(As, bs, **kw)
+                    times = sorted(solver.solve(As, bs, **kw)[1].ms for _ in range(9))
+                    med[m] = times[4] * 1e3
+                slope = (med[200] - med[50]) / 150.0
+                entry[variant] = {"marginal_us_per_iter": round(slope, 2),
+                                  "fixed_us_per_solve": round(med[50] - 50 * slope, 1)}
+            entry["ratio_marginal"] = round(entry["bicgstab"]["marginal_us_per_iter"]
+                                            / entry["pbicgstab_rr"]["marginal_us_per_iter"], 3)
+            fixed[f"{wname}_{side}"] = entry
+            del As, bs, xs, rps, cols, vals
 
     # ---- the CG family (Section 2) on the symmetric counterpart of the operator --
     cgfam = None
