@@ -76,3 +76,23 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_binding_constants_match_the_header():
+    """Every PBCGS_ enumerator the header defines has the value the Python
+    binding passes for it, and the binding's option maps cover them all."""
+    import re
+    from paper_1612_01395_amd import solver
+    text = open(_lib.HEADER).read()
+    enum = {m.group(1): int(m.group(2)) for m in re.finditer(r"\bPBCGS_([A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+    for name in ("SUCCESS", "MAXIT", "BREAKDOWN", "NONFINITE", "ERR_INVALID_ARG", "ERR_ALLOC", "ERR_HIP",
+                 "ERR_UNSUPPORTED", "BICGSTAB", "PBICGSTAB", "PBICGSTAB_RR", "CA_BICGSTAB", "CG", "CGCG",
+                 "PIPE_CG", "PRECOND_NONE", "PRECOND_JACOBI", "PRECOND_JACOBI_FOLDED", "FP64", "FP32_RR64"):
+        assert enum[name] == getattr(_lib, name), name
+    variants = {v for k, v in enum.items() if k in ("BICGSTAB", "PBICGSTAB", "PBICGSTAB_RR", "CA_BICGSTAB", "CG",
+                                                      "CGCG", "PIPE_CG")}
+    assert set(solver.VARIANTS.values()) == variants
+    assert set(solver.PRECISIONS.values()) == {enum["FP64"], enum["FP32_RR64"]}
+    # option flags documented in the header
+    assert "bit 0" in text and "bit 1" in text and "bit 2" in text
+    assert (_lib.FLAG_DIRECT, _lib.FLAG_TIME_KERNELS, _lib.FLAG_ALPHA_EQ5) == (1, 2, 4)
