@@ -264,7 +264,11 @@ int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts*
  * system of n rows gets the smallest R with at most that many workgroups)
  * and keeps the fastest on the context for later pbcgs_solve_batched calls
  * (PBCGS_BATCH_GCAP takes precedence).  Arguments as pbcgs_solve_batched,
- * without x (scratch of its own).
+ * without x (scratch of its own).  iters = 0 times complete solves at
+ * opts->tol and opts->maxit instead of `iters` iterations at tol 0 (then
+ * ms_per_iter holds the time of one whole batched solve): systems stop at
+ * different iterations, so the cap that is best for the whole solve can
+ * differ from the one that is best while every system still runs.
  */
 int pbcgs_tune_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const double* const* b,
                        const pbcgs_opts* opts, int32_t iters, pbcgs_tune_report* rep);

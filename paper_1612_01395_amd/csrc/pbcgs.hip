@@ -1661,7 +1661,12 @@ int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts*
 int pbcgs_tune_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const double* const* b,
                        const pbcgs_opts* opts, int32_t iters, pbcgs_tune_report* rep) {
   if (!ctx || !A || !b || !opts || !rep || nsys <= 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad argument");
-  if (iters < 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "iters must be positive");
+  if (iters < 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "iters must not be negative");
+  // iters = 0: time complete solves at the caller's tol and maxit.  Systems
+  // stop at different iterations, so the best cap for the whole solve (many
+  // systems at first, a few large ones at the end) differs from the best cap
+  // for its first iterations.
+  const bool complete = (iters == 0);
   DeviceGuard guard(ctx->device);
   std::memset(rep, 0, sizeof *rep);
   size_t tot = 0;
@@ -1679,8 +1684,10 @@ int pbcgs_tune_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const
     off += padded(A[k]->n);
   }
   pbcgs_opts o = *opts;
-  o.tol = 0.0;
-  o.maxit = iters;
+  if (!complete) {
+    o.tol = 0.0;
+    o.maxit = iters;
+  }
   o.history = nullptr;
   o.flags = 0;
   const int32_t saved = ctx->batch_gcap;
@@ -1696,7 +1703,7 @@ int pbcgs_tune_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const
       ms = infos[0].ms;
     }
     if (rc < 0) break;
-    const double per = ms / iters;
+    const double per = complete ? ms : ms / iters;
     rep->cand[rep->ncand] = gcap;
     rep->ms_per_iter[rep->ncand] = per;
     ++rep->ncand;

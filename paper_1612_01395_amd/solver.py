@@ -398,7 +398,9 @@ def tune(A: Operator, b: torch.Tensor, iters: int = 20, **opts) -> dict:
 
 
 def tune_batched(ops: list, bs: list, iters: int = 20, **opts) -> dict:
-    """The same for batched solves: the per-system workgroup cap, kept on the context."""
+    """The same for batched solves: the per-system workgroup cap, kept on the
+    context.  ``iters=0`` times complete solves at the given tol and maxit
+    (``tried`` then holds ms per whole batched solve)."""
     nsys = len(ops)
     ctx = ops[0].ctx
     VP = ctypes.c_void_p * nsys

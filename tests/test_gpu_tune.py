@@ -40,3 +40,24 @@ def test_tune_batched_keeps_results():
     for k, (A, b) in enumerate(zip(As, bs)):
         x_or, i_or = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, tol=1e-9)
         assert infos[k].iters == i_or["iters"] and same(host(xs[k]), x_or)
+
+
+def test_tune_batched_on_complete_solves():
+    """iters = 0 ranks the caps on whole solves at the caller's tol; results
+    stay the same bit for bit, and a negative iteration count is refused."""
+    require_gpu()
+    from paper_1612_01395_amd import _lib
+    systems = inputs.batch_systems(count=16, lo=8, hi=120)
+    As = [oracle.assemble(2, sy.n, 5, sy.beta) for sy in systems]
+    bs = [oracle.spmv(A, inputs.batch_x_true(sy.k, A.n)) for sy, A in zip(systems, As)]
+    ops = [csr_op(A) for A in As]
+    bd = [dev_t(b) for b in bs]
+    rep = solver.tune_batched(ops, bd, iters=0, variant="pbicgstab_rr", tol=1e-9, maxit=2000, rr_period=17)
+    say(f"tune batched (complete solves): {rep}")
+    assert rep["best"] in rep["tried"] and rep["best_ms_per_iter"] == min(rep["tried"].values())
+    with pytest.raises(_lib.PbcgsError):
+        solver.tune_batched(ops, bd, iters=-1, variant="pbicgstab_rr")
+    xs, infos = solver.solve_batched(ops, bd, variant="pbicgstab_rr", tol=1e-9, rr_period=17)
+    for k, (A, b) in enumerate(zip(As, bs)):
+        x_or, i_or = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, tol=1e-9, rr_period=17)
+        assert infos[k].iters == i_or["iters"] and same(host(xs[k]), x_or)
