@@ -3,8 +3,15 @@
 Tensors provide device memory and the current HIP stream; every computation
 is a call into libpbcgs.so.  The solvers are those of Cools & Vanroose,
 arXiv 1612.01395: standard BiCGStab (Algorithm 7, preconditioned: 10),
-pipelined BiCGStab (Algorithm 9, preconditioned: 11) and pipelined BiCGStab
-with residual replacement (Section 4.2).
+pipelined BiCGStab (Algorithm 9, preconditioned: 11), pipelined BiCGStab
+with residual replacement (Section 4.2), communication-avoiding BiCGStab
+(Algorithm 8), and the CG family of Section 2 for symmetric positive definite
+systems: CG (Algorithm 2), Chronopoulos & Gear CG (Algorithm 4) and
+pipelined CG (Algorithm 6).
+
+A context is bound to the stream that was current when it was created (the
+default context of each device and stream is cached), and an operator runs
+its solves on its context's stream.
 """
 
 from __future__ import annotations
