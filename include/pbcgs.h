@@ -1,11 +1,13 @@
 /*
  * pbcgs -- pipelined BiCGStab with residual replacement on one MI355X (gfx950).
  *
- * C ABI of the HIP library libpbcgs.so.  It solves A x = b for an unsymmetric
- * sparse A (CSR, or a matrix-free constant-coefficient 5/7-point stencil)
- * with one of three Krylov methods of S. Cools and W. Vanroose, "The
- * communication-hiding pipelined BiCGStab method for the parallel solution of
- * large unsymmetric linear systems" (arXiv 1612.01395):
+ * C ABI of the HIP library libpbcgs.so.  It solves A x = b for a sparse A
+ * (CSR, or a matrix-free constant-coefficient 5/7-point stencil) with the
+ * Krylov methods of S. Cools and W. Vanroose, "The communication-hiding
+ * pipelined BiCGStab method for the parallel solution of large unsymmetric
+ * linear systems" (arXiv 1612.01395): the BiCGStab variants for unsymmetric
+ * A, and the CG family the paper derives its framework on for symmetric
+ * positive definite A:
  *
  *   PBCGS_BICGSTAB       standard BiCGStab, the paper's Algorithm 7, or its
  *                        right-preconditioned form Algorithm 10 (Section 3.6);
@@ -117,8 +119,9 @@ typedef struct {
     int32_t check_every; /* iterations between host polls of the device status; 0 = auto   */
     int32_t flags;       /* bit 0: launch each kernel directly instead of through a
                             captured HIP graph; bit 1: time the fused kernels with events;
-                            bit 2: alpha_{i+1} of PBICGSTAB(_RR) and CA_BICGSTAB by eq. (5), the form
-                            without (r0, s_i), instead of eq. (3) (Section 3.1)          */
+                            bit 2: alpha_{i+1} of PBICGSTAB(_RR) and CA_BICGSTAB by
+                            eq. (5), the form without (r0, s_i), instead of eq. (3)
+                            (Section 3.1)                                                   */
     double* history;     /* nullable DEVICE array of maxit+1 doubles: history[i] =
                             ||r_i|| / ||r_0|| after i iterations (history[0] = 1)           */
 } pbcgs_opts;
@@ -131,10 +134,13 @@ typedef struct {
     int32_t syncs_per_iter;  /* kernel boundaries of one regular iteration (1 to 5)       */
     double relres_rec;       /* last ||r_i|| / ||r_0|| of the recurrence                  */
     double relres_true;      /* ||b - A x|| / ||r_0|| of the returned x                   */
-    double ms;               /* wall time of the iteration loop (HIP events), ms           */
-    double kernel_ms[2];     /* with flags bit 1: summed duration of the two fused kernels
-                                of the iteration (p-BiCGStab: t-phase, v-phase; BiCGStab:
-                                the two SpMV phases)                                      */
+    double ms;               /* device time (HIP events) from the setup to the last
+                                reduction, ms; the true residual is not included          */
+    double kernel_ms[2];     /* with flags bit 1: summed duration of two kernels of the
+                                iteration -- p-BiCGStab: t-phase, v-phase; BiCGStab and
+                                CA-BiCGStab: the two SpMV kernels; CG: s = A p and the
+                                x, r, u update; Chronopoulos & Gear: the update and
+                                w = A u; p-CG: its one kernel (slot 0)                    */
     int32_t kernel_calls[2]; /* launches timed for kernel_ms                              */
 } pbcgs_info;
 
@@ -230,8 +236,8 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
  * reductions and stopping test, and a system that stops leaves the later
  * launches at once.  Reductions are the same pairwise trees as in
  * pbcgs_solve, so each system's result equals that of its own pbcgs_solve
- * bit for bit.  No preconditioner, binary64, no history (ERR_UNSUPPORTED
- * otherwise).  The context keeps the batch workspace (8 vectors per system).
+ * bit for bit.  BiCGStab and p-BiCGStab (with or without replacement) only,
+ * no preconditioner, binary64, no history (ERR_UNSUPPORTED otherwise).  The context keeps the batch workspace (8 vectors per system).
  * Returns the largest numerical status of the systems, or a negative error.
  */
 int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const double* const* b,
