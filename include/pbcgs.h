@@ -163,6 +163,9 @@ const char* pbcgs_status_str(int status);
  * float64 val[nnz].  Each row is applied in stored order; ascending columns
  * are the convention.  The arrays are borrowed and must outlive the operator.
  * The structure is validated on the device (ERR_INVALID_ARG if malformed).
+ * One launch covers at most 1024 workgroups x 4 waves x 1024 blocks x 64 rows,
+ * so n <= 268,435,456, and nnz <= 2^31 - 1025 (int32 indexing); ERR_UNSUPPORTED
+ * beyond.
  */
 int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr,
                  const int32_t* col_idx, const double* val, pbcgs_op_t* out);

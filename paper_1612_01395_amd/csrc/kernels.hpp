@@ -40,7 +40,8 @@ namespace pbcgs {
 
 constexpr int kWG = 256;                  // threads per workgroup: 4 x wave64
 constexpr int kMaxD = 5;                  // dot products per reduction phase
-constexpr int kMaxR = 64;                 // 64-row blocks per wave
+constexpr int kMaxR = 1024;               // 64-row blocks per wave (a power of two)
+constexpr int kLevels = 11;               // levels of a wave's pairwise tree: kMaxR = 2^(kLevels-1)
 constexpr int kMaxG = 1024;               // workgroups of a producing kernel
 constexpr int kChunk = kMaxG / kWG;       // partials per thread when consuming
 
@@ -312,9 +313,18 @@ __device__ __forceinline__ bool sys_leader(const Args& a) { return wg_index(a) =
 // pout[k][blockIdx.x].  Body(row, valid, d) is called by all 64 lanes of a
 // block (so an operator may work on the block cooperatively); lanes with
 // valid == false (rows past n) must leave d at 0 and touch no vector.
+//
+// The partial is the pairwise sum of the workgroup's 4 R block totals in row
+// order.  Each wave builds the balanced tree over its R blocks (R a power of
+// two) as the blocks complete, like the digits of a binary counter: lvl[l]
+// holds the sum of the last finished group of 2^l blocks, and finishing block
+// j merges one level per trailing 1 bit of j (left subtree + right subtree).
+// Only lane 63, which holds a block's wave sum, touches the wave's levels.
+// The four wave totals then combine as (w0 + w1) + (w2 + w3).
 template <int ND, class T = double, class Body>
 __device__ __forceinline__ void produce(const Args& a, Body body) {
-  __shared__ T blk[ND][kWG];
+  __shared__ T lvl[4][kLevels][ND];
+  __shared__ T wtot[ND][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t wbase = ((int64_t)wg_index(a) * 4 + wave) * a.R * 64;
   for (int j = 0; j < a.R; ++j) {
@@ -328,19 +338,27 @@ __device__ __forceinline__ void produce(const Args& a, Body body) {
       wave_sum63<ND, T>(d);
     }
     if (lane == 63) {
+      int l = 0;
+      for (int bits = j; bits & 1; bits >>= 1, ++l) {
 #pragma unroll
-      for (int k = 0; k < ND; ++k) blk[k][wave * a.R + j] = d[k];
+        for (int k = 0; k < ND; ++k) d[k] = lvl[wave][l][k] + d[k];
+      }
+#pragma unroll
+      for (int k = 0; k < ND; ++k) lvl[wave][l][k] = d[k];
     }
   }
-  __syncthreads();
-  T v[ND], tot[ND];
+  if (lane == 63) {
+    const int top = __builtin_ctz((unsigned)a.R);  // the whole tree of R = 2^top blocks
 #pragma unroll
-  for (int k = 0; k < ND; ++k) v[k] = ((int)threadIdx.x < 4 * a.R) ? blk[k][threadIdx.x] : T(0);
-  wg_sum_all<ND, T>(v, tot);
+    for (int k = 0; k < ND; ++k) wtot[k][wave] = lvl[wave][top][k];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < ND; ++k) a.pout[k * a.pstride + wg_index(a)] = double(tot[k]);
+    for (int k = 0; k < ND; ++k)
+      a.pout[k * a.pstride + wg_index(a)] = double((wtot[k][0] + wtot[k][1]) + (wtot[k][2] + wtot[k][3]));
   }
+  __syncthreads();  // wtot and lvl may be reused by a later reduction of the same kernel
 }
 
 // The workgroup's rows without a reduction; Body(row, valid) as above.

@@ -1127,6 +1127,9 @@ int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr
   if (!ctx || !out) return fail(ctx, PBCGS_ERR_INVALID_ARG, "ctx or out is NULL");
   if (n <= 0 || nnz < 0 || nnz > INT32_MAX) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad n or nnz");
   if (!row_ptr || (nnz > 0 && (!col_idx || !val))) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL CSR array");
+  // the product streams non-zeros in int32 index rounds of kStage past the last one
+  if (nnz > (int64_t)INT32_MAX - 2 * CsrOp::kStage)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "nnz too large for int32 non-zero indexing");
   Shape sh;
   if (!make_shape(n, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows for one launch");
   DeviceGuard guard(ctx->device);
@@ -1632,6 +1635,7 @@ int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts*
   for (int R = 1; R <= kMaxR && rep->ncand < 12; R *= 2) {
     const int64_t G = ((int64_t)A->n + 256 * (int64_t)R - 1) / (256 * (int64_t)R);
     if (G > kMaxG) continue;
+    if (rep->ncand > 0 && G < 64) break;  // fewer workgroups than a quarter of the CUs: not a candidate
     A->tuned_R = R;
     double ms = 0.0;
     for (int t = 0; t < 2 && rc >= 0; ++t) {  // the first run captures the graphs

@@ -255,16 +255,18 @@ def test_api_errors():
 
 def test_size_limits():
     """An empty operator is refused; the largest system one launch covers is
-    1024 workgroups x 4 waves x 64 blocks x 64 rows = 16,777,216 rows (256^3),
-    and an operator one row larger is refused as unsupported rather than
-    mis-launched."""
+    1024 workgroups x 4 waves x 1024 blocks x 64 rows = 268,435,456 rows
+    (about 645^3), and an operator one row larger is refused as unsupported
+    rather than mis-launched.  The maximum-size solve (2 I x = 1, one
+    iteration, about 40 GB of device memory) runs every reduction through the
+    deepest per-wave tree."""
     require_gpu()
     from paper_1612_01395_amd import _lib
     dev = torch.device("cuda", 0)
     with pytest.raises(_lib.PbcgsError):
         solver.csr(torch.zeros(1, dtype=torch.int32, device=dev), torch.zeros(0, dtype=torch.int32, device=dev),
                    torch.zeros(0, dtype=torch.float64, device=dev))
-    n = 16777216 + 1
+    n = 268435456 + 1
     rp = torch.arange(n + 1, dtype=torch.int32, device=dev)
     col = torch.arange(n, dtype=torch.int32, device=dev)
     val = torch.full((n,), 2.0, dtype=torch.float64, device=dev)
@@ -273,7 +275,7 @@ def test_size_limits():
     assert e.value.code == _lib.ERR_UNSUPPORTED
     b = torch.ones(n, dtype=torch.float64, device=dev)
     # exactly the maximum: 2I x = 1 converges in one step
-    n = 16777216
+    n = 268435456
     op = solver.csr(rp[: n + 1].contiguous(), col[:n].contiguous(), val[:n].contiguous())
     x, info = solver.solve(op, b[:n].contiguous(), tol=1e-12)
     assert info.status == 0 and info.iters == 1
