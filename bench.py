@@ -55,9 +55,9 @@ def measured_traffic(kernel: str):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != kernel_source_hash() or t.get("kernel") != kernel:
+    if t.get("source_hash") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_launch", {}).get(kernel)
 
 
 def parse():
@@ -301,6 +301,13 @@ def main():
         "avg_launch_us": round(avg[dom] * 1e3, 2),
         "other_kernel_avg_us": round(avg[1 - dom] * 1e3, 2),
         "launches_timed": pinfo.kernel_calls[dom],
+        # the two fused kernels take nearly the same time, so which one is
+        # dominant can change from run to run: both, side by side
+        "per_kernel": {name: {"avg_launch_us": round(avg[k] * 1e3, 2), "bytes_per_launch": (ba, bb)[k],
+                              "achieved": round((ba, bb)[k] / (avg[k] * 1e-3) / 1e9, 1),
+                              "frac": round((ba, bb)[k] / (avg[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "traffic": measured_traffic(name)}
+                       for k, name in enumerate(("k_pa", "k_pb"))},
     }
 
     # ---- precision form at 256^3 (tol 1e-10): binary32 + binary64 replacement vs binary64

@@ -1576,9 +1576,26 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
     d.rp = op->rp; d.ci = op->ci; d.va = op->va;
     d.x = x[k]; d.b = b[k];
     d.np = (int64_t)padded(op->n);
-    d.n = op->n; d.G = (int32_t)G; d.R = R; d.wg0 = (int32_t)totalG;
+    d.n = op->n; d.G = (int32_t)G; d.R = R;
     totalG += G;
     wsneed += (size_t)8 * (size_t)d.np;
+  }
+  // Workgroups are dispatched in index order: the systems whose workgroups
+  // hold the most rows (largest R, then most rows) come first, so that a
+  // launch does not end waiting on long workgroups dispatched last.  Each
+  // system's reductions index its own workgroups, so results do not change.
+  {
+    std::vector<int32_t> order((size_t)nsys);
+    for (int32_t k = 0; k < nsys; ++k) order[(size_t)k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t p, int32_t q) {
+      const SysDesc &dp = desc[(size_t)p], &dq = desc[(size_t)q];
+      return dp.R != dq.R ? dp.R > dq.R : dp.n > dq.n;
+    });
+    int64_t wg = 0;
+    for (int32_t k : order) {
+      desc[(size_t)k].wg0 = (int32_t)wg;
+      wg += desc[(size_t)k].G;
+    }
   }
   if (totalG > (int64_t)INT32_MAX / 2) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many workgroups");
   DeviceGuard guard(ctx->device);
