@@ -261,7 +261,9 @@ __device__ __forceinline__ void wave_sum63(T (&v)[ND]) {
 }
 
 // Balanced-tree sum of one value per thread over the workgroup (256 threads,
-// 4 waves); every thread receives the totals.
+// 4 waves); every thread receives the totals.  No barrier after the last read
+// of lw: a kernel gathers at most once per launch (its branches are
+// exclusive), and the persistent kernel's grid barrier separates its gathers.
 template <int ND, class T>
 __device__ __forceinline__ void wg_sum_all(T (&v)[ND], T (&out)[ND]) {
   __shared__ T lw[4][ND];
@@ -273,7 +275,6 @@ __device__ __forceinline__ void wg_sum_all(T (&v)[ND], T (&out)[ND]) {
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < ND; ++k) out[k] = (lw[0][k] + lw[1][k]) + (lw[2][k] + lw[3][k]);
-  __syncthreads();
 }
 
 // Totals of the Gin partials of each of the ND sums in pin, in pairwise
@@ -358,7 +359,8 @@ __device__ __forceinline__ void produce(const Args& a, Body body) {
     for (int k = 0; k < ND; ++k)
       a.pout[k * a.pstride + wg_index(a)] = double((wtot[k][0] + wtot[k][1]) + (wtot[k][2] + wtot[k][3]));
   }
-  __syncthreads();  // wtot and lvl may be reused by a later reduction of the same kernel
+  // no barrier here: a kernel produces once per launch, and the persistent
+  // kernel's grid barrier separates its reductions
 }
 
 // The workgroup's rows without a reduction; Body(row, valid) as above.
