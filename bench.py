@@ -36,12 +36,37 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_pb_c2.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1612_01395_amd", "csrc", f) for f in ("kernels.hpp", "pbcgs.hip")]
 
 
+def code_text(src: str) -> str:
+    """The source with comments and blank lines removed (string literals kept),
+    so that editing a comment does not count as changing a kernel."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return "\n".join(line.rstrip() for line in "".join(out).splitlines() if line.strip())
+
+
 def kernel_source_hash() -> str:
+    """Hash of the code (without comments) of the kernel and launch sources."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -133,7 +158,7 @@ def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np

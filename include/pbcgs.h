@@ -73,7 +73,7 @@ typedef enum {
     PBCGS_ERR_INVALID_ARG = -1,   /* bad pointer, size, option or matrix structure         */
     PBCGS_ERR_ALLOC = -2,         /* device memory allocation failed                       */
     PBCGS_ERR_HIP = -3,           /* a HIP runtime call failed                             */
-    PBCGS_ERR_UNSUPPORTED = -4    /* valid request this build does not implement           */
+    PBCGS_ERR_UNSUPPORTED = -4    /* valid request the library does not implement          */
 } pbcgs_status;
 
 enum {

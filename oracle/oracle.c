@@ -388,7 +388,7 @@ static int bicgstab(const csr_t* A, const double* dinv, const double* b, double*
     if (!prod) goto oom;
 
     info->iters = 0; info->n_rr = 0; info->relres_rec = 0.0; info->relres_true = 0.0;
-    /* l.2: r_0 := b - A x_0 ; p_0 := r_0 */
+    /* r_0 := b - A x_0 ; p_0 := r_0 */
     spmv(A, x, tmp);
     PAR for (int32_t j = 0; j < n; ++j) r0[j] = b[j] - tmp[j];
     double gamma = DOT(r0, r0); /* (r_0, r_0) = (r_0, r_i) at i = 0 */
@@ -401,7 +401,7 @@ static int bicgstab(const csr_t* A, const double* dinv, const double* b, double*
     memcpy(p, r0, sizeof(double) * (size_t)n);
 
     for (int32_t i = 0; i < o->maxit; ++i) {
-        /* l.4-5 (Alg. 10): p^_i := M^{-1} p_i ; s_i := A p^_i */
+        /* Alg. 10: p^_i := M^{-1} p_i ; s_i := A p^_i */
         if (pc) { PAR for (int32_t j = 0; j < n; ++j) ph[j] = dinv[j] * p[j]; g_ctr.pc++; }
         spmv(A, ph, s);
         /* reduction (r_0, s_i) ; alpha_i := (r_0, r_i) / (r_0, s_i) */
@@ -484,7 +484,7 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
     if (!prod) goto oom;
 
     info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
-    /* l.2: r_0 := b - A x_0 ; r^_0 := M^{-1} r_0 ; w_0 := A r^_0 ; w^_0 := M^{-1} w_0 */
+    /* r_0 := b - A x_0 ; r^_0 := M^{-1} r_0 ; w_0 := A r^_0 ; w^_0 := M^{-1} w_0 */
     spmv(A, x, tmp);
     PAR for (int32_t j = 0; j < n; ++j) r0[j] = b[j] - tmp[j];
     double gamma = DOT(r0, r0); /* (r_0, r_0) */
@@ -496,7 +496,7 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
     if (pc) { PAR for (int32_t j = 0; j < n; ++j) rh[j] = dinv[j] * r[j]; g_ctr.pc++; }
     spmv(A, rh, w);
     if (pc) { PAR for (int32_t j = 0; j < n; ++j) wh[j] = dinv[j] * w[j]; g_ctr.pc++; }
-    /* l.3: t_0 := A w^_0 ; alpha_0 := (r_0, r_0) / (r_0, w_0) ; beta_{-1} := 0 */
+    /* t_0 := A w^_0 ; alpha_0 := (r_0, r_0) / (r_0, w_0) ; beta_{-1} := 0 */
     spmv(A, wh, t);
     double delta = DOT(r0, w);
     if (!isfinite(delta)) { info->status = OR_NONFINITE; goto done; }
@@ -508,7 +508,7 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
     int32_t n_rr = 0;
 
     for (int32_t i = 0; i < o->maxit; ++i) {
-        /* l.5: p^_i := r^_i + beta_{i-1} (p^_{i-1} - omega_{i-1} s^_{i-1}) */
+        /* p^_i := r^_i + beta_{i-1} (p^_{i-1} - omega_{i-1} s^_{i-1}) */
         PAR for (int32_t j = 0; j < n; ++j) ph[j] = rh[j] + beta * (ph[j] - omega * sh[j]);
         FLOPS(4); REC(1);
         if (rr_pending) {
@@ -518,26 +518,26 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
             spmv(A, sh, z);
             rr_pending = 0;
         } else {
-            /* l.6: s_i := w_i + beta_{i-1} (s_{i-1} - omega_{i-1} z_{i-1}) */
+            /* s_i := w_i + beta_{i-1} (s_{i-1} - omega_{i-1} z_{i-1}) */
             PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + beta * (s[j] - omega * z[j]);
-            /* l.7: s^_i := w^_i + beta_{i-1} (s^_{i-1} - omega_{i-1} z^_{i-1}) */
+            /* s^_i := w^_i + beta_{i-1} (s^_{i-1} - omega_{i-1} z^_{i-1}) */
             if (pc) PAR for (int32_t j = 0; j < n; ++j) sh[j] = wh[j] + beta * (sh[j] - omega * zh[j]);
-            /* l.8: z_i := t_i + beta_{i-1} (z_{i-1} - omega_{i-1} v_{i-1}) */
+            /* z_i := t_i + beta_{i-1} (z_{i-1} - omega_{i-1} v_{i-1}) */
             PAR for (int32_t j = 0; j < n; ++j) z[j] = t[j] + beta * (z[j] - omega * v[j]);
             FLOPS(pc ? 12 : 8); REC(pc ? 3 : 2);
         }
-        /* l.9-11: q_i := r_i - alpha_i s_i ; q^_i := r^_i - alpha_i s^_i ; y_i := w_i - alpha_i z_i */
+        /* q_i := r_i - alpha_i s_i ; q^_i := r^_i - alpha_i s^_i ; y_i := w_i - alpha_i z_i */
         PAR for (int32_t j = 0; j < n; ++j) q[j] = r[j] - alpha * s[j];
         if (pc) PAR for (int32_t j = 0; j < n; ++j) qh[j] = rh[j] - alpha * sh[j];
         PAR for (int32_t j = 0; j < n; ++j) y[j] = w[j] - alpha * z[j];
         FLOPS(pc ? 6 : 4); REC(pc ? 3 : 2);
-        /* l.12: begin reduction (q_i, y_i), (y_i, y_i) */
+        /* begin reduction (q_i, y_i), (y_i, y_i) */
         double th1 = DOT(q, y), th2 = DOT(y, y);
         g_ctr.glred++; g_ctr.dots += 2; FLOPS(4);
-        /* l.13-14: z^_i := M^{-1} z_i ; v_i := A z^_i  (overlapping the reduction) */
+        /* z^_i := M^{-1} z_i ; v_i := A z^_i  (overlapping the reduction) */
         if (pc) { PAR for (int32_t j = 0; j < n; ++j) zh[j] = dinv[j] * z[j]; g_ctr.pc++; }
         spmv(A, zh, v);
-        /* l.15-16: end reduction ; omega_i := (q_i, y_i) / (y_i, y_i) */
+        /* end reduction ; omega_i := (q_i, y_i) / (y_i, y_i) */
         if (!isfinite(th1) || !isfinite(th2)) { info->status = OR_NONFINITE; goto done; }
         if (th2 == 0.0) {
             PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * ph[j];
@@ -547,13 +547,13 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
         }
         omega = th1 / th2;
         if (!isfinite(omega)) { info->status = OR_NONFINITE; goto done; }
-        /* l.17: x_{i+1} := x_i + alpha_i p^_i + omega_i q^_i */
+        /* x_{i+1} := x_i + alpha_i p^_i + omega_i q^_i */
         PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * ph[j] + omega * qh[j];
-        /* l.18: r_{i+1} := q_i - omega_i y_i */
+        /* r_{i+1} := q_i - omega_i y_i */
         PAR for (int32_t j = 0; j < n; ++j) r[j] = q[j] - omega * y[j];
-        /* l.19: r^_{i+1} := q^_i - omega_i (w^_i - alpha_i z^_i) */
+        /* r^_{i+1} := q^_i - omega_i (w^_i - alpha_i z^_i) */
         if (pc) PAR for (int32_t j = 0; j < n; ++j) rh[j] = qh[j] - omega * (wh[j] - alpha * zh[j]);
-        /* l.20: w_{i+1} := y_i - omega_i (t_i - alpha_i v_i) */
+        /* w_{i+1} := y_i - omega_i (t_i - alpha_i v_i) */
         PAR for (int32_t j = 0; j < n; ++j) w[j] = y[j] - omega * (t[j] - alpha * v[j]);
         FLOPS(pc ? 14 : 10); REC(pc ? 4 : 3);
         info->iters = i + 1;
@@ -567,7 +567,7 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
             ++n_rr;
             info->n_rr = n_rr;
         }
-        /* l.21: begin reduction (r_0,r_{i+1}), (r_0,w_{i+1}), (r_0,s_i), (r_0,z_i), plus ||r_{i+1}||^2 */
+        /* begin reduction (r_0,r_{i+1}), (r_0,w_{i+1}), (r_0,s_i), (r_0,z_i), plus ||r_{i+1}||^2 */
         double gamma1 = DOT(r0, r), eta = DOT(r0, w), sig_s = DOT(r0, s), sig_z = DOT(r0, z);
         double nu = DOT(r, r);
         g_ctr.glred++; g_ctr.dots += 4; FLOPS(8);
@@ -578,10 +578,10 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
         info->relres_rec = sqrt(nu) / rho0;
         if (o->history) o->history[i + 1] = info->relres_rec;
         if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
-        /* l.22-23: w^_{i+1} := M^{-1} w_{i+1} ; t_{i+1} := A w^_{i+1} */
+        /* w^_{i+1} := M^{-1} w_{i+1} ; t_{i+1} := A w^_{i+1} */
         if (pc) { PAR for (int32_t j = 0; j < n; ++j) wh[j] = dinv[j] * w[j]; g_ctr.pc++; }
         spmv(A, wh, t);
-        /* l.24-26: end reduction ; beta_i ; alpha_{i+1} by eq. (3) */
+        /* end reduction ; beta_i ; alpha_{i+1} by eq. (3) */
         if (omega == 0.0 || gamma == 0.0) { info->status = OR_BREAKDOWN; goto done; }
         beta = (alpha / omega) * (gamma1 / gamma);
         if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }
@@ -1086,7 +1086,7 @@ static int pbicgstab_mp(const csr_t* A, const double* b, double* x, const or_opt
 
     for (int32_t i = 0; i < o->maxit; ++i) {
         const float af = (float)alpha, bf = (float)beta, wf = (float)omega;
-        /* l.4: p_i := r_i + beta (p_{i-1} - omega s_{i-1}) */
+        /* p_i := r_i + beta (p_{i-1} - omega s_{i-1}) */
         PAR for (int32_t j = 0; j < n; ++j) p[j] = r[j] + bf * (p[j] - wf * s[j]);
         if (rr_pending) {
             /* replacement, second half, in binary64: s = f(A p), z = f(A (A p)) */
@@ -1096,14 +1096,14 @@ static int pbicgstab_mp(const csr_t* A, const double* b, double* x, const or_opt
             PAR for (int32_t j = 0; j < n; ++j) z[j] = (float)w64[j];
             rr_pending = 0;
         } else {
-            /* l.5-6: s_i, z_i from the old s, z, v */
+            /* s_i, z_i from the old s, z, v */
             PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + bf * (s[j] - wf * z[j]);
             PAR for (int32_t j = 0; j < n; ++j) z[j] = t[j] + bf * (z[j] - wf * v[j]);
         }
-        /* l.7-8: q_i := r_i - alpha s_i ; y_i := w_i - alpha z_i */
+        /* q_i := r_i - alpha s_i ; y_i := w_i - alpha z_i */
         PAR for (int32_t j = 0; j < n; ++j) { q[j] = r[j] - af * s[j]; y[j] = w[j] - af * z[j]; }
         double th1 = DOT32(q, y), th2 = DOT32(y, y);
-        /* l.10: v_i := A z_i */
+        /* v_i := A z_i */
         spmv32(&A32, z, v);
         if (!isfinite(th1) || !isfinite(th2)) { info->status = OR_NONFINITE; goto done; }
         if (th2 == 0.0) {
@@ -1115,9 +1115,9 @@ static int pbicgstab_mp(const csr_t* A, const double* b, double* x, const or_opt
         omega = th1 / th2;
         if (!isfinite(omega)) { info->status = OR_NONFINITE; goto done; }
         const float wn = (float)omega;
-        /* l.13 in binary64: x_{i+1} := x_i + alpha p_i + omega q_i */
+        /* in binary64: x_{i+1} := x_i + alpha p_i + omega q_i */
         PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * (double)p[j] + omega * (double)q[j];
-        /* l.14-15: r_{i+1} := q_i - omega y_i ; w_{i+1} := y_i - omega (t_i - alpha v_i) */
+        /* r_{i+1} := q_i - omega y_i ; w_{i+1} := y_i - omega (t_i - alpha v_i) */
         PAR for (int32_t j = 0; j < n; ++j) {
             r[j] = q[j] - wn * y[j];
             w[j] = y[j] - wn * (t[j] - af * v[j]);
@@ -1138,7 +1138,7 @@ static int pbicgstab_mp(const csr_t* A, const double* b, double* x, const or_opt
                 info->n_rr = n_rr;
                 replaced = (replaced == 3) ? 4 : 2;  /* 4: forced; no second stop test */
             }
-            /* l.16: (r0,r), (r0,w), (r0,s), (r0,z) and ||r||^2 */
+            /* (r0,r), (r0,w), (r0,s), (r0,z) and ||r||^2 */
             double gamma1 = DOT32(r0, r), eta = DOT32(r0, w), sig_s = DOT32(r0, s), sig_z = DOT32(r0, z);
             double nu = DOT32(r, r);
             if (!isfinite(gamma1) || !isfinite(eta) || !isfinite(sig_s) || !isfinite(sig_z) || !isfinite(nu)) {
@@ -1156,9 +1156,9 @@ static int pbicgstab_mp(const csr_t* A, const double* b, double* x, const or_opt
                 replaced = 3;  /* not converged: replace now and reduce again */
                 continue;
             }
-            /* l.17: t_{i+1} := A w_{i+1} */
+            /* t_{i+1} := A w_{i+1} */
             spmv32(&A32, w, t);
-            /* l.18-20: beta_i ; alpha_{i+1} by eq. (3) */
+            /* beta_i ; alpha_{i+1} by eq. (3) */
             if (omega == 0.0 || gamma == 0.0) { info->status = OR_BREAKDOWN; goto done; }
             beta = (alpha / omega) * (gamma1 / gamma);
             if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }

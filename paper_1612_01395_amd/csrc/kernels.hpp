@@ -8,8 +8,8 @@
 //
 //   p-BiCGStab (paper Algorithms 9 and 11, Sections 3.3 and 3.6):
 //     k_pa  finishes reduction 2 of the previous iteration (stop test, beta,
-//           alpha), then t := A w^ ; lines 5-11 and 13 ; partials (q,y), (y,y)
-//     k_pb  finishes reduction 1 (omega), then v := A z^ ; lines 17-20 and 22 ;
+//           alpha), then t := A w^ ; the p^, s, s^, z, q, y recurrences and z^ ; partials (q,y), (y,y)
+//     k_pb  finishes reduction 1 (omega), then v := A z^ ; the x, r, r^, w updates and w^ ;
 //           partials (r0,r), (r0,w), (r0,s), (r0,z), (r,r)
 //   two kernel boundaries per iteration, against five for BiCGStab (Algorithm 7:
 //   SpMV | reduction | AXPY | SpMV + reduction | AXPY + reduction | AXPY).
@@ -408,7 +408,7 @@ __device__ __forceinline__ void publish(const Args& a, const State& s) {
 // inputs; only the leader writes the history.
 // ---------------------------------------------------------------------------
 
-// gamma = (r0, r0), rho0 = ||r0|| (Algorithms 7-11, line 2).
+// gamma = (r0, r0), rho0 = ||r0|| (the setup of Algorithms 7-11).
 __device__ __forceinline__ void fin_setup_gamma(State& s, double* hist, double g) {
   s.gamma = g;
   const double rho0 = sqrt(g);
@@ -419,7 +419,7 @@ __device__ __forceinline__ void fin_setup_gamma(State& s, double* hist, double g
   else if (rho0 == 0.0) { s.status = DS_SUCCESS; s.relres = 0.0; }
 }
 
-// alpha_0 = (r0, r0) / (r0, w0), beta_{-1} = omega_{-1} = 0 (Algorithm 9/11, lines 2-3).
+// alpha_0 = (r0, r0) / (r0, w0), beta_{-1} = omega_{-1} = 0 (the setup of Algorithms 9 and 11).
 __device__ __forceinline__ void fin_setup_alpha(State& s, double delta) {
   if (!finite(delta)) { s.status = DS_NONFINITE; return; }
   if (delta == 0.0) { s.status = DS_BREAKDOWN; return; }
@@ -430,8 +430,8 @@ __device__ __forceinline__ void fin_setup_alpha(State& s, double delta) {
   s.omega = 0.0;
 }
 
-// omega_i = (q, y) / (y, y)  (reduction 1; Algorithm 7 lines 9-10, Algorithm
-// 9 line 12, Algorithm 11 line 16).  Returns true when (y, y) = 0: then q = 0
+// omega_i = (q, y) / (y, y)  (reduction 1 of Algorithms 7, 9, 10 and 11).
+// Returns true when (y, y) = 0: then q = 0
 // and x_i + alpha_i p^_i is the solution; the caller applies that update.
 __device__ __forceinline__ bool fin_omega(State& s, double* hist, double qy, double yy) {
   if (!finite(qy) || !finite(yy)) { s.status = DS_NONFINITE; return false; }
@@ -492,7 +492,7 @@ __device__ __forceinline__ void fin_pipe_b(State& s, double* hist, const double 
   next_alpha(s, aform, g1, eta, sig_s, sig_z, beta, omega);
 }
 
-// alpha_i = (r0, r_i) / (r0, s_i)  (Algorithm 7 lines 5-6).
+// alpha_i = (r0, r_i) / (r0, s_i)  (the first reduction of Algorithm 7).
 __device__ __forceinline__ void fin_bicg_alpha(State& s, double delta) {
   if (!finite(delta)) { s.status = DS_NONFINITE; return; }
   if (delta == 0.0) { s.status = DS_BREAKDOWN; return; }
@@ -501,7 +501,7 @@ __device__ __forceinline__ void fin_bicg_alpha(State& s, double delta) {
   s.alpha = alpha;
 }
 
-// Stopping test and beta_i = (alpha/omega) (r0, r_{i+1}) / (r0, r_i)  (Algorithm 7 lines 13-14).
+// Stopping test and beta_i = (alpha/omega) (r0, r_{i+1}) / (r0, r_i)  (the last reduction of Algorithm 7).
 __device__ __forceinline__ void fin_bicg_beta(State& s, double* hist, double g1, double nu) {
   s.iters += 1;
   if (!finite(g1) || !finite(nu)) { s.status = DS_NONFINITE; return; }
@@ -584,10 +584,10 @@ __global__ __launch_bounds__(kWG) void k_setup_w0(Op op, Args a) { d_setup_w0<Op
 
 // Phase A of iteration i.  First it finishes the previous reduction: in the
 // first iteration alpha_0 (setup 2), later reduction 2 of iteration i-1 (stop
-// test, beta_{i-1}, alpha_i).  RR2 = false: t = A w^ and the recurrences of
-// lines 5-11 and 13.  RR2 = true (the iteration after a residual replacement):
+// test, beta_{i-1}, alpha_i).  RR2 = false: t = A w^, the recurrences of p^,
+// s, s^, z, q, y, and z^.  RR2 = true (the iteration after a residual replacement):
 // p^, s, s^ were already recomputed and reduction 2 already finished, so
-// t = A w^ and z = A s^ (both gathers), then lines 9-11 and 13.
+// t = A w^ and z = A s^ (both gathers), then q, q^, y and z^.
 // Partials: (q, y), (y, y).
 template <class Op, int PC, bool RR2>
 __device__ __forceinline__ void d_pa(Op op, Args a) {
@@ -607,7 +607,7 @@ __device__ __forceinline__ void d_pa(Op op, Args a) {
   if (st.status != DS_RUNNING) return;
   const double alpha = st.alpha, beta = st.beta, omega = st.omega;
   produce<2>(a, [&](int32_t row, bool valid, double (&d)[2]) {
-    const double t = op.spmv(row, valid, a.wh);  // line 23 of the previous iteration
+    const double t = op.spmv(row, valid, a.wh);  // t = A w^, the last step of the previous iteration
     const double z_rr = RR2 ? op.spmv(row, valid, a.sh) : 0.0;
     if (!valid) return;
     const double r = a.r[row], w = a.w[row];
@@ -621,20 +621,20 @@ __device__ __forceinline__ void d_pa(Op op, Args a) {
       if (PC != PC_NONE) {
         const double rh = a.rh[row], wh = a.wh[row];
         const double sh_old = a.sh[row], zh_old = a.zh[row];
-        a.ph[row] = rh + beta * (a.ph[row] - omega * sh_old);          // line 5
-        a.sh[row] = wh + beta * (sh_old - omega * zh_old);             // line 7
+        a.ph[row] = rh + beta * (a.ph[row] - omega * sh_old);          // p^
+        a.sh[row] = wh + beta * (sh_old - omega * zh_old);             // s^
       } else {
-        a.ph[row] = r + beta * (a.ph[row] - omega * s_old);            // Alg. 9 line 4
+        a.ph[row] = r + beta * (a.ph[row] - omega * s_old);            // p (Algorithm 9)
       }
-      s = w + beta * (s_old - omega * z_old);                          // line 6
-      z = t + beta * (z_old - omega * v);                              // line 8
+      s = w + beta * (s_old - omega * z_old);                          // s
+      z = t + beta * (z_old - omega * v);                              // z
       a.s[row] = s;
     }
-    const double q = r - alpha * s;                                    // line 9
-    const double y = w - alpha * z;                                    // line 11
+    const double q = r - alpha * s;                                    // q
+    const double y = w - alpha * z;                                    // y
     a.t[row] = t;
     a.z[row] = z;
-    if (PC != PC_NONE) a.zh[row] = apply_pc<PC>(a, row, z);            // line 13
+    if (PC != PC_NONE) a.zh[row] = apply_pc<PC>(a, row, z);            // z^ = M^{-1} z
     d[0] = q * y;
     d[1] = y * y;
   });
@@ -643,7 +643,7 @@ template <class Op, int PC, bool RR2>
 __global__ __launch_bounds__(kWG) void k_pa(Op op, Args a) { d_pa<Op, PC, RR2>(op, a); }
 
 // Phase B of iteration i: omega_i from phase A's partials ; v = A z^ ;
-// lines 9-11 recomputed ; lines 17-20 ; line 22 ; partials of (r0,r),
+// q, q^, y recomputed ; the x, r, r^, w updates ; w^ ; partials of (r0,r),
 // (r0,w), (r0,s), (r0,z), (r,r) (reduction 2).
 template <class Op, int PC>
 __device__ __forceinline__ void d_pb(Op op, Args a) {
@@ -662,7 +662,7 @@ __device__ __forceinline__ void d_pb(Op op, Args a) {
   if (st.status != DS_RUNNING) return;
   const double omega = st.omega;
   produce<5>(a, [&](int32_t row, bool valid, double (&d)[5]) {
-    const double v = op.spmv(row, valid, a.zh);                        // line 14
+    const double v = op.spmv(row, valid, a.zh);                        // v = A z^
     if (!valid) return;
     const double r = a.r[row], s = a.s[row], w = a.w[row], z = a.z[row];
     const double q = r - alpha * s;
@@ -671,19 +671,19 @@ __device__ __forceinline__ void d_pb(Op op, Args a) {
     double rn;
     if (PC != PC_NONE) {
       const double rh = a.rh[row], sh = a.sh[row], wh = a.wh[row], zh = a.zh[row];
-      const double qh = rh - alpha * sh;                               // line 10
-      a.x[row] = a.x[row] + alpha * a.ph[row] + omega * qh;            // line 17
-      rn = q - omega * y;                                              // line 18
-      a.rh[row] = qh - omega * (wh - alpha * zh);                      // line 19
+      const double qh = rh - alpha * sh;                               // q^
+      a.x[row] = a.x[row] + alpha * a.ph[row] + omega * qh;            // x
+      rn = q - omega * y;                                              // r
+      a.rh[row] = qh - omega * (wh - alpha * zh);                      // r^
     } else {
       a.x[row] = a.x[row] + alpha * a.ph[row] + omega * q;
       rn = q - omega * y;
     }
-    const double wn = y - omega * (t - alpha * v);                     // line 20
+    const double wn = y - omega * (t - alpha * v);                     // w
     a.v[row] = v;
     a.r[row] = rn;
     a.w[row] = wn;
-    if (PC != PC_NONE) a.wh[row] = apply_pc<PC>(a, row, wn);           // line 22
+    if (PC != PC_NONE) a.wh[row] = apply_pc<PC>(a, row, wn);           // w^ = M^{-1} w
     const double r0 = a.r0[row];
     d[0] = r0 * rn;
     d[1] = r0 * wn;
@@ -696,7 +696,7 @@ template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_pb(Op op, Args a) { d_pb<Op, PC>(op, a); }
 
 // Residual-replacement iteration, phase B': omega_i, then only the x update
-// of line 17 (r, r^, w are replaced next, so lines 18-20 and v are not needed).
+// of x (r, r^, w are replaced next, so their recurrences and v are not needed).
 template <int PC>
 __device__ __forceinline__ void d_rr_x(Args a) {
   PBCGS_PROLOGUE(st)
@@ -760,7 +760,7 @@ template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_rr_w(Op op, Args a) { d_rr_w<Op, PC>(op, a); }
 
 // Second half, in the iteration after a replacement: reduction 2 (stop test,
-// beta, alpha), then line 5 (p^ update) alone.
+// beta, alpha), then the p^ update alone.
 template <int PC>
 __device__ __forceinline__ void d_rr_p(Args a) {
   PBCGS_PROLOGUE(st)
@@ -1416,7 +1416,7 @@ __global__ __launch_bounds__(kWG) void k_mp_setup_w0(Op64 op, Args a) {
 }
 
 // Phase A: finishes the previous reduction (setup alpha or reduction 2), then
-// t = A w (binary32) and lines 4-8 of Algorithm 9.  RR2: s was replaced by
+// t = A w (binary32) and the p, s, z, q, y recurrences of Algorithm 9.  RR2: s was replaced by
 // f(A p) already; z = f(A s64) in binary64 instead of the recurrence.
 template <class Op32, class Op64, bool RR2>
 __global__ __launch_bounds__(kWG) void k_mp_pa(Op32 op, Op64 op64, Args a) {
