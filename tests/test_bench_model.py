@@ -1,0 +1,50 @@
+"""CPU checks of the benchmark's bookkeeping: the algorithmic byte model the
+roofline divides by, and the source hash that decides whether the recorded
+HBM traffic still describes the kernels."""
+
+import json
+
+import bench
+
+N, NNZ = 2097152, 14581760          # 3-D 7-point 128^3
+VEC, MAT = 8 * N, 4 * (N + 1) + 12 * NNZ
+
+
+def test_fused_kernel_bytes_at_128():
+    ka, kb, it = bench.algorithmic_bytes(N, NNZ, "pbicgstab", False)
+    assert (ka, kb) == (MAT + 10 * VEC, MAT + 12 * VEC) == (351141892, 384696324)
+    assert it == 2 * MAT + 22 * VEC
+    # BiCGStab 19 passes folded, 23 with the hatted vectors; literal Algorithm 11 34
+    assert bench.algorithmic_bytes(N, NNZ, "bicgstab", False)[2] == 2 * MAT + 19 * VEC
+    assert bench.algorithmic_bytes(N, NNZ, "bicgstab", False, folded=False)[2] == 2 * MAT + 23 * VEC
+    assert bench.algorithmic_bytes(N, NNZ, "pbicgstab", False, folded=False)[2] == 2 * MAT + 34 * VEC
+    assert bench.algorithmic_bytes(N, NNZ, "ca_bicgstab", False)[2] == 2 * MAT + 24 * VEC
+    assert bench.algorithmic_bytes(N, NNZ, "pbicgstab", True)[2] == 22 * VEC  # stencil: no operator bytes
+
+
+def test_cg_family_bytes():
+    for variant, passes in (("cg", 12), ("cgcg", 14), ("pipe_cg", 18)):
+        assert bench.algorithmic_bytes_cg(N, NNZ, variant, True) == MAT + passes * VEC
+
+
+def test_code_text_ignores_comments_only():
+    src = 'int a = 1; // note\n/* block\n comment */ int b = 2;\nconst char* s = "x // y /* z */";\nchar c = \'/\';\n'
+    code = bench.code_text(src)
+    assert "note" not in code and "block" not in code
+    assert '"x // y /* z */"' in code and "'/'" in code
+    assert bench.code_text(src.replace("// note", "// other note")) == code
+    assert bench.code_text(src.replace("int b = 2", "int b = 3")) != code
+
+
+def test_recorded_traffic_matches_the_sources():
+    """The committed counter summary was taken on the current kernels (after a
+    kernel change the benchmark reports no traffic until the counters are
+    taken again; this test then skips with that reason)."""
+    import pytest
+    with open(bench.TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t["source_hash"] != bench.kernel_source_hash():
+        pytest.skip("kernel sources changed since the HBM counters were taken")
+    for k in ("k_pa", "k_pb"):
+        got = bench.measured_traffic(k)
+        assert got is not None and got > bench.algorithmic_bytes(N, NNZ, "pbicgstab", False)[0 if k == "k_pa" else 1]
