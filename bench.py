@@ -94,20 +94,22 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     p.add_argument("--only", default="",
-                   help="comma list of legs to run: pipe,bicg,explicit,stencil,fixed,cg,precision,batched,sweep,paper,"
+                   help="comma list of legs to run: pipe,index32,bicg,explicit,stencil,fixed,cg,precision,batched,sweep,paper,"
                         "configs")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
     return p.parse_args()
 
 
-def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: bool = True):
+def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: bool = True, index_bytes: int = 4):
     """Algorithmic HBM bytes of the two dominant kernels of one iteration and
     of the whole iteration: (K_a, K_b, iteration).
 
     Every array a kernel touches is counted once: the operator (int32
-    row_ptr, int32 col, f64 val; nothing for the stencil) and one read or
-    write of each N-vector (the gathered SpMV input counted once).  Jacobi
+    row_ptr, the column indices at `index_bytes` each -- 2 for the compact
+    int16 copy, 4 for int32 columns -- and f64 val; nothing for the stencil)
+    and one read or write of each N-vector (the gathered SpMV input counted
+    once).  Jacobi
     with a constant diagonal is a scalar (no dinv vector).
 
     Folded Jacobi (A M^{-1} formed, Algorithm 9 on it): K_a reads w, r, v, s,
@@ -124,7 +126,7 @@ def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: boo
     w, z, x, p, writes x, r: 8): 24 per iteration.
     """
     vec = 8 * N
-    mat = 0 if stencil else 4 * (N + 1) + 12 * nnz
+    mat = 0 if stencil else 4 * (N + 1) + (8 + index_bytes) * nnz
     if variant == "ca_bicgstab":
         return mat + 4 * vec, mat + 5 * vec, 24 * vec + 2 * mat
     if variant == "bicgstab":
@@ -136,7 +138,7 @@ def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: boo
     return mat + 16 * vec, mat + 18 * vec, 34 * vec + 2 * mat
 
 
-def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool):
+def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool, index_bytes: int = 4):
     """Algorithmic HBM bytes of one iteration of the CG family (Section 2) on
     a CSR operator with Jacobi by a constant (a scalar, no vector) or none.
 
@@ -150,7 +152,7 @@ def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool):
     m = w: 12.  One SpMV per iteration in each.
     """
     vec = 8 * N
-    mat = 4 * (N + 1) + 12 * nnz
+    mat = 4 * (N + 1) + (8 + index_bytes) * nnz
     passes = {"cg": (12, 11), "cgcg": (14, 11), "pipe_cg": (18, 12)}[variant][0 if jacobi else 1]
     return passes * vec + mat
 
@@ -171,13 +173,14 @@ def main():
     dev = torch.device("cuda", 0)
     w = inputs.workload("c2", n=args.n)
     N = w.N
-    legs = set(args.only.split(",")) if args.only else {"pipe", "bicg", "explicit", "stencil", "fixed", "cg",
+    legs = set(args.only.split(",")) if args.only else {"pipe", "index32", "bicg", "explicit", "stencil", "fixed", "cg",
                                                          "precision", "batched", "sweep", "paper", "configs"}
 
     # ---- inputs resident in HBM -------------------------------------------------
     rp, col, val = solver.assemble_convdiff(w.dim, w.n, w.npts, w.beta)
     nnz = val.numel()
     A = solver.csr(rp, col, val)
+    ib = A.index_bytes  # 2: the operator holds the compact int16 column copy
     xt = torch.from_numpy(inputs.x_true(N)).to(dev)
     b = solver.spmv(A, xt)
     mid = w.n // 2
@@ -191,15 +194,15 @@ def main():
     # launch shape of the 128^3 operator from the autotuner (never changes a result)
     tune = solver.tune(A, b, iters=20, variant="pbicgstab_rr", precond="jacobi_folded", rr_period=w.rr_period)
 
-    def timed_leg(op, variant, precond):
+    def timed_leg(op, variant, precond, **extra):
         for _ in range(args.warmup):
-            solver.solve(op, b, variant=variant, precond=precond, out=xbuf, **common)
+            solver.solve(op, b, variant=variant, precond=precond, out=xbuf, **common, **extra)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         iters = 0
         last = None
         for _ in range(args.steps):
-            _, info = solver.solve(op, b, variant=variant, precond=precond, out=xbuf, **common)
+            _, info = solver.solve(op, b, variant=variant, precond=precond, out=xbuf, **common, **extra)
             iters += info.iters
             last = info
         torch.cuda.synchronize()
@@ -212,23 +215,24 @@ def main():
         "bicg": ("csr", "bicgstab", "jacobi_folded"),
         "ca": ("csr", "ca_bicgstab", "jacobi_folded"),
         "pipe_norr": ("csr", "pbicgstab", "jacobi_folded"),
+        "pipe_i32": ("csr", "pbicgstab_rr", "jacobi_folded", {"index32": True}),  # int32 columns
         "pipe_alg11": ("csr", "pbicgstab_rr", "jacobi"),
         "bicg_alg10": ("csr", "bicgstab", "jacobi"),
         "st_pipe": ("stencil", "pbicgstab_rr", "jacobi_folded"),
         "st_bicg": ("stencil", "bicgstab", "jacobi_folded"),
     }
-    groups = {"pipe": ["pipe", "pipe_norr"], "bicg": ["bicg", "ca"], "explicit": ["pipe_alg11", "bicg_alg10"],
+    groups = {"pipe": ["pipe", "pipe_norr"], "index32": ["pipe_i32"], "bicg": ["bicg", "ca"], "explicit": ["pipe_alg11", "bicg_alg10"],
               "stencil": ["st_pipe", "st_bicg"]}
     res = {}
-    for g in ("pipe", "bicg", "explicit", "stencil"):
+    for g in ("pipe", "index32", "bicg", "explicit", "stencil"):
         if g not in legs:
             continue
         for leg in groups[g]:
-            kind, variant, precond = LEGS[leg]
+            kind, variant, precond, *extra = LEGS[leg]
             op = A if kind == "csr" else S
             if op is None:
                 continue
-            res[leg] = timed_leg(op, variant, precond)
+            res[leg] = timed_leg(op, variant, precond, **(extra[0] if extra else {}))
 
     # ---- fixed-iteration mode: tol = 0, 200 iterations, device-timed -----------
     fixed = None
@@ -300,7 +304,8 @@ def main():
                 rate = its / cdt
                 entry[variant] = {"iters_per_s": round(rate, 2), "iters_per_solve": cinfo.iters,
                                   "ms_per_solve": round(cdt / args.steps * 1e3, 3),
-                                  "gbps_effective": round(algorithmic_bytes_cg(ws.N, vals.numel(), variant, True)
+                                  "gbps_effective": round(algorithmic_bytes_cg(ws.N, vals.numel(), variant, True,
+                                                                              As.index_bytes)
                                                           * rate / 1e9, 1),
                                   "syncs_per_iter": cinfo.syncs_per_iter, "relres_true": cinfo.relres_true}
             cgfam[f"{side}^3"] = entry
@@ -309,7 +314,7 @@ def main():
     # ---- roofline of the dominant kernel: one solve with per-kernel events -------
     _, pinfo = solver.solve(A, b, variant="pbicgstab_rr", precond="jacobi_folded", out=xbuf, time_kernels=True,
                             **common)
-    ba, bb, _ = algorithmic_bytes(N, nnz, "pbicgstab", False)
+    ba, bb, _ = algorithmic_bytes(N, nnz, "pbicgstab", False, index_bytes=ib)
     avg = [pinfo.kernel_ms[k] / max(pinfo.kernel_calls[k], 1) for k in range(2)]
     dom = 0 if pinfo.kernel_ms[0] >= pinfo.kernel_ms[1] else 1
     dom_bytes = (ba, bb)[dom]
@@ -323,6 +328,7 @@ def main():
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": measured_traffic(("k_pa", "k_pb")[dom]),
         "bytes_per_launch": dom_bytes,
+        "column_index_bytes": ib,
         "avg_launch_us": round(avg[dom] * 1e3, 2),
         "other_kernel_avg_us": round(avg[1 - dom] * 1e3, 2),
         "launches_timed": pinfo.kernel_calls[dom],
@@ -542,7 +548,7 @@ def main():
 
     it, dt, info = res.get("pipe", (0, 1.0, None))
     value = it / dt if it else None
-    _, _, per_iter_bytes = algorithmic_bytes(N, nnz, "pbicgstab", False)
+    _, _, per_iter_bytes = algorithmic_bytes(N, nnz, "pbicgstab", False, index_bytes=ib)
     out = {
         "metric": "p-BiCGStab iters/sec + HBM GB/s (3D 7-pt 128^3 FP64) vs plain BiCGStab, same GPU",
         "value": round(value, 2) if value else None,
@@ -568,10 +574,10 @@ def main():
         "autotuned_rows_per_wave_blocks": tune["best"],
     }
 
-    def leg_summary(key, variant, stencil, folded):
+    def leg_summary(key, variant, stencil, folded, index_bytes=ib):
         lit, ldt, linfo = res[key]
         lval = lit / ldt
-        _, _, lbytes = algorithmic_bytes(N, nnz, variant, stencil, folded)
+        _, _, lbytes = algorithmic_bytes(N, nnz, variant, stencil, folded, index_bytes=index_bytes)
         return {"iters_per_s": round(lval, 2), "iters_per_solve": linfo.iters,
                 "ms_per_solve": round(ldt / args.steps * 1e3, 3), "gbps_effective": round(lbytes * lval / 1e9, 1),
                 "syncs_per_iter": linfo.syncs_per_iter, "relres_true": linfo.relres_true}
@@ -589,6 +595,11 @@ def main():
             out["pbicgstab_over_ca_bicgstab_iters_per_s"] = round(value / out["ca_bicgstab"]["iters_per_s"], 4)
     if "pipe_norr" in res:
         out["pbicgstab_without_replacement"] = leg_summary("pipe_norr", "pbicgstab", False, True)
+    if "pipe_i32" in res:
+        out["pbicgstab_rr_int32_columns"] = leg_summary("pipe_i32", "pbicgstab", False, True, index_bytes=4)
+        if value:
+            out["compact_over_int32_columns_iters_per_s"] = round(
+                value / out["pbicgstab_rr_int32_columns"]["iters_per_s"], 4)
     if "pipe_alg11" in res:
         out["explicit_jacobi"] = {"pbicgstab_rr_alg11": leg_summary("pipe_alg11", "pbicgstab", False, False),
                                   "bicgstab_alg10": leg_summary("bicg_alg10", "bicgstab", False, False)}

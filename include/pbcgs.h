@@ -121,7 +121,8 @@ typedef struct {
                             captured HIP graph; bit 1: time the fused kernels with events;
                             bit 2: alpha_{i+1} of PBICGSTAB(_RR) and CA_BICGSTAB by
                             eq. (5), the form without (r0, s_i), instead of eq. (3)
-                            (Section 3.1)                                                   */
+                            (Section 3.1); bit 3: read the caller's int32 col_idx
+                            even when the operator holds the compact int16 copy      */
     double* history;     /* nullable DEVICE array of maxit+1 doubles: history[i] =
                             ||r_i|| / ||r_0|| after i iterations (history[0] = 1)           */
 } pbcgs_opts;
@@ -163,6 +164,13 @@ const char* pbcgs_status_str(int status);
  * float64 val[nnz].  Each row is applied in stored order; ascending columns
  * are the convention.  The arrays are borrowed and must outlive the operator.
  * The structure is validated on the device (ERR_INVALID_ARG if malformed).
+ * When every column j of a row i satisfies -32768 <= j - (i & ~63) <= 32767
+ * (banded matrices such as the paper's stencil discretisations), the operator
+ * also keeps a compact copy of the columns as int16 offsets from the row's
+ * 64-row block start (2 nnz bytes of device memory, freed with it), which the
+ * solves and pbcgs_spmv read instead of col_idx: 2 instead of 4 bytes per
+ * non-zero and product, with identical results.  Values may change between
+ * calls; row_ptr and col_idx must not change while the operator exists.
  * One launch covers at most 1024 workgroups x 4 waves x 1024 blocks x 64 rows,
  * so n <= 268,435,456, and nnz <= 2^31 - 1025 (int32 indexing); ERR_UNSUPPORTED
  * beyond.
@@ -203,6 +211,11 @@ int pbcgs_csr_outer_grad(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* lambda, co
 
 /* Number of rows of op (host), or a negative status. */
 int64_t pbcgs_op_rows(pbcgs_op_t op);
+
+/* Bytes per stored column index the solves read for op: 2 when a CSR operator
+ * holds the compact int16 copy (see pbcgs_op_csr), 4 for int32 columns, 0 for
+ * a stencil; ERR_INVALID_ARG for NULL. */
+int pbcgs_op_index_bytes(pbcgs_op_t op);
 
 /* y := A x (device pointers, n doubles each; x and y must not overlap). */
 int pbcgs_spmv(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* x, double* y);

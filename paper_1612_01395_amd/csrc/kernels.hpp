@@ -36,6 +36,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace pbcgs {
 
 constexpr int kWG = 256;                  // threads per workgroup: 4 x wave64
@@ -68,15 +70,26 @@ struct alignas(128) DevState {
 // ---------------------------------------------------------------------------
 // Operators: apply one row of y = A x, summing in ascending column order.
 // ---------------------------------------------------------------------------
-template <class V>
+//
+// Column indices (type I) are either the caller's int32 columns or a compact
+// int16 copy in which each column is stored as its offset from the first row
+// of its row's 64-row block (row & ~63); a wave always works on a whole
+// block that starts at a multiple of 64, so that row is known to every lane.
+template <class V, class I = int32_t>
 struct CsrOpT {
   using Val = V;
   const int32_t* __restrict__ rp;
-  const int32_t* __restrict__ ci;
+  const I* __restrict__ ci;
   const V* __restrict__ va;
   int32_t n;
 
   static constexpr int kStage = 512;  // staged non-zeros per wave and round
+
+  // column of a stored index; base = first row of the row's 64-row block
+  static __device__ __forceinline__ int32_t col(I c, int32_t base) {
+    if constexpr (sizeof(I) == sizeof(int32_t)) return (int32_t)c;
+    else return base + (int32_t)c;
+  }
 
   // Row `row` of A x, computed by the whole wave for its 64-row block (all 64
   // lanes call it; lanes with valid == false return 0).  The block's
@@ -109,7 +122,7 @@ struct CsrOpT {
 #pragma unroll
       for (int u = 0; u < kStage / 64; ++u) {
         const int32_t k = min(c0 + u * 64 + lane, c1 - 1);
-        cc[u] = __builtin_nontemporal_load(&ci[k]);
+        cc[u] = col(__builtin_nontemporal_load(&ci[k]), b0);
         vv[u] = __builtin_nontemporal_load(&va[k]);
       }
 #pragma unroll
@@ -126,14 +139,20 @@ struct CsrOpT {
   template <class X>
   __device__ __forceinline__ V apply(int32_t row, const X* __restrict__ x) const {
     const int32_t e = rp[row + 1];
+    const int32_t base = row & ~63;
     V acc = V(0);
     for (int32_t k = rp[row]; k < e; ++k)
-      acc = acc + __builtin_nontemporal_load(&va[k]) * V(x[__builtin_nontemporal_load(&ci[k])]);
+      acc = acc + __builtin_nontemporal_load(&va[k]) * V(x[col(__builtin_nontemporal_load(&ci[k]), base)]);
     return acc;
   }
 };
 using CsrOp = CsrOpT<double>;
 using CsrOp32 = CsrOpT<float>;
+using CsrOp16 = CsrOpT<double, int16_t>;
+using CsrOp16f = CsrOpT<float, int16_t>;
+
+template <class Op> struct IsCsr : std::false_type {};
+template <class V, class I> struct IsCsr<CsrOpT<V, I>> : std::true_type {};
 
 // Constant-coefficient 5-point (nz == 1) or 7-point stencil, Dirichlet
 // boundaries; c[] in ascending column order, so the result equals the CSR
@@ -1811,6 +1830,28 @@ __global__ __launch_bounds__(kWG) void k_csr_check(CsrOp op, int32_t n, int64_t 
     }
   }
   if (bad) atomicOr(flag, 1);
+}
+
+// flag := 1 if some stored column lies outside int16 range of its row's 64-row
+// block start (the compact index copy cannot hold it).
+__global__ __launch_bounds__(kWG) void k_c16_check(CsrOp op, int32_t n, int32_t* flag) {
+  const int32_t row = blockIdx.x * kWG + threadIdx.x;
+  if (row >= n) return;
+  const int32_t base = row & ~63, e = op.rp[row + 1];
+  bool bad = false;
+  for (int32_t k = op.rp[row]; k < e; ++k) {
+    const int32_t d = op.ci[k] - base;
+    if (d < -32768 || d > 32767) bad = true;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+// c16[k] := col_k - (row_k & ~63), one row per thread.
+__global__ __launch_bounds__(kWG) void k_c16_fill(CsrOp op, int32_t n, int16_t* __restrict__ c16) {
+  const int32_t row = blockIdx.x * kWG + threadIdx.x;
+  if (row >= n) return;
+  const int32_t base = row & ~63, e = op.rp[row + 1];
+  for (int32_t k = op.rp[row]; k < e; ++k) c16[k] = (int16_t)(op.ci[k] - base);
 }
 
 // ===========================================================================

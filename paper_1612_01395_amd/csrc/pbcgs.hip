@@ -84,6 +84,9 @@ struct pbcgs_op_s {
   int32_t* own_rp = nullptr;
   int32_t* own_ci = nullptr;
   double* own_va = nullptr;
+  // compact int16 column indices (offsets from the row's 64-row block start),
+  // made at creation when every offset fits; owned by the operator
+  int16_t* c16 = nullptr;
 };
 
 namespace {
@@ -161,6 +164,8 @@ bool cg_family(int32_t variant) {
 
 // opts.flags bit 2 selects eq. (5) for alpha_{i+1}; eq. (3) otherwise.
 int32_t alpha_form(const pbcgs_opts& o) { return (o.flags & 4) ? 5 : 3; }
+// opts.flags bit 3 keeps a solve on the caller's int32 column indices.
+bool compact_ok(const pbcgs_opts& o) { return (o.flags & 8) == 0; }
 
 Args base_args(pbcgs_ctx_t ctx, const Shape& sh) {
   Args a;
@@ -229,12 +234,13 @@ int ensure_a32(pbcgs_ctx_t ctx, size_t floats) {
 }
 
 // The binary32 twin of an operator: values rounded once.
-CsrOp32 to_binary32(pbcgs_ctx_t ctx, const CsrOp& op, int64_t nnz) {
+template <class I>
+CsrOpT<float, I> to_binary32(pbcgs_ctx_t ctx, const CsrOpT<double, I>& op, int64_t nnz) {
   if (nnz > 0) {
     const int g = (int)std::min<int64_t>((nnz + kWG - 1) / kWG, 8192);
     k_round_vals<<<g, kWG, 0, ctx->stream>>>(nnz, op.va, ctx->a32);
   }
-  return CsrOp32{op.rp, op.ci, ctx->a32, op.n};
+  return CsrOpT<float, I>{op.rp, op.ci, ctx->a32, op.n};
 }
 template <int NPTS>
 StencilOp<NPTS, float> to_binary32(pbcgs_ctx_t, const StencilOp<NPTS, double>& op, int64_t) {
@@ -772,9 +778,14 @@ struct Driver {
   }
 };
 
+// f(op) with the operator's device form: for CSR the compact int16 columns
+// when the operator holds them and `compact` allows, else the int32 ones.
 template <class F>
-int with_op(pbcgs_op_t A, F f) {
-  if (A->kind == OP_CSR) return f(CsrOp{A->rp, A->ci, A->va, A->n});
+int with_op(pbcgs_op_t A, F f, bool compact = true) {
+  if (A->kind == OP_CSR) {
+    if (compact && A->c16) return f(CsrOp16{A->rp, A->c16, A->va, A->n});
+    return f(CsrOp{A->rp, A->ci, A->va, A->n});
+  }
   if (A->kind == OP_ST7) {
     StencilOp<7> s;
     std::memset(&s, 0, sizeof s);
@@ -1122,6 +1133,38 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
   return PBCGS_SUCCESS;
 }
 
+namespace {
+// Makes the compact int16 column copy of a validated CSR operator when every
+// column fits in int16 around its row's 64-row block start.  It only changes
+// how the columns are read, never a result, so an operator that does not fit
+// (or a failed allocation) keeps the int32 columns and no error is raised.
+int make_compact(pbcgs_ctx_t ctx, pbcgs_op_t A) {
+  if (A->nnz == 0) return PBCGS_SUCCESS;
+  const CsrOp op{A->rp, A->ci, A->va, A->n};
+  int rc = reset_flag(ctx);
+  if (rc != PBCGS_SUCCESS) return rc;
+  const int g = (A->n + kWG - 1) / kWG;
+  k_c16_check<<<g, kWG, 0, ctx->stream>>>(op, A->n, ctx->flag);
+  int32_t flag = 0;
+  rc = read_flag(ctx, &flag);
+  if (rc != PBCGS_SUCCESS) return rc;
+  if (flag) return PBCGS_SUCCESS;
+  int16_t* c16 = nullptr;
+  if (hipMalloc((void**)&c16, sizeof(int16_t) * (size_t)A->nnz) != hipSuccess) {
+    (void)hipGetLastError();
+    return PBCGS_SUCCESS;
+  }
+  k_c16_fill<<<g, kWG, 0, ctx->stream>>>(op, A->n, c16);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    (void)hipFree(c16);
+    return fail(ctx, PBCGS_ERR_HIP, std::string("compact column copy: ") + hipGetErrorString(e));
+  }
+  A->c16 = c16;
+  return PBCGS_SUCCESS;
+}
+}  // namespace
+
 int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
                  const double* val, pbcgs_op_t* out) {
   if (!ctx || !out) return fail(ctx, PBCGS_ERR_INVALID_ARG, "ctx or out is NULL");
@@ -1149,6 +1192,11 @@ int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr
   A->rp = row_ptr;
   A->ci = col_idx;
   A->va = val;
+  rc = make_compact(ctx, A);
+  if (rc != PBCGS_SUCCESS) {
+    delete A;
+    return rc;
+  }
   *out = A;
   return PBCGS_SUCCESS;
 }
@@ -1189,6 +1237,7 @@ int pbcgs_op_destroy(pbcgs_op_t op) {
     if (op->own_rp) (void)hipFree(op->own_rp);
     if (op->own_ci) (void)hipFree(op->own_ci);
     if (op->own_va) (void)hipFree(op->own_va);
+    if (op->c16) (void)hipFree(op->c16);
   }
   delete op;
   return PBCGS_SUCCESS;
@@ -1197,6 +1246,12 @@ int pbcgs_op_destroy(pbcgs_op_t op) {
 int64_t pbcgs_op_rows(pbcgs_op_t op) {
   if (!op) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "op is NULL");
   return op->n;
+}
+
+int pbcgs_op_index_bytes(pbcgs_op_t op) {
+  if (!op) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "op is NULL");
+  if (op->kind != OP_CSR) return 0;
+  return op->c16 ? 2 : 4;
 }
 
 int pbcgs_spmv(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* x, double* y) {
@@ -1369,11 +1424,12 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
       using Op = decltype(op);
       Op op64 = op;
       if (folded) {
-        if constexpr (std::is_same<Op, CsrOp>::value) {
+        if constexpr (IsCsr<Op>::value) {
           const int fg = (int)std::min<int64_t>((A->nnz + kWG - 1) / kWG, 8192);
+          const CsrOp op32i{A->rp, A->ci, A->va, A->n};  // the fold reads each entry's int32 column
           if (A->nnz > 0) {
-            if (pc == PC_VEC) k_fold_csr<PC_VEC><<<fg, kWG, 0, ctx->stream>>>(op, A->nnz, ctx->ahat, dv, ds);
-            else k_fold_csr<PC_SCALAR><<<fg, kWG, 0, ctx->stream>>>(op, A->nnz, ctx->ahat, dv, ds);
+            if (pc == PC_VEC) k_fold_csr<PC_VEC><<<fg, kWG, 0, ctx->stream>>>(op32i, A->nnz, ctx->ahat, dv, ds);
+            else k_fold_csr<PC_SCALAR><<<fg, kWG, 0, ctx->stream>>>(op32i, A->nnz, ctx->ahat, dv, ds);
           }
           op64.va = ctx->ahat;
         } else {
@@ -1394,7 +1450,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
       const int rc2 = true_relres(ctx, op, a, drv.rho0, &info->relres_true);
       if (rc2 != PBCGS_SUCCESS) return rc2;
       return st;
-    });
+    }, compact_ok(o));
   }
 
   if (folded) {
@@ -1411,11 +1467,12 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     return with_op(A, [&](auto op) -> int {
       using Op = decltype(op);
       Op fop = op;
-      if constexpr (std::is_same<Op, CsrOp>::value) {
+      if constexpr (IsCsr<Op>::value) {
         const int fg = (int)std::min<int64_t>((A->nnz + kWG - 1) / kWG, 8192);
+        const CsrOp op32i{A->rp, A->ci, A->va, A->n};  // the fold reads each entry's int32 column
         if (A->nnz > 0) {
-          if (pc == PC_VEC) k_fold_csr<PC_VEC><<<fg, kWG, 0, ctx->stream>>>(op, A->nnz, ctx->ahat, dv, ds);
-          else k_fold_csr<PC_SCALAR><<<fg, kWG, 0, ctx->stream>>>(op, A->nnz, ctx->ahat, dv, ds);
+          if (pc == PC_VEC) k_fold_csr<PC_VEC><<<fg, kWG, 0, ctx->stream>>>(op32i, A->nnz, ctx->ahat, dv, ds);
+          else k_fold_csr<PC_SCALAR><<<fg, kWG, 0, ctx->stream>>>(op32i, A->nnz, ctx->ahat, dv, ds);
         }
         fop.va = ctx->ahat;
       } else {
@@ -1434,7 +1491,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
       const int rc2 = true_relres(ctx, op, a, drv.rho0, &info->relres_true);
       if (rc2 != PBCGS_SUCCESS) return rc2;
       return st;
-    });
+    }, compact_ok(o));
   }
 
   return with_op(A, [&](auto op) -> int {
@@ -1442,7 +1499,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     if (pc == PC_NONE) return Driver<Op, PC_NONE>(ctx, op, a, o).run(info);
     if (pc == PC_VEC) return Driver<Op, PC_VEC>(ctx, op, a, o).run(info);
     return Driver<Op, PC_SCALAR>(ctx, op, a, o).run(info);
-  });
+  }, compact_ok(o));
 }
 
 // Transpose of a CSR operator (see include/pbcgs.h).
@@ -1522,6 +1579,11 @@ int pbcgs_op_transpose(pbcgs_ctx_t ctx, pbcgs_op_t A, pbcgs_op_t* out) {
   T->rp = T->own_rp = rp_t;
   T->ci = T->own_ci = ci_t;
   T->va = T->own_va = va_t;
+  const int rc2 = make_compact(ctx, T);
+  if (rc2 != PBCGS_SUCCESS) {
+    (void)pbcgs_op_destroy(T);
+    return rc2;
+  }
   *out = T;
   return PBCGS_SUCCESS;
 }

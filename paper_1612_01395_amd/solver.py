@@ -106,6 +106,12 @@ class Operator:
         self._keep = keep  # the borrowed device arrays stay alive with the operator
         self.kind = kind
 
+    @property
+    def index_bytes(self) -> int:
+        """Bytes per column index the solves read: 2 (compact int16 copy), 4
+        (int32 columns) or 0 (stencil)."""
+        return L.check(L.lib().pbcgs_op_index_bytes(self.handle), self.ctx.handle)
+
     def close(self):
         if getattr(self, "handle", None):
             L.lib().pbcgs_op_destroy(self.handle)
@@ -230,11 +236,12 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
           precond: str | None = None, dinv: torch.Tensor | None = None, tol: float = 1e-8, maxit: int = 2000,
           rr_period: int = 50, rr_max: int = -1, history: bool = False, check_every: int = 0,
           graph: bool = True, time_kernels: bool = False, out: torch.Tensor | None = None,
-          precision: str = "fp64", alpha_form: int = 3):
+          precision: str = "fp64", alpha_form: int = 3, index32: bool = False):
     """Solve A x = b; returns (x, SolveInfo).  x0 defaults to zero; ``out``
     (optional) receives the iterate in place of a new tensor.  ``alpha_form``
     5 takes alpha_{i+1} of the pipelined variants from eq. (5) instead of
-    eq. (3) (Section 3.1)."""
+    eq. (3) (Section 3.1).  ``index32`` reads the int32 column indices even
+    where the operator holds its compact int16 copy (same result)."""
     _check_vec(b, A.n, "b")
     _check_alpha_form(alpha_form)
     if variant not in VARIANTS:
@@ -266,7 +273,7 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
     o.rr_max = int(rr_max)
     o.check_every = int(check_every)
     o.flags = ((0 if graph else L.FLAG_DIRECT) | (L.FLAG_TIME_KERNELS if time_kernels else 0)
-               | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0))
+               | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0) | (L.FLAG_INDEX32 if index32 else 0))
     o.history = hist.data_ptr() if hist is not None else None
     info = L.Info()
     L.check(L.lib().pbcgs_solve(A.ctx.handle, A.handle, _ptr(b), _ptr(x), _ptr(dinv), ctypes.byref(o),

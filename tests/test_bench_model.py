@@ -22,6 +22,16 @@ def test_fused_kernel_bytes_at_128():
     assert bench.algorithmic_bytes(N, NNZ, "pbicgstab", True)[2] == 22 * VEC  # stencil: no operator bytes
 
 
+def test_compact_column_bytes_at_128():
+    """With the int16 column copy each non-zero costs 10 bytes instead of 12."""
+    mat16 = 4 * (N + 1) + 10 * NNZ
+    ka, kb, it = bench.algorithmic_bytes(N, NNZ, "pbicgstab", False, index_bytes=2)
+    assert (ka, kb) == (mat16 + 10 * VEC, mat16 + 12 * VEC) == (321978372, 355532804)
+    assert it == 2 * mat16 + 22 * VEC
+    assert bench.algorithmic_bytes(N, NNZ, "pbicgstab", True, index_bytes=2)[2] == 22 * VEC
+    assert bench.algorithmic_bytes_cg(N, NNZ, "pipe_cg", True, 2) == mat16 + 18 * VEC
+
+
 def test_cg_family_bytes():
     for variant, passes in (("cg", 12), ("cgcg", 14), ("pipe_cg", 18)):
         assert bench.algorithmic_bytes_cg(N, NNZ, variant, True) == MAT + passes * VEC
@@ -45,6 +55,9 @@ def test_recorded_traffic_matches_the_sources():
         t = json.load(f)
     if t["source_hash"] != bench.kernel_source_hash():
         pytest.skip("kernel sources changed since the HBM counters were taken")
+    ib = t["column_index_bytes"]
     for k in ("k_pa", "k_pb"):
         got = bench.measured_traffic(k)
-        assert got is not None and got > bench.algorithmic_bytes(N, NNZ, "pbicgstab", False)[0 if k == "k_pa" else 1]
+        algo = bench.algorithmic_bytes(N, NNZ, "pbicgstab", False, index_bytes=ib)[0 if k == "k_pa" else 1]
+        # at least the algorithmic bytes, and no more than 10 % above them
+        assert got is not None and algo < got < 1.10 * algo, (k, got, algo)

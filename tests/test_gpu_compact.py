@@ -1,0 +1,171 @@
+"""GPU parity of the compact int16 column copy of a CSR operator.
+
+The copy changes only how a product finds its columns (each stored as the
+offset from the first row of its row's 64-row block), never the arithmetic:
+every solve and product must equal the oracle bit for bit whether the kernels
+read the compact copy or the caller's int32 columns (solve flag ``index32``).
+The edge matrices put columns exactly at the int16 limits -32768 and +32767
+around their block start, and one past them (then the operator keeps int32).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1612_01395_amd import inputs, solver
+from gpu_util import csr_op, dev_t, host, require_gpu, same, say
+
+pytestmark = pytest.mark.gpu
+
+ALG = {"bicgstab": oracle.ALG_BICGSTAB, "pbicgstab": oracle.ALG_PBICGSTAB, "pbicgstab_rr": oracle.ALG_PBICGSTAB_RR,
+       "ca_bicgstab": oracle.ALG_CA_BICGSTAB, "cg": oracle.ALG_CG, "cgcg": oracle.ALG_CGCG,
+       "pipe_cg": oracle.ALG_PIPE_CG}
+
+
+def edge_matrix(n, fits, seed=7):
+    """Unsymmetric, diagonally dominant: 4 on the diagonal, -1 - U[0, 0.2) at
+    i +- 1, and far entries U[0.01, 0.1) at base - 32768 and base + 32767
+    (base = i & ~63) in every 97th row where they exist; with fits False one
+    row also holds base + 32768, which int16 offsets cannot reach."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    far_row = None
+    for i in range(n):
+        base = i & ~63
+        ent = {i: 4.0}
+        if i > 0:
+            ent[i - 1] = -1.0 - 0.2 * rng.random()
+        if i < n - 1:
+            ent[i + 1] = -1.0 - 0.2 * rng.random()
+        if i % 97 == 5:
+            for j in (base - 32768, base + 32767):
+                if 0 <= j < n and j not in ent:
+                    ent[j] = 0.01 + 0.09 * rng.random()
+        if not fits and far_row is None and base + 32768 < n and i % 64 == 3:
+            ent[base + 32768] = 0.05
+            far_row = i
+        for j in sorted(ent):
+            rows.append(i)
+            cols.append(j)
+            vals.append(ent[j])
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, np.asarray(rows) + 1, 1)
+    return oracle.CSR(np.cumsum(rp), np.asarray(cols), np.asarray(vals))
+
+
+def _cases():
+    return {
+        "edge_fit": edge_matrix(70001, True),     # 70001 = 1093 * 64 + 49: ragged last block
+        "edge_nofit": edge_matrix(70001, False),
+        "c2_24": oracle.assemble_workload(inputs.workload("c2", n=24)),
+        "c2s_24": oracle.assemble_workload(inputs.workload("c2s", n=24)),
+    }
+
+
+CASES = _cases()
+
+
+def test_edge_matrices_reach_the_limits():
+    """The fitting matrix holds offsets -32768 and +32767 exactly; the other
+    one offset +32768 (host check of the test inputs themselves)."""
+    for name, lo, hi in (("edge_fit", -32768, 32767), ("edge_nofit", -32768, 32768)):
+        A = CASES[name]
+        rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+        off = A.col.astype(np.int64) - (rows & ~63)
+        assert off.min() == lo and off.max() == hi, (name, off.min(), off.max())
+
+
+def test_index_bytes():
+    require_gpu()
+    assert csr_op(CASES["edge_fit"]).index_bytes == 2
+    assert csr_op(CASES["edge_nofit"]).index_bytes == 4
+    assert csr_op(CASES["c2_24"]).index_bytes == 2
+    assert solver.stencil(8, 8, 8, [-1, -1, -1, 6, -1, -1, -1]).index_bytes == 0
+    assert solver.transpose(csr_op(CASES["c2_24"])).index_bytes == 2
+
+
+@pytest.mark.parametrize("name", ["edge_fit", "edge_nofit", "c2_24"])
+def test_spmv_bitwise(name):
+    require_gpu()
+    A = CASES[name]
+    x = inputs.random_vector(A.n, 11)
+    y = host(solver.spmv(csr_op(A), dev_t(x)))
+    assert same(y, oracle.spmv(A, x)), float(np.abs(y - oracle.spmv(A, x)).max())
+
+
+def _solve_both(A, variant, precond, tol, maxit, rr=20, precision="fp64"):
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    op = csr_op(A)
+    out = []
+    for index32 in (False, True):
+        say(f"compact: n={A.n} {variant} precond={precond} precision={precision} index32={index32}")
+        x, info = solver.solve(op, dev_t(b), variant=variant, precond=precond, tol=tol, maxit=maxit,
+                               rr_period=rr, history=True, precision=precision, index32=index32)
+        out.append((host(x), info))
+    return b, out
+
+
+def _oracle(A, b, variant, precond, tol, maxit, rr=20):
+    dv = oracle.jacobi_dinv(A) if precond else None
+    solve = oracle.solve_folded if precond == "jacobi_folded" else oracle.solve
+    return solve(A, b, algo=ALG[variant], dinv=dv, tol=tol, maxit=maxit, rr_period=rr, history=True)
+
+
+def _check(out, x_or, i_or):
+    for x, info in out:
+        assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"]), (info, i_or)
+        assert same(x, x_or), float(np.abs(x - x_or).max())
+        assert same(host(info.history), i_or["history"])
+        assert same([info.relres_rec, info.relres_true], [i_or["relres_rec"], i_or["relres_true"]])
+
+
+@pytest.mark.parametrize("variant,precond", [
+    ("bicgstab", None), ("bicgstab", "jacobi"), ("bicgstab", "jacobi_folded"),
+    ("pbicgstab", None), ("pbicgstab_rr", "jacobi"), ("pbicgstab_rr", "jacobi_folded"),
+    ("ca_bicgstab", None), ("ca_bicgstab", "jacobi_folded")])
+@pytest.mark.parametrize("name", ["edge_fit", "c2_24"])
+def test_solve_bitwise_both_index_forms(name, variant, precond):
+    require_gpu()
+    A = CASES[name]
+    b, out = _solve_both(A, variant, precond, 1e-10, 400)
+    x_or, i_or = _oracle(A, b, variant, precond, 1e-10, 400)
+    _check(out, x_or, i_or)
+    assert out[0][1].status == 0
+
+
+@pytest.mark.parametrize("variant", ["cg", "cgcg", "pipe_cg"])
+def test_cg_family_bitwise_both_index_forms(variant):
+    require_gpu()
+    A = CASES["c2s_24"]
+    b, out = _solve_both(A, variant, "jacobi", 1e-10, 400)
+    x_or, i_or = _oracle(A, b, variant, "jacobi", 1e-10, 400)
+    _check(out, x_or, i_or)
+
+
+@pytest.mark.parametrize("name", ["edge_fit", "c2_24"])
+def test_precision_form_bitwise_both_index_forms(name):
+    require_gpu()
+    A = CASES[name]
+    b, out = _solve_both(A, "pbicgstab_rr", "jacobi_folded", 1e-10, 800, precision="fp32_rr64")
+    x_or, i_or = oracle.solve_mp(A, b, dinv=oracle.jacobi_dinv(A), tol=1e-10, maxit=800, rr_period=20,
+                                 history=True)
+    _check(out, x_or, i_or)
+
+
+def test_values_may_change_between_solves():
+    """The compact copy holds only columns: new values in val are used."""
+    require_gpu()
+    A = CASES["edge_fit"]
+    rp, col, val = dev_t(A.row_ptr), dev_t(A.col), dev_t(A.val)
+    op = solver.csr(rp, col, val)
+    assert op.index_bytes == 2
+    A2 = oracle.CSR(A.row_ptr, A.col, A.val * 1.5)
+    val.mul_(1.5)
+    torch.cuda.synchronize()
+    b = oracle.spmv(A2, inputs.x_true(A.n))
+    x, info = solver.solve(op, dev_t(b), variant="pbicgstab_rr", precond="jacobi_folded", tol=1e-10, maxit=400,
+                           rr_period=20)
+    x_or, i_or = oracle.solve_folded(A2, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=oracle.jacobi_dinv(A2), tol=1e-10,
+                                     maxit=400, rr_period=20)
+    assert info.iters == i_or["iters"] and same(host(x), x_or)
