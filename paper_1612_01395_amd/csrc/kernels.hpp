@@ -90,6 +90,14 @@ struct CsrOpT {
     if constexpr (sizeof(I) == sizeof(int32_t)) return (int32_t)c;
     else return base + (int32_t)c;
   }
+  // a staged column inside [0, n): a round may begin one non-zero before the
+  // block (the last one of the previous row); an int16 offset of it is decoded
+  // against this block's start.  Its product's slot is never read; the clamp
+  // only keeps its gather in bounds (int32 columns are valid as they are).
+  __device__ __forceinline__ int32_t staged_col(int32_t c) const {
+    if constexpr (sizeof(I) == sizeof(int32_t)) return c;
+    else return min(max(c, 0), n - 1);
+  }
 
   // Row `row` of A x, computed by the whole wave for its 64-row block (all 64
   // lanes call it; lanes with valid == false return 0).  The block's
@@ -98,35 +106,68 @@ struct CsrOpT {
   // (CSR-stream); each lane then adds its own row's products in stored order,
   // starting from 0.0 -- the same operations as a row-by-row loop.  V is the
   // arithmetic type of the product; x (type X) is widened to it first.
+  //
+  // Each lane loads two neighbouring non-zeros at once (a pair of values and
+  // of columns; rounds start at an even non-zero), halving the load
+  // instructions.  A pair that starts at a round's last non-zero also reads
+  // the next one, which at the very end of an odd-length matrix would be past
+  // nnz: that one round (a wave-uniform test) loads one non-zero per lane.
   template <class X>
   __device__ __forceinline__ V spmv(int32_t row, bool valid, const X* __restrict__ x) const {
     __shared__ V stage[4][kStage];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t b0 = __builtin_amdgcn_readfirstlane(row);  // lane 0: first row of the block
-    const int32_t rc = min(row, n - 1);  // clamped: the four loads issue together
+    const int32_t rc = min(row, n - 1);  // clamped: the loads issue together
     const int32_t rlo = rp[b0];
     const int32_t rhi = rp[min(b0 + 64, n)];
+    const int32_t nnz = rp[n];
     const int32_t rb0 = rp[rc], re0 = rp[rc + 1];
     const int32_t rb = valid ? rb0 : rhi;
     const int32_t re = valid ? re0 : rhi;
     V acc = V(0);
-    for (int32_t c0 = rlo; c0 < rhi; c0 += kStage) {
+    for (int32_t c0 = rlo & ~1; c0 < rhi; c0 += kStage) {
       const int32_t c1 = min(c0 + kStage, rhi);
       // branch-free: indices past the chunk are clamped into it (their
       // products land in slots that are never read), so all loads issue at once
       // The matrix is streamed once per product: its loads are non-temporal
       // so that they do not evict the Krylov vectors, which the next kernel
       // reads again, from L2 and the Infinity Cache.
-      int32_t cc[kStage / 64];
-      V vv[kStage / 64];
+      if (!(c1 == nnz && (c1 & 1))) {
+        const int32_t pmax = (c1 - 1) & ~1;  // the last pair start of the round
+        int32_t ca[kStage / 128], cb[kStage / 128];
+        V va0[kStage / 128], va1[kStage / 128];
 #pragma unroll
-      for (int u = 0; u < kStage / 64; ++u) {
-        const int32_t k = min(c0 + u * 64 + lane, c1 - 1);
-        cc[u] = col(__builtin_nontemporal_load(&ci[k]), b0);
-        vv[u] = __builtin_nontemporal_load(&va[k]);
+        for (int u = 0; u < kStage / 128; ++u) {
+          const int32_t k = min(c0 + 2 * (u * 64 + lane), pmax);
+          if constexpr (sizeof(I) == 2) {
+            // one 32-bit word: the low half is non-zero k, the high half k + 1
+            const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(ci) + (k >> 1));
+            ca[u] = col((I)(w & 0xffffu), b0);
+            cb[u] = col((I)(w >> 16), b0);
+          } else {
+            ca[u] = __builtin_nontemporal_load(&ci[k]);
+            cb[u] = __builtin_nontemporal_load(&ci[k + 1]);
+          }
+          va0[u] = __builtin_nontemporal_load(&va[k]);
+          va1[u] = __builtin_nontemporal_load(&va[k + 1]);
+        }
+#pragma unroll
+        for (int u = 0; u < kStage / 128; ++u) {
+          stage[wave][2 * (u * 64 + lane)] = va0[u] * V(x[staged_col(ca[u])]);
+          stage[wave][2 * (u * 64 + lane) + 1] = va1[u] * V(x[staged_col(cb[u])]);
+        }
+      } else {
+        int32_t cc[kStage / 64];
+        V vv[kStage / 64];
+#pragma unroll
+        for (int u = 0; u < kStage / 64; ++u) {
+          const int32_t k = min(c0 + u * 64 + lane, c1 - 1);
+          cc[u] = staged_col(col(__builtin_nontemporal_load(&ci[k]), b0));
+          vv[u] = __builtin_nontemporal_load(&va[k]);
+        }
+#pragma unroll
+        for (int u = 0; u < kStage / 64; ++u) stage[wave][u * 64 + lane] = vv[u] * V(x[cc[u]]);
       }
-#pragma unroll
-      for (int u = 0; u < kStage / 64; ++u) stage[wave][u * 64 + lane] = vv[u] * V(x[cc[u]]);
       __builtin_amdgcn_wave_barrier();
       const int32_t kb = max(rb, c0), ke = min(re, c1);
       for (int32_t k = kb; k < ke; ++k) acc = acc + stage[wave][k - c0];

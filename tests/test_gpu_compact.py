@@ -169,3 +169,45 @@ def test_values_may_change_between_solves():
     x_or, i_or = oracle.solve_folded(A2, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=oracle.jacobi_dinv(A2), tol=1e-10,
                                      maxit=400, rr_period=20)
     assert info.iters == i_or["iters"] and same(host(x), x_or)
+
+
+def tail_matrix(n, odd_nnz, empty_tail, seed):
+    """Banded random matrix (0 to 5 entries per row within +-40 of the
+    diagonal, whole empty 64-row blocks in the middle, the last `empty_tail`
+    rows empty) with nnz of the requested parity: exercises the pair loads'
+    odd starts, empty blocks and the end of the non-zero array."""
+    rng = np.random.default_rng([seed, n, int(odd_nnz), empty_tail])
+    rows, cols = [], []
+    for i in range(n - empty_tail):
+        if (i // 64) % 7 == 3:
+            continue  # an empty block
+        cnt = int(rng.integers(0, 6))
+        lo, hi = max(0, i - 40), min(n, i + 41)
+        for j in sorted(rng.choice(np.arange(lo, hi), size=min(cnt, hi - lo), replace=False)):
+            rows.append(i)
+            cols.append(int(j))
+    if (len(cols) % 2 == 1) != odd_nnz:
+        rows.pop(0)
+        cols.pop(0)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, np.asarray(rows, dtype=np.int64) + 1, 1)
+    vals = rng.uniform(-1.0, 1.0, len(cols))
+    return oracle.CSR(np.cumsum(rp), np.asarray(cols), vals)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 5001])
+@pytest.mark.parametrize("odd_nnz", [False, True])
+@pytest.mark.parametrize("empty_tail", [0, 70])
+def test_spmv_pair_loads_at_the_edges(n, odd_nnz, empty_tail):
+    require_gpu()
+    empty_tail = min(empty_tail, n - 1)
+    A = tail_matrix(n, odd_nnz, empty_tail, 5)
+    if A.nnz == 0:
+        pytest.skip("no non-zeros at this size")
+    assert (A.nnz % 2 == 1) == odd_nnz
+    say(f"pair loads: n={n} nnz={A.nnz} empty_tail={empty_tail}")
+    op = csr_op(A)
+    assert op.index_bytes == 2
+    x = inputs.random_vector(A.n, 13)
+    y = host(solver.spmv(op, dev_t(x)))
+    assert same(y, oracle.spmv(A, x))
