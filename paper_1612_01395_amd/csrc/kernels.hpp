@@ -82,6 +82,9 @@ struct CsrOpT {
   const I* __restrict__ ci;
   const V* __restrict__ va;
   int32_t n;
+  // explicit, always 0: the driver keys its cached graphs on the operator's
+  // bytes, which must then hold no indeterminate padding
+  int32_t pad_ = 0;
 
   static constexpr int kStage = 512;  // staged non-zeros per wave and round
 

@@ -778,6 +778,16 @@ struct Driver {
   }
 };
 
+// Graph keys hold the bytes of the operator and argument structs, so these
+// structs must have no padding (whose contents would be indeterminate).
+static_assert(sizeof(CsrOp) == 3 * sizeof(void*) + 2 * sizeof(int32_t), "CsrOp padding");
+static_assert(sizeof(CsrOp16) == sizeof(CsrOp) && sizeof(CsrOp32) == sizeof(CsrOp) &&
+              sizeof(CsrOp16f) == sizeof(CsrOp), "CsrOpT padding");
+static_assert(sizeof(StencilOp<7>) == 4 * sizeof(int32_t) + 7 * sizeof(double), "StencilOp padding");
+static_assert(sizeof(StencilOp<5>) == 4 * sizeof(int32_t) + 5 * sizeof(double), "StencilOp padding");
+static_assert(sizeof(StencilOp<7, float>) == 4 * sizeof(int32_t) + 7 * sizeof(float), "StencilOp padding");
+static_assert(sizeof(StencilOp<5, float>) == 4 * sizeof(int32_t) + 5 * sizeof(float), "StencilOp padding");
+
 // f(op) with the operator's device form: for CSR the compact int16 columns
 // when the operator holds them and `compact` allows, else the int32 ones.
 template <class F>
