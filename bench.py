@@ -497,8 +497,11 @@ def main():
             torch.cuda.synchronize()
             dtb = (time.perf_counter() - t0) / reps
             its = [i.iters for i in infs]
-            byts = sum(it_ * (passes * 8 * Nk + 2 * (4 * (Nk + 1) + 12 * zk)) for it_, Nk, zk in zip(its, bN, bnnz))
-            return {"ms_per_batch_solve": round(dtb * 1e3, 2), "iters_total": int(sum(its)),
+            # the batch reads int16 columns when every operator holds them
+            ibb = 2 if all(op.index_bytes == 2 for op in ops_) else 4
+            byts = sum(it_ * (passes * 8 * Nk + 2 * (4 * (Nk + 1) + (8 + ibb) * zk))
+                       for it_, Nk, zk in zip(its, bN, bnnz))
+            return {"ms_per_batch_solve": round(dtb * 1e3, 2), "column_index_bytes": ibb, "iters_total": int(sum(its)),
                     "iters_max": int(max(its)), "iters_per_s_aggregate": round(sum(its) / dtb, 1),
                     "gbps_effective": round(byts / dtb / 1e9, 1),
                     "all_converged": all(i.status == 0 for i in infs),

@@ -253,7 +253,10 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
  * launches at once.  Reductions are the same pairwise trees as in
  * pbcgs_solve, so each system's result equals that of its own pbcgs_solve
  * bit for bit.  BiCGStab and p-BiCGStab (with or without replacement) only,
- * no preconditioner, binary64, no history (ERR_UNSUPPORTED otherwise).  The context keeps the batch workspace (8 vectors per system).
+ * no preconditioner, binary64, no history (ERR_UNSUPPORTED otherwise).  The
+ * batch reads the compact int16 columns when every operator holds them (see
+ * pbcgs_op_csr) and opts.flags bit 3 is clear, else every system's int32
+ * columns.  The context keeps the batch workspace (8 vectors per system).
  * Returns the largest numerical status of the systems, or a negative error.
  */
 int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const double* const* b,

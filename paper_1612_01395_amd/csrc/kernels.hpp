@@ -1909,6 +1909,7 @@ __global__ __launch_bounds__(kWG) void k_c16_fill(CsrOp op, int32_t n, int16_t* 
 struct SysDesc {
   const int32_t* rp;
   const int32_t* ci;
+  const int16_t* c16;  // the operator's compact columns (read by CsrOp16 launches only)
   const double* va;
   double* ws;        // 8 vectors of np doubles
   double* x;
@@ -1921,9 +1922,10 @@ struct SysDesc {
 // Per-system arguments from the launch template: rows, shape, state slots
 // (template field par), partial-sum rows (offset to the system's workgroups)
 // and the vector layout of p-BiCGStab (PIPE) or BiCGStab.
-template <bool PIPE>
-__device__ __forceinline__ void bind_sys(const SysDesc& d, Args& a, CsrOp& op) {
-  op = CsrOp{d.rp, d.ci, d.va, d.n};
+template <bool PIPE, class Op>
+__device__ __forceinline__ void bind_sys(const SysDesc& d, Args& a, Op& op) {
+  if constexpr (std::is_same<Op, CsrOp16>::value) op = Op{d.rp, d.c16, d.va, d.n};
+  else op = Op{d.rp, d.ci, d.va, d.n};
   a.n = d.n;
   a.G = d.G;
   a.R = d.R;
@@ -1948,58 +1950,72 @@ __device__ __forceinline__ void bind_sys(const SysDesc& d, Args& a, CsrOp& op) {
   }
 }
 
+// Op: CsrOp (int32 columns) or CsrOp16 (every system's compact columns)
 #define PBCGS_BIND_WG(PIPE)                        \
   const SysDesc d_ = sys[map[blockIdx.x]];         \
   a.wg = (int32_t)blockIdx.x - d_.wg0;             \
-  CsrOp op;                                        \
+  Op op;                                           \
   bind_sys<PIPE>(d_, a, op);
 
-template <bool PIPE>
+template <class Op, bool PIPE>
 __global__ __launch_bounds__(kWG) void kb_setup_r0(const SysDesc* sys, const int32_t* map, Args a) {
-  PBCGS_BIND_WG(PIPE) d_setup_r0<CsrOp, PC_NONE, PIPE>(op, a);
+  PBCGS_BIND_WG(PIPE) d_setup_r0<Op, PC_NONE, PIPE>(op, a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_setup_w0(const SysDesc* sys, const int32_t* map, Args a) {
-  PBCGS_BIND_WG(true) d_setup_w0<CsrOp, PC_NONE>(op, a);
+  PBCGS_BIND_WG(true) d_setup_w0<Op, PC_NONE>(op, a);
 }
-template <bool RR2>
+template <class Op, bool RR2>
 __global__ __launch_bounds__(kWG) void kb_pa(const SysDesc* sys, const int32_t* map, Args a) {
-  PBCGS_BIND_WG(true) d_pa<CsrOp, PC_NONE, RR2>(op, a);
+  PBCGS_BIND_WG(true) d_pa<Op, PC_NONE, RR2>(op, a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_pb(const SysDesc* sys, const int32_t* map, Args a) {
-  PBCGS_BIND_WG(true) d_pb<CsrOp, PC_NONE>(op, a);
+  PBCGS_BIND_WG(true) d_pb<Op, PC_NONE>(op, a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_rr_x(const SysDesc* sys, const int32_t* map, Args a) {
   PBCGS_BIND_WG(true) (void)op; d_rr_x<PC_NONE>(a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_rr_r(const SysDesc* sys, const int32_t* map, Args a) {
-  PBCGS_BIND_WG(true) d_rr_r<CsrOp, PC_NONE>(op, a);
+  PBCGS_BIND_WG(true) d_rr_r<Op, PC_NONE>(op, a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_rr_w(const SysDesc* sys, const int32_t* map, Args a) {
-  PBCGS_BIND_WG(true) d_rr_w<CsrOp, PC_NONE>(op, a);
+  PBCGS_BIND_WG(true) d_rr_w<Op, PC_NONE>(op, a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_rr_p(const SysDesc* sys, const int32_t* map, Args a) {
   PBCGS_BIND_WG(true) (void)op; d_rr_p<PC_NONE>(a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_rr_s(const SysDesc* sys, const int32_t* map, Args a) {
-  PBCGS_BIND_WG(true) d_rr_s<CsrOp, PC_NONE>(op, a);
+  PBCGS_BIND_WG(true) d_rr_s<Op, PC_NONE>(op, a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_b1(const SysDesc* sys, const int32_t* map, Args a) {
-  PBCGS_BIND_WG(false) d_b1<CsrOp, PC_NONE>(op, a);
+  PBCGS_BIND_WG(false) d_b1<Op, PC_NONE>(op, a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_b2(const SysDesc* sys, const int32_t* map, Args a) {
   PBCGS_BIND_WG(false) (void)op; d_b2<PC_NONE>(a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_b3(const SysDesc* sys, const int32_t* map, Args a) {
-  PBCGS_BIND_WG(false) d_b3<CsrOp, PC_NONE>(op, a);
+  PBCGS_BIND_WG(false) d_b3<Op, PC_NONE>(op, a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_b4(const SysDesc* sys, const int32_t* map, Args a) {
   PBCGS_BIND_WG(false) (void)op; d_b4<PC_NONE>(a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_b5(const SysDesc* sys, const int32_t* map, Args a) {
   PBCGS_BIND_WG(false) (void)op; d_b5<PC_NONE>(a);
 }
+template <class Op>
 __global__ __launch_bounds__(kWG) void kb_true_res(const SysDesc* sys, const int32_t* map, Args a) {
-  PBCGS_BIND_WG(true) d_true_res<CsrOp>(op, a);
+  PBCGS_BIND_WG(true) d_true_res<Op>(op, a);
 }
 // One workgroup per system: a pending reduction (modes of k_finish).
 template <int MODE, bool PIPE>

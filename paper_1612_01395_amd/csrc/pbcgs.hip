@@ -841,6 +841,8 @@ int grow(pbcgs_ctx_t ctx, T*& p, size_t& cap, size_t count, const char* what) {
 
 // Batched solve of independent CSR systems without a preconditioner: the
 // schedule of Driver, every launch covering all systems (see SysDesc).
+// Op: CsrOp (int32 columns) or CsrOp16 (every system holds compact columns).
+template <class Op>
 struct BatchDriver {
   pbcgs_ctx_t ctx;
   const pbcgs_opts& o;
@@ -871,11 +873,11 @@ struct BatchDriver {
   void setup() {
     hipStream_t s = ctx->stream;
     if (!pipe) {
-      kb_setup_r0<false><<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, L(-1, PB_SETUP1));
+      kb_setup_r0<Op, false><<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, L(-1, PB_SETUP1));
       return;
     }
-    kb_setup_r0<true><<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, L(-1, PB_SETUP1));
-    kb_setup_w0<<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, L(PB_SETUP1, PB_SETUP2));
+    kb_setup_r0<Op, true><<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, L(-1, PB_SETUP1));
+    kb_setup_w0<Op><<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, L(PB_SETUP1, PB_SETUP2));
   }
 
   void iteration(int64_t i) {
@@ -883,26 +885,26 @@ struct BatchDriver {
     const SysDesc* S = ctx->bsys;
     const int32_t* M = ctx->bmap;
     if (!pipe) {
-      kb_b1<<<totalG, kWG, 0, s>>>(S, M, L(PB_SETUP1, PB_B1, i == 0));
-      kb_b2<<<totalG, kWG, 0, s>>>(S, M, L(PB_B1, -1));
-      kb_b3<<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_B3));
-      kb_b4<<<totalG, kWG, 0, s>>>(S, M, L(PB_B3, PB_B4));
-      kb_b5<<<totalG, kWG, 0, s>>>(S, M, L(PB_B4, -1));
+      kb_b1<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_SETUP1, PB_B1, i == 0));
+      kb_b2<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B1, -1));
+      kb_b3<Op><<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_B3));
+      kb_b4<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B3, PB_B4));
+      kb_b5<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B4, -1));
       return;
     }
     if (rr_due(o, i - 1)) {
-      kb_rr_p<<<totalG, kWG, 0, s>>>(S, M, L(PB_B, -1));
-      kb_rr_s<<<totalG, kWG, 0, s>>>(S, M, L(-1, -1));
-      kb_pa<true><<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_A));
+      kb_rr_p<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B, -1));
+      kb_rr_s<Op><<<totalG, kWG, 0, s>>>(S, M, L(-1, -1));
+      kb_pa<Op, true><<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_A));
     } else {
-      kb_pa<false><<<totalG, kWG, 0, s>>>(S, M, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
+      kb_pa<Op, false><<<totalG, kWG, 0, s>>>(S, M, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
     }
     if (rr_due(o, i)) {
-      kb_rr_x<<<totalG, kWG, 0, s>>>(S, M, L(PB_A, -1));
-      kb_rr_r<<<totalG, kWG, 0, s>>>(S, M, L(-1, -1));
-      kb_rr_w<<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_B));
+      kb_rr_x<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_A, -1));
+      kb_rr_r<Op><<<totalG, kWG, 0, s>>>(S, M, L(-1, -1));
+      kb_rr_w<Op><<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_B));
     } else {
-      kb_pb<<<totalG, kWG, 0, s>>>(S, M, L(PB_A, PB_B));
+      kb_pb<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_A, PB_B));
     }
   }
 
@@ -924,8 +926,9 @@ struct BatchDriver {
   std::string key(int64_t i0, int m) const {
     std::string k = "batch|";
     char buf[160];
-    std::snprintf(buf, sizeof buf, "%p|%p|%p|%d|%d|%d|%d|%lld|%d|", (void*)ctx->bsys, (void*)ctx->bmap,
-                  (void*)ctx->bpart, nsys, totalG, o.variant, m, (long long)(q & 1), i0 == 0 ? 1 : 0);
+    std::snprintf(buf, sizeof buf, "%p|%p|%p|%d|%d|%d|%d|%lld|%d|%d|", (void*)ctx->bsys, (void*)ctx->bmap,
+                  (void*)ctx->bpart, nsys, totalG, o.variant, m, (long long)(q & 1), i0 == 0 ? 1 : 0,
+                  std::is_same<Op, CsrOp16>::value ? 2 : 4);
     k += buf;
     for (int j = 0; j < m; ++j) {
       const int64_t i = i0 + j;
@@ -1016,7 +1019,7 @@ struct BatchDriver {
     // true residuals ||b - A x|| of every system, pairwise, via utility slots 2 -> 3
     Args t = tmpl;
     t.pout = part(PB_UTIL);
-    kb_true_res<<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, t);
+    kb_true_res<Op><<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap, t);
     kb_init_state<<<(nsys + 63) / 64, 64, 0, s>>>(ctx->bsys, nsys, 2, 0.0);
     Args f = tmpl;
     f.par = 2;
@@ -1629,6 +1632,7 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
   int gcap = env_int("PBCGS_BATCH_GCAP", ctx->batch_gcap > 0 ? ctx->batch_gcap : 64);
   if (gcap < 1 || gcap > kMaxG) gcap = 64;
   std::vector<SysDesc> desc((size_t)nsys);
+  bool compact = compact_ok(o);  // every system holds compact columns
   int64_t totalG = 0;
   size_t wsneed = 0;
   for (int32_t k = 0; k < nsys; ++k) {
@@ -1645,8 +1649,9 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
     }
     if (G > kMaxG) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "system " + std::to_string(k) + " too large");
     SysDesc& d = desc[(size_t)k];
-    d.rp = op->rp; d.ci = op->ci; d.va = op->va;
+    d.rp = op->rp; d.ci = op->ci; d.c16 = op->c16; d.va = op->va;
     d.x = x[k]; d.b = b[k];
+    compact = compact && op->c16 != nullptr;
     d.np = (int64_t)padded(op->n);
     d.n = op->n; d.G = (int32_t)G; d.R = R;
     totalG += G;
@@ -1699,8 +1704,8 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
   HIP_TRY(ctx, hipMemcpyAsync(ctx->bsys, desc.data(), desc.size() * sizeof(SysDesc), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->bmap, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the host tables may go away after this
-  BatchDriver drv(ctx, o, nsys, (int32_t)totalG);
-  return drv.run(infos);
+  if (compact) return BatchDriver<CsrOp16>(ctx, o, nsys, (int32_t)totalG).run(infos);
+  return BatchDriver<CsrOp>(ctx, o, nsys, (int32_t)totalG).run(infos);
 }
 
 // Autotuner of the launch shape (see include/pbcgs.h).

@@ -287,10 +287,12 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
 
 def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str = "pbicgstab_rr", tol: float = 1e-8,
                   maxit: int = 2000, rr_period: int = 50, rr_max: int = -1, check_every: int = 0, graph: bool = True,
-                  outs: list | None = None, alpha_form: int = 3):
+                  outs: list | None = None, alpha_form: int = 3, index32: bool = False):
     """Solve the independent systems ops[k] x_k = bs[k] in one batched call
     (CSR operators of one context, no preconditioner, binary64).  Returns
-    (xs, infos); each system's result equals its own :func:`solve` bit for bit."""
+    (xs, infos); each system's result equals its own :func:`solve` bit for bit.
+    The batch reads compact int16 columns when every operator holds them and
+    ``index32`` is false."""
     _check_alpha_form(alpha_form)
     nsys = len(ops)
     if nsys == 0 or len(bs) != nsys:
@@ -323,7 +325,8 @@ def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str 
     o.rr_period = int(rr_period)
     o.rr_max = int(rr_max)
     o.check_every = int(check_every)
-    o.flags = (0 if graph else L.FLAG_DIRECT) | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0)
+    o.flags = ((0 if graph else L.FLAG_DIRECT) | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0)
+               | (L.FLAG_INDEX32 if index32 else 0))
     o.history = None
     VP = ctypes.c_void_p * nsys
     hs = VP(*[A.handle.value for A in ops])

@@ -85,3 +85,50 @@ def test_batched_errors():
         solver.solve_batched([op, st], [b, dev_t(np.ones(64))])
     with pytest.raises(ValueError):
         solver.solve_batched([], [])
+
+
+@pytest.mark.parametrize("variant", ["bicgstab", "pbicgstab_rr"])
+def test_batched_compact_and_int32_columns(variant):
+    """Every system holds the compact int16 columns, so the batch reads them;
+    ``index32`` makes it read the int32 columns.  Both equal each system's own
+    oracle solve bit for bit."""
+    require_gpu()
+    bs = [oracle.spmv(A, inputs.batch_x_true(k, A.n)) for k, A in enumerate(BATCH)]
+    ops = [csr_op(A) for A in BATCH]
+    assert all(op.index_bytes == 2 for op in ops)
+    kw = dict(tol=1e-10, maxit=3000, rr_period=17)
+    ref = [oracle.solve(A, b, algo=ALG[variant], **kw) for A, b in zip(BATCH, bs)]
+    for index32 in (False, True):
+        say(f"batched {variant} index32={index32}")
+        xs, infos = solver.solve_batched(ops, [dev_t(b) for b in bs], variant=variant, index32=index32, **kw)
+        for k, (x_or, i_or) in enumerate(ref):
+            assert (infos[k].status, infos[k].iters, infos[k].n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"])
+            assert same(host(xs[k]), x_or), (index32, k)
+
+
+def test_batched_mixed_column_forms():
+    """One system whose columns do not fit int16 keeps the whole batch on
+    int32 columns; results still equal the oracle's."""
+    require_gpu()
+    n = 40000
+    rows = np.arange(n)
+    far = (rows + 33000) % n  # offsets beyond int16 from the block start
+    r = np.concatenate([rows, rows])
+    c = np.concatenate([rows, far])
+    v = np.concatenate([np.full(n, 4.0), np.full(n, 0.5)])
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, r + 1, 1)
+    wide = oracle.CSR(np.cumsum(rp), c, v)
+    sysl = [BATCH[4], wide, BATCH[6]]
+    ops = [csr_op(A) for A in sysl]
+    assert [op.index_bytes for op in ops] == [2, 4, 2]
+    bs = [oracle.spmv(A, inputs.batch_x_true(k, A.n)) for k, A in enumerate(sysl)]
+    kw = dict(tol=1e-10, maxit=500, rr_period=17)
+    say("batched mixed column forms")
+    xs, infos = solver.solve_batched(ops, [dev_t(b) for b in bs], variant="pbicgstab_rr", **kw)
+    for k, (A, b) in enumerate(zip(sysl, bs)):
+        x_or, i_or = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, **kw)
+        assert (infos[k].status, infos[k].iters) == (i_or["status"], i_or["iters"]), k
+        assert same(host(xs[k]), x_or), k
