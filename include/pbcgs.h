@@ -167,10 +167,14 @@ const char* pbcgs_status_str(int status);
  * When every column j of a row i satisfies -32768 <= j - (i & ~63) <= 32767
  * (banded matrices such as the paper's stencil discretisations), the operator
  * also keeps a compact copy of the columns as int16 offsets from the row's
- * 64-row block start (2 nnz bytes of device memory, freed with it), which the
- * solves and pbcgs_spmv read instead of col_idx: 2 instead of 4 bytes per
- * non-zero and product, with identical results.  Values may change between
- * calls; row_ptr and col_idx must not change while the operator exists.
+ * 64-row block start (PBCGS_COLS_BLOCK16).  Otherwise, when the matrix has at
+ * most 64 distinct diagonals j - i (stencils of any size), it keeps 16-bit
+ * codes of (i & 63, the diagonal's index) with a 64-entry diagonal table
+ * (PBCGS_COLS_DIAG16).  Either copy takes 2 nnz bytes of device memory, freed
+ * with the operator, and the solves and pbcgs_spmv read it instead of
+ * col_idx: 2 instead of 4 bytes per non-zero and product, with identical
+ * results.  Values may change between calls; row_ptr and col_idx must not
+ * change while the operator exists.
  * One launch covers at most 1024 workgroups x 4 waves x 1024 blocks x 64 rows,
  * so n <= 268,435,456, and nnz <= 2^31 - 1025 (int32 indexing); ERR_UNSUPPORTED
  * beyond.
@@ -213,9 +217,13 @@ int pbcgs_csr_outer_grad(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* lambda, co
 int64_t pbcgs_op_rows(pbcgs_op_t op);
 
 /* Bytes per stored column index the solves read for op: 2 when a CSR operator
- * holds the compact int16 copy (see pbcgs_op_csr), 4 for int32 columns, 0 for
- * a stencil; ERR_INVALID_ARG for NULL. */
+ * holds a compact copy (either form, see pbcgs_op_csr), 4 for int32 columns,
+ * 0 for a stencil; ERR_INVALID_ARG for NULL. */
 int pbcgs_op_index_bytes(pbcgs_op_t op);
+
+/* Which column form the solves read for op (see pbcgs_op_csr). */
+enum { PBCGS_COLS_INT32 = 0, PBCGS_COLS_BLOCK16 = 1, PBCGS_COLS_DIAG16 = 2, PBCGS_COLS_NONE = 3 };
+int pbcgs_op_column_form(pbcgs_op_t op);
 
 /* y := A x (device pointers, n doubles each; x and y must not overlap). */
 int pbcgs_spmv(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* x, double* y);

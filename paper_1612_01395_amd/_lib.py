@@ -19,6 +19,7 @@ ERR_INVALID_ARG, ERR_ALLOC, ERR_HIP, ERR_UNSUPPORTED = -1, -2, -3, -4
 BICGSTAB, PBICGSTAB, PBICGSTAB_RR, CA_BICGSTAB, CG, CGCG, PIPE_CG = 0, 1, 2, 3, 4, 5, 6
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_JACOBI_FOLDED = 0, 1, 2
 FP64, FP32_RR64 = 0, 1
+COLS_INT32, COLS_BLOCK16, COLS_DIAG16, COLS_NONE = 0, 1, 2, 3
 
 FLAG_DIRECT = 1       # launch kernels directly instead of replaying a HIP graph
 FLAG_TIME_KERNELS = 2  # time the two fused kernels of each iteration with events
@@ -90,6 +91,7 @@ _SIGNATURES = {
     "pbcgs_csr_outer_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "pbcgs_op_rows": (_i64, [_vp]),
     "pbcgs_op_index_bytes": (ctypes.c_int, [_vp]),
+    "pbcgs_op_column_form": (ctypes.c_int, [_vp]),
     "pbcgs_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "pbcgs_dot": (ctypes.c_int, [_vp, _i64, _vp, _vp, ctypes.POINTER(_f64)]),
     "pbcgs_jacobi_dinv": (ctypes.c_int, [_vp, _vp, _vp]),

@@ -71,10 +71,17 @@ struct alignas(128) DevState {
 // Operators: apply one row of y = A x, summing in ascending column order.
 // ---------------------------------------------------------------------------
 //
-// Column indices (type I) are either the caller's int32 columns or a compact
-// int16 copy in which each column is stored as its offset from the first row
-// of its row's 64-row block (row & ~63); a wave always works on a whole
-// block that starts at a multiple of 64, so that row is known to every lane.
+// Column indices (type I) take one of three forms:
+//  - int32_t: the caller's columns;
+//  - int16_t: a compact copy holding each column as its offset from the first
+//    row of its row's 64-row block (row & ~63).  A wave always works on a
+//    whole block that starts at a multiple of 64, so that row is known to
+//    every lane;
+//  - uint16_t: a compact copy holding, for a matrix with at most 64 distinct
+//    diagonals j - i, the row's place in its block (6 bits) and the index of
+//    its diagonal in a 64-entry table dg (6 bits): j = (i & ~63) + (i & 63) +
+//    dg[index].  Each lane holds one table entry in a register and the
+//    columns are decoded with a cross-lane read, so no shared memory is used.
 template <class V, class I = int32_t>
 struct CsrOpT {
   using Val = V;
@@ -85,13 +92,19 @@ struct CsrOpT {
   // explicit, always 0: the driver keys its cached graphs on the operator's
   // bytes, which must then hold no indeterminate padding
   int32_t pad_ = 0;
+  const int32_t* __restrict__ dg = nullptr;  // diagonal table of the uint16_t form
 
   static constexpr int kStage = 512;  // staged non-zeros per wave and round
 
-  // column of a stored index; base = first row of the row's 64-row block
-  static __device__ __forceinline__ int32_t col(I c, int32_t base) {
+  static constexpr bool kDiag = std::is_same<I, uint16_t>::value;
+
+  // column of a stored index; base = first row of the row's 64-row block,
+  // dreg = this lane's entry of the diagonal table (uint16_t form).  All 64
+  // lanes must call it together in the uint16_t form.
+  static __device__ __forceinline__ int32_t col(I c, int32_t base, int32_t dreg) {
     if constexpr (sizeof(I) == sizeof(int32_t)) return (int32_t)c;
-    else return base + (int32_t)c;
+    else if constexpr (!kDiag) return base + (int32_t)c;
+    else return base + (int32_t)(c & 63u) + __shfl(dreg, (int)(c >> 6), 64);
   }
   // a staged column inside [0, n): a round may begin one non-zero before the
   // block (the last one of the previous row); an int16 offset of it is decoded
@@ -125,6 +138,7 @@ struct CsrOpT {
     const int32_t rhi = rp[min(b0 + 64, n)];
     const int32_t nnz = rp[n];
     const int32_t rb0 = rp[rc], re0 = rp[rc + 1];
+    const int32_t dreg = kDiag ? dg[lane] : 0;
     const int32_t rb = valid ? rb0 : rhi;
     const int32_t re = valid ? re0 : rhi;
     V acc = V(0);
@@ -145,8 +159,8 @@ struct CsrOpT {
           if constexpr (sizeof(I) == 2) {
             // one 32-bit word: the low half is non-zero k, the high half k + 1
             const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(ci) + (k >> 1));
-            ca[u] = col((I)(w & 0xffffu), b0);
-            cb[u] = col((I)(w >> 16), b0);
+            ca[u] = col((I)(w & 0xffffu), b0, dreg);
+            cb[u] = col((I)(w >> 16), b0, dreg);
           } else {
             ca[u] = __builtin_nontemporal_load(&ci[k]);
             cb[u] = __builtin_nontemporal_load(&ci[k + 1]);
@@ -165,7 +179,7 @@ struct CsrOpT {
 #pragma unroll
         for (int u = 0; u < kStage / 64; ++u) {
           const int32_t k = min(c0 + u * 64 + lane, c1 - 1);
-          cc[u] = staged_col(col(__builtin_nontemporal_load(&ci[k]), b0));
+          cc[u] = staged_col(col(__builtin_nontemporal_load(&ci[k]), b0, dreg));
           vv[u] = __builtin_nontemporal_load(&va[k]);
         }
 #pragma unroll
@@ -178,22 +192,13 @@ struct CsrOpT {
     }
     return acc;
   }
-
-  // One row by itself (utility kernels).
-  template <class X>
-  __device__ __forceinline__ V apply(int32_t row, const X* __restrict__ x) const {
-    const int32_t e = rp[row + 1];
-    const int32_t base = row & ~63;
-    V acc = V(0);
-    for (int32_t k = rp[row]; k < e; ++k)
-      acc = acc + __builtin_nontemporal_load(&va[k]) * V(x[col(__builtin_nontemporal_load(&ci[k]), base)]);
-    return acc;
-  }
 };
 using CsrOp = CsrOpT<double>;
 using CsrOp32 = CsrOpT<float>;
 using CsrOp16 = CsrOpT<double, int16_t>;
 using CsrOp16f = CsrOpT<float, int16_t>;
+using CsrOpDg = CsrOpT<double, uint16_t>;
+using CsrOpDgf = CsrOpT<float, uint16_t>;
 
 template <class Op> struct IsCsr : std::false_type {};
 template <class V, class I> struct IsCsr<CsrOpT<V, I>> : std::true_type {};
@@ -1896,6 +1901,67 @@ __global__ __launch_bounds__(kWG) void k_c16_fill(CsrOp op, int32_t n, int16_t* 
   if (row >= n) return;
   const int32_t base = row & ~63, e = op.rp[row + 1];
   for (int32_t k = op.rp[row]; k < e; ++k) c16[k] = (int16_t)(op.ci[k] - base);
+}
+
+// Diagonal table of the uint16_t column form: a 64-slot open-addressing set of
+// the distinct diagonals j - i (kEmptyDiag marks a free slot; no diagonal of an
+// int32-indexed matrix equals it).  Which slot a diagonal lands in depends on
+// the order of the atomic operations; decoding is exact whatever the slots.
+constexpr int32_t kEmptyDiag = INT32_MIN;
+__device__ __forceinline__ int diag_hash(int32_t d) { return (int)(((uint32_t)d * 2654435761u) >> 26); }
+
+// Inserts d into the 64-slot set; false when the set is full.
+__device__ __forceinline__ bool diag_insert(int32_t* set, int32_t d) {
+  const int h = diag_hash(d);
+  for (int p = 0; p < 64; ++p) {
+    const int32_t prev = atomicCAS(&set[(h + p) & 63], kEmptyDiag, d);
+    if (prev == kEmptyDiag || prev == d) return true;
+  }
+  return false;
+}
+
+// Gathers the distinct diagonals of the operator into tab[64] (filled with
+// kEmptyDiag beforehand): each workgroup collects its rows' diagonals in an LDS
+// set, then merges them into tab.  flag := 1 if there are more than 64.
+__global__ __launch_bounds__(kWG) void k_diag_collect(CsrOp op, int32_t n, int32_t* tab, int32_t* flag) {
+  __shared__ int32_t set[64];
+  __shared__ int32_t full;
+  if (threadIdx.x < 64) set[threadIdx.x] = kEmptyDiag;
+  if (threadIdx.x == 0) full = 0;
+  __syncthreads();
+  const int32_t row = blockIdx.x * kWG + threadIdx.x;
+  if (row < n) {
+    const int32_t e = op.rp[row + 1];
+    for (int32_t k = op.rp[row]; k < e; ++k)
+      if (!diag_insert(set, op.ci[k] - row)) { full = 1; break; }
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int32_t d = set[threadIdx.x];
+    if (d != kEmptyDiag && !diag_insert(tab, d)) full = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && full) atomicOr(flag, 1);
+}
+
+// cd[k] := (row_k & 63) | (slot of diagonal col_k - row_k in tab) << 6, one row per thread.
+__global__ __launch_bounds__(kWG) void k_diag_code(CsrOp op, int32_t n, const int32_t* __restrict__ tab,
+                                                   uint16_t* __restrict__ cd) {
+  __shared__ int32_t t[64];
+  if (threadIdx.x < 64) t[threadIdx.x] = tab[threadIdx.x];
+  __syncthreads();
+  const int32_t row = blockIdx.x * kWG + threadIdx.x;
+  if (row >= n) return;
+  const int32_t e = op.rp[row + 1];
+  for (int32_t k = op.rp[row]; k < e; ++k) {
+    const int32_t d = op.ci[k] - row;
+    const int h = diag_hash(d);
+    int slot = 0;
+    for (int p = 0; p < 64; ++p) {
+      if (t[(h + p) & 63] == d) { slot = (h + p) & 63; break; }
+    }
+    cd[k] = (uint16_t)((row & 63) | (slot << 6));
+  }
 }
 
 // ===========================================================================

@@ -87,6 +87,10 @@ struct pbcgs_op_s {
   // compact int16 column indices (offsets from the row's 64-row block start),
   // made at creation when every offset fits; owned by the operator
   int16_t* c16 = nullptr;
+  // otherwise, with at most 64 distinct diagonals: 16-bit diagonal codes and
+  // the 64-entry diagonal table; owned by the operator
+  uint16_t* cd = nullptr;
+  int32_t* dg = nullptr;
 };
 
 namespace {
@@ -240,7 +244,7 @@ CsrOpT<float, I> to_binary32(pbcgs_ctx_t ctx, const CsrOpT<double, I>& op, int64
     const int g = (int)std::min<int64_t>((nnz + kWG - 1) / kWG, 8192);
     k_round_vals<<<g, kWG, 0, ctx->stream>>>(nnz, op.va, ctx->a32);
   }
-  return CsrOpT<float, I>{op.rp, op.ci, ctx->a32, op.n};
+  return CsrOpT<float, I>{op.rp, op.ci, ctx->a32, op.n, 0, op.dg};
 }
 template <int NPTS>
 StencilOp<NPTS, float> to_binary32(pbcgs_ctx_t, const StencilOp<NPTS, double>& op, int64_t) {
@@ -780,9 +784,10 @@ struct Driver {
 
 // Graph keys hold the bytes of the operator and argument structs, so these
 // structs must have no padding (whose contents would be indeterminate).
-static_assert(sizeof(CsrOp) == 3 * sizeof(void*) + 2 * sizeof(int32_t), "CsrOp padding");
+static_assert(sizeof(CsrOp) == 4 * sizeof(void*) + 2 * sizeof(int32_t), "CsrOp padding");
 static_assert(sizeof(CsrOp16) == sizeof(CsrOp) && sizeof(CsrOp32) == sizeof(CsrOp) &&
-              sizeof(CsrOp16f) == sizeof(CsrOp), "CsrOpT padding");
+              sizeof(CsrOp16f) == sizeof(CsrOp) && sizeof(CsrOpDg) == sizeof(CsrOp) &&
+              sizeof(CsrOpDgf) == sizeof(CsrOp), "CsrOpT padding");
 static_assert(sizeof(StencilOp<7>) == 4 * sizeof(int32_t) + 7 * sizeof(double), "StencilOp padding");
 static_assert(sizeof(StencilOp<5>) == 4 * sizeof(int32_t) + 5 * sizeof(double), "StencilOp padding");
 static_assert(sizeof(StencilOp<7, float>) == 4 * sizeof(int32_t) + 7 * sizeof(float), "StencilOp padding");
@@ -794,6 +799,7 @@ template <class F>
 int with_op(pbcgs_op_t A, F f, bool compact = true) {
   if (A->kind == OP_CSR) {
     if (compact && A->c16) return f(CsrOp16{A->rp, A->c16, A->va, A->n});
+    if (compact && A->cd) return f(CsrOpDg{A->rp, A->cd, A->va, A->n, 0, A->dg});
     return f(CsrOp{A->rp, A->ci, A->va, A->n});
   }
   if (A->kind == OP_ST7) {
@@ -1147,10 +1153,56 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
 }
 
 namespace {
+// The diagonal-coded copy (at most 64 distinct diagonals), for an operator
+// whose columns do not fit the int16 block offsets.  Like the int16 copy it
+// only changes how columns are read; an operator with more diagonals (or a
+// failed allocation) keeps the int32 columns.
+int make_diag_coded(pbcgs_ctx_t ctx, pbcgs_op_t A, const CsrOp& op, int g) {
+  int32_t* dg = nullptr;
+  uint16_t* cd = nullptr;
+  if (hipMalloc((void**)&dg, sizeof(int32_t) * 64) != hipSuccess) {
+    (void)hipGetLastError();
+    return PBCGS_SUCCESS;
+  }
+  const std::vector<int32_t> empty(64, kEmptyDiag);
+  int rc = reset_flag(ctx);
+  if (rc == PBCGS_SUCCESS && hipMemcpyAsync(dg, empty.data(), sizeof(int32_t) * 64, hipMemcpyHostToDevice,
+                                            ctx->stream) != hipSuccess)
+    rc = fail(ctx, PBCGS_ERR_HIP, "diagonal table upload failed");
+  if (rc != PBCGS_SUCCESS) {
+    (void)hipFree(dg);
+    return rc;
+  }
+  k_diag_collect<<<g, kWG, 0, ctx->stream>>>(op, A->n, dg, ctx->flag);
+  int32_t flag = 0;
+  rc = read_flag(ctx, &flag);  // synchronises the stream: `empty` is no longer read
+  if (rc != PBCGS_SUCCESS || flag) {
+    (void)hipFree(dg);
+    return rc;
+  }
+  if (hipMalloc((void**)&cd, sizeof(uint16_t) * (size_t)A->nnz) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(dg);
+    return PBCGS_SUCCESS;
+  }
+  k_diag_code<<<g, kWG, 0, ctx->stream>>>(op, A->n, dg, cd);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    (void)hipFree(cd);
+    (void)hipFree(dg);
+    return fail(ctx, PBCGS_ERR_HIP, std::string("diagonal-coded column copy: ") + hipGetErrorString(e));
+  }
+  A->cd = cd;
+  A->dg = dg;
+  return PBCGS_SUCCESS;
+}
+
 // Makes the compact int16 column copy of a validated CSR operator when every
-// column fits in int16 around its row's 64-row block start.  It only changes
-// how the columns are read, never a result, so an operator that does not fit
-// (or a failed allocation) keeps the int32 columns and no error is raised.
+// column fits in int16 around its row's 64-row block start, else the
+// diagonal-coded copy when the matrix has at most 64 distinct diagonals.  It
+// only changes how the columns are read, never a result, so an operator that
+// fits neither (or a failed allocation) keeps the int32 columns and no error
+// is raised.
 int make_compact(pbcgs_ctx_t ctx, pbcgs_op_t A) {
   if (A->nnz == 0) return PBCGS_SUCCESS;
   const CsrOp op{A->rp, A->ci, A->va, A->n};
@@ -1161,7 +1213,7 @@ int make_compact(pbcgs_ctx_t ctx, pbcgs_op_t A) {
   int32_t flag = 0;
   rc = read_flag(ctx, &flag);
   if (rc != PBCGS_SUCCESS) return rc;
-  if (flag) return PBCGS_SUCCESS;
+  if (flag) return make_diag_coded(ctx, A, op, g);
   int16_t* c16 = nullptr;
   if (hipMalloc((void**)&c16, sizeof(int16_t) * (size_t)A->nnz) != hipSuccess) {
     (void)hipGetLastError();
@@ -1251,6 +1303,8 @@ int pbcgs_op_destroy(pbcgs_op_t op) {
     if (op->own_ci) (void)hipFree(op->own_ci);
     if (op->own_va) (void)hipFree(op->own_va);
     if (op->c16) (void)hipFree(op->c16);
+    if (op->cd) (void)hipFree(op->cd);
+    if (op->dg) (void)hipFree(op->dg);
   }
   delete op;
   return PBCGS_SUCCESS;
@@ -1264,7 +1318,15 @@ int64_t pbcgs_op_rows(pbcgs_op_t op) {
 int pbcgs_op_index_bytes(pbcgs_op_t op) {
   if (!op) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "op is NULL");
   if (op->kind != OP_CSR) return 0;
-  return op->c16 ? 2 : 4;
+  return (op->c16 || op->cd) ? 2 : 4;
+}
+
+int pbcgs_op_column_form(pbcgs_op_t op) {
+  if (!op) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "op is NULL");
+  if (op->kind != OP_CSR) return PBCGS_COLS_NONE;
+  if (op->c16) return PBCGS_COLS_BLOCK16;
+  if (op->cd) return PBCGS_COLS_DIAG16;
+  return PBCGS_COLS_INT32;
 }
 
 int pbcgs_spmv(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* x, double* y) {

@@ -108,9 +108,17 @@ class Operator:
 
     @property
     def index_bytes(self) -> int:
-        """Bytes per column index the solves read: 2 (compact int16 copy), 4
+        """Bytes per column index the solves read: 2 (a compact copy), 4
         (int32 columns) or 0 (stencil)."""
         return L.check(L.lib().pbcgs_op_index_bytes(self.handle), self.ctx.handle)
+
+    @property
+    def column_form(self) -> str:
+        """The column form the solves read: "int32", "block16" (int16 offsets
+        from the 64-row block start), "diag16" (diagonal codes) or "none"
+        (stencil)."""
+        f = L.check(L.lib().pbcgs_op_column_form(self.handle), self.ctx.handle)
+        return {L.COLS_INT32: "int32", L.COLS_BLOCK16: "block16", L.COLS_DIAG16: "diag16", L.COLS_NONE: "none"}[f]
 
     def close(self):
         if getattr(self, "handle", None):

@@ -87,7 +87,8 @@ def test_binding_constants_match_the_header():
     enum = {m.group(1): int(m.group(2)) for m in re.finditer(r"\bPBCGS_([A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
     for name in ("SUCCESS", "MAXIT", "BREAKDOWN", "NONFINITE", "ERR_INVALID_ARG", "ERR_ALLOC", "ERR_HIP",
                  "ERR_UNSUPPORTED", "BICGSTAB", "PBICGSTAB", "PBICGSTAB_RR", "CA_BICGSTAB", "CG", "CGCG",
-                 "PIPE_CG", "PRECOND_NONE", "PRECOND_JACOBI", "PRECOND_JACOBI_FOLDED", "FP64", "FP32_RR64"):
+                 "PIPE_CG", "PRECOND_NONE", "PRECOND_JACOBI", "PRECOND_JACOBI_FOLDED", "FP64", "FP32_RR64",
+                 "COLS_INT32", "COLS_BLOCK16", "COLS_DIAG16", "COLS_NONE"):
         assert enum[name] == getattr(_lib, name), name
     variants = {v for k, v in enum.items() if k in ("BICGSTAB", "PBICGSTAB", "PBICGSTAB_RR", "CA_BICGSTAB", "CG",
                                                       "CGCG", "PIPE_CG")}

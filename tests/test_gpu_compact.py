@@ -211,3 +211,144 @@ def test_spmv_pair_loads_at_the_edges(n, odd_nnz, empty_tail):
     x = inputs.random_vector(A.n, 13)
     y = host(solver.spmv(op, dev_t(x)))
     assert same(y, oracle.spmv(A, x))
+
+
+# ---- the diagonal-coded form: at most 64 distinct diagonals, offsets beyond int16
+
+def grid7(nx, ny, nz, seed, symmetric=False):
+    """3-D 7-point operator on an nx x ny x nz grid (x fastest): diagonally
+    dominant, unsymmetric U[0.5, 1.5) couplings unless `symmetric`; with
+    nx * ny > 32767 the +-nx*ny diagonals do not fit the int16 block offsets."""
+    rng = np.random.default_rng([seed, nx, ny, nz])
+    n = nx * ny * nz
+    i = np.arange(n)
+    x, y, z = i % nx, (i // nx) % ny, i // (nx * ny)
+    offs = [(-nx * ny, z > 0), (-nx, y > 0), (-1, x > 0), (0, np.ones(n, bool)),
+            (1, x < nx - 1), (nx, y < ny - 1), (nx * ny, z < nz - 1)]
+    rows, cols, vals = [], [], []
+    for d, ok in offs:
+        r = i[ok]
+        rows.append(r)
+        cols.append(r + d)
+        if d == 0:
+            vals.append(np.full(r.size, 8.0))
+        elif symmetric:
+            vals.append(-np.ones(r.size))
+        else:
+            vals.append(-rng.uniform(0.5, 1.5, r.size))
+    r, c, v = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    o = np.lexsort((c, r))
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, r + 1, 1)
+    return oracle.CSR(np.cumsum(rp), c[o], v[o])
+
+
+def diag_set_matrix(n, diags, seed, odd_nnz=None, empty_tail=0):
+    """Random matrix whose entries lie on the given diagonals only (each
+    present with probability 0.6, the main diagonal always, 0 to be dominant)."""
+    rng = np.random.default_rng([seed, n, len(diags)])
+    rows, cols = [], []
+    for d in diags:
+        r = np.arange(max(0, -d), min(n, n - d))
+        r = r[r < n - empty_tail]
+        if d != 0:
+            r = r[rng.random(r.size) < 0.6]
+        rows.append(r)
+        cols.append(r + d)
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    if odd_nnz is not None and (r.size % 2 == 1) != odd_nnz:
+        keep = np.ones(r.size, bool)
+        keep[np.flatnonzero(c != r)[0]] = False
+        r, c = r[keep], c[keep]
+    v = np.where(c == r, float(len(diags)) + 1.0, rng.uniform(-1.0, 1.0, r.size))
+    o = np.lexsort((c, r))
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, r + 1, 1)
+    return oracle.CSR(np.cumsum(rp), c[o], v[o])
+
+
+WIDE = [-40000, -33000, -200, -1, 0, 1, 200, 33000, 40000]
+DCASES = {
+    "grid_200x200x3": grid7(200, 200, 3, 1),
+    "grid_200x200x3_sym": grid7(200, 200, 3, 2, symmetric=True),
+    "diag64": diag_set_matrix(70001, sorted(set([0] + [s * (33000 + 7 * k) for k in range(32) for s in (1, -1)][:63])), 3),
+    "diag65": diag_set_matrix(70001, sorted(set([0] + [s * (33000 + 7 * k) for k in range(33) for s in (1, -1)][:64])), 3),
+}
+
+
+def test_diag_inputs():
+    """Host check of the test inputs: 64 and 65 distinct diagonals, offsets beyond int16."""
+    for name, want in (("diag64", 64), ("diag65", 65), ("grid_200x200x3", 7)):
+        A = DCASES[name]
+        rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+        assert np.unique(A.col - rows).size == want, name
+        assert np.abs(A.col - (rows & ~63)).max() > 32767, name
+
+
+def test_column_forms():
+    require_gpu()
+    assert csr_op(CASES["c2_24"]).column_form == "block16"
+    assert csr_op(DCASES["grid_200x200x3"]).column_form == "diag16"
+    assert csr_op(DCASES["diag64"]).column_form == "diag16"
+    assert csr_op(DCASES["diag65"]).column_form == "int32"
+    assert csr_op(DCASES["diag65"]).index_bytes == 4
+    assert csr_op(DCASES["diag64"]).index_bytes == 2
+    assert solver.stencil(8, 8, 8, [-1, -1, -1, 6, -1, -1, -1]).column_form == "none"
+    assert solver.transpose(csr_op(DCASES["grid_200x200x3"])).column_form == "diag16"
+
+
+@pytest.mark.parametrize("name", list(DCASES))
+def test_diag_spmv_bitwise(name):
+    require_gpu()
+    A = DCASES[name]
+    x = inputs.random_vector(A.n, 17)
+    y = host(solver.spmv(csr_op(A), dev_t(x)))
+    assert same(y, oracle.spmv(A, x))
+
+
+@pytest.mark.parametrize("n", [65, 1000, 70001])
+@pytest.mark.parametrize("odd_nnz", [False, True])
+@pytest.mark.parametrize("empty_tail", [0, 70])
+def test_diag_spmv_at_the_edges(n, odd_nnz, empty_tail):
+    """Odd and even nnz, empty trailing rows and ragged blocks in the coded form."""
+    require_gpu()
+    empty_tail = min(empty_tail, n // 2)
+    diags = [d for d in WIDE if abs(d) < n] + [n - 1, -(n - 1)] if n > 40000 else [-(n - 1), -3, 0, 5, n - 1]
+    A = diag_set_matrix(n, sorted(set(diags)), 9, odd_nnz=odd_nnz, empty_tail=empty_tail)
+    assert (A.nnz % 2 == 1) == odd_nnz
+    op = csr_op(A)
+    want = "diag16" if n > 32767 + 64 else "block16"
+    assert op.column_form == want
+    say(f"diag edges: n={n} nnz={A.nnz} form={want}")
+    x = inputs.random_vector(A.n, 19)
+    assert same(host(solver.spmv(op, dev_t(x))), oracle.spmv(A, x))
+
+
+@pytest.mark.parametrize("variant,precond", [
+    ("bicgstab", None), ("bicgstab", "jacobi_folded"), ("pbicgstab", "jacobi"),
+    ("pbicgstab_rr", None), ("pbicgstab_rr", "jacobi"), ("pbicgstab_rr", "jacobi_folded"),
+    ("ca_bicgstab", "jacobi_folded")])
+def test_diag_solves_bitwise_both_index_forms(variant, precond):
+    require_gpu()
+    A = DCASES["grid_200x200x3"]
+    b, out = _solve_both(A, variant, precond, 1e-10, 300)
+    x_or, i_or = _oracle(A, b, variant, precond, 1e-10, 300)
+    _check(out, x_or, i_or)
+    assert out[0][1].status == 0
+
+
+@pytest.mark.parametrize("variant", ["cg", "pipe_cg"])
+def test_diag_cg_family_bitwise(variant):
+    require_gpu()
+    A = DCASES["grid_200x200x3_sym"]
+    b, out = _solve_both(A, variant, "jacobi", 1e-10, 300)
+    x_or, i_or = _oracle(A, b, variant, "jacobi", 1e-10, 300)
+    _check(out, x_or, i_or)
+
+
+def test_diag_precision_form_bitwise():
+    require_gpu()
+    A = DCASES["grid_200x200x3"]
+    b, out = _solve_both(A, "pbicgstab_rr", "jacobi_folded", 1e-10, 600, precision="fp32_rr64")
+    x_or, i_or = oracle.solve_mp(A, b, dinv=oracle.jacobi_dinv(A), tol=1e-10, maxit=600, rr_period=20, history=True)
+    _check(out, x_or, i_or)
