@@ -497,8 +497,8 @@ def main():
             torch.cuda.synchronize()
             dtb = (time.perf_counter() - t0) / reps
             its = [i.iters for i in infs]
-            # the batch reads int16 columns when every operator holds them
-            ibb = 2 if all(op.index_bytes == 2 for op in ops_) else 4
+            # the batch reads int16 block offsets when every operator holds them
+            ibb = 2 if all(op.column_form == "block16" for op in ops_) else 4
             byts = sum(it_ * (passes * 8 * Nk + 2 * (4 * (Nk + 1) + (8 + ibb) * zk))
                        for it_, Nk, zk in zip(its, bN, bnnz))
             return {"ms_per_batch_solve": round(dtb * 1e3, 2), "column_index_bytes": ibb, "iters_total": int(sum(its)),

@@ -95,7 +95,7 @@ def test_batched_compact_and_int32_columns(variant):
     require_gpu()
     bs = [oracle.spmv(A, inputs.batch_x_true(k, A.n)) for k, A in enumerate(BATCH)]
     ops = [csr_op(A) for A in BATCH]
-    assert all(op.index_bytes == 2 for op in ops)
+    assert all(op.column_form == "block16" for op in ops)
     kw = dict(tol=1e-10, maxit=3000, rr_period=17)
     ref = [oracle.solve(A, b, algo=ALG[variant], **kw) for A, b in zip(BATCH, bs)]
     for index32 in (False, True):
@@ -107,8 +107,9 @@ def test_batched_compact_and_int32_columns(variant):
 
 
 def test_batched_mixed_column_forms():
-    """One system whose columns do not fit int16 keeps the whole batch on
-    int32 columns; results still equal the oracle's."""
+    """One system whose columns do not fit the int16 block offsets (it holds
+    diagonal codes instead) keeps the whole batch on int32 columns; results
+    still equal the oracle's."""
     require_gpu()
     n = 40000
     rows = np.arange(n)
@@ -123,7 +124,7 @@ def test_batched_mixed_column_forms():
     wide = oracle.CSR(np.cumsum(rp), c, v)
     sysl = [BATCH[4], wide, BATCH[6]]
     ops = [csr_op(A) for A in sysl]
-    assert [op.index_bytes for op in ops] == [2, 4, 2]
+    assert [op.column_form for op in ops] == ["block16", "diag16", "block16"]
     bs = [oracle.spmv(A, inputs.batch_x_true(k, A.n)) for k, A in enumerate(sysl)]
     kw = dict(tol=1e-10, maxit=500, rr_period=17)
     say("batched mixed column forms")
