@@ -378,9 +378,9 @@ def main():
         torch.cuda.empty_cache()
 
     # ---- the other configurations: 2-D 64^2 (latency-bound) and 3-D 27-point 256^3 (matrix-bound)
-    configs = None
+    other_cfg = None
     if "configs" in legs:
-        configs = {}
+        other_cfg = {}
         for name, precond, steps in (("c1", None, 20), ("c3", "jacobi_folded", 2)):
             wc = inputs.workload(name)
             kappa = None
@@ -409,7 +409,7 @@ def main():
                                 "syncs_per_iter": inf.syncs_per_iter, "relres_true": inf.relres_true}
             row["pbicgstab_over_bicgstab_iters_per_s"] = round(
                 row["pbicgstab_rr"]["iters_per_s"] / row["bicgstab"]["iters_per_s"], 4)
-            configs[name] = row
+            other_cfg[name] = row
             del Ac, rpc, colc, valc, bc, xc, kappa
             torch.cuda.empty_cache()
 
@@ -621,8 +621,8 @@ def main():
         out["size_sweep_3d_7pt_csr_folded_jacobi"] = sweep
     if paper is not None:
         out["paper_test_problems"] = paper
-    if configs is not None:
-        out["other_configs"] = configs
+    if other_cfg is not None:
+        out["other_configs"] = other_cfg
     out["roofline"] = roofline
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -75,7 +75,7 @@ def test_c2_full_solve_bitwise(c2, variant, precond):
     assert same(host(x), x_or)
     assert same([info.relres_rec, info.relres_true], [i_or["relres_rec"], i_or["relres_true"]])
     assert same(host(info.history), i_or["history"])
-    # the benchmark spec's bound, met trivially by bitwise equality
+    # the stated accuracy bound ||x - x_oracle|| <= 1e-8 ||x_oracle||, met trivially by bitwise equality
     assert np.linalg.norm(host(x) - x_or) <= 1e-8 * np.linalg.norm(x_or)
 
 
