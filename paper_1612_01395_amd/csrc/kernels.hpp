@@ -107,9 +107,10 @@ struct CsrOpT {
     else return base + (int32_t)(c & 63u) + __shfl(dreg, (int)(c >> 6), 64);
   }
   // a staged column inside [0, n): a round may begin one non-zero before the
-  // block (the last one of the previous row); an int16 offset of it is decoded
-  // against this block's start.  Its product's slot is never read; the clamp
-  // only keeps its gather in bounds (int32 columns are valid as they are).
+  // block (the last one of the previous row), whose compact column (either
+  // 16-bit form) is then decoded against this block's start.  Its product's
+  // slot is never read; the clamp only keeps its gather in bounds (int32
+  // columns are valid as they are).
   __device__ __forceinline__ int32_t staged_col(int32_t c) const {
     if constexpr (sizeof(I) == sizeof(int32_t)) return c;
     else return min(max(c, 0), n - 1);
