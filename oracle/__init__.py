@@ -9,9 +9,14 @@ oracle on tiny systems.
 Algorithms (numbered as in arXiv 1612.01395, in order of appearance):
 ``ALG_BICGSTAB`` -> Algorithm 7 (Algorithm 10 when ``dinv`` is given);
 ``ALG_PBICGSTAB`` -> Algorithm 9 (Algorithm 11 with ``dinv``);
-``ALG_PBICGSTAB_RR`` -> the same with residual replacement (Section 4.2).
+``ALG_PBICGSTAB_RR`` -> the same with residual replacement (Section 4.2);
+``ALG_CA_BICGSTAB`` -> Algorithm 8 (Section 3.1); ``ALG_CG``, ``ALG_CGCG``,
+``ALG_PIPE_CG`` -> Algorithms 2, 4 and 6 (Section 2).
 :func:`solve_folded` runs Algorithm 7 / 9 on A M^{-1} formed explicitly (the
 right preconditioning of Section 3.6 with the product built).
+:func:`solve_mp` is the precision form of Algorithm 9 with replacement; its
+exact binary32 rounding sequence beyond the facts its tests pin is parity
+unpinned.
 """
 
 from __future__ import annotations
