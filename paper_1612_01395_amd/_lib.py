@@ -24,7 +24,7 @@ COLS_INT32, COLS_BLOCK16, COLS_DIAG16, COLS_NONE = 0, 1, 2, 3
 FLAG_DIRECT = 1       # launch kernels directly instead of replaying a HIP graph
 FLAG_TIME_KERNELS = 2  # time the two fused kernels of each iteration with events
 FLAG_ALPHA_EQ5 = 4     # alpha_{i+1} of the pipelined variants by eq. (5) instead of eq. (3)
-FLAG_INDEX32 = 8       # read the int32 columns even where the operator holds the int16 copy
+FLAG_INDEX32 = 8       # read the int32 columns even where the operator holds a compact copy
 
 
 class Opts(ctypes.Structure):

@@ -793,8 +793,9 @@ static_assert(sizeof(StencilOp<5>) == 4 * sizeof(int32_t) + 5 * sizeof(double), 
 static_assert(sizeof(StencilOp<7, float>) == 4 * sizeof(int32_t) + 7 * sizeof(float), "StencilOp padding");
 static_assert(sizeof(StencilOp<5, float>) == 4 * sizeof(int32_t) + 5 * sizeof(float), "StencilOp padding");
 
-// f(op) with the operator's device form: for CSR the compact int16 columns
-// when the operator holds them and `compact` allows, else the int32 ones.
+// f(op) with the operator's device form: for CSR the compact copy the
+// operator holds (int16 block offsets or diagonal codes) when `compact`
+// allows, else the int32 columns.
 template <class F>
 int with_op(pbcgs_op_t A, F f, bool compact = true) {
   if (A->kind == OP_CSR) {

@@ -249,7 +249,7 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
     (optional) receives the iterate in place of a new tensor.  ``alpha_form``
     5 takes alpha_{i+1} of the pipelined variants from eq. (5) instead of
     eq. (3) (Section 3.1).  ``index32`` reads the int32 column indices even
-    where the operator holds its compact int16 copy (same result)."""
+    where the operator holds a compact copy (same result)."""
     _check_vec(b, A.n, "b")
     _check_alpha_form(alpha_form)
     if variant not in VARIANTS:
@@ -299,8 +299,9 @@ def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str 
     """Solve the independent systems ops[k] x_k = bs[k] in one batched call
     (CSR operators of one context, no preconditioner, binary64).  Returns
     (xs, infos); each system's result equals its own :func:`solve` bit for bit.
-    The batch reads compact int16 columns when every operator holds them and
-    ``index32`` is false."""
+    The batch reads the int16 block offsets when every operator holds them
+    (``column_form == "block16"``) and ``index32`` is false, else the int32
+    columns."""
     _check_alpha_form(alpha_form)
     nsys = len(ops)
     if nsys == 0 or len(bs) != nsys:
