@@ -11,7 +11,9 @@ pipelined CG (Algorithm 6).
 
 A context is bound to the stream that was current when it was created (the
 default context of each device and stream is cached), and an operator runs
-its solves on its context's stream.
+its solves on its context's stream.  A CSR operator keeps a compact 16-bit
+copy of its column indices where one fits (``Operator.column_form``); it
+changes how columns are read, never a result.
 """
 
 from __future__ import annotations
