@@ -44,6 +44,9 @@ def test_null_arguments_are_rejected_not_crashing():
     assert L.pbcgs_ctx_create(0, None, None) == _lib.ERR_INVALID_ARG
     assert L.pbcgs_ctx_destroy(None) == _lib.ERR_INVALID_ARG
     assert L.pbcgs_op_destroy(None) == _lib.ERR_INVALID_ARG
+    assert L.pbcgs_op_rows(None) == _lib.ERR_INVALID_ARG
+    assert L.pbcgs_op_index_bytes(None) == _lib.ERR_INVALID_ARG
+    assert L.pbcgs_op_column_form(None) == _lib.ERR_INVALID_ARG
     assert _lib.last_error(None)
 
 
