@@ -77,3 +77,75 @@ def run_case(seed):
 def test_random_system_bitwise(seed):
     require_gpu()
     run_case(seed)
+
+
+def random_banded_system(rng, spd):
+    """A random system of 33,000 to 80,000 rows whose entries lie on a random
+    set of diagonals, some of them beyond the int16 block offsets: with up to
+    64 diagonals the operator holds diagonal codes, with more it keeps int32
+    columns.  Diagonally dominant (symmetric with `spd`)."""
+    n = int(rng.integers(33000, 80001))
+    ndiag = int(rng.choice([3, 8, 20, 40, 63, 70]))
+    half = max(1, ndiag // 2)
+    offs = set()
+    while len(offs) < half:
+        offs.add(int(rng.choice([rng.integers(1, 200), rng.integers(32800, n - 1)])))
+    nneg = half if (spd or ndiag >= 63) else max(1, half // 2)  # mirrored offsets
+    diags = sorted(offs | {-int(d) for d in rng.choice(sorted(offs), size=nneg, replace=False)} | {0})
+    rows, cols, vals = [], [], []
+    for d in diags:
+        r = np.arange(max(0, -d), min(n, n - d))
+        if d != 0:
+            r = r[rng.random(r.size) < 0.7]
+        rows.append(r)
+        cols.append(r + d)
+        vals.append(rng.uniform(-1.0, 1.0, r.size))
+    r, c, v = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    M = sp.csr_matrix((v, (r, c)), shape=(n, n))
+    if spd:
+        M = M + M.T
+    rowsum = np.asarray(abs(M).sum(axis=1)).ravel()
+    M = (M + sp.diags(rowsum * rng.uniform(1.05, 2.0, n) + rng.uniform(0.1, 1.0, n))).tocsr()
+    M.sum_duplicates()
+    M.sort_indices()
+    return oracle.CSR(M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
+def expected_form(A):
+    """The column form the library must choose, computed on the host."""
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    off = A.col.astype(np.int64) - (rows & ~63)
+    if off.min() >= -32768 and off.max() <= 32767:
+        return "block16"
+    return "diag16" if np.unique(A.col.astype(np.int64) - rows).size <= 64 else "int32"
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_wide_system_bitwise(seed):
+    """Random wide-band systems: the form the operator picks (diagonal codes or
+    int32) matches the host's prediction, and solves equal the oracle's bit for
+    bit in that form and with ``index32``."""
+    require_gpu()
+    rng = np.random.default_rng(5000 + seed)
+    spd = bool(seed % 4 == 3)
+    A = random_banded_system(rng, spd)
+    form = expected_form(A)
+    variant = str(rng.choice(["cg", "pipe_cg"] if spd else ["bicgstab", "pbicgstab_rr", "ca_bicgstab"]))
+    precond = "jacobi" if spd else str(rng.choice(["jacobi_folded", "none"]))
+    precond = None if precond == "none" else precond
+    tol, maxit, rr = 1e-10, int(rng.choice([7, 60, 400])), int(rng.choice([5, 50]))
+    b = rng.standard_normal(A.n)
+    say(f"random wide case {seed}: n={A.n} nnz={len(A.val)} form={form} {variant} precond={precond} maxit={maxit}")
+    op = csr_op(A)
+    assert op.column_form == form
+    dv = oracle.jacobi_dinv(A) if precond else None
+    kw = dict(tol=tol, maxit=maxit, rr_period=rr, history=True)
+    if precond == "jacobi_folded":
+        x_or, i_or = oracle.solve_folded(A, b, algo=ALG[variant], dinv=dv, **kw)
+    else:
+        x_or, i_or = oracle.solve(A, b, algo=ALG[variant], dinv=dv, **kw)
+    for index32 in (False, True):
+        x, info = solver.solve(op, dev_t(b), variant=variant, precond=precond, index32=index32, **kw)
+        assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"]), (info, i_or)
+        assert same(host(x), x_or), (index32, float(np.nanmax(np.abs(host(x) - x_or))))
+        assert same(host(info.history), i_or["history"])
