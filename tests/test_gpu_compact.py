@@ -352,3 +352,20 @@ def test_diag_precision_form_bitwise():
     b, out = _solve_both(A, "pbicgstab_rr", "jacobi_folded", 1e-10, 600, precision="fp32_rr64")
     x_or, i_or = oracle.solve_mp(A, b, dinv=oracle.jacobi_dinv(A), tol=1e-10, maxit=600, rr_period=20, history=True)
     _check(out, x_or, i_or)
+
+
+def test_alternating_forms_reuse_cached_graphs():
+    """Solves alternate between the compact and the int32 columns of one
+    operator: each form replays its own cached graphs (the cache is keyed on
+    the operator's bytes) and every solve equals the oracle bit for bit."""
+    require_gpu()
+    A = CASES["c2_24"]
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    x_or, i_or = oracle.solve_folded(A, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=oracle.jacobi_dinv(A), tol=1e-10,
+                                     maxit=400, rr_period=20)
+    op = csr_op(A)
+    for rep in range(3):
+        for index32 in (False, True, False):
+            x, info = solver.solve(op, dev_t(b), variant="pbicgstab_rr", precond="jacobi_folded", tol=1e-10,
+                                   maxit=400, rr_period=20, index32=index32)
+            assert info.iters == i_or["iters"] and same(host(x), x_or), (rep, index32)
