@@ -14,9 +14,9 @@ Algorithms (numbered as in arXiv 1612.01395, in order of appearance):
 ``ALG_PIPE_CG`` -> Algorithms 2, 4 and 6 (Section 2).
 :func:`solve_folded` runs Algorithm 7 / 9 on A M^{-1} formed explicitly (the
 right preconditioning of Section 3.6 with the product built).
-:func:`solve_mp` is the precision form of Algorithm 9 with replacement; its
-exact binary32 rounding sequence beyond the facts its tests pin is parity
-unpinned.
+:func:`solve_mp` is the precision form of Algorithm 9 with replacement; an
+exact-rational twin with IEEE 754 rounding of every operation
+(``exact.pbicgstab_mp``, ``ieee.py``) pins its rounding sequence bit for bit.
 """
 
 from __future__ import annotations

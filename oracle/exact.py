@@ -372,3 +372,210 @@ def pipe_cg(A, b, x0, maxit, dinv=None):
         if all(v == 0 for v in r):
             return out, "converged"
     return out, "maxit"
+
+
+# ---------------------------------------------------------------------------
+# The precision form, every operation rounded as an IEEE machine rounds it.
+# ---------------------------------------------------------------------------
+
+def _pairwise(vals, rnd):
+    """Balanced-tree sum of a power-of-two number of values, each addition
+    rounded by ``rnd``."""
+    if len(vals) == 1:
+        return vals[0]
+    h = len(vals) // 2
+    return rnd(_pairwise(vals[:h], rnd) + _pairwise(vals[h:], rnd))
+
+
+def _dot_rounded(u, v, rnd):
+    """Rounded products, zero-padded to a power of two, summed pairwise with
+    every addition rounded; the final + 0 only normalises a signed zero."""
+    prods = [rnd(a * b) for a, b in zip(u, v)]
+    size = 1
+    while size < len(prods):
+        size *= 2
+    prods += [ZERO] * (size - len(prods))
+    return _pairwise(prods, rnd)
+
+
+def _spmv_rounded(A, x, rnd):
+    """Each row summed in stored order from 0, product and sum rounded."""
+    out = []
+    for row in A:
+        acc = ZERO
+        for c, a in row:
+            acc = rnd(acc + rnd(a * x[c]))
+        out.append(acc)
+    return out
+
+
+def pbicgstab_mp(A, b, x0, *, tol, maxit, rr_period=0, rr_max=-1, reading=()):
+    """Precision form of p-BiCGStab with residual replacement, with every
+    operation an exactly computed rational rounded once to binary32 or
+    binary64 (:mod:`oracle.ieee`).
+
+    ``A`` holds binary64 values (rows of ``(col, Fraction)``), ``b`` and
+    ``x0`` binary64 vectors.  The reading of the precision form followed here:
+    binary32 operator f(A), vectors, recurrences and dot products (pairwise,
+    binary32 additions, widened afterwards); alpha, beta, omega in binary64
+    from the widened dots, passed to the vector updates rounded to binary32;
+    x updated in binary64 from the binary32 p and q; every replacement step in
+    binary64 on A and x, rounded once when stored: r = f(b - A x),
+    w = f(A (b - A x)) in the iteration that replaces, s = f(A p),
+    z = f(A (A p)) at the start of the next one (Section 4.2 placement "C");
+    the setup is such a replacement and rho_0 = sqrt((r_0, r_0)) with the
+    binary32 dot.  A binary32 recursive residual at or below tol is confirmed
+    by the binary64 ||b - A x|| / rho_0; if that is above tol the iteration
+    replaces r and w, reduces again and goes on without a second stop test.
+
+    ``reading`` names deliberate departures, used to show that the tests can
+    tell them apart: ``"scalars64"`` (the vector updates use the unrounded
+    binary64 scalars, in binary64, rounded when stored), ``"w_of_rounded_r"``
+    (a replacement forms w from the rounded binary32 r instead of the binary64
+    one), ``"rho0_64"`` (rho_0 from the binary64 residual).
+
+    Returns ``(x, info)`` with ``info`` = iters, n_rr, status ("success",
+    "maxit", "breakdown"), relres_rec, relres_true and the history of the
+    recursive relative residuals.
+    """
+    from oracle.ieee import round32 as f32, round64 as f64, sqrt64
+
+    alt = set(reading)
+    unknown = alt - {"scalars64", "w_of_rounded_r", "rho0_64"}
+    if unknown:
+        raise ValueError(f"unknown readings {sorted(unknown)}")
+    n = len(b)
+    A32 = [[(c, f32(a)) for c, a in row] for row in A]
+    tol = Fraction(tol)
+    x = [Fraction(v) for v in x0]
+    b = [Fraction(v) for v in b]
+
+    def spmv64(v):
+        return _spmv_rounded(A, v, f64)
+
+    def spmv32(v):
+        return _spmv_rounded(A32, v, f32)
+
+    def dot32(u, v):
+        return _dot_rounded(u, v, f32)
+
+    def true_residual64():
+        ax = spmv64(x)
+        return [f64(bi - ai) for bi, ai in zip(b, ax)]
+
+    def replace_r_w():
+        """r = f(b - A x), w = f(A (b - A x)): binary64 steps, rounded when stored."""
+        res64 = true_residual64()
+        r_new = [f32(v) for v in res64]
+        w64 = spmv64(r_new if "w_of_rounded_r" in alt else res64)
+        return r_new, [f32(v) for v in w64], res64
+
+    def upd(base, sc, other, sc2=None, third=None):
+        """base + sc (other - sc2 third), or base - sc other when sc2 is None,
+        with the scalars as the vector updates see them."""
+        if "scalars64" in alt:
+            rnd = f64
+        else:
+            rnd = f32
+        if sc2 is None:
+            return [f32(rnd(bv - rnd(sc * ov))) for bv, ov in zip(base, other)]
+        return [f32(rnd(bv + rnd(sc * rnd(ov - rnd(sc2 * tv))))) for bv, ov, tv in zip(base, other, third)]
+
+    def scal(v):
+        return v if "scalars64" in alt else f32(v)
+
+    info = {"iters": 0, "n_rr": 0, "status": "maxit", "relres_rec": Fraction(1), "history": [Fraction(1)]}
+
+    def finish(status):
+        info["status"] = status
+        res = true_residual64()
+        nr = _dot_rounded(res, res, f64)
+        info["relres_true"] = f64(sqrt64(nr) / rho0) if rho0 > 0 else ZERO
+        return x, info
+
+    # setup (a replacement): r_0, w_0, t_0 = A w_0, rho_0, alpha_0
+    r, w, res64 = replace_r_w()
+    r0 = list(r)
+    gamma = dot32(r0, r0)
+    rho0 = sqrt64(_dot_rounded(res64, res64, f64)) if "rho0_64" in alt else sqrt64(gamma)
+    if rho0 == 0:
+        info["relres_rec"] = ZERO
+        return finish("success")
+    t = spmv32(w)
+    delta = dot32(r0, w)
+    if delta == 0:
+        return finish("breakdown")
+    alpha, beta, omega = f64(gamma / delta), ZERO, ZERO
+    p = [ZERO] * n
+    s = [ZERO] * n
+    z = [ZERO] * n
+    v = [ZERO] * n
+    pending = False
+    n_rr = 0
+
+    for i in range(maxit):
+        af, bf, wf = scal(alpha), scal(beta), scal(omega)
+        # search direction, then s and z: by recurrence, or (after a
+        # replacement) recomputed in binary64 from the new p
+        p = upd(r, bf, p, wf, s)
+        if pending:
+            s64 = spmv64(p)
+            s = [f32(e) for e in s64]
+            z = [f32(e) for e in spmv64(s64)]
+            pending = False
+        else:
+            s, z = upd(w, bf, s, wf, z), upd(t, bf, z, wf, v)
+        # q, y; reduction 1; v = A z
+        q = upd(r, af, s)
+        y = upd(w, af, z)
+        th1, th2 = dot32(q, y), dot32(y, y)
+        v = spmv32(z)
+        if th2 == 0:
+            x = [f64(xi + f64(alpha * pi)) for xi, pi in zip(x, p)]
+            info["iters"] = i + 1
+            info["relres_rec"] = ZERO
+            info["history"].append(ZERO)
+            return finish("success")
+        omega = f64(th1 / th2)
+        wn = scal(omega)
+        # binary64 x; binary32 r and w recurrences
+        x = [f64(f64(xi + f64(alpha * pi)) + f64(omega * qi)) for xi, pi, qi in zip(x, p, q)]
+        r = upd(q, wn, y)
+        tav = upd(t, af, v)
+        w = upd(y, wn, tav)
+        info["iters"] = i + 1
+        forced = False
+        replace = rr_period > 0 and (i + 1) % rr_period == 0 and (rr_max < 0 or (i + 1) // rr_period <= rr_max)
+        while True:
+            if replace:
+                r, w, _ = replace_r_w()
+                pending = True
+                n_rr += 1
+                info["n_rr"] = n_rr
+                replace = False
+            # reduction 2 and the stopping test
+            g1, eta, sig_s, sig_z, nu = dot32(r0, r), dot32(r0, w), dot32(r0, s), dot32(r0, z), dot32(r, r)
+            rel = f64(sqrt64(nu) / rho0)
+            info["relres_rec"] = rel
+            if len(info["history"]) == i + 2:
+                info["history"][i + 1] = rel
+            else:
+                info["history"].append(rel)
+            if rel <= tol and not forced:
+                res = true_residual64()
+                if f64(sqrt64(_dot_rounded(res, res, f64)) / rho0) <= tol:
+                    return finish("success")
+                forced = True
+                replace = True
+                continue
+            break
+        t = spmv32(w)
+        if omega == 0 or gamma == 0:
+            return finish("breakdown")
+        beta = f64(f64(alpha / omega) * f64(g1 / gamma))
+        den = f64(f64(eta + f64(beta * sig_s)) - f64(f64(beta * omega) * sig_z))
+        if den == 0 or g1 == 0:
+            return finish("breakdown")
+        alpha = f64(g1 / den)
+        gamma = g1
+    return finish("maxit")

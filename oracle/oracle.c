@@ -23,10 +23,11 @@
  * or_solve_mp is the precision form of Algorithm 9 with residual replacement:
  * binary32 vectors, SpMV, recurrences and dot products, binary64 replacement
  * steps, x update and scalars, and a binary64 true-residual check before any
- * SUCCESS.  Its pins are special cases and accuracy facts (exact binary32
- * cases, tracking of the binary64 iterates, the stall without replacement,
- * the confirmed convergence); its exact rounding sequence beyond them is
- * parity unpinned.
+ * SUCCESS.  Its rounding sequence is pinned operation by operation by an
+ * exact-rational twin that rounds each exact result to binary32 or binary64
+ * as IEEE 754 defines it (exact.py, ieee.py), besides special cases and
+ * accuracy facts (exact binary32 cases, tracking of the binary64 iterates,
+ * the stall without replacement, the confirmed convergence).
  *
  * Residual replacement follows Section 4.2: every k iterations r, r^, w and
  * s, s^, z are recomputed from their definitions (4 SpMVs + 2 preconditioner

@@ -17,8 +17,9 @@ the recurrences.  What mathematics fixes about it, and is checked here:
 * a recursive residual that passes tol while the true one does not forces a
   replacement instead of a false SUCCESS.
 
-Beyond these, the exact rounding sequence of the mixed form has no
-independent reference ("parity unpinned" past the checks above).
+The exact rounding sequence of the mixed form is pinned separately, operation
+by operation, against an exact-rational twin with IEEE 754 rounding
+(``test_oracle_precision_exact.py``).
 """
 
 import json
