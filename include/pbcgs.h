@@ -251,6 +251,29 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
                 const pbcgs_opts* opts, pbcgs_info* info);
 
 /*
+ * pbcgs_solve without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, results and errors as pbcgs_solve; the
+ * solve runs the same kernels and returns the same bits.  Every device buffer
+ * the solve needs beyond b, x and dinv -- the state slots, the partial sums of
+ * the reductions, the 14 workspace vectors and, for JACOBI_FOLDED on a CSR
+ * operator, the values of A M^{-1} -- lies in one statically allocated device
+ * array of the library, about 64.3 MiB, of which a pool of 2^23 doubles holds
+ * the vectors and folded values: 14 per row (rows rounded up to a multiple of
+ * 64) plus one per non-zero when folded must fit in it, else
+ * ERR_UNSUPPORTED (e.g. up to 599,186 rows unfolded; a 64^3 7-point CSR
+ * system folded).  The call calls no hipMalloc or hipFree: kernels are
+ * launched directly (no HIP graph is instantiated), and it refuses the
+ * precision form and kernel timing (opts.flags bit 1) with ERR_UNSUPPORTED.
+ * Each device that loads the library holds one copy of the array until the
+ * process ends; every call on that device shares it and leaves the last
+ * call's contents there (each solve initialises what it reads), so calls that
+ * overlap on one device -- from two contexts or two threads -- race.
+ */
+int pbcgs_solve_noalloc(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const double* dinv,
+                        const pbcgs_opts* opts, pbcgs_info* info);
+
+/*
  * Batched solve of nsys independent systems A[k] x[k] = b[k] with the same
  * options (the batched workload of many small and large systems).  A: HOST
  * array of nsys CSR operators of ctx; b, x: HOST arrays of nsys DEVICE

@@ -96,6 +96,7 @@ _SIGNATURES = {
     "pbcgs_dot": (ctypes.c_int, [_vp, _i64, _vp, _vp, ctypes.POINTER(_f64)]),
     "pbcgs_jacobi_dinv": (ctypes.c_int, [_vp, _vp, _vp]),
     "pbcgs_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
+    "pbcgs_solve_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
     "pbcgs_solve_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                            ctypes.POINTER(_vp), ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
     "pbcgs_tune": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(Opts), _i32, ctypes.POINTER(TuneReport)]),

@@ -1699,6 +1699,11 @@ __global__ void k_init_state(DevState* st, double tol) {
   }
 }
 
+// Clears a structural-error flag word.
+__global__ void k_clear_flag(int32_t* flag) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 0;
+}
+
 template <class Op>
 __global__ __launch_bounds__(kWG) void k_spmv(Op op, Args a, const double* __restrict__ xin,
                                               double* __restrict__ yout) {

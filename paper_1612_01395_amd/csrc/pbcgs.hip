@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -28,6 +29,59 @@ enum OpKind { OP_CSR = 0, OP_ST5 = 1, OP_ST7 = 2 };
 // Partial-sum buffers, one per producing kernel role.
 enum PartBuf { PB_SETUP1 = 0, PB_SETUP2, PB_A, PB_B, PB_B1, PB_B3, PB_B4, PB_UTIL, PB_COUNT };
 
+// Device memory of pbcgs_solve_noalloc: four state slots, the partial-sum
+// buffers and a pool of doubles for the solver vectors (and A M^{-1} of a
+// folded CSR solve).  One copy per device, shared by every call on it.
+constexpr size_t kScratchStates = 4;
+constexpr size_t kScratchPartDoubles = (size_t)PB_COUNT * kMaxD * kMaxG;
+constexpr size_t kScratchPoolDoubles = (size_t)1 << 23;  // 64 MiB
+constexpr size_t kScratchPartOffset = kScratchStates * sizeof(DevState);
+constexpr size_t kScratchPoolOffset = kScratchPartOffset + kScratchPartDoubles * sizeof(double);
+constexpr size_t kScratchBytes = kScratchPoolOffset + kScratchPoolDoubles * sizeof(double);
+static_assert(kScratchPartOffset % 256 == 0 && kScratchPoolOffset % 256 == 0, "scratch regions stay 256-byte aligned");
+
+}  // namespace
+
+// The array itself.  Its name is a host-side stand-in in host code: kernels
+// receive the device address that hipGetSymbolAddress returns (scratch_address).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (every device holds its own copy at its own address).
+struct ScratchTable {
+  std::mutex mu;
+  std::map<int, void*> addr;
+  std::map<int, std::string> err;
+};
+ScratchTable& scratch_table() {
+  static ScratchTable t;
+  return t;
+}
+
+// Called with `device` current.  Returns the address, or nullptr with *why set.
+void* scratch_address(int device, std::string* why) {
+  ScratchTable& t = scratch_table();
+  std::lock_guard<std::mutex> lock(t.mu);
+  auto it = t.addr.find(device);
+  if (it != t.addr.end()) return it->second;
+  auto e = t.err.find(device);
+  if (e != t.err.end()) {
+    *why = e->second;
+    return nullptr;
+  }
+  void* ptr = nullptr;
+  const hipError_t rc = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (rc != hipSuccess || !ptr) {
+    *why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(rc);
+    t.err[device] = *why;
+    return nullptr;
+  }
+  t.addr[device] = ptr;
+  return ptr;
+}
+
 }  // namespace
 
 struct pbcgs_ctx_s {
@@ -35,7 +89,7 @@ struct pbcgs_ctx_s {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   DevState* st = nullptr;   // state slots (device): 0, 1 solver ring; 2, 3 utility reductions
-  DevState* hst = nullptr;  // pinned host copies for polling (two slots)
+  DevState* hst = nullptr;  // pinned host copies: slots 0, 1 for polling, 2 for reads of a state or a scalar
   int32_t* flag = nullptr;  // structural error flags of utility kernels
   GridBar* bar = nullptr;   // grid barrier of the persistent form
   int64_t* qout = nullptr;  // phases run by the persistent form
@@ -67,6 +121,9 @@ struct pbcgs_ctx_s {
   std::vector<hipEvent_t> kev;  // pool for per-kernel timing
   std::map<std::string, hipGraphExec_t> graphs;
   std::string err;
+  unsigned char* scratch = nullptr;  // device address of this device's `scratch` (nullptr: unavailable)
+  std::string scratch_err;
+  bool noalloc = false;              // inside pbcgs_solve_noalloc: nothing may be allocated
 };
 
 struct pbcgs_op_s {
@@ -189,6 +246,7 @@ double* part_buf(pbcgs_ctx_t ctx, int which) { return ctx->part + (size_t)which 
 
 int ensure_ws(pbcgs_ctx_t ctx, size_t doubles) {
   if (ctx->ws_cap >= doubles) return PBCGS_SUCCESS;
+  if (ctx->noalloc) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the call may not allocate and its scratch is too small");
   if (ctx->ws) {
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipFree(ctx->ws);
@@ -207,6 +265,7 @@ int ensure_ws(pbcgs_ctx_t ctx, size_t doubles) {
 
 int ensure_ahat(pbcgs_ctx_t ctx, size_t doubles) {
   if (ctx->ahat_cap >= doubles) return PBCGS_SUCCESS;
+  if (ctx->noalloc) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the call may not allocate and its scratch is too small");
   if (ctx->ahat) {
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipFree(ctx->ahat);
@@ -223,6 +282,7 @@ int ensure_ahat(pbcgs_ctx_t ctx, size_t doubles) {
 
 int ensure_a32(pbcgs_ctx_t ctx, size_t floats) {
   if (ctx->a32_cap >= floats) return PBCGS_SUCCESS;
+  if (ctx->noalloc) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the call may not allocate and its scratch is too small");
   if (ctx->a32) {
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipFree(ctx->a32);
@@ -257,14 +317,25 @@ StencilOp<NPTS, float> to_binary32(pbcgs_ctx_t, const StencilOp<NPTS, double>& o
 
 size_t padded(int32_t n) { return ((size_t)n + 63) / 64 * 64; }
 
+// Reads go through the context's pinned slot 2 (no pageable staging).
 int read_state(pbcgs_ctx_t ctx, int slot, DevState* out) {
-  HIP_TRY(ctx, hipMemcpyAsync(out, ctx->st + slot, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(&ctx->hst[2], ctx->st + slot, sizeof(DevState), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  *out = ctx->hst[2];
   return PBCGS_SUCCESS;
 }
 
+int read_double(pbcgs_ctx_t ctx, const double* dev, double* out) {
+  HIP_TRY(ctx, hipMemcpyAsync(&ctx->hst[2].result, dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  *out = ctx->hst[2].result;
+  return PBCGS_SUCCESS;
+}
+
+// A kernel, not a memset, clears the flag word.
 int reset_flag(pbcgs_ctx_t ctx) {
-  HIP_TRY(ctx, hipMemsetAsync(ctx->flag, 0, sizeof(int32_t), ctx->stream));
+  k_clear_flag<<<1, 64, 0, ctx->stream>>>(ctx->flag);
+  HIP_TRY(ctx, hipGetLastError());
   return PBCGS_SUCCESS;
 }
 
@@ -608,6 +679,7 @@ struct Driver {
   // larger the grid, so the graph schedule is the default at every size.
   bool use_persistent() {
     if constexpr (MP) return false;
+    if (ctx->noalloc) return false;
     if (o.flags & 2) return false;
     if (o.variant >= PBCGS_CA_BICGSTAB) return false;
     if (o.maxit > 200000) return false;
@@ -662,8 +734,9 @@ struct Driver {
 
   int run(pbcgs_info* info) {
     if (use_persistent()) return run_persistent(info);
-    const bool use_graph = !(o.flags & 1) && !(o.flags & 2);
-    timing = (o.flags & 2) != 0;
+    // graphs are instantiated (allocated) on first use: never without allocation
+    const bool use_graph = !(o.flags & 1) && !(o.flags & 2) && !ctx->noalloc;
+    timing = (o.flags & 2) != 0 && !ctx->noalloc;
     const int check = o.check_every > 0 ? o.check_every : (a.n >= (1 << 20) ? 8 : 32);
     hipStream_t s = ctx->stream;
     HIP_TRY(ctx, hipEventRecord(ctx->ev_start, s));
@@ -832,6 +905,7 @@ namespace {
 template <class T>
 int grow(pbcgs_ctx_t ctx, T*& p, size_t& cap, size_t count, const char* what) {
   if (cap >= count) return PBCGS_SUCCESS;
+  if (ctx->noalloc) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the call may not allocate");
   if (p) {
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipFree(p);
@@ -1103,7 +1177,7 @@ int pbcgs_ctx_create(int device, void* hip_stream, pbcgs_ctx_t* out) {
             hipMalloc(&c->flag, 64) == hipSuccess &&
             hipMalloc(&c->bar, sizeof(GridBar)) == hipSuccess &&
             hipMalloc(&c->qout, sizeof(int64_t)) == hipSuccess &&
-            hipHostMalloc(&c->hst, 2 * sizeof(DevState), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(&c->hst, 3 * sizeof(DevState), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc(&c->hflag, 64, hipHostMallocDefault) == hipSuccess &&
             hipEventCreate(&c->ev_start) == hipSuccess && hipEventCreate(&c->ev_stop) == hipSuccess &&
             hipEventCreateWithFlags(&c->ev_poll[0], hipEventDisableTiming) == hipSuccess &&
@@ -1112,6 +1186,8 @@ int pbcgs_ctx_create(int device, void* hip_stream, pbcgs_ctx_t* out) {
     pbcgs_ctx_destroy(c);
     return fail(nullptr, PBCGS_ERR_ALLOC, "context allocation failed");
   }
+  // the no-allocation solve's device array, once per device (the guard made it current)
+  c->scratch = static_cast<unsigned char*>(scratch_address(device, &c->scratch_err));
   k_init_state<<<1, 64, 0, c->stream>>>(c->st, 0.0);
   k_init_state<<<1, 64, 0, c->stream>>>(c->st + 1, 0.0);
   if (hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -1448,8 +1524,8 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
         a.dinv = dv;
       } else {
         pc = PC_SCALAR;
-        HIP_TRY(ctx, hipMemcpyAsync(&a.dinv_s, dv, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        rc = read_double(ctx, dv, &a.dinv_s);
+        if (rc != PBCGS_SUCCESS) return rc;
       }
     }
   }
@@ -1576,6 +1652,50 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     if (pc == PC_VEC) return Driver<Op, PC_VEC>(ctx, op, a, o).run(info);
     return Driver<Op, PC_SCALAR>(ctx, op, a, o).run(info);
   }, compact_ok(o));
+}
+
+// The same solve with every device buffer it needs taken from `scratch`
+// (see include/pbcgs.h): the context's state slots, partial sums and
+// workspace are swapped for regions of the array for the duration of the call,
+// and any attempt to allocate fails instead.
+int pbcgs_solve_noalloc(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const double* dinv,
+                        const pbcgs_opts* opts, pbcgs_info* info) {
+  if (!ctx || !A || !opts) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  if (!ctx->scratch) return fail(ctx, PBCGS_ERR_HIP, "no scratch array on this device: " + ctx->scratch_err);
+  if (opts->precision != PBCGS_FP64)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "pbcgs_solve_noalloc runs binary64 solves only");
+  if (opts->flags & 2)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "pbcgs_solve_noalloc does not time kernels (events would be created)");
+  const size_t vec = padded(A->n) * 14;
+  const size_t folded_vals =
+      (opts->precond == PBCGS_PRECOND_JACOBI_FOLDED && A->kind == OP_CSR) ? (size_t)std::max<int64_t>(A->nnz, 1) : 0;
+  if (vec + folded_vals > kScratchPoolDoubles)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED,
+                "pbcgs_solve_noalloc needs " + std::to_string(vec + folded_vals) + " doubles of scratch (14 per row" +
+                    (folded_vals ? " plus one per non-zero" : "") + "); at most " +
+                    std::to_string(kScratchPoolDoubles) + " are available");
+  struct View {
+    pbcgs_ctx_t c;
+    DevState* st;
+    double *part, *ws, *ahat;
+    size_t ws_cap, ahat_cap;
+    explicit View(pbcgs_ctx_t c_)
+        : c(c_), st(c_->st), part(c_->part), ws(c_->ws), ahat(c_->ahat), ws_cap(c_->ws_cap), ahat_cap(c_->ahat_cap) {}
+    ~View() {
+      c->st = st; c->part = part; c->ws = ws; c->ahat = ahat;
+      c->ws_cap = ws_cap; c->ahat_cap = ahat_cap;
+      c->noalloc = false;
+    }
+  } view(ctx);
+  double* pool = reinterpret_cast<double*>(ctx->scratch + kScratchPoolOffset);
+  ctx->st = reinterpret_cast<DevState*>(ctx->scratch);
+  ctx->part = reinterpret_cast<double*>(ctx->scratch + kScratchPartOffset);
+  ctx->ws = pool;
+  ctx->ws_cap = vec;
+  ctx->ahat = pool + vec;
+  ctx->ahat_cap = kScratchPoolDoubles - vec;
+  ctx->noalloc = true;
+  return pbcgs_solve(ctx, A, b, x, dinv, opts, info);
 }
 
 // Transpose of a CSR operator (see include/pbcgs.h).

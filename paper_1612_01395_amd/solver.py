@@ -252,6 +252,29 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
     5 takes alpha_{i+1} of the pipelined variants from eq. (5) instead of
     eq. (3) (Section 3.1).  ``index32`` reads the int32 column indices even
     where the operator holds a compact copy (same result)."""
+    return _solve(L.lib().pbcgs_solve, A, b, x0, variant=variant, precond=precond, dinv=dinv, tol=tol,
+                  maxit=maxit, rr_period=rr_period, rr_max=rr_max, history=history, check_every=check_every,
+                  graph=graph, time_kernels=time_kernels, out=out, precision=precision, alpha_form=alpha_form,
+                  index32=index32)
+
+
+def solve_noalloc(A: Operator, b: torch.Tensor, x: torch.Tensor, *, variant: str = "pbicgstab_rr",
+                  precond: str | None = None, dinv: torch.Tensor | None = None, tol: float = 1e-8,
+                  maxit: int = 2000, rr_period: int = 50, rr_max: int = -1, history: torch.Tensor | None = None,
+                  check_every: int = 0, alpha_form: int = 3, index32: bool = False):
+    """``pbcgs_solve_noalloc``: the binary64 solve with every device buffer
+    taken from the library's static scratch array, for callers that cannot
+    allocate.  ``x`` holds x_0 and receives the iterate in place; ``history``
+    (optional) is a caller-provided tensor of maxit + 1 doubles.  Nothing is
+    allocated here either.  Returns (x, SolveInfo)."""
+    return _solve(L.lib().pbcgs_solve_noalloc, A, b, None, variant=variant, precond=precond, dinv=dinv, tol=tol,
+                  maxit=maxit, rr_period=rr_period, rr_max=rr_max, history=history, check_every=check_every,
+                  graph=False, time_kernels=False, out=x, keep_x=True, precision="fp64", alpha_form=alpha_form,
+                  index32=index32)
+
+
+def _solve(entry, A: Operator, b: torch.Tensor, x0, *, variant, precond, dinv, tol, maxit, rr_period, rr_max,
+           history, check_every, graph, time_kernels, out, precision, alpha_form, index32, keep_x=False):
     _check_vec(b, A.n, "b")
     _check_alpha_form(alpha_form)
     if variant not in VARIANTS:
@@ -263,7 +286,9 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
     if out is not None:
         _check_vec(out, A.n, "out")
         x = out
-        if x0 is None:
+        if keep_x:
+            pass  # the caller's x holds x_0
+        elif x0 is None:
             x.zero_()
         else:
             x.copy_(x0)
@@ -272,7 +297,11 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
     _check_vec(x, A.n, "x")
     if dinv is not None:
         _check_vec(dinv, A.n, "dinv")
-    hist = torch.full((maxit + 1,), float("nan"), dtype=torch.float64, device=b.device) if history else None
+    if isinstance(history, torch.Tensor):
+        _check_vec(history, maxit + 1, "history")
+        hist = history
+    else:
+        hist = torch.full((maxit + 1,), float("nan"), dtype=torch.float64, device=b.device) if history else None
     o = L.Opts()
     o.variant = VARIANTS[variant]
     o.precond = PRECONDS[precond]
@@ -286,8 +315,8 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
                | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0) | (L.FLAG_INDEX32 if index32 else 0))
     o.history = hist.data_ptr() if hist is not None else None
     info = L.Info()
-    L.check(L.lib().pbcgs_solve(A.ctx.handle, A.handle, _ptr(b), _ptr(x), _ptr(dinv), ctypes.byref(o),
-                                ctypes.byref(info)), A.ctx.handle)
+    L.check(entry(A.ctx.handle, A.handle, _ptr(b), _ptr(x), _ptr(dinv), ctypes.byref(o), ctypes.byref(info)),
+            A.ctx.handle)
     si = SolveInfo(info.iters, info.n_rr, info.status, info.syncs_per_iter, info.relres_rec, info.relres_true,
                    info.ms, tuple(info.kernel_ms), tuple(info.kernel_calls))
     if hist is not None:
