@@ -2,7 +2,8 @@
  * pbcgs -- pipelined BiCGStab with residual replacement on one MI355X (gfx950).
  *
  * C ABI of the HIP library libpbcgs.so.  It solves A x = b for a sparse A
- * (CSR, or a matrix-free constant-coefficient 5/7-point stencil) with the
+ * (CSR, a matrix-free constant-coefficient 5/7-point stencil, or the
+ * matrix-free variable-coefficient 27-point convection-diffusion operator) with the
  * Krylov methods of S. Cools and W. Vanroose, "The communication-hiding
  * pipelined BiCGStab method for the parallel solution of large unsymmetric
  * linear systems" (arXiv 1612.01395): the BiCGStab variants for unsymmetric
@@ -192,6 +193,31 @@ int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr
  */
 int pbcgs_op_stencil(pbcgs_ctx_t ctx, int32_t nx, int32_t ny, int32_t nz, int32_t npts,
                      const double* coef, pbcgs_op_t* out);
+
+/*
+ * Matrix-free 27-point variable-coefficient convection-diffusion operator
+ * (the SPMV building block of Section 2 without a stored matrix): exactly the
+ * operator pbcgs_assemble_convdiff(ctx, 3, n, 27, beta, kappa, shift, ...)
+ * assembles, applied without storing it.  n^3 interior nodes of the unit
+ * cube, h = 1/(n+1), rows x fastest, Dirichlet boundaries.  kappa: DEVICE
+ * array of (n+1)^3 cell coefficients, x fastest, borrowed (it must outlive the
+ * operator; values may change between calls).  beta: HOST array of 3
+ * convection coefficients; hb_a = beta_a / (n+1).  For each of the 26
+ * neighbours p + d the coupling is -kbar_d, the mean of the cell coefficients
+ * the two nodes share (4, 2 or 1 cells), minus |hb_a| on the upwind face of
+ * axis a (p - e_a when beta_a >= 0, else p + e_a); the diagonal is the sum of
+ * all 26 kbar_d, plus (|hb_x| + |hb_y|) + |hb_z|, plus shift.  Every entry is
+ * formed in the assembly's operation order and each row is summed in
+ * ascending column order, so products, solves and Jacobi (dinv = 1 / a_ii
+ * from the formed diagonal) equal those on the assembled CSR matrix bit for
+ * bit, while a product reads 8 bytes of kappa per row instead of about 270
+ * bytes of matrix.  JACOBI_FOLDED scales each entry by dinv_j as it is formed
+ * (the same single rounding as the folded CSR values).  Not transposable
+ * (ERR_UNSUPPORTED), not batched.  ERR_UNSUPPORTED when n^3 exceeds the launch
+ * limit of pbcgs_op_csr.
+ */
+int pbcgs_op_convdiff27(pbcgs_ctx_t ctx, int32_t n, const double* kappa, const double* beta, double shift,
+                        pbcgs_op_t* out);
 
 int pbcgs_op_destroy(pbcgs_op_t op);
 

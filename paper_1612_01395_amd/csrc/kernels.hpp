@@ -243,6 +243,140 @@ struct StencilOp {
   }
 };
 
+// Matrix-free 27-point variable-coefficient convection-diffusion operator on
+// the n^3 interior nodes of the unit cube (h = 1/(n+1)), Dirichlet boundaries,
+// rows x fastest.  Its entries are formed from the (n+1)^3 cell coefficients
+// kappa exactly as the workload's assembly forms them: for each offset d of
+// the 26 neighbours, in (dz, dy, dx) order, kbar_d is the sum of the 4, 2 or 1
+// cells node p shares with p + d (in (c, b, a) order, from 0.0) times
+// 1/count; the coupling is -kbar_d, minus |hb_a| on the upwind face of axis
+// a; the diagonal is (sum of all 26 kbar_d + hsum) + shift.  The row is then
+// summed in ascending column order from 0, so the product equals the
+// assembled CSR product bit for bit.  FOLD: the entries are scaled by the
+// column's dscale (A M^{-1}, each a_ij * dinv_j rounded once, as the folded
+// CSR values are).  V: the arithmetic type of the product; a binary32 product
+// rounds each binary64 entry once, like the binary32 copy of a CSR operator.
+template <class V, bool FOLD>
+struct Conv27Op {
+  using Val = V;
+  int32_t n;
+  int32_t upneg;                          // bit a: beta_a >= 0, the upwind neighbour is p - e_a
+  const double* __restrict__ kappa;       // (n+1)^3 cells, x fastest
+  const double* __restrict__ dscale;      // FOLD: dinv per column
+  double hab[3];                          // |hb_a| = |beta_a / (n+1)|
+  double hsum;                            // (|hb_x| + |hb_y|) + |hb_z|
+  double shift;
+
+  // The cells node (i, j, k) touches: K[c][b][a] = kappa(i+a, j+b, k+c).
+  __device__ __forceinline__ void cells(int32_t i, int32_t j, int32_t k, double (&K)[2][2][2]) const {
+    const int64_t cn = (int64_t)n + 1;
+    const double* kp = kappa + (i + cn * (j + cn * (int64_t)k));
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) K[c][b][a] = kp[a + cn * (b + cn * c)];
+  }
+
+  // kbar of offset e = (dz+1)*9 + (dy+1)*3 + (dx+1), e != 13.
+  template <int E>
+  static __device__ __forceinline__ double kbar(const double (&K)[2][2][2]) {
+    constexpr int dx = E % 3 - 1, dy = (E / 3) % 3 - 1, dz = E / 9 - 1;
+    constexpr int alo = dx > 0 ? 1 : 0, ahi = dx < 0 ? 0 : 1;
+    constexpr int blo = dy > 0 ? 1 : 0, bhi = dy < 0 ? 0 : 1;
+    constexpr int clo = dz > 0 ? 1 : 0, chi = dz < 0 ? 0 : 1;
+    constexpr int cnt = (ahi - alo + 1) * (bhi - blo + 1) * (chi - clo + 1);
+    double ks = 0.0;
+#pragma unroll
+    for (int c = clo; c <= chi; ++c)
+#pragma unroll
+      for (int b = blo; b <= bhi; ++b)
+#pragma unroll
+        for (int a = alo; a <= ahi; ++a) ks = ks + K[c][b][a];
+    return ks * (1.0 / (double)cnt);
+  }
+
+  template <int E>
+  static __device__ __forceinline__ void kbars(const double (&K)[2][2][2], double (&kb)[27], double& dsum) {
+    if constexpr (E < 27) {
+      if constexpr (E != 13) {
+        kb[E] = kbar<E>(K);
+        dsum = dsum + kb[E];
+      }
+      kbars<E + 1>(K, kb, dsum);
+    }
+  }
+
+  // Entry E of the row, and the product term it adds (when the neighbour exists).
+  template <int E, class X>
+  __device__ __forceinline__ void term(int32_t row, int32_t i, int32_t j, int32_t k, const double (&kb)[27],
+                                       double diag, const X* __restrict__ x, V& acc) const {
+    if constexpr (E < 27) {
+      constexpr int dx = E % 3 - 1, dy = (E / 3) % 3 - 1, dz = E / 9 - 1;
+      const bool in = (dx < 0 ? i > 0 : (dx > 0 ? i < n - 1 : true)) &&
+                      (dy < 0 ? j > 0 : (dy > 0 ? j < n - 1 : true)) &&
+                      (dz < 0 ? k > 0 : (dz > 0 ? k < n - 1 : true));
+      if (in) {
+        double a;
+        if constexpr (E == 13) {
+          a = diag;
+        } else {
+          a = -kb[E];
+          constexpr int nzc = (dx != 0) + (dy != 0) + (dz != 0);
+          if constexpr (nzc == 1) {
+            constexpr int ax = dx != 0 ? 0 : (dy != 0 ? 1 : 2);
+            constexpr int side = dx != 0 ? dx : (dy != 0 ? dy : dz);
+            const bool upwind = ((upneg >> ax) & 1) ? (side < 0) : (side > 0);
+            if (upwind) a = -kb[E] - hab[ax];
+          }
+        }
+        const int32_t col = row + dx + n * dy + n * n * dz;
+        if constexpr (FOLD) a = a * dscale[col];
+        acc = acc + V(a) * V(x[col]);
+      }
+      term<E + 1>(row, i, j, k, kb, diag, x, acc);
+    }
+  }
+
+  __device__ __forceinline__ double diag_of(const double (&kb)[27], double dsum) const {
+    (void)kb;
+    return (dsum + hsum) + shift;
+  }
+
+  // a_ii of row `row` (the unscaled operator).
+  __device__ __forceinline__ double diagonal(int32_t row) const {
+    const int32_t i = row % n, jk = row / n, j = jk % n, k = jk / n;
+    double K[2][2][2], kb[27];
+    cells(i, j, k, K);
+    double dsum = 0.0;
+    kbars<0>(K, kb, dsum);
+    return diag_of(kb, dsum);
+  }
+
+  template <class X>
+  __device__ __forceinline__ V spmv(int32_t row, bool valid, const X* __restrict__ x) const {
+    return valid ? apply(row, x) : V(0);
+  }
+  template <class X>
+  __device__ __forceinline__ V apply(int32_t row, const X* __restrict__ x) const {
+    const int32_t i = row % n, jk = row / n, j = jk % n, k = jk / n;
+    double K[2][2][2], kb[27];
+    cells(i, j, k, K);
+    double dsum = 0.0;
+    kbars<0>(K, kb, dsum);
+    const double diag = diag_of(kb, dsum);
+    V acc = V(0);
+    term<0>(row, i, j, k, kb, diag, x, acc);
+    return acc;
+  }
+};
+using Conv27 = Conv27Op<double, false>;
+using Conv27F = Conv27Op<double, true>;
+
+template <class Op> struct IsConv27 : std::false_type {};
+template <class V, bool F> struct IsConv27<Conv27Op<V, F>> : std::true_type {};
+
 // Preconditioner modes: none (Algorithms 7 and 9), Jacobi with a vector of
 // 1/a_ii, Jacobi with one constant 1/a_ii (constant diagonal).
 enum { PC_NONE = 0, PC_VEC = 1, PC_SCALAR = 2 };
@@ -1770,6 +1904,14 @@ __global__ __launch_bounds__(kWG) void k_dinv_csr(CsrOp op, int32_t n, double* d
 }
 
 // flag bit 1 unless every dinv_i equals dinv_0 (then Jacobi is one scalar).
+// Jacobi of the matrix-free 27-point operator: dinv = 1 / a_ii from its formed diagonal.
+__global__ __launch_bounds__(kWG) void k_dinv_conv27(Conv27 op, int32_t n, double* dinv, int32_t* flag) {
+  const int32_t row = blockIdx.x * kWG + threadIdx.x;
+  if (row >= n) return;
+  const double d = op.diagonal(row);
+  if (d == 0.0 || !finite(d)) atomicOr(flag, 1);
+  dinv[row] = 1.0 / d;
+}
 __global__ __launch_bounds__(kWG) void k_dinv_const(int32_t n, const double* dinv, int32_t* flag) {
   const int32_t row = blockIdx.x * kWG + threadIdx.x;
   if (row >= n) return;

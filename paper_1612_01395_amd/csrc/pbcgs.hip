@@ -24,7 +24,7 @@ namespace {
 
 thread_local std::string g_last_error;
 
-enum OpKind { OP_CSR = 0, OP_ST5 = 1, OP_ST7 = 2 };
+enum OpKind { OP_CSR = 0, OP_ST5 = 1, OP_ST7 = 2, OP_CV27 = 3 };
 
 // Partial-sum buffers, one per producing kernel role.
 enum PartBuf { PB_SETUP1 = 0, PB_SETUP2, PB_A, PB_B, PB_B1, PB_B3, PB_B4, PB_UTIL, PB_COUNT };
@@ -136,6 +136,10 @@ struct pbcgs_op_s {
   const double* va = nullptr;
   int32_t nx = 0, ny = 0, nz = 0;
   double coef[7] = {0, 0, 0, 0, 0, 0, 0};
+  // matrix-free 27-point operator: cell coefficients (borrowed) and the convection terms
+  const double* kappa = nullptr;
+  double hb[3] = {0, 0, 0};
+  double shift = 0.0;
   int32_t tuned_R = 0;  // rows-per-wave blocks chosen by pbcgs_tune (0: default shape)
   // arrays the library allocated for this operator (a transpose), freed with it
   int32_t* own_rp = nullptr;
@@ -313,6 +317,11 @@ StencilOp<NPTS, float> to_binary32(pbcgs_ctx_t, const StencilOp<NPTS, double>& o
   f.nx = op.nx; f.ny = op.ny; f.nz = op.nz;
   for (int k = 0; k < NPTS; ++k) f.c[k] = float(op.c[k]);
   return f;
+}
+
+template <bool F>
+Conv27Op<float, F> to_binary32(pbcgs_ctx_t, const Conv27Op<double, F>& op, int64_t) {
+  return Conv27Op<float, F>{op.n, op.upneg, op.kappa, op.dscale, {op.hab[0], op.hab[1], op.hab[2]}, op.hsum, op.shift};
 }
 
 size_t padded(int32_t n) { return ((size_t)n + 63) / 64 * 64; }
@@ -865,6 +874,23 @@ static_assert(sizeof(StencilOp<7>) == 4 * sizeof(int32_t) + 7 * sizeof(double), 
 static_assert(sizeof(StencilOp<5>) == 4 * sizeof(int32_t) + 5 * sizeof(double), "StencilOp padding");
 static_assert(sizeof(StencilOp<7, float>) == 4 * sizeof(int32_t) + 7 * sizeof(float), "StencilOp padding");
 static_assert(sizeof(StencilOp<5, float>) == 4 * sizeof(int32_t) + 5 * sizeof(float), "StencilOp padding");
+static_assert(sizeof(Conv27) == 2 * sizeof(int32_t) + 2 * sizeof(void*) + 5 * sizeof(double) &&
+              sizeof(Conv27Op<float, true>) == sizeof(Conv27), "Conv27Op padding");
+
+// The matrix-free 27-point operator of A (kind OP_CV27).
+Conv27 conv27_of(pbcgs_op_t A) {
+  Conv27 c;
+  std::memset(&c, 0, sizeof c);
+  c.n = A->nx;
+  c.kappa = A->kappa;
+  for (int ax = 0; ax < 3; ++ax) {
+    c.hab[ax] = std::fabs(A->hb[ax]);
+    if (A->hb[ax] >= 0.0) c.upneg |= 1 << ax;
+  }
+  c.hsum = (c.hab[0] + c.hab[1]) + c.hab[2];
+  c.shift = A->shift;
+  return c;
+}
 
 // f(op) with the operator's device form: for CSR the compact copy the
 // operator holds (int16 block offsets or diagonal codes) when `compact`
@@ -876,6 +902,7 @@ int with_op(pbcgs_op_t A, F f, bool compact = true) {
     if (compact && A->cd) return f(CsrOpDg{A->rp, A->cd, A->va, A->n, 0, A->dg});
     return f(CsrOp{A->rp, A->ci, A->va, A->n});
   }
+  if (A->kind == OP_CV27) return f(conv27_of(A));
   if (A->kind == OP_ST7) {
     StencilOp<7> s;
     std::memset(&s, 0, sizeof s);
@@ -888,6 +915,31 @@ int with_op(pbcgs_op_t A, F f, bool compact = true) {
   s.nx = A->nx; s.ny = A->ny; s.nz = 1;
   for (int k = 0; k < 5; ++k) s.c[k] = A->coef[k];
   return f(s);
+}
+
+// A M^{-1} (Section 3.6 with the product formed), each entry a_ij * dinv_j
+// rounded once: CSR values written to the context's ahat (enough room made by
+// the caller), stencil coefficients scaled by the constant dinv, the
+// matrix-free 27-point operator scaling its entries by dinv as it forms them.
+template <class Op>
+auto fold_operator(pbcgs_ctx_t ctx, pbcgs_op_t A, const Op& op, int pc, const double* dv, double ds) {
+  if constexpr (IsCsr<Op>::value) {
+    const int fg = (int)std::min<int64_t>((A->nnz + kWG - 1) / kWG, 8192);
+    const CsrOp op32i{A->rp, A->ci, A->va, A->n};  // the fold reads each entry's int32 column
+    if (A->nnz > 0) {
+      if (pc == PC_VEC) k_fold_csr<PC_VEC><<<fg, kWG, 0, ctx->stream>>>(op32i, A->nnz, ctx->ahat, dv, ds);
+      else k_fold_csr<PC_SCALAR><<<fg, kWG, 0, ctx->stream>>>(op32i, A->nnz, ctx->ahat, dv, ds);
+    }
+    Op fop = op;
+    fop.va = ctx->ahat;
+    return fop;
+  } else if constexpr (IsConv27<Op>::value) {
+    return Conv27Op<double, true>{op.n, op.upneg, op.kappa, dv, {op.hab[0], op.hab[1], op.hab[2]}, op.hsum, op.shift};
+  } else {
+    Op fop = op;
+    for (double& c : fop.c) c = c * ds;  // one rounding per coefficient, as a_ij * dinv_j
+    return fop;
+  }
 }
 
 }  // namespace
@@ -1367,6 +1419,28 @@ int pbcgs_op_stencil(pbcgs_ctx_t ctx, int32_t nx, int32_t ny, int32_t nz, int32_
   return PBCGS_SUCCESS;
 }
 
+int pbcgs_op_convdiff27(pbcgs_ctx_t ctx, int32_t n, const double* kappa, const double* beta, double shift,
+                        pbcgs_op_t* out) {
+  if (!ctx || !out || !kappa || !beta) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  if (n <= 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad grid size");
+  const int64_t N = (int64_t)n * n * n;
+  if (N > INT32_MAX) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "grid too large");
+  Shape sh;
+  if (!make_shape((int32_t)N, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows for one launch");
+  pbcgs_op_t A = new pbcgs_op_s();
+  A->ctx = ctx;
+  A->kind = OP_CV27;
+  A->n = (int32_t)N;
+  A->nx = A->ny = A->nz = n;
+  A->kappa = kappa;
+  for (int ax = 0; ax < 3; ++ax) A->hb[ax] = beta[ax] / (double)(n + 1);  // one IEEE division, as assembled
+  A->shift = shift;
+  const int64_t m = 3 * (int64_t)n - 2;  // stored entries of the equivalent CSR matrix
+  A->nnz = m * m * m;
+  *out = A;
+  return PBCGS_SUCCESS;
+}
+
 int pbcgs_op_destroy(pbcgs_op_t op) {
   if (!op) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "op is NULL");
   pbcgs_ctx_t ctx = op->ctx;
@@ -1438,6 +1512,16 @@ int pbcgs_dot(pbcgs_ctx_t ctx, int64_t n, const double* x, const double* y, doub
 int pbcgs_jacobi_dinv(pbcgs_ctx_t ctx, pbcgs_op_t A, double* dinv) {
   if (!ctx || !A || !dinv) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
   DeviceGuard guard(ctx->device);
+  if (A->kind == OP_CV27) {
+    int rc = reset_flag(ctx);
+    if (rc != PBCGS_SUCCESS) return rc;
+    k_dinv_conv27<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(conv27_of(A), A->n, dinv, ctx->flag);
+    int32_t flag = 0;
+    rc = read_flag(ctx, &flag);
+    if (rc != PBCGS_SUCCESS) return rc;
+    if (flag & 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero or non-finite diagonal entry");
+    return PBCGS_SUCCESS;
+  }
   if (A->kind != OP_CSR) {
     const double c = (A->kind == OP_ST7) ? A->coef[3] : A->coef[2];
     if (c == 0.0 || !std::isfinite(c)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero diagonal");
@@ -1500,9 +1584,10 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
 
   // preconditioner mode: none, a vector of 1/a_ii, or one constant
   int pc = PC_NONE;
+  const double* dinv_vec = nullptr;  // the vector of 1/a_ii when there is one (also when constant)
   if (o.precond != PBCGS_PRECOND_NONE) {
     const double* dv = dinv;
-    if (!dv && A->kind != OP_CSR) {
+    if (!dv && (A->kind == OP_ST5 || A->kind == OP_ST7)) {
       const double c = (A->kind == OP_ST7) ? A->coef[3] : A->coef[2];
       if (c == 0.0 || !std::isfinite(c)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero diagonal");
       pc = PC_SCALAR;
@@ -1513,6 +1598,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
         if (rc != PBCGS_SUCCESS) return rc;
         dv = v[13];
       }
+      dinv_vec = dv;
       rc = reset_flag(ctx);
       if (rc != PBCGS_SUCCESS) return rc;
       k_dinv_const<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(A->n, dv, ctx->flag);
@@ -1529,7 +1615,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
       }
     }
   }
-  if (folded && pc == PC_VEC && A->kind != OP_CSR)
+  if (folded && pc == PC_VEC && (A->kind == OP_ST5 || A->kind == OP_ST7))
     return fail(ctx, PBCGS_ERR_UNSUPPORTED, "folded Jacobi on a stencil needs a constant diagonal");
   const bool hat = (pc != PC_NONE) && !folded;
   if (cg_family(o.variant)) {
@@ -1560,7 +1646,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     a.r64 = ctx->ws + 4 * np;
     a.s64 = ctx->ws + 5 * np;
     const int xg = (A->n + kWG - 1) / kWG;
-    const double* dv = a.dinv;
+    const double* dv = dinv_vec;
     const double ds = a.dinv_s;
     a.dinv = nullptr;
     a.dinv_s = 0.0;
@@ -1573,42 +1659,33 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
       if (rc != PBCGS_SUCCESS) return rc;
     }
     return with_op(A, [&](auto op) -> int {
-      using Op = decltype(op);
-      Op op64 = op;
-      if (folded) {
-        if constexpr (IsCsr<Op>::value) {
-          const int fg = (int)std::min<int64_t>((A->nnz + kWG - 1) / kWG, 8192);
-          const CsrOp op32i{A->rp, A->ci, A->va, A->n};  // the fold reads each entry's int32 column
-          if (A->nnz > 0) {
-            if (pc == PC_VEC) k_fold_csr<PC_VEC><<<fg, kWG, 0, ctx->stream>>>(op32i, A->nnz, ctx->ahat, dv, ds);
-            else k_fold_csr<PC_SCALAR><<<fg, kWG, 0, ctx->stream>>>(op32i, A->nnz, ctx->ahat, dv, ds);
-          }
-          op64.va = ctx->ahat;
-        } else {
-          for (double& c : op64.c) c = c * ds;
-        }
-        if (pc == PC_VEC) k_fold_x<PC_VEC, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
-        else k_fold_x<PC_SCALAR, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
-      }
-      auto op32 = to_binary32(ctx, op64, A->nnz);
-      HIP_TRY(ctx, hipGetLastError());
-      Driver<decltype(op32), PC_NONE, Op, true> drv(ctx, op32, op64, a, o);
-      drv.true_res = !folded;
-      const int st = drv.run(info);
-      if (st < 0 || !folded) return st;
-      if (pc == PC_VEC) k_fold_x<PC_VEC, false><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
-      else k_fold_x<PC_SCALAR, false><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
-      HIP_TRY(ctx, hipGetLastError());
-      const int rc2 = true_relres(ctx, op, a, drv.rho0, &info->relres_true);
-      if (rc2 != PBCGS_SUCCESS) return rc2;
-      return st;
+      // run the binary32 form on op64 (A, or A M^{-1} formed)
+      auto go = [&](auto op64) -> int {
+        auto op32 = to_binary32(ctx, op64, A->nnz);
+        HIP_TRY(ctx, hipGetLastError());
+        Driver<decltype(op32), PC_NONE, decltype(op64), true> drv(ctx, op32, op64, a, o);
+        drv.true_res = !folded;
+        const int st = drv.run(info);
+        if (st < 0 || !folded) return st;
+        if (pc == PC_VEC) k_fold_x<PC_VEC, false><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+        else k_fold_x<PC_SCALAR, false><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+        HIP_TRY(ctx, hipGetLastError());
+        const int rc2 = true_relres(ctx, op, a, drv.rho0, &info->relres_true);
+        if (rc2 != PBCGS_SUCCESS) return rc2;
+        return st;
+      };
+      if (!folded) return go(op);
+      auto fop = fold_operator(ctx, A, op, pc, dv, ds);
+      if (pc == PC_VEC) k_fold_x<PC_VEC, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+      else k_fold_x<PC_SCALAR, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+      return go(fop);
     }, compact_ok(o));
   }
 
   if (folded) {
     // A M^{-1} y = b from y_0 = x_0 / dinv, then x = dinv * y (Section 3.6)
     const int xg = (A->n + kWG - 1) / kWG;
-    const double* dv = a.dinv;
+    const double* dv = dinv_vec;
     const double ds = a.dinv_s;
     a.dinv = nullptr;
     a.dinv_s = 0.0;
@@ -1617,23 +1694,11 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
       if (rc != PBCGS_SUCCESS) return rc;
     }
     return with_op(A, [&](auto op) -> int {
-      using Op = decltype(op);
-      Op fop = op;
-      if constexpr (IsCsr<Op>::value) {
-        const int fg = (int)std::min<int64_t>((A->nnz + kWG - 1) / kWG, 8192);
-        const CsrOp op32i{A->rp, A->ci, A->va, A->n};  // the fold reads each entry's int32 column
-        if (A->nnz > 0) {
-          if (pc == PC_VEC) k_fold_csr<PC_VEC><<<fg, kWG, 0, ctx->stream>>>(op32i, A->nnz, ctx->ahat, dv, ds);
-          else k_fold_csr<PC_SCALAR><<<fg, kWG, 0, ctx->stream>>>(op32i, A->nnz, ctx->ahat, dv, ds);
-        }
-        fop.va = ctx->ahat;
-      } else {
-        for (double& c : fop.c) c = c * ds;  // one rounding per coefficient, as a_ij * dinv_j
-      }
+      auto fop = fold_operator(ctx, A, op, pc, dv, ds);
       if (pc == PC_VEC) k_fold_x<PC_VEC, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
       else k_fold_x<PC_SCALAR, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
       HIP_TRY(ctx, hipGetLastError());
-      Driver<Op, PC_NONE> drv(ctx, fop, a, o);
+      Driver<decltype(fop), PC_NONE> drv(ctx, fop, a, o);
       drv.true_res = false;
       const int st = drv.run(info);
       if (st < 0) return st;

@@ -159,6 +159,20 @@ def stencil(nx: int, ny: int, nz: int, coef, ctx: Context | None = None) -> Oper
     return Operator(ctx, h, nx * ny * nz, (), f"stencil{len(coef)}")
 
 
+def convdiff27(n: int, kappa: torch.Tensor, beta, shift: float = 0.0, ctx: Context | None = None) -> Operator:
+    """Matrix-free 27-point variable-coefficient convection-diffusion operator
+    on the n^3 grid: the operator ``assemble_convdiff(3, n, 27, beta, kappa,
+    shift)`` assembles, applied without a stored matrix (bitwise the same
+    products).  ``kappa``: (n+1)^3 cell coefficients on the GPU, kept alive by
+    the operator."""
+    ctx = ctx or default_context(kappa.device.index)
+    _check_vec(kappa, (n + 1) ** 3, "kappa")
+    b = (ctypes.c_double * 3)(*[float(v) for v in beta])
+    h = ctypes.c_void_p()
+    L.check(L.lib().pbcgs_op_convdiff27(ctx.handle, n, _ptr(kappa), b, float(shift), ctypes.byref(h)), ctx.handle)
+    return Operator(ctx, h, n ** 3, (kappa,), "convdiff27")
+
+
 def transpose(A: Operator) -> Operator:
     """The transposed CSR operator (the library owns its arrays)."""
     h = ctypes.c_void_p()
