@@ -243,6 +243,21 @@ struct StencilOp {
   }
 };
 
+// Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane l receives the
+// value of lane l - 1 (shr) or l + 1 (shl); the lane without a source (0 or 63)
+// keeps `fill`.
+constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double fill, double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float wave_shift(float fill, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 // Matrix-free 27-point variable-coefficient convection-diffusion operator on
 // the n^3 interior nodes of the unit cube (h = 1/(n+1)), Dirichlet boundaries,
 // rows x fastest.  Its entries are formed from the (n+1)^3 cell coefficients
@@ -308,34 +323,60 @@ struct Conv27Op {
     }
   }
 
-  // Entry E of the row, and the product term it adds (when the neighbour exists).
-  template <int E, class X>
-  __device__ __forceinline__ void term(int32_t row, int32_t i, int32_t j, int32_t k, const double (&kb)[27],
-                                       double diag, const X* __restrict__ x, V& acc) const {
-    if constexpr (E < 27) {
+  // Entry E = (dz+1)*9 + (dy+1)*3 + (dx+1) of the row (before any scaling).
+  template <int E>
+  __device__ __forceinline__ double entry(const double (&kb)[27], double diag) const {
+    if constexpr (E == 13) {
+      return diag;
+    } else {
       constexpr int dx = E % 3 - 1, dy = (E / 3) % 3 - 1, dz = E / 9 - 1;
-      const bool in = (dx < 0 ? i > 0 : (dx > 0 ? i < n - 1 : true)) &&
-                      (dy < 0 ? j > 0 : (dy > 0 ? j < n - 1 : true)) &&
-                      (dz < 0 ? k > 0 : (dz > 0 ? k < n - 1 : true));
-      if (in) {
-        double a;
-        if constexpr (E == 13) {
-          a = diag;
-        } else {
-          a = -kb[E];
-          constexpr int nzc = (dx != 0) + (dy != 0) + (dz != 0);
-          if constexpr (nzc == 1) {
-            constexpr int ax = dx != 0 ? 0 : (dy != 0 ? 1 : 2);
-            constexpr int side = dx != 0 ? dx : (dy != 0 ? dy : dz);
-            const bool upwind = ((upneg >> ax) & 1) ? (side < 0) : (side > 0);
-            if (upwind) a = -kb[E] - hab[ax];
-          }
-        }
-        const int32_t col = row + dx + n * dy + n * n * dz;
-        if constexpr (FOLD) a = a * dscale[col];
-        acc = acc + V(a) * V(x[col]);
+      double a = -kb[E];
+      if constexpr ((dx != 0) + (dy != 0) + (dz != 0) == 1) {
+        constexpr int ax = dx != 0 ? 0 : (dy != 0 ? 1 : 2);
+        constexpr int side = dx != 0 ? dx : (dy != 0 ? dy : dz);
+        const bool upwind = ((upneg >> ax) & 1) ? (side < 0) : (side > 0);
+        if (upwind) a = -kb[E] - hab[ax];
       }
-      term<E + 1>(row, i, j, k, kb, diag, x, acc);
+      return a;
+    }
+  }
+
+  // The three terms of grid line L = (dz+1)*3 + (dy+1) (dx = -1, 0, +1).  All
+  // 64 lanes take part: the centre value x[row + off] is loaded by every lane
+  // (its own row when the line leaves the grid, a value then never used), and
+  // the dx = -1 / +1 neighbours come from the adjacent lanes by a wave shift;
+  // lanes 0 and 63 receive instead the one extra value loaded per line (the
+  // element before / after the block), supplied as the shift's fill value.
+  // Terms whose neighbour lies outside the grid are not added (the selected
+  // accumulator keeps its value), as the assembled row has no such entry.
+  template <int L, class X>
+  __device__ __forceinline__ void line(int32_t row, int32_t b0, int lane, int32_t i, int32_t j, int32_t k,
+                                       const double (&kb)[27], double diag, const X* __restrict__ x, V& acc) const {
+    if constexpr (L < 9) {
+      constexpr int dy = L % 3 - 1, dz = L / 3 - 1;
+      const int32_t N = n * n * n;
+      const int32_t off = n * dy + n * n * dz;
+      const bool lin = (dy < 0 ? j > 0 : (dy > 0 ? j < n - 1 : true)) && (dz < 0 ? k > 0 : (dz > 0 ? k < n - 1 : true));
+      const int32_t c = lin ? row + off : row;
+      const int32_t e = min(max(lane < 32 ? b0 + off - 1 : b0 + 64 + off, 0), N - 1);
+      const X xc = x[c], xe = x[e];
+      const X xs[3] = {wave_shift<kWaveShr1>(xe, xc), xc, wave_shift<kWaveShl1>(xe, xc)};
+      double ss[3] = {1.0, 1.0, 1.0};
+      if constexpr (FOLD) {
+        const double sc = dscale[c], se = dscale[e];
+        ss[0] = wave_shift<kWaveShr1>(se, sc);
+        ss[1] = sc;
+        ss[2] = wave_shift<kWaveShl1>(se, sc);
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const bool in = lin && (q == 0 ? i > 0 : (q == 2 ? i < n - 1 : true));
+        double a = (q == 0) ? entry<L * 3>(kb, diag) : (q == 1 ? entry<L * 3 + 1>(kb, diag) : entry<L * 3 + 2>(kb, diag));
+        if constexpr (FOLD) a = a * ss[q];
+        const V t = acc + V(a) * V(xs[q]);
+        acc = in ? t : acc;
+      }
+      line<L + 1>(row, b0, lane, i, j, k, kb, diag, x, acc);
     }
   }
 
@@ -354,21 +395,22 @@ struct Conv27Op {
     return diag_of(kb, dsum);
   }
 
+  // Row `row` of A x (all 64 lanes of the row's 64-row block call it together;
+  // lanes with valid == false return 0).
   template <class X>
   __device__ __forceinline__ V spmv(int32_t row, bool valid, const X* __restrict__ x) const {
-    return valid ? apply(row, x) : V(0);
-  }
-  template <class X>
-  __device__ __forceinline__ V apply(int32_t row, const X* __restrict__ x) const {
-    const int32_t i = row % n, jk = row / n, j = jk % n, k = jk / n;
+    const int lane = threadIdx.x & 63;
+    const int32_t b0 = row - lane;
+    const int32_t rc = min(row, n * n * n - 1);  // rows past the grid compute a discarded copy of the last
+    const int32_t i = rc % n, jk = rc / n, j = jk % n, k = jk / n;
     double K[2][2][2], kb[27];
     cells(i, j, k, K);
     double dsum = 0.0;
     kbars<0>(K, kb, dsum);
     const double diag = diag_of(kb, dsum);
     V acc = V(0);
-    term<0>(row, i, j, k, kb, diag, x, acc);
-    return acc;
+    line<0>(rc, b0, lane, i, j, k, kb, diag, x, acc);
+    return valid ? acc : V(0);
   }
 };
 using Conv27 = Conv27Op<double, false>;
