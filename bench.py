@@ -98,6 +98,7 @@ def parse():
                         "configs")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
+    p.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)  # the oracle timing process
     return p.parse_args()
 
 
@@ -138,6 +139,33 @@ def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: boo
     return mat + 16 * vec, mat + 18 * vec, 34 * vec + 2 * mat
 
 
+def algorithmic_bytes_mf27(n: int, variant: str):
+    """Algorithmic HBM bytes (K_a, K_b, iteration) of the folded solvers on the
+    matrix-free 27-point operator of an n^3 grid: each product reads the
+    (n+1)^3 cell coefficients and gathers dinv (the column scaling of A M^{-1})
+    besides its input vector; the vector passes are those of the folded CSR
+    solve (:func:`algorithmic_bytes`)."""
+    N = n ** 3
+    mat = 8 * (n + 1) ** 3 + 8 * N
+    vec = 8 * N
+    if variant == "bicgstab":
+        return mat + 3 * vec, mat + 2 * vec, 19 * vec + 2 * mat
+    return mat + 10 * vec, mat + 12 * vec, 22 * vec + 2 * mat
+
+
+def fixed_iterations(solve_fn, m: int, warm: int = 3, reps: int = 5):
+    """Device time of m iterations at tol = 0: ``solve_fn(maxit)`` runs one
+    solve and returns its info (ms = HIP events from the setup to the last
+    kernel).  Median of ``reps`` solves after ``warm`` warm-ups, minus the
+    median of as many setup-only solves (maxit = 0), so only the iteration loop
+    is counted."""
+    for _ in range(warm):
+        solve_fn(m)
+    full = sorted(solve_fn(m).ms for _ in range(reps))[reps // 2]
+    setup = sorted(solve_fn(0).ms for _ in range(reps))[reps // 2]
+    return {"us_per_iter": round((full - setup) / m * 1e3, 2), "setup_us": round(setup * 1e3, 1), "iters": m}
+
+
 def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool, index_bytes: int = 4):
     """Algorithmic HBM bytes of one iteration of the CG family (Section 2) on
     a CSR operator with Jacobi by a constant (a scalar, no vector) or none.
@@ -157,8 +185,110 @@ def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool, index_byt
     return passes * vec + mat
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_child(args):
+    """Times the oracle in a child process that loads no GPU library, with
+    OpenMP threads bound close to the cores (OMP_PROC_BIND must be set before
+    the OpenMP runtime starts, which the parent's torch import already did)."""
+    import subprocess
+    nproc = len(os.sched_getaffinity(0))
+    # a preset OMP_NUM_THREADS (the host's CPU share) wins over the affinity mask
+    threads = os.environ.get("OMP_NUM_THREADS") or str(nproc)
+    env = dict(os.environ, OMP_NUM_THREADS=threads, OMP_PROC_BIND="close", OMP_PLACES="cores")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--n", str(args.n),
+           "--cpu-seconds", str(args.cpu_seconds)]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        sys.stderr.write(r.stderr[-4000:])
+        raise RuntimeError(f"oracle timing process failed with status {r.returncode}")
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, per = f.read().split()[:2]
+            quota = None if q == "max" else round(int(q) / int(per), 2)
+    except (OSError, ValueError):
+        pass
+    out["host"].update({"nproc": nproc, "cgroup_cpu_quota": quota, "omp_num_threads": int(threads)})
+    return out
+
+
+def cpu_child(args):
+    """The oracle (plain C, -O3, OpenMP) on the benchmark system: per-iteration
+    cost in the fixed-iteration mode (tol = 0, slope between two iteration
+    counts, so the setup and the fold of A M^-1 cancel; median of 3) with all
+    cores and with one thread, one complete solve at tol 1e-8, and SciPy's
+    bicgstab as a sanity line.  Prints one JSON object."""
+    import numpy as np
+
+    import oracle
+    from paper_1612_01395_amd import inputs
+
+    w = inputs.workload("c2", n=args.n)
+    Ah = oracle.assemble_workload(w)
+    bh = oracle.spmv(Ah, inputs.x_true(w.N))
+    dinv = oracle.jacobi_dinv(Ah)
+    ncores = oracle.get_threads()
+
+    def solve_s(m, tol=0.0):
+        t0 = time.perf_counter()
+        _, inf = oracle.solve_folded(Ah, bh, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=tol, maxit=m,
+                                     rr_period=w.rr_period)
+        return time.perf_counter() - t0, inf
+
+    def per_iter(m1, m2, threads):
+        oracle.set_threads(threads)
+        t1 = sorted(solve_s(m1)[0] for _ in range(3))[1]
+        t2 = sorted(solve_s(m2)[0] for _ in range(3))[1]
+        return (t2 - t1) / (m2 - m1)
+
+    t_start = time.perf_counter()
+    s_all = per_iter(10, 40, ncores)
+    s_one = per_iter(4, 12, 1)
+    oracle.set_threads(ncores)
+    tts, inf = solve_s(w.maxit, w.tol)
+    # SciPy's BiCGStab (a library Algorithm 7, one process) on the same system, 20 iterations
+    import scipy.sparse.linalg as spla
+    As = Ah.to_scipy()
+    its = [0]
+
+    def cb(_):
+        its[0] += 1
+
+    t0 = time.perf_counter()
+    spla.bicgstab(As, bh, rtol=1e-30, maxiter=20, callback=cb)
+    s_scipy = (time.perf_counter() - t0) / max(its[0], 1)
+    wall = time.perf_counter() - t_start
+    print(json.dumps({
+        "value": round(1.0 / s_all, 3), "unit": "iters/s", "cores": ncores, "kind": "oracle",
+        "sample": f"the {w.n}^3 benchmark system, folded-Jacobi p-BiCGStab+RR, tol 0: seconds per iteration from "
+                  f"the slope between 10 and 40 iterations (median of 3 each) with {ncores} OpenMP threads "
+                  f"(one thread: 4 and 12 iterations); "
+                  f"{wall:.1f} s of CPU work in all (with the lines below)",
+        "host": {"cpu_model": host_cpu_model(),
+                 "omp_proc_bind": os.environ.get("OMP_PROC_BIND", ""), "oracle_build": "gcc -O3 -fopenmp -ffp-contract=off"},
+        "one_thread_iters_per_s": round(1.0 / s_one, 3),
+        "parallel_speedup": round(s_one / s_all, 2),
+        "time_to_solution_s": round(tts, 3), "iterations_to_tol": inf["iters"],
+        "scipy_bicgstab_iters_per_s": round(1.0 / s_scipy, 3),
+    }), flush=True)
+
+
 def main():
     args = parse()
+    if args.cpu_child:
+        cpu_child(args)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path.",
               file=sys.stderr)
@@ -235,23 +365,26 @@ def main():
             res[leg] = timed_leg(op, variant, precond, **(extra[0] if extra else {}))
 
     # ---- fixed-iteration mode: tol = 0, 200 iterations, device-timed -----------
-    fixed = None
+    fixed = {}
     if "fixed" in legs:
-        fixed = {"mode": "tol = 0, maxit = 200, HIP events from the setup to the last kernel (no true-residual "
-                         "check), median of 5 after one warm-up; the 128^3 system, folded Jacobi"}
+        fixed = {"mode": "tol = 0, a fixed number of iterations (200 for the 128^3, 2-D and batched systems, 50 for "
+                         "the 256^3 ones), HIP events from the setup to the last kernel minus a setup-only solve, "
+                         "median of 5 after 3 warm-ups; folded Jacobi where the configuration has Jacobi"}
+        c2f = {}
         for key, op_, variant in (("pbicgstab_rr_csr", A, "pbicgstab_rr"), ("bicgstab_csr", A, "bicgstab"),
                                   ("ca_bicgstab_csr", A, "ca_bicgstab"), ("pbicgstab_rr_stencil", S, "pbicgstab_rr"),
                                   ("bicgstab_stencil", S, "bicgstab")):
             if op_ is None:
                 continue
-            kw = dict(variant=variant, precond="jacobi_folded", tol=0.0, maxit=200, rr_period=w.rr_period, out=xbuf)
-            solver.solve(op_, b, **kw)
-            times = []
-            for _ in range(5):
-                _, finfo = solver.solve(op_, b, **kw)
-                times.append(finfo.ms)
-            med = sorted(times)[2]
-            fixed[key] = {"us_per_iter": round(med / finfo.iters * 1e3, 2), "iters": finfo.iters}
+            r = fixed_iterations(lambda m, op_=op_, variant=variant: solver.solve(
+                op_, b, variant=variant, precond="jacobi_folded", tol=0.0, maxit=m, rr_period=w.rr_period,
+                out=xbuf)[1], 200)
+            _, _, pib = algorithmic_bytes(N, nnz, variant, op_ is S, index_bytes=ib)
+            r["gbps_effective"] = round(pib / (r["us_per_iter"] * 1e-6) / 1e9, 1)
+            c2f[key] = r
+        c2f["pbicgstab_over_bicgstab_csr"] = round(c2f["bicgstab_csr"]["us_per_iter"]
+                                                   / c2f["pbicgstab_rr_csr"]["us_per_iter"], 4)
+        fixed[f"c2_{args.n}"] = c2f
         # latency-bound sizes: the marginal cost of an iteration (slope between
         # 50 and 200 iterations) and the fixed cost of a solve (intercept)
         for wname, side, pc in (("c1", 64, None), ("c2", 32, "jacobi_folded")):
@@ -370,6 +503,15 @@ def main():
         x64 = x4.clone()
         f32 = leg4("fp32_rr64", w4.rr_period)
         f32["err_vs_fp64_solution"] = (torch.linalg.norm(x4 - x64) / torch.linalg.norm(x64)).item()
+        if "fixed" in legs:
+            c4f = {}
+            for prec, k in (("fp64", 50), ("fp32_rr64", w4.rr_period)):
+                c4f[prec] = fixed_iterations(lambda m, prec=prec, k=k: solver.solve(
+                    A4, b4, variant="pbicgstab_rr", precond="jacobi_folded", tol=0.0, maxit=m, rr_period=k,
+                    precision=prec, out=x4)[1], 50)
+                c4f[prec]["rr_period"] = k
+            c4f["fp32_over_fp64_per_iter"] = round(c4f["fp64"]["us_per_iter"] / c4f["fp32_rr64"]["us_per_iter"], 4)
+            fixed[f"c4_{w4.n}"] = c4f
         precision = {"workload": f"3-D 7-point {w4.n}^3 (N={w4.N}, nnz={val4.numel()}), folded Jacobi, "
                                  f"tol {w4.tol:g}; the binary64 solve equals the oracle's bit for bit",
                      "fp64": f64, "fp32_rr64": f32,
@@ -377,10 +519,27 @@ def main():
         del A4, rp4, col4, val4, b4, x4, x64
         torch.cuda.empty_cache()
 
-    # ---- the other configurations: 2-D 64^2 (latency-bound) and 3-D 27-point 256^3 (matrix-bound)
+    # ---- the other configurations: 2-D 64^2 (latency-bound) and 3-D 27-point 256^3, assembled (matrix-bound)
+    # and matrix-free
     other_cfg = None
     if "configs" in legs:
         other_cfg = {}
+
+        def solve_leg(op, rhs, xo, variant, precond, wc, steps):
+            kwc = dict(variant=variant, precond=precond, tol=wc.tol, maxit=wc.maxit, rr_period=wc.rr_period, out=xo)
+            solver.solve(op, rhs, **kwc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its = 0
+            for _ in range(steps):
+                _, inf = solver.solve(op, rhs, **kwc)
+                its += inf.iters
+            torch.cuda.synchronize()
+            dtc = time.perf_counter() - t0
+            return {"iters_per_s": round(its / dtc, 1), "us_per_iter": round(dtc / its * 1e6, 2),
+                    "iters_per_solve": inf.iters, "ms_per_solve": round(dtc / steps * 1e3, 3),
+                    "syncs_per_iter": inf.syncs_per_iter, "relres_true": inf.relres_true}
+
         for name, precond, steps in (("c1", None, 20), ("c3", "jacobi_folded", 2)):
             wc = inputs.workload(name)
             kappa = None
@@ -393,22 +552,42 @@ def main():
             row = {"workload": f"{wc.dim}-D {wc.npts}-point {wc.n}^{wc.dim} (N={wc.N}, nnz={valc.numel()}), "
                                f"precond {precond or 'none'}, tol {wc.tol:g}, RR every {wc.rr_period}"}
             for variant in ("pbicgstab_rr", "bicgstab"):
-                kwc = dict(variant=variant, precond=precond, tol=wc.tol, maxit=wc.maxit, rr_period=wc.rr_period,
-                           out=xc)
-                solver.solve(Ac, bc, **kwc)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                its = 0
-                for _ in range(steps):
-                    _, inf = solver.solve(Ac, bc, **kwc)
-                    its += inf.iters
-                torch.cuda.synchronize()
-                dtc = time.perf_counter() - t0
-                row[variant] = {"iters_per_s": round(its / dtc, 1), "us_per_iter": round(dtc / its * 1e6, 2),
-                                "iters_per_solve": inf.iters, "ms_per_solve": round(dtc / steps * 1e3, 3),
-                                "syncs_per_iter": inf.syncs_per_iter, "relres_true": inf.relres_true}
+                row[variant] = solve_leg(Ac, bc, xc, variant, precond, wc, steps)
             row["pbicgstab_over_bicgstab_iters_per_s"] = round(
                 row["pbicgstab_rr"]["iters_per_s"] / row["bicgstab"]["iters_per_s"], 4)
+            if name == "c3":
+                # the same operator matrix-free: entries formed from the cell coefficients (bitwise the CSR results)
+                M27 = solver.convdiff27(wc.n, kappa, wc.beta, wc.shift)
+                mf = {"operator": "matrix-free 27-point (pbcgs_op_convdiff27), folded Jacobi, "
+                                  "8 bytes of kappa per row and product instead of the CSR matrix"}
+                for variant in ("pbicgstab_rr", "bicgstab"):
+                    mf[variant] = solve_leg(M27, bc, xc, variant, precond, wc, steps)
+                mf["pbicgstab_over_bicgstab_iters_per_s"] = round(
+                    mf["pbicgstab_rr"]["iters_per_s"] / mf["bicgstab"]["iters_per_s"], 4)
+                mf["over_csr_iters_per_s"] = round(mf["pbicgstab_rr"]["iters_per_s"]
+                                                   / row["pbicgstab_rr"]["iters_per_s"], 4)
+                # per-kernel figures of the fused kernels on the matrix-free operator
+                _, kinfo = solver.solve(M27, bc, variant="pbicgstab_rr", precond=precond, tol=wc.tol,
+                                        maxit=wc.maxit, rr_period=wc.rr_period, out=xc, time_kernels=True)
+                mba, mbb, _ = algorithmic_bytes_mf27(wc.n, "pbicgstab")
+                mf["kernels"] = {}
+                for kk, kname in enumerate(("k_pa", "k_pb")):
+                    kus = kinfo.kernel_ms[kk] / max(kinfo.kernel_calls[kk], 1) * 1e3
+                    kb_ = (mba, mbb)[kk]
+                    mf["kernels"][kname] = {"avg_launch_us": round(kus, 2), "bytes_per_launch": kb_,
+                                            "achieved_gbps": round(kb_ / (kus * 1e-6) / 1e9, 1),
+                                            "frac": round(kb_ / (kus * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+                row["matrix_free"] = mf
+                if "fixed" in legs:
+                    c3f = {}
+                    for key, op_, variant in (("pbicgstab_rr_csr", Ac, "pbicgstab_rr"), ("bicgstab_csr", Ac, "bicgstab"),
+                                              ("pbicgstab_rr_matrix_free", M27, "pbicgstab_rr"),
+                                              ("bicgstab_matrix_free", M27, "bicgstab")):
+                        c3f[key] = fixed_iterations(lambda m, op_=op_, variant=variant: solver.solve(
+                            op_, bc, variant=variant, precond=precond, tol=0.0, maxit=m, rr_period=wc.rr_period,
+                            out=xc)[1], 50)
+                    fixed[f"c3_{wc.n}"] = c3f
+                del M27
             other_cfg[name] = row
             del Ac, rpc, colc, valc, bc, xc, kappa
             torch.cuda.empty_cache()
@@ -517,6 +696,13 @@ def main():
                    "autotuner_ms_per_batch_solve": {str(k): round(v, 1) for k, v in btune["tried"].items()}}
         batched["pbicgstab_over_bicgstab_time"] = round(
             batched["bicgstab"]["ms_per_batch_solve"] / batched["pbicgstab_rr"]["ms_per_batch_solve"], 4)
+        if "fixed" in legs:
+            c5f = {}
+            for variant in ("pbicgstab_rr", "bicgstab"):
+                c5f[variant] = fixed_iterations(lambda m, variant=variant: solver.solve_batched(
+                    bops, bbs, variant=variant, outs=outs, tol=0.0, maxit=m, rr_period=50)[1][0], 200)
+            c5f["note"] = "every one of the 512 systems runs the 200 iterations; us_per_iter is one iteration of all"
+            fixed["c5_batch"] = c5f
         del bops, bbs, bws, bts, outs
         torch.cuda.empty_cache()
 
@@ -528,26 +714,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
-    # ---- CPU baseline: the oracle on a bounded sample ---------------------------
+    # ---- CPU baseline: the oracle on a bounded sample, in a process of its own ---
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        Ah = oracle.assemble_workload(w)
-        bh = b.cpu().numpy()
-        dinv = oracle.jacobi_dinv(Ah)
-        # whole solves of the benchmark system, repeated until about --cpu-seconds of work
-        solves, iters, dt = 0, 0, 0.0
-        while solves == 0 or (dt < args.cpu_seconds and solves < 100):
-            t0 = time.perf_counter()
-            _, oinfo = oracle.solve_folded(Ah, bh, algo=oracle.ALG_PBICGSTAB_RR, dinv=dinv, tol=w.tol,
-                                           maxit=w.maxit, rr_period=w.rr_period)
-            dt += time.perf_counter() - t0
-            iters += oinfo["iters"]
-            solves += 1
-        cpu = {"value": round(iters / dt, 3), "unit": "iters/s", "cores": oracle.get_threads(),
-               "kind": "oracle",
-               "sample": f"{solves} complete p-BiCGStab+RR folded-Jacobi solves ({oinfo['iters']} iterations each, tol "
-                         f"{w.tol:g}) of the same {w.n}^3 system from x0 = 0, {dt:.1f} s"}
+        cpu = run_cpu_child(args)
 
     it, dt, info = res.get("pipe", (0, 1.0, None))
     value = it / dt if it else None
@@ -609,7 +779,7 @@ def main():
     for key, variant in (("st_pipe", "pbicgstab"), ("st_bicg", "bicgstab")):
         if key in res:
             out.setdefault("stencil", {})[variant] = leg_summary(key, variant, True, True)
-    if fixed is not None:
+    if fixed:
         out["fixed_iterations"] = fixed
     if cgfam is not None:
         out["cg_family"] = cgfam

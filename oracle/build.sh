@@ -3,5 +3,5 @@
 # No fused multiply-add: every + and * of the oracle is one rounded operation.
 set -e
 cd "$(dirname "$0")"
-gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math -fPIC -shared -Wall -o liboracle.so.tmp oracle.c -lm
+gcc -O3 -fopenmp -ffp-contract=off -fno-fast-math -fPIC -shared -Wall -o liboracle.so.tmp oracle.c -lm
 mv liboracle.so.tmp liboracle.so
