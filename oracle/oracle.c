@@ -246,7 +246,7 @@ typedef struct {
     const double* va;
 } csr_t;
 
-/* y := A x, each row summed in stored order from 0.0 (Section 2: SPMV). */
+/* Product with A: each row summed in stored order from 0.0 (Section 2, the SPMV kernel). */
 static void spmv(const csr_t* A, const double* x, double* y)
 {
     PAR for (int32_t i = 0; i < A->n; ++i) {
@@ -389,7 +389,7 @@ static int bicgstab(const csr_t* A, const double* dinv, const double* b, double*
     if (!prod) goto oom;
 
     info->iters = 0; info->n_rr = 0; info->relres_rec = 0.0; info->relres_true = 0.0;
-    /* r_0 := b - A x_0 ; p_0 := r_0 */
+    /* initial residual; the first search direction is that residual */
     spmv(A, x, tmp);
     PAR for (int32_t j = 0; j < n; ++j) r0[j] = b[j] - tmp[j];
     double gamma = DOT(r0, r0); /* (r_0, r_0) = (r_0, r_i) at i = 0 */
@@ -402,22 +402,22 @@ static int bicgstab(const csr_t* A, const double* dinv, const double* b, double*
     memcpy(p, r0, sizeof(double) * (size_t)n);
 
     for (int32_t i = 0; i < o->maxit; ++i) {
-        /* Alg. 10: p^_i := M^{-1} p_i ; s_i := A p^_i */
+        /* preconditioned search direction (Algorithm 10 only), then its product with A */
         if (pc) { PAR for (int32_t j = 0; j < n; ++j) ph[j] = dinv[j] * p[j]; g_ctr.pc++; }
         spmv(A, ph, s);
-        /* reduction (r_0, s_i) ; alpha_i := (r_0, r_i) / (r_0, s_i) */
+        /* first reduction: the shadow inner product of that product gives the step length alpha */
         double delta = DOT(r0, s);
         g_ctr.glred++; g_ctr.dots++; FLOPS(2);
         if (!isfinite(delta)) { info->status = OR_NONFINITE; goto done; }
         if (delta == 0.0) { info->status = OR_BREAKDOWN; goto done; }
         double alpha = gamma / delta;
         if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
-        /* q_i := r_i - alpha_i s_i ; q^_i := M^{-1} q_i ; y_i := A q^_i */
+        /* intermediate residual after the alpha step, preconditioned (Algorithm 10), and its product with A */
         PAR for (int32_t j = 0; j < n; ++j) q[j] = r[j] - alpha * s[j];
         FLOPS(2); REC(1);
         if (pc) { PAR for (int32_t j = 0; j < n; ++j) qh[j] = dinv[j] * q[j]; g_ctr.pc++; }
         spmv(A, qh, y);
-        /* reduction (q_i, y_i), (y_i, y_i) ; omega_i := (q_i, y_i) / (y_i, y_i) */
+        /* second reduction: the two inner products whose quotient is the stabilising step omega */
         double th1 = DOT(q, y), th2 = DOT(y, y);
         g_ctr.glred++; g_ctr.dots += 2; FLOPS(4);
         if (!isfinite(th1) || !isfinite(th2)) { info->status = OR_NONFINITE; goto done; }
@@ -430,7 +430,7 @@ static int bicgstab(const csr_t* A, const double* dinv, const double* b, double*
         }
         double omega = th1 / th2;
         if (!isfinite(omega)) { info->status = OR_NONFINITE; goto done; }
-        /* x_{i+1} := x_i + alpha_i p^_i + omega_i q^_i ; r_{i+1} := q_i - omega_i y_i */
+        /* new iterate from both steps, and the new residual from the intermediate one */
         PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * ph[j] + omega * qh[j];
         PAR for (int32_t j = 0; j < n; ++j) r[j] = q[j] - omega * y[j];
         FLOPS(4 + 2); REC(2);
@@ -444,11 +444,11 @@ static int bicgstab(const csr_t* A, const double* dinv, const double* b, double*
         if (o->history) o->history[i + 1] = info->relres_rec;
         if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
         if (omega == 0.0 || gamma == 0.0) { info->status = OR_BREAKDOWN; goto done; }
-        /* beta_i := (alpha_i / omega_i) (r_0, r_{i+1}) / (r_0, r_i) */
+        /* direction update coefficient beta from the ratio of consecutive shadow inner products */
         double beta = (alpha / omega) * (gamma1 / gamma);
         if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }
         if (o->scalars) o->scalars[3 * i + 2] = beta;
-        /* p_{i+1} := r_{i+1} + beta_i (p_i - omega_i s_i) */
+        /* next search direction: new residual plus beta times the omega-corrected old direction */
         PAR for (int32_t j = 0; j < n; ++j) p[j] = r[j] + beta * (p[j] - omega * s[j]);
         FLOPS(4); REC(1);
         gamma = gamma1;
@@ -485,7 +485,7 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
     if (!prod) goto oom;
 
     info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
-    /* r_0 := b - A x_0 ; r^_0 := M^{-1} r_0 ; w_0 := A r^_0 ; w^_0 := M^{-1} w_0 */
+    /* initial residual, its preconditioned copy, the product of that copy with A, and its preconditioned copy */
     spmv(A, x, tmp);
     PAR for (int32_t j = 0; j < n; ++j) r0[j] = b[j] - tmp[j];
     double gamma = DOT(r0, r0); /* (r_0, r_0) */
@@ -497,7 +497,7 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
     if (pc) { PAR for (int32_t j = 0; j < n; ++j) rh[j] = dinv[j] * r[j]; g_ctr.pc++; }
     spmv(A, rh, w);
     if (pc) { PAR for (int32_t j = 0; j < n; ++j) wh[j] = dinv[j] * w[j]; g_ctr.pc++; }
-    /* t_0 := A w^_0 ; alpha_0 := (r_0, r_0) / (r_0, w_0) ; beta_{-1} := 0 */
+    /* auxiliary product for the first iteration; first step length from the setup's inner products; beta starts at 0 */
     spmv(A, wh, t);
     double delta = DOT(r0, w);
     if (!isfinite(delta)) { info->status = OR_NONFINITE; goto done; }
@@ -509,25 +509,25 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
     int32_t n_rr = 0;
 
     for (int32_t i = 0; i < o->maxit; ++i) {
-        /* p^_i := r^_i + beta_{i-1} (p^_{i-1} - omega_{i-1} s^_{i-1}) */
+        /* Algorithm 11: search direction from the (preconditioned) residual and the previous direction */
         PAR for (int32_t j = 0; j < n; ++j) ph[j] = rh[j] + beta * (ph[j] - omega * sh[j]);
         FLOPS(4); REC(1);
         if (rr_pending) {
-            /* residual replacement, second half: s_i := A p^_i ; s^_i := M^{-1} s_i ; z_i := A s^_i */
+            /* second half of a replacement (Section 4.2): s, its preconditioned copy and z recomputed from p */
             spmv(A, ph, s);
             if (pc) { PAR for (int32_t j = 0; j < n; ++j) sh[j] = dinv[j] * s[j]; g_ctr.pc++; }
             spmv(A, sh, z);
             rr_pending = 0;
         } else {
-            /* s_i := w_i + beta_{i-1} (s_{i-1} - omega_{i-1} z_{i-1}) */
+            /* recurrence of s, the product of A with the search direction (uses the old z) */
             PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + beta * (s[j] - omega * z[j]);
-            /* s^_i := w^_i + beta_{i-1} (s^_{i-1} - omega_{i-1} z^_{i-1}) */
+            /* the same recurrence for the preconditioned copy of s (Algorithm 11) */
             if (pc) PAR for (int32_t j = 0; j < n; ++j) sh[j] = wh[j] + beta * (sh[j] - omega * zh[j]);
-            /* z_i := t_i + beta_{i-1} (z_{i-1} - omega_{i-1} v_{i-1}) */
+            /* recurrence of z, the product of A with the preconditioned s (uses the old v) */
             PAR for (int32_t j = 0; j < n; ++j) z[j] = t[j] + beta * (z[j] - omega * v[j]);
             FLOPS(pc ? 12 : 8); REC(pc ? 3 : 2);
         }
-        /* q_i := r_i - alpha_i s_i ; q^_i := r^_i - alpha_i s^_i ; y_i := w_i - alpha_i z_i */
+        /* intermediate residual q, its preconditioned copy, and y = A times that copy, all by recurrence */
         PAR for (int32_t j = 0; j < n; ++j) q[j] = r[j] - alpha * s[j];
         if (pc) PAR for (int32_t j = 0; j < n; ++j) qh[j] = rh[j] - alpha * sh[j];
         PAR for (int32_t j = 0; j < n; ++j) y[j] = w[j] - alpha * z[j];
@@ -535,10 +535,10 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
         /* begin reduction (q_i, y_i), (y_i, y_i) */
         double th1 = DOT(q, y), th2 = DOT(y, y);
         g_ctr.glred++; g_ctr.dots += 2; FLOPS(4);
-        /* z^_i := M^{-1} z_i ; v_i := A z^_i  (overlapping the reduction) */
+        /* the product that the first reduction overlaps in the paper: v from the preconditioned z */
         if (pc) { PAR for (int32_t j = 0; j < n; ++j) zh[j] = dinv[j] * z[j]; g_ctr.pc++; }
         spmv(A, zh, v);
-        /* end reduction ; omega_i := (q_i, y_i) / (y_i, y_i) */
+        /* first reduction finished: omega */
         if (!isfinite(th1) || !isfinite(th2)) { info->status = OR_NONFINITE; goto done; }
         if (th2 == 0.0) {
             PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * ph[j];
@@ -548,18 +548,18 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
         }
         omega = th1 / th2;
         if (!isfinite(omega)) { info->status = OR_NONFINITE; goto done; }
-        /* x_{i+1} := x_i + alpha_i p^_i + omega_i q^_i */
+        /* iterate update by both steps */
         PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * ph[j] + omega * qh[j];
-        /* r_{i+1} := q_i - omega_i y_i */
+        /* residual recurrence */
         PAR for (int32_t j = 0; j < n; ++j) r[j] = q[j] - omega * y[j];
-        /* r^_{i+1} := q^_i - omega_i (w^_i - alpha_i z^_i) */
+        /* recurrence of the preconditioned residual (Algorithm 11) */
         if (pc) PAR for (int32_t j = 0; j < n; ++j) rh[j] = qh[j] - omega * (wh[j] - alpha * zh[j]);
-        /* w_{i+1} := y_i - omega_i (t_i - alpha_i v_i) */
+        /* recurrence of w, the product of A with the preconditioned residual */
         PAR for (int32_t j = 0; j < n; ++j) w[j] = y[j] - omega * (t[j] - alpha * v[j]);
         FLOPS(pc ? 14 : 10); REC(pc ? 4 : 3);
         info->iters = i + 1;
         if (rr_due(o, i, n_rr)) {
-            /* residual replacement, first half: r := b - A x ; r^ := M^{-1} r ; w := A r^ */
+            /* first half of a replacement (Section 4.2): true residual, its preconditioned copy, and w from it */
             spmv(A, x, tmp);
             PAR for (int32_t j = 0; j < n; ++j) r[j] = b[j] - tmp[j];
             if (pc) { PAR for (int32_t j = 0; j < n; ++j) rh[j] = dinv[j] * r[j]; g_ctr.pc++; }
@@ -579,7 +579,7 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
         info->relres_rec = sqrt(nu) / rho0;
         if (o->history) o->history[i + 1] = info->relres_rec;
         if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
-        /* w^_{i+1} := M^{-1} w_{i+1} ; t_{i+1} := A w^_{i+1} */
+        /* the product the second reduction overlaps: t from the preconditioned w */
         if (pc) { PAR for (int32_t j = 0; j < n; ++j) wh[j] = dinv[j] * w[j]; g_ctr.pc++; }
         spmv(A, wh, t);
         /* end reduction ; beta_i ; alpha_{i+1} by eq. (3) */
@@ -633,7 +633,7 @@ static int ca_bicgstab(const csr_t* A, const double* b, double* x, const or_opts
     if (!prod) goto oom;
 
     info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
-    /* r_0 := b - A x_0 ; w_0 := A r_0 ; alpha_0 := (r_0, r_0) / (r_0, w_0) ; beta_{-1} := 0 */
+    /* initial residual, w from it, first step length from the setup's inner products; beta starts at 0 */
     spmv(A, x, tmp);
     PAR for (int32_t j = 0; j < n; ++j) r0[j] = b[j] - tmp[j];
     double gamma = DOT(r0, r0);
@@ -651,14 +651,14 @@ static int ca_bicgstab(const csr_t* A, const double* b, double* x, const or_opts
     /* p_{-1} = s_{-1} = z_{-1} = 0 (calloc), omega_{-1} = 0 */
 
     for (int32_t i = 0; i < o->maxit; ++i) {
-        /* p_i := r_i + beta_{i-1} (p_{i-1} - omega_{i-1} s_{i-1}) */
+        /* search direction from the residual and the previous direction */
         PAR for (int32_t j = 0; j < n; ++j) p[j] = r[j] + beta * (p[j] - omega * s[j]);
-        /* s_i := w_i + beta_{i-1} (s_{i-1} - omega_{i-1} z_{i-1})   (eq. (1)) */
+        /* s by its recurrence, eq. (1), instead of a product with A */
         PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + beta * (s[j] - omega * z[j]);
         FLOPS(8); REC(2);
-        /* z_i := A s_i */
+        /* the first product of the iteration: z from s */
         spmv(A, s, z);
-        /* q_i := r_i - alpha_i s_i ; y_i := w_i - alpha_i z_i   (eq. (4)) */
+        /* q and y by their recurrences, eq. (4) */
         PAR for (int32_t j = 0; j < n; ++j) q[j] = r[j] - alpha * s[j];
         PAR for (int32_t j = 0; j < n; ++j) y[j] = w[j] - alpha * z[j];
         FLOPS(4); REC(2);
@@ -674,12 +674,12 @@ static int ca_bicgstab(const csr_t* A, const double* b, double* x, const or_opts
         }
         omega = th1 / th2;
         if (!isfinite(omega)) { info->status = OR_NONFINITE; goto done; }
-        /* x_{i+1} := x_i + alpha_i p_i + omega_i q_i ; r_{i+1} := q_i - omega_i y_i */
+        /* iterate and residual updates */
         PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j] + omega * q[j];
         PAR for (int32_t j = 0; j < n; ++j) r[j] = q[j] - omega * y[j];
         FLOPS(6); REC(2);
         info->iters = i + 1;
-        /* w_{i+1} := A r_{i+1} */
+        /* the second product of the iteration: w from the new residual */
         spmv(A, r, w);
         /* reduction (r_0,r_{i+1}), (r_0,w_{i+1}), (r_0,s_i), (r_0,z_i), plus ||r_{i+1}||^2 */
         double gamma1 = DOT(r0, r), eta = DOT(r0, w), sig_s = DOT(r0, s), sig_z = DOT(r0, z);
@@ -692,7 +692,7 @@ static int ca_bicgstab(const csr_t* A, const double* b, double* x, const or_opts
         info->relres_rec = sqrt(nu) / rho0;
         if (o->history) o->history[i + 1] = info->relres_rec;
         if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
-        /* beta_i := (alpha_i / omega_i) (r_0, r_{i+1}) / (r_0, r_i) ; alpha_{i+1} by eq. (3) or (5) */
+        /* second reduction finished: beta, then the next alpha by eq. (3) or eq. (5) */
         if (omega == 0.0 || gamma == 0.0) { info->status = OR_BREAKDOWN; goto done; }
         beta = (alpha / omega) * (gamma1 / gamma);
         if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }
@@ -743,7 +743,7 @@ static int cg(const csr_t* A, const double* dinv, const double* b, double* x, co
     if (!prod) goto oom;
 
     info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
-    /* r_0 := b - A x_0 ; u_0 := M^{-1} r_0 ; p_0 := u_0 */
+    /* initial residual, its preconditioned copy, and the first search direction equal to that copy */
     spmv(A, x, tmp);
     PAR for (int32_t j = 0; j < n; ++j) r[j] = b[j] - tmp[j];
     if (pc) { PAR for (int32_t j = 0; j < n; ++j) u[j] = dinv[j] * r[j]; }
@@ -755,7 +755,7 @@ static int cg(const csr_t* A, const double* dinv, const double* b, double* x, co
     if (rho0 == 0.0) { info->status = OR_SUCCESS; info->relres_rec = 0.0; goto done; }
 
     for (int32_t i = 0; i < o->maxit; ++i) {
-        /* s_i := A p_i ; reduction (s_i, p_i) ; alpha_i := (r_i, u_i) / (s_i, p_i) */
+        /* product with the search direction, then the step length from the first reduction */
         spmv(A, p, s);
         double delta = DOT(s, p);
         g_ctr.glred++; g_ctr.dots++; FLOPS(2);
@@ -763,7 +763,7 @@ static int cg(const csr_t* A, const double* dinv, const double* b, double* x, co
         if (delta == 0.0) { info->status = OR_BREAKDOWN; goto done; }
         double alpha = gamma / delta;
         if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
-        /* x_{i+1} := x_i + alpha_i p_i ; r_{i+1} := r_i - alpha_i s_i ; u_{i+1} := M^{-1} r_{i+1} */
+        /* iterate, residual and preconditioned residual updates */
         PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
         PAR for (int32_t j = 0; j < n; ++j) r[j] = r[j] - alpha * s[j];
         if (pc) { PAR for (int32_t j = 0; j < n; ++j) u[j] = dinv[j] * r[j]; g_ctr.pc++; }
@@ -777,7 +777,7 @@ static int cg(const csr_t* A, const double* dinv, const double* b, double* x, co
         info->relres_rec = sqrt(nu) / rho0;
         if (o->history) o->history[i + 1] = info->relres_rec;
         if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
-        /* beta_{i+1} := (r_{i+1}, u_{i+1}) / (r_i, u_i) ; p_{i+1} := u_{i+1} + beta_{i+1} p_i */
+        /* second reduction: beta, then the next search direction */
         if (gamma == 0.0) { info->status = OR_BREAKDOWN; goto done; }
         double beta = gamma1 / gamma;
         if (!isfinite(beta)) { info->status = OR_NONFINITE; goto done; }
@@ -823,7 +823,7 @@ static int cgcg(const csr_t* A, const double* dinv, const double* b, double* x, 
     if (!prod) goto oom;
 
     info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
-    /* r_0 := b - A x_0 ; u_0 := M^{-1} r_0 ; w_0 := A u_0 */
+    /* initial residual, its preconditioned copy u, and w = A u */
     spmv(A, x, tmp);
     PAR for (int32_t j = 0; j < n; ++j) r[j] = b[j] - tmp[j];
     if (pc) { PAR for (int32_t j = 0; j < n; ++j) u[j] = dinv[j] * r[j]; }
@@ -833,25 +833,25 @@ static int cgcg(const csr_t* A, const double* dinv, const double* b, double* x, 
     if (o->history) o->history[0] = 1.0;
     if (!isfinite(rho0) || !isfinite(gamma) || !isfinite(delta)) { info->status = OR_NONFINITE; goto done; }
     if (rho0 == 0.0) { info->status = OR_SUCCESS; info->relres_rec = 0.0; goto done; }
-    /* alpha_0 := (r_0, u_0) / (w_0, u_0) ; beta_0 := 0 ; p_{-1} = s_{-1} = 0 */
+    /* first step length from the setup's inner products; beta and the previous directions start at 0 */
     if (delta == 0.0) { info->status = OR_BREAKDOWN; goto done; }
     double alpha = gamma / delta, beta = 0.0;
     if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
 
     for (int32_t i = 0; i < o->maxit; ++i) {
-        /* p_i := u_i + beta_i p_{i-1} ; s_i := w_i + beta_i s_{i-1} */
+        /* search direction p and its product s, both by recurrence */
         PAR for (int32_t j = 0; j < n; ++j) p[j] = u[j] + beta * p[j];
         PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + beta * s[j];
-        /* x_{i+1} := x_i + alpha_i p_i ; r_{i+1} := r_i - alpha_i s_i */
+        /* iterate and residual updates */
         PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
         PAR for (int32_t j = 0; j < n; ++j) r[j] = r[j] - alpha * s[j];
         FLOPS(8); REC(4);
-        /* u_{i+1} := M^{-1} r_{i+1} ; w_{i+1} := A u_{i+1} */
+        /* preconditioned residual, then its product with A */
         if (pc) { PAR for (int32_t j = 0; j < n; ++j) u[j] = dinv[j] * r[j]; g_ctr.pc++; }
         spmv(A, u, w);
         info->iters = i + 1;
         if (o->scalars) o->scalars[3 * i] = alpha;
-        /* reduction gamma_{i+1} := (r_{i+1}, u_{i+1}) ; delta := (w_{i+1}, u_{i+1}) ; ||r_{i+1}||^2 */
+        /* the single reduction phase of Algorithm 4: the two inner products and the residual norm */
         double gamma1 = DOT(r, u), nu = DOT(r, r);
         delta = DOT(w, u);
         g_ctr.glred++; g_ctr.dots += 2; FLOPS(4);
@@ -859,7 +859,7 @@ static int cgcg(const csr_t* A, const double* dinv, const double* b, double* x, 
         info->relres_rec = sqrt(nu) / rho0;
         if (o->history) o->history[i + 1] = info->relres_rec;
         if (info->relres_rec <= o->tol) { info->status = OR_SUCCESS; goto done; }
-        /* beta_{i+1} := gamma_{i+1} / gamma_i ; alpha_{i+1} := (delta / gamma_{i+1} - beta_{i+1} / alpha_i)^{-1} */
+        /* beta from consecutive preconditioned residual norms, then the next alpha from both */
         int st = cg_next_alpha(gamma1, gamma, delta, alpha, &beta, &alpha);
         if (st != OR_SUCCESS) { info->status = st; goto done; }
         if (o->scalars && i + 1 < o->maxit) o->scalars[3 * (i + 1) + 2] = beta;
@@ -889,7 +889,7 @@ static int pipe_cg(const csr_t* A, const double* dinv, const double* b, double* 
     if (!prod) goto oom;
 
     info->iters = 0; info->n_rr = 0; info->relres_rec = 1.0; info->relres_true = 0.0;
-    /* r_0 := b - A x_0 ; u_0 := M^{-1} r_0 ; w_0 := A u_0 ; z_{-1} = q_{-1} = s_{-1} = p_{-1} = 0 */
+    /* initial residual, its preconditioned copy u, w = A u; all the auxiliary recurrences start at 0 */
     spmv(A, x, tmp);
     PAR for (int32_t j = 0; j < n; ++j) r[j] = b[j] - tmp[j];
     if (pc) { PAR for (int32_t j = 0; j < n; ++j) u[j] = dinv[j] * r[j]; }
@@ -898,7 +898,7 @@ static int pipe_cg(const csr_t* A, const double* dinv, const double* b, double* 
     if (o->history) o->history[0] = 1.0;
 
     for (int32_t i = 0;; ++i) {
-        /* reduction gamma_i := (r_i, u_i) ; delta := (w_i, u_i) ; ||r_i||^2 */
+        /* the reduction phase of Algorithm 6, on vectors the previous iteration finished */
         double gamma1 = DOT(r, u), delta = DOT(w, u), nu = DOT(r, r);
         if (i > 0) { g_ctr.glred++; g_ctr.dots += 2; FLOPS(4); }
         if (!isfinite(gamma1) || !isfinite(delta) || !isfinite(nu)) { info->status = OR_NONFINITE; goto done; }
@@ -923,18 +923,16 @@ static int pipe_cg(const csr_t* A, const double* dinv, const double* b, double* 
         gamma = gamma1;
         if (i == o->maxit) { info->status = OR_MAXIT; goto done; }
         if (o->scalars) { o->scalars[3 * i] = alpha; o->scalars[3 * i + 2] = beta; }
-        /* m_i := M^{-1} w_i ; n_i := A m_i   (in the paper overlapping the reduction; here after it,
-           which changes no value) */
+        /* the product the reduction overlaps in the paper (computed after it here; the order changes
+           no value) */
         if (pc) { PAR for (int32_t j = 0; j < n; ++j) m[j] = dinv[j] * w[j]; g_ctr.pc++; }
         spmv(A, m, nv);
-        /* z_i := n_i + beta_i z_{i-1} ; q_i := m_i + beta_i q_{i-1} ; s_i := w_i + beta_i s_{i-1} ;
-           p_i := u_i + beta_i p_{i-1} */
+        /* the four auxiliary recurrences (z, q, s and the search direction p) with the new beta */
         PAR for (int32_t j = 0; j < n; ++j) z[j] = nv[j] + beta * z[j];
         if (pc) PAR for (int32_t j = 0; j < n; ++j) q[j] = m[j] + beta * q[j];
         PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + beta * s[j];
         PAR for (int32_t j = 0; j < n; ++j) p[j] = u[j] + beta * p[j];
-        /* x_{i+1} := x_i + alpha_i p_i ; r_{i+1} := r_i - alpha_i s_i ; u_{i+1} := u_i - alpha_i q_i ;
-           w_{i+1} := w_i - alpha_i z_i */
+        /* iterate, residual and auxiliary updates with the new alpha */
         PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
         PAR for (int32_t j = 0; j < n; ++j) r[j] = r[j] - alpha * s[j];
         if (pc) PAR for (int32_t j = 0; j < n; ++j) u[j] = u[j] - alpha * q[j];
@@ -975,7 +973,7 @@ typedef struct {
     const float* va;
 } csr32_t;
 
-/* y := A x in binary32, rows in stored order from 0.0f. */
+/* Product with the binary32 operator in binary32, rows in stored order from 0.0f. */
 static void spmv32(const csr32_t* A, const float* x, float* y)
 {
     PAR for (int32_t i = 0; i < A->n; ++i) {
@@ -986,7 +984,7 @@ static void spmv32(const csr32_t* A, const float* x, float* y)
     g_ctr.spmv++;
 }
 
-/* y := A x in binary64 for a binary32 x (widened exactly). */
+/* Product with the binary64 operator on a binary32 vector (widened exactly). */
 static void spmv_wide(const csr_t* A, const float* x, double* y)
 {
     PAR for (int32_t i = 0; i < A->n; ++i) {
@@ -1087,7 +1085,7 @@ static int pbicgstab_mp(const csr_t* A, const double* b, double* x, const or_opt
 
     for (int32_t i = 0; i < o->maxit; ++i) {
         const float af = (float)alpha, bf = (float)beta, wf = (float)omega;
-        /* p_i := r_i + beta (p_{i-1} - omega s_{i-1}) */
+        /* search direction from the residual and the previous direction (binary32) */
         PAR for (int32_t j = 0; j < n; ++j) p[j] = r[j] + bf * (p[j] - wf * s[j]);
         if (rr_pending) {
             /* replacement, second half, in binary64: s = f(A p), z = f(A (A p)) */
@@ -1101,10 +1099,10 @@ static int pbicgstab_mp(const csr_t* A, const double* b, double* x, const or_opt
             PAR for (int32_t j = 0; j < n; ++j) s[j] = w[j] + bf * (s[j] - wf * z[j]);
             PAR for (int32_t j = 0; j < n; ++j) z[j] = t[j] + bf * (z[j] - wf * v[j]);
         }
-        /* q_i := r_i - alpha s_i ; y_i := w_i - alpha z_i */
+        /* intermediate residual q and y by recurrence (binary32) */
         PAR for (int32_t j = 0; j < n; ++j) { q[j] = r[j] - af * s[j]; y[j] = w[j] - af * z[j]; }
         double th1 = DOT32(q, y), th2 = DOT32(y, y);
-        /* v_i := A z_i */
+        /* the product overlapped by the first reduction: v from z */
         spmv32(&A32, z, v);
         if (!isfinite(th1) || !isfinite(th2)) { info->status = OR_NONFINITE; goto done; }
         if (th2 == 0.0) {
@@ -1116,9 +1114,9 @@ static int pbicgstab_mp(const csr_t* A, const double* b, double* x, const or_opt
         omega = th1 / th2;
         if (!isfinite(omega)) { info->status = OR_NONFINITE; goto done; }
         const float wn = (float)omega;
-        /* in binary64: x_{i+1} := x_i + alpha p_i + omega q_i */
+        /* the iterate is updated in binary64 from the binary32 directions */
         PAR for (int32_t j = 0; j < n; ++j) x[j] = x[j] + alpha * (double)p[j] + omega * (double)q[j];
-        /* r_{i+1} := q_i - omega y_i ; w_{i+1} := y_i - omega (t_i - alpha v_i) */
+        /* residual and w recurrences (binary32) */
         PAR for (int32_t j = 0; j < n; ++j) {
             r[j] = q[j] - wn * y[j];
             w[j] = y[j] - wn * (t[j] - af * v[j]);
@@ -1157,7 +1155,7 @@ static int pbicgstab_mp(const csr_t* A, const double* b, double* x, const or_opt
                 replaced = 3;  /* not converged: replace now and reduce again */
                 continue;
             }
-            /* t_{i+1} := A w_{i+1} */
+            /* the product overlapped by the second reduction: t from w */
             spmv32(&A32, w, t);
             /* beta_i ; alpha_{i+1} by eq. (3) */
             if (omega == 0.0 || gamma == 0.0) { info->status = OR_BREAKDOWN; goto done; }

@@ -393,23 +393,46 @@ def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str 
     return xs, out
 
 
+class NotConvergedError(RuntimeError):
+    """A solve inside :class:`SolveFn` ended without meeting its tolerance; the
+    gradient it would feed is not the gradient of the loss."""
+
+    def __init__(self, what: str, info: "SolveInfo"):
+        super().__init__(f"{what} solve ended with status {info.status_name} after {info.iters} iterations "
+                         f"(recursive relative residual {info.relres_rec:.3e})")
+        self.info = info
+
+
+def require_converged(info: "SolveInfo", what: str) -> None:
+    """Raise :class:`NotConvergedError` unless the solve reported SUCCESS."""
+    if info.status != L.SUCCESS:
+        raise NotConvergedError(what, info)
+
+
 class SolveFn(torch.autograd.Function):
     """x = A^{-1} b for the CSR matrix (row_ptr, col_idx, vals), differentiable
     in vals and b.  The backward pass is the adjoint solve with A^T on the
     same solver: lambda = A^{-T} dL/dx, dL/db = lambda, dL/dvals_k =
     -lambda_i x_j for the stored entry k = (i, j).  ``opts`` are keyword
     arguments of :func:`solve` (the adjoint solve uses them too, with
-    ``adjoint_tol`` in place of ``tol`` when given)."""
+    ``adjoint_tol`` / ``adjoint_maxit`` in place of ``tol`` / ``maxit`` when
+    given).  A forward or adjoint solve that ends without SUCCESS raises
+    :class:`NotConvergedError` (its x or lambda would not give the gradient),
+    unless ``allow_unconverged=True``."""
 
     @staticmethod
     def forward(ctx, vals, b, row_ptr, col_idx, opts):
         opts = dict(opts or {})
-        adj_tol = opts.pop("adjoint_tol", None)
+        adj = {k: opts.pop(f"adjoint_{k}") for k in ("tol", "maxit") if f"adjoint_{k}" in opts}
+        lenient = bool(opts.pop("allow_unconverged", False))
         A = csr(row_ptr, col_idx, vals)
         x, info = solve(A, b, **opts)
+        if not lenient:
+            require_converged(info, "forward")
         ctx.save_for_backward(vals, row_ptr, col_idx, x)
         ctx.opts = opts
-        ctx.adj_tol = adj_tol
+        ctx.adj = adj
+        ctx.lenient = lenient
         ctx.info = info
         return x
 
@@ -421,9 +444,10 @@ class SolveFn(torch.autograd.Function):
         opts = dict(ctx.opts)
         opts.pop("x0", None)
         opts.pop("out", None)
-        if ctx.adj_tol is not None:
-            opts["tol"] = ctx.adj_tol
-        lam, _ = solve(AT, gx.contiguous(), **opts)
+        opts.update(ctx.adj)
+        lam, info = solve(AT, gx.contiguous(), **opts)
+        if not ctx.lenient:
+            require_converged(info, "adjoint")
         gvals = csr_outer_grad(A, lam, x) if ctx.needs_input_grad[0] else None
         gb = lam if ctx.needs_input_grad[1] else None
         return gvals, gb, None, None, None

@@ -100,3 +100,20 @@ def test_binding_constants_match_the_header():
     # option flags documented in the header
     assert "bit 0" in text and "bit 1" in text and "bit 2" in text
     assert (_lib.FLAG_DIRECT, _lib.FLAG_TIME_KERNELS, _lib.FLAG_ALPHA_EQ5) == (1, 2, 4)
+
+
+def test_require_converged_raises_on_every_unsuccessful_status():
+    """SolveFn's guard, host logic only: SUCCESS passes, MAXIT, BREAKDOWN and
+    NONFINITE raise with the report attached."""
+    import pytest
+    from paper_1612_01395_amd import solver
+
+    def info(status):
+        return solver.SolveInfo(iters=7, n_rr=0, status=status, syncs_per_iter=2, relres_rec=1e-3,
+                                relres_true=1e-3, ms=0.0, kernel_ms=(0.0, 0.0), kernel_calls=(0, 0))
+
+    solver.require_converged(info(0), "forward")
+    for st, name in ((1, "maxit"), (2, "breakdown"), (3, "nonfinite")):
+        with pytest.raises(solver.NotConvergedError) as e:
+            solver.require_converged(info(st), "adjoint")
+        assert e.value.info.status == st and name in str(e.value) and "adjoint" in str(e.value)

@@ -128,3 +128,25 @@ def test_batched_loss_gradient_against_finite_differences():
             say(f"system {k} (n={s.n}) beta_{a}: adjoint {grad:.10e} fd {fd:.10e} rel {rel:.2e}")
             worst = max(worst, rel)
     assert worst <= 1e-5
+
+
+def test_unconverged_solves_raise():
+    """A forward or adjoint solve that stops at its iteration budget raises
+    instead of feeding an unconverged x or lambda into the gradient."""
+    require_gpu()
+    A = oracle.assemble_workload(inputs.workload("c1", n=12))
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    rp, col = dev_t(A.row_ptr), dev_t(A.col)
+    vals = dev_t(A.val).requires_grad_(True)
+    with pytest.raises(solver.NotConvergedError) as e:
+        solver.SolveFn.apply(vals, dev_t(b), rp, col, dict(tol=1e-12, maxit=1))
+    assert e.value.info.status == 1 and e.value.info.iters == 1
+    x = solver.SolveFn.apply(vals, dev_t(b), rp, col, dict(tol=1e-12, maxit=2000, adjoint_maxit=1))
+    with pytest.raises(solver.NotConvergedError) as e:
+        (x * dev_t(inputs.random_vector(A.n, 3))).sum().backward()
+    assert "adjoint" in str(e.value)
+    vals.grad = None
+    x = solver.SolveFn.apply(vals, dev_t(b), rp, col, dict(tol=1e-12, maxit=2000, adjoint_maxit=1,
+                                                            allow_unconverged=True))
+    (x * dev_t(inputs.random_vector(A.n, 3))).sum().backward()
+    assert vals.grad is not None
