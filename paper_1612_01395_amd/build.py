@@ -2,7 +2,11 @@
 
 hipcc cross-compiles without a GPU.  Flags: -ffp-contract=off keeps every
 + and * a separately rounded binary64 operation (the library's arithmetic
-contract); packed FP32 instructions are disabled.
+contract); the device target feature -packed-fp32-ops keeps the compiler from
+forming packed binary32 instructions.  hipcc's host pass warns that x86 does
+not know that feature; the device pass honours it (tests/test_build_flags.py
+shows the difference on a small kernel and checks the built library's device
+code for packed binary32 instructions).
 """
 
 from __future__ import annotations

@@ -2022,12 +2022,17 @@ __global__ __launch_bounds__(kWG) void k_fill_t(CsrOp op, int32_t* __restrict__ 
   }
 }
 
-// Orders each row of A^T by (row of A, stored position): insertion sort.
+// Rows of A^T longer than this are ordered by a workgroup each (k_sort_t_long).
+constexpr int32_t kShortRowT = 64;
+
+// Orders each short row of A^T by (row of A, stored position): insertion sort
+// by one thread.
 __global__ __launch_bounds__(kWG) void k_sort_t(int32_t n, const int32_t* __restrict__ rp_t, int32_t* __restrict__ ci_t,
                                                 double* __restrict__ va_t, int32_t* __restrict__ orig) {
   const int32_t j = blockIdx.x * kWG + threadIdx.x;
   if (j >= n) return;
   const int32_t b = rp_t[j], e = rp_t[j + 1];
+  if (e - b > kShortRowT) return;
   for (int32_t k = b + 1; k < e; ++k) {
     const int32_t c = ci_t[k], o = orig[k];
     const double v = va_t[k];
@@ -2041,6 +2046,55 @@ __global__ __launch_bounds__(kWG) void k_sort_t(int32_t n, const int32_t* __rest
     ci_t[m + 1] = c;
     va_t[m + 1] = v;
     orig[m + 1] = o;
+  }
+}
+
+// Orders each long row of A^T (more than kShortRowT entries) by the stored
+// position of its entries in A -- the same order as (row of A, stored
+// position), since CSR stores rows in order; the positions are distinct.  One
+// workgroup per row (grid-strided), a bitonic network in the form whose every
+// compare-exchange puts the smaller key at the lower index: each merge of two
+// sorted halves compares element t with its mirror in the block, then
+// half-cleaners at distances size/4, ..., 1.  Indices past the row's length
+// then behave as +infinity and are never read or written, so the row needs no
+// padding.  O(L log^2 L) work per row of length L.
+__global__ __launch_bounds__(kWG) void k_sort_t_long(int32_t n, const int32_t* __restrict__ rp_t,
+                                                     int32_t* __restrict__ ci_t, double* __restrict__ va_t,
+                                                     int32_t* __restrict__ orig) {
+  for (int32_t j = blockIdx.x; j < n; j += gridDim.x) {
+    const int32_t b = rp_t[j], len = rp_t[j + 1] - b;
+    if (len <= kShortRowT) continue;  // the same for every thread of the workgroup
+    int32_t P = 1;
+    while (P < len) P <<= 1;
+    auto cmp_swap = [&](int32_t lo, int32_t hi) {  // lo < hi
+      if (hi >= len) return;
+      const int32_t ol = orig[b + lo], oh = orig[b + hi];
+      if (ol > oh) {
+        orig[b + lo] = oh;
+        orig[b + hi] = ol;
+        const int32_t c = ci_t[b + lo];
+        ci_t[b + lo] = ci_t[b + hi];
+        ci_t[b + hi] = c;
+        const double v = va_t[b + lo];
+        va_t[b + lo] = va_t[b + hi];
+        va_t[b + hi] = v;
+      }
+    };
+    for (int32_t size = 2; size <= P; size <<= 1) {
+      const int32_t half = size >> 1;
+      for (int32_t t = threadIdx.x; t < P / 2; t += kWG) {
+        const int32_t blk = t / half, off = t % half;
+        cmp_swap(blk * size + off, blk * size + size - 1 - off);
+      }
+      __syncthreads();
+      for (int32_t d = size >> 2; d >= 1; d >>= 1) {
+        for (int32_t t = threadIdx.x; t < P / 2; t += kWG) {
+          const int32_t lo = (t / d) * 2 * d + t % d;
+          cmp_swap(lo, lo + d);
+        }
+        __syncthreads();
+      }
+    }
   }
 }
 

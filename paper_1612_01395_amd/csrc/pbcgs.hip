@@ -1820,6 +1820,7 @@ int pbcgs_op_transpose(pbcgs_ctx_t ctx, pbcgs_op_t A, pbcgs_op_t* out) {
     HIP_TRY(ctx, hipMemcpyAsync(cnt, rp_t, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
     k_fill_t<<<(n + kWG - 1) / kWG, kWG, 0, s>>>(op, cnt, ci_t, va_t, orig);
     k_sort_t<<<(n + kWG - 1) / kWG, kWG, 0, s>>>(n, rp_t, ci_t, va_t, orig);
+    k_sort_t_long<<<(int)std::min<int64_t>(n, 1024), kWG, 0, s>>>(n, rp_t, ci_t, va_t, orig);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipStreamSynchronize(s));
     return PBCGS_SUCCESS;

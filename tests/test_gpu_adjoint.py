@@ -36,6 +36,43 @@ def _mats():
 MATS = _mats()
 
 
+def _arrowhead(n, extra_long=()):
+    """Dense first row and first column plus the diagonal (column 0 of A, so
+    row 0 of A^T, holds n entries), and further columns with the given numbers
+    of entries at random rows; values random of both signs."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(n)
+    rows = [np.zeros(n, np.int64), np.arange(n), np.arange(n)]
+    cols = [np.arange(n), np.zeros(n, np.int64), np.arange(n)]
+    for c, m in extra_long:
+        rows.append(rng.choice(n, size=m, replace=False))
+        cols.append(np.full(m, c))
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    v = rng.standard_normal(len(r))
+    M = sp.coo_matrix((v, (r, c)), shape=(n, n)).tocsr()  # duplicates summed
+    M.sort_indices()
+    M = M + sp.diags(np.full(n, 50.0))
+    M = M.tocsr()
+    M.sort_indices()
+    return oracle.CSR(M.indptr, M.indices, M.data)
+
+
+@pytest.mark.parametrize("n,extra", [(20000, ()), (3000, ((5, 65), (6, 64), (7, 1000), (8, 2049), (9, 2999))),
+                                     (70, ((3, 65),))])
+def test_transpose_long_columns_bitwise(n, extra):
+    """Columns longer than one thread's share are ordered by a workgroup each;
+    the product with A^T sums every row in ascending column order like the
+    oracle's transpose."""
+    require_gpu()
+    A = _arrowhead(n, extra)
+    say(f"transpose arrowhead n={n} longest column {int(np.bincount(A.col).max())}")
+    T_or = oracle.transpose(A)
+    T = solver.transpose(csr_op(A))
+    for seed in (3, 4):
+        x = inputs.random_vector(A.n, seed)
+        assert same(host(solver.spmv(T, dev_t(x))), oracle.spmv(T_or, x))
+
+
 @pytest.mark.parametrize("name", list(MATS))
 def test_transpose_bitwise(name):
     require_gpu()
