@@ -102,7 +102,8 @@ def parse():
     return p.parse_args()
 
 
-def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: bool = True, index_bytes: int = 4):
+def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: bool = True, index_bytes: int = 4,
+                      dia: int = 0):
     """Algorithmic HBM bytes of the two dominant kernels of one iteration and
     of the whole iteration: (K_a, K_b, iteration).
 
@@ -111,7 +112,10 @@ def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: boo
     int16 copy, 4 for int32 columns -- and f64 val; nothing for the stencil)
     and one read or write of each N-vector (the gathered SpMV input counted
     once).  Jacobi
-    with a constant diagonal is a scalar (no dinv vector).
+    with a constant diagonal is a scalar (no dinv vector).  With ``dia`` > 0
+    the operator is read through its diagonal layout instead: a 4-byte mask per
+    row and one 8-byte value per diagonal and row (absent entries' slots
+    included).
 
     Folded Jacobi (A M^{-1} formed, Algorithm 9 on it): K_a reads w, r, v, s,
     z, p and writes p, s, t, z (10 vectors); K_b reads z, r, s, w, t, x, p, r0
@@ -127,7 +131,7 @@ def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: boo
     w, z, x, p, writes x, r: 8): 24 per iteration.
     """
     vec = 8 * N
-    mat = 0 if stencil else 4 * (N + 1) + (8 + index_bytes) * nnz
+    mat = 0 if stencil else (4 * N + 8 * dia * N if dia else 4 * (N + 1) + (8 + index_bytes) * nnz)
     if variant == "ca_bicgstab":
         return mat + 4 * vec, mat + 5 * vec, 24 * vec + 2 * mat
     if variant == "bicgstab":
@@ -166,7 +170,7 @@ def fixed_iterations(solve_fn, m: int, warm: int = 3, reps: int = 5):
     return {"us_per_iter": round((full - setup) / m * 1e3, 2), "setup_us": round(setup * 1e3, 1), "iters": m}
 
 
-def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool, index_bytes: int = 4):
+def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool, index_bytes: int = 4, dia: int = 0):
     """Algorithmic HBM bytes of one iteration of the CG family (Section 2) on
     a CSR operator with Jacobi by a constant (a scalar, no vector) or none.
 
@@ -180,7 +184,7 @@ def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool, index_byt
     m = w: 12.  One SpMV per iteration in each.
     """
     vec = 8 * N
-    mat = 4 * (N + 1) + (8 + index_bytes) * nnz
+    mat = 4 * N + 8 * dia * N if dia else 4 * (N + 1) + (8 + index_bytes) * nnz
     passes = {"cg": (12, 11), "cgcg": (14, 11), "pipe_cg": (18, 12)}[variant][0 if jacobi else 1]
     return passes * vec + mat
 
@@ -311,6 +315,7 @@ def main():
     nnz = val.numel()
     A = solver.csr(rp, col, val)
     ib = A.index_bytes  # 2: the operator holds the compact int16 column copy
+    nd = A.diagonals    # 7: the solves read the operator through its diagonal layout
     xt = torch.from_numpy(inputs.x_true(N)).to(dev)
     b = solver.spmv(A, xt)
     mid = w.n // 2
@@ -346,12 +351,13 @@ def main():
         "ca": ("csr", "ca_bicgstab", "jacobi_folded"),
         "pipe_norr": ("csr", "pbicgstab", "jacobi_folded"),
         "pipe_i32": ("csr", "pbicgstab_rr", "jacobi_folded", {"index32": True}),  # int32 columns
+        "pipe_csr": ("csr", "pbicgstab_rr", "jacobi_folded", {"diagonal_layout": False}),  # CSR stream, compact columns
         "pipe_alg11": ("csr", "pbicgstab_rr", "jacobi"),
         "bicg_alg10": ("csr", "bicgstab", "jacobi"),
         "st_pipe": ("stencil", "pbicgstab_rr", "jacobi_folded"),
         "st_bicg": ("stencil", "bicgstab", "jacobi_folded"),
     }
-    groups = {"pipe": ["pipe", "pipe_norr"], "index32": ["pipe_i32"], "bicg": ["bicg", "ca"], "explicit": ["pipe_alg11", "bicg_alg10"],
+    groups = {"pipe": ["pipe", "pipe_norr"], "index32": ["pipe_i32", "pipe_csr"], "bicg": ["bicg", "ca"], "explicit": ["pipe_alg11", "bicg_alg10"],
               "stencil": ["st_pipe", "st_bicg"]}
     res = {}
     for g in ("pipe", "index32", "bicg", "explicit", "stencil"):
@@ -379,7 +385,7 @@ def main():
             r = fixed_iterations(lambda m, op_=op_, variant=variant: solver.solve(
                 op_, b, variant=variant, precond="jacobi_folded", tol=0.0, maxit=m, rr_period=w.rr_period,
                 out=xbuf)[1], 200)
-            _, _, pib = algorithmic_bytes(N, nnz, variant, op_ is S, index_bytes=ib)
+            _, _, pib = algorithmic_bytes(N, nnz, variant, op_ is S, index_bytes=ib, dia=nd)
             r["gbps_effective"] = round(pib / (r["us_per_iter"] * 1e-6) / 1e9, 1)
             c2f[key] = r
         c2f["pbicgstab_over_bicgstab_csr"] = round(c2f["bicgstab_csr"]["us_per_iter"]
@@ -438,7 +444,7 @@ def main():
                 entry[variant] = {"iters_per_s": round(rate, 2), "iters_per_solve": cinfo.iters,
                                   "ms_per_solve": round(cdt / args.steps * 1e3, 3),
                                   "gbps_effective": round(algorithmic_bytes_cg(ws.N, vals.numel(), variant, True,
-                                                                              As.index_bytes)
+                                                                              As.index_bytes, As.diagonals)
                                                           * rate / 1e9, 1),
                                   "syncs_per_iter": cinfo.syncs_per_iter, "relres_true": cinfo.relres_true}
             cgfam[f"{side}^3"] = entry
@@ -447,7 +453,7 @@ def main():
     # ---- roofline of the dominant kernel: one solve with per-kernel events -------
     _, pinfo = solver.solve(A, b, variant="pbicgstab_rr", precond="jacobi_folded", out=xbuf, time_kernels=True,
                             **common)
-    ba, bb, _ = algorithmic_bytes(N, nnz, "pbicgstab", False, index_bytes=ib)
+    ba, bb, _ = algorithmic_bytes(N, nnz, "pbicgstab", False, index_bytes=ib, dia=nd)
     avg = [pinfo.kernel_ms[k] / max(pinfo.kernel_calls[k], 1) for k in range(2)]
     dom = 0 if pinfo.kernel_ms[0] >= pinfo.kernel_ms[1] else 1
     dom_bytes = (ba, bb)[dom]
@@ -462,6 +468,8 @@ def main():
         "traffic": measured_traffic(("k_pa", "k_pb")[dom]),
         "bytes_per_launch": dom_bytes,
         "column_index_bytes": ib,
+        "operator_layout": f"diagonal layout, {nd} diagonals (4-byte row mask + 8 bytes per diagonal and row)"
+        if nd else f"CSR stream, {ib}-byte column indices",
         "avg_launch_us": round(avg[dom] * 1e3, 2),
         "other_kernel_avg_us": round(avg[1 - dom] * 1e3, 2),
         "launches_timed": pinfo.kernel_calls[dom],
@@ -525,8 +533,9 @@ def main():
     if "configs" in legs:
         other_cfg = {}
 
-        def solve_leg(op, rhs, xo, variant, precond, wc, steps):
-            kwc = dict(variant=variant, precond=precond, tol=wc.tol, maxit=wc.maxit, rr_period=wc.rr_period, out=xo)
+        def solve_leg(op, rhs, xo, variant, precond, wc, steps, **extra):
+            kwc = dict(variant=variant, precond=precond, tol=wc.tol, maxit=wc.maxit, rr_period=wc.rr_period, out=xo,
+                       **extra)
             solver.solve(op, rhs, **kwc)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -551,10 +560,17 @@ def main():
             xc = torch.empty_like(bc)
             row = {"workload": f"{wc.dim}-D {wc.npts}-point {wc.n}^{wc.dim} (N={wc.N}, nnz={valc.numel()}), "
                                f"precond {precond or 'none'}, tol {wc.tol:g}, RR every {wc.rr_period}"}
+            row["operator_layout"] = (f"diagonal layout, {Ac.diagonals} diagonals" if Ac.diagonals
+                                      else f"CSR stream, {Ac.column_form} columns")
             for variant in ("pbicgstab_rr", "bicgstab"):
                 row[variant] = solve_leg(Ac, bc, xc, variant, precond, wc, steps)
             row["pbicgstab_over_bicgstab_iters_per_s"] = round(
                 row["pbicgstab_rr"]["iters_per_s"] / row["bicgstab"]["iters_per_s"], 4)
+            if Ac.diagonals and name == "c3":
+                row["csr_stream"] = {"operator": f"CSR stream, {Ac.column_form} columns"}
+                for variant in ("pbicgstab_rr", "bicgstab"):
+                    row["csr_stream"][variant] = solve_leg(Ac, bc, xc, variant, precond, wc, steps,
+                                                           diagonal_layout=False)
             if name == "c3":
                 # the same operator matrix-free: entries formed from the cell coefficients (bitwise the CSR results)
                 M27 = solver.convdiff27(wc.n, kappa, wc.beta, wc.shift)
@@ -580,12 +596,15 @@ def main():
                 row["matrix_free"] = mf
                 if "fixed" in legs:
                     c3f = {}
-                    for key, op_, variant in (("pbicgstab_rr_csr", Ac, "pbicgstab_rr"), ("bicgstab_csr", Ac, "bicgstab"),
-                                              ("pbicgstab_rr_matrix_free", M27, "pbicgstab_rr"),
-                                              ("bicgstab_matrix_free", M27, "bicgstab")):
-                        c3f[key] = fixed_iterations(lambda m, op_=op_, variant=variant: solver.solve(
+                    for key, op_, variant, lay in (
+                            ("pbicgstab_rr_assembled", Ac, "pbicgstab_rr", True), ("bicgstab_assembled", Ac, "bicgstab", True),
+                            ("pbicgstab_rr_csr_stream", Ac, "pbicgstab_rr", False),
+                            ("bicgstab_csr_stream", Ac, "bicgstab", False),
+                            ("pbicgstab_rr_matrix_free", M27, "pbicgstab_rr", True),
+                            ("bicgstab_matrix_free", M27, "bicgstab", True)):
+                        c3f[key] = fixed_iterations(lambda m, op_=op_, variant=variant, lay=lay: solver.solve(
                             op_, bc, variant=variant, precond=precond, tol=0.0, maxit=m, rr_period=wc.rr_period,
-                            out=xc)[1], 50)
+                            out=xc, diagonal_layout=lay)[1], 50)
                     fixed[f"c3_{wc.n}"] = c3f
                 del M27
             other_cfg[name] = row
@@ -721,7 +740,7 @@ def main():
 
     it, dt, info = res.get("pipe", (0, 1.0, None))
     value = it / dt if it else None
-    _, _, per_iter_bytes = algorithmic_bytes(N, nnz, "pbicgstab", False, index_bytes=ib)
+    _, _, per_iter_bytes = algorithmic_bytes(N, nnz, "pbicgstab", False, index_bytes=ib, dia=nd)
     out = {
         "metric": "p-BiCGStab iters/sec + HBM GB/s (3D 7-pt 128^3 FP64) vs plain BiCGStab, same GPU",
         "value": round(value, 2) if value else None,
@@ -747,10 +766,10 @@ def main():
         "autotuned_rows_per_wave_blocks": tune["best"],
     }
 
-    def leg_summary(key, variant, stencil, folded, index_bytes=ib):
+    def leg_summary(key, variant, stencil, folded, index_bytes=ib, dia=nd):
         lit, ldt, linfo = res[key]
         lval = lit / ldt
-        _, _, lbytes = algorithmic_bytes(N, nnz, variant, stencil, folded, index_bytes=index_bytes)
+        _, _, lbytes = algorithmic_bytes(N, nnz, variant, stencil, folded, index_bytes=index_bytes, dia=dia)
         return {"iters_per_s": round(lval, 2), "iters_per_solve": linfo.iters,
                 "ms_per_solve": round(ldt / args.steps * 1e3, 3), "gbps_effective": round(lbytes * lval / 1e9, 1),
                 "syncs_per_iter": linfo.syncs_per_iter, "relres_true": linfo.relres_true}
@@ -769,10 +788,15 @@ def main():
     if "pipe_norr" in res:
         out["pbicgstab_without_replacement"] = leg_summary("pipe_norr", "pbicgstab", False, True)
     if "pipe_i32" in res:
-        out["pbicgstab_rr_int32_columns"] = leg_summary("pipe_i32", "pbicgstab", False, True, index_bytes=4)
+        out["pbicgstab_rr_int32_columns"] = leg_summary("pipe_i32", "pbicgstab", False, True, index_bytes=4, dia=0)
         if value:
-            out["compact_over_int32_columns_iters_per_s"] = round(
+            out["diagonal_layout_over_int32_columns_iters_per_s"] = round(
                 value / out["pbicgstab_rr_int32_columns"]["iters_per_s"], 4)
+    if "pipe_csr" in res:
+        out["pbicgstab_rr_csr_stream"] = leg_summary("pipe_csr", "pbicgstab", False, True, dia=0)
+        if value:
+            out["diagonal_layout_over_csr_stream_iters_per_s"] = round(
+                value / out["pbicgstab_rr_csr_stream"]["iters_per_s"], 4)
     if "pipe_alg11" in res:
         out["explicit_jacobi"] = {"pbicgstab_rr_alg11": leg_summary("pipe_alg11", "pbicgstab", False, False),
                                   "bicgstab_alg10": leg_summary("bicg_alg10", "bicgstab", False, False)}

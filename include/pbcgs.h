@@ -123,7 +123,9 @@ typedef struct {
                             bit 2: alpha_{i+1} of PBICGSTAB(_RR) and CA_BICGSTAB by
                             eq. (5), the form without (r0, s_i), instead of eq. (3)
                             (Section 3.1); bit 3: read the caller's int32 col_idx
-                            even when the operator holds the compact int16 copy      */
+                            even when the operator holds a compact copy (implies
+                            bit 4); bit 4: read the CSR arrays even when the
+                            operator has a diagonal layout (pbcgs_op_diagonals)  */
     double* history;     /* nullable DEVICE array of maxit+1 doubles: history[i] =
                             ||r_i|| / ||r_0|| after i iterations (history[0] = 1)           */
 } pbcgs_opts;
@@ -163,8 +165,11 @@ const char* pbcgs_status_str(int status);
  * CSR operator (Section 2: the SPMV building block): n x n, int32 row_ptr[n+1]
  * with row_ptr[0] = 0 and row_ptr[n] = nnz, int32 col_idx[nnz] in [0, n),
  * float64 val[nnz].  Each row is applied in stored order; ascending columns
- * are the convention.  The arrays are borrowed and must outlive the operator.
- * The structure is validated on the device (ERR_INVALID_ARG if malformed).
+ * are the convention, not a requirement: a row stored in another order is
+ * summed in that order (so the result equals a row-by-row loop over the
+ * stored entries, bit for bit, but not the ascending-order sum).  The
+ * arrays are borrowed and must outlive the operator.  The structure is
+ * validated on the device (ERR_INVALID_ARG if malformed).
  * When every column j of a row i satisfies -32768 <= j - (i & ~63) <= 32767
  * (banded matrices such as the paper's stencil discretisations), the operator
  * also keeps a compact copy of the columns as int16 offsets from the row's
@@ -246,6 +251,19 @@ int64_t pbcgs_op_rows(pbcgs_op_t op);
  * holds a compact copy (either form, see pbcgs_op_csr), 4 for int32 columns,
  * 0 for a stencil; ERR_INVALID_ARG for NULL. */
 int pbcgs_op_index_bytes(pbcgs_op_t op);
+
+/* Number of diagonals of op's diagonal layout, or 0 when it has none.  A CSR
+ * operator with at most 32 distinct diagonals j - i, every row stored with
+ * strictly ascending columns, and at most 5/4 as many layout slots (diagonals
+ * x rows) as stored entries, also keeps a 32-bit mask per row of the diagonals
+ * it holds (4 n bytes, freed with the operator).  Solves then read it through a
+ * per-solve copy of the values laid out diagonal by diagonal (diagonals x rows
+ * doubles of context workspace, or floats in the precision form): per row the
+ * mask and one value per diagonal, no row pointers or column indices.  Each
+ * row is still summed over its entries in ascending column order, so results
+ * equal those of the CSR arrays bit for bit.  pbcgs_spmv, pbcgs_solve_noalloc
+ * and batched solves read the CSR arrays. */
+int pbcgs_op_diagonals(pbcgs_op_t op);
 
 /* Which column form the solves read for op (see pbcgs_op_csr). */
 enum { PBCGS_COLS_INT32 = 0, PBCGS_COLS_BLOCK16 = 1, PBCGS_COLS_DIAG16 = 2, PBCGS_COLS_NONE = 3 };

@@ -25,6 +25,7 @@ FLAG_DIRECT = 1       # launch kernels directly instead of replaying a HIP graph
 FLAG_TIME_KERNELS = 2  # time the two fused kernels of each iteration with events
 FLAG_ALPHA_EQ5 = 4     # alpha_{i+1} of the pipelined variants by eq. (5) instead of eq. (3)
 FLAG_INDEX32 = 8       # read the int32 columns even where the operator holds a compact copy
+FLAG_NO_DIA = 16       # read the CSR arrays even where the operator has a diagonal layout
 
 
 class Opts(ctypes.Structure):
@@ -93,6 +94,7 @@ _SIGNATURES = {
     "pbcgs_op_rows": (_i64, [_vp]),
     "pbcgs_op_index_bytes": (ctypes.c_int, [_vp]),
     "pbcgs_op_column_form": (ctypes.c_int, [_vp]),
+    "pbcgs_op_diagonals": (ctypes.c_int, [_vp]),
     "pbcgs_spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "pbcgs_dot": (ctypes.c_int, [_vp, _i64, _vp, _vp, ctypes.POINTER(_f64)]),
     "pbcgs_jacobi_dinv": (ctypes.c_int, [_vp, _vp, _vp]),

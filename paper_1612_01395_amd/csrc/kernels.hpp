@@ -243,6 +243,87 @@ struct StencilOp {
   }
 };
 
+// Diagonal layout of a CSR operator with at most kMaxDia distinct diagonals j - i
+// (stencil discretisations): the values of diagonal d (offset off[d], the
+// offsets ascending) lie contiguously, va[d * ld + i], and a 32-bit mask per
+// row marks the diagonals the row holds.  A product reads per row the mask and
+// one value per diagonal -- no row pointers, no column indices, every load
+// coalesced -- and sums the row's present diagonals in ascending offset
+// order, which is its CSR order (the layout is made only for rows stored with
+// ascending columns), so the result is the CSR product bit for bit.  The
+// values are a copy the context makes for each solve (binary64, the folded
+// values of A M^{-1}, or their binary32 rounding); the mask is structure and
+// belongs to the operator.
+constexpr int kMaxDia = 32;
+template <class V>
+struct DiaOpT {
+  using Val = V;
+  const uint32_t* __restrict__ mask;
+  const V* __restrict__ va;
+  int32_t n;
+  int32_t nd;
+  int32_t ld;     // stride between diagonals (rows rounded up to a multiple of 64)
+  int32_t pad_ = 0;
+  int32_t off[kMaxDia];
+
+  template <class X>
+  __device__ __forceinline__ V spmv(int32_t row, bool valid, const X* __restrict__ x) const {
+    const int32_t rc = min(row, n - 1);
+    const uint32_t m = valid ? mask[rc] : 0u;
+    V acc = V(0);
+#pragma unroll 4
+    for (int d = 0; d < nd; ++d) {
+      const bool present = (m >> d) & 1u;
+      const int32_t c = present ? rc + off[d] : rc;  // a present diagonal's column lies in [0, n)
+      const V v = __builtin_nontemporal_load(&va[(int64_t)d * ld + rc]);
+      const V t = acc + v * V(x[c]);
+      acc = present ? t : acc;
+    }
+    return acc;
+  }
+
+  // Rows row and row + 1 (row even) by one lane, for the kernels that take two
+  // rows per lane: the two values of a diagonal are one 2-element load, and
+  // for an even offset so are the two x values.  valid1 implies valid0.
+  template <class X>
+  __device__ __forceinline__ void spmv2(int32_t row, bool valid0, bool valid1, const X* __restrict__ x, V& y0,
+                                        V& y1) const {
+    typedef V V2 __attribute__((ext_vector_type(2)));
+    typedef X X2 __attribute__((ext_vector_type(2)));
+    const int32_t r0 = min(row, n - 1);
+    const int32_t r1 = min(row + 1, n - 1);
+    const uint32_t m0 = valid0 ? mask[r0] : 0u, m1 = valid1 ? mask[r1] : 0u;
+    // an even slot whose pair lies inside the layout (rows past n read a
+    // discarded copy of the last pair)
+    const int32_t rv = min(row, (n - 1) & ~1);
+    V a0 = V(0), a1 = V(0);
+#pragma unroll 4
+    for (int d = 0; d < nd; ++d) {
+      const bool p0 = (m0 >> d) & 1u, p1 = (m1 >> d) & 1u;
+      const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2*>(&va[(int64_t)d * ld + rv]));
+      X x0, x1;
+      // with an even offset and row + 1's entry present, x[row + off], x[row + off + 1]
+      // both lie in [0, n) (row + 1 + off is odd, so at least 1) and form an
+      // aligned pair of the (at least 16-byte aligned) vector
+      if ((off[d] & 1) == 0 && p1) {
+        const X2 xx = *reinterpret_cast<const X2*>(&x[row + off[d]]);
+        x0 = xx.x;
+        x1 = xx.y;
+      } else {
+        x0 = x[p0 ? r0 + off[d] : r0];
+        x1 = x[p1 ? r1 + off[d] : r1];
+      }
+      const V t0 = a0 + v.x * V(x0), t1 = a1 + v.y * V(x1);
+      a0 = p0 ? t0 : a0;
+      a1 = p1 ? t1 : a1;
+    }
+    y0 = a0;
+    y1 = a1;
+  }
+};
+using DiaOp = DiaOpT<double>;
+using DiaOpF = DiaOpT<float>;
+
 // Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane l receives the
 // value of lane l - 1 (shr) or l + 1 (shl); the lane without a source (0 or 63)
 // keeps `fill`.
@@ -606,6 +687,52 @@ __device__ __forceinline__ void produce(const Args& a, Body body) {
   }
   // no barrier here: a kernel produces once per launch, and the persistent
   // kernel's grid barrier separates its reductions
+}
+
+// As produce(), with each lane taking two neighbouring rows: lane l of a
+// 128-row block handles rows 2l and 2l + 1, and the body returns their sum.
+// Those two rows are sibling leaves of the balanced tree over the row index,
+// so the wave, workgroup and grid sums are the same tree and the partials are
+// bit for bit those of produce(); the wave covers the same 64 R rows as R / 2
+// blocks of 128.  Body(row, valid0, valid1, d) with row even; needs R >= 2.
+template <int ND, class T = double, class Body>
+__device__ __forceinline__ void produce2(const Args& a, Body body) {
+  __shared__ T lvl[4][kLevels][ND];
+  __shared__ T wtot[ND][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t wbase = ((int64_t)wg_index(a) * 4 + wave) * a.R * 64;
+  const int R2 = a.R >> 1;
+  for (int j = 0; j < R2; ++j) {
+    const int64_t b0 = wbase + (int64_t)j * 128;
+    T d[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) d[k] = T(0);
+    if (b0 < a.n) {
+      const int32_t row = (int32_t)(b0 + 2 * lane);
+      body(row, row < a.n, row + 1 < a.n, d);
+      wave_sum63<ND, T>(d);
+    }
+    if (lane == 63) {
+      int l = 0;
+      for (int bits = j; bits & 1; bits >>= 1, ++l) {
+#pragma unroll
+        for (int k = 0; k < ND; ++k) d[k] = lvl[wave][l][k] + d[k];
+      }
+#pragma unroll
+      for (int k = 0; k < ND; ++k) lvl[wave][l][k] = d[k];
+    }
+  }
+  if (lane == 63) {
+    const int top = __builtin_ctz((unsigned)R2);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) wtot[k][wave] = lvl[wave][top][k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < ND; ++k)
+      a.pout[k * a.pstride + wg_index(a)] = double((wtot[k][0] + wtot[k][1]) + (wtot[k][2] + wtot[k][3]));
+  }
 }
 
 // The workgroup's rows without a reduction; Body(row, valid) as above.
@@ -1747,6 +1874,113 @@ __global__ __launch_bounds__(kWG) void k_mp_pb(Op32 op, Args a) {
   });
 }
 
+// k_mp_pa (without a pending replacement) and k_mp_pb with two neighbouring
+// rows per lane (see produce2): each binary32 vector access is one 8-byte
+// load or store of the pair, so a wave moves 512 instead of 256 bytes per
+// access; the operator provides spmv2.  The arithmetic of each row and the
+// reduction trees are those of k_mp_pa / k_mp_pb, so the results are the same
+// bits.  The workspace vectors are padded to 64 rows, so a pair starting at
+// the last row stays inside them (the element past n receives an unused
+// value); x, the caller's n doubles, is accessed row by row.
+template <class Op32>
+__global__ __launch_bounds__(kWG) void k_mp_pa2(Op32 op, Args a) {
+  PBCGS_PROLOGUE(st)
+  if (a.first) {
+    double g[1];
+    gather_sums<1, float>(a, g);
+    fin_setup_alpha(st, g[0]);
+  } else {
+    double g[5];
+    gather_sums<5, float>(a, g);
+    fin_pipe_b_mp(st, a.hist, g, false, a.aform);
+  }
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const float af = float(st.alpha), bf = float(st.beta), wf_ = float(st.omega);
+  produce2<2, float>(a, [&](int32_t row, bool valid0, bool valid1, float (&d)[2]) {
+    float t0, t1;
+    op.spmv2(row, valid0, valid1, a.wf, t0, t1);
+    if (!valid0) return;
+    const float2 r = *reinterpret_cast<const float2*>(&a.rf[row]);
+    const float2 w = *reinterpret_cast<const float2*>(&a.wf[row]);
+    const float2 v = *reinterpret_cast<const float2*>(&a.vf[row]);
+    const float2 so = *reinterpret_cast<const float2*>(&a.sf[row]);
+    const float2 zo = *reinterpret_cast<const float2*>(&a.zf[row]);
+    const float2 po = *reinterpret_cast<const float2*>(&a.pf[row]);
+    float2 p, s, z, t;
+    p.x = r.x + bf * (po.x - wf_ * so.x);
+    p.y = r.y + bf * (po.y - wf_ * so.y);
+    s.x = w.x + bf * (so.x - wf_ * zo.x);
+    s.y = w.y + bf * (so.y - wf_ * zo.y);
+    z.x = t0 + bf * (zo.x - wf_ * v.x);
+    z.y = t1 + bf * (zo.y - wf_ * v.y);
+    t.x = t0;
+    t.y = t1;
+    *reinterpret_cast<float2*>(&a.pf[row]) = p;
+    *reinterpret_cast<float2*>(&a.sf[row]) = s;
+    *reinterpret_cast<float2*>(&a.tf[row]) = t;
+    *reinterpret_cast<float2*>(&a.zf[row]) = z;
+    const float q0 = r.x - af * s.x, y0 = w.x - af * z.x;
+    const float q1 = r.y - af * s.y, y1 = w.y - af * z.y;
+    // the pair's two leaves of the reduction tree (a row past n is a zero leaf)
+    d[0] = q0 * y0 + (valid1 ? q1 * y1 : 0.0f);
+    d[1] = y0 * y0 + (valid1 ? y1 * y1 : 0.0f);
+  });
+}
+
+template <class Op32>
+__global__ __launch_bounds__(kWG) void k_mp_pb2(Op32 op, Args a) {
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2, float>(a, g2);
+  const double alpha = st.alpha;
+  const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
+  if (yz) {
+    each_row(a, [&](int32_t row, bool valid) {
+      if (valid) a.x[row] = a.x[row] + alpha * double(a.pf[row]);
+    });
+    return;
+  }
+  if (st.status != DS_RUNNING) return;
+  const double omega = st.omega;
+  const float af = float(alpha), wn = float(omega);
+  produce2<5, float>(a, [&](int32_t row, bool valid0, bool valid1, float (&d)[5]) {
+    float v0, v1;
+    op.spmv2(row, valid0, valid1, a.zf, v0, v1);
+    if (!valid0) return;
+    const float2 r = *reinterpret_cast<const float2*>(&a.rf[row]);
+    const float2 s = *reinterpret_cast<const float2*>(&a.sf[row]);
+    const float2 w = *reinterpret_cast<const float2*>(&a.wf[row]);
+    const float2 z = *reinterpret_cast<const float2*>(&a.zf[row]);
+    const float2 t = *reinterpret_cast<const float2*>(&a.tf[row]);
+    const float2 p = *reinterpret_cast<const float2*>(&a.pf[row]);
+    const float2 r0 = *reinterpret_cast<const float2*>(&a.r0f[row]);
+    const float q0 = r.x - af * s.x, y0 = w.x - af * z.x;
+    const float q1 = r.y - af * s.y, y1 = w.y - af * z.y;
+    float2 rn, wnew, vv;
+    rn.x = q0 - wn * y0;
+    rn.y = q1 - wn * y1;
+    wnew.x = y0 - wn * (t.x - af * v0);
+    wnew.y = y1 - wn * (t.y - af * v1);
+    vv.x = v0;
+    vv.y = v1;
+    a.x[row] = a.x[row] + alpha * double(p.x) + omega * double(q0);
+    if (valid1) a.x[row + 1] = a.x[row + 1] + alpha * double(p.y) + omega * double(q1);
+    *reinterpret_cast<float2*>(&a.vf[row]) = vv;
+    *reinterpret_cast<float2*>(&a.rf[row]) = rn;
+    *reinterpret_cast<float2*>(&a.wf[row]) = wnew;
+    d[0] = r0.x * rn.x + (valid1 ? r0.y * rn.y : 0.0f);
+    d[1] = r0.x * wnew.x + (valid1 ? r0.y * wnew.y : 0.0f);
+    d[2] = r0.x * s.x + (valid1 ? r0.y * s.y : 0.0f);
+    d[3] = r0.x * z.x + (valid1 ? r0.y * z.y : 0.0f);
+    d[4] = rn.x * rn.x + (valid1 ? rn.y * rn.y : 0.0f);
+  });
+}
+
+template <class Op> struct HasSpmv2 : std::false_type {};
+template <class V> struct HasSpmv2<DiaOpT<V>> : std::true_type {};
+
 // Replacement iteration, phase B': omega, then only the binary64 x update.
 __global__ __launch_bounds__(kWG) void k_mp_rr_x(Args a) {
   PBCGS_PROLOGUE(st)
@@ -2205,6 +2439,55 @@ __global__ __launch_bounds__(kWG) void k_diag_code(CsrOp op, int32_t n, const in
       if (t[(h + p) & 63] == d) { slot = (h + p) & 63; break; }
     }
     cd[k] = (uint16_t)((row & 63) | (slot << 6));
+  }
+}
+
+// Mask of the diagonal layout: bit d of mask[i] is set when row i holds
+// diagonal off[d] (off: nd sorted offsets).  flag := 1 when a row's columns do
+// not strictly ascend or a diagonal is missing from off (no layout then).
+__global__ __launch_bounds__(kWG) void k_dia_mask(CsrOp op, int32_t n, const int32_t* __restrict__ off, int32_t nd,
+                                                  uint32_t* __restrict__ mask, int32_t* flag) {
+  const int32_t row = blockIdx.x * kWG + threadIdx.x;
+  if (row >= n) return;
+  uint32_t m = 0;
+  int32_t prev = INT32_MIN;
+  bool bad = false;
+  const int32_t e = op.rp[row + 1];
+  for (int32_t k = op.rp[row]; k < e; ++k) {
+    const int32_t d = op.ci[k] - row;
+    int s = -1;
+    for (int t = 0; t < nd; ++t)
+      if (off[t] == d) s = t;
+    if (s < 0 || d <= prev) { bad = true; break; }
+    m |= 1u << s;
+    prev = d;
+  }
+  mask[row] = m;
+  if (bad) atomicOr(flag, 1);
+}
+
+// Values of the diagonal layout for one solve: the row's stored values in
+// order into its present slots (absent slots 0), scaled by dinv of the column
+// when folded (PC_VEC: the vector, PC_SCALAR: the constant; one rounding, as
+// the folded CSR values) and rounded once to V.
+template <int PC, class V>
+__global__ __launch_bounds__(kWG) void k_dia_fill(CsrOp op, int32_t n, const uint32_t* __restrict__ mask, int32_t nd,
+                                                  int32_t ld, V* __restrict__ dia, const double* __restrict__ dinv,
+                                                  double dinv_s) {
+  const int32_t row = blockIdx.x * kWG + threadIdx.x;
+  if (row >= n) return;
+  const uint32_t m = mask[row];
+  int32_t k = op.rp[row];
+  for (int d = 0; d < nd; ++d) {
+    V v = V(0);
+    if ((m >> d) & 1u) {
+      double a = op.va[k];
+      if (PC == PC_VEC) a = a * dinv[op.ci[k]];
+      if (PC == PC_SCALAR) a = a * dinv_s;
+      v = V(a);
+      ++k;
+    }
+    dia[(int64_t)d * ld + row] = v;
   }
 }
 

@@ -102,6 +102,8 @@ struct pbcgs_ctx_s {
   size_t ahat_cap = 0;      // doubles
   float* a32 = nullptr;     // binary32 operator values (precision form, CSR)
   size_t a32_cap = 0;       // floats
+  void* dia = nullptr;      // values of an operator's diagonal layout for the current solve
+  size_t dia_cap = 0;       // bytes
   // batched solves: system table, workgroup map, vectors, states, partials, host poll copies
   SysDesc* bsys = nullptr;
   size_t bsys_cap = 0;
@@ -152,6 +154,11 @@ struct pbcgs_op_s {
   // the 64-entry diagonal table; owned by the operator
   uint16_t* cd = nullptr;
   int32_t* dg = nullptr;
+  // diagonal layout (at most kMaxDia diagonals, rows with ascending columns):
+  // the per-row masks and the ascending diagonal offsets; owned by the operator
+  uint32_t* dmask = nullptr;
+  int32_t ndia = 0;
+  int32_t dia_off[kMaxDia] = {};
 };
 
 namespace {
@@ -231,6 +238,8 @@ bool cg_family(int32_t variant) {
 int32_t alpha_form(const pbcgs_opts& o) { return (o.flags & 4) ? 5 : 3; }
 // opts.flags bit 3 keeps a solve on the caller's int32 column indices.
 bool compact_ok(const pbcgs_opts& o) { return (o.flags & 8) == 0; }
+// opts.flags bit 4 (or bit 3) keeps a solve on the CSR stream where the operator has a diagonal layout.
+bool dia_ok(const pbcgs_opts& o) { return (o.flags & 24) == 0; }
 
 Args base_args(pbcgs_ctx_t ctx, const Shape& sh) {
   Args a;
@@ -298,6 +307,25 @@ int ensure_a32(pbcgs_ctx_t ctx, size_t floats) {
     return fail(ctx, PBCGS_ERR_ALLOC, "allocation of " + std::to_string(floats * 4) + " bytes of binary32 values failed");
   }
   ctx->a32_cap = floats;
+  return PBCGS_SUCCESS;
+}
+
+int ensure_dia(pbcgs_ctx_t ctx, size_t bytes) {
+  if (ctx->dia_cap >= bytes) return PBCGS_SUCCESS;
+  if (ctx->noalloc) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the call may not allocate and its scratch is too small");
+  if (ctx->dia) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->dia);
+    ctx->dia = nullptr;
+    ctx->dia_cap = 0;
+    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+  }
+  if (hipMalloc(&ctx->dia, std::max<size_t>(bytes, 8)) != hipSuccess) {
+    ctx->dia = nullptr;
+    return fail(ctx, PBCGS_ERR_ALLOC, "allocation of " + std::to_string(bytes) + " bytes of diagonal-layout values failed");
+  }
+  ctx->dia_cap = bytes;
   return PBCGS_SUCCESS;
 }
 
@@ -474,6 +502,13 @@ struct Driver {
 
   dim3 grid() const { return dim3((unsigned)a.G); }
 
+  // the binary32 kernels take two rows per lane when the operator supports it
+  // and every wave owns at least two 64-row blocks (PBCGS_TWO_ROWS=0 turns it off)
+  bool two_rows() const {
+    if constexpr (MP && HasSpmv2<Op>::value) return a.R >= 2 && env_int("PBCGS_TWO_ROWS", 1) != 0;
+    return false;
+  }
+
   void setup() {
     hipStream_t s = ctx->stream;
     if constexpr (MP) {
@@ -506,7 +541,12 @@ struct Driver {
         k_mp_pa<Op, Op64, true><<<grid(), kWG, 0, s>>>(op, op64, L(-1, PB_A));
       } else {
         timed(0, [&] {
-          k_mp_pa<Op, Op64, false><<<grid(), kWG, 0, s>>>(op, op64, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
+          if (two_rows()) {
+            if constexpr (HasSpmv2<Op>::value)
+              k_mp_pa2<Op><<<grid(), kWG, 0, s>>>(op, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
+          } else {
+            k_mp_pa<Op, Op64, false><<<grid(), kWG, 0, s>>>(op, op64, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
+          }
         });
       }
       if (rr) {
@@ -514,7 +554,13 @@ struct Driver {
         k_mp_rr_r<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, -1));
         k_mp_rr_w<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, PB_B));
       } else {
-        timed(1, [&] { k_mp_pb<Op><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B)); });
+        timed(1, [&] {
+          if (two_rows()) {
+            if constexpr (HasSpmv2<Op>::value) k_mp_pb2<Op><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B));
+          } else {
+            k_mp_pb<Op><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B));
+          }
+        });
       }
     } else {
       iteration64(i);
@@ -874,6 +920,8 @@ static_assert(sizeof(StencilOp<7>) == 4 * sizeof(int32_t) + 7 * sizeof(double), 
 static_assert(sizeof(StencilOp<5>) == 4 * sizeof(int32_t) + 5 * sizeof(double), "StencilOp padding");
 static_assert(sizeof(StencilOp<7, float>) == 4 * sizeof(int32_t) + 7 * sizeof(float), "StencilOp padding");
 static_assert(sizeof(StencilOp<5, float>) == 4 * sizeof(int32_t) + 5 * sizeof(float), "StencilOp padding");
+static_assert(sizeof(DiaOp) == 2 * sizeof(void*) + (4 + kMaxDia) * sizeof(int32_t) && sizeof(DiaOpF) == sizeof(DiaOp),
+              "DiaOpT padding");
 static_assert(sizeof(Conv27) == 2 * sizeof(int32_t) + 2 * sizeof(void*) + 5 * sizeof(double) &&
               sizeof(Conv27Op<float, true>) == sizeof(Conv27), "Conv27Op padding");
 
@@ -1263,6 +1311,7 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->ahat) (void)hipFree(ctx->ahat);
   if (ctx->a32) (void)hipFree(ctx->a32);
+  if (ctx->dia) (void)hipFree(ctx->dia);
   if (ctx->bsys) (void)hipFree(ctx->bsys);
   if (ctx->bmap) (void)hipFree(ctx->bmap);
   if (ctx->bws) (void)hipFree(ctx->bws);
@@ -1359,6 +1408,115 @@ int make_compact(pbcgs_ctx_t ctx, pbcgs_op_t A) {
 }
 }  // namespace
 
+// Makes the diagonal layout's structure (see DiaOpT) for a validated CSR
+// operator with at most kMaxDia distinct diagonals whose rows store their
+// columns in ascending order, when the layout's slots (diagonals x rows) are at
+// most 5/4 of the stored entries.  Like the compact columns it changes how
+// the operator is read, never a result; an operator that does not qualify (or
+// a failed allocation) keeps the CSR stream and no error is raised.
+int make_dia(pbcgs_ctx_t ctx, pbcgs_op_t A) {
+  if (A->nnz == 0) return PBCGS_SUCCESS;
+  int32_t* tab = nullptr;
+  int32_t* doff = nullptr;
+  uint32_t* mask = nullptr;
+  auto release = [&]() {
+    if (tab) (void)hipFree(tab);
+    if (doff) (void)hipFree(doff);
+    if (mask) (void)hipFree(mask);
+  };
+  if (hipMalloc((void**)&tab, sizeof(int32_t) * 64) != hipSuccess ||
+      hipMalloc((void**)&doff, sizeof(int32_t) * kMaxDia) != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return PBCGS_SUCCESS;
+  }
+  const CsrOp op{A->rp, A->ci, A->va, A->n};
+  const int g = (A->n + kWG - 1) / kWG;
+  std::vector<int32_t> h(64, kEmptyDiag);
+  int rc = reset_flag(ctx);
+  if (rc == PBCGS_SUCCESS && hipMemcpyAsync(tab, h.data(), sizeof(int32_t) * 64, hipMemcpyHostToDevice,
+                                            ctx->stream) != hipSuccess)
+    rc = fail(ctx, PBCGS_ERR_HIP, "diagonal table upload failed");
+  if (rc != PBCGS_SUCCESS) {
+    release();
+    return rc;
+  }
+  k_diag_collect<<<g, kWG, 0, ctx->stream>>>(op, A->n, tab, ctx->flag);
+  int32_t flag = 0;
+  rc = read_flag(ctx, &flag);  // synchronises: `h` may be reused
+  if (rc != PBCGS_SUCCESS || flag) {
+    release();
+    return rc;
+  }
+  if (hipMemcpy(h.data(), tab, sizeof(int32_t) * 64, hipMemcpyDeviceToHost) != hipSuccess) {
+    release();
+    return fail(ctx, PBCGS_ERR_HIP, "diagonal table download failed");
+  }
+  std::vector<int32_t> offs;
+  for (int32_t d : h)
+    if (d != kEmptyDiag) offs.push_back(d);
+  std::sort(offs.begin(), offs.end());
+  const int nd = (int)offs.size();
+  if (nd == 0 || nd > kMaxDia || (double)nd * (double)A->n > 1.25 * (double)A->nnz) {
+    release();
+    return PBCGS_SUCCESS;
+  }
+  if (hipMalloc((void**)&mask, sizeof(uint32_t) * (size_t)A->n) != hipSuccess) {
+    (void)hipGetLastError();
+    mask = nullptr;
+    release();
+    return PBCGS_SUCCESS;
+  }
+  rc = reset_flag(ctx);
+  if (rc == PBCGS_SUCCESS && hipMemcpyAsync(doff, offs.data(), sizeof(int32_t) * nd, hipMemcpyHostToDevice,
+                                            ctx->stream) != hipSuccess)
+    rc = fail(ctx, PBCGS_ERR_HIP, "diagonal offsets upload failed");
+  if (rc != PBCGS_SUCCESS) {
+    release();
+    return rc;
+  }
+  k_dia_mask<<<g, kWG, 0, ctx->stream>>>(op, A->n, doff, nd, mask, ctx->flag);
+  rc = read_flag(ctx, &flag);  // synchronises: `offs` may go
+  if (rc != PBCGS_SUCCESS || flag) {
+    release();
+    return rc;
+  }
+  A->dmask = mask;
+  A->ndia = nd;
+  for (int d = 0; d < nd; ++d) A->dia_off[d] = offs[(size_t)d];
+  mask = nullptr;
+  release();
+  return PBCGS_SUCCESS;
+}
+
+// The diagonal layout of A with this solve's values: the stored values, or
+// those of A M^{-1} (pc_fold PC_VEC / PC_SCALAR), rounded once to V.
+extern "C++" {
+template <class V>
+int dia_operator(pbcgs_ctx_t ctx, pbcgs_op_t A, int pc_fold, const double* dv, double ds, DiaOpT<V>* out) {
+  const int32_t ld = (int32_t)padded(A->n);
+  const int rc = ensure_dia(ctx, (size_t)A->ndia * (size_t)ld * sizeof(V));
+  if (rc != PBCGS_SUCCESS) return rc;
+  V* buf = static_cast<V*>(ctx->dia);
+  const CsrOp op{A->rp, A->ci, A->va, A->n};
+  const int g = (A->n + kWG - 1) / kWG;
+  if (pc_fold == PC_VEC) k_dia_fill<PC_VEC, V><<<g, kWG, 0, ctx->stream>>>(op, A->n, A->dmask, A->ndia, ld, buf, dv, ds);
+  else if (pc_fold == PC_SCALAR) k_dia_fill<PC_SCALAR, V><<<g, kWG, 0, ctx->stream>>>(op, A->n, A->dmask, A->ndia, ld, buf, dv, ds);
+  else k_dia_fill<PC_NONE, V><<<g, kWG, 0, ctx->stream>>>(op, A->n, A->dmask, A->ndia, ld, buf, dv, ds);
+  HIP_TRY(ctx, hipGetLastError());
+  DiaOpT<V> d;
+  std::memset(&d, 0, sizeof d);
+  d.mask = A->dmask;
+  d.va = buf;
+  d.n = A->n;
+  d.nd = A->ndia;
+  d.ld = ld;
+  for (int k = 0; k < A->ndia; ++k) d.off[k] = A->dia_off[k];
+  *out = d;
+  return PBCGS_SUCCESS;
+}
+}  // extern "C++"
+
 int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
                  const double* val, pbcgs_op_t* out) {
   if (!ctx || !out) return fail(ctx, PBCGS_ERR_INVALID_ARG, "ctx or out is NULL");
@@ -1387,8 +1545,9 @@ int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr
   A->ci = col_idx;
   A->va = val;
   rc = make_compact(ctx, A);
+  if (rc == PBCGS_SUCCESS) rc = make_dia(ctx, A);
   if (rc != PBCGS_SUCCESS) {
-    delete A;
+    (void)pbcgs_op_destroy(A);
     return rc;
   }
   *out = A;
@@ -1456,6 +1615,7 @@ int pbcgs_op_destroy(pbcgs_op_t op) {
     if (op->c16) (void)hipFree(op->c16);
     if (op->cd) (void)hipFree(op->cd);
     if (op->dg) (void)hipFree(op->dg);
+    if (op->dmask) (void)hipFree(op->dmask);
   }
   delete op;
   return PBCGS_SUCCESS;
@@ -1478,6 +1638,11 @@ int pbcgs_op_column_form(pbcgs_op_t op) {
   if (op->c16) return PBCGS_COLS_BLOCK16;
   if (op->cd) return PBCGS_COLS_DIAG16;
   return PBCGS_COLS_INT32;
+}
+
+int pbcgs_op_diagonals(pbcgs_op_t op) {
+  if (!op) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "op is NULL");
+  return op->ndia;
 }
 
 int pbcgs_spmv(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* x, double* y) {
@@ -1618,6 +1783,8 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
   if (folded && pc == PC_VEC && (A->kind == OP_ST5 || A->kind == OP_ST7))
     return fail(ctx, PBCGS_ERR_UNSUPPORTED, "folded Jacobi on a stencil needs a constant diagonal");
   const bool hat = (pc != PC_NONE) && !folded;
+  // a CSR operator with a diagonal layout is read through it (same results)
+  const bool use_dia = A->kind == OP_CSR && A->ndia > 0 && dia_ok(o) && !ctx->noalloc;
   if (cg_family(o.variant)) {
     // r, p, s, w, z; u = M^{-1} r in r^ and q in s^ (aliases without a preconditioner)
     a.r = v[1]; a.p = v[2]; a.s = v[3]; a.w = v[4]; a.z = v[5];
@@ -1654,15 +1821,12 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
       rc = ensure_ahat(ctx, (size_t)A->nnz);
       if (rc != PBCGS_SUCCESS) return rc;
     }
-    if (A->kind == OP_CSR) {
+    if (A->kind == OP_CSR && !use_dia) {
       rc = ensure_a32(ctx, (size_t)A->nnz);
       if (rc != PBCGS_SUCCESS) return rc;
     }
     return with_op(A, [&](auto op) -> int {
-      // run the binary32 form on op64 (A, or A M^{-1} formed)
-      auto go = [&](auto op64) -> int {
-        auto op32 = to_binary32(ctx, op64, A->nnz);
-        HIP_TRY(ctx, hipGetLastError());
+      auto run_mp = [&](auto op32, auto op64) -> int {
         Driver<decltype(op32), PC_NONE, decltype(op64), true> drv(ctx, op32, op64, a, o);
         drv.true_res = !folded;
         const int st = drv.run(info);
@@ -1673,6 +1837,21 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
         const int rc2 = true_relres(ctx, op, a, drv.rho0, &info->relres_true);
         if (rc2 != PBCGS_SUCCESS) return rc2;
         return st;
+      };
+      // run the binary32 form on op64 (A, or A M^{-1} formed); its binary32
+      // operator is op64 rounded, or the diagonal layout of those values
+      auto go = [&](auto op64) -> int {
+        if constexpr (IsCsr<decltype(op64)>::value) {
+          if (use_dia) {
+            DiaOpF op32;
+            const int rcd = dia_operator<float>(ctx, A, folded ? pc : PC_NONE, dv, ds, &op32);
+            if (rcd != PBCGS_SUCCESS) return rcd;
+            return run_mp(op32, op64);
+          }
+        }
+        auto op32 = to_binary32(ctx, op64, A->nnz);
+        HIP_TRY(ctx, hipGetLastError());
+        return run_mp(op32, op64);
       };
       if (!folded) return go(op);
       auto fop = fold_operator(ctx, A, op, pc, dv, ds);
@@ -1689,12 +1868,12 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     const double ds = a.dinv_s;
     a.dinv = nullptr;
     a.dinv_s = 0.0;
-    if (A->kind == OP_CSR) {
+    if (A->kind == OP_CSR && !use_dia) {
       rc = ensure_ahat(ctx, (size_t)A->nnz);
       if (rc != PBCGS_SUCCESS) return rc;
     }
     return with_op(A, [&](auto op) -> int {
-      auto fop = fold_operator(ctx, A, op, pc, dv, ds);
+      auto run_folded = [&](auto fop) -> int {
       if (pc == PC_VEC) k_fold_x<PC_VEC, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
       else k_fold_x<PC_SCALAR, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
       HIP_TRY(ctx, hipGetLastError());
@@ -1708,9 +1887,27 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
       const int rc2 = true_relres(ctx, op, a, drv.rho0, &info->relres_true);
       if (rc2 != PBCGS_SUCCESS) return rc2;
       return st;
+      };
+      if constexpr (IsCsr<decltype(op)>::value) {
+        if (use_dia) {
+          DiaOp dop;
+          const int rcd = dia_operator<double>(ctx, A, pc, dv, ds, &dop);
+          if (rcd != PBCGS_SUCCESS) return rcd;
+          return run_folded(dop);
+        }
+      }
+      return run_folded(fold_operator(ctx, A, op, pc, dv, ds));
     }, compact_ok(o));
   }
 
+  if (use_dia) {
+    DiaOp dop;
+    rc = dia_operator<double>(ctx, A, PC_NONE, nullptr, 0.0, &dop);
+    if (rc != PBCGS_SUCCESS) return rc;
+    if (pc == PC_NONE) return Driver<DiaOp, PC_NONE>(ctx, dop, a, o).run(info);
+    if (pc == PC_VEC) return Driver<DiaOp, PC_VEC>(ctx, dop, a, o).run(info);
+    return Driver<DiaOp, PC_SCALAR>(ctx, dop, a, o).run(info);
+  }
   return with_op(A, [&](auto op) -> int {
     using Op = decltype(op);
     if (pc == PC_NONE) return Driver<Op, PC_NONE>(ctx, op, a, o).run(info);
@@ -1841,7 +2038,8 @@ int pbcgs_op_transpose(pbcgs_ctx_t ctx, pbcgs_op_t A, pbcgs_op_t* out) {
   T->rp = T->own_rp = rp_t;
   T->ci = T->own_ci = ci_t;
   T->va = T->own_va = va_t;
-  const int rc2 = make_compact(ctx, T);
+  int rc2 = make_compact(ctx, T);
+  if (rc2 == PBCGS_SUCCESS) rc2 = make_dia(ctx, T);
   if (rc2 != PBCGS_SUCCESS) {
     (void)pbcgs_op_destroy(T);
     return rc2;

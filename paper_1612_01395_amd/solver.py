@@ -122,6 +122,12 @@ class Operator:
         f = L.check(L.lib().pbcgs_op_column_form(self.handle), self.ctx.handle)
         return {L.COLS_INT32: "int32", L.COLS_BLOCK16: "block16", L.COLS_DIAG16: "diag16", L.COLS_NONE: "none"}[f]
 
+    @property
+    def diagonals(self) -> int:
+        """Diagonals of the operator's diagonal layout (0: it has none; see
+        ``pbcgs_op_diagonals``)."""
+        return L.check(L.lib().pbcgs_op_diagonals(self.handle), self.ctx.handle)
+
     def close(self):
         if getattr(self, "handle", None):
             L.lib().pbcgs_op_destroy(self.handle)
@@ -260,16 +266,18 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
           precond: str | None = None, dinv: torch.Tensor | None = None, tol: float = 1e-8, maxit: int = 2000,
           rr_period: int = 50, rr_max: int = -1, history: bool = False, check_every: int = 0,
           graph: bool = True, time_kernels: bool = False, out: torch.Tensor | None = None,
-          precision: str = "fp64", alpha_form: int = 3, index32: bool = False):
+          precision: str = "fp64", alpha_form: int = 3, index32: bool = False, diagonal_layout: bool = True):
     """Solve A x = b; returns (x, SolveInfo).  x0 defaults to zero; ``out``
     (optional) receives the iterate in place of a new tensor.  ``alpha_form``
     5 takes alpha_{i+1} of the pipelined variants from eq. (5) instead of
     eq. (3) (Section 3.1).  ``index32`` reads the int32 column indices even
-    where the operator holds a compact copy (same result)."""
+    where the operator holds a compact copy; ``diagonal_layout=False`` reads
+    the CSR arrays even where the operator has a diagonal layout (same
+    results either way)."""
     return _solve(L.lib().pbcgs_solve, A, b, x0, variant=variant, precond=precond, dinv=dinv, tol=tol,
                   maxit=maxit, rr_period=rr_period, rr_max=rr_max, history=history, check_every=check_every,
                   graph=graph, time_kernels=time_kernels, out=out, precision=precision, alpha_form=alpha_form,
-                  index32=index32)
+                  index32=index32, diagonal_layout=diagonal_layout)
 
 
 def solve_noalloc(A: Operator, b: torch.Tensor, x: torch.Tensor, *, variant: str = "pbicgstab_rr",
@@ -288,7 +296,8 @@ def solve_noalloc(A: Operator, b: torch.Tensor, x: torch.Tensor, *, variant: str
 
 
 def _solve(entry, A: Operator, b: torch.Tensor, x0, *, variant, precond, dinv, tol, maxit, rr_period, rr_max,
-           history, check_every, graph, time_kernels, out, precision, alpha_form, index32, keep_x=False):
+           history, check_every, graph, time_kernels, out, precision, alpha_form, index32, keep_x=False,
+           diagonal_layout=True):
     _check_vec(b, A.n, "b")
     _check_alpha_form(alpha_form)
     if variant not in VARIANTS:
@@ -326,7 +335,8 @@ def _solve(entry, A: Operator, b: torch.Tensor, x0, *, variant, precond, dinv, t
     o.rr_max = int(rr_max)
     o.check_every = int(check_every)
     o.flags = ((0 if graph else L.FLAG_DIRECT) | (L.FLAG_TIME_KERNELS if time_kernels else 0)
-               | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0) | (L.FLAG_INDEX32 if index32 else 0))
+               | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0) | (L.FLAG_INDEX32 if index32 else 0)
+               | (0 if diagonal_layout else L.FLAG_NO_DIA))
     o.history = hist.data_ptr() if hist is not None else None
     info = L.Info()
     L.check(entry(A.ctx.handle, A.handle, _ptr(b), _ptr(x), _ptr(dinv), ctypes.byref(o), ctypes.byref(info)),

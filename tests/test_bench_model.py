@@ -61,3 +61,25 @@ def test_recorded_traffic_matches_the_sources():
         algo = bench.algorithmic_bytes(N, NNZ, "pbicgstab", False, index_bytes=ib)[0 if k == "k_pa" else 1]
         # at least the algorithmic bytes, and no more than 10 % above them
         assert got is not None and algo < got < 1.10 * algo, (k, got, algo)
+
+
+def test_diagonal_layout_bytes_at_128():
+    """Read through its diagonal layout the 7-point operator costs a 4-byte
+    mask and 7 values (8 bytes each) per row: 60 bytes per row and product,
+    against 4 + 10 nnz/N = 73.5 with the compact CSR stream."""
+    ka, kb, it = bench.algorithmic_bytes(N, NNZ, "pbicgstab", False, dia=7)
+    assert (ka, kb) == (60 * N + 10 * VEC, 60 * N + 12 * VEC) == (293601280, 327155712)
+    assert it == 2 * 60 * N + 22 * VEC
+    assert bench.algorithmic_bytes_cg(N, NNZ, "pipe_cg", True, dia=7) == 60 * N + 18 * VEC
+
+
+def test_matrix_free_27_point_bytes_at_256():
+    """The matrix-free 27-point product reads the (n+1)^3 cell coefficients and
+    gathers dinv (folded Jacobi) besides its input vector."""
+    n = 256
+    Nn = n ** 3
+    mat = 8 * (n + 1) ** 3 + 8 * Nn
+    ka, kb, it = bench.algorithmic_bytes_mf27(n, "pbicgstab_rr")
+    assert (ka, kb) == (mat + 10 * 8 * Nn, mat + 12 * 8 * Nn)
+    assert it == 2 * mat + 22 * 8 * Nn
+    assert bench.algorithmic_bytes_mf27(n, "bicgstab")[2] == 2 * mat + 19 * 8 * Nn

@@ -4,6 +4,8 @@ The copy changes only how a product finds its columns (each stored as the
 offset from the first row of its row's 64-row block), never the arithmetic:
 every solve and product must equal the oracle bit for bit whether the kernels
 read the compact copy or the caller's int32 columns (solve flag ``index32``).
+The solves here read the CSR stream (``diagonal_layout=False``) even where an
+operator also has a diagonal layout, which ``test_gpu_dia.py`` covers.
 The edge matrices put columns exactly at the int16 limits -32768 and +32767
 around their block start, and one past them (then the operator keeps int32).
 """
@@ -101,7 +103,8 @@ def _solve_both(A, variant, precond, tol, maxit, rr=20, precision="fp64"):
     for index32 in (False, True):
         say(f"compact: n={A.n} {variant} precond={precond} precision={precision} index32={index32}")
         x, info = solver.solve(op, dev_t(b), variant=variant, precond=precond, tol=tol, maxit=maxit,
-                               rr_period=rr, history=True, precision=precision, index32=index32)
+                               rr_period=rr, history=True, precision=precision, index32=index32,
+                               diagonal_layout=False)
         out.append((host(x), info))
     return b, out
 
@@ -165,7 +168,7 @@ def test_values_may_change_between_solves():
     torch.cuda.synchronize()
     b = oracle.spmv(A2, inputs.x_true(A.n))
     x, info = solver.solve(op, dev_t(b), variant="pbicgstab_rr", precond="jacobi_folded", tol=1e-10, maxit=400,
-                           rr_period=20)
+                           rr_period=20, diagonal_layout=False)
     x_or, i_or = oracle.solve_folded(A2, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=oracle.jacobi_dinv(A2), tol=1e-10,
                                      maxit=400, rr_period=20)
     assert info.iters == i_or["iters"] and same(host(x), x_or)
@@ -367,5 +370,5 @@ def test_alternating_forms_reuse_cached_graphs():
     for rep in range(3):
         for index32 in (False, True, False):
             x, info = solver.solve(op, dev_t(b), variant="pbicgstab_rr", precond="jacobi_folded", tol=1e-10,
-                                   maxit=400, rr_period=20, index32=index32)
+                                   maxit=400, rr_period=20, index32=index32, diagonal_layout=False)
             assert info.iters == i_or["iters"] and same(host(x), x_or), (rep, index32)

@@ -149,3 +149,33 @@ def test_random_wide_system_bitwise(seed):
         assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"]), (info, i_or)
         assert same(host(x), x_or), (index32, float(np.nanmax(np.abs(host(x) - x_or))))
         assert same(host(info.history), i_or["history"])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_unsorted_columns_follow_stored_order(seed):
+    """Columns need not be ascending within a row: every product sums a row in
+    stored order, as the oracle does, so results equal the oracle's on the same
+    arrays bit for bit (and differ in rounding from the sorted matrix).  The
+    compact column copies keep each entry's column whatever the order."""
+    require_gpu()
+    rng = np.random.default_rng(400 + seed)
+    A = random_system(rng, False)
+    col, val = A.col.copy(), A.val.copy()
+    for i in range(A.n):  # reverse or shuffle each row's entries
+        lo, hi = A.row_ptr[i], A.row_ptr[i + 1]
+        perm = rng.permutation(hi - lo) if seed % 2 else np.arange(hi - lo)[::-1]
+        col[lo:hi], val[lo:hi] = col[lo:hi][perm], val[lo:hi][perm]
+    U = oracle.CSR(A.row_ptr, col, val)
+    say(f"unsorted n={U.n} nnz={U.nnz}")
+    op = csr_op(U)
+    x = inputs.random_vector(U.n, 5)
+    assert same(host(solver.spmv(op, dev_t(x))), oracle.spmv(U, x))
+    b = oracle.spmv(U, inputs.x_true(U.n))
+    kw = dict(tol=1e-10, maxit=500, rr_period=9)
+    xg, info = solver.solve(op, dev_t(b), variant="pbicgstab_rr", precond="jacobi_folded", **kw)
+    d = oracle.jacobi_dinv(U)
+    xo, io = oracle.solve_folded(U, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=d, **kw)
+    assert (info.status, info.iters, info.n_rr) == (io["status"], io["iters"], io["n_rr"])
+    assert same(host(xg), xo)
+    xi, _ = solver.solve(op, dev_t(b), variant="pbicgstab_rr", precond="jacobi_folded", index32=True, **kw)
+    assert same(host(xi), xo)
