@@ -735,6 +735,21 @@ __device__ __forceinline__ void produce2(const Args& a, Body body) {
   }
 }
 
+// The workgroup's rows without a reduction, two neighbouring rows per lane
+// (as produce2); Body(row, valid0, valid1) with row even; needs R >= 2.
+template <class Body>
+__device__ __forceinline__ void each_row2(const Args& a, Body body) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t wbase = ((int64_t)wg_index(a) * 4 + wave) * a.R * 64;
+  for (int j = 0; j < (a.R >> 1); ++j) {
+    const int64_t b0 = wbase + (int64_t)j * 128;
+    if (b0 < a.n) {
+      const int32_t row = (int32_t)(b0 + 2 * lane);
+      body(row, row < a.n, row + 1 < a.n);
+    }
+  }
+}
+
 // The workgroup's rows without a reduction; Body(row, valid) as above.
 template <class Body>
 __device__ __forceinline__ void each_row(const Args& a, Body body) {
@@ -1975,6 +1990,227 @@ __global__ __launch_bounds__(kWG) void k_mp_pb2(Op32 op, Args a) {
     d[2] = r0.x * s.x + (valid1 ? r0.y * s.y : 0.0f);
     d[3] = r0.x * z.x + (valid1 ? r0.y * z.y : 0.0f);
     d[4] = rn.x * rn.x + (valid1 ? rn.y * rn.y : 0.0f);
+  });
+}
+
+// k_pa / k_pb of the unpreconditioned p-BiCGStab (Algorithm 9, also on A M^{-1})
+// with two neighbouring rows per lane, as k_mp_pa2 / k_mp_pb2: 16-byte vector
+// accesses, the same arithmetic per row and the same reduction trees, so the
+// same bits as k_pa / k_pb.  Not used after a residual replacement (k_pa with
+// RR2 then).
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_pa2(Op op, Args a) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  PBCGS_PROLOGUE(st)
+  if (a.first) {
+    double g[1];
+    gather_sums<1>(a, g);
+    fin_setup_alpha(st, g[0]);
+  } else {
+    double g[5];
+    gather_sums<5>(a, g);
+    fin_pipe_b(st, a.hist, g, a.aform);
+  }
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double alpha = st.alpha, beta = st.beta, omega = st.omega;
+  produce2<2>(a, [&](int32_t row, bool valid0, bool valid1, double (&d)[2]) {
+    double t0, t1;
+    op.spmv2(row, valid0, valid1, a.w, t0, t1);
+    if (!valid0) return;
+    const D2 r = *reinterpret_cast<const D2*>(&a.r[row]);
+    const D2 w = *reinterpret_cast<const D2*>(&a.w[row]);
+    const D2 v = *reinterpret_cast<const D2*>(&a.v[row]);
+    const D2 so = *reinterpret_cast<const D2*>(&a.s[row]);
+    const D2 zo = *reinterpret_cast<const D2*>(&a.z[row]);
+    const D2 po = *reinterpret_cast<const D2*>(&a.ph[row]);
+    D2 p, sn, zn, t;
+    p.x = r.x + beta * (po.x - omega * so.x);
+    p.y = r.y + beta * (po.y - omega * so.y);
+    sn.x = w.x + beta * (so.x - omega * zo.x);
+    sn.y = w.y + beta * (so.y - omega * zo.y);
+    zn.x = t0 + beta * (zo.x - omega * v.x);
+    zn.y = t1 + beta * (zo.y - omega * v.y);
+    t.x = t0;
+    t.y = t1;
+    *reinterpret_cast<D2*>(&a.ph[row]) = p;
+    *reinterpret_cast<D2*>(&a.s[row]) = sn;
+    *reinterpret_cast<D2*>(&a.t[row]) = t;
+    *reinterpret_cast<D2*>(&a.z[row]) = zn;
+    const double q0 = r.x - alpha * sn.x, y0 = w.x - alpha * zn.x;
+    const double q1 = r.y - alpha * sn.y, y1 = w.y - alpha * zn.y;
+    d[0] = q0 * y0 + (valid1 ? q1 * y1 : 0.0);
+    d[1] = y0 * y0 + (valid1 ? y1 * y1 : 0.0);
+  });
+}
+
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_pb2(Op op, Args a) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2>(a, g2);
+  const double alpha = st.alpha;
+  const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
+  if (yz) {
+    each_row(a, [&](int32_t row, bool valid) {
+      if (valid) a.x[row] = a.x[row] + alpha * a.ph[row];
+    });
+    return;
+  }
+  if (st.status != DS_RUNNING) return;
+  const double omega = st.omega;
+  produce2<5>(a, [&](int32_t row, bool valid0, bool valid1, double (&d)[5]) {
+    double v0, v1;
+    op.spmv2(row, valid0, valid1, a.z, v0, v1);
+    if (!valid0) return;
+    const D2 r = *reinterpret_cast<const D2*>(&a.r[row]);
+    const D2 s = *reinterpret_cast<const D2*>(&a.s[row]);
+    const D2 w = *reinterpret_cast<const D2*>(&a.w[row]);
+    const D2 z = *reinterpret_cast<const D2*>(&a.z[row]);
+    const D2 t = *reinterpret_cast<const D2*>(&a.t[row]);
+    const D2 p = *reinterpret_cast<const D2*>(&a.ph[row]);
+    const D2 r0 = *reinterpret_cast<const D2*>(&a.r0[row]);
+    const double q0 = r.x - alpha * s.x, y0 = w.x - alpha * z.x;
+    const double q1 = r.y - alpha * s.y, y1 = w.y - alpha * z.y;
+    a.x[row] = a.x[row] + alpha * p.x + omega * q0;
+    if (valid1) a.x[row + 1] = a.x[row + 1] + alpha * p.y + omega * q1;
+    D2 rn, wn, vv;
+    rn.x = q0 - omega * y0;
+    rn.y = q1 - omega * y1;
+    wn.x = y0 - omega * (t.x - alpha * v0);
+    wn.y = y1 - omega * (t.y - alpha * v1);
+    vv.x = v0;
+    vv.y = v1;
+    *reinterpret_cast<D2*>(&a.v[row]) = vv;
+    *reinterpret_cast<D2*>(&a.r[row]) = rn;
+    *reinterpret_cast<D2*>(&a.w[row]) = wn;
+    d[0] = r0.x * rn.x + (valid1 ? r0.y * rn.y : 0.0);
+    d[1] = r0.x * wn.x + (valid1 ? r0.y * wn.y : 0.0);
+    d[2] = r0.x * s.x + (valid1 ? r0.y * s.y : 0.0);
+    d[3] = r0.x * z.x + (valid1 ? r0.y * z.y : 0.0);
+    d[4] = rn.x * rn.x + (valid1 ? rn.y * rn.y : 0.0);
+  });
+}
+
+// The five BiCGStab kernels (Algorithm 7, also on A M^{-1}) with two
+// neighbouring rows per lane, as k_pa2 / k_pb2: the same arithmetic per row
+// and the same reduction trees as k_b1 ... k_b5, so the same bits.
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_b1_2(Op op, Args a) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  PBCGS_PROLOGUE(st)
+  if (a.first) {
+    double g[1];
+    gather_sums<1>(a, g);
+    fin_setup_gamma(st, a.hist, g[0]);
+  }
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  produce2<1>(a, [&](int32_t row, bool valid0, bool valid1, double (&d)[1]) {
+    double s0, s1;
+    op.spmv2(row, valid0, valid1, a.ph, s0, s1);
+    if (!valid0) return;
+    D2 sv;
+    sv.x = s0;
+    sv.y = s1;
+    *reinterpret_cast<D2*>(&a.s[row]) = sv;
+    const D2 r0 = *reinterpret_cast<const D2*>(&a.r0[row]);
+    d[0] = r0.x * s0 + (valid1 ? r0.y * s1 : 0.0);
+  });
+}
+
+__global__ __launch_bounds__(kWG) void k_b2_2(Args a) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  PBCGS_PROLOGUE(st)
+  double g[1];
+  gather_sums<1>(a, g);
+  fin_bicg_alpha(st, g[0]);
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double alpha = st.alpha;
+  each_row2(a, [&](int32_t row, bool valid0, bool) {
+    if (!valid0) return;
+    const D2 r = *reinterpret_cast<const D2*>(&a.r[row]);
+    const D2 sv = *reinterpret_cast<const D2*>(&a.s[row]);
+    D2 q;
+    q.x = r.x - alpha * sv.x;
+    q.y = r.y - alpha * sv.y;
+    *reinterpret_cast<D2*>(&a.q[row]) = q;
+  });
+}
+
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_b3_2(Op op, Args a) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  produce2<2>(a, [&](int32_t row, bool valid0, bool valid1, double (&d)[2]) {
+    double y0, y1;
+    op.spmv2(row, valid0, valid1, a.qh, y0, y1);
+    if (!valid0) return;
+    D2 yv;
+    yv.x = y0;
+    yv.y = y1;
+    *reinterpret_cast<D2*>(&a.y[row]) = yv;
+    const D2 q = *reinterpret_cast<const D2*>(&a.q[row]);
+    d[0] = q.x * y0 + (valid1 ? q.y * y1 : 0.0);
+    d[1] = y0 * y0 + (valid1 ? y1 * y1 : 0.0);
+  });
+}
+
+__global__ __launch_bounds__(kWG) void k_b4_2(Args a) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2>(a, g2);
+  const double alpha = st.alpha;
+  const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
+  if (yz) {
+    each_row(a, [&](int32_t row, bool valid) {
+      if (valid) a.x[row] = a.x[row] + alpha * a.ph[row];
+    });
+    return;
+  }
+  if (st.status != DS_RUNNING) return;
+  const double omega = st.omega;
+  produce2<2>(a, [&](int32_t row, bool valid0, bool valid1, double (&d)[2]) {
+    if (!valid0) return;
+    const D2 q = *reinterpret_cast<const D2*>(&a.q[row]);
+    const D2 p = *reinterpret_cast<const D2*>(&a.ph[row]);
+    const D2 y = *reinterpret_cast<const D2*>(&a.y[row]);
+    const D2 r0 = *reinterpret_cast<const D2*>(&a.r0[row]);
+    a.x[row] = a.x[row] + alpha * p.x + omega * q.x;
+    if (valid1) a.x[row + 1] = a.x[row + 1] + alpha * p.y + omega * q.y;
+    D2 r;
+    r.x = q.x - omega * y.x;
+    r.y = q.y - omega * y.y;
+    *reinterpret_cast<D2*>(&a.r[row]) = r;
+    d[0] = r0.x * r.x + (valid1 ? r0.y * r.y : 0.0);
+    d[1] = r.x * r.x + (valid1 ? r.y * r.y : 0.0);
+  });
+}
+
+__global__ __launch_bounds__(kWG) void k_b5_2(Args a) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2>(a, g2);
+  fin_bicg_beta(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double beta = st.beta, omega = st.omega;
+  each_row2(a, [&](int32_t row, bool valid0, bool) {
+    if (!valid0) return;
+    const D2 r = *reinterpret_cast<const D2*>(&a.r[row]);
+    const D2 po = *reinterpret_cast<const D2*>(&a.p[row]);
+    const D2 sv = *reinterpret_cast<const D2*>(&a.s[row]);
+    D2 p;
+    p.x = r.x + beta * (po.x - omega * sv.x);
+    p.y = r.y + beta * (po.y - omega * sv.y);
+    *reinterpret_cast<D2*>(&a.p[row]) = p;
   });
 }
 

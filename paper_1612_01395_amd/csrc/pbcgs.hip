@@ -502,6 +502,12 @@ struct Driver {
 
   dim3 grid() const { return dim3((unsigned)a.G); }
 
+  // the unpreconditioned binary64 p-BiCGStab kernels likewise (PBCGS_TWO_ROWS64=0 turns it off)
+  bool two_rows64() const {
+    if constexpr (!MP && PC == PC_NONE && HasSpmv2<Op>::value) return a.R >= 2 && env_int("PBCGS_TWO_ROWS64", 1) != 0;
+    return false;
+  }
+
   // the binary32 kernels take two rows per lane when the operator supports it
   // and every wave owns at least two 64-row blocks (PBCGS_TWO_ROWS=0 turns it off)
   bool two_rows() const {
@@ -599,6 +605,16 @@ struct Driver {
       return;
     }
     if (o.variant == PBCGS_BICGSTAB) {
+      if (two_rows64()) {
+        if constexpr (PC == PC_NONE && HasSpmv2<Op>::value) {
+          timed(0, [&] { k_b1_2<Op><<<grid(), kWG, 0, s>>>(op, L(PB_SETUP1, PB_B1, i == 0)); });
+          k_b2_2<<<grid(), kWG, 0, s>>>(L(PB_B1, -1));
+          timed(1, [&] { k_b3_2<Op><<<grid(), kWG, 0, s>>>(op, L(-1, PB_B3)); });
+          k_b4_2<<<grid(), kWG, 0, s>>>(L(PB_B3, PB_B4));
+          k_b5_2<<<grid(), kWG, 0, s>>>(L(PB_B4, -1));
+        }
+        return;
+      }
       timed(0, [&] { k_b1<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_SETUP1, PB_B1, i == 0)); });
       k_b2<PC><<<grid(), kWG, 0, s>>>(L(PB_B1, -1));
       timed(1, [&] { k_b3<Op, PC><<<grid(), kWG, 0, s>>>(op, L(-1, PB_B3)); });
@@ -613,14 +629,27 @@ struct Driver {
       k_rr_s<Op, PC><<<grid(), kWG, 0, s>>>(op, L(-1, -1));
       k_pa<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_A));
     } else {
-      timed(0, [&] { k_pa<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0)); });
+      timed(0, [&] {
+        if (two_rows64()) {
+          if constexpr (PC == PC_NONE && HasSpmv2<Op>::value)
+            k_pa2<Op><<<grid(), kWG, 0, s>>>(op, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
+        } else {
+          k_pa<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
+        }
+      });
     }
     if (rr) {
       k_rr_x<PC><<<grid(), kWG, 0, s>>>(L(PB_A, -1));
       k_rr_r<Op, PC><<<grid(), kWG, 0, s>>>(op, L(-1, -1));
       k_rr_w<Op, PC><<<grid(), kWG, 0, s>>>(op, L(-1, PB_B));
     } else {
-      timed(1, [&] { k_pb<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B)); });
+      timed(1, [&] {
+        if (two_rows64()) {
+          if constexpr (PC == PC_NONE && HasSpmv2<Op>::value) k_pb2<Op><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B));
+        } else {
+          k_pb<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B));
+        }
+      });
     }
   }
 

@@ -172,9 +172,10 @@ def test_values_changed_between_solves():
 
 @pytest.mark.parametrize("name,n", [("c2", 23), ("c1", 45), ("c3", 13), ("c2", 32)])
 @pytest.mark.parametrize("gtarget", [8, 64, 1024])
-def test_precision_form_two_rows_per_lane(name, n, gtarget, monkeypatch):
-    """With two or more 64-row blocks per wave the binary32 kernels take two
-    neighbouring rows per lane; launch shapes that force it, row counts odd
+def test_two_rows_per_lane_bitwise(name, n, gtarget, monkeypatch):
+    """With two or more 64-row blocks per wave the binary32 kernels and the
+    unpreconditioned (here folded) binary64 p-BiCGStab and BiCGStab kernels
+    take two neighbouring rows per lane; launch shapes that force it, row counts odd
     (a last pair with one row) and even, equal the oracle bit for bit."""
     require_gpu()
     w = inputs.workload(name, n=n)
@@ -191,3 +192,11 @@ def test_precision_form_two_rows_per_lane(name, n, gtarget, monkeypatch):
     assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"])
     assert same(host(x), x_or)
     assert same(host(info.history), i_or["history"])
+    for variant in ("pbicgstab_rr", "pbicgstab", "bicgstab"):
+        x, info = solver.solve(op, dev_t(b), variant=variant, precond="jacobi_folded", tol=1e-10, maxit=2000,
+                               rr_period=7, history=True)
+        x_or, i_or = oracle.solve_folded(A, b, algo=ALG[variant], dinv=d, tol=1e-10, maxit=2000, rr_period=7,
+                                         history=True)
+        assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"])
+        assert same(host(x), x_or)
+        assert same(host(info.history), i_or["history"])
