@@ -216,6 +216,13 @@ struct StencilOp {
   __device__ __forceinline__ V spmv(int32_t row, bool valid, const X* __restrict__ x) const {
     return valid ? apply(row, x) : V(0);
   }
+  // Rows row and row + 1 by one lane (the kernels with two rows per lane).
+  template <class X>
+  __device__ __forceinline__ void spmv2(int32_t row, bool valid0, bool valid1, const X* __restrict__ x, V& y0,
+                                        V& y1) const {
+    y0 = valid0 ? apply(row, x) : V(0);
+    y1 = valid1 ? apply(row + 1, x) : V(0);
+  }
   template <class X>
   __device__ __forceinline__ V apply(int32_t row, const X* __restrict__ x) const {
     const int32_t i = row % nx;
@@ -2216,6 +2223,9 @@ __global__ __launch_bounds__(kWG) void k_b5_2(Args a) {
 
 template <class Op> struct HasSpmv2 : std::false_type {};
 template <class V> struct HasSpmv2<DiaOpT<V>> : std::true_type {};
+template <int NPTS, class V> struct HasSpmv2<StencilOp<NPTS, V>> : std::true_type {};
+template <class Op> struct IsDia : std::false_type {};
+template <class V> struct IsDia<DiaOpT<V>> : std::true_type {};
 
 // Replacement iteration, phase B': omega, then only the binary64 x update.
 __global__ __launch_bounds__(kWG) void k_mp_rr_x(Args a) {

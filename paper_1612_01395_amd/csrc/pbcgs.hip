@@ -502,9 +502,14 @@ struct Driver {
 
   dim3 grid() const { return dim3((unsigned)a.G); }
 
-  // the unpreconditioned binary64 p-BiCGStab kernels likewise (PBCGS_TWO_ROWS64=0 turns it off)
+  // the unpreconditioned binary64 BiCGStab kernels likewise, and the p-BiCGStab
+  // ones on the diagonal layout (measured: on a stencil they gain nothing);
+  // PBCGS_TWO_ROWS64=0 turns both off
   bool two_rows64() const {
-    if constexpr (!MP && PC == PC_NONE && HasSpmv2<Op>::value) return a.R >= 2 && env_int("PBCGS_TWO_ROWS64", 1) != 0;
+    if constexpr (!MP && PC == PC_NONE && HasSpmv2<Op>::value) {
+      if (o.variant != PBCGS_BICGSTAB && !IsDia<Op>::value) return false;
+      return a.R >= 2 && env_int("PBCGS_TWO_ROWS64", 1) != 0;
+    }
     return false;
   }
 

@@ -168,35 +168,3 @@ def test_values_changed_between_solves():
     x_or, i_or = oracle.solve_folded(A2, b2, algo=oracle.ALG_PBICGSTAB_RR, dinv=oracle.jacobi_dinv(A2), tol=1e-10,
                                      maxit=400, rr_period=20)
     assert i2.iters == i_or["iters"] and same(host(x2), x_or)
-
-
-@pytest.mark.parametrize("name,n", [("c2", 23), ("c1", 45), ("c3", 13), ("c2", 32)])
-@pytest.mark.parametrize("gtarget", [8, 64, 1024])
-def test_two_rows_per_lane_bitwise(name, n, gtarget, monkeypatch):
-    """With two or more 64-row blocks per wave the binary32 kernels and the
-    unpreconditioned (here folded) binary64 p-BiCGStab and BiCGStab kernels
-    take two neighbouring rows per lane; launch shapes that force it, row counts odd
-    (a last pair with one row) and even, equal the oracle bit for bit."""
-    require_gpu()
-    w = inputs.workload(name, n=n)
-    A = oracle.assemble_workload(w, inputs.kappa_cells(n) if w.npts == 27 else None)
-    b = oracle.spmv(A, inputs.x_true(A.n))
-    op = csr_op(A)
-    assert op.diagonals > 0
-    monkeypatch.setenv("PBCGS_GTARGET", str(gtarget))
-    say(f"dia two rows {name} n={n} rows={A.n} gtarget={gtarget}")
-    d = oracle.jacobi_dinv(A)
-    x, info = solver.solve(op, dev_t(b), variant="pbicgstab_rr", precond="jacobi_folded", precision="fp32_rr64",
-                           tol=1e-10, maxit=2000, rr_period=10, history=True)
-    x_or, i_or = oracle.solve_mp(A, b, dinv=d, tol=1e-10, maxit=2000, rr_period=10, history=True)
-    assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"])
-    assert same(host(x), x_or)
-    assert same(host(info.history), i_or["history"])
-    for variant in ("pbicgstab_rr", "pbicgstab", "bicgstab"):
-        x, info = solver.solve(op, dev_t(b), variant=variant, precond="jacobi_folded", tol=1e-10, maxit=2000,
-                               rr_period=7, history=True)
-        x_or, i_or = oracle.solve_folded(A, b, algo=ALG[variant], dinv=d, tol=1e-10, maxit=2000, rr_period=7,
-                                         history=True)
-        assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"])
-        assert same(host(x), x_or)
-        assert same(host(info.history), i_or["history"])
