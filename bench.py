@@ -685,23 +685,31 @@ def main():
         # region, timed on complete solves: the systems stop at different iterations
         btune = solver.tune_batched(bops, bbs, iters=0, variant="pbicgstab_rr", **kwb)
 
-        def batch_leg(ops_, rhs, variant, passes):
-            solver.solve_batched(ops_, rhs, variant=variant, outs=outs, **kwb)
+        def batch_leg(ops_, rhs, variant, passes, diagonal_layout=True):
+            kwl = dict(kwb, diagonal_layout=diagonal_layout)
+            solver.solve_batched(ops_, rhs, variant=variant, outs=outs, **kwl)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             reps = 2
             for _ in range(reps):
-                _, infs = solver.solve_batched(ops_, rhs, variant=variant, outs=outs, **kwb)
+                _, infs = solver.solve_batched(ops_, rhs, variant=variant, outs=outs, **kwl)
             torch.cuda.synchronize()
             dtb = (time.perf_counter() - t0) / reps
             its = [i.iters for i in infs]
-            # the batch reads int16 block offsets when every operator holds them
-            ibb = 2 if all(op.column_form == "block16" for op in ops_) else 4
-            byts = sum(it_ * (passes * 8 * Nk + 2 * (4 * (Nk + 1) + (8 + ibb) * zk))
-                       for it_, Nk, zk in zip(its, bN, bnnz))
-            return {"ms_per_batch_solve": round(dtb * 1e3, 2), "column_index_bytes": ibb, "iters_total": int(sum(its)),
-                    "iters_max": int(max(its)), "iters_per_s_aggregate": round(sum(its) / dtb, 1),
-                    "gbps_effective": round(byts / dtb / 1e9, 1),
+            # the batch reads every system through its diagonal layout when all have
+            # one, else int16 block offsets when every operator holds them
+            nds = [op.diagonals for op in ops_]
+            if diagonal_layout and all(nds):
+                layout = "diagonal"
+                mats = [4 * Nk + 8 * nd * Nk for Nk, nd in zip(bN, nds)]
+            else:
+                ibb = 2 if all(op.column_form == "block16" for op in ops_) else 4
+                layout = f"csr, int{8 * ibb} columns"
+                mats = [4 * (Nk + 1) + (8 + ibb) * zk for Nk, zk in zip(bN, bnnz)]
+            byts = sum(it_ * (passes * 8 * Nk + 2 * mk) for it_, Nk, mk in zip(its, bN, mats))
+            return {"ms_per_batch_solve": round(dtb * 1e3, 2), "operator_layout": layout,
+                    "iters_total": int(sum(its)), "iters_max": int(max(its)),
+                    "iters_per_s_aggregate": round(sum(its) / dtb, 1), "gbps_effective": round(byts / dtb / 1e9, 1),
                     "all_converged": all(i.status == 0 for i in infs),
                     "max_relres_true": max(i.relres_true for i in infs)}
 
@@ -710,6 +718,7 @@ def main():
                                f"no preconditioner, tol 1e-8, RR every 50; one step = all systems solved",
                    "pbicgstab_rr": batch_leg(bops, bbs, "pbicgstab_rr", 22),
                    "bicgstab": batch_leg(bops, bbs, "bicgstab", 19),
+                   "pbicgstab_rr_csr_stream": batch_leg(bops, bbs, "pbicgstab_rr", 22, diagonal_layout=False),
                    "adjoint_pbicgstab_rr": batch_leg(bts, bws, "pbicgstab_rr", 22),
                    "autotuned_workgroup_cap": btune["best"],
                    "autotuner_ms_per_batch_solve": {str(k): round(v, 1) for k, v in btune["tried"].items()}}

@@ -262,7 +262,17 @@ struct StencilOp {
 // values of A M^{-1}, or their binary32 rounding); the mask is structure and
 // belongs to the operator.
 constexpr int kMaxDia = 32;
-template <class V>
+// OFFP: the offsets are read through a pointer (the batch's per-system table)
+// instead of being held in the operator (a kernel argument, whose array the
+// loops index directly).  NT: the values are loaded with the nontemporal
+// hint, which keeps them from displacing the vectors in the caches (and in the
+// memory-side cache); without it they compete like any other data, which is
+// the better choice when the vectors and the layout fit there together.
+template <class T>
+__device__ __forceinline__ T load_nt(const T* p, std::true_type) { return __builtin_nontemporal_load(p); }
+template <class T>
+__device__ __forceinline__ T load_nt(const T* p, std::false_type) { return *p; }
+template <class V, bool OFFP = false, bool NT = true>
 struct DiaOpT {
   using Val = V;
   const uint32_t* __restrict__ mask;
@@ -271,7 +281,7 @@ struct DiaOpT {
   int32_t nd;
   int32_t ld;     // stride between diagonals (rows rounded up to a multiple of 64)
   int32_t pad_ = 0;
-  int32_t off[kMaxDia];
+  std::conditional_t<OFFP, const int32_t*, int32_t[kMaxDia]> off;
 
   template <class X>
   __device__ __forceinline__ V spmv(int32_t row, bool valid, const X* __restrict__ x) const {
@@ -282,7 +292,7 @@ struct DiaOpT {
     for (int d = 0; d < nd; ++d) {
       const bool present = (m >> d) & 1u;
       const int32_t c = present ? rc + off[d] : rc;  // a present diagonal's column lies in [0, n)
-      const V v = __builtin_nontemporal_load(&va[(int64_t)d * ld + rc]);
+      const V v = load_nt(&va[(int64_t)d * ld + rc], std::integral_constant<bool, NT>());
       const V t = acc + v * V(x[c]);
       acc = present ? t : acc;
     }
@@ -307,7 +317,7 @@ struct DiaOpT {
 #pragma unroll 4
     for (int d = 0; d < nd; ++d) {
       const bool p0 = (m0 >> d) & 1u, p1 = (m1 >> d) & 1u;
-      const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2*>(&va[(int64_t)d * ld + rv]));
+      const V2 v = load_nt(reinterpret_cast<const V2*>(&va[(int64_t)d * ld + rv]), std::integral_constant<bool, NT>());
       X x0, x1;
       // with an even offset and row + 1's entry present, x[row + off], x[row + off + 1]
       // both lie in [0, n) (row + 1 + off is odd, so at least 1) and form an
@@ -330,6 +340,8 @@ struct DiaOpT {
 };
 using DiaOp = DiaOpT<double>;
 using DiaOpF = DiaOpT<float>;
+using DiaOpB = DiaOpT<double, true>;  // batched: offsets in the system table
+using DiaOpC = DiaOpT<double, false, false>;  // ordinary value loads
 
 // Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane l receives the
 // value of lane l - 1 (shr) or l + 1 (shl); the lane without a source (0 or 63)
@@ -740,6 +752,24 @@ __device__ __forceinline__ void produce2(const Args& a, Body body) {
     for (int k = 0; k < ND; ++k)
       a.pout[k * a.pstride + wg_index(a)] = double((wtot[k][0] + wtot[k][1]) + (wtot[k][2] + wtot[k][3]));
   }
+}
+
+// x[row] = (x[row] + u0) + v0 and x[row + 1] = (x[row + 1] + u1) + v1 (row
+// even) on the caller's x: one 16-byte load and store when x is 16-byte
+// aligned, so each cache line is written whole by one instruction; else row
+// by row.  The same arithmetic either way.
+__device__ __forceinline__ void update_x2(double* __restrict__ x, int32_t row, bool valid1, double u0, double u1,
+                                          double v0, double v1) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  if (valid1 && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+    D2 xx = *reinterpret_cast<const D2*>(&x[row]);
+    xx.x = xx.x + u0 + v0;
+    xx.y = xx.y + u1 + v1;
+    *reinterpret_cast<D2*>(&x[row]) = xx;
+    return;
+  }
+  x[row] = x[row] + u0 + v0;
+  if (valid1) x[row + 1] = x[row + 1] + u1 + v1;
 }
 
 // The workgroup's rows without a reduction, two neighbouring rows per lane
@@ -1987,8 +2017,7 @@ __global__ __launch_bounds__(kWG) void k_mp_pb2(Op32 op, Args a) {
     wnew.y = y1 - wn * (t.y - af * v1);
     vv.x = v0;
     vv.y = v1;
-    a.x[row] = a.x[row] + alpha * double(p.x) + omega * double(q0);
-    if (valid1) a.x[row + 1] = a.x[row + 1] + alpha * double(p.y) + omega * double(q1);
+    update_x2(a.x, row, valid1, alpha * double(p.x), alpha * double(p.y), omega * double(q0), omega * double(q1));
     *reinterpret_cast<float2*>(&a.vf[row]) = vv;
     *reinterpret_cast<float2*>(&a.rf[row]) = rn;
     *reinterpret_cast<float2*>(&a.wf[row]) = wnew;
@@ -2006,7 +2035,7 @@ __global__ __launch_bounds__(kWG) void k_mp_pb2(Op32 op, Args a) {
 // same bits as k_pa / k_pb.  Not used after a residual replacement (k_pa with
 // RR2 then).
 template <class Op>
-__global__ __launch_bounds__(kWG) void k_pa2(Op op, Args a) {
+__device__ __forceinline__ void d_pa2(Op op, Args a) {
   typedef double D2 __attribute__((ext_vector_type(2)));
   PBCGS_PROLOGUE(st)
   if (a.first) {
@@ -2052,7 +2081,7 @@ __global__ __launch_bounds__(kWG) void k_pa2(Op op, Args a) {
 }
 
 template <class Op>
-__global__ __launch_bounds__(kWG) void k_pb2(Op op, Args a) {
+__device__ __forceinline__ void d_pb2(Op op, Args a) {
   typedef double D2 __attribute__((ext_vector_type(2)));
   PBCGS_PROLOGUE(st)
   double g2[2];
@@ -2081,8 +2110,7 @@ __global__ __launch_bounds__(kWG) void k_pb2(Op op, Args a) {
     const D2 r0 = *reinterpret_cast<const D2*>(&a.r0[row]);
     const double q0 = r.x - alpha * s.x, y0 = w.x - alpha * z.x;
     const double q1 = r.y - alpha * s.y, y1 = w.y - alpha * z.y;
-    a.x[row] = a.x[row] + alpha * p.x + omega * q0;
-    if (valid1) a.x[row + 1] = a.x[row + 1] + alpha * p.y + omega * q1;
+    update_x2(a.x, row, valid1, alpha * p.x, alpha * p.y, omega * q0, omega * q1);
     D2 rn, wn, vv;
     rn.x = q0 - omega * y0;
     rn.y = q1 - omega * y1;
@@ -2105,7 +2133,7 @@ __global__ __launch_bounds__(kWG) void k_pb2(Op op, Args a) {
 // neighbouring rows per lane, as k_pa2 / k_pb2: the same arithmetic per row
 // and the same reduction trees as k_b1 ... k_b5, so the same bits.
 template <class Op>
-__global__ __launch_bounds__(kWG) void k_b1_2(Op op, Args a) {
+__device__ __forceinline__ void d_b1_2(Op op, Args a) {
   typedef double D2 __attribute__((ext_vector_type(2)));
   PBCGS_PROLOGUE(st)
   if (a.first) {
@@ -2128,7 +2156,7 @@ __global__ __launch_bounds__(kWG) void k_b1_2(Op op, Args a) {
   });
 }
 
-__global__ __launch_bounds__(kWG) void k_b2_2(Args a) {
+__device__ __forceinline__ void d_b2_2(Args a) {
   typedef double D2 __attribute__((ext_vector_type(2)));
   PBCGS_PROLOGUE(st)
   double g[1];
@@ -2149,7 +2177,7 @@ __global__ __launch_bounds__(kWG) void k_b2_2(Args a) {
 }
 
 template <class Op>
-__global__ __launch_bounds__(kWG) void k_b3_2(Op op, Args a) {
+__device__ __forceinline__ void d_b3_2(Op op, Args a) {
   typedef double D2 __attribute__((ext_vector_type(2)));
   PBCGS_PROLOGUE(st)
   publish(a, st);
@@ -2167,7 +2195,7 @@ __global__ __launch_bounds__(kWG) void k_b3_2(Op op, Args a) {
   });
 }
 
-__global__ __launch_bounds__(kWG) void k_b4_2(Args a) {
+__device__ __forceinline__ void d_b4_2(Args a) {
   typedef double D2 __attribute__((ext_vector_type(2)));
   PBCGS_PROLOGUE(st)
   double g2[2];
@@ -2189,8 +2217,7 @@ __global__ __launch_bounds__(kWG) void k_b4_2(Args a) {
     const D2 p = *reinterpret_cast<const D2*>(&a.ph[row]);
     const D2 y = *reinterpret_cast<const D2*>(&a.y[row]);
     const D2 r0 = *reinterpret_cast<const D2*>(&a.r0[row]);
-    a.x[row] = a.x[row] + alpha * p.x + omega * q.x;
-    if (valid1) a.x[row + 1] = a.x[row + 1] + alpha * p.y + omega * q.y;
+    update_x2(a.x, row, valid1, alpha * p.x, alpha * p.y, omega * q.x, omega * q.y);
     D2 r;
     r.x = q.x - omega * y.x;
     r.y = q.y - omega * y.y;
@@ -2200,7 +2227,7 @@ __global__ __launch_bounds__(kWG) void k_b4_2(Args a) {
   });
 }
 
-__global__ __launch_bounds__(kWG) void k_b5_2(Args a) {
+__device__ __forceinline__ void d_b5_2(Args a) {
   typedef double D2 __attribute__((ext_vector_type(2)));
   PBCGS_PROLOGUE(st)
   double g2[2];
@@ -2221,11 +2248,23 @@ __global__ __launch_bounds__(kWG) void k_b5_2(Args a) {
   });
 }
 
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_pa2(Op op, Args a) { d_pa2<Op>(op, a); }
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_pb2(Op op, Args a) { d_pb2<Op>(op, a); }
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_b1_2(Op op, Args a) { d_b1_2<Op>(op, a); }
+__global__ __launch_bounds__(kWG) void k_b2_2(Args a) { d_b2_2(a); }
+template <class Op>
+__global__ __launch_bounds__(kWG) void k_b3_2(Op op, Args a) { d_b3_2<Op>(op, a); }
+__global__ __launch_bounds__(kWG) void k_b4_2(Args a) { d_b4_2(a); }
+__global__ __launch_bounds__(kWG) void k_b5_2(Args a) { d_b5_2(a); }
+
 template <class Op> struct HasSpmv2 : std::false_type {};
-template <class V> struct HasSpmv2<DiaOpT<V>> : std::true_type {};
+template <class V, bool P, bool N> struct HasSpmv2<DiaOpT<V, P, N>> : std::true_type {};
 template <int NPTS, class V> struct HasSpmv2<StencilOp<NPTS, V>> : std::true_type {};
 template <class Op> struct IsDia : std::false_type {};
-template <class V> struct IsDia<DiaOpT<V>> : std::true_type {};
+template <class V, bool P, bool N> struct IsDia<DiaOpT<V, P, N>> : std::true_type {};
 
 // Replacement iteration, phase B': omega, then only the binary64 x update.
 __global__ __launch_bounds__(kWG) void k_mp_rr_x(Args a) {
@@ -2756,15 +2795,31 @@ struct SysDesc {
   DevState* st;      // 4 state slots: 0, 1 the iteration ring, 2, 3 utility sums
   int64_t np;
   int32_t n, G, R, wg0;  // rows, workgroups, blocks per wave, first workgroup of the grid
+  // diagonal layout (read by DiaOpB launches only): the operator's row masks,
+  // this solve's copy of the values (nd slots of np), the offsets
+  const uint32_t* dmask;
+  double* dva;
+  int32_t nd, pad_;
+  int32_t doff[kMaxDia];
 };
 
 // Per-system arguments from the launch template: rows, shape, state slots
 // (template field par), partial-sum rows (offset to the system's workgroups)
 // and the vector layout of p-BiCGStab (PIPE) or BiCGStab.
 template <bool PIPE, class Op>
-__device__ __forceinline__ void bind_sys(const SysDesc& d, Args& a, Op& op) {
-  if constexpr (std::is_same<Op, CsrOp16>::value) op = Op{d.rp, d.c16, d.va, d.n};
-  else op = Op{d.rp, d.ci, d.va, d.n};
+__device__ __forceinline__ void bind_sys(const SysDesc& d, const SysDesc* dp, Args& a, Op& op) {
+  if constexpr (std::is_same<Op, CsrOp16>::value) {
+    op = Op{d.rp, d.c16, d.va, d.n};
+  } else if constexpr (std::is_same<Op, DiaOpB>::value) {
+    op.off = dp->doff;  // read in place: the loops index the offsets
+    op.mask = d.dmask;
+    op.va = d.dva;
+    op.n = d.n;
+    op.nd = d.nd;
+    op.ld = (int32_t)d.np;
+  } else {
+    op = Op{d.rp, d.ci, d.va, d.n};
+  }
   a.n = d.n;
   a.G = d.G;
   a.R = d.R;
@@ -2789,12 +2844,14 @@ __device__ __forceinline__ void bind_sys(const SysDesc& d, Args& a, Op& op) {
   }
 }
 
-// Op: CsrOp (int32 columns) or CsrOp16 (every system's compact columns)
+// Op: CsrOp (int32 columns), CsrOp16 (every system's compact columns) or
+// DiaOpB (every system's diagonal layout)
 #define PBCGS_BIND_WG(PIPE)                        \
-  const SysDesc d_ = sys[map[blockIdx.x]];         \
+  const SysDesc* dp_ = sys + map[blockIdx.x];      \
+  const SysDesc d_ = *dp_;                         \
   a.wg = (int32_t)blockIdx.x - d_.wg0;             \
   Op op;                                           \
-  bind_sys<PIPE>(d_, a, op);
+  bind_sys<PIPE>(d_, dp_, a, op);
 
 template <class Op, bool PIPE>
 __global__ __launch_bounds__(kWG) void kb_setup_r0(const SysDesc* sys, const int32_t* map, Args a) {
@@ -2852,6 +2909,55 @@ template <class Op>
 __global__ __launch_bounds__(kWG) void kb_b5(const SysDesc* sys, const int32_t* map, Args a) {
   PBCGS_BIND_WG(false) (void)op; d_b5<PC_NONE>(a);
 }
+// Two rows per lane (every system's waves own at least two blocks): the
+// diagonal-layout batch, as k_pa2 / k_pb2 and k_b1_2 ... k_b5_2.
+template <class Op>
+__global__ __launch_bounds__(kWG) void kb_pa2(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(true) d_pa2<Op>(op, a);
+}
+template <class Op>
+__global__ __launch_bounds__(kWG) void kb_pb2(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(true) d_pb2<Op>(op, a);
+}
+template <class Op>
+__global__ __launch_bounds__(kWG) void kb_b1_2(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(false) d_b1_2<Op>(op, a);
+}
+template <class Op>
+__global__ __launch_bounds__(kWG) void kb_b2_2(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(false) (void)op; d_b2_2(a);
+}
+template <class Op>
+__global__ __launch_bounds__(kWG) void kb_b3_2(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(false) d_b3_2<Op>(op, a);
+}
+template <class Op>
+__global__ __launch_bounds__(kWG) void kb_b4_2(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(false) (void)op; d_b4_2(a);
+}
+template <class Op>
+__global__ __launch_bounds__(kWG) void kb_b5_2(const SysDesc* sys, const int32_t* map, Args a) {
+  PBCGS_BIND_WG(false) (void)op; d_b5_2(a);
+}
+// Every system's diagonal-layout values from its CSR values (as k_dia_fill),
+// over the batch's workgroups: workgroup g of a system fills the rows of its
+// 256 R row range.
+__global__ __launch_bounds__(kWG) void kb_dia_fill(const SysDesc* sys, const int32_t* map) {
+  const SysDesc& d = sys[map[blockIdx.x]];
+  const int64_t base = ((int64_t)blockIdx.x - d.wg0) * kWG * d.R;
+  for (int j = 0; j < d.R; ++j) {
+    const int64_t r = base + (int64_t)j * kWG + threadIdx.x;
+    if (r >= d.n) return;
+    const int32_t row = (int32_t)r;
+    const uint32_t m = d.dmask[row];
+    int32_t k = d.rp[row];
+    for (int q = 0; q < d.nd; ++q) {
+      double v = 0.0;
+      if ((m >> q) & 1u) v = d.va[k++];
+      d.dva[(int64_t)q * d.np + row] = v;
+    }
+  }
+}
 template <class Op>
 __global__ __launch_bounds__(kWG) void kb_true_res(const SysDesc* sys, const int32_t* map, Args a) {
   PBCGS_BIND_WG(true) d_true_res<Op>(op, a);
@@ -2862,7 +2968,7 @@ __global__ __launch_bounds__(kWG) void kb_finish(const SysDesc* sys, Args a) {
   const SysDesc d = sys[blockIdx.x];
   a.wg = 0;
   CsrOp op;
-  bind_sys<PIPE>(d, a, op);
+  bind_sys<PIPE>(d, sys + blockIdx.x, a, op);
   d_finish<MODE>(a);
 }
 // Slot `slot` of every system's state: running, no scalars yet.

@@ -111,6 +111,8 @@ struct pbcgs_ctx_s {
   size_t bmap_cap = 0;
   double* bws = nullptr;
   size_t bws_cap = 0;
+  double* bdia = nullptr;    // every system's diagonal-layout values for the current batch
+  size_t bdia_cap = 0;
   DevState* bst = nullptr;
   size_t bst_cap = 0;
   double* bpart = nullptr;
@@ -1056,9 +1058,13 @@ int grow(pbcgs_ctx_t ctx, T*& p, size_t& cap, size_t count, const char* what) {
 
 // Batched solve of independent CSR systems without a preconditioner: the
 // schedule of Driver, every launch covering all systems (see SysDesc).
-// Op: CsrOp (int32 columns) or CsrOp16 (every system holds compact columns).
+// Op: CsrOp (int32 columns), CsrOp16 (every system holds compact columns) or
+// DiaOpB (every system has a diagonal layout: its values are laid out at the
+// start of the solve, and the kernels that have a two-rows-per-lane form use
+// it, every system's waves owning at least two blocks).
 template <class Op>
 struct BatchDriver {
+  static constexpr bool kTwo = IsDia<Op>::value;
   pbcgs_ctx_t ctx;
   const pbcgs_opts& o;
   int32_t nsys, totalG;
@@ -1100,17 +1106,27 @@ struct BatchDriver {
     const SysDesc* S = ctx->bsys;
     const int32_t* M = ctx->bmap;
     if (!pipe) {
-      kb_b1<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_SETUP1, PB_B1, i == 0));
-      kb_b2<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B1, -1));
-      kb_b3<Op><<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_B3));
-      kb_b4<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B3, PB_B4));
-      kb_b5<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B4, -1));
+      if constexpr (kTwo) {
+        kb_b1_2<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_SETUP1, PB_B1, i == 0));
+        kb_b2_2<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B1, -1));
+        kb_b3_2<Op><<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_B3));
+        kb_b4_2<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B3, PB_B4));
+        kb_b5_2<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B4, -1));
+      } else {
+        kb_b1<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_SETUP1, PB_B1, i == 0));
+        kb_b2<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B1, -1));
+        kb_b3<Op><<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_B3));
+        kb_b4<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B3, PB_B4));
+        kb_b5<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B4, -1));
+      }
       return;
     }
     if (rr_due(o, i - 1)) {
       kb_rr_p<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_B, -1));
       kb_rr_s<Op><<<totalG, kWG, 0, s>>>(S, M, L(-1, -1));
       kb_pa<Op, true><<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_A));
+    } else if constexpr (kTwo) {
+      kb_pa2<Op><<<totalG, kWG, 0, s>>>(S, M, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
     } else {
       kb_pa<Op, false><<<totalG, kWG, 0, s>>>(S, M, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
     }
@@ -1118,6 +1134,8 @@ struct BatchDriver {
       kb_rr_x<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_A, -1));
       kb_rr_r<Op><<<totalG, kWG, 0, s>>>(S, M, L(-1, -1));
       kb_rr_w<Op><<<totalG, kWG, 0, s>>>(S, M, L(-1, PB_B));
+    } else if constexpr (kTwo) {
+      kb_pb2<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_A, PB_B));
     } else {
       kb_pb<Op><<<totalG, kWG, 0, s>>>(S, M, L(PB_A, PB_B));
     }
@@ -1143,7 +1161,7 @@ struct BatchDriver {
     char buf[160];
     std::snprintf(buf, sizeof buf, "%p|%p|%p|%d|%d|%d|%d|%lld|%d|%d|", (void*)ctx->bsys, (void*)ctx->bmap,
                   (void*)ctx->bpart, nsys, totalG, o.variant, m, (long long)(q & 1), i0 == 0 ? 1 : 0,
-                  std::is_same<Op, CsrOp16>::value ? 2 : 4);
+                  kTwo ? 1 : std::is_same<Op, CsrOp16>::value ? 2 : 4);
     k += buf;
     for (int j = 0; j < m; ++j) {
       const int64_t i = i0 + j;
@@ -1191,6 +1209,7 @@ struct BatchDriver {
     const int check = o.check_every > 0 ? o.check_every : 8;
     const size_t nst = (size_t)nsys * 4;
     HIP_TRY(ctx, hipEventRecord(ctx->ev_start, s));
+    if constexpr (kTwo) kb_dia_fill<<<totalG, kWG, 0, s>>>(ctx->bsys, ctx->bmap);
     kb_init_state<<<(nsys + 63) / 64, 64, 0, s>>>(ctx->bsys, nsys, 0, o.tol);
     q = 0;
     setup();
@@ -1349,6 +1368,7 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
   if (ctx->bsys) (void)hipFree(ctx->bsys);
   if (ctx->bmap) (void)hipFree(ctx->bmap);
   if (ctx->bws) (void)hipFree(ctx->bws);
+  if (ctx->bdia) (void)hipFree(ctx->bdia);
   if (ctx->bst) (void)hipFree(ctx->bst);
   if (ctx->bpart) (void)hipFree(ctx->bpart);
   if (ctx->bhst) (void)hipHostFree(ctx->bhst);
@@ -1548,6 +1568,28 @@ int dia_operator(pbcgs_ctx_t ctx, pbcgs_op_t A, int pc_fold, const double* dv, d
   for (int k = 0; k < A->ndia; ++k) d.off[k] = A->dia_off[k];
   *out = d;
   return PBCGS_SUCCESS;
+}
+
+// Whether a binary64 solve reads the diagonal layout's values with ordinary
+// loads (true) instead of the nontemporal hint.  Measured at 128^3 (7
+// diagonals, about 264 MiB of vectors and layout per iteration), ordinary
+// loads make BiCGStab 10 % and p-BiCGStab 2 % faster per iteration, as the
+// layout then shares the 256 MiB memory-side cache with the vectors; with a
+// working set several times larger (the 512-system batch) the hint is
+// faster.  The estimate counts nine vectors (the most any solver keeps live
+// per iteration) besides the layout; PBCGS_DIA_CACHED=0 or 1 overrides.
+static bool dia_cached(const pbcgs_op_s* A) {
+  const double n = (double)padded(A->n);
+  const double ws = 9.0 * 8.0 * n + (8.0 * A->ndia + 4.0) * n;
+  return env_int("PBCGS_DIA_CACHED", ws <= 320.0 * 1024 * 1024 ? 1 : 0) != 0;
+}
+
+// The same operator read with ordinary value loads (the layouts are identical).
+static DiaOpC cached_loads(const DiaOp& d) {
+  static_assert(sizeof(DiaOpC) == sizeof(DiaOp), "DiaOpT layouts");
+  DiaOpC c;
+  std::memcpy(&c, &d, sizeof c);
+  return c;
 }
 }  // extern "C++"
 
@@ -1927,6 +1969,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
           DiaOp dop;
           const int rcd = dia_operator<double>(ctx, A, pc, dv, ds, &dop);
           if (rcd != PBCGS_SUCCESS) return rcd;
+          if (dia_cached(A)) return run_folded(cached_loads(dop));
           return run_folded(dop);
         }
       }
@@ -1938,6 +1981,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     DiaOp dop;
     rc = dia_operator<double>(ctx, A, PC_NONE, nullptr, 0.0, &dop);
     if (rc != PBCGS_SUCCESS) return rc;
+    if (pc == PC_NONE && dia_cached(A)) return Driver<DiaOpC, PC_NONE>(ctx, cached_loads(dop), a, o).run(info);
     if (pc == PC_NONE) return Driver<DiaOp, PC_NONE>(ctx, dop, a, o).run(info);
     if (pc == PC_VEC) return Driver<DiaOp, PC_VEC>(ctx, dop, a, o).run(info);
     return Driver<DiaOp, PC_SCALAR>(ctx, dop, a, o).run(info);
@@ -2114,16 +2158,18 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
   if (gcap < 1 || gcap > kMaxG) gcap = 64;
   std::vector<SysDesc> desc((size_t)nsys);
   bool compact = compact_ok(o);  // every system holds compact columns
+  bool dia = dia_ok(o);          // every system has a diagonal layout
+  for (int32_t k = 0; k < nsys && dia; ++k) dia = A[k] && A[k]->kind == OP_CSR && A[k]->ndia > 0;
   int64_t totalG = 0;
-  size_t wsneed = 0;
+  size_t wsneed = 0, dianeed = 0;
   for (int32_t k = 0; k < nsys; ++k) {
     const pbcgs_op_t op = A[k];
     if (!op || op->ctx != ctx) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad operator " + std::to_string(k));
     if (op->kind != OP_CSR) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves take CSR operators");
     if (!b[k] || !x[k] || (const void*)b[k] == (const void*)x[k])
       return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad b or x of system " + std::to_string(k));
-    int32_t R = 1;
-    int64_t G = ((int64_t)op->n + 255) / 256;
+    int32_t R = dia ? 2 : 1;  // the two-rows-per-lane kernels need two blocks per wave
+    int64_t G = ((int64_t)op->n + 256 * (int64_t)R - 1) / (256 * (int64_t)R);
     while (G > gcap && R < kMaxR) {
       R *= 2;
       G = ((int64_t)op->n + 256 * (int64_t)R - 1) / (256 * (int64_t)R);
@@ -2135,6 +2181,12 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
     compact = compact && op->c16 != nullptr;
     d.np = (int64_t)padded(op->n);
     d.n = op->n; d.G = (int32_t)G; d.R = R;
+    if (dia) {
+      d.dmask = op->dmask;
+      d.nd = op->ndia;
+      for (int j = 0; j < op->ndia; ++j) d.doff[j] = op->dia_off[j];
+      dianeed += (size_t)op->ndia * (size_t)d.np;
+    }
     totalG += G;
     wsneed += (size_t)8 * (size_t)d.np;
   }
@@ -2163,6 +2215,7 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
   if (rc == PBCGS_SUCCESS) rc = grow(ctx, ctx->bws, ctx->bws_cap, wsneed, "batch vectors");
   if (rc == PBCGS_SUCCESS) rc = grow(ctx, ctx->bst, ctx->bst_cap, nst, "batch states");
   if (rc == PBCGS_SUCCESS) rc = grow(ctx, ctx->bpart, ctx->bpart_cap, (size_t)PB_COUNT * kMaxD * totalG, "partials");
+  if (rc == PBCGS_SUCCESS && dia) rc = grow(ctx, ctx->bdia, ctx->bdia_cap, dianeed, "diagonal-layout values");
   if (rc != PBCGS_SUCCESS) return rc;
   if (ctx->bhst_cap < nst) {
     if (ctx->bhst) { (void)hipStreamSynchronize(ctx->stream); (void)hipHostFree(ctx->bhst); ctx->bhst = nullptr; }
@@ -2174,17 +2227,22 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
     ctx->bhst_cap = nst;
   }
   std::vector<int32_t> map((size_t)totalG);
-  size_t off = 0;
+  size_t off = 0, doff = 0;
   for (int32_t k = 0; k < nsys; ++k) {
     SysDesc& d = desc[(size_t)k];
     d.ws = ctx->bws + off;
     off += (size_t)8 * (size_t)d.np;
+    if (dia) {
+      d.dva = ctx->bdia + doff;
+      doff += (size_t)d.nd * (size_t)d.np;
+    }
     d.st = ctx->bst + (size_t)k * 4;
     for (int32_t g = 0; g < d.G; ++g) map[(size_t)d.wg0 + g] = k;
   }
   HIP_TRY(ctx, hipMemcpyAsync(ctx->bsys, desc.data(), desc.size() * sizeof(SysDesc), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->bmap, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the host tables may go away after this
+  if (dia) return BatchDriver<DiaOpB>(ctx, o, nsys, (int32_t)totalG).run(infos);
   if (compact) return BatchDriver<CsrOp16>(ctx, o, nsys, (int32_t)totalG).run(infos);
   return BatchDriver<CsrOp>(ctx, o, nsys, (int32_t)totalG).run(infos);
 }

@@ -350,13 +350,15 @@ def _solve(entry, A: Operator, b: torch.Tensor, x0, *, variant, precond, dinv, t
 
 def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str = "pbicgstab_rr", tol: float = 1e-8,
                   maxit: int = 2000, rr_period: int = 50, rr_max: int = -1, check_every: int = 0, graph: bool = True,
-                  outs: list | None = None, alpha_form: int = 3, index32: bool = False):
+                  outs: list | None = None, alpha_form: int = 3, index32: bool = False, diagonal_layout: bool = True):
     """Solve the independent systems ops[k] x_k = bs[k] in one batched call
     (CSR operators of one context, no preconditioner, binary64).  Returns
     (xs, infos); each system's result equals its own :func:`solve` bit for bit.
-    The batch reads the int16 block offsets when every operator holds them
-    (``column_form == "block16"``) and ``index32`` is false, else the int32
-    columns."""
+    The batch reads every system through its diagonal layout when every
+    operator has one (``diagonals > 0``) and neither ``index32`` nor
+    ``diagonal_layout=False`` asks for the CSR arrays; else the int16 block
+    offsets when every operator holds them (``column_form == "block16"``) and
+    ``index32`` is false; else the int32 columns."""
     _check_alpha_form(alpha_form)
     nsys = len(ops)
     if nsys == 0 or len(bs) != nsys:
@@ -390,7 +392,7 @@ def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str 
     o.rr_max = int(rr_max)
     o.check_every = int(check_every)
     o.flags = ((0 if graph else L.FLAG_DIRECT) | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0)
-               | (L.FLAG_INDEX32 if index32 else 0))
+               | (L.FLAG_INDEX32 if index32 else 0) | (0 if diagonal_layout else L.FLAG_NO_DIA))
     o.history = None
     VP = ctypes.c_void_p * nsys
     hs = VP(*[A.handle.value for A in ops])

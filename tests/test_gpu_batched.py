@@ -5,6 +5,7 @@ different iterations; a stopped system must leave the later launches alone."""
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from paper_1612_01395_amd import inputs, solver
@@ -128,6 +129,94 @@ def test_batched_mixed_column_forms():
     bs = [oracle.spmv(A, inputs.batch_x_true(k, A.n)) for k, A in enumerate(sysl)]
     kw = dict(tol=1e-10, maxit=500, rr_period=17)
     say("batched mixed column forms")
+    xs, infos = solver.solve_batched(ops, [dev_t(b) for b in bs], variant="pbicgstab_rr", **kw)
+    for k, (A, b) in enumerate(zip(sysl, bs)):
+        x_or, i_or = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, **kw)
+        assert (infos[k].status, infos[k].iters) == (i_or["status"], i_or["iters"]), k
+        assert same(host(xs[k]), x_or), k
+
+
+def dia_batch():
+    """Systems that all have a diagonal layout (2-D 5-point from a single node
+    to 257^2, 3-D 7-point up to 34^3), so the batch reads every one of them
+    through it, two rows per lane."""
+    rng = np.random.default_rng(11)
+    sys = [oracle.assemble(2, n, 5, tuple(rng.uniform(0.0, 200.0, 2))) for n in (1, 5, 16, 33, 64, 100, 150, 257)]
+    sys += [oracle.assemble(3, n, 7, tuple(rng.uniform(0.0, 100.0, 3))) for n in (12, 24, 34)]
+    return sys
+
+
+DIA_BATCH = dia_batch()
+
+
+@pytest.mark.parametrize("variant", list(ALG))
+def test_batched_diagonal_layout(variant):
+    require_gpu()
+    ops = [csr_op(A) for A in DIA_BATCH]
+    assert all(op.diagonals > 0 for op in ops)
+    bs = [oracle.spmv(A, inputs.batch_x_true(k, A.n)) for k, A in enumerate(DIA_BATCH)]
+    kw = dict(tol=1e-10, maxit=3000, rr_period=17)
+    ref = [oracle.solve(A, b, algo=ALG[variant], **kw) for A, b in zip(DIA_BATCH, bs)]
+    for layout in (True, False):
+        say(f"batched {variant} diagonal_layout={layout}: N = {[A.n for A in DIA_BATCH]}")
+        xs, infos = solver.solve_batched(ops, [dev_t(b) for b in bs], variant=variant, diagonal_layout=layout, **kw)
+        for k, (x_or, i_or) in enumerate(ref):
+            info = infos[k]
+            assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"]), (layout, k)
+            assert same(host(xs[k]), x_or), (layout, k)
+            assert same([info.relres_rec, info.relres_true], [i_or["relres_rec"], i_or["relres_true"]]), (layout, k)
+
+
+@pytest.mark.parametrize("variant", ["bicgstab", "pbicgstab_rr"])
+def test_batched_diagonal_layout_shapes_and_x0(variant, monkeypatch):
+    """Per-system workgroup caps from 1 (many blocks per wave) to 64, graph
+    replay and direct launches, a non-zero x_0 and a fixed iteration count,
+    values changed in place between two batches (the layout's values are laid
+    out for each batch)."""
+    require_gpu()
+    sub = DIA_BATCH[1:8]
+    ops = [csr_op(A) for A in sub]
+    bs = [oracle.spmv(A, inputs.batch_x_true(k, A.n)) for k, A in enumerate(sub)]
+    x0s = [inputs.random_vector(A.n, 40 + k) for k, A in enumerate(sub)]
+    kw = dict(tol=0.0, maxit=37, rr_period=5)
+    ref = [oracle.solve(A, b, algo=ALG[variant], x0=x0, **kw) for A, b, x0 in zip(sub, bs, x0s)]
+    for gcap in ("1", "4", "64"):
+        monkeypatch.setenv("PBCGS_BATCH_GCAP", gcap)
+        for graph in (True, False):
+            say(f"batched diagonal layout {variant} gcap={gcap} graph={graph}")
+            xs, infos = solver.solve_batched(ops, [dev_t(b) for b in bs], [dev_t(x0) for x0 in x0s],
+                                             variant=variant, graph=graph, **kw)
+            for k, (x_or, i_or) in enumerate(ref):
+                assert (infos[k].status, infos[k].iters) == (i_or["status"], i_or["iters"]), (gcap, graph, k)
+                assert same(host(xs[k]), x_or), (gcap, graph, k)
+    monkeypatch.delenv("PBCGS_BATCH_GCAP")
+    # values scaled in place: the next batch lays out the new values
+    A0 = sub[2]
+    rp, col, val = dev_t(A0.row_ptr), dev_t(A0.col), dev_t(A0.val)
+    op0 = solver.csr(rp, col, val)
+    ops2 = [ops[0], ops[1], op0] + ops[3:]
+    solver.solve_batched(ops2, [dev_t(b) for b in bs], variant=variant, tol=1e-10, maxit=500)
+    val.mul_(1.5)
+    torch.cuda.synchronize()
+    A2 = oracle.CSR(A0.row_ptr, A0.col, A0.val * 1.5)
+    xs, infos = solver.solve_batched(ops2, [dev_t(b) for b in bs], variant=variant, tol=1e-10, maxit=500)
+    x_or, i_or = oracle.solve(A2, bs[2], algo=ALG[variant], tol=1e-10, maxit=500)
+    assert infos[2].iters == i_or["iters"] and same(host(xs[2]), x_or)
+    x_or, i_or = oracle.solve(sub[3], bs[3], algo=ALG[variant], tol=1e-10, maxit=500)
+    assert infos[3].iters == i_or["iters"] and same(host(xs[3]), x_or)
+
+
+def test_batched_one_system_without_layout_keeps_csr():
+    """One system with no diagonal layout (a 2 x 2 grid: 5 diagonals for 12
+    entries) puts the whole batch on the CSR arrays; results still equal the
+    oracle's."""
+    require_gpu()
+    sysl = [DIA_BATCH[2], oracle.assemble(2, 2, 5, (10.0, 20.0)), DIA_BATCH[4]]
+    ops = [csr_op(A) for A in sysl]
+    assert [op.diagonals > 0 for op in ops] == [True, False, True]
+    bs = [oracle.spmv(A, inputs.batch_x_true(k, A.n)) for k, A in enumerate(sysl)]
+    kw = dict(tol=1e-10, maxit=500, rr_period=17)
+    say("batched, one system without a diagonal layout")
     xs, infos = solver.solve_batched(ops, [dev_t(b) for b in bs], variant="pbicgstab_rr", **kw)
     for k, (A, b) in enumerate(zip(sysl, bs)):
         x_or, i_or = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, **kw)

@@ -15,6 +15,8 @@ solve read through the CSR arrays (``diagonal_layout=False``):
   binary64 ones) on 2-D and 3-D systems with ragged last blocks;
 * values changed in place between solves (the layout's values are copied for
   each solve);
+* the values read with ordinary loads and with the nontemporal hint (chosen
+  by the working set's size; both forced here);
 * exactly 32 diagonals, the widest layout.
 """
 
@@ -99,10 +101,14 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("cached", ["0", "1"])
 @pytest.mark.parametrize("name", ["c1", "c2_24", "c3_10", "band32"])
 @pytest.mark.parametrize("variant,precond,k", CASES)
-def test_solves_bitwise(name, variant, precond, k):
+def test_solves_bitwise(name, variant, precond, k, cached, monkeypatch):
+    """cached: the layout's values read with ordinary loads (1) or with the
+    nontemporal hint (0); the choice is by working-set size, forced here."""
     require_gpu()
+    monkeypatch.setenv("PBCGS_DIA_CACHED", cached)
     A = SYS[name]
     b = oracle.spmv(A, inputs.x_true(A.n))
     op = csr_op(A)
