@@ -96,6 +96,7 @@ def parse():
     p.add_argument("--only", default="",
                    help="comma list of legs to run: pipe,index32,bicg,explicit,stencil,fixed,cg,precision,batched,sweep,paper,"
                         "configs")
+    p.add_argument("--configs", default="c1,c3", help="comma list of the configs the configs leg runs")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
     p.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)  # the oracle timing process
@@ -550,6 +551,8 @@ def main():
                     "syncs_per_iter": inf.syncs_per_iter, "relres_true": inf.relres_true}
 
         for name, precond, steps in (("c1", None, 20), ("c3", "jacobi_folded", 2)):
+            if name not in args.configs.split(","):
+                continue
             wc = inputs.workload(name)
             kappa = None
             if wc.npts == 27:

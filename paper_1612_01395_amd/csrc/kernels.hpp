@@ -2454,14 +2454,38 @@ __global__ __launch_bounds__(kWG) void k_fold_x(int32_t n, double* __restrict__ 
 }
 
 // dinv_i = 1 / a_ii ; flag bit 0 if a diagonal entry is zero, non-finite or absent.
-__global__ __launch_bounds__(kWG) void k_dinv_csr(CsrOp op, int32_t n, double* dinv, int32_t* flag) {
-  const int32_t row = blockIdx.x * kWG + threadIdx.x;
-  if (row >= n) return;
-  double d = 0.0;
-  for (int32_t k = op.rp[row]; k < op.rp[row + 1]; ++k)
-    if (op.ci[k] == row) d = op.va[k];
-  if (d == 0.0 || !finite(d)) atomicOr(flag, 1);
-  dinv[row] = 1.0 / d;
+// One wave per 64 rows: the rows' entries are scanned in storage order
+// (coalesced); a row's diagonal entry is its last entry in column i (the last
+// of duplicates), found as the largest such index.
+__global__ __launch_bounds__(64) void k_dinv_csr(CsrOp op, int32_t n, double* dinv, int32_t* flag) {
+  __shared__ int32_t srp[65];
+  __shared__ int32_t sdk[64];
+  const int lane = threadIdx.x;
+  const int32_t r0 = (int32_t)blockIdx.x * 64;
+  srp[lane] = op.rp[min(r0 + lane, n)];
+  if (lane == 0) srp[64] = op.rp[min(r0 + 64, n)];
+  sdk[lane] = -1;
+  __syncthreads();
+  const int32_t k1 = srp[64];
+  for (int32_t k = srp[0] + lane; k < k1; k += 64) {
+    int lo = 0, hi = 64;  // srp[lo] <= k < srp[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (srp[mid] <= k) lo = mid;
+      else hi = mid;
+    }
+    if (op.ci[k] == r0 + lo) atomicMax(&sdk[lo], k);
+  }
+  __syncthreads();
+  const int32_t row = r0 + lane;
+  bool bad = false;
+  if (row < n) {
+    const int32_t k = sdk[lane];
+    const double d = k >= 0 ? op.va[k] : 0.0;
+    bad = d == 0.0 || !finite(d);
+    dinv[row] = 1.0 / d;
+  }
+  if (__any(bad) && lane == 0) atomicOr(flag, 1);
 }
 
 // flag bit 1 unless every dinv_i equals dinv_0 (then Jacobi is one scalar).
@@ -2474,9 +2498,13 @@ __global__ __launch_bounds__(kWG) void k_dinv_conv27(Conv27 op, int32_t n, doubl
   dinv[row] = 1.0 / d;
 }
 __global__ __launch_bounds__(kWG) void k_dinv_const(int32_t n, const double* dinv, int32_t* flag) {
+  // once a wave has set the bit the rest have nothing to add: they read the
+  // flag (from the device-coherent cache) and return
+  if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) return;
   const int32_t row = blockIdx.x * kWG + threadIdx.x;
-  if (row >= n) return;
-  if (!(dinv[row] == dinv[0]) || !finite(dinv[row]) || dinv[row] == 0.0) atomicOr(flag, 2);
+  bool bad = false;
+  if (row < n) bad = !(dinv[row] == dinv[0]) || !finite(dinv[row]) || dinv[row] == 0.0;
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 2);  // one atomic per wave
 }
 
 // ---------------------------------------------------------------------------
@@ -2751,29 +2779,53 @@ __global__ __launch_bounds__(kWG) void k_dia_mask(CsrOp op, int32_t n, const int
   if (bad) atomicOr(flag, 1);
 }
 
-// Values of the diagonal layout for one solve: the row's stored values in
-// order into its present slots (absent slots 0), scaled by dinv of the column
-// when folded (PC_VEC: the vector, PC_SCALAR: the constant; one rounding, as
-// the folded CSR values) and rounded once to V.
+// Values of the diagonal layout for one solve: each stored value goes to the
+// slot of its diagonal (absent slots 0), scaled by dinv of the column when
+// folded (PC_VEC: the vector, PC_SCALAR: the constant; one rounding, as the
+// folded CSR values) and rounded once to V.  One wave per 64 rows: the rows'
+// entries are read in storage order (coalesced), each placed in an LDS tile
+// at (its diagonal, its row) -- the row by a search of the row pointers, the
+// diagonal by a search of the ascending offsets -- and the tile is written
+// out diagonal by diagonal.  A row holds at most one entry per diagonal (the
+// layout is made only for rows with strictly ascending columns).
 template <int PC, class V>
-__global__ __launch_bounds__(kWG) void k_dia_fill(CsrOp op, int32_t n, const uint32_t* __restrict__ mask, int32_t nd,
-                                                  int32_t ld, V* __restrict__ dia, const double* __restrict__ dinv,
-                                                  double dinv_s) {
-  const int32_t row = blockIdx.x * kWG + threadIdx.x;
-  if (row >= n) return;
-  const uint32_t m = mask[row];
-  int32_t k = op.rp[row];
-  for (int d = 0; d < nd; ++d) {
-    V v = V(0);
-    if ((m >> d) & 1u) {
-      double a = op.va[k];
-      if (PC == PC_VEC) a = a * dinv[op.ci[k]];
-      if (PC == PC_SCALAR) a = a * dinv_s;
-      v = V(a);
-      ++k;
+__global__ __launch_bounds__(64) void k_dia_fill(CsrOp op, int32_t n, const int32_t* __restrict__ doff, int32_t nd,
+                                                 int32_t ld, V* __restrict__ dia, const double* __restrict__ dinv,
+                                                 double dinv_s) {
+  __shared__ V tile[kMaxDia][64];
+  __shared__ int32_t srp[65];
+  __shared__ int32_t soff[kMaxDia];
+  const int lane = threadIdx.x;
+  const int32_t r0 = (int32_t)blockIdx.x * 64;
+  for (int d = 0; d < nd; ++d) tile[d][lane] = V(0);
+  if (lane < nd) soff[lane] = doff[lane];
+  srp[lane] = op.rp[min(r0 + lane, n)];
+  if (lane == 0) srp[64] = op.rp[min(r0 + 64, n)];
+  __syncthreads();
+  const int32_t k1 = srp[64];
+  for (int32_t k = srp[0] + lane; k < k1; k += 64) {
+    int lo = 0, hi = 64;  // srp[lo] <= k < srp[hi]: k is an entry of row r0 + lo
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (srp[mid] <= k) lo = mid;
+      else hi = mid;
     }
-    dia[(int64_t)d * ld + row] = v;
+    const int32_t c = op.ci[k];
+    const int32_t off = c - (r0 + lo);
+    int a = 0, b = nd - 1;  // the slot whose offset is off
+    while (a < b) {
+      const int m = (a + b) >> 1;
+      if (soff[m] < off) a = m + 1;
+      else b = m;
+    }
+    double v = op.va[k];
+    if (PC == PC_VEC) v = v * dinv[c];
+    if (PC == PC_SCALAR) v = v * dinv_s;
+    tile[a][lo] = V(v);
   }
+  __syncthreads();
+  if (r0 + lane < n)
+    for (int d = 0; d < nd; ++d) dia[(int64_t)d * ld + r0 + lane] = tile[d][lane];
 }
 
 // ===========================================================================

@@ -159,6 +159,7 @@ struct pbcgs_op_s {
   // diagonal layout (at most kMaxDia diagonals, rows with ascending columns):
   // the per-row masks and the ascending diagonal offsets; owned by the operator
   uint32_t* dmask = nullptr;
+  int32_t* ddoff = nullptr;     // the diagonal offsets, on the device
   int32_t ndia = 0;
   int32_t dia_off[kMaxDia] = {};
 };
@@ -1536,9 +1537,11 @@ int make_dia(pbcgs_ctx_t ctx, pbcgs_op_t A) {
     return rc;
   }
   A->dmask = mask;
+  A->ddoff = doff;
   A->ndia = nd;
   for (int d = 0; d < nd; ++d) A->dia_off[d] = offs[(size_t)d];
   mask = nullptr;
+  doff = nullptr;
   release();
   return PBCGS_SUCCESS;
 }
@@ -1553,10 +1556,10 @@ int dia_operator(pbcgs_ctx_t ctx, pbcgs_op_t A, int pc_fold, const double* dv, d
   if (rc != PBCGS_SUCCESS) return rc;
   V* buf = static_cast<V*>(ctx->dia);
   const CsrOp op{A->rp, A->ci, A->va, A->n};
-  const int g = (A->n + kWG - 1) / kWG;
-  if (pc_fold == PC_VEC) k_dia_fill<PC_VEC, V><<<g, kWG, 0, ctx->stream>>>(op, A->n, A->dmask, A->ndia, ld, buf, dv, ds);
-  else if (pc_fold == PC_SCALAR) k_dia_fill<PC_SCALAR, V><<<g, kWG, 0, ctx->stream>>>(op, A->n, A->dmask, A->ndia, ld, buf, dv, ds);
-  else k_dia_fill<PC_NONE, V><<<g, kWG, 0, ctx->stream>>>(op, A->n, A->dmask, A->ndia, ld, buf, dv, ds);
+  const int g = (A->n + 63) / 64;
+  if (pc_fold == PC_VEC) k_dia_fill<PC_VEC, V><<<g, 64, 0, ctx->stream>>>(op, A->n, A->ddoff, A->ndia, ld, buf, dv, ds);
+  else if (pc_fold == PC_SCALAR) k_dia_fill<PC_SCALAR, V><<<g, 64, 0, ctx->stream>>>(op, A->n, A->ddoff, A->ndia, ld, buf, dv, ds);
+  else k_dia_fill<PC_NONE, V><<<g, 64, 0, ctx->stream>>>(op, A->n, A->ddoff, A->ndia, ld, buf, dv, ds);
   HIP_TRY(ctx, hipGetLastError());
   DiaOpT<V> d;
   std::memset(&d, 0, sizeof d);
@@ -1692,6 +1695,7 @@ int pbcgs_op_destroy(pbcgs_op_t op) {
     if (op->cd) (void)hipFree(op->cd);
     if (op->dg) (void)hipFree(op->dg);
     if (op->dmask) (void)hipFree(op->dmask);
+    if (op->ddoff) (void)hipFree(op->ddoff);
   }
   delete op;
   return PBCGS_SUCCESS;
@@ -1774,7 +1778,7 @@ int pbcgs_jacobi_dinv(pbcgs_ctx_t ctx, pbcgs_op_t A, double* dinv) {
   }
   int rc = reset_flag(ctx);
   if (rc != PBCGS_SUCCESS) return rc;
-  k_dinv_csr<<<(A->n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(CsrOp{A->rp, A->ci, A->va, A->n}, A->n, dinv, ctx->flag);
+  k_dinv_csr<<<(A->n + 63) / 64, 64, 0, ctx->stream>>>(CsrOp{A->rp, A->ci, A->va, A->n}, A->n, dinv, ctx->flag);
   int32_t flag = 0;
   rc = read_flag(ctx, &flag);
   if (rc != PBCGS_SUCCESS) return rc;
