@@ -327,10 +327,20 @@ def main():
     torch.cuda.synchronize()
 
     common = dict(tol=w.tol, maxit=w.maxit, rr_period=w.rr_period)
-    # launch shape of the 128^3 operator from the autotuner (never changes a result)
-    tune = solver.tune(A, b, iters=20, variant="pbicgstab_rr", precond="jacobi_folded", rr_period=w.rr_period)
+    # launch shapes from the autotuner (never change a result), kept on the
+    # operator per variant: each leg is tuned for its own variant and
+    # preconditioner form before it is timed
+    shapes = {}
 
-    def timed_leg(op, variant, precond, **extra):
+    def tune_for(op, variant, precond, label, **extra):
+        rep_ = solver.tune(op, b, iters=20, variant=variant, precond=precond, rr_period=w.rr_period, **extra)
+        shapes[label] = rep_["best"]
+        return rep_
+
+    tune = tune_for(A, "pbicgstab_rr", "jacobi_folded", "pipe")
+
+    def timed_leg(op, variant, precond, label, **extra):
+        tune_for(op, variant, precond, label, **extra)
         for _ in range(args.warmup):
             solver.solve(op, b, variant=variant, precond=precond, out=xbuf, **common, **extra)
         torch.cuda.synchronize()
@@ -369,7 +379,14 @@ def main():
             op = A if kind == "csr" else S
             if op is None:
                 continue
-            res[leg] = timed_leg(op, variant, precond, **(extra[0] if extra else {}))
+            res[leg] = timed_leg(op, variant, precond, leg, **(extra[0] if extra else {}))
+    # the fixed-iteration legs and the per-kernel roofline run the folded solves at their tuned shapes
+    tune = tune_for(A, "pbicgstab_rr", "jacobi_folded", "pipe")
+    tune_for(A, "bicgstab", "jacobi_folded", "bicg")
+    tune_for(A, "ca_bicgstab", "jacobi_folded", "ca")
+    if S is not None:
+        tune_for(S, "pbicgstab_rr", "jacobi_folded", "st_pipe")
+        tune_for(S, "bicgstab", "jacobi_folded", "st_bicg")
 
     # ---- fixed-iteration mode: tol = 0, 200 iterations, device-timed -----------
     fixed = {}
@@ -776,6 +793,7 @@ def main():
         "gbps_effective": round(per_iter_bytes * value / 1e9, 1) if value else None,
         "syncs_per_iter": info.syncs_per_iter if info else None,
         "autotuned_rows_per_wave_blocks": tune["best"],
+        "autotuned_rows_per_wave_blocks_per_leg": shapes,
     }
 
     def leg_summary(key, variant, stencil, folded, index_bytes=ib, dia=nd):

@@ -350,11 +350,16 @@ typedef struct {
 /*
  * Autotuner of the launch shape, measured on the device: runs `iters`
  * iterations (tol 0) of the solve described by opts (b: DEVICE right-hand
- * side; x is a scratch vector of its own) for every rows-per-wave block
- * count R whose grid fits, and keeps the fastest R on the operator; later
- * pbcgs_solve calls on A use it (the environment variables PBCGS_R and
- * PBCGS_GTARGET still take precedence).  The shape never changes a result:
- * every reduction is the same pairwise tree whatever R is.
+ * side; x is a scratch vector of its own; of opts->flags only the alpha form
+ * and the read-path bits are kept: graph replay, no kernel timing) for
+ * every rows-per-wave block
+ * count R whose grid fits, and keeps the fastest R on the operator for the
+ * variant and precision of opts (each variant's kernels have their own best
+ * shape); later pbcgs_solve calls on A of that variant and precision use it
+ * (the environment variables PBCGS_R and PBCGS_GTARGET still take
+ * precedence).  An unknown variant or precision is PBCGS_ERR_INVALID_ARG.
+ * The shape never changes a result: every reduction is the same pairwise
+ * tree whatever R is.
  */
 int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts* opts, int32_t iters,
                pbcgs_tune_report* rep);

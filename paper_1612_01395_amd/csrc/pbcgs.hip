@@ -144,7 +144,8 @@ struct pbcgs_op_s {
   const double* kappa = nullptr;
   double hb[3] = {0, 0, 0};
   double shift = 0.0;
-  int32_t tuned_R = 0;  // rows-per-wave blocks chosen by pbcgs_tune (0: default shape)
+  // rows-per-wave blocks chosen by pbcgs_tune per variant and precision (0: default shape)
+  int32_t tuned_R[PBCGS_PIPE_CG + 1][2] = {};
   // arrays the library allocated for this operator (a transpose), freed with it
   int32_t* own_rp = nullptr;
   int32_t* own_ci = nullptr;
@@ -1813,7 +1814,8 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
   if ((const void*)b == (const void*)x) return fail(ctx, PBCGS_ERR_INVALID_ARG, "b and x must not overlap");
   DeviceGuard guard(ctx->device);
   Shape sh;
-  if (!make_shape(A->n, &sh, A->tuned_R)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows");
+  if (!make_shape(A->n, &sh, A->tuned_R[o.variant][mp ? 1 : 0]))
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows");
   std::memset(info, 0, sizeof *info);
 
   const size_t np = padded(A->n);
@@ -2256,6 +2258,9 @@ int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts*
                pbcgs_tune_report* rep) {
   if (!ctx || !A || !b || !opts || !rep) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
   if (iters < 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "iters must be positive");
+  if (opts->variant < PBCGS_BICGSTAB || opts->variant > PBCGS_PIPE_CG ||
+      (opts->precision != PBCGS_FP64 && opts->precision != PBCGS_FP32_RR64))
+    return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown variant or precision");
   DeviceGuard guard(ctx->device);
   std::memset(rep, 0, sizeof *rep);
   double* xs = nullptr;
@@ -2264,16 +2269,17 @@ int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts*
   o.tol = 0.0;
   o.maxit = iters;
   o.history = nullptr;
-  o.flags = 0;
+  o.flags = opts->flags & (4 | 8 | 16);  // keep the alpha form and the read path; graph replay, no timing
   o.check_every = 0;
-  const int32_t saved = A->tuned_R;
+  int32_t& slot = A->tuned_R[o.variant][o.precision == PBCGS_FP32_RR64 ? 1 : 0];
+  const int32_t saved = slot;
   double best = -1.0;
   int rc = PBCGS_SUCCESS;
   for (int R = 1; R <= kMaxR && rep->ncand < 12; R *= 2) {
     const int64_t G = ((int64_t)A->n + 256 * (int64_t)R - 1) / (256 * (int64_t)R);
     if (G > kMaxG) continue;
     if (rep->ncand > 0 && G < 64) break;  // fewer workgroups than a quarter of the CUs: not a candidate
-    A->tuned_R = R;
+    slot = R;
     double ms = 0.0;
     for (int t = 0; t < 2 && rc >= 0; ++t) {  // the first run captures the graphs
       pbcgs_info info;
@@ -2291,10 +2297,10 @@ int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts*
   }
   (void)hipFree(xs);
   if (rc < 0) {
-    A->tuned_R = saved;
+    slot = saved;
     return rc;
   }
-  A->tuned_R = rep->best;
+  slot = rep->best;
   rep->best_ms_per_iter = best;
   return PBCGS_SUCCESS;
 }

@@ -473,7 +473,8 @@ def solve_adjoint_batched(ops: list, gs: list, **kw):
     return lams, infos, ts
 
 
-def _opts(variant="pbicgstab_rr", precond=None, precision="fp64", tol=1e-8, maxit=2000, rr_period=50, rr_max=-1):
+def _opts(variant="pbicgstab_rr", precond=None, precision="fp64", tol=1e-8, maxit=2000, rr_period=50, rr_max=-1,
+          index32=False, diagonal_layout=True):
     o = L.Opts()
     o.variant = VARIANTS[variant]
     o.precond = PRECONDS[precond]
@@ -483,7 +484,7 @@ def _opts(variant="pbicgstab_rr", precond=None, precision="fp64", tol=1e-8, maxi
     o.rr_period = int(rr_period)
     o.rr_max = int(rr_max)
     o.check_every = 0
-    o.flags = 0
+    o.flags = (L.FLAG_INDEX32 if index32 else 0) | (0 if diagonal_layout else L.FLAG_NO_DIA)
     o.history = None
     return o
 
@@ -495,7 +496,9 @@ def _report(r) -> dict:
 
 def tune(A: Operator, b: torch.Tensor, iters: int = 20, **opts) -> dict:
     """Time `iters` iterations for each launch shape (rows-per-wave blocks R)
-    and keep the fastest on A for later solves; returns the report."""
+    and keep the fastest on A for later solves of the same variant and
+    precision; returns the report.  ``index32`` / ``diagonal_layout=False``
+    time the solves on those read paths."""
     _check_vec(b, A.n, "b")
     o = _opts(**opts)
     r = L.TuneReport()

@@ -27,6 +27,34 @@ def test_tune_single_system_keeps_results():
     assert info.iters == i_or["iters"] and same(host(x), x_or)
 
 
+def test_tune_per_variant_and_read_path():
+    """Each variant keeps its own tuned shape; tuning BiCGStab after
+    p-BiCGStab (and on the CSR stream) changes neither solve's bits, and an
+    unknown precision is refused."""
+    require_gpu()
+    from paper_1612_01395_amd import _lib
+    A = oracle.assemble_workload(inputs.workload("c2", n=36))
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    op = csr_op(A)
+    bd = dev_t(b)
+    d = oracle.jacobi_dinv(A)
+    kw = dict(precond="jacobi_folded", rr_period=20)
+    r1 = solver.tune(op, bd, iters=8, variant="pbicgstab_rr", **kw)
+    r2 = solver.tune(op, bd, iters=8, variant="bicgstab", **kw)
+    r3 = solver.tune(op, bd, iters=8, variant="pbicgstab_rr", diagonal_layout=False, **kw)
+    say(f"tune per variant: {r1['best']} {r2['best']} {r3['best']}")
+    for variant, algo in (("pbicgstab_rr", oracle.ALG_PBICGSTAB_RR), ("bicgstab", oracle.ALG_BICGSTAB)):
+        x_or, i_or = oracle.solve_folded(A, b, algo=algo, dinv=d, tol=1e-10, rr_period=20)
+        for layout in (True, False):
+            x, info = solver.solve(op, bd, variant=variant, tol=1e-10, diagonal_layout=layout, **kw)
+            assert info.iters == i_or["iters"] and same(host(x), x_or), (variant, layout)
+    o = solver._opts(variant="bicgstab")
+    o.precision = 7
+    r = _lib.TuneReport()
+    assert _lib.lib().pbcgs_tune(op.ctx.handle, op.handle, solver._ptr(bd), _lib.ctypes.byref(o), 4,
+                                 _lib.ctypes.byref(r)) == _lib.ERR_INVALID_ARG
+
+
 def test_tune_batched_keeps_results():
     require_gpu()
     systems = inputs.batch_systems(count=24, lo=8, hi=160)
