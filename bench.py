@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_pb_c2.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1612_01395_amd", "csrc", f) for f in ("kernels.hpp", "pbcgs.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1612_01395_amd", "csrc", "kernels.hpp")]  # every solver kernel
 
 
 def code_text(src: str) -> str:
@@ -61,7 +61,7 @@ def code_text(src: str) -> str:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the code (without comments) of the kernel and launch sources."""
+    """Hash of the code (without comments) of the kernel source."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -70,11 +70,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
-    reading for a plain copy of known size), or None if the kernel sources
-    changed since the counters were taken."""
+def measured_traffic(kernel: str, grid_threads: int):
+    """HBM bytes per launch of `kernel` at a grid of `grid_threads` threads
+    from the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE,
+    each scaled by the same counter's reading for a plain copy of known
+    size), or None if the kernel source changed since the counters were taken
+    or the grid was not measured."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -82,7 +83,13 @@ def measured_traffic(kernel: str):
         return None
     if t.get("source_hash") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch", {}).get(kernel)
+    return t.get("bytes_per_launch", {}).get(kernel, {}).get(str(grid_threads))
+
+
+def progress(msg: str) -> None:
+    """One line on stderr when a leg of the benchmark ends."""
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
 
 
 def parse():
@@ -333,7 +340,7 @@ def main():
     shapes = {}
 
     def tune_for(op, variant, precond, label, **extra):
-        rep_ = solver.tune(op, b, iters=20, variant=variant, precond=precond, rr_period=w.rr_period, **extra)
+        rep_ = solver.tune(op, b, iters=40, variant=variant, precond=precond, rr_period=w.rr_period, **extra)
         shapes[label] = rep_["best"]
         return rep_
 
@@ -380,6 +387,7 @@ def main():
             if op is None:
                 continue
             res[leg] = timed_leg(op, variant, precond, leg, **(extra[0] if extra else {}))
+            progress(f"leg {leg} done")
     # the fixed-iteration legs and the per-kernel roofline run the folded solves at their tuned shapes
     tune = tune_for(A, "pbicgstab_rr", "jacobi_folded", "pipe")
     tune_for(A, "bicgstab", "jacobi_folded", "bicg")
@@ -388,6 +396,7 @@ def main():
         tune_for(S, "pbicgstab_rr", "jacobi_folded", "st_pipe")
         tune_for(S, "bicgstab", "jacobi_folded", "st_bicg")
 
+    progress("section: fixed-iteration mode")
     # ---- fixed-iteration mode: tol = 0, 200 iterations, device-timed -----------
     fixed = {}
     if "fixed" in legs:
@@ -433,6 +442,7 @@ def main():
             fixed[f"{wname}_{side}"] = entry
             del As, bs, xs, rps, cols, vals
 
+    progress("section: the CG family")
     # ---- the CG family (Section 2) on the symmetric counterpart of the operator --
     cgfam = None
     if "cg" in legs:
@@ -468,6 +478,7 @@ def main():
             cgfam[f"{side}^3"] = entry
             del As, bs, xs, rps, cols, vals
 
+    progress("section: roofline of the dominant kernel")
     # ---- roofline of the dominant kernel: one solve with per-kernel events -------
     _, pinfo = solver.solve(A, b, variant="pbicgstab_rr", precond="jacobi_folded", out=xbuf, time_kernels=True,
                             **common)
@@ -476,6 +487,8 @@ def main():
     dom = 0 if pinfo.kernel_ms[0] >= pinfo.kernel_ms[1] else 1
     dom_bytes = (ba, bb)[dom]
     achieved = dom_bytes / (avg[dom] * 1e-3) / 1e9
+    # the launch grid at the tuned shape: ceil(N / (256 R)) workgroups of 256 threads
+    grid_threads = -(-N // (256 * tune["best"])) * 256
     roofline = {
         "bound": "hbm",
         "kernel": ("k_pa (t = A w, recurrences, (q,y),(y,y))", "k_pb (v = A z, x/r/w updates, 5 dots)")[dom],
@@ -483,8 +496,10 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(("k_pa", "k_pb")[dom]),
+        "traffic": measured_traffic(("k_pa", "k_pb")[dom], grid_threads),
         "bytes_per_launch": dom_bytes,
+        "grid_threads": grid_threads,
+        "rows_per_wave_blocks": tune["best"],
         "column_index_bytes": ib,
         "operator_layout": f"diagonal layout, {nd} diagonals (4-byte row mask + 8 bytes per diagonal and row)"
         if nd else f"CSR stream, {ib}-byte column indices",
@@ -496,10 +511,11 @@ def main():
         "per_kernel": {name: {"avg_launch_us": round(avg[k] * 1e3, 2), "bytes_per_launch": (ba, bb)[k],
                               "achieved": round((ba, bb)[k] / (avg[k] * 1e-3) / 1e9, 1),
                               "frac": round((ba, bb)[k] / (avg[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                              "traffic": measured_traffic(name)}
+                              "traffic": measured_traffic(name, grid_threads)}
                        for k, name in enumerate(("k_pa", "k_pb"))},
     }
 
+    progress("section: precision form at 256^3")
     # ---- precision form at 256^3 (tol 1e-10): binary32 + binary64 replacement vs binary64
     precision = None
     if "precision" in legs:
@@ -545,6 +561,7 @@ def main():
         del A4, rp4, col4, val4, b4, x4, x64
         torch.cuda.empty_cache()
 
+    progress("section: the other configurations")
     # ---- the other configurations: 2-D 64^2 (latency-bound) and 3-D 27-point 256^3, assembled (matrix-bound)
     # and matrix-free
     other_cfg = None
@@ -631,6 +648,7 @@ def main():
             del Ac, rpc, colc, valc, bc, xc, kappa
             torch.cuda.empty_cache()
 
+    progress("section: the paper's test problems")
     # ---- the paper's test problems (Section 5): 1000^2 five-point stencils, x_hat = 1, tol 1e-6
     paper = None
     if "paper" in legs:
@@ -655,6 +673,7 @@ def main():
         paper["note"] = ("paper (20 nodes, 240 ranks): PTP1 205-282 iterations, PTP2 1283-2112; "
                          "matrix-free stencil here, bitwise equal to the CSR solve and the oracle")
 
+    progress("section: size sweep")
     # ---- size sweep: where the two kernel boundaries per iteration pay off
     sweep = None
     if "sweep" in legs:
@@ -684,6 +703,7 @@ def main():
                 row["pbicgstab_rr"]["iters_per_s"] / row["bicgstab"]["iters_per_s"], 4)
             sweep[f"{ns}^3"] = row
 
+    progress("section: batched form")
     # ---- batched form: 512 independent 2-D systems of uneven size, forward and adjoint
     batched = None
     if "batched" in legs:
@@ -762,6 +782,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
+    progress("section: CPU baseline")
     # ---- CPU baseline: the oracle on a bounded sample, in a process of its own ---
     cpu = None
     if not args.no_cpu_baseline:

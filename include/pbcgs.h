@@ -352,10 +352,10 @@ typedef struct {
  * iterations (tol 0) of the solve described by opts (b: DEVICE right-hand
  * side; x is a scratch vector of its own; of opts->flags only the alpha form
  * and the read-path bits are kept: graph replay, no kernel timing) for
- * every rows-per-wave block
- * count R whose grid fits, and keeps the fastest R on the operator for the
- * variant and precision of opts (each variant's kernels have their own best
- * shape); later pbcgs_solve calls on A of that variant and precision use it
+ * every rows-per-wave block count R whose grid fits -- once to capture the
+ * graphs, then three times, the fastest counting -- and keeps the fastest R
+ * on the operator for the variant and precision of opts (each variant's
+ * kernels have their own best shape); later pbcgs_solve calls on A of that variant and precision use it
  * (the environment variables PBCGS_R and PBCGS_GTARGET still take
  * precedence).  An unknown variant or precision is PBCGS_ERR_INVALID_ARG.
  * The shape never changes a result: every reduction is the same pairwise

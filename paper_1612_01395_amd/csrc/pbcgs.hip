@@ -102,8 +102,8 @@ struct pbcgs_ctx_s {
   size_t ahat_cap = 0;      // doubles
   float* a32 = nullptr;     // binary32 operator values (precision form, CSR)
   size_t a32_cap = 0;       // floats
-  void* dia = nullptr;      // values of an operator's diagonal layout for the current solve
-  size_t dia_cap = 0;       // bytes
+  void* dia[2] = {nullptr, nullptr};  // values of an operator's diagonal layout for the current solve
+  size_t dia_cap[2] = {0, 0};         // bytes (slot 1: the binary64 layout beside a binary32 one)
   // batched solves: system table, workgroup map, vectors, states, partials, host poll copies
   SysDesc* bsys = nullptr;
   size_t bsys_cap = 0;
@@ -314,22 +314,22 @@ int ensure_a32(pbcgs_ctx_t ctx, size_t floats) {
   return PBCGS_SUCCESS;
 }
 
-int ensure_dia(pbcgs_ctx_t ctx, size_t bytes) {
-  if (ctx->dia_cap >= bytes) return PBCGS_SUCCESS;
+int ensure_dia(pbcgs_ctx_t ctx, size_t bytes, int slot) {
+  if (ctx->dia_cap[slot] >= bytes) return PBCGS_SUCCESS;
   if (ctx->noalloc) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the call may not allocate and its scratch is too small");
-  if (ctx->dia) {
+  if (ctx->dia[slot]) {
     (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(ctx->dia);
-    ctx->dia = nullptr;
-    ctx->dia_cap = 0;
+    (void)hipFree(ctx->dia[slot]);
+    ctx->dia[slot] = nullptr;
+    ctx->dia_cap[slot] = 0;
     for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
     ctx->graphs.clear();
   }
-  if (hipMalloc(&ctx->dia, std::max<size_t>(bytes, 8)) != hipSuccess) {
-    ctx->dia = nullptr;
+  if (hipMalloc(&ctx->dia[slot], std::max<size_t>(bytes, 8)) != hipSuccess) {
+    ctx->dia[slot] = nullptr;
     return fail(ctx, PBCGS_ERR_ALLOC, "allocation of " + std::to_string(bytes) + " bytes of diagonal-layout values failed");
   }
-  ctx->dia_cap = bytes;
+  ctx->dia_cap[slot] = bytes;
   return PBCGS_SUCCESS;
 }
 
@@ -1366,7 +1366,8 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->ahat) (void)hipFree(ctx->ahat);
   if (ctx->a32) (void)hipFree(ctx->a32);
-  if (ctx->dia) (void)hipFree(ctx->dia);
+  for (void* d : ctx->dia)
+    if (d) (void)hipFree(d);
   if (ctx->bsys) (void)hipFree(ctx->bsys);
   if (ctx->bmap) (void)hipFree(ctx->bmap);
   if (ctx->bws) (void)hipFree(ctx->bws);
@@ -1548,14 +1549,16 @@ int make_dia(pbcgs_ctx_t ctx, pbcgs_op_t A) {
 }
 
 // The diagonal layout of A with this solve's values: the stored values, or
-// those of A M^{-1} (pc_fold PC_VEC / PC_SCALAR), rounded once to V.
+// those of A M^{-1} (pc_fold PC_VEC / PC_SCALAR), rounded once to V, in the
+// context's values buffer `slot`.
 extern "C++" {
 template <class V>
-int dia_operator(pbcgs_ctx_t ctx, pbcgs_op_t A, int pc_fold, const double* dv, double ds, DiaOpT<V>* out) {
+int dia_operator(pbcgs_ctx_t ctx, pbcgs_op_t A, int pc_fold, const double* dv, double ds, DiaOpT<V>* out,
+                 int slot = 0) {
   const int32_t ld = (int32_t)padded(A->n);
-  const int rc = ensure_dia(ctx, (size_t)A->ndia * (size_t)ld * sizeof(V));
+  const int rc = ensure_dia(ctx, (size_t)A->ndia * (size_t)ld * sizeof(V), slot);
   if (rc != PBCGS_SUCCESS) return rc;
-  V* buf = static_cast<V*>(ctx->dia);
+  V* buf = static_cast<V*>(ctx->dia[slot]);
   const CsrOp op{A->rp, A->ci, A->va, A->n};
   const int g = (A->n + 63) / 64;
   if (pc_fold == PC_VEC) k_dia_fill<PC_VEC, V><<<g, 64, 0, ctx->stream>>>(op, A->n, A->ddoff, A->ndia, ld, buf, dv, ds);
@@ -1899,7 +1902,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     const double ds = a.dinv_s;
     a.dinv = nullptr;
     a.dinv_s = 0.0;
-    if (folded && A->kind == OP_CSR) {
+    if (folded && A->kind == OP_CSR && !use_dia) {
       rc = ensure_ahat(ctx, (size_t)A->nnz);
       if (rc != PBCGS_SUCCESS) return rc;
     }
@@ -1921,20 +1924,30 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
         return st;
       };
       // run the binary32 form on op64 (A, or A M^{-1} formed); its binary32
-      // operator is op64 rounded, or the diagonal layout of those values
+      // operator is op64 rounded
       auto go = [&](auto op64) -> int {
-        if constexpr (IsCsr<decltype(op64)>::value) {
-          if (use_dia) {
-            DiaOpF op32;
-            const int rcd = dia_operator<float>(ctx, A, folded ? pc : PC_NONE, dv, ds, &op32);
-            if (rcd != PBCGS_SUCCESS) return rcd;
-            return run_mp(op32, op64);
-          }
-        }
         auto op32 = to_binary32(ctx, op64, A->nnz);
         HIP_TRY(ctx, hipGetLastError());
         return run_mp(op32, op64);
       };
+      if constexpr (IsCsr<decltype(op)>::value) {
+        if (use_dia) {
+          // both operators through the diagonal layout: the binary32 values
+          // and, for the replacement steps, the binary64 ones (A, or A M^{-1}
+          // formed in the layout's fill, one rounding each as k_fold_csr's)
+          const int pcf = folded ? pc : PC_NONE;
+          DiaOpF op32;
+          DiaOp op64;
+          int rcd = dia_operator<float>(ctx, A, pcf, dv, ds, &op32, 0);
+          if (rcd == PBCGS_SUCCESS) rcd = dia_operator<double>(ctx, A, pcf, dv, ds, &op64, 1);
+          if (rcd != PBCGS_SUCCESS) return rcd;
+          if (folded) {
+            if (pc == PC_VEC) k_fold_x<PC_VEC, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+            else k_fold_x<PC_SCALAR, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+          }
+          return run_mp(op32, op64);
+        }
+      }
       if (!folded) return go(op);
       auto fop = fold_operator(ctx, A, op, pc, dv, ds);
       if (pc == PC_VEC) k_fold_x<PC_VEC, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
@@ -2281,11 +2294,12 @@ int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts*
     if (rep->ncand > 0 && G < 64) break;  // fewer workgroups than a quarter of the CUs: not a candidate
     slot = R;
     double ms = 0.0;
-    for (int t = 0; t < 2 && rc >= 0; ++t) {  // the first run captures the graphs
+    // the first run captures the graphs; the fastest of the next three counts
+    for (int t = 0; t < 4 && rc >= 0; ++t) {
       pbcgs_info info;
       HIP_TRY(ctx, hipMemsetAsync(xs, 0, sizeof(double) * (size_t)A->n, ctx->stream));
       rc = pbcgs_solve(ctx, A, b, xs, nullptr, &o, &info);
-      ms = info.ms;
+      if (t == 1 || (t > 1 && info.ms < ms)) ms = info.ms;
     }
     if (rc < 0) break;
     const double per = ms / iters;
