@@ -2352,6 +2352,87 @@ __global__ __launch_bounds__(kWG) void k_mp_rr_s(Op64 op, Args a) {
   });
 }
 
+// The binary64 replacement steps with two neighbouring rows per lane (as
+// k_mp_pa2): the same arithmetic per row and the same reduction trees as
+// k_mp_rr_w, k_mp_rr_s and k_mp_pa<..., true>, so the same bits.  Their
+// product inputs are workspace vectors (r64, p, s64, w), whose pairs are
+// aligned; r = b - A x reads the caller's x and keeps one row per lane.
+template <class Op64>
+__global__ __launch_bounds__(kWG) void k_mp_rr_w2(Op64 op, Args a) {
+  PBCGS_PROLOGUE(st)
+  st.n_rr += 1;
+  publish(a, st);
+  produce2<5, float>(a, [&](int32_t row, bool valid0, bool valid1, float (&d)[5]) {
+    double w0, w1;
+    op.spmv2(row, valid0, valid1, a.r64, w0, w1);
+    if (!valid0) return;
+    float2 wf;
+    wf.x = float(w0);
+    wf.y = float(w1);
+    *reinterpret_cast<float2*>(&a.wf[row]) = wf;
+    const float2 r0 = *reinterpret_cast<const float2*>(&a.r0f[row]);
+    const float2 r = *reinterpret_cast<const float2*>(&a.rf[row]);
+    const float2 sv = *reinterpret_cast<const float2*>(&a.sf[row]);
+    const float2 zv = *reinterpret_cast<const float2*>(&a.zf[row]);
+    d[0] = r0.x * r.x + (valid1 ? r0.y * r.y : 0.0f);
+    d[1] = r0.x * wf.x + (valid1 ? r0.y * wf.y : 0.0f);
+    d[2] = r0.x * sv.x + (valid1 ? r0.y * sv.y : 0.0f);
+    d[3] = r0.x * zv.x + (valid1 ? r0.y * zv.y : 0.0f);
+    d[4] = r.x * r.x + (valid1 ? r.y * r.y : 0.0f);
+  });
+}
+
+template <class Op64>
+__global__ __launch_bounds__(kWG) void k_mp_rr_s2(Op64 op, Args a) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  each_row2(a, [&](int32_t row, bool valid0, bool valid1) {
+    double s0, s1;
+    op.spmv2(row, valid0, valid1, a.pf, s0, s1);
+    if (!valid0) return;
+    D2 sv;
+    sv.x = s0;
+    sv.y = s1;
+    *reinterpret_cast<D2*>(&a.s64[row]) = sv;
+    float2 sf;
+    sf.x = float(s0);
+    sf.y = float(s1);
+    *reinterpret_cast<float2*>(&a.sf[row]) = sf;
+  });
+}
+
+// K_a of the iteration after a replacement (k_mp_pa<..., true>): t = A w in
+// binary32, z = f(A s64) in binary64, q and y from the replaced s.
+template <class Op32, class Op64>
+__global__ __launch_bounds__(kWG) void k_mp_pa2_rr(Op32 op, Op64 op64, Args a) {
+  PBCGS_PROLOGUE(st)
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const float af = float(st.alpha);
+  produce2<2, float>(a, [&](int32_t row, bool valid0, bool valid1, float (&d)[2]) {
+    float t0, t1;
+    op.spmv2(row, valid0, valid1, a.wf, t0, t1);
+    double z0, z1;
+    op64.spmv2(row, valid0, valid1, a.s64, z0, z1);
+    if (!valid0) return;
+    const float2 r = *reinterpret_cast<const float2*>(&a.rf[row]);
+    const float2 w = *reinterpret_cast<const float2*>(&a.wf[row]);
+    const float2 sv = *reinterpret_cast<const float2*>(&a.sf[row]);
+    float2 z, t;
+    z.x = float(z0);
+    z.y = float(z1);
+    t.x = t0;
+    t.y = t1;
+    const float q0 = r.x - af * sv.x, y0 = w.x - af * z.x;
+    const float q1 = r.y - af * sv.y, y1 = w.y - af * z.y;
+    *reinterpret_cast<float2*>(&a.tf[row]) = t;
+    *reinterpret_cast<float2*>(&a.zf[row]) = z;
+    d[0] = q0 * y0 + (valid1 ? q1 * y1 : 0.0f);
+    d[1] = y0 * y0 + (valid1 ? y1 * y1 : 0.0f);
+  });
+}
+
 // Pending reduction finished by one workgroup: MODE 0 reduction 2 (a.mode as
 // in k_mp_rr_p), 1 the setup alpha.
 template <int MODE>

@@ -523,6 +523,22 @@ struct Driver {
     if constexpr (MP && HasSpmv2<Op>::value) return a.R >= 2 && env_int("PBCGS_TWO_ROWS", 1) != 0;
     return false;
   }
+  // the replacement steps of the binary32 form with two rows per lane too
+  // (their binary64 operator has the two-row product)
+  bool two_rows_rr() const {
+    if constexpr (MP && HasSpmv2<Op>::value && HasSpmv2<Op64>::value) return two_rows();
+    return false;
+  }
+  void launch_rr_w() {
+    hipStream_t s = ctx->stream;
+    if constexpr (MP && HasSpmv2<Op64>::value) {
+      if (two_rows_rr()) {
+        k_mp_rr_w2<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, PB_B));
+        return;
+      }
+    }
+    k_mp_rr_w<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, PB_B));
+  }
 
   void setup() {
     hipStream_t s = ctx->stream;
@@ -552,8 +568,18 @@ struct Driver {
       const bool pending = pending_rr(i), recheck = was_forced(i - 1), rr = rr_due(o, i);
       if (pending) {
         k_mp_rr_p<<<grid(), kWG, 0, s>>>(L(PB_B, -1, false, recheck ? 1 : 0));
-        k_mp_rr_s<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, -1));
-        k_mp_pa<Op, Op64, true><<<grid(), kWG, 0, s>>>(op, op64, L(-1, PB_A));
+        bool done = false;
+        if constexpr (HasSpmv2<Op>::value && HasSpmv2<Op64>::value) {
+          if (two_rows_rr()) {
+            k_mp_rr_s2<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, -1));
+            k_mp_pa2_rr<Op, Op64><<<grid(), kWG, 0, s>>>(op, op64, L(-1, PB_A));
+            done = true;
+          }
+        }
+        if (!done) {
+          k_mp_rr_s<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, -1));
+          k_mp_pa<Op, Op64, true><<<grid(), kWG, 0, s>>>(op, op64, L(-1, PB_A));
+        }
       } else {
         timed(0, [&] {
           if (two_rows()) {
@@ -567,7 +593,7 @@ struct Driver {
       if (rr) {
         k_mp_rr_x<<<grid(), kWG, 0, s>>>(L(PB_A, -1));
         k_mp_rr_r<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, -1));
-        k_mp_rr_w<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, PB_B));
+        launch_rr_w();
       } else {
         timed(1, [&] {
           if (two_rows()) {
@@ -902,7 +928,7 @@ struct Driver {
           // not yet: replace r, w now and go on (s, z follow in the next iteration)
           k_resume<<<1, 64, 0, s>>>(ctx->st + (q & 1));
           k_mp_rr_r<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, -1));
-          k_mp_rr_w<Op64><<<grid(), kWG, 0, s>>>(op64, L(-1, PB_B));
+          launch_rr_w();
           HIP_TRY(ctx, hipGetLastError());
           forced.push_back((int64_t)fin.iters - 1);
           launched = fin.iters;
