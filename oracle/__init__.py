@@ -105,6 +105,8 @@ def lib():
         L.or_spmv32.argtypes = [ctypes.c_int32, _i32p, _i32p, _f32p, _f32p, _f32p]
         L.or_set_alpha_form.restype = None
         L.or_set_alpha_form.argtypes = [ctypes.c_int32]
+        L.or_set_perturb.restype = None
+        L.or_set_perturb.argtypes = [ctypes.c_int32, ctypes.c_double]
         L.or_counters_get.restype = None
         L.or_counters_get.argtypes = [np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")]
         L.or_counters_reset.restype = None
@@ -214,14 +216,16 @@ def jacobi_dinv(A: CSR) -> np.ndarray:
 
 def solve(A: CSR, b, *, algo: int = ALG_PBICGSTAB_RR, dinv=None, x0=None, tol: float = 1e-8,
           maxit: int = 2000, rr_period: int = 50, rr_max: int = -1, history: bool = False,
-          scalars: bool = False, alpha_form: int = 3):
+          scalars: bool = False, alpha_form: int = 3, perturb=None):
     """Run one solver of the paper; returns ``(x, info)``.
 
     ``info`` holds iters, n_rr, status, relres_rec (last ||r_i||/||r_0||),
     relres_true (||b - A x|| / ||r_0||) and, on request, the residual
     history (length maxit+1) and the per-iteration scalars alpha, omega, beta.
     ``alpha_form`` 5 computes alpha_{i+1} of the pipelined solvers by eq. (5)
-    instead of eq. (3).
+    instead of eq. (3).  ``perturb = (j, c)`` multiplies the recursive
+    residual r_{j+1} of the pipelined solvers by c at the end of iteration j,
+    after its reductions (a test hook for the replacement of Section 4.2).
     """
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
@@ -231,11 +235,14 @@ def solve(A: CSR, b, *, algo: int = ALG_PBICGSTAB_RR, dinv=None, x0=None, tol: f
     ints = np.zeros(3, np.int32)
     dbl = np.zeros(2, np.float64)
     lib().or_set_alpha_form(int(alpha_form))
+    if perturb is not None:
+        lib().or_set_perturb(int(perturb[0]), float(perturb[1]))
     try:
         st = lib().or_solve(algo, A.n, A.row_ptr, A.col, A.val, dv, b, x, float(tol), int(maxit),
                             int(rr_period), int(rr_max), hist, sc, ints, dbl)
     finally:
         lib().or_set_alpha_form(3)
+        lib().or_set_perturb(-1, 1.0)
     if st < 0:
         raise ValueError(f"oracle solve failed with code {st}")
     info = {"iters": int(ints[0]), "n_rr": int(ints[1]), "status": int(ints[2]),

@@ -38,6 +38,9 @@
  *  - shadow residual r~ = r_0; quantities with index -1 are zero, omega_{-1}=0;
  *  - alpha_{i+1} uses the four-dot expression (eq. 3) by default; eq. (5),
  *    the three-dot form, on request (or_set_alpha_form);
+ *  - a test hook (or_set_perturb) scales the recursive residual of the
+ *    pipelined solvers after one iteration, so that tests can watch the next
+ *    replacement close the gap to b - A x;
  *  - residual replacement in iteration i with (i+1) mod k == 0: r, r^, w are
  *    replaced after the x-update of iteration i (so the second reduction,
  *    beta_i, alpha_{i+1}, w^ and t all see the true values) and s, s^, z
@@ -85,6 +88,17 @@ static or_counters g_ctr;
  * is equal in exact arithmetic. */
 static int g_alpha_form = 3;
 void or_set_alpha_form(int32_t form) { g_alpha_form = (form == 5) ? 5 : 3; }
+
+/* Test hook for the residual replacement of Section 4.2.  At the end of
+ * iteration g_perturb_iter of the pipelined BiCGStab solvers (Algorithms 9
+ * and 11), after that iteration's reductions and scalars, every entry of the
+ * recursive residual r_{i+1} is multiplied by g_perturb_scale (the
+ * preconditioned copy r^ is left alone).  This opens a gap between r and
+ * b - A x, as accumulated rounding does, which the next replacement must
+ * close.  -1 = off. */
+static int32_t g_perturb_iter = -1;
+static double g_perturb_scale = 1.0;
+void or_set_perturb(int32_t iter, double scale) { g_perturb_iter = iter; g_perturb_scale = scale; }
 
 void or_counters_get(int64_t* out6)
 {
@@ -601,6 +615,7 @@ static int pbicgstab(const csr_t* A, const double* dinv, const double* b, double
         }
         if (!isfinite(alpha)) { info->status = OR_NONFINITE; goto done; }
         gamma = gamma1;
+        if (i == g_perturb_iter) PAR for (int32_t j = 0; j < n; ++j) r[j] = g_perturb_scale * r[j];
     }
     info->status = OR_MAXIT;
 done:
