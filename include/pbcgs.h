@@ -125,7 +125,16 @@ typedef struct {
                             (Section 3.1); bit 3: read the caller's int32 col_idx
                             even when the operator holds a compact copy (implies
                             bit 4); bit 4: read the CSR arrays even when the
-                            operator has a diagonal layout (pbcgs_op_diagonals)  */
+                            operator has a diagonal layout (pbcgs_op_diagonals);
+                            bit 5 (a test hook): fill the solve's workspace --
+                            vectors with their padding, partial sums, the
+                            diagonal layout's values, A M^{-1} and binary32
+                            values -- with NaN bits before the solve writes it,
+                            so that a read of anything the solve did not write
+                            (the index -1 vectors of the pipelined methods, say)
+                            turns the results into NaN; results are otherwise
+                            unchanged (pbcgs_solve, pbcgs_solve_noalloc and
+                            pbcgs_solve_batched)                                   */
     double* history;     /* nullable DEVICE array of maxit+1 doubles: history[i] =
                             ||r_i|| / ||r_0|| after i iterations (history[0] = 1)           */
 } pbcgs_opts;
@@ -377,6 +386,21 @@ int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts*
  */
 int pbcgs_tune_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const double* const* b,
                        const pbcgs_opts* opts, int32_t iters, pbcgs_tune_report* rep);
+
+/*
+ * Test hook for the residual replacement of Section 4.2.  After iteration
+ * `iter` of later binary64 PBCGS_PBICGSTAB and PBCGS_PBICGSTAB_RR solves on
+ * ctx -- once that iteration's reductions are taken, before the next one
+ * starts -- every entry of the recursive residual r_{iter+1} is multiplied by
+ * `scale` (one rounding each; r^ is left alone).  The recursive residual then
+ * departs from b - A x, as accumulated rounding makes it do, and the next
+ * replacement must bring the two together again.  iter = -1 switches the hook
+ * off (the default); scale must be finite.  While the hook is on, solves launch
+ * their kernels directly (no HIP graph), and pbcgs_solve of another variant
+ * or of the precision form, and pbcgs_solve_batched, return ERR_UNSUPPORTED.
+ * The setting stays on the context until changed.
+ */
+int pbcgs_debug_perturb(pbcgs_ctx_t ctx, int32_t iter, double scale);
 
 /*
  * Workload builder (not part of the method): assembles on the device the

@@ -26,6 +26,7 @@ FLAG_TIME_KERNELS = 2  # time the two fused kernels of each iteration with event
 FLAG_ALPHA_EQ5 = 4     # alpha_{i+1} of the pipelined variants by eq. (5) instead of eq. (3)
 FLAG_INDEX32 = 8       # read the int32 columns even where the operator holds a compact copy
 FLAG_NO_DIA = 16       # read the CSR arrays even where the operator has a diagonal layout
+FLAG_POISON = 32       # test hook: NaN-fill the workspace before the solve writes it
 
 
 class Opts(ctypes.Structure):
@@ -105,6 +106,7 @@ _SIGNATURES = {
     "pbcgs_tune": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(Opts), _i32, ctypes.POINTER(TuneReport)]),
     "pbcgs_tune_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(Opts),
                                           _i32, ctypes.POINTER(TuneReport)]),
+    "pbcgs_debug_perturb": (ctypes.c_int, [_vp, _i32, _f64]),
     "pbcgs_convdiff_nnz": (_i64, [_i32, _i32, _i32]),
     "pbcgs_assemble_convdiff": (ctypes.c_int, [_vp, _i32, _i32, _i32, ctypes.POINTER(_f64), _vp, _f64,
                                                _vp, _vp, _vp]),

@@ -17,6 +17,7 @@
 #include "../../include/pbcgs.h"
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "debug.hpp"
 
 using namespace pbcgs;
 
@@ -128,6 +129,12 @@ struct pbcgs_ctx_s {
   unsigned char* scratch = nullptr;  // device address of this device's `scratch` (nullptr: unavailable)
   std::string scratch_err;
   bool noalloc = false;              // inside pbcgs_solve_noalloc: nothing may be allocated
+  // test hooks: NaN-fill the workspace before a solve writes it (opts.flags
+  // bit 5, for the duration of one call); scale the recursive residual after
+  // one iteration (pbcgs_debug_perturb; -1 = off)
+  bool poison = false;
+  int32_t perturb_iter = -1;
+  double perturb_scale = 1.0;
 };
 
 struct pbcgs_op_s {
@@ -260,6 +267,21 @@ Args base_args(pbcgs_ctx_t ctx, const Shape& sh) {
 }
 
 double* part_buf(pbcgs_ctx_t ctx, int which) { return ctx->part + (size_t)which * kMaxD * kMaxG; }
+
+// With the poisoning hook on, fills `bytes` of a workspace buffer with NaN
+// bits (the stream orders it before the kernels that write the buffer).
+void poison(pbcgs_ctx_t ctx, void* p, size_t bytes) {
+  if (!ctx->poison || !p || bytes < 4) return;
+  const int64_t words = (int64_t)(bytes / 4);
+  k_poison<<<debug_blocks(words), kDebugWG, 0, ctx->stream>>>(static_cast<uint32_t*>(p), words);
+}
+
+// Switches the poisoning hook on for one call (off again on every return).
+struct PoisonScope {
+  pbcgs_ctx_t c;
+  PoisonScope(pbcgs_ctx_t c_, bool on) : c(c_) { c->poison = on; }
+  ~PoisonScope() { c->poison = false; }
+};
 
 int ensure_ws(pbcgs_ctx_t ctx, size_t doubles) {
   if (ctx->ws_cap >= doubles) return PBCGS_SUCCESS;
@@ -686,6 +708,9 @@ struct Driver {
         }
       });
     }
+    // test hook: r_{i+1} scaled after the iteration's reductions were taken
+    // (the next kernels read the scaled r; the state is not touched)
+    if (i == ctx->perturb_iter) k_scale_vec<<<debug_blocks(a.n), kDebugWG, 0, s>>>(a.r, a.n, ctx->perturb_scale);
   }
 
   // Launch count of iteration i (the schedule of iteration()).
@@ -802,6 +827,7 @@ struct Driver {
     if (o.flags & 2) return false;
     if (o.variant >= PBCGS_CA_BICGSTAB) return false;
     if (o.maxit > 200000) return false;
+    if (ctx->perturb_iter >= 0) return false;
     if (env_int("PBCGS_PERSIST", 0) != 1) return false;
     if (ctx->coop < 0) {
       int v = 0;
@@ -854,7 +880,7 @@ struct Driver {
   int run(pbcgs_info* info) {
     if (use_persistent()) return run_persistent(info);
     // graphs are instantiated (allocated) on first use: never without allocation
-    const bool use_graph = !(o.flags & 1) && !(o.flags & 2) && !ctx->noalloc;
+    const bool use_graph = !(o.flags & 1) && !(o.flags & 2) && !ctx->noalloc && ctx->perturb_iter < 0;
     timing = (o.flags & 2) != 0 && !ctx->noalloc;
     const int check = o.check_every > 0 ? o.check_every : (a.n >= (1 << 20) ? 8 : 32);
     hipStream_t s = ctx->stream;
@@ -1379,6 +1405,16 @@ int pbcgs_ctx_create(int device, void* hip_stream, pbcgs_ctx_t* out) {
   return PBCGS_SUCCESS;
 }
 
+// Test hook of the residual replacement (see include/pbcgs.h).
+int pbcgs_debug_perturb(pbcgs_ctx_t ctx, int32_t iter, double scale) {
+  if (!ctx) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "ctx is NULL");
+  if (iter < -1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "iter must be -1 (off) or an iteration index");
+  if (!std::isfinite(scale)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "scale must be finite");
+  ctx->perturb_iter = iter;
+  ctx->perturb_scale = scale;
+  return PBCGS_SUCCESS;
+}
+
 int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
   if (!ctx) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "ctx is NULL");
   DeviceGuard guard(ctx->device);
@@ -1585,6 +1621,7 @@ int dia_operator(pbcgs_ctx_t ctx, pbcgs_op_t A, int pc_fold, const double* dv, d
   const int rc = ensure_dia(ctx, (size_t)A->ndia * (size_t)ld * sizeof(V), slot);
   if (rc != PBCGS_SUCCESS) return rc;
   V* buf = static_cast<V*>(ctx->dia[slot]);
+  poison(ctx, buf, (size_t)A->ndia * (size_t)ld * sizeof(V));
   const CsrOp op{A->rp, A->ci, A->va, A->n};
   const int g = (A->n + 63) / 64;
   if (pc_fold == PC_VEC) k_dia_fill<PC_VEC, V><<<g, 64, 0, ctx->stream>>>(op, A->n, A->ddoff, A->ndia, ld, buf, dv, ds);
@@ -1841,16 +1878,21 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
   if (o.maxit < 0 || !(o.tol >= 0.0)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad maxit or tol");
   if (o.variant == PBCGS_PBICGSTAB_RR && o.rr_period < 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad rr_period");
   if ((const void*)b == (const void*)x) return fail(ctx, PBCGS_ERR_INVALID_ARG, "b and x must not overlap");
+  if (ctx->perturb_iter >= 0 && (mp || (o.variant != PBCGS_PBICGSTAB && o.variant != PBCGS_PBICGSTAB_RR)))
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the residual perturbation hook applies to binary64 p-BiCGStab only");
   DeviceGuard guard(ctx->device);
   Shape sh;
   if (!make_shape(A->n, &sh, A->tuned_R[o.variant][mp ? 1 : 0]))
     return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows");
   std::memset(info, 0, sizeof *info);
+  PoisonScope poison_scope(ctx, (o.flags & 32) != 0);
 
   const size_t np = padded(A->n);
   const int nvec = 14;
   int rc = ensure_ws(ctx, np * nvec);
   if (rc != PBCGS_SUCCESS) return rc;
+  poison(ctx, ctx->ws, np * nvec * sizeof(double));
+  poison(ctx, ctx->part, (size_t)PB_COUNT * kMaxD * kMaxG * sizeof(double));
   Args a = base_args(ctx, sh);
   a.hist = o.history;
   a.b = b;
@@ -1931,10 +1973,12 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     if (folded && A->kind == OP_CSR && !use_dia) {
       rc = ensure_ahat(ctx, (size_t)A->nnz);
       if (rc != PBCGS_SUCCESS) return rc;
+      poison(ctx, ctx->ahat, (size_t)A->nnz * sizeof(double));
     }
     if (A->kind == OP_CSR && !use_dia) {
       rc = ensure_a32(ctx, (size_t)A->nnz);
       if (rc != PBCGS_SUCCESS) return rc;
+      poison(ctx, ctx->a32, (size_t)A->nnz * sizeof(float));
     }
     return with_op(A, [&](auto op) -> int {
       auto run_mp = [&](auto op32, auto op64) -> int {
@@ -1992,6 +2036,7 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     if (A->kind == OP_CSR && !use_dia) {
       rc = ensure_ahat(ctx, (size_t)A->nnz);
       if (rc != PBCGS_SUCCESS) return rc;
+      poison(ctx, ctx->ahat, (size_t)A->nnz * sizeof(double));
     }
     return with_op(A, [&](auto op) -> int {
       auto run_folded = [&](auto fop) -> int {
@@ -2199,6 +2244,8 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
   if (o.maxit < 0 || !(o.tol >= 0.0)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad maxit or tol");
   if (o.variant == PBCGS_PBICGSTAB_RR && o.rr_period < 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad rr_period");
   if (o.history) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "batched solves keep no history");
+  if (ctx->perturb_iter >= 0)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the residual perturbation hook applies to single solves only");
   int gcap = env_int("PBCGS_BATCH_GCAP", ctx->batch_gcap > 0 ? ctx->batch_gcap : 64);
   if (gcap < 1 || gcap > kMaxG) gcap = 64;
   std::vector<SysDesc> desc((size_t)nsys);
@@ -2262,6 +2309,10 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
   if (rc == PBCGS_SUCCESS) rc = grow(ctx, ctx->bpart, ctx->bpart_cap, (size_t)PB_COUNT * kMaxD * totalG, "partials");
   if (rc == PBCGS_SUCCESS && dia) rc = grow(ctx, ctx->bdia, ctx->bdia_cap, dianeed, "diagonal-layout values");
   if (rc != PBCGS_SUCCESS) return rc;
+  PoisonScope poison_scope(ctx, (o.flags & 32) != 0);
+  poison(ctx, ctx->bws, wsneed * sizeof(double));
+  poison(ctx, ctx->bpart, (size_t)PB_COUNT * kMaxD * (size_t)totalG * sizeof(double));
+  if (dia) poison(ctx, ctx->bdia, dianeed * sizeof(double));
   if (ctx->bhst_cap < nst) {
     if (ctx->bhst) { (void)hipStreamSynchronize(ctx->stream); (void)hipHostFree(ctx->bhst); ctx->bhst = nullptr; }
     ctx->bhst_cap = 0;

@@ -54,9 +54,17 @@ def _check_vec(t: torch.Tensor, n: int, name: str, dtype=torch.float64):
 
 
 class Context:
-    """A library context bound to one device and one HIP stream."""
+    """A library context bound to one device and one HIP stream.
+
+    The library requires a context's operators to be destroyed before the
+    context (``pbcgs_op_destroy`` uses it).  Python may finalize the two in
+    either order when they are garbage in one reference cycle, so the
+    context counts its live operators and :meth:`close` destroys it only
+    once the last of them is closed."""
 
     def __init__(self, device: int | None = None, stream: torch.cuda.Stream | None = None):
+        self._live_ops = 0
+        self._closing = False
         if device is None:
             device = torch.cuda.current_device()
         self.device = int(device)
@@ -69,9 +77,15 @@ class Context:
         self.handle = h
 
     def close(self):
-        if getattr(self, "handle", None):
+        self._closing = True
+        if getattr(self, "_live_ops", 0) == 0 and getattr(self, "handle", None):
             L.lib().pbcgs_ctx_destroy(self.handle)
             self.handle = None
+
+    def _op_closed(self):
+        self._live_ops -= 1
+        if self._closing and self._live_ops == 0:
+            self.close()
 
     def __del__(self):
         try:
@@ -81,6 +95,13 @@ class Context:
 
     def error(self) -> str:
         return L.last_error(self.handle)
+
+    def debug_perturb(self, iteration: int = -1, scale: float = 1.0) -> None:
+        """Test hook of the residual replacement (Section 4.2): later binary64
+        p-BiCGStab solves on this context multiply the recursive residual
+        r_{iteration+1} by ``scale`` at the end of iteration ``iteration``,
+        after its reductions.  ``iteration=-1`` switches it off."""
+        L.check(L.lib().pbcgs_debug_perturb(self.handle, int(iteration), float(scale)), self.handle)
 
 
 _contexts: dict = {}
@@ -104,6 +125,7 @@ class Operator:
     def __init__(self, ctx: Context, handle, n: int, keep: tuple, kind: str):
         self.ctx = ctx
         self.handle = handle
+        ctx._live_ops += 1
         self.n = n
         self._keep = keep  # the borrowed device arrays stay alive with the operator
         self.kind = kind
@@ -132,6 +154,7 @@ class Operator:
         if getattr(self, "handle", None):
             L.lib().pbcgs_op_destroy(self.handle)
             self.handle = None
+            self.ctx._op_closed()
 
     def __del__(self):
         try:
@@ -266,24 +289,26 @@ def solve(A: Operator, b: torch.Tensor, x0: torch.Tensor | None = None, *, varia
           precond: str | None = None, dinv: torch.Tensor | None = None, tol: float = 1e-8, maxit: int = 2000,
           rr_period: int = 50, rr_max: int = -1, history: bool = False, check_every: int = 0,
           graph: bool = True, time_kernels: bool = False, out: torch.Tensor | None = None,
-          precision: str = "fp64", alpha_form: int = 3, index32: bool = False, diagonal_layout: bool = True):
+          precision: str = "fp64", alpha_form: int = 3, index32: bool = False, diagonal_layout: bool = True,
+          poison: bool = False):
     """Solve A x = b; returns (x, SolveInfo).  x0 defaults to zero; ``out``
     (optional) receives the iterate in place of a new tensor.  ``alpha_form``
     5 takes alpha_{i+1} of the pipelined variants from eq. (5) instead of
     eq. (3) (Section 3.1).  ``index32`` reads the int32 column indices even
     where the operator holds a compact copy; ``diagonal_layout=False`` reads
     the CSR arrays even where the operator has a diagonal layout (same
-    results either way)."""
+    results either way).  ``poison`` (a test hook) fills the workspace with
+    NaN bits before the solve writes it."""
     return _solve(L.lib().pbcgs_solve, A, b, x0, variant=variant, precond=precond, dinv=dinv, tol=tol,
                   maxit=maxit, rr_period=rr_period, rr_max=rr_max, history=history, check_every=check_every,
                   graph=graph, time_kernels=time_kernels, out=out, precision=precision, alpha_form=alpha_form,
-                  index32=index32, diagonal_layout=diagonal_layout)
+                  index32=index32, diagonal_layout=diagonal_layout, poison=poison)
 
 
 def solve_noalloc(A: Operator, b: torch.Tensor, x: torch.Tensor, *, variant: str = "pbicgstab_rr",
                   precond: str | None = None, dinv: torch.Tensor | None = None, tol: float = 1e-8,
                   maxit: int = 2000, rr_period: int = 50, rr_max: int = -1, history: torch.Tensor | None = None,
-                  check_every: int = 0, alpha_form: int = 3, index32: bool = False):
+                  check_every: int = 0, alpha_form: int = 3, index32: bool = False, poison: bool = False):
     """``pbcgs_solve_noalloc``: the binary64 solve with every device buffer
     taken from the library's static scratch array, for callers that cannot
     allocate.  ``x`` holds x_0 and receives the iterate in place; ``history``
@@ -292,12 +317,12 @@ def solve_noalloc(A: Operator, b: torch.Tensor, x: torch.Tensor, *, variant: str
     return _solve(L.lib().pbcgs_solve_noalloc, A, b, None, variant=variant, precond=precond, dinv=dinv, tol=tol,
                   maxit=maxit, rr_period=rr_period, rr_max=rr_max, history=history, check_every=check_every,
                   graph=False, time_kernels=False, out=x, keep_x=True, precision="fp64", alpha_form=alpha_form,
-                  index32=index32)
+                  index32=index32, poison=poison)
 
 
 def _solve(entry, A: Operator, b: torch.Tensor, x0, *, variant, precond, dinv, tol, maxit, rr_period, rr_max,
            history, check_every, graph, time_kernels, out, precision, alpha_form, index32, keep_x=False,
-           diagonal_layout=True):
+           diagonal_layout=True, poison=False):
     _check_vec(b, A.n, "b")
     _check_alpha_form(alpha_form)
     if variant not in VARIANTS:
@@ -336,7 +361,7 @@ def _solve(entry, A: Operator, b: torch.Tensor, x0, *, variant, precond, dinv, t
     o.check_every = int(check_every)
     o.flags = ((0 if graph else L.FLAG_DIRECT) | (L.FLAG_TIME_KERNELS if time_kernels else 0)
                | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0) | (L.FLAG_INDEX32 if index32 else 0)
-               | (0 if diagonal_layout else L.FLAG_NO_DIA))
+               | (0 if diagonal_layout else L.FLAG_NO_DIA) | (L.FLAG_POISON if poison else 0))
     o.history = hist.data_ptr() if hist is not None else None
     info = L.Info()
     L.check(entry(A.ctx.handle, A.handle, _ptr(b), _ptr(x), _ptr(dinv), ctypes.byref(o), ctypes.byref(info)),
@@ -350,7 +375,8 @@ def _solve(entry, A: Operator, b: torch.Tensor, x0, *, variant, precond, dinv, t
 
 def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str = "pbicgstab_rr", tol: float = 1e-8,
                   maxit: int = 2000, rr_period: int = 50, rr_max: int = -1, check_every: int = 0, graph: bool = True,
-                  outs: list | None = None, alpha_form: int = 3, index32: bool = False, diagonal_layout: bool = True):
+                  outs: list | None = None, alpha_form: int = 3, index32: bool = False, diagonal_layout: bool = True,
+                  poison: bool = False):
     """Solve the independent systems ops[k] x_k = bs[k] in one batched call
     (CSR operators of one context, no preconditioner, binary64).  Returns
     (xs, infos); each system's result equals its own :func:`solve` bit for bit.
@@ -392,7 +418,8 @@ def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str 
     o.rr_max = int(rr_max)
     o.check_every = int(check_every)
     o.flags = ((0 if graph else L.FLAG_DIRECT) | (L.FLAG_ALPHA_EQ5 if alpha_form == 5 else 0)
-               | (L.FLAG_INDEX32 if index32 else 0) | (0 if diagonal_layout else L.FLAG_NO_DIA))
+               | (L.FLAG_INDEX32 if index32 else 0) | (0 if diagonal_layout else L.FLAG_NO_DIA)
+               | (L.FLAG_POISON if poison else 0))
     o.history = None
     VP = ctypes.c_void_p * nsys
     hs = VP(*[A.handle.value for A in ops])
