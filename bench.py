@@ -106,6 +106,11 @@ def parse():
     p.add_argument("--configs", default="c1,c3", help="comma list of the configs the configs leg runs")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run a plain 256 MiB device copy (to calibrate HBM byte counters)")
+    p.add_argument("--tune-cache", default=os.environ.get("PBCGS_TUNE_CACHE",
+                                                           os.path.join(os.path.expanduser("~"), ".cache", "pbcgs",
+                                                                        "tune.json")),
+                   help="JSON file of tuned launch shapes: read before tuning, written after ('' = none)")
+    p.add_argument("--retune", action="store_true", help="tune every leg even where the cache holds its shape")
     p.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)  # the oracle timing process
     return p.parse_args()
 
@@ -335,13 +340,34 @@ def main():
 
     common = dict(tol=w.tol, maxit=w.maxit, rr_period=w.rr_period)
     # launch shapes from the autotuner (never change a result), kept on the
-    # operator per variant: each leg is tuned for its own variant and
-    # preconditioner form before it is timed
+    # operator per variant and read path and in the library's launch-shape
+    # cache: each leg is tuned for its own variant and preconditioner form
+    # before it is timed, unless the cache file already holds its shape
     shapes = {}
+    shape_source = {}
+    if args.tune_cache:
+        try:
+            n_loaded = solver.load_tune_cache(args.tune_cache)
+            progress(f"launch-shape cache {args.tune_cache}: {n_loaded} entries")
+        except (OSError, ValueError) as e:
+            progress(f"launch-shape cache {args.tune_cache} not read: {e}")
 
     def tune_for(op, variant, precond, label, **extra):
+        cached = None if args.retune else solver.tuned_shape(
+            op, variant, extra.get("precision", "fp64"), extra.get("index32", False),
+            extra.get("diagonal_layout", True))
+        if cached is not None:
+            shapes[label] = cached
+            shape_source[label] = "cache"
+            return {"best": cached}
         rep_ = solver.tune(op, b, iters=40, variant=variant, precond=precond, rr_period=w.rr_period, **extra)
         shapes[label] = rep_["best"]
+        shape_source[label] = "measured"
+        if args.tune_cache:
+            try:
+                solver.save_tune_cache(args.tune_cache)
+            except OSError as e:
+                progress(f"launch-shape cache {args.tune_cache} not written: {e}")
         return rep_
 
     tune = tune_for(A, "pbicgstab_rr", "jacobi_folded", "pipe")
@@ -815,6 +841,7 @@ def main():
         "syncs_per_iter": info.syncs_per_iter if info else None,
         "autotuned_rows_per_wave_blocks": tune["best"],
         "autotuned_rows_per_wave_blocks_per_leg": shapes,
+        "launch_shape_source_per_leg": shape_source,
     }
 
     def leg_summary(key, variant, stencil, folded, index_bytes=ib, dia=nd):

@@ -155,6 +155,9 @@ typedef struct {
                                 x, r, u update; Chronopoulos & Gear: the update and
                                 w = A u; p-CG: its one kernel (slot 0)                    */
     int32_t kernel_calls[2]; /* launches timed for kernel_ms                              */
+    int32_t rows_per_wave_blocks; /* the launch shape that ran: 64-row blocks per wave,  */
+    int32_t workgroups;           /* and workgroups of 256 threads (the system's own in a
+                                     batch)                                               */
 } pbcgs_info;
 
 /* Create a context on HIP device `device` working on stream `hip_stream`
@@ -363,10 +366,11 @@ typedef struct {
  * and the read-path bits are kept: graph replay, no kernel timing) for
  * every rows-per-wave block count R whose grid fits -- once to capture the
  * graphs, then three times, the fastest counting -- and keeps the fastest R
- * on the operator for the variant and precision of opts (each variant's
- * kernels have their own best shape); later pbcgs_solve calls on A of that variant and precision use it
- * (the environment variables PBCGS_R and PBCGS_GTARGET still take
- * precedence).  An unknown variant or precision is PBCGS_ERR_INVALID_ARG.
+ * on the operator for the variant, precision and read path of opts (each
+ * variant's kernels have their own best shape) and in the launch-shape cache
+ * below; later pbcgs_solve calls on A, or on another operator of the same
+ * cache key, with that variant, precision and read path use it (the environment variables PBCGS_R
+ * and PBCGS_GTARGET still take precedence).  An unknown variant or precision is PBCGS_ERR_INVALID_ARG.
  * The shape never changes a result: every reduction is the same pairwise
  * tree whatever R is.
  */
@@ -386,6 +390,53 @@ int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts*
  */
 int pbcgs_tune_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, const double* const* b,
                        const pbcgs_opts* opts, int32_t iters, pbcgs_tune_report* rep);
+
+/*
+ * Process-wide launch-shape cache.  Every shape pbcgs_tune keeps is also
+ * recorded here under a key: the device (its architecture name and compute
+ * unit count), the library build that measured it, the operator's rows,
+ * stored non-zeros (CSR; 0 for matrix-free operators) and kind, the variant,
+ * the precision and the read path.  A pbcgs_solve on an operator that has no
+ * tuned shape of its own for these takes the cached shape of its key, so
+ * a new operator of the same size and kind (values changed, say) is not tuned
+ * again; PBCGS_R and PBCGS_GTARGET still take precedence.  The shape never
+ * changes a result.  Entries can be read out and put back (to keep them in a
+ * file between processes: the Python layer's save_tune_cache and
+ * load_tune_cache do that as JSON).  The cache is shared by every context of
+ * the process and guarded by a mutex; it holds single-system shapes only
+ * (pbcgs_tune_batched keeps its cap on the context).
+ */
+typedef struct {
+    char device[64];     /* "<architecture> <compute units>cu", NUL-terminated        */
+    char build[32];      /* the library build that measured it, NUL-terminated       */
+    int64_t nnz;         /* stored non-zeros of a CSR operator, 0 for matrix-free     */
+    int32_t n;           /* rows                                                     */
+    int32_t op_kind;     /* 0 CSR, 1 5-point stencil, 2 7-point stencil,
+                            3 27-point matrix-free (pbcgs_op_convdiff27)             */
+    int32_t variant;     /* PBCGS_BICGSTAB .. PBCGS_PIPE_CG                          */
+    int32_t precision;   /* PBCGS_FP64 or PBCGS_FP32_RR64                            */
+    int32_t read_path;   /* 0 the operator's default (its diagonal layout or compact
+                            columns where it has them), 1 the CSR arrays
+                            (opts.flags bit 4), 2 the int32 columns (bit 3)          */
+    int32_t best;        /* the shape: 64-row blocks per wave, a power of two whose
+                            grid of ceil(n / (256 best)) workgroups is at most 1024 */
+} pbcgs_tune_entry;
+
+/* Number of cache entries. */
+int32_t pbcgs_tune_cache_size(void);
+/* Copy entry i (0 <= i < size) to *out (host struct); ERR_INVALID_ARG otherwise. */
+int pbcgs_tune_cache_get(int32_t i, pbcgs_tune_entry* out);
+/* Add an entry, or replace the shape of the entry with the same key.  A key
+ * field out of range, an unterminated string or a shape that does not fit n
+ * is ERR_INVALID_ARG (the cache is then unchanged). */
+int pbcgs_tune_cache_put(const pbcgs_tune_entry* e);
+/* Remove every entry. */
+int pbcgs_tune_cache_clear(void);
+/* Fill *out with the key of (ctx's device, this build, A, variant, precision,
+ * the read path that opts.flags `flags` select) and out->best with the cached
+ * shape of that key, or 0 when there is none. */
+int pbcgs_tune_cache_key(pbcgs_ctx_t ctx, pbcgs_op_t A, int32_t variant, int32_t precision, int32_t flags,
+                         pbcgs_tune_entry* out);
 
 /*
  * Test hook for the residual replacement of Section 4.2.  After iteration

@@ -55,6 +55,8 @@ class Info(ctypes.Structure):
         ("ms", ctypes.c_double),
         ("kernel_ms", ctypes.c_double * 2),
         ("kernel_calls", ctypes.c_int32 * 2),
+        ("rows_per_wave_blocks", ctypes.c_int32),
+        ("workgroups", ctypes.c_int32),
     ]
 
 
@@ -65,6 +67,20 @@ class TuneReport(ctypes.Structure):
         ("cand", ctypes.c_int32 * 12),
         ("ms_per_iter", ctypes.c_double * 12),
         ("best_ms_per_iter", ctypes.c_double),
+    ]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_char * 64),
+        ("build", ctypes.c_char * 32),
+        ("nnz", ctypes.c_int64),
+        ("n", ctypes.c_int32),
+        ("op_kind", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("read_path", ctypes.c_int32),
+        ("best", ctypes.c_int32),
     ]
 
 
@@ -107,6 +123,11 @@ _SIGNATURES = {
     "pbcgs_tune_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(Opts),
                                           _i32, ctypes.POINTER(TuneReport)]),
     "pbcgs_debug_perturb": (ctypes.c_int, [_vp, _i32, _f64]),
+    "pbcgs_tune_cache_size": (_i32, []),
+    "pbcgs_tune_cache_get": (ctypes.c_int, [_i32, ctypes.POINTER(TuneEntry)]),
+    "pbcgs_tune_cache_put": (ctypes.c_int, [ctypes.POINTER(TuneEntry)]),
+    "pbcgs_tune_cache_clear": (ctypes.c_int, []),
+    "pbcgs_tune_cache_key": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, ctypes.POINTER(TuneEntry)]),
     "pbcgs_convdiff_nnz": (_i64, [_i32, _i32, _i32]),
     "pbcgs_assemble_convdiff": (ctypes.c_int, [_vp, _i32, _i32, _i32, ctypes.POINTER(_f64), _vp, _f64,
                                                _vp, _vp, _vp]),

@@ -135,6 +135,7 @@ struct pbcgs_ctx_s {
   bool poison = false;
   int32_t perturb_iter = -1;
   double perturb_scale = 1.0;
+  std::string devkey;  // "<architecture> <compute units>cu": the device part of launch-shape cache keys
 };
 
 struct pbcgs_op_s {
@@ -151,8 +152,9 @@ struct pbcgs_op_s {
   const double* kappa = nullptr;
   double hb[3] = {0, 0, 0};
   double shift = 0.0;
-  // rows-per-wave blocks chosen by pbcgs_tune per variant and precision (0: default shape)
-  int32_t tuned_R[PBCGS_PIPE_CG + 1][2] = {};
+  // rows-per-wave blocks chosen by pbcgs_tune per variant, precision and read
+  // path (read_path(); 0: default shape)
+  int32_t tuned_R[PBCGS_PIPE_CG + 1][2][3] = {};
   // arrays the library allocated for this operator (a transpose), freed with it
   int32_t* own_rp = nullptr;
   int32_t* own_ci = nullptr;
@@ -228,6 +230,75 @@ bool make_shape(int32_t n, Shape* sh, int prefer_R = 0) {
     }
   }
   return false;
+}
+
+// ---------------------------------------------------------------------------
+// Process-wide launch-shape cache (pbcgs_tune_entry in include/pbcgs.h).
+// ---------------------------------------------------------------------------
+// The build that measured an entry: a rebuilt library may prefer other shapes.
+const char kBuildId[] = __DATE__ " " __TIME__;
+
+struct TuneCache {
+  std::mutex mu;
+  std::vector<pbcgs_tune_entry> entries;
+};
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
+
+bool same_key(const pbcgs_tune_entry& a, const pbcgs_tune_entry& b) {
+  return std::strncmp(a.device, b.device, sizeof a.device) == 0 &&
+         std::strncmp(a.build, b.build, sizeof a.build) == 0 && a.n == b.n && a.nnz == b.nnz &&
+         a.op_kind == b.op_kind && a.variant == b.variant && a.precision == b.precision &&
+         a.read_path == b.read_path;
+}
+
+// The read path of a solve, part of a tuned shape's key: 0 the operator's
+// default (its diagonal layout or compact columns where it has them), 1 the
+// CSR arrays (opts.flags bit 4), 2 the caller's int32 columns (bit 3).
+int32_t read_path(int32_t flags) { return (flags & 8) ? 2 : (flags & 16) ? 1 : 0; }
+
+// The shape a cache entry holds fits its row count: a power of two R whose
+// grid has at most kMaxG workgroups.
+bool shape_fits(int32_t n, int32_t R) {
+  if (n <= 0 || R < 1 || R > kMaxR || (R & (R - 1)) != 0) return false;
+  return ((int64_t)n + 256 * (int64_t)R - 1) / (256 * (int64_t)R) <= kMaxG;
+}
+
+// The cached shape for a key (best ignored), or 0.
+int32_t cache_find(const pbcgs_tune_entry& key) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  for (const auto& e : c.entries)
+    if (same_key(e, key)) return e.best;
+  return 0;
+}
+
+void cache_store(const pbcgs_tune_entry& e) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  for (auto& x : c.entries)
+    if (same_key(x, e)) {
+      x.best = e.best;
+      return;
+    }
+  c.entries.push_back(e);
+}
+
+// The cache key of (device, build, operator, variant, precision, read path); best = 0.
+pbcgs_tune_entry make_key(pbcgs_ctx_t ctx, const pbcgs_op_s* A, int32_t variant, int32_t precision, int32_t path) {
+  pbcgs_tune_entry e;
+  std::memset(&e, 0, sizeof e);
+  std::snprintf(e.device, sizeof e.device, "%s", ctx->devkey.c_str());
+  std::snprintf(e.build, sizeof e.build, "%s", kBuildId);
+  e.n = A->n;
+  e.nnz = (A->kind == OP_CSR) ? A->nnz : 0;
+  e.op_kind = A->kind;
+  e.variant = variant;
+  e.precision = precision;
+  e.read_path = path;
+  return e;
 }
 
 // Kernel boundaries of one regular iteration of each variant.
@@ -987,6 +1058,8 @@ struct Driver {
     info->syncs_per_iter = syncs_per_iteration(o.variant);
     info->relres_rec = fin.relres;
     info->ms = ms;
+    info->rows_per_wave_blocks = a.R;
+    info->workgroups = a.G;
     for (int k = 0; k < 2; ++k) {
       double tot = 0.0;
       for (auto& pr : tev[k]) {
@@ -1401,6 +1474,11 @@ int pbcgs_ctx_create(int device, void* hip_stream, pbcgs_ctx_t* out) {
     pbcgs_ctx_destroy(c);
     return fail(nullptr, PBCGS_ERR_HIP, "context initialisation failed");
   }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess)
+    c->devkey = std::string(prop.gcnArchName) + " " + std::to_string(prop.multiProcessorCount) + "cu";
+  else
+    c->devkey = "device" + std::to_string(device);
   *out = c;
   return PBCGS_SUCCESS;
 }
@@ -1882,7 +1960,10 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     return fail(ctx, PBCGS_ERR_UNSUPPORTED, "the residual perturbation hook applies to binary64 p-BiCGStab only");
   DeviceGuard guard(ctx->device);
   Shape sh;
-  if (!make_shape(A->n, &sh, A->tuned_R[o.variant][mp ? 1 : 0]))
+  // the operator's own tuned shape, else one the cache holds for its key
+  int32_t prefer_R = A->tuned_R[o.variant][mp ? 1 : 0][read_path(o.flags)];
+  if (prefer_R == 0) prefer_R = cache_find(make_key(ctx, A, o.variant, o.precision, read_path(o.flags)));
+  if (!make_shape(A->n, &sh, prefer_R))
     return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows");
   std::memset(info, 0, sizeof *info);
   PoisonScope poison_scope(ctx, (o.flags & 32) != 0);
@@ -2338,9 +2419,15 @@ int pbcgs_solve_batched(pbcgs_ctx_t ctx, int32_t nsys, const pbcgs_op_t* A, cons
   HIP_TRY(ctx, hipMemcpyAsync(ctx->bsys, desc.data(), desc.size() * sizeof(SysDesc), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->bmap, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the host tables may go away after this
-  if (dia) return BatchDriver<DiaOpB>(ctx, o, nsys, (int32_t)totalG).run(infos);
-  if (compact) return BatchDriver<CsrOp16>(ctx, o, nsys, (int32_t)totalG).run(infos);
-  return BatchDriver<CsrOp>(ctx, o, nsys, (int32_t)totalG).run(infos);
+  const int st = dia       ? BatchDriver<DiaOpB>(ctx, o, nsys, (int32_t)totalG).run(infos)
+                 : compact ? BatchDriver<CsrOp16>(ctx, o, nsys, (int32_t)totalG).run(infos)
+                           : BatchDriver<CsrOp>(ctx, o, nsys, (int32_t)totalG).run(infos);
+  if (st >= 0)
+    for (int32_t k = 0; k < nsys; ++k) {
+      infos[k].rows_per_wave_blocks = desc[(size_t)k].R;
+      infos[k].workgroups = desc[(size_t)k].G;
+    }
+  return st;
 }
 
 // Autotuner of the launch shape (see include/pbcgs.h).
@@ -2361,7 +2448,7 @@ int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts*
   o.history = nullptr;
   o.flags = opts->flags & (4 | 8 | 16);  // keep the alpha form and the read path; graph replay, no timing
   o.check_every = 0;
-  int32_t& slot = A->tuned_R[o.variant][o.precision == PBCGS_FP32_RR64 ? 1 : 0];
+  int32_t& slot = A->tuned_R[o.variant][o.precision == PBCGS_FP32_RR64 ? 1 : 0][read_path(o.flags)];
   const int32_t saved = slot;
   double best = -1.0;
   int rc = PBCGS_SUCCESS;
@@ -2393,6 +2480,68 @@ int pbcgs_tune(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, const pbcgs_opts*
   }
   slot = rep->best;
   rep->best_ms_per_iter = best;
+  pbcgs_tune_entry e = make_key(ctx, A, o.variant, o.precision, read_path(o.flags));
+  e.best = rep->best;
+  cache_store(e);
+  return PBCGS_SUCCESS;
+}
+
+// The launch-shape cache (see include/pbcgs.h).
+int32_t pbcgs_tune_cache_size(void) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  return (int32_t)c.entries.size();
+}
+
+int pbcgs_tune_cache_get(int32_t i, pbcgs_tune_entry* out) {
+  if (!out) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "out is NULL");
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  if (i < 0 || (size_t)i >= c.entries.size()) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "no cache entry at this index");
+  *out = c.entries[(size_t)i];
+  return PBCGS_SUCCESS;
+}
+
+int pbcgs_tune_cache_put(const pbcgs_tune_entry* e) {
+  if (!e) return fail(nullptr, PBCGS_ERR_INVALID_ARG, "entry is NULL");
+  if (std::memchr(e->device, 0, sizeof e->device) == nullptr || std::memchr(e->build, 0, sizeof e->build) == nullptr)
+    return fail(nullptr, PBCGS_ERR_INVALID_ARG, "device and build must be NUL-terminated");
+  if (e->variant < PBCGS_BICGSTAB || e->variant > PBCGS_PIPE_CG ||
+      (e->precision != PBCGS_FP64 && e->precision != PBCGS_FP32_RR64) || e->op_kind < OP_CSR ||
+      e->op_kind > OP_CV27 || e->nnz < 0 || e->read_path < 0 || e->read_path > 2)
+    return fail(nullptr, PBCGS_ERR_INVALID_ARG, "bad variant, precision, operator kind, nnz or read path");
+  if (!shape_fits(e->n, e->best))
+    return fail(nullptr, PBCGS_ERR_INVALID_ARG, "best must be a power of two whose grid fits n rows");
+  pbcgs_tune_entry c;
+  std::memset(&c, 0, sizeof c);
+  std::memcpy(c.device, e->device, sizeof c.device);
+  std::memcpy(c.build, e->build, sizeof c.build);
+  c.nnz = e->nnz;
+  c.n = e->n;
+  c.op_kind = e->op_kind;
+  c.variant = e->variant;
+  c.precision = e->precision;
+  c.read_path = e->read_path;
+  c.best = e->best;
+  cache_store(c);
+  return PBCGS_SUCCESS;
+}
+
+int pbcgs_tune_cache_clear(void) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  c.entries.clear();
+  return PBCGS_SUCCESS;
+}
+
+int pbcgs_tune_cache_key(pbcgs_ctx_t ctx, pbcgs_op_t A, int32_t variant, int32_t precision, int32_t flags,
+                         pbcgs_tune_entry* out) {
+  if (!ctx || !A || !out) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
+  if (A->ctx != ctx) return fail(ctx, PBCGS_ERR_INVALID_ARG, "operator belongs to another context");
+  if (variant < PBCGS_BICGSTAB || variant > PBCGS_PIPE_CG || (precision != PBCGS_FP64 && precision != PBCGS_FP32_RR64))
+    return fail(ctx, PBCGS_ERR_INVALID_ARG, "unknown variant or precision");
+  *out = make_key(ctx, A, variant, precision, read_path(flags));
+  out->best = cache_find(*out);
   return PBCGS_SUCCESS;
 }
 

@@ -279,6 +279,7 @@ class SolveInfo:
     kernel_ms: tuple
     kernel_calls: tuple
     history: torch.Tensor | None = None
+    shape: tuple = (0, 0)  # the launch shape that ran: (64-row blocks per wave, workgroups)
 
     @property
     def status_name(self) -> str:
@@ -368,6 +369,7 @@ def _solve(entry, A: Operator, b: torch.Tensor, x0, *, variant, precond, dinv, t
             A.ctx.handle)
     si = SolveInfo(info.iters, info.n_rr, info.status, info.syncs_per_iter, info.relres_rec, info.relres_true,
                    info.ms, tuple(info.kernel_ms), tuple(info.kernel_calls))
+    si.shape = (int(info.rows_per_wave_blocks), int(info.workgroups))
     if hist is not None:
         si.history = hist[: info.iters + 1]
     return x, si
@@ -428,7 +430,8 @@ def solve_batched(ops: list, bs: list, x0s: list | None = None, *, variant: str 
     infos = (L.Info * nsys)()
     L.check(L.lib().pbcgs_solve_batched(ctx.handle, nsys, hs, bp, xp, ctypes.byref(o), infos), ctx.handle)
     out = [SolveInfo(i.iters, i.n_rr, i.status, i.syncs_per_iter, i.relres_rec, i.relres_true, i.ms,
-                     tuple(i.kernel_ms), tuple(i.kernel_calls)) for i in infos]
+                     tuple(i.kernel_ms), tuple(i.kernel_calls), shape=(int(i.rows_per_wave_blocks), int(i.workgroups)))
+           for i in infos]
     return xs, out
 
 
@@ -523,8 +526,8 @@ def _report(r) -> dict:
 
 def tune(A: Operator, b: torch.Tensor, iters: int = 20, **opts) -> dict:
     """Time `iters` iterations for each launch shape (rows-per-wave blocks R)
-    and keep the fastest on A for later solves of the same variant and
-    precision; returns the report.  ``index32`` / ``diagonal_layout=False``
+    and keep the fastest on A, and in the process-wide launch-shape cache,
+    for later solves of the same variant and precision; returns the report.  ``index32`` / ``diagonal_layout=False``
     time the solves on those read paths."""
     _check_vec(b, A.n, "b")
     o = _opts(**opts)
@@ -532,6 +535,111 @@ def tune(A: Operator, b: torch.Tensor, iters: int = 20, **opts) -> dict:
     L.check(L.lib().pbcgs_tune(A.ctx.handle, A.handle, _ptr(b), ctypes.byref(o), int(iters), ctypes.byref(r)),
             A.ctx.handle)
     return _report(r)
+
+
+OP_KINDS = {0: "csr", 1: "stencil5", 2: "stencil7", 3: "convdiff27"}
+READ_PATHS = {0: "default", 1: "csr_arrays", 2: "int32_columns"}
+_TUNE_CACHE_FORMAT = "pbcgs launch-shape cache"
+
+
+def _entry_dict(e) -> dict:
+    inv_v = {v: k for k, v in VARIANTS.items()}
+    inv_p = {v: k for k, v in PRECISIONS.items()}
+    return {"device": e.device.decode(), "build": e.build.decode(), "n": int(e.n), "nnz": int(e.nnz),
+            "operator": OP_KINDS[e.op_kind], "variant": inv_v[e.variant], "precision": inv_p[e.precision],
+            "read_path": READ_PATHS[e.read_path], "rows_per_wave_blocks": int(e.best)}
+
+
+def tune_cache() -> list:
+    """The process-wide launch-shape cache (``pbcgs_tune_entry``): one dict
+    per entry, keyed by device, library build, rows, non-zeros, operator kind,
+    variant and precision."""
+    lib = L.lib()
+    out = []
+    for i in range(lib.pbcgs_tune_cache_size()):
+        e = L.TuneEntry()
+        L.check(lib.pbcgs_tune_cache_get(i, ctypes.byref(e)))
+        out.append(_entry_dict(e))
+    return out
+
+
+def tune_cache_put(entry: dict) -> None:
+    """Add one entry (a dict as :func:`tune_cache` returns them)."""
+    kinds = {v: k for k, v in OP_KINDS.items()}
+    paths = {v: k for k, v in READ_PATHS.items()}
+    e = L.TuneEntry()
+    e.device = str(entry["device"]).encode()[:63]
+    e.build = str(entry["build"]).encode()[:31]
+    e.n = int(entry["n"])
+    e.nnz = int(entry["nnz"])
+    e.op_kind = kinds[entry["operator"]]
+    e.variant = VARIANTS[entry["variant"]]
+    e.precision = PRECISIONS[entry["precision"]]
+    e.read_path = paths[entry["read_path"]]
+    e.best = int(entry["rows_per_wave_blocks"])
+    L.check(L.lib().pbcgs_tune_cache_put(ctypes.byref(e)))
+
+
+def tune_cache_clear() -> None:
+    L.check(L.lib().pbcgs_tune_cache_clear())
+
+
+def tune_cache_key(A: Operator, variant: str = "pbicgstab_rr", precision: str = "fp64", index32: bool = False,
+                   diagonal_layout: bool = True) -> dict:
+    """A's cache key for this variant, precision and read path, as a dict
+    like :func:`tune_cache`'s entries; ``rows_per_wave_blocks`` holds the
+    cached shape, or 0 when the cache has none."""
+    flags = (L.FLAG_INDEX32 if index32 else 0) | (0 if diagonal_layout else L.FLAG_NO_DIA)
+    e = L.TuneEntry()
+    L.check(L.lib().pbcgs_tune_cache_key(A.ctx.handle, A.handle, VARIANTS[variant], PRECISIONS[precision], flags,
+                                         ctypes.byref(e)), A.ctx.handle)
+    return _entry_dict(e)
+
+
+def tuned_shape(A: Operator, variant: str = "pbicgstab_rr", precision: str = "fp64", index32: bool = False,
+                diagonal_layout: bool = True):
+    """The cached shape (rows-per-wave blocks) of A's key for this variant,
+    precision and read path, or None when the cache has none."""
+    best = tune_cache_key(A, variant, precision, index32, diagonal_layout)["rows_per_wave_blocks"]
+    return best if best > 0 else None
+
+
+def save_tune_cache(path: str) -> int:
+    """Write the cache to a JSON file; returns the number of entries."""
+    import json
+    import os
+
+    entries = tune_cache()
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump({"format": _TUNE_CACHE_FORMAT, "version": 1, "entries": entries}, f, indent=1)
+    os.replace(tmp, path)
+    return len(entries)
+
+
+def load_tune_cache(path: str) -> int:
+    """Put the entries of a JSON file written by :func:`save_tune_cache`
+    into the cache; returns how many were put (entries the library refuses
+    are skipped).  A missing file puts nothing."""
+    import json
+    import os
+
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("format") != _TUNE_CACHE_FORMAT or doc.get("version") != 1:
+        raise ValueError(f"{path} is not a launch-shape cache of this format")
+    put = 0
+    for entry in doc.get("entries", []):
+        try:
+            tune_cache_put(entry)
+            put += 1
+        except (L.PbcgsError, KeyError, TypeError, ValueError):
+            continue
+    return put
 
 
 def tune_batched(ops: list, bs: list, iters: int = 20, **opts) -> dict:

@@ -89,3 +89,72 @@ def test_tune_batched_on_complete_solves():
     for k, (A, b) in enumerate(zip(As, bs)):
         x_or, i_or = oracle.solve(A, b, algo=oracle.ALG_PBICGSTAB_RR, tol=1e-9, rr_period=17)
         assert infos[k].iters == i_or["iters"] and same(host(xs[k]), x_or)
+
+
+def test_tune_cache_serves_new_operators(tmp_path, monkeypatch):
+    """pbcgs_tune records its shape in the process-wide cache; a new operator
+    of the same key (rows, non-zeros, kind, variant, precision, read path)
+    runs the cached shape without tuning, another read path does not, and the
+    cache survives a JSON round trip.  Results never change."""
+    require_gpu()
+    monkeypatch.delenv("PBCGS_R", raising=False)
+    monkeypatch.delenv("PBCGS_GTARGET", raising=False)
+    A = oracle.assemble_workload(inputs.workload("c2", n=36))
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    bd = dev_t(b)
+    d = oracle.jacobi_dinv(A)
+    kw = dict(precond="jacobi_folded", rr_period=20)
+    x_or, i_or = oracle.solve_folded(A, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=d, tol=1e-10, rr_period=20)
+    solver.tune_cache_clear()
+    try:
+        _, i0 = solver.solve(csr_op(A), bd, variant="pbicgstab_rr", tol=1e-10, **kw)
+        default_R = i0.shape[0]
+        rep = solver.tune(csr_op(A), bd, iters=8, variant="pbicgstab_rr", **kw)
+        op = csr_op(A)  # a new operator: no shape of its own
+        key = solver.tune_cache_key(op, "pbicgstab_rr")
+        assert key["rows_per_wave_blocks"] == rep["best"]
+        assert key in solver.tune_cache()
+        x, info = solver.solve(op, bd, variant="pbicgstab_rr", tol=1e-10, **kw)
+        assert info.shape[0] == rep["best"]
+        assert info.iters == i_or["iters"] and same(host(x), x_or)
+        # a shape the tuner would not pick, put by hand, is the one that runs
+        alt = next(R for R in (1, 2, 4, 8, 16) if R not in (default_R, rep["best"]))
+        solver.tune_cache_put(dict(key, rows_per_wave_blocks=alt))
+        op2 = csr_op(A)
+        x, info = solver.solve(op2, bd, variant="pbicgstab_rr", tol=1e-10, **kw)
+        say(f"cache: default R {default_R}, tuned {rep['best']}, put {alt}, ran {info.shape}")
+        assert info.shape == (alt, (A.n + 256 * alt - 1) // (256 * alt))
+        assert info.iters == i_or["iters"] and same(host(x), x_or)
+        # another read path or variant has its own key
+        assert solver.tuned_shape(op2, "pbicgstab_rr", diagonal_layout=False) is None
+        assert solver.tuned_shape(op2, "bicgstab") is None
+        _, info = solver.solve(op2, bd, variant="pbicgstab_rr", tol=1e-10, diagonal_layout=False, **kw)
+        assert info.shape[0] == default_R
+        # JSON round trip
+        path = str(tmp_path / "tune.json")
+        assert solver.save_tune_cache(path) >= 1
+        solver.tune_cache_clear()
+        assert solver.tuned_shape(csr_op(A), "pbicgstab_rr") is None
+        solver.load_tune_cache(path)
+        op3 = csr_op(A)
+        assert solver.tuned_shape(op3, "pbicgstab_rr") == alt
+        x, info = solver.solve(op3, bd, variant="pbicgstab_rr", tol=1e-10, **kw)
+        assert info.shape[0] == alt and same(host(x), x_or)
+        # the environment still takes precedence
+        env_R = 8 if alt != 8 else 16
+        monkeypatch.setenv("PBCGS_R", str(env_R))
+        _, info = solver.solve(op3, bd, variant="pbicgstab_rr", tol=1e-10, **kw)
+        assert info.shape[0] == env_R
+    finally:
+        solver.tune_cache_clear()
+
+
+def test_batched_reports_each_systems_shape():
+    require_gpu()
+    systems = inputs.batch_systems(count=12, lo=8, hi=200)
+    As = [oracle.assemble(2, sy.n, 5, sy.beta) for sy in systems]
+    bs = [dev_t(oracle.spmv(A, inputs.batch_x_true(sy.k, A.n))) for sy, A in zip(systems, As)]
+    _, infos = solver.solve_batched([csr_op(A) for A in As], bs, variant="pbicgstab_rr", tol=1e-9)
+    for A, info in zip(As, infos):
+        R, G = info.shape
+        assert R >= 1 and (R & (R - 1)) == 0 and G == (A.n + 256 * R - 1) // (256 * R), (A.n, info.shape)
