@@ -337,6 +337,87 @@ struct DiaOpT {
     y0 = a0;
     y1 = a1;
   }
+
+  // Rows row .. row + 3 (row a multiple of 4) by one lane, for the kernels
+  // that take four rows per lane; nv of the four lie below n.  The four
+  // values of a diagonal are one 4-element load.  The four x values are one
+  // aligned 4-element load for an offset that is a multiple of 4, two aligned
+  // pairs for an offset of 2 modulo 4, else four single loads.  Each row's sum
+  // runs over its present diagonals in ascending order, as spmv's.
+  template <class X>
+  __device__ __forceinline__ void spmv4(int32_t row, int nv, const X* __restrict__ x, V (&y)[4]) const {
+    typedef V V4 __attribute__((ext_vector_type(4)));
+    typedef X X4 __attribute__((ext_vector_type(4)));
+    typedef X X2 __attribute__((ext_vector_type(2)));
+    int32_t rr[4];
+    uint32_t m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rr[k] = min(row + k, n - 1);
+    if (nv == 4) {
+      // row .. row + 3 < n: one aligned 16-byte load of the four masks
+      typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+      const U4 mm = *reinterpret_cast<const U4*>(&mask[row]);
+      m[0] = mm.x;
+      m[1] = mm.y;
+      m[2] = mm.z;
+      m[3] = mm.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) m[k] = (k < nv) ? mask[rr[k]] : 0u;
+    }
+    // a slot of four inside the layout (rows past n read a discarded copy of the last four)
+    const int32_t rv = min(row, (n - 1) & ~3);
+    V acc[4] = {V(0), V(0), V(0), V(0)};
+#pragma unroll 2
+    for (int d = 0; d < nd; ++d) {
+      bool p[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) p[k] = (m[k] >> d) & 1u;
+      const V4 v = load_nt(reinterpret_cast<const V4*>(&va[(int64_t)d * ld + rv]), std::integral_constant<bool, NT>());
+      const int32_t o = off[d];
+      X xs[4];
+      // a present entry's column lies in [0, n).  For an offset of 0 mod 4 with
+      // row + 3's entry present, row + o .. row + o + 3 lie in [0, n) (row + o is
+      // a multiple of 4 and row + 3 + o >= 0), an aligned four of the (at least
+      // 16-byte aligned) vector; likewise an offset of 2 mod 4 and row + 1's
+      // (row + 3's) entry for the aligned pair at row + o (row + o + 2).
+      if ((o & 3) == 0 && p[3]) {
+        const X4 q = *reinterpret_cast<const X4*>(&x[row + o]);
+        xs[0] = q.x;
+        xs[1] = q.y;
+        xs[2] = q.z;
+        xs[3] = q.w;
+      } else if ((o & 1) == 0) {
+        if (p[1]) {
+          const X2 q = *reinterpret_cast<const X2*>(&x[row + o]);
+          xs[0] = q.x;
+          xs[1] = q.y;
+        } else {
+          xs[0] = x[p[0] ? rr[0] + o : rr[0]];
+          xs[1] = x[rr[1]];
+        }
+        if (p[3]) {
+          const X2 q = *reinterpret_cast<const X2*>(&x[row + 2 + o]);
+          xs[2] = q.x;
+          xs[3] = q.y;
+        } else {
+          xs[2] = x[p[2] ? rr[2] + o : rr[2]];
+          xs[3] = x[rr[3]];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xs[k] = x[p[k] ? rr[k] + o : rr[k]];
+      }
+      const V vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const V t = acc[k] + vv[k] * V(xs[k]);
+        acc[k] = p[k] ? t : acc[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) y[k] = acc[k];
+  }
 };
 using DiaOp = DiaOpT<double>;
 using DiaOpF = DiaOpT<float>;
@@ -770,6 +851,76 @@ __device__ __forceinline__ void update_x2(double* __restrict__ x, int32_t row, b
   }
   x[row] = x[row] + u0 + v0;
   if (valid1) x[row + 1] = x[row + 1] + u1 + v1;
+}
+
+// As produce2, with each lane taking four neighbouring rows: lane l of a
+// 256-row block handles rows 4l .. 4l + 3, which form one subtree of two
+// levels of the balanced tree over the row index, and the body returns that
+// subtree's sum ((d0 + d1) + (d2 + d3), a row past n a zero leaf).  The wave
+// covers the same 64 R rows as R / 4 blocks of 256, so the partials are bit
+// for bit those of produce().  Body(row, nv, d) with row a multiple of 4 and
+// nv = the rows of the four below n (0 to 4); needs R >= 4.
+template <int ND, class T = double, class Body>
+__device__ __forceinline__ void produce4(const Args& a, Body body) {
+  __shared__ T lvl[4][kLevels][ND];
+  __shared__ T wtot[ND][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t wbase = ((int64_t)wg_index(a) * 4 + wave) * a.R * 64;
+  const int R4 = a.R >> 2;
+  for (int j = 0; j < R4; ++j) {
+    const int64_t b0 = wbase + (int64_t)j * 256;
+    T d[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) d[k] = T(0);
+    if (b0 < a.n) {
+      const int32_t row = (int32_t)(b0 + 4 * lane);
+      body(row, (int)max(0, min(4, a.n - row)), d);
+      wave_sum63<ND, T>(d);
+    }
+    if (lane == 63) {
+      int l = 0;
+      for (int bits = j; bits & 1; bits >>= 1, ++l) {
+#pragma unroll
+        for (int k = 0; k < ND; ++k) d[k] = lvl[wave][l][k] + d[k];
+      }
+#pragma unroll
+      for (int k = 0; k < ND; ++k) lvl[wave][l][k] = d[k];
+    }
+  }
+  if (lane == 63) {
+    const int top = __builtin_ctz((unsigned)R4);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) wtot[k][wave] = lvl[wave][top][k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < ND; ++k)
+      a.pout[k * a.pstride + wg_index(a)] = double((wtot[k][0] + wtot[k][1]) + (wtot[k][2] + wtot[k][3]));
+  }
+}
+
+// x[row + k] = (x[row + k] + u[k]) + v[k] for the nv rows of four (row a
+// multiple of 4) on the caller's x: two 16-byte loads and stores when all four
+// are rows and x is 16-byte aligned, else row by row.  The same arithmetic
+// either way.
+__device__ __forceinline__ void update_x4(double* __restrict__ x, int32_t row, int nv, const double (&u)[4],
+                                          const double (&v)[4]) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  if (nv == 4 && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+    D2 lo = *reinterpret_cast<const D2*>(&x[row]);
+    D2 hi = *reinterpret_cast<const D2*>(&x[row + 2]);
+    lo.x = lo.x + u[0] + v[0];
+    lo.y = lo.y + u[1] + v[1];
+    hi.x = hi.x + u[2] + v[2];
+    hi.y = hi.y + u[3] + v[3];
+    *reinterpret_cast<D2*>(&x[row]) = lo;
+    *reinterpret_cast<D2*>(&x[row + 2]) = hi;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (k < nv) x[row + k] = x[row + k] + u[k] + v[k];
 }
 
 // The workgroup's rows without a reduction, two neighbouring rows per lane
@@ -2029,6 +2180,120 @@ __global__ __launch_bounds__(kWG) void k_mp_pb2(Op32 op, Args a) {
   });
 }
 
+// k_mp_pa2 / k_mp_pb2 with four neighbouring rows per lane (see produce4):
+// each binary32 vector access is one 16-byte load or store, as wide as the
+// binary64 kernels' pairs, so a wave moves 1 KB per access; the operator
+// provides spmv4.  The arithmetic of each row and the reduction trees are
+// those of k_mp_pa / k_mp_pb, so the results are the same bits.  A four
+// starting below n stays inside the workspace vectors (padded to 64 rows);
+// x, the caller's n doubles, is updated for the rows below n only.
+template <class Op32>
+__global__ __launch_bounds__(kWG) void k_mp_pa4(Op32 op, Args a) {
+  typedef float F4 __attribute__((ext_vector_type(4)));
+  PBCGS_PROLOGUE(st)
+  if (a.first) {
+    double g[1];
+    gather_sums<1, float>(a, g);
+    fin_setup_alpha(st, g[0]);
+  } else {
+    double g[5];
+    gather_sums<5, float>(a, g);
+    fin_pipe_b_mp(st, a.hist, g, false, a.aform);
+  }
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const float af = float(st.alpha), bf = float(st.beta), wf_ = float(st.omega);
+  produce4<2, float>(a, [&](int32_t row, int nv, float (&d)[2]) {
+    float t[4];
+    op.spmv4(row, nv, a.wf, t);
+    if (nv <= 0) return;
+    const F4 r4 = *reinterpret_cast<const F4*>(&a.rf[row]);
+    const F4 w4 = *reinterpret_cast<const F4*>(&a.wf[row]);
+    const F4 v4 = *reinterpret_cast<const F4*>(&a.vf[row]);
+    const F4 so4 = *reinterpret_cast<const F4*>(&a.sf[row]);
+    const F4 zo4 = *reinterpret_cast<const F4*>(&a.zf[row]);
+    const F4 po4 = *reinterpret_cast<const F4*>(&a.pf[row]);
+    const float r[4] = {r4.x, r4.y, r4.z, r4.w}, w[4] = {w4.x, w4.y, w4.z, w4.w};
+    const float v[4] = {v4.x, v4.y, v4.z, v4.w}, so[4] = {so4.x, so4.y, so4.z, so4.w};
+    const float zo[4] = {zo4.x, zo4.y, zo4.z, zo4.w}, po[4] = {po4.x, po4.y, po4.z, po4.w};
+    float p[4], s[4], z[4], l0[4], l1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      p[k] = r[k] + bf * (po[k] - wf_ * so[k]);
+      s[k] = w[k] + bf * (so[k] - wf_ * zo[k]);
+      z[k] = t[k] + bf * (zo[k] - wf_ * v[k]);
+      const float q = r[k] - af * s[k], y = w[k] - af * z[k];
+      // the four leaves of the reduction tree (a row past n is a zero leaf)
+      l0[k] = k < nv ? q * y : 0.0f;
+      l1[k] = k < nv ? y * y : 0.0f;
+    }
+    *reinterpret_cast<F4*>(&a.pf[row]) = F4{p[0], p[1], p[2], p[3]};
+    *reinterpret_cast<F4*>(&a.sf[row]) = F4{s[0], s[1], s[2], s[3]};
+    *reinterpret_cast<F4*>(&a.tf[row]) = F4{t[0], t[1], t[2], t[3]};
+    *reinterpret_cast<F4*>(&a.zf[row]) = F4{z[0], z[1], z[2], z[3]};
+    d[0] = (l0[0] + l0[1]) + (l0[2] + l0[3]);
+    d[1] = (l1[0] + l1[1]) + (l1[2] + l1[3]);
+  });
+}
+
+template <class Op32>
+__global__ __launch_bounds__(kWG) void k_mp_pb4(Op32 op, Args a) {
+  typedef float F4 __attribute__((ext_vector_type(4)));
+  PBCGS_PROLOGUE(st)
+  double g2[2];
+  gather_sums<2, float>(a, g2);
+  const double alpha = st.alpha;
+  const bool yz = fin_omega(st, a.hist, g2[0], g2[1]);
+  publish(a, st);
+  if (yz) {
+    each_row(a, [&](int32_t row, bool valid) {
+      if (valid) a.x[row] = a.x[row] + alpha * double(a.pf[row]);
+    });
+    return;
+  }
+  if (st.status != DS_RUNNING) return;
+  const double omega = st.omega;
+  const float af = float(alpha), wn = float(omega);
+  produce4<5, float>(a, [&](int32_t row, int nv, float (&d)[5]) {
+    float vv[4];
+    op.spmv4(row, nv, a.zf, vv);
+    if (nv <= 0) return;
+    const F4 r4 = *reinterpret_cast<const F4*>(&a.rf[row]);
+    const F4 s4 = *reinterpret_cast<const F4*>(&a.sf[row]);
+    const F4 w4 = *reinterpret_cast<const F4*>(&a.wf[row]);
+    const F4 z4 = *reinterpret_cast<const F4*>(&a.zf[row]);
+    const F4 t4 = *reinterpret_cast<const F4*>(&a.tf[row]);
+    const F4 p4 = *reinterpret_cast<const F4*>(&a.pf[row]);
+    const F4 r04 = *reinterpret_cast<const F4*>(&a.r0f[row]);
+    const float r[4] = {r4.x, r4.y, r4.z, r4.w}, s[4] = {s4.x, s4.y, s4.z, s4.w};
+    const float w[4] = {w4.x, w4.y, w4.z, w4.w}, z[4] = {z4.x, z4.y, z4.z, z4.w};
+    const float t[4] = {t4.x, t4.y, t4.z, t4.w}, p[4] = {p4.x, p4.y, p4.z, p4.w};
+    const float r0[4] = {r04.x, r04.y, r04.z, r04.w};
+    float rn[4], wnew[4], l[5][4];
+    double u[4], ux[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float q = r[k] - af * s[k], y = w[k] - af * z[k];
+      rn[k] = q - wn * y;
+      wnew[k] = y - wn * (t[k] - af * vv[k]);
+      u[k] = alpha * double(p[k]);
+      ux[k] = omega * double(q);
+      const bool in = k < nv;
+      l[0][k] = in ? r0[k] * rn[k] : 0.0f;
+      l[1][k] = in ? r0[k] * wnew[k] : 0.0f;
+      l[2][k] = in ? r0[k] * s[k] : 0.0f;
+      l[3][k] = in ? r0[k] * z[k] : 0.0f;
+      l[4][k] = in ? rn[k] * rn[k] : 0.0f;
+    }
+    update_x4(a.x, row, nv, u, ux);
+    *reinterpret_cast<F4*>(&a.vf[row]) = F4{vv[0], vv[1], vv[2], vv[3]};
+    *reinterpret_cast<F4*>(&a.rf[row]) = F4{rn[0], rn[1], rn[2], rn[3]};
+    *reinterpret_cast<F4*>(&a.wf[row]) = F4{wnew[0], wnew[1], wnew[2], wnew[3]};
+#pragma unroll
+    for (int j = 0; j < 5; ++j) d[j] = (l[j][0] + l[j][1]) + (l[j][2] + l[j][3]);
+  });
+}
+
 // k_pa / k_pb of the unpreconditioned p-BiCGStab (Algorithm 9, also on A M^{-1})
 // with two neighbouring rows per lane, as k_mp_pa2 / k_mp_pb2: 16-byte vector
 // accesses, the same arithmetic per row and the same reduction trees, so the
@@ -2263,6 +2528,8 @@ __global__ __launch_bounds__(kWG) void k_b5_2(Args a) { d_b5_2(a); }
 template <class Op> struct HasSpmv2 : std::false_type {};
 template <class V, bool P, bool N> struct HasSpmv2<DiaOpT<V, P, N>> : std::true_type {};
 template <int NPTS, class V> struct HasSpmv2<StencilOp<NPTS, V>> : std::true_type {};
+template <class Op> struct HasSpmv4 : std::false_type {};
+template <class V, bool P, bool N> struct HasSpmv4<DiaOpT<V, P, N>> : std::true_type {};
 template <class Op> struct IsDia : std::false_type {};
 template <class V, bool P, bool N> struct IsDia<DiaOpT<V, P, N>> : std::true_type {};
 

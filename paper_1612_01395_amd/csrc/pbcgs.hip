@@ -616,6 +616,13 @@ struct Driver {
     if constexpr (MP && HasSpmv2<Op>::value) return a.R >= 2 && env_int("PBCGS_TWO_ROWS", 1) != 0;
     return false;
   }
+  // the binary32 fused kernels take four rows per lane (16-byte vector
+  // accesses) when the operator supports it and every wave owns at least four
+  // 64-row blocks (PBCGS_FOUR_ROWS=0 turns it off; then two rows per lane)
+  bool four_rows() const {
+    if constexpr (MP && HasSpmv4<Op>::value) return a.R >= 4 && env_int("PBCGS_FOUR_ROWS", 1) != 0;
+    return false;
+  }
   // the replacement steps of the binary32 form with two rows per lane too
   // (their binary64 operator has the two-row product)
   bool two_rows_rr() const {
@@ -675,7 +682,10 @@ struct Driver {
         }
       } else {
         timed(0, [&] {
-          if (two_rows()) {
+          if (four_rows()) {
+            if constexpr (HasSpmv4<Op>::value)
+              k_mp_pa4<Op><<<grid(), kWG, 0, s>>>(op, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
+          } else if (two_rows()) {
             if constexpr (HasSpmv2<Op>::value)
               k_mp_pa2<Op><<<grid(), kWG, 0, s>>>(op, L(i == 0 ? PB_SETUP2 : PB_B, PB_A, i == 0));
           } else {
@@ -689,7 +699,9 @@ struct Driver {
         launch_rr_w();
       } else {
         timed(1, [&] {
-          if (two_rows()) {
+          if (four_rows()) {
+            if constexpr (HasSpmv4<Op>::value) k_mp_pb4<Op><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B));
+          } else if (two_rows()) {
             if constexpr (HasSpmv2<Op>::value) k_mp_pb2<Op><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B));
           } else {
             k_mp_pb<Op><<<grid(), kWG, 0, s>>>(op, L(PB_A, PB_B));
@@ -842,8 +854,9 @@ struct Driver {
     k.append(reinterpret_cast<const char*>(&a), sizeof(Args));
     k.append(reinterpret_cast<const char*>(&op), sizeof(Op));
     k.append(reinterpret_cast<const char*>(&op64), sizeof(Op64));
-    std::snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%lld|%d|%d|", PC, MP ? 1 : 0, o.variant, m, (long long)(q & 1),
-                  i0 == 0 ? 1 : 0, (int)(i0 & 1));
+    // the kernel forms the environment selects are part of the schedule
+    std::snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%lld|%d|%d|%d%d%d|", PC, MP ? 1 : 0, o.variant, m, (long long)(q & 1),
+                  i0 == 0 ? 1 : 0, (int)(i0 & 1), four_rows() ? 1 : 0, two_rows() ? 1 : 0, two_rows64() ? 1 : 0);
     k += buf;
     for (int j = 0; j < m; ++j) {
       const int64_t i = i0 + j;
