@@ -204,9 +204,29 @@ using CsrOpDgf = CsrOpT<float, uint16_t>;
 template <class Op> struct IsCsr : std::false_type {};
 template <class V, class I> struct IsCsr<CsrOpT<V, I>> : std::true_type {};
 
+// Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane l receives the
+// value of lane l - 1 (shr) or l + 1 (shl); the lane without a source (0 or 63)
+// keeps `fill`.
+constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double fill, double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float wave_shift(float fill, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 // Constant-coefficient 5-point (nz == 1) or 7-point stencil, Dirichlet
 // boundaries; c[] in ascending column order, so the result equals the CSR
-// product of the assembled matrix bit for bit.
+// product of the assembled matrix bit for bit.  All 64 lanes of a row block
+// call spmv / spmv2 together (lane l holds row b0 + l, or rows b0 + 2l and
+// b0 + 2l + 1): each lane loads the x of its own rows once, and the x-direction
+// neighbours x[row - 1], x[row + 1] come from the adjacent lanes by a wave
+// shift (one shared load for each end of the block), so a row costs five x
+// loads instead of seven (the 5-point stencil three instead of five).
 template <int NPTS, class V = double>
 struct StencilOp {
   using Val = V;
@@ -214,17 +234,108 @@ struct StencilOp {
   V c[NPTS];
   template <class X>
   __device__ __forceinline__ V spmv(int32_t row, bool valid, const X* __restrict__ x) const {
-    return valid ? apply(row, x) : V(0);
+    const int lane = threadIdx.x & 63;
+    const int32_t n = nx * ny * nz;
+    const int32_t b0 = row - lane;
+    const X xc = x[min(row, n - 1)];
+    const X xm = wave_shift<kWaveShr1>(x[max(b0 - 1, 0)], xc);      // x[row - 1]
+    const X xp = wave_shift<kWaveShl1>(x[min(b0 + 64, n - 1)], xc);  // x[row + 1]
+    return valid ? apply(row, x, xm, xc, xp) : V(0);
   }
-  // Rows row and row + 1 by one lane (the kernels with two rows per lane).
+  // Rows row and row + 1 (row even) by one lane.  valid1 implies valid0.
   template <class X>
   __device__ __forceinline__ void spmv2(int32_t row, bool valid0, bool valid1, const X* __restrict__ x, V& y0,
                                         V& y1) const {
-    y0 = valid0 ? apply(row, x) : V(0);
-    y1 = valid1 ? apply(row + 1, x) : V(0);
+    typedef X X2 __attribute__((ext_vector_type(2)));
+    const int lane = threadIdx.x & 63;
+    const int32_t n = nx * ny * nz;
+    const int32_t b0 = row - 2 * lane;
+    X c0, c1;
+    if (valid1) {  // row + 1 < n: an aligned pair of the (at least 16-byte aligned) vector
+      const X2 q = *reinterpret_cast<const X2*>(&x[row]);
+      c0 = q.x;
+      c1 = q.y;
+    } else {
+      c0 = x[min(row, n - 1)];
+      c1 = x[min(row + 1, n - 1)];
+    }
+    const X xm = wave_shift<kWaveShr1>(x[max(b0 - 1, 0)], c1);       // x[row - 1]
+    const X xp = wave_shift<kWaveShl1>(x[min(b0 + 128, n - 1)], c0);  // x[row + 2]
+    if ((nx & 1) == 0) {
+      // an even x extent: row and row + 1 lie on one grid line (and n is even,
+      // so valid0 implies valid1), and their y / z neighbours are aligned pairs
+      y0 = V(0);
+      y1 = V(0);
+      if (valid0) apply_pair(row, x, xm, c0, c1, xp, y0, y1);
+      return;
+    }
+    y0 = valid0 ? apply(row, x, xm, c0, c1) : V(0);
+    y1 = valid1 ? apply(row + 1, x, c0, c1, xp) : V(0);
   }
+  // Rows row, row + 1 of one grid line (row even, nx even) with x[row - 1],
+  // x[row], x[row + 1], x[row + 2] given: each row's terms in the order of apply.
   template <class X>
-  __device__ __forceinline__ V apply(int32_t row, const X* __restrict__ x) const {
+  __device__ __forceinline__ void apply_pair(int32_t row, const X* __restrict__ x, X xm, X c0, X c1, X xp, V& y0,
+                                             V& y1) const {
+    typedef X X2 __attribute__((ext_vector_type(2)));
+    const int32_t i = row % nx;  // even, so i + 1 <= nx - 1 and row + 1 has a left neighbour
+    const int32_t jk = row / nx;
+    V a0 = V(0), a1 = V(0);
+    if constexpr (NPTS == 7) {
+      const int32_t j = jk % ny, k = jk / ny;
+      const int32_t nxy = nx * ny;
+      if (k > 0) {
+        const X2 q = *reinterpret_cast<const X2*>(&x[row - nxy]);
+        a0 = a0 + c[0] * V(q.x);
+        a1 = a1 + c[0] * V(q.y);
+      }
+      if (j > 0) {
+        const X2 q = *reinterpret_cast<const X2*>(&x[row - nx]);
+        a0 = a0 + c[1] * V(q.x);
+        a1 = a1 + c[1] * V(q.y);
+      }
+      if (i > 0) a0 = a0 + c[2] * V(xm);
+      a1 = a1 + c[2] * V(c0);
+      a0 = a0 + c[3] * V(c0);
+      a1 = a1 + c[3] * V(c1);
+      a0 = a0 + c[4] * V(c1);
+      if (i + 1 < nx - 1) a1 = a1 + c[4] * V(xp);
+      if (j < ny - 1) {
+        const X2 q = *reinterpret_cast<const X2*>(&x[row + nx]);
+        a0 = a0 + c[5] * V(q.x);
+        a1 = a1 + c[5] * V(q.y);
+      }
+      if (k < nz - 1) {
+        const X2 q = *reinterpret_cast<const X2*>(&x[row + nxy]);
+        a0 = a0 + c[6] * V(q.x);
+        a1 = a1 + c[6] * V(q.y);
+      }
+    } else {
+      const int32_t j = jk;
+      if (j > 0) {
+        const X2 q = *reinterpret_cast<const X2*>(&x[row - nx]);
+        a0 = a0 + c[0] * V(q.x);
+        a1 = a1 + c[0] * V(q.y);
+      }
+      if (i > 0) a0 = a0 + c[1] * V(xm);
+      a1 = a1 + c[1] * V(c0);
+      a0 = a0 + c[2] * V(c0);
+      a1 = a1 + c[2] * V(c1);
+      a0 = a0 + c[3] * V(c1);
+      if (i + 1 < nx - 1) a1 = a1 + c[3] * V(xp);
+      if (j < ny - 1) {
+        const X2 q = *reinterpret_cast<const X2*>(&x[row + nx]);
+        a0 = a0 + c[4] * V(q.x);
+        a1 = a1 + c[4] * V(q.y);
+      }
+    }
+    y0 = a0;
+    y1 = a1;
+  }
+  // Row `row` with x[row - 1], x[row], x[row + 1] given (xm / xp are used only
+  // where the row has that neighbour).
+  template <class X>
+  __device__ __forceinline__ V apply(int32_t row, const X* __restrict__ x, X xm, X xc, X xp) const {
     const int32_t i = row % nx;
     const int32_t jk = row / nx;
     V acc = V(0);
@@ -233,17 +344,17 @@ struct StencilOp {
       const int32_t nxy = nx * ny;
       if (k > 0) acc = acc + c[0] * V(x[row - nxy]);
       if (j > 0) acc = acc + c[1] * V(x[row - nx]);
-      if (i > 0) acc = acc + c[2] * V(x[row - 1]);
-      acc = acc + c[3] * V(x[row]);
-      if (i < nx - 1) acc = acc + c[4] * V(x[row + 1]);
+      if (i > 0) acc = acc + c[2] * V(xm);
+      acc = acc + c[3] * V(xc);
+      if (i < nx - 1) acc = acc + c[4] * V(xp);
       if (j < ny - 1) acc = acc + c[5] * V(x[row + nx]);
       if (k < nz - 1) acc = acc + c[6] * V(x[row + nxy]);
     } else {
       const int32_t j = jk;
       if (j > 0) acc = acc + c[0] * V(x[row - nx]);
-      if (i > 0) acc = acc + c[1] * V(x[row - 1]);
-      acc = acc + c[2] * V(x[row]);
-      if (i < nx - 1) acc = acc + c[3] * V(x[row + 1]);
+      if (i > 0) acc = acc + c[1] * V(xm);
+      acc = acc + c[2] * V(xc);
+      if (i < nx - 1) acc = acc + c[3] * V(xp);
       if (j < ny - 1) acc = acc + c[4] * V(x[row + nx]);
     }
     return acc;
@@ -423,21 +534,6 @@ using DiaOp = DiaOpT<double>;
 using DiaOpF = DiaOpT<float>;
 using DiaOpB = DiaOpT<double, true>;  // batched: offsets in the system table
 using DiaOpC = DiaOpT<double, false, false>;  // ordinary value loads
-
-// Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane l receives the
-// value of lane l - 1 (shr) or l + 1 (shl); the lane without a source (0 or 63)
-// keeps `fill`.
-constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;
-template <int CTRL>
-__device__ __forceinline__ double wave_shift(double fill, double v) {
-  const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-template <int CTRL>
-__device__ __forceinline__ float wave_shift(float fill, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
 
 // Matrix-free 27-point variable-coefficient convection-diffusion operator on
 // the n^3 interior nodes of the unit cube (h = 1/(n+1)), Dirichlet boundaries,
