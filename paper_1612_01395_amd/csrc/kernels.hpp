@@ -2624,6 +2624,8 @@ __global__ __launch_bounds__(kWG) void k_b5_2(Args a) { d_b5_2(a); }
 template <class Op> struct HasSpmv2 : std::false_type {};
 template <class V, bool P, bool N> struct HasSpmv2<DiaOpT<V, P, N>> : std::true_type {};
 template <int NPTS, class V> struct HasSpmv2<StencilOp<NPTS, V>> : std::true_type {};
+template <class Op> struct IsStencil : std::false_type {};
+template <int NPTS, class V> struct IsStencil<StencilOp<NPTS, V>> : std::true_type {};
 template <class Op> struct HasSpmv4 : std::false_type {};
 template <class V, bool P, bool N> struct HasSpmv4<DiaOpT<V, P, N>> : std::true_type {};
 template <class Op> struct IsDia : std::false_type {};
