@@ -201,15 +201,32 @@ int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr
                  const int32_t* col_idx, const double* val, pbcgs_op_t* out);
 
 /*
- * Matrix-free constant-coefficient stencil on the interior nodes of an
- * nx x ny (x nz) grid, rows ordered x fastest, Dirichlet boundaries (entries
- * that would leave the grid are dropped).  npts = 5 (nz must be 1) or 7.
- * coef is a HOST array of npts coefficients in ascending-column order:
- * 5-point {-y, -x, centre, +x, +y}; 7-point {-z, -y, -x, centre, +x, +y, +z}.
- * Applying it gives bit for bit the product with the equivalent CSR matrix.
+ * Matrix-free stencil operator (the SPMV building block of Section 2 without
+ * a stored matrix) on the interior nodes of an nx x ny x nz grid, rows
+ * ordered x fastest, Dirichlet boundaries (entries that would leave the grid
+ * are dropped).  npts = 5 (nz must be 1), 7 or 27.  The terms of a row, in
+ * ascending column order: 5-point {-y, -x, centre, +x, +y}; 7-point {-z, -y,
+ * -x, centre, +x, +y, +z}; 27-point the offsets (dz, dy, dx) in {-1, 0, 1}^3
+ * with dz slowest and dx fastest (term 13 is the centre).
+ * coef_per_row = 0: coef is a HOST array of npts constant coefficients,
+ * copied.  coef_per_row = 1: coef is a DEVICE array of npts * n doubles
+ * (n = nx ny nz), coefficient d of row r at coef[d * n + r] (each term's
+ * coefficients contiguous over the rows, so a block of rows reads them in
+ * one sweep); borrowed: it must outlive the operator and may change between
+ * calls; the slots of terms that leave the grid are never read.  A row sums
+ * its present terms in the order above, so applying the operator gives bit
+ * for bit the product with the equivalent CSR matrix, and every solver, the
+ * precision form and the allocation-free entry point accept it.  Jacobi
+ * takes 1 / the centre coefficient (ERR_INVALID_ARG for a zero or non-finite
+ * one); folded Jacobi on per-row coefficients forms A M^{-1} in npts * n
+ * doubles of context workspace, and on constant coefficients needs a constant
+ * diagonal.  Not transposable, not batched (ERR_UNSUPPORTED).  ERR_INVALID_ARG
+ * for a bad size, npts or coef_per_row; ERR_UNSUPPORTED when n exceeds the
+ * launch limit of pbcgs_op_csr or npts * n exceeds 2^31 - 1 per-row
+ * coefficients.
  */
 int pbcgs_op_stencil(pbcgs_ctx_t ctx, int32_t nx, int32_t ny, int32_t nz, int32_t npts,
-                     const double* coef, pbcgs_op_t* out);
+                     const double* coef, int32_t coef_per_row, pbcgs_op_t* out);
 
 /*
  * Matrix-free 27-point variable-coefficient convection-diffusion operator
@@ -412,7 +429,9 @@ typedef struct {
     int64_t nnz;         /* stored non-zeros of a CSR operator, 0 for matrix-free     */
     int32_t n;           /* rows                                                     */
     int32_t op_kind;     /* 0 CSR, 1 5-point stencil, 2 7-point stencil,
-                            3 27-point matrix-free (pbcgs_op_convdiff27)             */
+                            3 27-point matrix-free (pbcgs_op_convdiff27),
+                            4 27-point stencil, 5 stencil with per-row
+                            coefficients (pbcgs_op_stencil)                          */
     int32_t variant;     /* PBCGS_BICGSTAB .. PBCGS_PIPE_CG                          */
     int32_t precision;   /* PBCGS_FP64 or PBCGS_FP32_RR64                            */
     int32_t read_path;   /* 0 the operator's default (its diagonal layout or compact

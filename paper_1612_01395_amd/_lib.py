@@ -103,7 +103,7 @@ _SIGNATURES = {
     "pbcgs_last_error": (ctypes.c_char_p, [_vp]),
     "pbcgs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "pbcgs_op_csr": (ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
-    "pbcgs_op_stencil": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_vp)]),
+    "pbcgs_op_stencil": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _i32, ctypes.POINTER(_vp)]),
     "pbcgs_op_convdiff27": (ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_f64), _f64, ctypes.POINTER(_vp)]),
     "pbcgs_op_destroy": (ctypes.c_int, [_vp]),
     "pbcgs_op_transpose": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),

@@ -361,6 +361,78 @@ struct StencilOp {
   }
 };
 
+// Matrix-free stencil on an nx x ny x nz grid (rows x fastest, Dirichlet
+// boundaries: entries that would leave the grid are dropped) with 5 (nz = 1),
+// 7 or 27 points, and either one set of constant coefficients (VAR = false:
+// the 27-point stencil, c[] kernel arguments) or coefficients per row
+// (VAR = true: coefficient d of row r at cf[d * n + r], so the rows of a block
+// read consecutive addresses).  Term d runs over the neighbour offsets in
+// ascending column order: 5-point {-y, -x, 0, +x, +y}, 7-point {-z, -y, -x, 0,
+// +x, +y, +z}, 27-point (dz, dy, dx) with dz slowest and dx fastest, each in
+// {-1, 0, +1}; a row's present terms are summed in that order, so the product
+// equals the CSR product of the equivalent matrix bit for bit.  All 64 lanes
+// of a row block call spmv together (lane l holds row b0 + l): each grid line
+// a row touches is loaded once per lane, and its x-direction neighbours come
+// from the adjacent lanes by a wave shift, with one load per lane for the
+// ends of the block.
+template <class V, bool VAR>
+struct GridOp {
+  using Val = V;
+  // the array length keeps the struct free of padding (it is hashed as bytes)
+  static constexpr int kC = VAR ? int(8 / sizeof(V)) : (sizeof(V) == 4 ? 28 : 27);
+  const V* __restrict__ cf;  // VAR: npts * n per-row coefficients (borrowed)
+  int32_t nx, ny, nz, npts;
+  V c[kC];                   // constant coefficients (the 27-point stencil)
+
+  __device__ __forceinline__ V coef(int d, int32_t row, int32_t n) const {
+    if constexpr (VAR) return cf[(int64_t)d * n + row];
+    else return c[d];
+  }
+
+  template <class X>
+  __device__ __forceinline__ V spmv(int32_t row, bool valid, const X* __restrict__ x) const {
+    const int lane = threadIdx.x & 63;
+    const int32_t nxy = nx * ny, n = nxy * nz;
+    const int32_t rc = min(row, n - 1);  // rows past the grid compute a discarded copy of the last
+    const int32_t b0 = row - lane;
+    const int32_t i = rc % nx, jk = rc / nx, j = jk % ny, k = jk / ny;
+    V acc = V(0);
+    if (npts == 27) {
+#pragma unroll
+      for (int l = 0; l < 9; ++l) {
+        const int dz = l / 3 - 1, dy = l % 3 - 1;
+        const bool lin = (dz < 0 ? k > 0 : (dz > 0 ? k < nz - 1 : true)) && (dy < 0 ? j > 0 : (dy > 0 ? j < ny - 1 : true));
+        const int32_t off = dz * nxy + dy * nx;
+        const X xc = x[lin ? rc + off : rc];
+        // lanes 0..31 fetch the line's entry left of the block, 32..63 the one right of it
+        const X xe = x[min(max(lane < 32 ? b0 + off - 1 : b0 + 64 + off, 0), n - 1)];
+        const X xm = wave_shift<kWaveShr1>(xe, xc), xp = wave_shift<kWaveShl1>(xe, xc);
+        if (lin && i > 0) acc = acc + coef(3 * l, rc, n) * V(xm);
+        if (lin) acc = acc + coef(3 * l + 1, rc, n) * V(xc);
+        if (lin && i < nx - 1) acc = acc + coef(3 * l + 2, rc, n) * V(xp);
+      }
+    } else {
+      const X xc = x[rc];
+      const X xe = x[min(max(lane < 32 ? b0 - 1 : b0 + 64, 0), n - 1)];
+      const X xm = wave_shift<kWaveShr1>(xe, xc), xp = wave_shift<kWaveShl1>(xe, xc);
+      int d = 0;
+      if (npts == 7) {
+        if (k > 0) acc = acc + coef(d, rc, n) * V(x[rc - nxy]);
+        ++d;
+      }
+      if (j > 0) acc = acc + coef(d, rc, n) * V(x[rc - nx]);
+      if (i > 0) acc = acc + coef(d + 1, rc, n) * V(xm);
+      acc = acc + coef(d + 2, rc, n) * V(xc);
+      if (i < nx - 1) acc = acc + coef(d + 3, rc, n) * V(xp);
+      if (j < ny - 1) acc = acc + coef(d + 4, rc, n) * V(x[rc + nx]);
+      if (npts == 7 && k < nz - 1) acc = acc + coef(d + 5, rc, n) * V(x[rc + nxy]);
+    }
+    return valid ? acc : V(0);
+  }
+};
+template <class Op> struct IsGrid : std::false_type {};
+template <class V, bool VAR> struct IsGrid<GridOp<V, VAR>> : std::true_type {};
+
 // Diagonal layout of a CSR operator with at most kMaxDia distinct diagonals j - i
 // (stencil discretisations): the values of diagonal d (offset off[d], the
 // offsets ascending) lie contiguously, va[d * ld + i], and a 32-bit mask per
@@ -699,6 +771,53 @@ template <class V, bool F> struct IsConv27<Conv27Op<V, F>> : std::true_type {};
 // Preconditioner modes: none (Algorithms 7 and 9), Jacobi with a vector of
 // 1/a_ii, Jacobi with one constant 1/a_ii (constant diagonal).
 enum { PC_NONE = 0, PC_VEC = 1, PC_SCALAR = 2 };
+
+// Folded Jacobi on per-row coefficients (Section 3.6 with A M^{-1} formed):
+// out[d * n + r] = coef(d, r) * dinv[column of term d], one rounding each, for
+// the terms present (the others are left as they are: never read).
+template <int PC>
+__global__ __launch_bounds__(256) void k_fold_grid(GridOp<double, true> op, double* __restrict__ out,
+                                                   const double* __restrict__ dinv, double dinv_s) {
+  const int32_t nxy = op.nx * op.ny, n = nxy * op.nz;
+  for (int32_t r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+    const int32_t i = r % op.nx, jk = r / op.nx, j = jk % op.ny, k = jk / op.ny;
+    auto put = [&](int d, bool present, int32_t col) {
+      if (present) out[(int64_t)d * n + r] = op.coef(d, r, n) * (PC == PC_VEC ? dinv[col] : dinv_s);
+    };
+    if (op.npts == 27) {
+      for (int l = 0; l < 27; ++l) {
+        const int dz = l / 9 - 1, dy = (l / 3) % 3 - 1, dx = l % 3 - 1;
+        const bool in = (dz < 0 ? k > 0 : (dz > 0 ? k < op.nz - 1 : true)) &&
+                        (dy < 0 ? j > 0 : (dy > 0 ? j < op.ny - 1 : true)) &&
+                        (dx < 0 ? i > 0 : (dx > 0 ? i < op.nx - 1 : true));
+        put(l, in, r + dz * nxy + dy * op.nx + dx);
+      }
+    } else {
+      int d = 0;
+      if (op.npts == 7) put(d++, k > 0, r - nxy);
+      put(d, j > 0, r - op.nx);
+      put(d + 1, i > 0, r - 1);
+      put(d + 2, true, r);
+      put(d + 3, i < op.nx - 1, r + 1);
+      put(d + 4, j < op.ny - 1, r + op.nx);
+      if (op.npts == 7) put(d + 5, k < op.nz - 1, r + nxy);
+    }
+  }
+}
+
+// dinv[r] = 1 / (the centre coefficient of row r) of per-row coefficients; bit 0
+// of *flag is set for a zero or non-finite diagonal entry.
+__global__ __launch_bounds__(256) void k_dinv_grid(GridOp<double, true> op, double* __restrict__ dinv,
+                                                   int32_t* flag) {
+  const int32_t n = op.nx * op.ny * op.nz;
+  const int centre = op.npts / 2;
+  for (int32_t r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+    const double a = op.coef(centre, r, n);
+    if (a == 0.0 || !isfinite(a)) atomicOr(flag, 1);
+    dinv[r] = 1.0 / a;
+  }
+}
+
 
 // Kernel arguments: sizes, launch shape, state slots, partial-sum buffers and
 // every vector of the solvers.  Without a preconditioner the hatted pointers

@@ -25,7 +25,8 @@ namespace {
 
 thread_local std::string g_last_error;
 
-enum OpKind { OP_CSR = 0, OP_ST5 = 1, OP_ST7 = 2, OP_CV27 = 3 };
+// OP_ST27: the constant 27-point stencil; OP_GRID: a stencil with coefficients per row
+enum OpKind { OP_CSR = 0, OP_ST5 = 1, OP_ST7 = 2, OP_CV27 = 3, OP_ST27 = 4, OP_GRID = 5 };
 
 // Partial-sum buffers, one per producing kernel role.
 enum PartBuf { PB_SETUP1 = 0, PB_SETUP2, PB_A, PB_B, PB_B1, PB_B3, PB_B4, PB_UTIL, PB_COUNT };
@@ -147,7 +148,9 @@ struct pbcgs_op_s {
   const int32_t* ci = nullptr;
   const double* va = nullptr;
   int32_t nx = 0, ny = 0, nz = 0;
-  double coef[7] = {0, 0, 0, 0, 0, 0, 0};
+  int32_t npts = 0;                 // stencil points (5, 7 or 27)
+  double coef[27] = {};             // constant stencil coefficients
+  const double* vcoef = nullptr;    // OP_GRID: npts * n per-row coefficients (borrowed, device)
   // matrix-free 27-point operator: cell coefficients (borrowed) and the convection terms
   const double* kappa = nullptr;
   double hb[3] = {0, 0, 0};
@@ -447,6 +450,25 @@ StencilOp<NPTS, float> to_binary32(pbcgs_ctx_t, const StencilOp<NPTS, double>& o
 template <bool F>
 Conv27Op<float, F> to_binary32(pbcgs_ctx_t, const Conv27Op<double, F>& op, int64_t) {
   return Conv27Op<float, F>{op.n, op.upneg, op.kappa, op.dscale, {op.hab[0], op.hab[1], op.hab[2]}, op.hsum, op.shift};
+}
+inline GridOp<float, false> to_binary32(pbcgs_ctx_t, const GridOp<double, false>& op, int64_t) {
+  GridOp<float, false> f;
+  std::memset(&f, 0, sizeof f);
+  f.nx = op.nx; f.ny = op.ny; f.nz = op.nz; f.npts = op.npts;
+  for (int k = 0; k < 27; ++k) f.c[k] = float(op.c[k]);
+  return f;
+}
+// per-row coefficients rounded once into the context's binary32 values (room
+// for npts * n made by the caller)
+inline GridOp<float, true> to_binary32(pbcgs_ctx_t ctx, const GridOp<double, true>& op, int64_t) {
+  const int64_t cnt = (int64_t)op.npts * op.nx * op.ny * op.nz;
+  const int g = (int)std::min<int64_t>((cnt + kWG - 1) / kWG, 8192);
+  k_round_vals<<<g, kWG, 0, ctx->stream>>>(cnt, op.cf, ctx->a32);
+  GridOp<float, true> f;
+  std::memset(&f, 0, sizeof f);
+  f.cf = ctx->a32;
+  f.nx = op.nx; f.ny = op.ny; f.nz = op.nz; f.npts = op.npts;
+  return f;
 }
 
 size_t padded(int32_t n) { return ((size_t)n + 63) / 64 * 64; }
@@ -1104,6 +1126,11 @@ static_assert(sizeof(StencilOp<7>) == 4 * sizeof(int32_t) + 7 * sizeof(double), 
 static_assert(sizeof(StencilOp<5>) == 4 * sizeof(int32_t) + 5 * sizeof(double), "StencilOp padding");
 static_assert(sizeof(StencilOp<7, float>) == 4 * sizeof(int32_t) + 7 * sizeof(float), "StencilOp padding");
 static_assert(sizeof(StencilOp<5, float>) == 4 * sizeof(int32_t) + 5 * sizeof(float), "StencilOp padding");
+static_assert(sizeof(GridOp<double, true>) == sizeof(void*) + 4 * sizeof(int32_t) + 8 &&
+              sizeof(GridOp<float, true>) == sizeof(GridOp<double, true>) &&
+              sizeof(GridOp<double, false>) == sizeof(void*) + 4 * sizeof(int32_t) + 27 * sizeof(double) &&
+              sizeof(GridOp<float, false>) == sizeof(void*) + 4 * sizeof(int32_t) + 28 * sizeof(float),
+              "GridOp padding");
 static_assert(sizeof(DiaOp) == 2 * sizeof(void*) + (4 + kMaxDia) * sizeof(int32_t) && sizeof(DiaOpF) == sizeof(DiaOp),
               "DiaOpT padding");
 static_assert(sizeof(Conv27) == 2 * sizeof(int32_t) + 2 * sizeof(void*) + 5 * sizeof(double) &&
@@ -1124,6 +1151,18 @@ Conv27 conv27_of(pbcgs_op_t A) {
   return c;
 }
 
+// Values an operator stores per solve in its folded or binary32 form: a CSR
+// operator's non-zeros, a stencil's per-row coefficients; 0 for the others.
+int64_t stored_values(const pbcgs_op_s* A) {
+  if (A->kind == OP_CSR) return A->nnz;
+  if (A->kind == OP_GRID) return (int64_t)A->npts * A->n;
+  return 0;
+}
+
+// A stencil with one set of constant coefficients, and its centre coefficient.
+bool const_stencil(const pbcgs_op_s* A) { return A->kind == OP_ST5 || A->kind == OP_ST7 || A->kind == OP_ST27; }
+double stencil_centre(const pbcgs_op_s* A) { return A->coef[A->kind == OP_ST27 ? 13 : (A->kind == OP_ST7 ? 3 : 2)]; }
+
 // f(op) with the operator's device form: for CSR the compact copy the
 // operator holds (int16 block offsets or diagonal codes) when `compact`
 // allows, else the int32 columns.
@@ -1135,6 +1174,20 @@ int with_op(pbcgs_op_t A, F f, bool compact = true) {
     return f(CsrOp{A->rp, A->ci, A->va, A->n});
   }
   if (A->kind == OP_CV27) return f(conv27_of(A));
+  if (A->kind == OP_ST27) {
+    GridOp<double, false> g;
+    std::memset(&g, 0, sizeof g);
+    g.nx = A->nx; g.ny = A->ny; g.nz = A->nz; g.npts = 27;
+    for (int k = 0; k < 27; ++k) g.c[k] = A->coef[k];
+    return f(g);
+  }
+  if (A->kind == OP_GRID) {
+    GridOp<double, true> g;
+    std::memset(&g, 0, sizeof g);
+    g.cf = A->vcoef;
+    g.nx = A->nx; g.ny = A->ny; g.nz = A->nz; g.npts = A->npts;
+    return f(g);
+  }
   if (A->kind == OP_ST7) {
     StencilOp<7> s;
     std::memset(&s, 0, sizeof s);
@@ -1167,6 +1220,14 @@ auto fold_operator(pbcgs_ctx_t ctx, pbcgs_op_t A, const Op& op, int pc, const do
     return fop;
   } else if constexpr (IsConv27<Op>::value) {
     return Conv27Op<double, true>{op.n, op.upneg, op.kappa, dv, {op.hab[0], op.hab[1], op.hab[2]}, op.hsum, op.shift};
+  } else if constexpr (std::is_same<Op, GridOp<double, true>>::value) {
+    // per-row coefficients: every present entry times its column's dinv, into ahat
+    const int g = (int)std::min<int64_t>((A->n + 255) / 256, 8192);
+    if (pc == PC_VEC) k_fold_grid<PC_VEC><<<g, 256, 0, ctx->stream>>>(op, ctx->ahat, dv, ds);
+    else k_fold_grid<PC_SCALAR><<<g, 256, 0, ctx->stream>>>(op, ctx->ahat, dv, ds);
+    Op fop = op;
+    fop.cf = ctx->ahat;
+    return fop;
   } else {
     Op fop = op;
     for (double& c : fop.c) c = c * ds;  // one rounding per coefficient, as a_ij * dinv_j
@@ -1800,25 +1861,42 @@ int pbcgs_op_csr(pbcgs_ctx_t ctx, int32_t n, int64_t nnz, const int32_t* row_ptr
 }
 
 int pbcgs_op_stencil(pbcgs_ctx_t ctx, int32_t nx, int32_t ny, int32_t nz, int32_t npts, const double* coef,
-                     pbcgs_op_t* out) {
+                     int32_t coef_per_row, pbcgs_op_t* out) {
   if (!ctx || !out || !coef) return fail(ctx, PBCGS_ERR_INVALID_ARG, "NULL argument");
   if (nx <= 0 || ny <= 0 || nz <= 0) return fail(ctx, PBCGS_ERR_INVALID_ARG, "bad grid size");
-  if (npts != 5 && npts != 7) return fail(ctx, PBCGS_ERR_INVALID_ARG, "npts must be 5 or 7");
+  if (npts != 5 && npts != 7 && npts != 27) return fail(ctx, PBCGS_ERR_INVALID_ARG, "npts must be 5, 7 or 27");
   if (npts == 5 && nz != 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "5-point stencil needs nz == 1");
+  if (coef_per_row != 0 && coef_per_row != 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "coef_per_row must be 0 or 1");
   const int64_t n = (int64_t)nx * ny * nz;
   if (n > INT32_MAX) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "grid too large");
   Shape sh;
   if (!make_shape((int32_t)n, &sh)) return fail(ctx, PBCGS_ERR_UNSUPPORTED, "too many rows for one launch");
+  if (coef_per_row && (int64_t)npts * n > INT32_MAX)
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "npts * n per-row coefficients exceed int32 indexing");
   pbcgs_op_t A = new pbcgs_op_s();
   A->ctx = ctx;
-  A->kind = (npts == 7) ? OP_ST7 : OP_ST5;
+  A->kind = coef_per_row ? OP_GRID : (npts == 27 ? OP_ST27 : (npts == 7 ? OP_ST7 : OP_ST5));
   A->n = (int32_t)n;
   A->nx = nx;
   A->ny = ny;
   A->nz = nz;
-  for (int k = 0; k < npts; ++k) A->coef[k] = coef[k];
-  const int64_t X = nx, Y = ny, Z = nz;  // stored entries of the equivalent CSR matrix
-  A->nnz = X * Y * Z + 2 * ((X - 1) * Y * Z + X * (Y - 1) * Z) + (npts == 7 ? 2 * X * Y * (Z - 1) : 0);
+  A->npts = npts;
+  if (coef_per_row) A->vcoef = coef;  // device array, borrowed
+  else
+    for (int k = 0; k < npts; ++k) A->coef[k] = coef[k];
+  // stored entries of the equivalent CSR matrix: per neighbour offset, the
+  // nodes whose neighbour lies in the grid
+  const int64_t X = nx, Y = ny, Z = nz;
+  auto count = [&](int dx, int dy, int dz) { return (X - std::abs(dx)) * (Y - std::abs(dy)) * (Z - std::abs(dz)); };
+  int64_t nnz = 0;
+  if (npts == 27) {
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) nnz += count(dx, dy, dz);
+  } else {
+    nnz = count(0, 0, 0) + 2 * (count(1, 0, 0) + count(0, 1, 0)) + (npts == 7 ? 2 * count(0, 0, 1) : 0);
+  }
+  A->nnz = nnz;
   *out = A;
   return PBCGS_SUCCESS;
 }
@@ -1933,8 +2011,22 @@ int pbcgs_jacobi_dinv(pbcgs_ctx_t ctx, pbcgs_op_t A, double* dinv) {
     if (flag & 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero or non-finite diagonal entry");
     return PBCGS_SUCCESS;
   }
+  if (A->kind == OP_GRID) {
+    int rc = reset_flag(ctx);
+    if (rc != PBCGS_SUCCESS) return rc;
+    GridOp<double, true> g;
+    std::memset(&g, 0, sizeof g);
+    g.cf = A->vcoef;
+    g.nx = A->nx; g.ny = A->ny; g.nz = A->nz; g.npts = A->npts;
+    k_dinv_grid<<<(int)std::min<int64_t>((A->n + 255) / 256, 8192), 256, 0, ctx->stream>>>(g, dinv, ctx->flag);
+    int32_t flag = 0;
+    rc = read_flag(ctx, &flag);
+    if (rc != PBCGS_SUCCESS) return rc;
+    if (flag & 1) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero or non-finite diagonal entry");
+    return PBCGS_SUCCESS;
+  }
   if (A->kind != OP_CSR) {
-    const double c = (A->kind == OP_ST7) ? A->coef[3] : A->coef[2];
+    const double c = stencil_centre(A);
     if (c == 0.0 || !std::isfinite(c)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero diagonal");
     const double d = 1.0 / c;
     std::vector<double> h((size_t)A->n, d);
@@ -2007,8 +2099,8 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
   const double* dinv_vec = nullptr;  // the vector of 1/a_ii when there is one (also when constant)
   if (o.precond != PBCGS_PRECOND_NONE) {
     const double* dv = dinv;
-    if (!dv && (A->kind == OP_ST5 || A->kind == OP_ST7)) {
-      const double c = (A->kind == OP_ST7) ? A->coef[3] : A->coef[2];
+    if (!dv && const_stencil(A)) {
+      const double c = stencil_centre(A);
       if (c == 0.0 || !std::isfinite(c)) return fail(ctx, PBCGS_ERR_INVALID_ARG, "zero diagonal");
       pc = PC_SCALAR;
       a.dinv_s = 1.0 / c;
@@ -2035,8 +2127,8 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
       }
     }
   }
-  if (folded && pc == PC_VEC && (A->kind == OP_ST5 || A->kind == OP_ST7))
-    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "folded Jacobi on a stencil needs a constant diagonal");
+  if (folded && pc == PC_VEC && const_stencil(A))
+    return fail(ctx, PBCGS_ERR_UNSUPPORTED, "folded Jacobi on a constant stencil needs a constant diagonal");
   const bool hat = (pc != PC_NONE) && !folded;
   // a CSR operator with a diagonal layout is read through it (same results)
   const bool use_dia = A->kind == OP_CSR && A->ndia > 0 && dia_ok(o) && !ctx->noalloc;
@@ -2072,15 +2164,15 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     const double ds = a.dinv_s;
     a.dinv = nullptr;
     a.dinv_s = 0.0;
-    if (folded && A->kind == OP_CSR && !use_dia) {
-      rc = ensure_ahat(ctx, (size_t)A->nnz);
+    if (folded && stored_values(A) > 0 && !use_dia) {
+      rc = ensure_ahat(ctx, (size_t)stored_values(A));
       if (rc != PBCGS_SUCCESS) return rc;
-      poison(ctx, ctx->ahat, (size_t)A->nnz * sizeof(double));
+      poison(ctx, ctx->ahat, (size_t)stored_values(A) * sizeof(double));
     }
-    if (A->kind == OP_CSR && !use_dia) {
-      rc = ensure_a32(ctx, (size_t)A->nnz);
+    if (stored_values(A) > 0 && !use_dia) {
+      rc = ensure_a32(ctx, (size_t)stored_values(A));
       if (rc != PBCGS_SUCCESS) return rc;
-      poison(ctx, ctx->a32, (size_t)A->nnz * sizeof(float));
+      poison(ctx, ctx->a32, (size_t)stored_values(A) * sizeof(float));
     }
     return with_op(A, [&](auto op) -> int {
       auto run_mp = [&](auto op32, auto op64) -> int {
@@ -2135,10 +2227,10 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     const double ds = a.dinv_s;
     a.dinv = nullptr;
     a.dinv_s = 0.0;
-    if (A->kind == OP_CSR && !use_dia) {
-      rc = ensure_ahat(ctx, (size_t)A->nnz);
+    if (stored_values(A) > 0 && !use_dia) {
+      rc = ensure_ahat(ctx, (size_t)stored_values(A));
       if (rc != PBCGS_SUCCESS) return rc;
-      poison(ctx, ctx->ahat, (size_t)A->nnz * sizeof(double));
+      poison(ctx, ctx->ahat, (size_t)stored_values(A) * sizeof(double));
     }
     return with_op(A, [&](auto op) -> int {
       auto run_folded = [&](auto fop) -> int {
@@ -2199,8 +2291,9 @@ int pbcgs_solve_noalloc(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* 
   if (opts->flags & 2)
     return fail(ctx, PBCGS_ERR_UNSUPPORTED, "pbcgs_solve_noalloc does not time kernels (events would be created)");
   const size_t vec = padded(A->n) * 14;
-  const size_t folded_vals =
-      (opts->precond == PBCGS_PRECOND_JACOBI_FOLDED && A->kind == OP_CSR) ? (size_t)std::max<int64_t>(A->nnz, 1) : 0;
+  const size_t folded_vals = (opts->precond == PBCGS_PRECOND_JACOBI_FOLDED && stored_values(A) > 0)
+                                 ? (size_t)std::max<int64_t>(stored_values(A), 1)
+                                 : 0;
   if (vec + folded_vals > kScratchPoolDoubles)
     return fail(ctx, PBCGS_ERR_UNSUPPORTED,
                 "pbcgs_solve_noalloc needs " + std::to_string(vec + folded_vals) + " doubles of scratch (14 per row" +
@@ -2529,7 +2622,7 @@ int pbcgs_tune_cache_put(const pbcgs_tune_entry* e) {
     return fail(nullptr, PBCGS_ERR_INVALID_ARG, "device and build must be NUL-terminated");
   if (e->variant < PBCGS_BICGSTAB || e->variant > PBCGS_PIPE_CG ||
       (e->precision != PBCGS_FP64 && e->precision != PBCGS_FP32_RR64) || e->op_kind < OP_CSR ||
-      e->op_kind > OP_CV27 || e->nnz < 0 || e->read_path < 0 || e->read_path > 2)
+      e->op_kind > OP_GRID || e->nnz < 0 || e->read_path < 0 || e->read_path > 2)
     return fail(nullptr, PBCGS_ERR_INVALID_ARG, "bad variant, precision, operator kind, nnz or read path");
   if (!shape_fits(e->n, e->best))
     return fail(nullptr, PBCGS_ERR_INVALID_ARG, "best must be a power of two whose grid fits n rows");

@@ -177,15 +177,30 @@ def csr(row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor, ctx: Co
     return Operator(ctx, h, n, (row_ptr, col_idx, val), "csr")
 
 
-def stencil(nx: int, ny: int, nz: int, coef, ctx: Context | None = None) -> Operator:
-    """Matrix-free constant-coefficient 5- (nz == 1) or 7-point stencil; coef in
-    ascending-column order ({-y,-x,c,+x,+y} or {-z,-y,-x,c,+x,+y,+z})."""
+def stencil(nx: int, ny: int, nz: int, coef, ctx: Context | None = None, npts: int | None = None) -> Operator:
+    """Matrix-free 5- (nz == 1), 7- or 27-point stencil on an nx x ny x nz grid
+    (rows x fastest, Dirichlet boundaries).  ``coef``: a sequence of npts
+    constant coefficients in ascending-column order ({-y,-x,c,+x,+y},
+    {-z,-y,-x,c,+x,+y,+z}, or the 27 offsets (dz, dy, dx) with dz slowest), or
+    a float64 device tensor of npts * n per-row coefficients (coefficient d of
+    row r at ``coef[d * n + r]``, borrowed by the operator; ``npts`` may be
+    given, else it is coef.numel() // n)."""
     ctx = ctx or default_context()
+    n = nx * ny * nz
+    if isinstance(coef, torch.Tensor):
+        if npts is None:
+            npts = coef.numel() // n if n > 0 else 0
+        _check_vec(coef, npts * n, "coef")
+        h = ctypes.c_void_p()
+        L.check(L.lib().pbcgs_op_stencil(ctx.handle, nx, ny, nz, int(npts), ctypes.c_void_p(coef.data_ptr()), 1,
+                                         ctypes.byref(h)), ctx.handle)
+        return Operator(ctx, h, n, (coef,), f"stencil{npts}_per_row")
     coef = [float(c) for c in coef]
     arr = (ctypes.c_double * len(coef))(*coef)
     h = ctypes.c_void_p()
-    L.check(L.lib().pbcgs_op_stencil(ctx.handle, nx, ny, nz, len(coef), arr, ctypes.byref(h)), ctx.handle)
-    return Operator(ctx, h, nx * ny * nz, (), f"stencil{len(coef)}")
+    L.check(L.lib().pbcgs_op_stencil(ctx.handle, nx, ny, nz, len(coef), ctypes.cast(arr, ctypes.c_void_p), 0,
+                                     ctypes.byref(h)), ctx.handle)
+    return Operator(ctx, h, n, (), f"stencil{len(coef)}")
 
 
 def convdiff27(n: int, kappa: torch.Tensor, beta, shift: float = 0.0, ctx: Context | None = None) -> Operator:
@@ -537,7 +552,7 @@ def tune(A: Operator, b: torch.Tensor, iters: int = 20, **opts) -> dict:
     return _report(r)
 
 
-OP_KINDS = {0: "csr", 1: "stencil5", 2: "stencil7", 3: "convdiff27"}
+OP_KINDS = {0: "csr", 1: "stencil5", 2: "stencil7", 3: "convdiff27", 4: "stencil27", 5: "stencil_per_row"}
 READ_PATHS = {0: "default", 1: "csr_arrays", 2: "int32_columns"}
 _TUNE_CACHE_FORMAT = "pbcgs launch-shape cache"
 

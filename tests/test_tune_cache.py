@@ -69,7 +69,7 @@ def test_put_refuses_bad_codes_and_unterminated_strings():
     base.n = 1000
     base.best = 1
     assert lib.pbcgs_tune_cache_put(_lib.ctypes.byref(base)) == 0
-    for field, value in (("variant", 7), ("variant", -1), ("precision", 2), ("op_kind", 4), ("read_path", 3)):
+    for field, value in (("variant", 7), ("variant", -1), ("precision", 2), ("op_kind", 6), ("read_path", 3)):
         e = _lib.TuneEntry.from_buffer_copy(base)
         setattr(e, field, value)
         assert lib.pbcgs_tune_cache_put(_lib.ctypes.byref(e)) == _lib.ERR_INVALID_ARG, field
