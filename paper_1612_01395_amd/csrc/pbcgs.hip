@@ -992,7 +992,9 @@ struct Driver {
   }
 
   int run(pbcgs_info* info) {
-    if (use_persistent()) return run_persistent(info);
+    if constexpr (!MP) {  // the precision form has no persistent kernel (and instantiates none)
+      if (use_persistent()) return run_persistent(info);
+    }
     // graphs are instantiated (allocated) on first use: never without allocation
     const bool use_graph = !(o.flags & 1) && !(o.flags & 2) && !ctx->noalloc && ctx->perturb_iter < 0;
     timing = (o.flags & 2) != 0 && !ctx->noalloc;
