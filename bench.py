@@ -156,6 +156,25 @@ def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: boo
     return mat + 16 * vec, mat + 18 * vec, 34 * vec + 2 * mat
 
 
+def grid_coefficients(rp, col, val, n: int, N: int):
+    """Per-row coefficients of an assembled 3-D 27-point CSR matrix on the n^3
+    grid, term-major as pbcgs_op_stencil takes them (term (dz, dy, dx) of row r
+    at term * N + r, dz slowest); slots of terms that leave the grid are NaN."""
+    import torch
+    rows = torch.repeat_interleave(torch.arange(N, device=rp.device), (rp[1:] - rp[:-1]).to(torch.int64))
+    off = col.to(torch.int64) - rows
+    n2 = n * n
+    dz = torch.div(off + n2 // 2, n2, rounding_mode="floor")
+    rem = off - dz * n2
+    dy = torch.div(rem + n // 2, n, rounding_mode="floor")
+    dx = rem - dy * n
+    term = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)
+    coef = torch.full((27 * N,), float("nan"), dtype=torch.float64, device=rp.device)
+    coef[term * N + rows] = val
+    del rows, off, dz, rem, dy, dx, term
+    return coef
+
+
 def algorithmic_bytes_mf27(n: int, variant: str):
     """Algorithmic HBM bytes (K_a, K_b, iteration) of the folded solvers on the
     matrix-free 27-point operator of an n^3 grid: each product reads the
@@ -657,6 +676,20 @@ def main():
                                             "achieved_gbps": round(kb_ / (kus * 1e-6) / 1e9, 1),
                                             "frac": round(kb_ / (kus * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
                 row["matrix_free"] = mf
+                # the same operator as a stencil with per-row coefficients: the assembled
+                # values rearranged term-major (term (dz, dy, dx) of row r at term * N + r)
+                G27 = grid_coefficients(rpc, colc, valc, wc.n, wc.N)
+                S27 = solver.stencil(wc.n, wc.n, wc.n, G27, npts=27)
+                pr = {"operator": "27-point stencil with per-row coefficients (pbcgs_op_stencil, coef_per_row = 1), "
+                                  "216 bytes of coefficients per row and product"}
+                for variant in ("pbicgstab_rr", "bicgstab"):
+                    pr[variant] = solve_leg(S27, bc, xc, variant, precond, wc, steps)
+                xs27 = xc.clone()
+                solver.solve(Ac, bc, variant="bicgstab", precond=precond, tol=wc.tol, maxit=wc.maxit,
+                             rr_period=wc.rr_period, out=xc)
+                pr["solution_bitwise_equal_to_assembled"] = bool(torch.equal(xs27, xc))
+                del xs27
+                row["per_row_stencil"] = pr
                 if "fixed" in legs:
                     c3f = {}
                     for key, op_, variant, lay in (
@@ -664,12 +697,14 @@ def main():
                             ("pbicgstab_rr_csr_stream", Ac, "pbicgstab_rr", False),
                             ("bicgstab_csr_stream", Ac, "bicgstab", False),
                             ("pbicgstab_rr_matrix_free", M27, "pbicgstab_rr", True),
-                            ("bicgstab_matrix_free", M27, "bicgstab", True)):
+                            ("bicgstab_matrix_free", M27, "bicgstab", True),
+                            ("pbicgstab_rr_per_row_stencil", S27, "pbicgstab_rr", True),
+                            ("bicgstab_per_row_stencil", S27, "bicgstab", True)):
                         c3f[key] = fixed_iterations(lambda m, op_=op_, variant=variant, lay=lay: solver.solve(
                             op_, bc, variant=variant, precond=precond, tol=0.0, maxit=m, rr_period=wc.rr_period,
                             out=xc, diagonal_layout=lay)[1], 50)
                     fixed[f"c3_{wc.n}"] = c3f
-                del M27
+                del M27, S27, G27
             other_cfg[name] = row
             del Ac, rpc, colc, valc, bc, xc, kappa
             torch.cuda.empty_cache()

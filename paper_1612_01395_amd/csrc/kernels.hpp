@@ -384,8 +384,10 @@ struct GridOp {
   int32_t nx, ny, nz, npts;
   V c[kC];                   // constant coefficients (the 27-point stencil)
 
+  // per-row coefficients are read once per product: the nontemporal hint keeps
+  // them from displacing the gathered vector in the caches
   __device__ __forceinline__ V coef(int d, int32_t row, int32_t n) const {
-    if constexpr (VAR) return cf[(int64_t)d * n + row];
+    if constexpr (VAR) return __builtin_nontemporal_load(&cf[(int64_t)d * n + row]);
     else return c[d];
   }
 
@@ -411,7 +413,7 @@ struct GridOp {
         if (lin) acc = acc + coef(3 * l + 1, rc, n) * V(xc);
         if (lin && i < nx - 1) acc = acc + coef(3 * l + 2, rc, n) * V(xp);
       }
-    } else {
+    } else if constexpr (VAR) {  // constant coefficients are the 27-point stencil only
       const X xc = x[rc];
       const X xe = x[min(max(lane < 32 ? b0 - 1 : b0 + 64, 0), n - 1)];
       const X xm = wave_shift<kWaveShr1>(xe, xc), xp = wave_shift<kWaveShl1>(xe, xc);
@@ -428,6 +430,117 @@ struct GridOp {
       if (npts == 7 && k < nz - 1) acc = acc + coef(d + 5, rc, n) * V(x[rc + nxy]);
     }
     return valid ? acc : V(0);
+  }
+
+  // Rows row and row + 1 (row even) by one lane; all 64 lanes of a 128-row
+  // block call it together.  With an even x extent (then n is even too) the
+  // two rows lie on one grid line and share every neighbour line: each line's
+  // x values and each term's two per-row coefficients are aligned pairs, and
+  // x[row + off - 1], x[row + off + 2] come from the adjacent lanes.  With an
+  // odd extent each row is summed on its own with direct loads.
+  template <class X>
+  __device__ __forceinline__ void spmv2(int32_t row, bool valid0, bool valid1, const X* __restrict__ x, V& y0,
+                                        V& y1) const {
+    typedef X X2 __attribute__((ext_vector_type(2)));
+    const int32_t nxy = nx * ny, n = nxy * nz;
+    if (nx & 1) {
+      y0 = valid0 ? direct(row, x, nxy, n) : V(0);
+      y1 = valid1 ? direct(row + 1, x, nxy, n) : V(0);
+      return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int32_t b0 = row - 2 * lane;
+    const int32_t rc = min(row, n - 2);  // a pair inside the grid for the lanes past it
+    const int32_t i = rc % nx, jk = rc / nx, j = jk % ny, k = jk / ny;
+    V a0 = V(0), a1 = V(0);
+    auto pair = [&](int d, V& c0, V& c1) {
+      if constexpr (VAR) {
+        typedef V V2 __attribute__((ext_vector_type(2)));
+        const V2 q = __builtin_nontemporal_load(reinterpret_cast<const V2*>(&cf[(int64_t)d * n + rc]));
+        c0 = q.x;
+        c1 = q.y;
+      } else {
+        c0 = c[d];
+        c1 = c[d];
+      }
+    };
+    // one neighbour line (offset off, present for both rows or for neither)
+    // with its terms d - 1, d, d + 1 in the x direction; xside: that line has
+    // x-direction terms (27-point) or only the centre term (5/7-point y, z lines)
+    auto line = [&](bool lin, int32_t off, int d, bool xside) {
+      const X2 q = *reinterpret_cast<const X2*>(&x[lin ? rc + off : rc]);
+      if (xside) {
+        const X xe = x[min(max(lane < 32 ? b0 + off - 1 : b0 + 128 + off, 0), n - 1)];
+        const X xm = wave_shift<kWaveShr1>(xe, q.y), xp = wave_shift<kWaveShl1>(xe, q.x);
+        if (lin) {
+          // row: x[row + off - 1], x[row + off], x[row + off + 1] = xm, q.x, q.y;
+          // row + 1: q.x, q.y, xp (i is even, so row + 1 always has its -x term
+          // and row its +x term)
+          V m0, m1, c0, c1, p0, p1;
+          pair(d - 1, m0, m1);
+          pair(d, c0, c1);
+          pair(d + 1, p0, p1);
+          if (i > 0) a0 = a0 + m0 * V(xm);
+          a0 = a0 + c0 * V(q.x);
+          a0 = a0 + p0 * V(q.y);
+          a1 = a1 + m1 * V(q.x);
+          a1 = a1 + c1 * V(q.y);
+          if (i + 1 < nx - 1) a1 = a1 + p1 * V(xp);
+        }
+      } else if (lin) {
+        V c0, c1;
+        pair(d, c0, c1);
+        a0 = a0 + c0 * V(q.x);
+        a1 = a1 + c1 * V(q.y);
+      }
+    };
+    if (npts == 27) {
+#pragma unroll
+      for (int l = 0; l < 9; ++l) {
+        const int dz = l / 3 - 1, dy = l % 3 - 1;
+        const bool lin = (dz < 0 ? k > 0 : (dz > 0 ? k < nz - 1 : true)) && (dy < 0 ? j > 0 : (dy > 0 ? j < ny - 1 : true));
+        line(lin, dz * nxy + dy * nx, 3 * l + 1, true);
+      }
+    } else if constexpr (VAR) {  // constant coefficients are the 27-point stencil only
+      const int base = (npts == 7) ? 1 : 0;  // index of the -y term
+      if (npts == 7) line(k > 0, -nxy, 0, false);
+      line(j > 0, -nx, base, false);
+      line(true, 0, base + 2, true);
+      line(j < ny - 1, nx, base + 4, false);
+      if (npts == 7) line(k < nz - 1, nxy, 6, false);
+    }
+    y0 = valid0 ? a0 : V(0);
+    y1 = valid1 ? a1 : V(0);
+  }
+
+  // Row `row` summed with direct loads of every neighbour (any lane mapping).
+  template <class X>
+  __device__ __forceinline__ V direct(int32_t row, const X* __restrict__ x, int32_t nxy, int32_t n) const {
+    const int32_t i = row % nx, jk = row / nx, j = jk % ny, k = jk / ny;
+    V acc = V(0);
+    if (npts == 27) {
+#pragma unroll
+      for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const bool in = (dz < 0 ? k > 0 : (dz > 0 ? k < nz - 1 : true)) &&
+                        (dy < 0 ? j > 0 : (dy > 0 ? j < ny - 1 : true)) &&
+                        (dx < 0 ? i > 0 : (dx > 0 ? i < nx - 1 : true));
+        if (in) acc = acc + coef(t, row, n) * V(x[row + dz * nxy + dy * nx + dx]);
+      }
+    } else if constexpr (VAR) {
+      int d = 0;
+      if (npts == 7) {
+        if (k > 0) acc = acc + coef(d, row, n) * V(x[row - nxy]);
+        ++d;
+      }
+      if (j > 0) acc = acc + coef(d, row, n) * V(x[row - nx]);
+      if (i > 0) acc = acc + coef(d + 1, row, n) * V(x[row - 1]);
+      acc = acc + coef(d + 2, row, n) * V(x[row]);
+      if (i < nx - 1) acc = acc + coef(d + 3, row, n) * V(x[row + 1]);
+      if (j < ny - 1) acc = acc + coef(d + 4, row, n) * V(x[row + nx]);
+      if (npts == 7 && k < nz - 1) acc = acc + coef(d + 5, row, n) * V(x[row + nxy]);
+    }
+    return acc;
   }
 };
 template <class Op> struct IsGrid : std::false_type {};
@@ -2743,6 +2856,7 @@ __global__ __launch_bounds__(kWG) void k_b5_2(Args a) { d_b5_2(a); }
 template <class Op> struct HasSpmv2 : std::false_type {};
 template <class V, bool P, bool N> struct HasSpmv2<DiaOpT<V, P, N>> : std::true_type {};
 template <int NPTS, class V> struct HasSpmv2<StencilOp<NPTS, V>> : std::true_type {};
+template <class V, bool VAR> struct HasSpmv2<GridOp<V, VAR>> : std::true_type {};
 template <class Op> struct IsStencil : std::false_type {};
 template <int NPTS, class V> struct IsStencil<StencilOp<NPTS, V>> : std::true_type {};
 template <class Op> struct HasSpmv4 : std::false_type {};

@@ -629,7 +629,7 @@ struct Driver {
   bool two_rows64() const {
     if constexpr (!MP && PC == PC_NONE && HasSpmv2<Op>::value) {
       if (o.variant != PBCGS_BICGSTAB && !IsDia<Op>::value) {
-        if constexpr (IsStencil<Op>::value) {
+        if constexpr (IsStencil<Op>::value || IsGrid<Op>::value) {
           if ((op.nx & 1) != 0) return false;
         } else {
           return false;

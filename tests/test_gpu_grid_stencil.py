@@ -257,3 +257,18 @@ def test_refused_uses():
     with pytest.raises(_lib.PbcgsError) as e:
         solver.solve(op, dev_t(np.ones(nx * ny * nz)), precond="jacobi_folded", dinv=dv)
     assert e.value.code == _lib.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("kind", ["27_per_row", "7_per_row", "5_per_row", "27_const"])
+@pytest.mark.parametrize("variant,precision", [("bicgstab", "fp64"), ("pbicgstab_rr", "fp64"),
+                                               ("pbicgstab_rr", "fp32_rr64")])
+@pytest.mark.parametrize("precond", [None, "jacobi_folded"])
+def test_two_rows_per_lane(kind, variant, precision, precond, monkeypatch):
+    """Few workgroups, so every wave owns several blocks and the kernels take
+    two rows per lane: with an even x extent (27_per_row, 5_per_row,
+    27_const) through aligned pairs shared by the lane's two rows, with an odd
+    one (7_per_row) row by row; the same bits either way."""
+    require_gpu()
+    monkeypatch.setenv("PBCGS_GTARGET", "2")
+    info = _compare(kind, variant, precond, precision=precision)
+    assert info.shape[0] >= 2
