@@ -1251,6 +1251,30 @@ __device__ __forceinline__ void update_x4(double* __restrict__ x, int32_t row, i
     if (k < nv) x[row + k] = x[row + k] + u[k] + v[k];
 }
 
+// produce2 for a kernel written row by row: the operator's product for both
+// rows of a lane comes from spmv2 (the two-row loads), and Body(row, valid,
+// y, d) -- the same one-row body produce() would run with y = A x at the row --
+// is called for each row; the pair's leaves are summed as produce2 requires
+// (a row past n leaves its d at 0, a zero leaf).  The body's vector accesses
+// stay one row at a time (8 bytes per lane, every other element), so this
+// pays for kernels that touch few vectors besides the product: measured at
+// 128^3, CG's s = A p and w = A u gained 14-16 %, while p-CG's one kernel
+// (ten vectors read or written) lost a third and keeps one row per lane.
+template <int ND, class Op, class X, class Body>
+__device__ __forceinline__ void produce2_rows(const Args& a, const Op& op, const X* x, Body body) {
+  produce2<ND>(a, [&](int32_t row, bool valid0, bool valid1, double (&d)[ND]) {
+    double y0, y1;
+    op.spmv2(row, valid0, valid1, x, y0, y1);
+    double d0[ND], d1[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) d0[k] = d1[k] = 0.0;
+    body(row, valid0, y0, d0);
+    body(row + 1, valid1, y1, d1);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) d[k] = d0[k] + d1[k];
+  });
+}
+
 // The workgroup's rows without a reduction, two neighbouring rows per lane
 // (as produce2); Body(row, valid0, valid1) with row even; needs R >= 2.
 template <class Body>
@@ -1876,12 +1900,12 @@ __global__ __launch_bounds__(kWG) void k_cg_setup(Op op, Args a) { d_cg_setup<Op
 // Setup of Algorithms 4 and 6, continued: w = A u ; with PIPE (Algorithm 6)
 // and a preconditioner also m = M^{-1} w into w^ ; partials (r, u), (w, u),
 // (r, r).
-template <class Op, int PC, bool PIPE>
+// TWO: two rows per lane for the product (produce2_rows), the same bits.
+template <class Op, int PC, bool PIPE, bool TWO>
 __device__ __forceinline__ void d_cg_setup_w(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   publish(a, st);
-  produce<3>(a, [&](int32_t row, bool valid, double (&d)[3]) {
-    const double w = op.spmv(row, valid, a.rh);
+  auto body = [&](int32_t row, bool valid, double w, double (&d)[3]) {
     if (!valid) return;
     a.w[row] = w;
     if (PIPE && PC != PC_NONE) a.wh[row] = apply_pc<PC>(a, row, w);
@@ -1889,14 +1913,19 @@ __device__ __forceinline__ void d_cg_setup_w(Op op, Args a) {
     d[0] = r * u;
     d[1] = w * u;
     d[2] = r * r;
-  });
+  };
+  if constexpr (TWO) {
+    produce2_rows<3>(a, op, a.rh, body);
+  } else {
+    produce<3>(a, [&](int32_t row, bool valid, double (&d)[3]) { body(row, valid, op.spmv(row, valid, a.rh), d); });
+  }
 }
-template <class Op, int PC, bool PIPE>
-__global__ __launch_bounds__(kWG) void k_cg_setup_w(Op op, Args a) { d_cg_setup_w<Op, PC, PIPE>(op, a); }
+template <class Op, int PC, bool PIPE, bool TWO = false>
+__global__ __launch_bounds__(kWG) void k_cg_setup_w(Op op, Args a) { d_cg_setup_w<Op, PC, PIPE, TWO>(op, a); }
 
 // Algorithm 2, kernel 1: (first iteration: rho0, gamma_0 from the setup) ;
 // s = A p ; partials of (s, p).
-template <class Op>
+template <class Op, bool TWO>
 __device__ __forceinline__ void d_cg_a(Op op, Args a) {
   PBCGS_PROLOGUE(st)
   if (a.first) {
@@ -1912,15 +1941,19 @@ __device__ __forceinline__ void d_cg_a(Op op, Args a) {
   }
   publish(a, st);
   if (st.status != DS_RUNNING) return;
-  produce<1>(a, [&](int32_t row, bool valid, double (&d)[1]) {
-    const double s = op.spmv(row, valid, a.p);
+  auto body = [&](int32_t row, bool valid, double s, double (&d)[1]) {
     if (!valid) return;
     a.s[row] = s;
     d[0] = s * a.p[row];
-  });
+  };
+  if constexpr (TWO) {
+    produce2_rows<1>(a, op, a.p, body);
+  } else {
+    produce<1>(a, [&](int32_t row, bool valid, double (&d)[1]) { body(row, valid, op.spmv(row, valid, a.p), d); });
+  }
 }
-template <class Op>
-__global__ __launch_bounds__(kWG) void k_cg_a(Op op, Args a) { d_cg_a<Op>(op, a); }
+template <class Op, bool TWO = false>
+__global__ __launch_bounds__(kWG) void k_cg_a(Op op, Args a) { d_cg_a<Op, TWO>(op, a); }
 
 // Algorithm 2, kernel 2: alpha = gamma / (s, p) ; x += alpha p ; r -= alpha s ;
 // u = M^{-1} r ; partials (r, u), (r, r).

@@ -640,6 +640,21 @@ struct Driver {
     return false;
   }
 
+  // CG's s = A p and the w = A u of Algorithms 4 and 6 take two rows per lane
+  // on the layout and on stencils with an even x extent (p-CG's iteration
+  // kernel keeps one; PBCGS_TWO_ROWS64=0 turns it off)
+  bool cg_two_rows() const {
+    if constexpr (!MP && HasSpmv2<Op>::value) {
+      if constexpr (IsStencil<Op>::value || IsGrid<Op>::value) {
+        if ((op.nx & 1) != 0) return false;
+      } else if constexpr (!IsDia<Op>::value) {
+        return false;
+      }
+      return a.R >= 2 && env_int("PBCGS_TWO_ROWS64", 1) != 0;
+    }
+    return false;
+  }
+
   // the binary32 kernels take two rows per lane when the operator supports it
   // and every wave owns at least two 64-row blocks (PBCGS_TWO_ROWS=0 turns it off)
   bool two_rows() const {
@@ -679,16 +694,27 @@ struct Driver {
       k_setup_r0<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
     } else if (o.variant == PBCGS_CG) {
       k_cg_setup<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
-    } else if (o.variant == PBCGS_CGCG) {
+    } else if (o.variant == PBCGS_CGCG || o.variant == PBCGS_PIPE_CG) {
       k_cg_setup<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
-      k_cg_setup_w<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP2));
-    } else if (o.variant == PBCGS_PIPE_CG) {
-      k_cg_setup<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
-      k_cg_setup_w<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP2));
+      launch_cg_setup_w(o.variant == PBCGS_PIPE_CG, L(-1, PB_SETUP2));
     } else {
       k_setup_r0<Op, PC, true><<<grid(), kWG, 0, s>>>(op, L(-1, PB_SETUP1));
       k_setup_w0<Op, PC><<<grid(), kWG, 0, s>>>(op, L(PB_SETUP1, PB_SETUP2));
     }
+  }
+
+  // w = A u of Algorithms 4 and 6 (PIPE: Algorithm 6), one or two rows per lane
+  void launch_cg_setup_w(bool pipe, const Args& b) {
+    hipStream_t s = ctx->stream;
+    if constexpr (!MP && HasSpmv2<Op>::value) {
+      if (cg_two_rows()) {
+        if (pipe) k_cg_setup_w<Op, PC, true, true><<<grid(), kWG, 0, s>>>(op, b);
+        else k_cg_setup_w<Op, PC, false, true><<<grid(), kWG, 0, s>>>(op, b);
+        return;
+      }
+    }
+    if (pipe) k_cg_setup_w<Op, PC, true><<<grid(), kWG, 0, s>>>(op, b);
+    else k_cg_setup_w<Op, PC, false><<<grid(), kWG, 0, s>>>(op, b);
   }
 
   // Kernels of iteration i.
@@ -756,14 +782,23 @@ struct Driver {
       }
     }
     if (o.variant == PBCGS_CG) {
-      timed(0, [&] { k_cg_a<Op><<<grid(), kWG, 0, s>>>(op, L(i == 0 ? PB_SETUP1 : -1, PB_A, i == 0)); });
+      timed(0, [&] {
+        const Args b = L(i == 0 ? PB_SETUP1 : -1, PB_A, i == 0);
+        if constexpr (!MP && HasSpmv2<Op>::value) {
+          if (cg_two_rows()) {
+            k_cg_a<Op, true><<<grid(), kWG, 0, s>>>(op, b);
+            return;
+          }
+        }
+        k_cg_a<Op><<<grid(), kWG, 0, s>>>(op, b);
+      });
       timed(1, [&] { k_cg_b<PC><<<grid(), kWG, 0, s>>>(L(PB_A, PB_B)); });
       k_cg_c<PC><<<grid(), kWG, 0, s>>>(L(PB_B, -1));
       return;
     }
     if (o.variant == PBCGS_CGCG) {
       timed(0, [&] { k_cc_a<PC><<<grid(), kWG, 0, s>>>(L(i == 0 ? PB_SETUP2 : PB_B, -1, i == 0)); });
-      timed(1, [&] { k_cg_setup_w<Op, PC, false><<<grid(), kWG, 0, s>>>(op, L(-1, PB_B)); });
+      timed(1, [&] { launch_cg_setup_w(false, L(-1, PB_B)); });
       return;
     }
     if (o.variant == PBCGS_PIPE_CG) {
@@ -885,8 +920,9 @@ struct Driver {
     k.append(reinterpret_cast<const char*>(&op), sizeof(Op));
     k.append(reinterpret_cast<const char*>(&op64), sizeof(Op64));
     // the kernel forms the environment selects are part of the schedule
-    std::snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%lld|%d|%d|%d%d%d|", PC, MP ? 1 : 0, o.variant, m, (long long)(q & 1),
-                  i0 == 0 ? 1 : 0, (int)(i0 & 1), four_rows() ? 1 : 0, two_rows() ? 1 : 0, two_rows64() ? 1 : 0);
+    std::snprintf(buf, sizeof buf, "|%d|%d|%d|%d|%lld|%d|%d|%d%d%d%d|", PC, MP ? 1 : 0, o.variant, m,
+                  (long long)(q & 1), i0 == 0 ? 1 : 0, (int)(i0 & 1), four_rows() ? 1 : 0, two_rows() ? 1 : 0,
+                  two_rows64() ? 1 : 0, cg_two_rows() ? 1 : 0);
     k += buf;
     for (int j = 0; j < m; ++j) {
       const int64_t i = i0 + j;

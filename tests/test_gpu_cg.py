@@ -123,3 +123,19 @@ def test_cg_family_unsupported_combinations():
                 solver.solve(op, b, variant=variant, **kw)
         with pytest.raises(_lib.PbcgsError):
             solver.solve_batched([op], [b], variant=variant)
+
+
+@pytest.mark.parametrize("gtarget", [2, 8])
+@pytest.mark.parametrize("opkind", ["csr", "stencil"])
+@pytest.mark.parametrize("variant", list(ALG))
+def test_cg_family_two_rows_per_lane(variant, opkind, gtarget, monkeypatch):
+    """Few workgroups, so every wave owns several blocks and the product
+    kernels (s = A p, w = A u, p-CG's n = A m) take two rows per lane: on the
+    diagonal layout and on stencils with an even x extent.  Same bits."""
+    require_gpu()
+    monkeypatch.setenv("PBCGS_GTARGET", str(gtarget))
+    for name in ("c1s", "c2s_24"):
+        for precond in (None, "jacobi"):
+            _run(name, variant, precond, opkind)
+    if opkind == "csr":
+        _run("c3s_10", variant, "jacobi", opkind)
