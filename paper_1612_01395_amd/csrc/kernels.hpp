@@ -1259,7 +1259,8 @@ __device__ __forceinline__ void update_x4(double* __restrict__ x, int32_t row, i
 // stay one row at a time (8 bytes per lane, every other element), so this
 // pays for kernels that touch few vectors besides the product: measured at
 // 128^3, CG's s = A p and w = A u gained 14-16 %, while p-CG's one kernel
-// (ten vectors read or written) lost a third and keeps one row per lane.
+// (ten vectors read or written) lost a third that way and has a two-row form
+// of its own with pair accesses (d_pcg2).
 template <int ND, class Op, class X, class Body>
 __device__ __forceinline__ void produce2_rows(const Args& a, const Op& op, const X* x, Body body) {
   produce2<ND>(a, [&](int32_t row, bool valid0, bool valid1, double (&d)[ND]) {
@@ -2104,6 +2105,95 @@ __device__ __forceinline__ void d_pcg(Op op, Args a) {
 }
 template <class Op, int PC>
 __global__ __launch_bounds__(kWG) void k_pcg(Op op, Args a) { d_pcg<Op, PC>(op, a); }
+
+// d_pcg with two neighbouring rows per lane (see produce2): every workspace
+// vector is read and written as a 16-byte pair, the caller's x as a pair when
+// it is 16-byte aligned (else row by row), and the operator provides spmv2.
+// The arithmetic of each row and the reduction trees are d_pcg's, so the
+// results are the same bits.
+template <class Op, int PC>
+__device__ __forceinline__ void d_pcg2(Op op, Args a) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  PBCGS_PROLOGUE(st)
+  double g[3];
+  gather_sums<3>(a, g);
+  if (a.first) fin_cgs_first(st, a.hist, g);
+  else fin_cgs_next(st, a.hist, g);
+  if (st.status == DS_RUNNING) st.iters += 1;  // the x update below
+  publish(a, st);
+  if (st.status != DS_RUNNING) return;
+  const double alpha = st.alpha, beta = st.beta;
+  produce2<3>(a, [&](int32_t row, bool valid0, bool valid1, double (&d)[3]) {
+    double nv[2];
+    op.spmv2(row, valid0, valid1, a.wh, nv[0], nv[1]);
+    if (!valid0) return;
+    auto ld = [&](const double* v, double (&o)[2]) {
+      const D2 q = *reinterpret_cast<const D2*>(&v[row]);
+      o[0] = q.x;
+      o[1] = q.y;
+    };
+    auto stv = [&](double* v, const double (&o)[2]) { *reinterpret_cast<D2*>(&v[row]) = D2{o[0], o[1]}; };
+    double m[2], zo[2], so[2], po[2], ro[2], w[2];
+    ld(a.wh, m);
+    ld(a.z, zo);
+    ld(a.s, so);
+    ld(a.p, po);
+    ld(a.r, ro);
+    if (PC != PC_NONE) ld(a.w, w);
+    else w[0] = m[0], w[1] = m[1];
+    double z[2], sv[2], p[2], r[2], u[2], wn[2], tt[2];
+    if (PC != PC_NONE) {
+      double sho[2], rho[2], q[2];
+      ld(a.sh, sho);
+      ld(a.rh, rho);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        z[k] = nv[k] + beta * zo[k];
+        sv[k] = w[k] + beta * so[k];
+        q[k] = m[k] + beta * sho[k];
+        p[k] = rho[k] + beta * po[k];
+        r[k] = ro[k] - alpha * sv[k];
+        u[k] = rho[k] - alpha * q[k];
+        wn[k] = w[k] - alpha * z[k];
+      }
+      tt[0] = apply_pc<PC>(a, row, wn[0]);
+      tt[1] = valid1 ? apply_pc<PC>(a, row + 1, wn[1]) : 0.0;  // dinv holds n entries
+      stv(a.sh, q);
+      stv(a.rh, u);
+      stv(a.w, wn);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        z[k] = nv[k] + beta * zo[k];
+        sv[k] = w[k] + beta * so[k];
+        p[k] = ro[k] + beta * po[k];
+        r[k] = ro[k] - alpha * sv[k];
+        u[k] = r[k];
+        wn[k] = w[k] - alpha * z[k];
+        tt[k] = wn[k];
+      }
+    }
+    stv(a.z, z);
+    stv(a.s, sv);
+    stv(a.t, tt);
+    stv(a.p, p);
+    stv(a.r, r);
+    if (valid1 && (reinterpret_cast<uintptr_t>(a.x) & 15) == 0) {
+      D2 xx = *reinterpret_cast<const D2*>(&a.x[row]);
+      xx.x = xx.x + alpha * p[0];
+      xx.y = xx.y + alpha * p[1];
+      *reinterpret_cast<D2*>(&a.x[row]) = xx;
+    } else {
+      a.x[row] = a.x[row] + alpha * p[0];
+      if (valid1) a.x[row + 1] = a.x[row + 1] + alpha * p[1];
+    }
+    d[0] = r[0] * u[0] + (valid1 ? r[1] * u[1] : 0.0);
+    d[1] = wn[0] * u[0] + (valid1 ? wn[1] * u[1] : 0.0);
+    d[2] = r[0] * r[0] + (valid1 ? r[1] * r[1] : 0.0);
+  });
+}
+template <class Op, int PC>
+__global__ __launch_bounds__(kWG) void k_pcg2(Op op, Args a) { d_pcg2<Op, PC>(op, a); }
 
 // Final reduction of the CG family.  MODE 0: Algorithm 2's setup (rho0,
 // gamma_0); 1: first reduction of Algorithms 4 and 6; 2: a later one.

@@ -640,9 +640,9 @@ struct Driver {
     return false;
   }
 
-  // CG's s = A p and the w = A u of Algorithms 4 and 6 take two rows per lane
-  // on the layout and on stencils with an even x extent (p-CG's iteration
-  // kernel keeps one; PBCGS_TWO_ROWS64=0 turns it off)
+  // the CG family's product kernels (CG's s = A p, the w = A u of Algorithms 4
+  // and 6, p-CG's iteration kernel) take two rows per lane on the layout and
+  // on stencils with an even x extent (PBCGS_TWO_ROWS64=0 turns it off)
   bool cg_two_rows() const {
     if constexpr (!MP && HasSpmv2<Op>::value) {
       if constexpr (IsStencil<Op>::value || IsGrid<Op>::value) {
@@ -806,7 +806,15 @@ struct Driver {
       // and writes m_{i+1} to the other; the partial sums alternate likewise
       Args b = L(pcg_part(i), pcg_part(i + 1), i == 0);
       if (i & 1) std::swap(b.wh, b.t);
-      timed(0, [&] { k_pcg<Op, PC><<<grid(), kWG, 0, s>>>(op, b); });
+      timed(0, [&] {
+        if constexpr (!MP && HasSpmv2<Op>::value) {
+          if (cg_two_rows()) {
+            k_pcg2<Op, PC><<<grid(), kWG, 0, s>>>(op, b);
+            return;
+          }
+        }
+        k_pcg<Op, PC><<<grid(), kWG, 0, s>>>(op, b);
+      });
       return;
     }
     if (o.variant == PBCGS_BICGSTAB) {

@@ -33,10 +33,12 @@ def _cases():
 
 
 CASES = _cases()
+# an odd row count: the last lane of a two-row block holds one row
+ODD = {"c2s_23": (oracle.assemble_workload(inputs.workload("c2s", n=23)), 3, 23)}
 
 
 def _run(name, variant, precond, opkind="csr", tol=1e-10, maxit=3000, x0=None, **kw):
-    A, dim, n = CASES[name]
+    A, dim, n = {**CASES, **ODD}[name]
     say(f"{variant} {name} precond={precond} op={opkind} tol={tol} maxit={maxit} {kw}")
     b = oracle.spmv(A, inputs.x_true(A.n))
     dv = oracle.jacobi_dinv(A) if precond else None
@@ -139,3 +141,24 @@ def test_cg_family_two_rows_per_lane(variant, opkind, gtarget, monkeypatch):
             _run(name, variant, precond, opkind)
     if opkind == "csr":
         _run("c3s_10", variant, "jacobi", opkind)
+
+
+@pytest.mark.parametrize("gtarget", [2, 8])
+def test_pipe_cg_two_rows_odd_rows_and_unaligned_x(gtarget, monkeypatch):
+    """p-CG's two-row kernel on 23^3 rows (the last pair holds one row), and
+    with the caller's x 16-byte aligned (pair updates) or only 8-byte aligned
+    (row by row): the oracle's bits, the rest of the buffer untouched."""
+    require_gpu()
+    monkeypatch.setenv("PBCGS_GTARGET", str(gtarget))
+    A, _, _ = ODD["c2s_23"]
+    assert A.n % 2 == 1
+    for precond in (None, "jacobi"):
+        ref, _ = _run("c2s_23", "pipe_cg", precond)
+        for shift in (1, 2):
+            buf = dev_t(np.full(A.n + 3, 7.0))
+            out = buf[shift:shift + A.n]
+            assert (out.data_ptr() % 16 == 0) == (shift == 2)
+            x, _ = _run("c2s_23", "pipe_cg", precond, out=out)
+            assert same(x, ref) and same(host(out), ref)
+            hb = host(buf)
+            assert (hb[:shift] == 7.0).all() and (hb[shift + A.n:] == 7.0).all()
