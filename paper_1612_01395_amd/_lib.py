@@ -57,6 +57,7 @@ class Info(ctypes.Structure):
         ("kernel_calls", ctypes.c_int32 * 2),
         ("rows_per_wave_blocks", ctypes.c_int32),
         ("workgroups", ctypes.c_int32),
+        ("value_codes", ctypes.c_int32),
     ]
 
 

@@ -720,6 +720,79 @@ using DiaOpF = DiaOpT<float>;
 using DiaOpB = DiaOpT<double, true>;  // batched: offsets in the system table
 using DiaOpC = DiaOpT<double, false, false>;  // ordinary value loads
 
+// The diagonal layout with its binary64 values given by value indexing (the
+// value compression of CSR-VI, Kourtis, Goumas and Koziris, 2008): slot
+// (d, row) holds a one-byte code into diagonal d's table of at most kViTab
+// distinct values, so the operator is 4 + nd bytes per row instead of
+// 4 + 8 nd.  A product reads the same binary64 value of every present entry
+// as DiaOpT does and sums the same terms in the same order: the same bits.
+constexpr int kViTab = 16;
+struct DiaViOp {
+  using Val = double;
+  const uint32_t* __restrict__ mask;
+  const uint8_t* __restrict__ code;  // [nd][ld]; absent slots hold 0
+  const double* __restrict__ tab;    // [nd][kViTab]
+  int32_t n;
+  int32_t nd;
+  int32_t ld;
+  int32_t pad_ = 0;
+  int32_t off[kMaxDia];
+
+  __device__ __forceinline__ double val(int d, int32_t slot) const {
+    return tab[d * kViTab + code[(int64_t)d * ld + slot]];
+  }
+
+  template <class X>
+  __device__ __forceinline__ double spmv(int32_t row, bool valid, const X* __restrict__ x) const {
+    const int32_t rc = min(row, n - 1);
+    const uint32_t m = valid ? mask[rc] : 0u;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int d = 0; d < nd; ++d) {
+      const bool present = (m >> d) & 1u;
+      const int32_t c = present ? rc + off[d] : rc;  // a present diagonal's column lies in [0, n)
+      const double t = acc + val(d, rc) * double(x[c]);
+      acc = present ? t : acc;
+    }
+    return acc;
+  }
+
+  // Rows row and row + 1 (row even) by one lane, as DiaOpT::spmv2: the two
+  // codes of a diagonal are one 2-byte load.
+  template <class X>
+  __device__ __forceinline__ void spmv2(int32_t row, bool valid0, bool valid1, const X* __restrict__ x, double& y0,
+                                        double& y1) const {
+    typedef X X2 __attribute__((ext_vector_type(2)));
+    const int32_t r0 = min(row, n - 1);
+    const int32_t r1 = min(row + 1, n - 1);
+    const uint32_t m0 = valid0 ? mask[r0] : 0u, m1 = valid1 ? mask[r1] : 0u;
+    // an even slot whose pair lies inside the layout (ld is a multiple of 64)
+    const int32_t rv = min(row, (n - 1) & ~1);
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll 4
+    for (int d = 0; d < nd; ++d) {
+      const bool p0 = (m0 >> d) & 1u, p1 = (m1 >> d) & 1u;
+      const uint16_t cc = *reinterpret_cast<const uint16_t*>(&code[(int64_t)d * ld + rv]);
+      const double v0 = tab[d * kViTab + (cc & 0xff)], v1 = tab[d * kViTab + (cc >> 8)];
+      X x0, x1;
+      // as DiaOpT::spmv2: an even offset with row + 1's entry present makes an aligned pair
+      if ((off[d] & 1) == 0 && p1) {
+        const X2 xx = *reinterpret_cast<const X2*>(&x[row + off[d]]);
+        x0 = xx.x;
+        x1 = xx.y;
+      } else {
+        x0 = x[p0 ? r0 + off[d] : r0];
+        x1 = x[p1 ? r1 + off[d] : r1];
+      }
+      const double t0 = a0 + v0 * double(x0), t1 = a1 + v1 * double(x1);
+      a0 = p0 ? t0 : a0;
+      a1 = p1 ? t1 : a1;
+    }
+    y0 = a0;
+    y1 = a1;
+  }
+};
+
 // Matrix-free 27-point variable-coefficient convection-diffusion operator on
 // the n^3 interior nodes of the unit cube (h = 1/(n+1)), Dirichlet boundaries,
 // rows x fastest.  Its entries are formed from the (n+1)^3 cell coefficients
@@ -2986,6 +3059,8 @@ template <class Op> struct HasSpmv4 : std::false_type {};
 template <class V, bool P, bool N> struct HasSpmv4<DiaOpT<V, P, N>> : std::true_type {};
 template <class Op> struct IsDia : std::false_type {};
 template <class V, bool P, bool N> struct IsDia<DiaOpT<V, P, N>> : std::true_type {};
+template <> struct HasSpmv2<DiaViOp> : std::true_type {};
+template <> struct IsDia<DiaViOp> : std::true_type {};
 
 // Replacement iteration, phase B': omega, then only the binary64 x update.
 __global__ __launch_bounds__(kWG) void k_mp_rr_x(Args a) {
@@ -3628,6 +3703,70 @@ __global__ __launch_bounds__(64) void k_dia_fill(CsrOp op, int32_t n, const int3
   __syncthreads();
   if (r0 + lane < n)
     for (int d = 0; d < nd; ++d) dia[(int64_t)d * ld + r0 + lane] = tile[d][lane];
+}
+
+// Value indexing of the binary64 layout (see DiaViOp).  Each diagonal's table
+// is a kViTab-slot open-addressing set of the bit patterns of the values its
+// present entries hold; kViEmpty (a NaN pattern) marks a free slot.  Which
+// slot a value lands in depends on the order of the atomic operations; the
+// codes are exact whatever the slots.  tab[nd * kViTab] is the overflow word:
+// nonzero when some diagonal holds more than kViTab distinct values (or the
+// marker pattern itself), and then the codes are not made.
+constexpr uint64_t kViEmpty = 0x7ff4a5a5a5a5a5a5ull;
+__device__ __forceinline__ int vi_hash(uint64_t b) {
+  return (int)(((b ^ (b >> 29) ^ (b >> 47)) * 0x9e3779b97f4a7c15ull) >> 60);
+}
+
+__global__ __launch_bounds__(kWG) void k_vi_reset(uint64_t* __restrict__ tab, int32_t nd) {
+  const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < nd * kViTab) tab[i] = kViEmpty;
+  if (i == nd * kViTab) tab[i] = 0;
+}
+
+__global__ __launch_bounds__(kWG) void k_vi_collect(DiaOpC d, uint64_t* __restrict__ tab) {
+  const int32_t row = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (row >= d.n) return;
+  const uint32_t m = d.mask[row];
+  for (int k = 0; k < d.nd; ++k) {
+    if (!((m >> k) & 1u)) continue;
+    const uint64_t b = (uint64_t)__double_as_longlong(d.va[(int64_t)k * d.ld + row]);
+    bool found = false;
+    if (b != kViEmpty) {
+      const int h = vi_hash(b);
+      for (int p = 0; p < kViTab && !found; ++p) {
+        uint64_t* slot = &tab[k * kViTab + ((h + p) & (kViTab - 1))];
+        uint64_t cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == kViEmpty) {
+          const uint64_t old = atomicCAS((unsigned long long*)slot, (unsigned long long)kViEmpty, (unsigned long long)b);
+          cur = old == kViEmpty ? b : old;
+        }
+        found = cur == b;
+      }
+    }
+    if (!found) __hip_atomic_store(&tab[d.nd * kViTab], (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_vi_encode(DiaOpC d, const uint64_t* __restrict__ tab,
+                                                   uint8_t* __restrict__ code) {
+  const int32_t row = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (row >= d.ld) return;
+  const uint32_t m = row < d.n ? d.mask[row] : 0u;
+  for (int k = 0; k < d.nd; ++k) {
+    int c = 0;  // absent slots (and the padding rows) read slot 0, never used
+    if ((m >> k) & 1u) {
+      const uint64_t b = (uint64_t)__double_as_longlong(d.va[(int64_t)k * d.ld + row]);
+      const int h = vi_hash(b);
+      for (int p = 0; p < kViTab; ++p) {
+        const int s = (h + p) & (kViTab - 1);
+        if (tab[k * kViTab + s] == b) {
+          c = s;
+          break;
+        }
+      }
+    }
+    code[(int64_t)k * d.ld + row] = (uint8_t)c;
+  }
 }
 
 // ===========================================================================

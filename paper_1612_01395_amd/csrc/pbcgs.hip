@@ -106,6 +106,8 @@ struct pbcgs_ctx_s {
   size_t a32_cap = 0;       // floats
   void* dia[2] = {nullptr, nullptr};  // values of an operator's diagonal layout for the current solve
   size_t dia_cap[2] = {0, 0};         // bytes (slot 1: the binary64 layout beside a binary32 one)
+  void* vi = nullptr;                 // the layout's value codes and tables (see DiaViOp)
+  size_t vi_cap = 0;                  // bytes
   // batched solves: system table, workgroup map, vectors, states, partials, host poll copies
   SysDesc* bsys = nullptr;
   size_t bsys_cap = 0;
@@ -1636,6 +1638,7 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
   if (ctx->a32) (void)hipFree(ctx->a32);
   for (void* d : ctx->dia)
     if (d) (void)hipFree(d);
+  if (ctx->vi) (void)hipFree(ctx->vi);
   if (ctx->bsys) (void)hipFree(ctx->bsys);
   if (ctx->bmap) (void)hipFree(ctx->bmap);
   if (ctx->bws) (void)hipFree(ctx->bws);
@@ -1866,6 +1869,57 @@ static DiaOpC cached_loads(const DiaOp& d) {
   DiaOpC c;
   std::memcpy(&c, &d, sizeof c);
   return c;
+}
+
+// The value-indexed form of a binary64 layout `d` just filled (see DiaViOp),
+// when every diagonal holds at most kViTab distinct values; false (and no
+// error) when some diagonal holds more, when the buffer cannot be had, or
+// when PBCGS_VALUE_CODES=0.  One host synchronisation reads the overflow word.
+static bool vi_operator(pbcgs_ctx_t ctx, const DiaOp& d, DiaViOp* out) {
+  if (env_int("PBCGS_VALUE_CODES", 1) == 0 || d.nd <= 0) return false;
+  const size_t code_bytes = ((size_t)d.nd * (size_t)d.ld + 255) & ~(size_t)255;
+  const size_t bytes = code_bytes + sizeof(uint64_t) * ((size_t)d.nd * kViTab + 1);
+  if (ctx->vi_cap < bytes) {
+    if (ctx->vi) {
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipFree(ctx->vi);
+      ctx->vi = nullptr;
+      ctx->vi_cap = 0;
+      for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+      ctx->graphs.clear();
+    }
+    if (hipMalloc(&ctx->vi, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->vi = nullptr;
+      return false;
+    }
+    ctx->vi_cap = bytes;
+  }
+  uint8_t* code = static_cast<uint8_t*>(ctx->vi);
+  uint64_t* tab = reinterpret_cast<uint64_t*>(code + code_bytes);
+  const DiaOpC c = cached_loads(d);
+  k_vi_reset<<<(d.nd * kViTab + 1 + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(tab, d.nd);
+  k_vi_collect<<<(d.n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(c, tab);
+  uint64_t overflow = 1;
+  if (hipMemcpyAsync(&overflow, tab + (size_t)d.nd * kViTab, sizeof overflow, hipMemcpyDeviceToHost, ctx->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (overflow != 0) return false;
+  k_vi_encode<<<(d.ld + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(c, tab, code);
+  DiaViOp v;
+  std::memset(&v, 0, sizeof v);
+  v.mask = d.mask;
+  v.code = code;
+  v.tab = reinterpret_cast<const double*>(tab);
+  v.n = d.n;
+  v.nd = d.nd;
+  v.ld = d.ld;
+  for (int k = 0; k < d.nd; ++k) v.off[k] = d.off[k];
+  *out = v;
+  return true;
 }
 }  // extern "C++"
 
@@ -2299,6 +2353,11 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
           DiaOp dop;
           const int rcd = dia_operator<double>(ctx, A, pc, dv, ds, &dop);
           if (rcd != PBCGS_SUCCESS) return rcd;
+          DiaViOp vop;
+          if (vi_operator(ctx, dop, &vop)) {
+            info->value_codes = 1;
+            return run_folded(vop);
+          }
           if (dia_cached(A)) return run_folded(cached_loads(dop));
           return run_folded(dop);
         }
@@ -2311,6 +2370,11 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     DiaOp dop;
     rc = dia_operator<double>(ctx, A, PC_NONE, nullptr, 0.0, &dop);
     if (rc != PBCGS_SUCCESS) return rc;
+    DiaViOp vop;
+    if (pc == PC_NONE && vi_operator(ctx, dop, &vop)) {
+      info->value_codes = 1;
+      return Driver<DiaViOp, PC_NONE>(ctx, vop, a, o).run(info);
+    }
     if (pc == PC_NONE && dia_cached(A)) return Driver<DiaOpC, PC_NONE>(ctx, cached_loads(dop), a, o).run(info);
     if (pc == PC_NONE) return Driver<DiaOp, PC_NONE>(ctx, dop, a, o).run(info);
     if (pc == PC_VEC) return Driver<DiaOp, PC_VEC>(ctx, dop, a, o).run(info);

@@ -295,6 +295,7 @@ class SolveInfo:
     kernel_calls: tuple
     history: torch.Tensor | None = None
     shape: tuple = (0, 0)  # the launch shape that ran: (64-row blocks per wave, workgroups)
+    value_codes: bool = False  # the layout's values were read as codes into per-diagonal tables
 
     @property
     def status_name(self) -> str:
@@ -385,6 +386,7 @@ def _solve(entry, A: Operator, b: torch.Tensor, x0, *, variant, precond, dinv, t
     si = SolveInfo(info.iters, info.n_rr, info.status, info.syncs_per_iter, info.relres_rec, info.relres_true,
                    info.ms, tuple(info.kernel_ms), tuple(info.kernel_calls))
     si.shape = (int(info.rows_per_wave_blocks), int(info.workgroups))
+    si.value_codes = bool(info.value_codes)
     if hist is not None:
         si.history = hist[: info.iters + 1]
     return x, si
