@@ -116,7 +116,7 @@ def parse():
 
 
 def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: bool = True, index_bytes: int = 4,
-                      dia: int = 0):
+                      dia: int = 0, codes: bool = False):
     """Algorithmic HBM bytes of the two dominant kernels of one iteration and
     of the whole iteration: (K_a, K_b, iteration).
 
@@ -128,7 +128,8 @@ def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: boo
     with a constant diagonal is a scalar (no dinv vector).  With ``dia`` > 0
     the operator is read through its diagonal layout instead: a 4-byte mask per
     row and one 8-byte value per diagonal and row (absent entries' slots
-    included).
+    included); with ``codes`` (value indexing, ``SolveInfo.value_codes``) an
+    8-byte word of one-byte codes per row and each diagonal's 16-entry table.
 
     Folded Jacobi (A M^{-1} formed, Algorithm 9 on it): K_a reads w, r, v, s,
     z, p and writes p, s, t, z (10 vectors); K_b reads z, r, s, w, t, x, p, r0
@@ -145,6 +146,8 @@ def algorithmic_bytes(N: int, nnz: int, variant: str, stencil: bool, folded: boo
     """
     vec = 8 * N
     mat = 0 if stencil else (4 * N + 8 * dia * N if dia else 4 * (N + 1) + (8 + index_bytes) * nnz)
+    if dia and codes:
+        mat = 8 * N + 16 * 8 * dia
     if variant == "ca_bicgstab":
         return mat + 4 * vec, mat + 5 * vec, 24 * vec + 2 * mat
     if variant == "bicgstab":
@@ -197,9 +200,11 @@ def fixed_iterations(solve_fn, m: int, warm: int = 3, reps: int = 5):
     is counted."""
     for _ in range(warm):
         solve_fn(m)
-    full = sorted(solve_fn(m).ms for _ in range(reps))[reps // 2]
+    infos = [solve_fn(m) for _ in range(reps)]
+    full = sorted(i.ms for i in infos)[reps // 2]
     setup = sorted(solve_fn(0).ms for _ in range(reps))[reps // 2]
-    return {"us_per_iter": round((full - setup) / m * 1e3, 2), "setup_us": round(setup * 1e3, 1), "iters": m}
+    return {"us_per_iter": round((full - setup) / m * 1e3, 2), "setup_us": round(setup * 1e3, 1), "iters": m,
+            "codes": bool(getattr(infos[-1], "value_codes", False))}
 
 
 def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool, index_bytes: int = 4, dia: int = 0):
@@ -457,7 +462,7 @@ def main():
             r = fixed_iterations(lambda m, op_=op_, variant=variant: solver.solve(
                 op_, b, variant=variant, precond="jacobi_folded", tol=0.0, maxit=m, rr_period=w.rr_period,
                 out=xbuf)[1], 200)
-            _, _, pib = algorithmic_bytes(N, nnz, variant, op_ is S, index_bytes=ib, dia=nd)
+            _, _, pib = algorithmic_bytes(N, nnz, variant, op_ is S, index_bytes=ib, dia=nd, codes=r.pop("codes"))
             r["gbps_effective"] = round(pib / (r["us_per_iter"] * 1e-6) / 1e9, 1)
             c2f[key] = r
         c2f["pbicgstab_over_bicgstab_csr"] = round(c2f["bicgstab_csr"]["us_per_iter"]
@@ -527,7 +532,7 @@ def main():
     # ---- roofline of the dominant kernel: one solve with per-kernel events -------
     _, pinfo = solver.solve(A, b, variant="pbicgstab_rr", precond="jacobi_folded", out=xbuf, time_kernels=True,
                             **common)
-    ba, bb, _ = algorithmic_bytes(N, nnz, "pbicgstab", False, index_bytes=ib, dia=nd)
+    ba, bb, _ = algorithmic_bytes(N, nnz, "pbicgstab", False, index_bytes=ib, dia=nd, codes=pinfo.value_codes)
     avg = [pinfo.kernel_ms[k] / max(pinfo.kernel_calls[k], 1) for k in range(2)]
     dom = 0 if pinfo.kernel_ms[0] >= pinfo.kernel_ms[1] else 1
     dom_bytes = (ba, bb)[dom]
@@ -546,7 +551,9 @@ def main():
         "grid_threads": grid_threads,
         "rows_per_wave_blocks": tune["best"],
         "column_index_bytes": ib,
-        "operator_layout": f"diagonal layout, {nd} diagonals (4-byte row mask + 8 bytes per diagonal and row)"
+        "operator_layout": (f"diagonal layout, {nd} diagonals, value-indexed (an 8-byte word of one-byte codes "
+                            f"per row, a 16-entry value table per diagonal)" if pinfo.value_codes else
+                            f"diagonal layout, {nd} diagonals (4-byte row mask + 8 bytes per diagonal and row)")
         if nd else f"CSR stream, {ib}-byte column indices",
         "avg_launch_us": round(avg[dom] * 1e3, 2),
         "other_kernel_avg_us": round(avg[1 - dom] * 1e3, 2),
@@ -851,7 +858,8 @@ def main():
 
     it, dt, info = res.get("pipe", (0, 1.0, None))
     value = it / dt if it else None
-    _, _, per_iter_bytes = algorithmic_bytes(N, nnz, "pbicgstab", False, index_bytes=ib, dia=nd)
+    _, _, per_iter_bytes = algorithmic_bytes(N, nnz, "pbicgstab", False, index_bytes=ib, dia=nd,
+                                             codes=bool(info and info.value_codes))
     out = {
         "metric": "p-BiCGStab iters/sec + HBM GB/s (3D 7-pt 128^3 FP64) vs plain BiCGStab, same GPU",
         "value": round(value, 2) if value else None,
@@ -882,7 +890,8 @@ def main():
     def leg_summary(key, variant, stencil, folded, index_bytes=ib, dia=nd):
         lit, ldt, linfo = res[key]
         lval = lit / ldt
-        _, _, lbytes = algorithmic_bytes(N, nnz, variant, stencil, folded, index_bytes=index_bytes, dia=dia)
+        _, _, lbytes = algorithmic_bytes(N, nnz, variant, stencil, folded, index_bytes=index_bytes, dia=dia,
+                                         codes=linfo.value_codes)
         return {"iters_per_s": round(lval, 2), "iters_per_solve": linfo.iters,
                 "ms_per_solve": round(ldt / args.steps * 1e3, 3), "gbps_effective": round(lbytes * lval / 1e9, 1),
                 "syncs_per_iter": linfo.syncs_per_iter, "relres_true": linfo.relres_true}

@@ -160,9 +160,10 @@ typedef struct {
                                      batch)                                               */
     int32_t value_codes;          /* 1 when the solve read the diagonal layout's binary64
                                      values as one-byte codes into a table of each
-                                     diagonal's distinct values (value indexing, used when
-                                     no diagonal holds more than 16 distinct values and
-                                     there is no separate preconditioner; same results) */
+                                     diagonal's distinct values (value indexing, used for
+                                     layouts of at most 8 diagonals none of which holds
+                                     more than 16 distinct values, without a separate
+                                     preconditioner; same results)                      */
 } pbcgs_info;
 
 /* Create a context on HIP device `device` working on stream `hip_stream`

@@ -721,72 +721,80 @@ using DiaOpB = DiaOpT<double, true>;  // batched: offsets in the system table
 using DiaOpC = DiaOpT<double, false, false>;  // ordinary value loads
 
 // The diagonal layout with its binary64 values given by value indexing (the
-// value compression of CSR-VI, Kourtis, Goumas and Koziris, 2008): slot
-// (d, row) holds a one-byte code into diagonal d's table of at most kViTab
-// distinct values, so the operator is 4 + nd bytes per row instead of
-// 4 + 8 nd.  A product reads the same binary64 value of every present entry
-// as DiaOpT does and sums the same terms in the same order: the same bits.
+// value compression of CSR-VI, Kourtis, Goumas and Koziris, 2008), for at
+// most kViDia diagonals: row i's word code[i] holds in byte d a code into
+// diagonal d's table of at most kViTab distinct values, or kViAbsent where
+// the row has no entry on d (and in the bytes past nd).  The operator is 8
+// bytes per row instead of 4 + 8 nd, and one load gives a row all its codes,
+// so each diagonal's table read depends on that one load only.  A product
+// reads the same binary64 value of every present entry as DiaOpT does and
+// sums the same terms in the same order: the same bits.
 constexpr int kViTab = 16;
+constexpr int kViDia = 8;
+constexpr uint32_t kViAbsent = 0xffu;
 struct DiaViOp {
   using Val = double;
-  const uint32_t* __restrict__ mask;
-  const uint8_t* __restrict__ code;  // [nd][ld]; absent slots hold 0
-  const double* __restrict__ tab;    // [nd][kViTab]
+  const uint64_t* __restrict__ code;  // [ld] (rows past n: every byte kViAbsent)
+  const double* __restrict__ tab;     // [nd][kViTab]
   int32_t n;
   int32_t nd;
   int32_t ld;
   int32_t pad_ = 0;
-  int32_t off[kMaxDia];
-
-  __device__ __forceinline__ double val(int d, int32_t slot) const {
-    return tab[d * kViTab + code[(int64_t)d * ld + slot]];
-  }
+  int32_t off[kViDia];
 
   template <class X>
   __device__ __forceinline__ double spmv(int32_t row, bool valid, const X* __restrict__ x) const {
     const int32_t rc = min(row, n - 1);
-    const uint32_t m = valid ? mask[rc] : 0u;
+    const uint64_t w = valid ? code[rc] : ~0ull;
     double acc = 0.0;
-#pragma unroll 4
-    for (int d = 0; d < nd; ++d) {
-      const bool present = (m >> d) & 1u;
-      const int32_t c = present ? rc + off[d] : rc;  // a present diagonal's column lies in [0, n)
-      const double t = acc + val(d, rc) * double(x[c]);
-      acc = present ? t : acc;
+#pragma unroll
+    for (int d = 0; d < kViDia; ++d) {
+      if (d < nd) {
+        const uint32_t c = (uint32_t)(w >> (8 * d)) & 0xffu;
+        const bool present = c != kViAbsent;
+        const int32_t col = present ? rc + off[d] : rc;  // a present diagonal's column lies in [0, n)
+        const double t = acc + tab[d * kViTab + (present ? c : 0u)] * double(x[col]);
+        acc = present ? t : acc;
+      }
     }
     return acc;
   }
 
   // Rows row and row + 1 (row even) by one lane, as DiaOpT::spmv2: the two
-  // codes of a diagonal are one 2-byte load.
+  // rows' code words are one 16-byte load.
   template <class X>
   __device__ __forceinline__ void spmv2(int32_t row, bool valid0, bool valid1, const X* __restrict__ x, double& y0,
                                         double& y1) const {
     typedef X X2 __attribute__((ext_vector_type(2)));
+    typedef uint64_t U2 __attribute__((ext_vector_type(2)));
     const int32_t r0 = min(row, n - 1);
     const int32_t r1 = min(row + 1, n - 1);
-    const uint32_t m0 = valid0 ? mask[r0] : 0u, m1 = valid1 ? mask[r1] : 0u;
-    // an even slot whose pair lies inside the layout (ld is a multiple of 64)
+    // an even word whose pair lies inside the array (ld is a multiple of 64)
     const int32_t rv = min(row, (n - 1) & ~1);
+    const U2 ww = *reinterpret_cast<const U2*>(&code[rv]);
+    const uint64_t w0 = valid0 ? (rv == row ? ww.x : code[r0]) : ~0ull;
+    const uint64_t w1 = valid1 ? ww.y : ~0ull;
     double a0 = 0.0, a1 = 0.0;
-#pragma unroll 4
-    for (int d = 0; d < nd; ++d) {
-      const bool p0 = (m0 >> d) & 1u, p1 = (m1 >> d) & 1u;
-      const uint16_t cc = *reinterpret_cast<const uint16_t*>(&code[(int64_t)d * ld + rv]);
-      const double v0 = tab[d * kViTab + (cc & 0xff)], v1 = tab[d * kViTab + (cc >> 8)];
-      X x0, x1;
-      // as DiaOpT::spmv2: an even offset with row + 1's entry present makes an aligned pair
-      if ((off[d] & 1) == 0 && p1) {
-        const X2 xx = *reinterpret_cast<const X2*>(&x[row + off[d]]);
-        x0 = xx.x;
-        x1 = xx.y;
-      } else {
-        x0 = x[p0 ? r0 + off[d] : r0];
-        x1 = x[p1 ? r1 + off[d] : r1];
+#pragma unroll
+    for (int d = 0; d < kViDia; ++d) {
+      if (d < nd) {
+        const uint32_t c0 = (uint32_t)(w0 >> (8 * d)) & 0xffu, c1 = (uint32_t)(w1 >> (8 * d)) & 0xffu;
+        const bool p0 = c0 != kViAbsent, p1 = c1 != kViAbsent;
+        const double v0 = tab[d * kViTab + (p0 ? c0 : 0u)], v1 = tab[d * kViTab + (p1 ? c1 : 0u)];
+        X x0, x1;
+        // as DiaOpT::spmv2: an even offset with row + 1's entry present makes an aligned pair
+        if ((off[d] & 1) == 0 && p1) {
+          const X2 xx = *reinterpret_cast<const X2*>(&x[row + off[d]]);
+          x0 = xx.x;
+          x1 = xx.y;
+        } else {
+          x0 = x[p0 ? r0 + off[d] : r0];
+          x1 = x[p1 ? r1 + off[d] : r1];
+        }
+        const double t0 = a0 + v0 * double(x0), t1 = a1 + v1 * double(x1);
+        a0 = p0 ? t0 : a0;
+        a1 = p1 ? t1 : a1;
       }
-      const double t0 = a0 + v0 * double(x0), t1 = a1 + v1 * double(x1);
-      a0 = p0 ? t0 : a0;
-      a1 = p1 ? t1 : a1;
     }
     y0 = a0;
     y1 = a1;
@@ -3723,50 +3731,71 @@ __global__ __launch_bounds__(kWG) void k_vi_reset(uint64_t* __restrict__ tab, in
   if (i == nd * kViTab) tab[i] = 0;
 }
 
+// Inserts b into diagonal k's set; false when the set is full.
+__device__ __forceinline__ bool vi_insert(uint64_t* __restrict__ tab, int k, uint64_t b) {
+  if (b == kViEmpty) return false;
+  const int h = vi_hash(b);
+  for (int p = 0; p < kViTab; ++p) {
+    uint64_t* slot = &tab[k * kViTab + ((h + p) & (kViTab - 1))];
+    uint64_t cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == kViEmpty) {
+      const uint64_t old = atomicCAS((unsigned long long*)slot, (unsigned long long)kViEmpty, (unsigned long long)b);
+      cur = old == kViEmpty ? b : old;
+    }
+    if (cur == b) return true;
+  }
+  return false;
+}
+
+// One thread per row.  The lanes of a wave that hold the same value on a
+// diagonal are served by one insert (their lowest lane's), so a diagonal of
+// few values costs each wave a few inserts; a wave stops at the first full
+// set, and waves start only while no set is full.
 __global__ __launch_bounds__(kWG) void k_vi_collect(DiaOpC d, uint64_t* __restrict__ tab) {
   const int32_t row = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (row >= d.n) return;
-  const uint32_t m = d.mask[row];
+  uint64_t* over = &tab[d.nd * kViTab];
+  if (__hip_atomic_load(over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;  // wave-uniform
+  const uint32_t m = row < d.n ? d.mask[row] : 0u;
+  const int lane = (int)(threadIdx.x & 63);
   for (int k = 0; k < d.nd; ++k) {
-    if (!((m >> k) & 1u)) continue;
-    const uint64_t b = (uint64_t)__double_as_longlong(d.va[(int64_t)k * d.ld + row]);
-    bool found = false;
-    if (b != kViEmpty) {
-      const int h = vi_hash(b);
-      for (int p = 0; p < kViTab && !found; ++p) {
-        uint64_t* slot = &tab[k * kViTab + ((h + p) & (kViTab - 1))];
-        uint64_t cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur == kViEmpty) {
-          const uint64_t old = atomicCAS((unsigned long long*)slot, (unsigned long long)kViEmpty, (unsigned long long)b);
-          cur = old == kViEmpty ? b : old;
-        }
-        found = cur == b;
+    bool pend = (m >> k) & 1u;
+    const uint64_t b = pend ? (uint64_t)__double_as_longlong(d.va[(int64_t)k * d.ld + row]) : 0ull;
+    for (;;) {
+      const uint64_t act = __ballot(pend);
+      if (act == 0) break;
+      const int leader = __ffsll((unsigned long long)act) - 1;
+      const uint64_t lb = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(b >> 32), leader) << 32) |
+                          (uint64_t)(uint32_t)__shfl((int)(uint32_t)b, leader);
+      if (pend && b == lb) pend = false;
+      int ok = 1;
+      if (lane == leader) ok = vi_insert(tab, k, lb) ? 1 : 0;
+      if (__shfl(ok, leader) == 0) {
+        if (lane == leader) __hip_atomic_store(over, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;  // wave-uniform
       }
     }
-    if (!found) __hip_atomic_store(&tab[d.nd * kViTab], (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
 __global__ __launch_bounds__(kWG) void k_vi_encode(DiaOpC d, const uint64_t* __restrict__ tab,
-                                                   uint8_t* __restrict__ code) {
+                                                   uint64_t* __restrict__ code) {
   const int32_t row = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
   if (row >= d.ld) return;
   const uint32_t m = row < d.n ? d.mask[row] : 0u;
+  uint64_t w = ~0ull;  // every byte kViAbsent
   for (int k = 0; k < d.nd; ++k) {
-    int c = 0;  // absent slots (and the padding rows) read slot 0, never used
-    if ((m >> k) & 1u) {
-      const uint64_t b = (uint64_t)__double_as_longlong(d.va[(int64_t)k * d.ld + row]);
-      const int h = vi_hash(b);
-      for (int p = 0; p < kViTab; ++p) {
-        const int s = (h + p) & (kViTab - 1);
-        if (tab[k * kViTab + s] == b) {
-          c = s;
-          break;
-        }
+    if (!((m >> k) & 1u)) continue;
+    const uint64_t b = (uint64_t)__double_as_longlong(d.va[(int64_t)k * d.ld + row]);
+    const int h = vi_hash(b);
+    for (int p = 0; p < kViTab; ++p) {
+      const int s = (h + p) & (kViTab - 1);
+      if (tab[k * kViTab + s] == b) {
+        w = (w & ~(0xffull << (8 * k))) | ((uint64_t)s << (8 * k));
+        break;
       }
     }
-    code[(int64_t)k * d.ld + row] = (uint8_t)c;
   }
+  code[row] = w;
 }
 
 // ===========================================================================

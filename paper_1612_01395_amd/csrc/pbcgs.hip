@@ -1872,12 +1872,13 @@ static DiaOpC cached_loads(const DiaOp& d) {
 }
 
 // The value-indexed form of a binary64 layout `d` just filled (see DiaViOp),
-// when every diagonal holds at most kViTab distinct values; false (and no
-// error) when some diagonal holds more, when the buffer cannot be had, or
-// when PBCGS_VALUE_CODES=0.  One host synchronisation reads the overflow word.
+// when it has at most kViDia diagonals and every diagonal holds at most
+// kViTab distinct values; false (and no error) otherwise, when the buffer
+// cannot be had, or when PBCGS_VALUE_CODES=0.  One host synchronisation
+// reads the overflow word.
 static bool vi_operator(pbcgs_ctx_t ctx, const DiaOp& d, DiaViOp* out) {
-  if (env_int("PBCGS_VALUE_CODES", 1) == 0 || d.nd <= 0) return false;
-  const size_t code_bytes = ((size_t)d.nd * (size_t)d.ld + 255) & ~(size_t)255;
+  if (env_int("PBCGS_VALUE_CODES", 1) == 0 || d.nd <= 0 || d.nd > kViDia) return false;
+  const size_t code_bytes = ((size_t)d.ld * sizeof(uint64_t) + 255) & ~(size_t)255;
   const size_t bytes = code_bytes + sizeof(uint64_t) * ((size_t)d.nd * kViTab + 1);
   if (ctx->vi_cap < bytes) {
     if (ctx->vi) {
@@ -1895,8 +1896,8 @@ static bool vi_operator(pbcgs_ctx_t ctx, const DiaOp& d, DiaViOp* out) {
     }
     ctx->vi_cap = bytes;
   }
-  uint8_t* code = static_cast<uint8_t*>(ctx->vi);
-  uint64_t* tab = reinterpret_cast<uint64_t*>(code + code_bytes);
+  uint64_t* code = static_cast<uint64_t*>(ctx->vi);
+  uint64_t* tab = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->vi) + code_bytes);
   const DiaOpC c = cached_loads(d);
   k_vi_reset<<<(d.nd * kViTab + 1 + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(tab, d.nd);
   k_vi_collect<<<(d.n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(c, tab);
@@ -1911,7 +1912,6 @@ static bool vi_operator(pbcgs_ctx_t ctx, const DiaOp& d, DiaViOp* out) {
   k_vi_encode<<<(d.ld + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(c, tab, code);
   DiaViOp v;
   std::memset(&v, 0, sizeof v);
-  v.mask = d.mask;
   v.code = code;
   v.tab = reinterpret_cast<const double*>(tab);
   v.n = d.n;

@@ -1,15 +1,17 @@
 """GPU parity of value indexing in the diagonal layout (``SolveInfo.value_codes``).
 
-When no diagonal of a CSR operator's layout holds more than 16 distinct
-binary64 values (after folding Jacobi in), and no separate preconditioner is
-applied, a solve reads each entry's value as a one-byte code into its
-diagonal's table of values.  The products use the same binary64 values in the
-same order, so every solve must equal the oracle bit for bit, and equal the
-same solve with the codes switched off (``PBCGS_VALUE_CODES=0``):
+When a CSR operator's layout has at most 8 diagonals, none of which holds more
+than 16 distinct binary64 values (after folding Jacobi in), and no separate
+preconditioner is applied, a solve reads each entry's value as a one-byte
+code into its diagonal's table of values (one 8-byte word of codes per row).
+The products use the same binary64 values in the same order, so every solve
+must equal the oracle bit for bit, and equal the same solve with the codes
+switched off (``PBCGS_VALUE_CODES=0``):
 
 * which solves use codes: constant-coefficient workloads with folded and
-  without Jacobi do; variable coefficients (27-point, random bands), the
-  literal Jacobi preconditioner and the switch do not;
+  without Jacobi do, and so do 8 constant diagonals; variable coefficients
+  (27-point, random bands), 9 diagonals, the literal Jacobi preconditioner
+  and the switch do not;
 * a table's capacity: 16 distinct values on a diagonal (among them +0 and -0,
   distinct bit patterns) use codes, 17 do not;
 * every BiCGStab variant and the CG family, with one and two rows per lane,
@@ -49,12 +51,12 @@ def _solve(A, op, variant, precond, codes, monkeypatch, **kw):
 
 
 def coded_band(n, per_diag, seed, extra=None):
-    """A banded matrix on diagonals -9, -2, 0, 1, 9 whose off-diagonal entries
-    take per_diag[d] distinct values (cycled by row; -1 holds +0 and -0 among
-    them), with a constant dominant diagonal, so that folding Jacobi keeps the
-    counts.  ``extra`` = (offset, row, value) sets one entry."""
-    rng = np.random.default_rng(seed)
-    offs = (-9, -2, 0, 1, 9)
+    """A banded matrix on diagonal 0 and the offsets d of per_diag whose
+    off-diagonal entries take per_diag[d] distinct values (cycled by row;
+    diagonal -2 holds +0 and -0 among them), with a constant dominant
+    diagonal, so that folding Jacobi keeps the counts.  ``extra`` =
+    (offset, row, value) sets one entry."""
+    offs = sorted(set(per_diag) | {0})
     rows, cols, vals = [], [], []
     for i in range(n):
         for o in offs:
@@ -62,7 +64,7 @@ def coded_band(n, per_diag, seed, extra=None):
             if not 0 <= j < n:
                 continue
             if o == 0:
-                v = 6.0
+                v = 0.0  # set below
             else:
                 k = per_diag[o]
                 pool = np.linspace(-1.0, 1.0, k) + 0.01 * o
@@ -73,13 +75,13 @@ def coded_band(n, per_diag, seed, extra=None):
             cols.append(j)
             vals.append(v)
     vals = np.asarray(vals)
+    vals[np.asarray(rows) == np.asarray(cols)] = 1.0 + 2.0 * sum(1 for o in offs if o != 0)
     if extra is not None:
         o, r, v = extra
         hit = [k for k in range(len(rows)) if rows[k] == r and cols[k] == r + o]
         vals[hit[0]] = v
     rp = np.zeros(n + 1, np.int32)
     np.add.at(rp, np.asarray(rows) + 1, 1)
-    del rng
     return oracle.CSR(np.cumsum(rp).astype(np.int32), np.asarray(cols, np.int32), vals)
 
 
@@ -96,6 +98,14 @@ def test_which_solves_use_codes(monkeypatch):
         say(f"value codes: n={A.n} precond={precond} switch={codes}")
         _, info = _solve(A, op, "pbicgstab_rr", precond, codes, monkeypatch, **kw)
         assert info.value_codes == want, (A.n, precond, codes)
+    for nd, want in ((8, True), (9, False)):
+        offs = [-40, -17, -3, -1, 1, 2, 5, 33][: nd - 1]
+        A = coded_band(2500, {o: 2 for o in offs}, seed=nd)
+        op = csr_op(A)
+        assert op.diagonals == nd
+        say(f"value codes: {nd} diagonals")
+        _, info = _solve(A, op, "pbicgstab_rr", "jacobi_folded", True, monkeypatch, **kw)
+        assert info.value_codes == want, nd
 
 
 @pytest.mark.parametrize("k,want", [(16, True), (17, False)])
