@@ -50,9 +50,11 @@ def test_recorded_traffic_matches_the_sources():
     """The committed counter summary was taken on the current kernels (after a
     kernel change the benchmark reports no traffic until the counters are
     taken again; this test then skips with that reason).  Every recorded
-    launch grid moved at least the algorithmic bytes and at most 15 % more
+    launch grid moved at least the algorithmic bytes and at most 25 % more
     (the excess is re-reads of the gathered vector's neighbours a plane
-    away)."""
+    away, 15-40 MB per launch at 128^3; with the value-coded operator the
+    algorithmic bytes are smallest, so the same excess is up to 20 % of
+    them)."""
     import pytest
     with open(bench.TRAFFIC_FILE) as f:
         t = json.load(f)
@@ -60,12 +62,13 @@ def test_recorded_traffic_matches_the_sources():
         pytest.skip("kernel sources changed since the HBM counters were taken")
     nd = t["diagonals"]
     for k in ("k_pa", "k_pb"):
-        algo = bench.algorithmic_bytes(N, NNZ, "pbicgstab", False, dia=nd)[0 if k == "k_pa" else 1]
+        algo = bench.algorithmic_bytes(N, NNZ, "pbicgstab", False, dia=nd,
+                                       codes=t.get("value_codes", False))[0 if k == "k_pa" else 1]
         grids = t["bytes_per_launch"][k]
         assert grids
         for g in grids:
             got = bench.measured_traffic(k, int(g))
-            assert got is not None and algo < got < 1.15 * algo, (k, g, got, algo)
+            assert got is not None and algo < got < 1.25 * algo, (k, g, got, algo)
         assert bench.measured_traffic(k, 12345) is None
 
 
@@ -77,6 +80,20 @@ def test_diagonal_layout_bytes_at_128():
     assert (ka, kb) == (60 * N + 10 * VEC, 60 * N + 12 * VEC) == (293601280, 327155712)
     assert it == 2 * 60 * N + 22 * VEC
     assert bench.algorithmic_bytes_cg(N, NNZ, "pipe_cg", True, dia=7) == 60 * N + 18 * VEC
+
+
+def test_value_coded_layout_bytes_at_128():
+    """With value indexing the operator is one 8-byte word of codes per row
+    and a 16-entry binary64 table per diagonal, whatever the row's entries."""
+    ka, kb, it = bench.algorithmic_bytes(N, NNZ, "pbicgstab", False, dia=7, codes=True)
+    tabs = 7 * 16 * 8
+    assert (ka, kb) == (8 * N + tabs + 10 * VEC, 8 * N + tabs + 12 * VEC) == (184550272, 218104704)
+    assert it == 2 * (8 * N + tabs) + 22 * VEC
+    b1, b3, itb = bench.algorithmic_bytes(N, NNZ, "bicgstab", False, dia=7, codes=True)
+    assert (b1, b3, itb) == (8 * N + tabs + 3 * VEC, 8 * N + tabs + 2 * VEC, 2 * (8 * N + tabs) + 19 * VEC)
+    # codes only change the bytes of a diagonal layout
+    assert bench.algorithmic_bytes(N, NNZ, "pbicgstab", False, codes=True) == \
+        bench.algorithmic_bytes(N, NNZ, "pbicgstab", False)
 
 
 def test_matrix_free_27_point_bytes_at_256():
