@@ -720,40 +720,48 @@ using DiaOpF = DiaOpT<float>;
 using DiaOpB = DiaOpT<double, true>;  // batched: offsets in the system table
 using DiaOpC = DiaOpT<double, false, false>;  // ordinary value loads
 
-// The diagonal layout with its binary64 values given by value indexing (the
-// value compression of CSR-VI, Kourtis, Goumas and Koziris, 2008), for at
-// most kViDia diagonals: row i's word code[i] holds in byte d a code into
+// The diagonal layout with its values given by value indexing (the value
+// compression of CSR-VI, Kourtis, Goumas and Koziris, 2008), for at most
+// kViDia diagonals: row i's word code[i] holds in byte d a code into
 // diagonal d's table of at most kViTab distinct values, or kViAbsent where
 // the row has no entry on d (and in the bytes past nd).  The operator is 8
-// bytes per row instead of 4 + 8 nd, and one load gives a row all its codes,
-// so each diagonal's table read depends on that one load only.  A product
-// reads the same binary64 value of every present entry as DiaOpT does and
+// bytes per row instead of 4 + sizeof(V) nd, and one load gives a row all its
+// codes, so each diagonal's table read depends on that one load only.  The
+// table keeps each value's bit pattern (binary32 ones zero-extended).  A
+// product reads the same value of every present entry as DiaOpT<V> does and
 // sums the same terms in the same order: the same bits.
 constexpr int kViTab = 16;
 constexpr int kViDia = 8;
 constexpr uint32_t kViAbsent = 0xffu;
-struct DiaViOp {
-  using Val = double;
+template <class V>
+struct DiaViOpT {
+  using Val = V;
   const uint64_t* __restrict__ code;  // [ld] (rows past n: every byte kViAbsent)
-  const double* __restrict__ tab;     // [nd][kViTab]
+  const uint64_t* __restrict__ tab;   // [nd][kViTab] bit patterns
   int32_t n;
   int32_t nd;
   int32_t ld;
   int32_t pad_ = 0;
   int32_t off[kViDia];
 
+  __device__ __forceinline__ V val(int d, uint32_t c, bool present) const {
+    const uint64_t b = tab[d * kViTab + (present ? c : 0u)];
+    if constexpr (sizeof(V) == 8) return __longlong_as_double((long long)b);
+    else return __uint_as_float((uint32_t)b);
+  }
+
   template <class X>
-  __device__ __forceinline__ double spmv(int32_t row, bool valid, const X* __restrict__ x) const {
+  __device__ __forceinline__ V spmv(int32_t row, bool valid, const X* __restrict__ x) const {
     const int32_t rc = min(row, n - 1);
     const uint64_t w = valid ? code[rc] : ~0ull;
-    double acc = 0.0;
+    V acc = V(0);
 #pragma unroll
     for (int d = 0; d < kViDia; ++d) {
       if (d < nd) {
         const uint32_t c = (uint32_t)(w >> (8 * d)) & 0xffu;
         const bool present = c != kViAbsent;
         const int32_t col = present ? rc + off[d] : rc;  // a present diagonal's column lies in [0, n)
-        const double t = acc + tab[d * kViTab + (present ? c : 0u)] * double(x[col]);
+        const V t = acc + val(d, c, present) * V(x[col]);
         acc = present ? t : acc;
       }
     }
@@ -763,8 +771,8 @@ struct DiaViOp {
   // Rows row and row + 1 (row even) by one lane, as DiaOpT::spmv2: the two
   // rows' code words are one 16-byte load.
   template <class X>
-  __device__ __forceinline__ void spmv2(int32_t row, bool valid0, bool valid1, const X* __restrict__ x, double& y0,
-                                        double& y1) const {
+  __device__ __forceinline__ void spmv2(int32_t row, bool valid0, bool valid1, const X* __restrict__ x, V& y0,
+                                        V& y1) const {
     typedef X X2 __attribute__((ext_vector_type(2)));
     typedef uint64_t U2 __attribute__((ext_vector_type(2)));
     const int32_t r0 = min(row, n - 1);
@@ -774,13 +782,13 @@ struct DiaViOp {
     const U2 ww = *reinterpret_cast<const U2*>(&code[rv]);
     const uint64_t w0 = valid0 ? (rv == row ? ww.x : code[r0]) : ~0ull;
     const uint64_t w1 = valid1 ? ww.y : ~0ull;
-    double a0 = 0.0, a1 = 0.0;
+    V a0 = V(0), a1 = V(0);
 #pragma unroll
     for (int d = 0; d < kViDia; ++d) {
       if (d < nd) {
         const uint32_t c0 = (uint32_t)(w0 >> (8 * d)) & 0xffu, c1 = (uint32_t)(w1 >> (8 * d)) & 0xffu;
         const bool p0 = c0 != kViAbsent, p1 = c1 != kViAbsent;
-        const double v0 = tab[d * kViTab + (p0 ? c0 : 0u)], v1 = tab[d * kViTab + (p1 ? c1 : 0u)];
+        const V v0 = val(d, c0, p0), v1 = val(d, c1, p1);
         X x0, x1;
         // as DiaOpT::spmv2: an even offset with row + 1's entry present makes an aligned pair
         if ((off[d] & 1) == 0 && p1) {
@@ -791,7 +799,7 @@ struct DiaViOp {
           x0 = x[p0 ? r0 + off[d] : r0];
           x1 = x[p1 ? r1 + off[d] : r1];
         }
-        const double t0 = a0 + v0 * double(x0), t1 = a1 + v1 * double(x1);
+        const V t0 = a0 + v0 * V(x0), t1 = a1 + v1 * V(x1);
         a0 = p0 ? t0 : a0;
         a1 = p1 ? t1 : a1;
       }
@@ -799,7 +807,86 @@ struct DiaViOp {
     y0 = a0;
     y1 = a1;
   }
+
+  // Rows row .. row + 3 (row a multiple of 4) by one lane, as DiaOpT::spmv4;
+  // nv of the four lie below n.  Their code words are two 16-byte loads when
+  // all four rows exist.
+  template <class X>
+  __device__ __forceinline__ void spmv4(int32_t row, int nv, const X* __restrict__ x, V (&y)[4]) const {
+    typedef X X4 __attribute__((ext_vector_type(4)));
+    typedef X X2 __attribute__((ext_vector_type(2)));
+    typedef uint64_t U2 __attribute__((ext_vector_type(2)));
+    int32_t rr[4];
+    uint64_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rr[k] = min(row + k, n - 1);
+    if (nv == 4) {
+      // row .. row + 3 < n: the four words, 32-byte aligned
+      const U2 a = *reinterpret_cast<const U2*>(&code[row]);
+      const U2 b = *reinterpret_cast<const U2*>(&code[row + 2]);
+      w[0] = a.x;
+      w[1] = a.y;
+      w[2] = b.x;
+      w[3] = b.y;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w[k] = (k < nv) ? code[rr[k]] : ~0ull;
+    }
+    V acc[4] = {V(0), V(0), V(0), V(0)};
+#pragma unroll
+    for (int d = 0; d < kViDia; ++d) {
+      if (d < nd) {
+        bool p[4];
+        V vv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t c = (uint32_t)(w[k] >> (8 * d)) & 0xffu;
+          p[k] = c != kViAbsent;
+          vv[k] = val(d, c, p[k]);
+        }
+        const int32_t o = off[d];
+        X xs[4];
+        // as DiaOpT::spmv4: aligned fours, aligned pairs or single loads by the offset
+        if ((o & 3) == 0 && p[3]) {
+          const X4 q = *reinterpret_cast<const X4*>(&x[row + o]);
+          xs[0] = q.x;
+          xs[1] = q.y;
+          xs[2] = q.z;
+          xs[3] = q.w;
+        } else if ((o & 1) == 0) {
+          if (p[1]) {
+            const X2 q = *reinterpret_cast<const X2*>(&x[row + o]);
+            xs[0] = q.x;
+            xs[1] = q.y;
+          } else {
+            xs[0] = x[p[0] ? rr[0] + o : rr[0]];
+            xs[1] = x[rr[1]];
+          }
+          if (p[3]) {
+            const X2 q = *reinterpret_cast<const X2*>(&x[row + 2 + o]);
+            xs[2] = q.x;
+            xs[3] = q.y;
+          } else {
+            xs[2] = x[p[2] ? rr[2] + o : rr[2]];
+            xs[3] = x[rr[3]];
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) xs[k] = x[p[k] ? rr[k] + o : rr[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const V t = acc[k] + vv[k] * V(xs[k]);
+          acc[k] = p[k] ? t : acc[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) y[k] = acc[k];
+  }
 };
+using DiaViOp = DiaViOpT<double>;
+using DiaViOpF = DiaViOpT<float>;
 
 // Matrix-free 27-point variable-coefficient convection-diffusion operator on
 // the n^3 interior nodes of the unit cube (h = 1/(n+1)), Dirichlet boundaries,
@@ -3067,8 +3154,9 @@ template <class Op> struct HasSpmv4 : std::false_type {};
 template <class V, bool P, bool N> struct HasSpmv4<DiaOpT<V, P, N>> : std::true_type {};
 template <class Op> struct IsDia : std::false_type {};
 template <class V, bool P, bool N> struct IsDia<DiaOpT<V, P, N>> : std::true_type {};
-template <> struct HasSpmv2<DiaViOp> : std::true_type {};
-template <> struct IsDia<DiaViOp> : std::true_type {};
+template <class V> struct HasSpmv2<DiaViOpT<V>> : std::true_type {};
+template <class V> struct HasSpmv4<DiaViOpT<V>> : std::true_type {};
+template <class V> struct IsDia<DiaViOpT<V>> : std::true_type {};
 
 // Replacement iteration, phase B': omega, then only the binary64 x update.
 __global__ __launch_bounds__(kWG) void k_mp_rr_x(Args a) {
@@ -3751,7 +3839,11 @@ __device__ __forceinline__ bool vi_insert(uint64_t* __restrict__ tab, int k, uin
 // diagonal are served by one insert (their lowest lane's), so a diagonal of
 // few values costs each wave a few inserts; a wave stops at the first full
 // set, and waves start only while no set is full.
-__global__ __launch_bounds__(kWG) void k_vi_collect(DiaOpC d, uint64_t* __restrict__ tab) {
+__device__ __forceinline__ uint64_t vi_bits(double v) { return (uint64_t)__double_as_longlong(v); }
+__device__ __forceinline__ uint64_t vi_bits(float v) { return (uint64_t)__float_as_uint(v); }
+
+template <class D>
+__global__ __launch_bounds__(kWG) void k_vi_collect(D d, uint64_t* __restrict__ tab) {
   const int32_t row = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
   uint64_t* over = &tab[d.nd * kViTab];
   if (__hip_atomic_load(over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;  // wave-uniform
@@ -3759,7 +3851,7 @@ __global__ __launch_bounds__(kWG) void k_vi_collect(DiaOpC d, uint64_t* __restri
   const int lane = (int)(threadIdx.x & 63);
   for (int k = 0; k < d.nd; ++k) {
     bool pend = (m >> k) & 1u;
-    const uint64_t b = pend ? (uint64_t)__double_as_longlong(d.va[(int64_t)k * d.ld + row]) : 0ull;
+    const uint64_t b = pend ? vi_bits(d.va[(int64_t)k * d.ld + row]) : 0ull;
     for (;;) {
       const uint64_t act = __ballot(pend);
       if (act == 0) break;
@@ -3777,7 +3869,8 @@ __global__ __launch_bounds__(kWG) void k_vi_collect(DiaOpC d, uint64_t* __restri
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_vi_encode(DiaOpC d, const uint64_t* __restrict__ tab,
+template <class D>
+__global__ __launch_bounds__(kWG) void k_vi_encode(D d, const uint64_t* __restrict__ tab,
                                                    uint64_t* __restrict__ code) {
   const int32_t row = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
   if (row >= d.ld) return;
@@ -3785,7 +3878,7 @@ __global__ __launch_bounds__(kWG) void k_vi_encode(DiaOpC d, const uint64_t* __r
   uint64_t w = ~0ull;  // every byte kViAbsent
   for (int k = 0; k < d.nd; ++k) {
     if (!((m >> k) & 1u)) continue;
-    const uint64_t b = (uint64_t)__double_as_longlong(d.va[(int64_t)k * d.ld + row]);
+    const uint64_t b = vi_bits(d.va[(int64_t)k * d.ld + row]);
     const int h = vi_hash(b);
     for (int p = 0; p < kViTab; ++p) {
       const int s = (h + p) & (kViTab - 1);

@@ -106,8 +106,8 @@ struct pbcgs_ctx_s {
   size_t a32_cap = 0;       // floats
   void* dia[2] = {nullptr, nullptr};  // values of an operator's diagonal layout for the current solve
   size_t dia_cap[2] = {0, 0};         // bytes (slot 1: the binary64 layout beside a binary32 one)
-  void* vi = nullptr;                 // the layout's value codes and tables (see DiaViOp)
-  size_t vi_cap = 0;                  // bytes
+  void* vi[2] = {nullptr, nullptr};   // value codes and tables of the layouts in dia[] (see DiaViOpT)
+  size_t vi_cap[2] = {0, 0};          // bytes
   // batched solves: system table, workgroup map, vectors, states, partials, host poll copies
   SysDesc* bsys = nullptr;
   size_t bsys_cap = 0;
@@ -1638,7 +1638,8 @@ int pbcgs_ctx_destroy(pbcgs_ctx_t ctx) {
   if (ctx->a32) (void)hipFree(ctx->a32);
   for (void* d : ctx->dia)
     if (d) (void)hipFree(d);
-  if (ctx->vi) (void)hipFree(ctx->vi);
+  for (void* v : ctx->vi)
+    if (v) (void)hipFree(v);
   if (ctx->bsys) (void)hipFree(ctx->bsys);
   if (ctx->bmap) (void)hipFree(ctx->bmap);
   if (ctx->bws) (void)hipFree(ctx->bws);
@@ -1871,36 +1872,36 @@ static DiaOpC cached_loads(const DiaOp& d) {
   return c;
 }
 
-// The value-indexed form of a binary64 layout `d` just filled (see DiaViOp),
-// when it has at most kViDia diagonals and every diagonal holds at most
-// kViTab distinct values; false (and no error) otherwise, when the buffer
-// cannot be had, or when PBCGS_VALUE_CODES=0.  One host synchronisation
-// reads the overflow word.
-static bool vi_operator(pbcgs_ctx_t ctx, const DiaOp& d, DiaViOp* out) {
+// The value-indexed form of a layout `d` just filled (see DiaViOpT), in the
+// context's codes buffer `slot`, when it has at most kViDia diagonals and
+// every diagonal holds at most kViTab distinct values; false (and no error)
+// otherwise, when the buffer cannot be had, or when PBCGS_VALUE_CODES=0.  One
+// host synchronisation reads the overflow word.
+template <class V>
+static bool vi_operator(pbcgs_ctx_t ctx, const DiaOpT<V>& d, DiaViOpT<V>* out, int slot = 0) {
   if (env_int("PBCGS_VALUE_CODES", 1) == 0 || d.nd <= 0 || d.nd > kViDia) return false;
   const size_t code_bytes = ((size_t)d.ld * sizeof(uint64_t) + 255) & ~(size_t)255;
   const size_t bytes = code_bytes + sizeof(uint64_t) * ((size_t)d.nd * kViTab + 1);
-  if (ctx->vi_cap < bytes) {
-    if (ctx->vi) {
+  if (ctx->vi_cap[slot] < bytes) {
+    if (ctx->vi[slot]) {
       (void)hipStreamSynchronize(ctx->stream);
-      (void)hipFree(ctx->vi);
-      ctx->vi = nullptr;
-      ctx->vi_cap = 0;
+      (void)hipFree(ctx->vi[slot]);
+      ctx->vi[slot] = nullptr;
+      ctx->vi_cap[slot] = 0;
       for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
       ctx->graphs.clear();
     }
-    if (hipMalloc(&ctx->vi, bytes) != hipSuccess) {
+    if (hipMalloc(&ctx->vi[slot], bytes) != hipSuccess) {
       (void)hipGetLastError();
-      ctx->vi = nullptr;
+      ctx->vi[slot] = nullptr;
       return false;
     }
-    ctx->vi_cap = bytes;
+    ctx->vi_cap[slot] = bytes;
   }
-  uint64_t* code = static_cast<uint64_t*>(ctx->vi);
-  uint64_t* tab = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->vi) + code_bytes);
-  const DiaOpC c = cached_loads(d);
+  uint64_t* code = static_cast<uint64_t*>(ctx->vi[slot]);
+  uint64_t* tab = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->vi[slot]) + code_bytes);
   k_vi_reset<<<(d.nd * kViTab + 1 + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(tab, d.nd);
-  k_vi_collect<<<(d.n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(c, tab);
+  k_vi_collect<<<(d.n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(d, tab);
   uint64_t overflow = 1;
   if (hipMemcpyAsync(&overflow, tab + (size_t)d.nd * kViTab, sizeof overflow, hipMemcpyDeviceToHost, ctx->stream) !=
           hipSuccess ||
@@ -1909,11 +1910,11 @@ static bool vi_operator(pbcgs_ctx_t ctx, const DiaOp& d, DiaViOp* out) {
     return false;
   }
   if (overflow != 0) return false;
-  k_vi_encode<<<(d.ld + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(c, tab, code);
-  DiaViOp v;
+  k_vi_encode<<<(d.ld + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(d, tab, code);
+  DiaViOpT<V> v;
   std::memset(&v, 0, sizeof v);
   v.code = code;
-  v.tab = reinterpret_cast<const double*>(tab);
+  v.tab = tab;
   v.n = d.n;
   v.nd = d.nd;
   v.ld = d.ld;
@@ -2308,6 +2309,14 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
           if (folded) {
             if (pc == PC_VEC) k_fold_x<PC_VEC, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
             else k_fold_x<PC_SCALAR, true><<<xg, kWG, 0, ctx->stream>>>(A->n, x, dv, ds);
+          }
+          // both layouts value-indexed when both fit (the binary32 rounding
+          // never has more distinct values than the binary64 values)
+          DiaViOpF v32;
+          DiaViOp v64;
+          if (vi_operator(ctx, op64, &v64, 1) && vi_operator(ctx, op32, &v32, 0)) {
+            info->value_codes = 1;
+            return run_mp(v32, v64);
           }
           return run_mp(op32, op64);
         }

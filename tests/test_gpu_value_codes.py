@@ -1,8 +1,8 @@
 """GPU parity of value indexing in the diagonal layout (``SolveInfo.value_codes``).
 
 When a CSR operator's layout has at most 8 diagonals, none of which holds more
-than 16 distinct binary64 values (after folding Jacobi in), and no separate
-preconditioner is applied, a solve reads each entry's value as a one-byte
+than 16 distinct values (after folding Jacobi in; binary64, or binary32 and
+binary64 for the precision form), and no separate preconditioner is applied, a solve reads each entry's value as a one-byte
 code into its diagonal's table of values (one 8-byte word of codes per row).
 The products use the same binary64 values in the same order, so every solve
 must equal the oracle bit for bit, and equal the same solve with the codes
@@ -16,6 +16,8 @@ switched off (``PBCGS_VALUE_CODES=0``):
   distinct bit patterns) use codes, 17 do not;
 * every BiCGStab variant and the CG family, with one and two rows per lane,
   on an odd row count;
+* the binary32 form with binary32 and binary64 tables, with one, two and
+  four rows per lane, offsets of every residue modulo 4 and ragged fours;
 * values changed between solves: the codes are made again for each solve,
   and a solve whose values no longer fit falls back to the values.
 """
@@ -168,3 +170,41 @@ def test_values_changed_between_solves(monkeypatch):
     val.copy_(dev_t(C.val))
     torch.cuda.synchronize()
     run(C, True)
+
+
+@pytest.mark.parametrize("gtarget", [1, 2, 8])
+@pytest.mark.parametrize("case", ["c2_23", "c1", "band"])
+def test_precision_form_bitwise(case, gtarget, monkeypatch):
+    """The binary32 form with both layouts value-indexed (binary32 tables for
+    the iteration's four- and two-row products, binary64 ones for the
+    replacement steps): the oracle's bits, and the same bits as on the
+    layouts' values.  The band has offsets of every residue modulo 4 (aligned
+    fours, aligned pairs, single loads) and 16 values with +0 and -0 on one
+    diagonal; 1003 rows leave a last four with three rows."""
+    require_gpu()
+    monkeypatch.setenv("PBCGS_GTARGET", str(gtarget))
+    if case == "c2_23":
+        A = oracle.assemble_workload(inputs.workload("c2", n=23))
+    elif case == "c1":
+        A = oracle.assemble_workload(inputs.workload("c1"))
+    else:
+        A = coded_band(1003, {-9: 3, -4: 2, -2: 16, 1: 5, 8: 1}, seed=11)
+    op = csr_op(A)
+    b = oracle.spmv(A, inputs.x_true(A.n))
+    kw = dict(tol=1e-9, maxit=1500, rr_period=10)
+    for folded in (True, False):
+        d = oracle.jacobi_dinv(A) if folded else None
+        x_or, i_or = oracle.solve_mp(A, b, dinv=d, history=True, **kw)
+        got = []
+        for codes in ("1", "0"):
+            monkeypatch.setenv("PBCGS_VALUE_CODES", codes)
+            say(f"value codes {codes}: precision form {case} folded={folded} gtarget={gtarget}")
+            x, info = solver.solve(op, dev_t(b), variant="pbicgstab_rr", precond="jacobi_folded" if folded else None,
+                                   precision="fp32_rr64", history=True, **kw)
+            assert info.value_codes == (codes == "1")
+            assert (info.status, info.iters, info.n_rr) == (i_or["status"], i_or["iters"], i_or["n_rr"]), (info, i_or)
+            assert same(host(x), x_or), float(np.abs(host(x) - x_or).max())
+            assert same(host(info.history), i_or["history"])
+            got.append(info.shape[0])
+        if gtarget == 1:
+            assert got[0] >= 4  # every wave owns at least four blocks: four rows per lane
