@@ -158,12 +158,13 @@ typedef struct {
     int32_t rows_per_wave_blocks; /* the launch shape that ran: 64-row blocks per wave,  */
     int32_t workgroups;           /* and workgroups of 256 threads (the system's own in a
                                      batch)                                               */
-    int32_t value_codes;          /* 1 when the solve read the diagonal layout's binary64
-                                     values as one-byte codes into a table of each
-                                     diagonal's distinct values (value indexing, used for
-                                     layouts of at most 8 diagonals none of which holds
-                                     more than 16 distinct values, without a separate
-                                     preconditioner; same results)                      */
+    int32_t value_codes;          /* 1 when the solve read its diagonal layout's values
+                                     (binary64, or binary32 and binary64 for the
+                                     precision form) as one-byte codes into a table of
+                                     each diagonal's distinct values (value indexing, used
+                                     for layouts of at most 8 diagonals none of which
+                                     holds more than 16 distinct values, without a
+                                     separate preconditioner; same results)             */
 } pbcgs_info;
 
 /* Create a context on HIP device `device` working on stream `hip_stream`
