@@ -1110,7 +1110,7 @@ struct Args {
   int32_t Gin;            // partials to consume (workgroups of the producer)
   int32_t first;          // first iteration: consume the setup reduction
   int32_t mode;           // precision form: 1 = reduction after a forced replacement
-  int32_t wg;             // workgroup index within the system (-1: blockIdx.x)
+  int32_t wg;             // workgroup index within the system (-1: blockIdx.x; -2: XCD-contiguous)
   int32_t pstride;        // stride between the ND partial-sum rows (kMaxG, or the batch's workgroups)
   int32_t par;            // batched launches: state slot read (written: par ^ 1)
   int32_t aform;          // alpha_{i+1} of the pipelined solvers: 5 = eq. (5), otherwise eq. (3)
@@ -1227,8 +1227,20 @@ __device__ __forceinline__ void gather_sums(const Args& a, double (&res)[ND]) {
   for (int k = 0; k < ND; ++k) res[k] = double(tot[k] + T(0));
 }
 
-// Index of this workgroup among the workgroups of its system.
-__device__ __forceinline__ int wg_index(const Args& a) { return a.wg >= 0 ? a.wg : (int)blockIdx.x; }
+// Index of this workgroup among the workgroups of its system.  With
+// wg == -2, consecutive indices share an XCD: the hardware deals the
+// workgroups of a launch to the 8 XCDs in turn (workgroup b runs on XCD
+// b % 8), so XCD x is given the x-th contiguous run of indices, and a row's
+// neighbours a grid plane away are mostly read through the same L2.  The map
+// is a bijection of [0, gridDim.x); which rows and partial slot an index owns
+// is unchanged, so are the results.
+__device__ __forceinline__ int wg_index(const Args& a) {
+  if (a.wg >= 0) return a.wg;
+  const int b = (int)blockIdx.x;
+  if (a.wg == -1) return b;
+  const int G = (int)gridDim.x, q = G >> 3, r = G & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
 // first thread of the system's first workgroup (batched launches hold many systems)
 __device__ __forceinline__ bool sys_leader(const Args& a) { return wg_index(a) == 0 && threadIdx.x == 0; }
 
