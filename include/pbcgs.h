@@ -297,8 +297,14 @@ int pbcgs_op_index_bytes(pbcgs_op_t op);
  * doubles of context workspace, or floats in the precision form): per row the
  * mask and one value per diagonal, no row pointers or column indices.  Each
  * row is still summed over its entries in ascending column order, so results
- * equal those of the CSR arrays bit for bit.  pbcgs_spmv, pbcgs_solve_noalloc
- * and batched solves read the CSR arrays. */
+ * equal those of the CSR arrays bit for bit.  With at most 8 diagonals, each
+ * holding at most 16 distinct values in the solve (after folding Jacobi in),
+ * and no separate preconditioner, a solve reads the laid-out values as
+ * one-byte codes into per-diagonal tables instead (value indexing: one 8-byte
+ * word per row and 128 bytes per diagonal of context workspace; same results;
+ * pbcgs_info.value_codes).  pbcgs_spmv and pbcgs_solve_noalloc read the CSR
+ * arrays; a batch reads every system's layout (values, not codes) when all
+ * its systems have one. */
 int pbcgs_op_diagonals(pbcgs_op_t op);
 
 /* Which column form the solves read for op (see pbcgs_op_csr). */
