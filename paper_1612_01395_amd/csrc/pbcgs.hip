@@ -1875,11 +1875,17 @@ static DiaOpC cached_loads(const DiaOp& d) {
 // The value-indexed form of a layout `d` just filled (see DiaViOpT), in the
 // context's codes buffer `slot`, when it has at most kViDia diagonals and
 // every diagonal holds at most kViTab distinct values; false (and no error)
-// otherwise, when the buffer cannot be had, or when PBCGS_VALUE_CODES=0.  One
-// host synchronisation reads the overflow word.
+// otherwise or when the buffer cannot be had.  PBCGS_VALUE_CODES=0 never
+// takes it, =1 wherever it fits; by default only from kViMinRows rows up:
+// below that a solve is bound by latency, and the codes' extra dependent load
+// per row cost more than their bytes saved (2-D 64^2: 13.1 against 12.4 us
+// per iteration; 16^3 to 48^3 within 0.3-1.5 us; 96^3: 43.9 against 52.9).
+// One host synchronisation reads the overflow word.
+constexpr int32_t kViMinRows = 1 << 18;
 template <class V>
 static bool vi_operator(pbcgs_ctx_t ctx, const DiaOpT<V>& d, DiaViOpT<V>* out, int slot = 0) {
-  if (env_int("PBCGS_VALUE_CODES", 1) == 0 || d.nd <= 0 || d.nd > kViDia) return false;
+  const int mode = env_int("PBCGS_VALUE_CODES", -1);
+  if (mode == 0 || (mode < 0 && d.n < kViMinRows) || d.nd <= 0 || d.nd > kViDia) return false;
   const size_t code_bytes = ((size_t)d.ld * sizeof(uint64_t) + 255) & ~(size_t)255;
   const size_t bytes = code_bytes + sizeof(uint64_t) * ((size_t)d.nd * kViTab + 1);
   if (ctx->vi_cap[slot] < bytes) {

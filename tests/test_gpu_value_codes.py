@@ -11,7 +11,8 @@ switched off (``PBCGS_VALUE_CODES=0``):
 * which solves use codes: constant-coefficient workloads with folded and
   without Jacobi do, and so do 8 constant diagonals; variable coefficients
   (27-point, random bands), 9 diagonals, the literal Jacobi preconditioner
-  and the switch do not;
+  and the switch do not; without the switch only from 2^18 rows up (the
+  other tests force them with ``PBCGS_VALUE_CODES=1``);
 * a table's capacity: 16 distinct values on a diagonal (among them +0 and -0,
   distinct bit patterns) use codes, 17 do not;
 * every BiCGStab variant and the CG family, with one and two rows per lane,
@@ -108,6 +109,22 @@ def test_which_solves_use_codes(monkeypatch):
         say(f"value codes: {nd} diagonals")
         _, info = _solve(A, op, "pbicgstab_rr", "jacobi_folded", True, monkeypatch, **kw)
         assert info.value_codes == want, nd
+
+
+def test_default_from_2_to_the_18_rows(monkeypatch):
+    """Without the switch, codes are taken from 2^18 rows up (below that a
+    solve is latency-bound); the results are the oracle's either way."""
+    require_gpu()
+    monkeypatch.delenv("PBCGS_VALUE_CODES", raising=False)
+    kw = dict(tol=1e-10, maxit=600, rr_period=50)
+    for n, want in ((24, False), (63, False), (64, True)):
+        A = oracle.assemble_workload(inputs.workload("c2", n=n))
+        b = oracle.spmv(A, inputs.x_true(A.n))
+        say(f"value codes by default: c2 n={n} rows={A.n}")
+        x, info = solver.solve(csr_op(A), dev_t(b), variant="pbicgstab_rr", precond="jacobi_folded", **kw)
+        x_or, i_or = oracle.solve_folded(A, b, algo=oracle.ALG_PBICGSTAB_RR, dinv=oracle.jacobi_dinv(A), **kw)
+        assert info.value_codes == want, n
+        assert info.iters == i_or["iters"] and same(host(x), x_or)
 
 
 @pytest.mark.parametrize("k,want", [(16, True), (17, False)])
