@@ -3847,35 +3847,48 @@ __device__ __forceinline__ bool vi_insert(uint64_t* __restrict__ tab, int k, uin
   return false;
 }
 
-// One thread per row.  The lanes of a wave that hold the same value on a
-// diagonal are served by one insert (their lowest lane's), so a diagonal of
-// few values costs each wave a few inserts; a wave stops at the first full
-// set, and waves start only while no set is full.
 __device__ __forceinline__ uint64_t vi_bits(double v) { return (uint64_t)__double_as_longlong(v); }
 __device__ __forceinline__ uint64_t vi_bits(float v) { return (uint64_t)__float_as_uint(v); }
 
+// Each wave walks its rows 64 at a time (a grid-stride loop).  The lanes
+// that hold the same value on a diagonal are served by one insert (their
+// lowest lane's), and a value the wave inserted last on that diagonal needs
+// none, so a diagonal of few values costs each wave a few inserts in all.  A
+// wave stops at the first full set, and at the start of each step once any
+// set is full.  At most kViDia diagonals (the host checks).
 template <class D>
 __global__ __launch_bounds__(kWG) void k_vi_collect(D d, uint64_t* __restrict__ tab) {
-  const int32_t row = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
   uint64_t* over = &tab[d.nd * kViTab];
-  if (__hip_atomic_load(over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;  // wave-uniform
-  const uint32_t m = row < d.n ? d.mask[row] : 0u;
   const int lane = (int)(threadIdx.x & 63);
-  for (int k = 0; k < d.nd; ++k) {
-    bool pend = (m >> k) & 1u;
-    const uint64_t b = pend ? vi_bits(d.va[(int64_t)k * d.ld + row]) : 0ull;
-    for (;;) {
-      const uint64_t act = __ballot(pend);
-      if (act == 0) break;
-      const int leader = __ffsll((unsigned long long)act) - 1;
-      const uint64_t lb = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(b >> 32), leader) << 32) |
-                          (uint64_t)(uint32_t)__shfl((int)(uint32_t)b, leader);
-      if (pend && b == lb) pend = false;
-      int ok = 1;
-      if (lane == leader) ok = vi_insert(tab, k, lb) ? 1 : 0;
-      if (__shfl(ok, leader) == 0) {
-        if (lane == leader) __hip_atomic_store(over, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return;  // wave-uniform
+  uint64_t last[kViDia];  // wave-uniform
+#pragma unroll
+  for (int k = 0; k < kViDia; ++k) last[k] = kViEmpty;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < d.n; base += stride) {
+    if (__hip_atomic_load(over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;  // wave-uniform
+    const int64_t row = base + lane;
+    const uint32_t m = row < d.n ? d.mask[row] : 0u;
+#pragma unroll
+    for (int k = 0; k < kViDia; ++k) {
+      if (k < d.nd) {
+        bool pend = (m >> k) & 1u;
+        const uint64_t b = pend ? vi_bits(d.va[(int64_t)k * d.ld + row]) : 0ull;
+        if (pend && b == last[k]) pend = false;
+        for (;;) {
+          const uint64_t act = __ballot(pend);
+          if (act == 0) break;
+          const int leader = __ffsll((unsigned long long)act) - 1;
+          const uint64_t lb = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(b >> 32), leader) << 32) |
+                              (uint64_t)(uint32_t)__shfl((int)(uint32_t)b, leader);
+          if (pend && b == lb) pend = false;
+          int ok = 1;
+          if (lane == leader) ok = vi_insert(tab, k, lb) ? 1 : 0;
+          if (__shfl(ok, leader) == 0) {
+            if (lane == leader) __hip_atomic_store(over, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;  // wave-uniform
+          }
+          last[k] = lb;
+        }
       }
     }
   }

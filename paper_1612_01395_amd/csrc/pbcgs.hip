@@ -1907,7 +1907,7 @@ static bool vi_operator(pbcgs_ctx_t ctx, const DiaOpT<V>& d, DiaViOpT<V>* out, i
   uint64_t* code = static_cast<uint64_t*>(ctx->vi[slot]);
   uint64_t* tab = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->vi[slot]) + code_bytes);
   k_vi_reset<<<(d.nd * kViTab + 1 + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(tab, d.nd);
-  k_vi_collect<<<(d.n + kWG - 1) / kWG, kWG, 0, ctx->stream>>>(d, tab);
+  k_vi_collect<<<std::min((d.n + kWG - 1) / kWG, 1024), kWG, 0, ctx->stream>>>(d, tab);
   uint64_t overflow = 1;
   if (hipMemcpyAsync(&overflow, tab + (size_t)d.nd * kViTab, sizeof overflow, hipMemcpyDeviceToHost, ctx->stream) !=
           hipSuccess ||
