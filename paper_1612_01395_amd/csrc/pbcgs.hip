@@ -2394,10 +2394,13 @@ int pbcgs_solve(pbcgs_ctx_t ctx, pbcgs_op_t A, const double* b, double* x, const
     DiaOp dop;
     rc = dia_operator<double>(ctx, A, PC_NONE, nullptr, 0.0, &dop);
     if (rc != PBCGS_SUCCESS) return rc;
+    // value-indexed without a preconditioner and with Jacobi by a constant
+    // diagonal (a scalar); a Jacobi vector keeps the values
     DiaViOp vop;
-    if (pc == PC_NONE && vi_operator(ctx, dop, &vop)) {
+    if (pc != PC_VEC && vi_operator(ctx, dop, &vop)) {
       info->value_codes = 1;
-      return Driver<DiaViOp, PC_NONE>(ctx, vop, a, o).run(info);
+      if (pc == PC_NONE) return Driver<DiaViOp, PC_NONE>(ctx, vop, a, o).run(info);
+      return Driver<DiaViOp, PC_SCALAR>(ctx, vop, a, o).run(info);
     }
     if (pc == PC_NONE && dia_cached(A)) return Driver<DiaOpC, PC_NONE>(ctx, cached_loads(dop), a, o).run(info);
     if (pc == PC_NONE) return Driver<DiaOp, PC_NONE>(ctx, dop, a, o).run(info);

@@ -8,10 +8,11 @@ The products use the same binary64 values in the same order, so every solve
 must equal the oracle bit for bit, and equal the same solve with the codes
 switched off (``PBCGS_VALUE_CODES=0``):
 
-* which solves use codes: constant-coefficient workloads with folded and
-  without Jacobi do, and so do 8 constant diagonals; variable coefficients
-  (27-point, random bands), 9 diagonals, the literal Jacobi preconditioner
-  and the switch do not; without the switch only from 2^18 rows up (the
+* which solves use codes: constant-coefficient workloads without, with
+  folded and with literal Jacobi by a constant diagonal do, and so do 8
+  constant diagonals and a diagonal of two values folded; variable
+  coefficients (27-point, random bands), 9 diagonals, literal Jacobi by a
+  vector and the switch do not; without the switch only from 2^18 rows up (the
   other tests force them with ``PBCGS_VALUE_CODES=1``);
 * a table's capacity: 16 distinct values on a diagonal (among them +0 and -0,
   distinct bit patterns) use codes, 17 do not;
@@ -93,8 +94,13 @@ def test_which_solves_use_codes(monkeypatch):
     c2 = oracle.assemble_workload(inputs.workload("c2", n=24))
     c3 = oracle.assemble_workload(inputs.workload("c3", n=10), inputs.kappa_cells(10))
     kw = dict(tol=1e-10, maxit=600, rr_period=13)
+    # a Jacobi vector: a banded matrix whose diagonal takes two values
+    V = coded_band(2000, {-9: 2, -1: 3, 1: 3, 9: 2}, seed=4)
+    dg = np.repeat(np.arange(V.n), np.diff(V.row_ptr)) == V.col
+    V.val[dg] = np.where(np.arange(V.n) % 2 == 0, 9.0, 11.0)
     for A, precond, codes, want in ((c2, "jacobi_folded", True, True), (c2, None, True, True),
-                                    (c2, "jacobi", True, False), (c2, "jacobi_folded", False, False),
+                                    (c2, "jacobi", True, True), (c2, "jacobi_folded", False, False),
+                                    (V, "jacobi", True, False), (V, "jacobi_folded", True, True),
                                     (c3, "jacobi_folded", True, False), (c3, None, True, False)):
         op = csr_op(A)
         assert op.diagonals > 0
@@ -143,9 +149,10 @@ def test_table_capacity(k, want, precond, monkeypatch):
 
 @pytest.mark.parametrize("gtarget", [1, 8])
 @pytest.mark.parametrize("variant,precond", [
-    ("pbicgstab_rr", "jacobi_folded"), ("pbicgstab_rr", None), ("pbicgstab", "jacobi_folded"),
-    ("bicgstab", "jacobi_folded"), ("bicgstab", None), ("ca_bicgstab", "jacobi_folded"),
-    ("cg", None), ("cgcg", None), ("pipe_cg", None)])
+    ("pbicgstab_rr", "jacobi_folded"), ("pbicgstab_rr", None), ("pbicgstab_rr", "jacobi"),
+    ("pbicgstab", "jacobi_folded"), ("bicgstab", "jacobi_folded"), ("bicgstab", None), ("bicgstab", "jacobi"),
+    ("ca_bicgstab", "jacobi_folded"), ("cg", None), ("cgcg", None), ("pipe_cg", None), ("cg", "jacobi"),
+    ("cgcg", "jacobi"), ("pipe_cg", "jacobi")])
 def test_variants_bitwise(variant, precond, gtarget, monkeypatch):
     require_gpu()
     monkeypatch.setenv("PBCGS_GTARGET", str(gtarget))
