@@ -207,7 +207,8 @@ def fixed_iterations(solve_fn, m: int, warm: int = 3, reps: int = 5):
             "codes": bool(getattr(infos[-1], "value_codes", False))}
 
 
-def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool, index_bytes: int = 4, dia: int = 0):
+def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool, index_bytes: int = 4, dia: int = 0,
+                         codes: bool = False):
     """Algorithmic HBM bytes of one iteration of the CG family (Section 2) on
     a CSR operator with Jacobi by a constant (a scalar, no vector) or none.
 
@@ -222,6 +223,8 @@ def algorithmic_bytes_cg(N: int, nnz: int, variant: str, jacobi: bool, index_byt
     """
     vec = 8 * N
     mat = 4 * N + 8 * dia * N if dia else 4 * (N + 1) + (8 + index_bytes) * nnz
+    if dia and codes:
+        mat = 8 * N + 16 * 8 * dia  # value-indexed layout (see algorithmic_bytes)
     passes = {"cg": (12, 11), "cgcg": (14, 11), "pipe_cg": (18, 12)}[variant][0 if jacobi else 1]
     return passes * vec + mat
 
@@ -522,7 +525,8 @@ def main():
                 entry[variant] = {"iters_per_s": round(rate, 2), "iters_per_solve": cinfo.iters,
                                   "ms_per_solve": round(cdt / args.steps * 1e3, 3),
                                   "gbps_effective": round(algorithmic_bytes_cg(ws.N, vals.numel(), variant, True,
-                                                                              As.index_bytes, As.diagonals)
+                                                                              As.index_bytes, As.diagonals,
+                                                                              cinfo.value_codes)
                                                           * rate / 1e9, 1),
                                   "syncs_per_iter": cinfo.syncs_per_iter, "relres_true": cinfo.relres_true}
             cgfam[f"{side}^3"] = entry

@@ -91,6 +91,7 @@ def test_value_coded_layout_bytes_at_128():
     assert it == 2 * (8 * N + tabs) + 22 * VEC
     b1, b3, itb = bench.algorithmic_bytes(N, NNZ, "bicgstab", False, dia=7, codes=True)
     assert (b1, b3, itb) == (8 * N + tabs + 3 * VEC, 8 * N + tabs + 2 * VEC, 2 * (8 * N + tabs) + 19 * VEC)
+    assert bench.algorithmic_bytes_cg(N, NNZ, "pipe_cg", True, dia=7, codes=True) == 8 * N + tabs + 18 * VEC
     # codes only change the bytes of a diagonal layout
     assert bench.algorithmic_bytes(N, NNZ, "pbicgstab", False, codes=True) == \
         bench.algorithmic_bytes(N, NNZ, "pbicgstab", False)
