@@ -163,8 +163,8 @@ typedef struct {
                                      precision form) as one-byte codes into a table of
                                      each diagonal's distinct values (value indexing, used
                                      for layouts of at most 8 diagonals none of which
-                                     holds more than 16 distinct values, without a
-                                     separate preconditioner; same results)             */
+                                     holds more than 16 distinct values, from 2^18 rows,
+                                     without a Jacobi vector; same results)             */
 } pbcgs_info;
 
 /* Create a context on HIP device `device` working on stream `hip_stream`
@@ -299,7 +299,8 @@ int pbcgs_op_index_bytes(pbcgs_op_t op);
  * row is still summed over its entries in ascending column order, so results
  * equal those of the CSR arrays bit for bit.  With at most 8 diagonals, each
  * holding at most 16 distinct values in the solve (after folding Jacobi in),
- * no separate preconditioner and at least 2^18 rows (PBCGS_VALUE_CODES=1:
+ * no Jacobi vector (none, folded, or a constant diagonal) and at least 2^18
+ * rows (PBCGS_VALUE_CODES=1:
  * any row count; =0: never), a solve reads the laid-out values as
  * one-byte codes into per-diagonal tables instead (value indexing: one 8-byte
  * word per row and 128 bytes per diagonal of context workspace; same results;

@@ -2,8 +2,10 @@
 
 When a CSR operator's layout has at most 8 diagonals, none of which holds more
 than 16 distinct values (after folding Jacobi in; binary64, or binary32 and
-binary64 for the precision form), and no separate preconditioner is applied, a solve reads each entry's value as a one-byte
-code into its diagonal's table of values (one 8-byte word of codes per row).
+binary64 for the precision form), and no Jacobi vector is applied (none,
+folded, or Jacobi by a constant diagonal), a solve reads each entry's value
+as a one-byte code into its diagonal's table of values (one 8-byte word of
+codes per row).
 The products use the same binary64 values in the same order, so every solve
 must equal the oracle bit for bit, and equal the same solve with the codes
 switched off (``PBCGS_VALUE_CODES=0``):
