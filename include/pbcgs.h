@@ -300,8 +300,8 @@ int pbcgs_op_index_bytes(pbcgs_op_t op);
  * equal those of the CSR arrays bit for bit.  With at most 8 diagonals, each
  * holding at most 16 distinct values in the solve (after folding Jacobi in),
  * no Jacobi vector (none, folded, or a constant diagonal) and at least 2^18
- * rows (PBCGS_VALUE_CODES=1:
- * any row count; =0: never), a solve reads the laid-out values as
+ * rows (PBCGS_VALUE_CODES=1: any row count; =0: never), a solve reads the
+ * laid-out values as
  * one-byte codes into per-diagonal tables instead (value indexing: one 8-byte
  * word per row and 128 bytes per diagonal of context workspace; same results;
  * pbcgs_info.value_codes).  pbcgs_spmv and pbcgs_solve_noalloc read the CSR
